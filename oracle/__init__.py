@@ -1,0 +1,262 @@
+"""Python access to the CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg use it; the product package never imports it.  The oracle is
+a plain, slow transcription of the paper's definitions (Alg. 1, Alg. 2,
+Eq. ema, Sec. "Population Management"), with every objective recomputed in
+full on a real copy of each candidate.
+
+Parity is pinned for every function here (tests/test_oracle_*.py): objectives
+by brute force and closed forms, Philox by published known-answer vectors, the
+exp tables by exact regeneration, the AOS arithmetic by a worked example, and
+whole runs by invariants (delta == full recompute, validity, determinism,
+greedy / random-walk limits, snapshot-resume equivalence).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+N_OPS = 6
+
+
+def build(force: bool = False) -> str:
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(
+            os.path.getmtime(src), os.path.getmtime(os.path.join(_HERE, "oracle.h"))):
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC",
+                               "-o", _SO + ".tmp", src])
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class _Desc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32),
+                ("a", C.POINTER(C.c_int32)), ("b", C.POINTER(C.c_int32)),
+                ("a_is_coords", C.c_int32), ("capacity", C.c_int32), ("vehicles", C.c_int32),
+                ("service_time", C.c_int32), ("horizon", C.c_int32), ("lb", C.c_int32),
+                ("ub", C.c_int32), ("n_edges", C.c_int32), ("key", C.c_uint32)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("generations", C.c_uint32), ("population", C.c_uint32),
+                ("candidates", C.c_uint32), ("op_mask", C.c_uint32), ("t0_q16", C.c_uint64),
+                ("alpha_q32", C.c_uint32), ("epoch", C.c_uint32), ("aos_alpha_q16", C.c_uint32),
+                ("w_floor_q16", C.c_uint32), ("stagnation_epochs", C.c_uint32),
+                ("credit", C.c_uint32), ("oversample_k", C.c_uint32), ("pad_", C.c_uint32)]
+
+
+class _State(C.Structure):
+    _fields_ = [("g", C.c_uint32), ("stag", C.c_uint32), ("T_q16", C.c_uint64),
+                ("epoch_ref", C.c_int64), ("w_op", C.c_uint32 * N_OPS), ("w_k", C.c_uint32 * 3),
+                ("pad_", C.c_uint32),
+                ("u_op", C.c_uint64 * N_OPS), ("v_op", C.c_uint64 * N_OPS),
+                ("u_k", C.c_uint64 * 3), ("v_k", C.c_uint64 * 3), ("accepted", C.c_uint64),
+                ("cur", C.POINTER(C.c_int32)), ("cur_f", C.POINTER(C.c_int64)),
+                ("best", C.POINTER(C.c_int32)), ("best_f", C.POINTER(C.c_int64))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = C.CDLL(build())
+        P32, P64 = C.POINTER(C.c_uint32), C.POINTER(C.c_int32)
+        L.or_philox4x32_10.argtypes = [P32, P32, P32]
+        L.or_nint_dist.argtypes = [C.c_int32] * 4
+        L.or_nint_dist.restype = C.c_int32
+        L.or_isqrt.argtypes = [C.c_uint64]
+        L.or_isqrt.restype = C.c_uint64
+        L.or_accept_threshold.argtypes = [C.c_uint64, C.c_uint64, C.POINTER(C.c_int)]
+        L.or_accept_threshold.restype = C.c_uint32
+        L.or_cool.argtypes = [C.c_uint64, C.c_uint32]
+        L.or_cool.restype = C.c_uint64
+        L.or_inst_new.argtypes = [C.POINTER(_Desc)]
+        L.or_inst_new.restype = C.c_void_p
+        L.or_inst_free.argtypes = [C.c_void_p]
+        L.or_objective.argtypes = [C.c_void_p, P64]
+        L.or_objective.restype = C.c_int64
+        L.or_dist.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+        L.or_dist.restype = C.c_int32
+        L.or_apply_op.argtypes = [C.c_void_p, P64, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.or_initial_weights.argtypes = [C.c_void_p, C.c_uint32, P32]
+        L.or_aos_update.argtypes = [C.POINTER(_Params), C.c_uint32, C.POINTER(_State), C.c_int64]
+        L.or_heuristic_perms.argtypes = [C.c_void_p, P64, C.c_int]
+        L.or_heuristic_perms.restype = C.c_int
+        L.or_init.argtypes = [C.c_void_p, C.POINTER(_Params), C.POINTER(_State)]
+        L.or_run.argtypes = [C.c_void_p, C.POINTER(_Params), C.POINTER(_State), C.c_uint32]
+        L.or_effective_mask.argtypes = [C.c_void_p, C.c_uint32]
+        L.or_effective_mask.restype = C.c_uint32
+        _lib = L
+    return _lib
+
+
+def _i32p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+# ------------------------------------------------------------------ helpers
+def philox(ctr, key) -> np.ndarray:
+    c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
+    k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    o = (C.c_uint32 * 4)()
+    lib().or_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def nint_dist(x1, y1, x2, y2) -> int:
+    return int(lib().or_nint_dist(x1, y1, x2, y2))
+
+
+def isqrt(v: int) -> int:
+    return int(lib().or_isqrt(v))
+
+
+def accept_threshold(delta: int, t_q16: int):
+    """(threshold, rejected_outright) for a positive delta."""
+    rej = C.c_int(0)
+    thr = lib().or_accept_threshold(delta, t_q16, C.byref(rej))
+    return int(thr), bool(rej.value)
+
+
+def cool(t_q16: int, alpha_q32: int) -> int:
+    return int(lib().or_cool(t_q16, alpha_q32))
+
+
+def _params(p) -> _Params:
+    return _Params(seed=p.seed & 0xFFFFFFFFFFFFFFFF, generations=p.generations,
+                   population=p.population, candidates=p.candidates or 128,
+                   op_mask=p.op_mask, t0_q16=p.t0_q16, alpha_q32=p.alpha_q32,
+                   epoch=p.epoch or 10, aos_alpha_q16=p.aos_alpha_q16 or 49152,
+                   w_floor_q16=p.w_floor_q16 or 1024,
+                   stagnation_epochs=p.stagnation_epochs or 5, credit=p.credit,
+                   oversample_k=p.oversample_k or 4)
+
+
+class OracleInstance:
+    """Owns the oracle's copy of an instance (the caller's arrays stay referenced)."""
+
+    def __init__(self, inst):
+        self.inst = inst
+        self._a = np.ascontiguousarray(inst.a, dtype=np.int32)
+        self._b = None if inst.b is None else np.ascontiguousarray(inst.b, dtype=np.int32)
+        d = _Desc(kind=inst.kind, n=inst.n, a=_i32p(self._a),
+                  b=_i32p(self._b) if self._b is not None else C.POINTER(C.c_int32)(),
+                  a_is_coords=inst.a_is_coords, capacity=inst.capacity, vehicles=inst.vehicles,
+                  service_time=inst.service_time, horizon=inst.horizon, lb=inst.lb, ub=inst.ub,
+                  n_edges=inst.n_edges, key=inst.key & 0xFFFFFFFF)
+        self._desc = d
+        self.h = lib().or_inst_new(C.byref(d))
+        if not self.h:
+            raise ValueError("oracle rejected the instance")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().or_inst_free(self.h)
+            self.h = None
+
+    @property
+    def n(self):
+        return self.inst.n
+
+    def objective(self, x) -> int:
+        x = np.ascontiguousarray(x, dtype=np.int32)
+        assert x.shape == (self.n,)
+        return int(lib().or_objective(self.h, _i32p(x)))
+
+    def dist(self, u, v) -> int:
+        return int(lib().or_dist(self.h, u, v))
+
+    def apply_op(self, x, op, w1, w2, w3):
+        x = np.array(x, dtype=np.int32, copy=True)
+        lib().or_apply_op(self.h, _i32p(x), op, w1 & 0xFFFFFFFF, w2 & 0xFFFFFFFF, w3 & 0xFFFFFFFF)
+        return x
+
+    def initial_weights(self, op_mask) -> np.ndarray:
+        w = (C.c_uint32 * N_OPS)()
+        lib().or_initial_weights(self.h, op_mask, w)
+        return np.array(list(w), dtype=np.uint32)
+
+    def effective_mask(self, op_mask) -> int:
+        return int(lib().or_effective_mask(self.h, op_mask))
+
+    def heuristic_perms(self) -> np.ndarray:
+        out = np.zeros((8, self.n), dtype=np.int32)
+        c = lib().or_heuristic_perms(self.h, _i32p(out), 8)
+        return out[:c]
+
+    # -------------------------------------------------------------- solve
+    def _state_struct(self, st: dict) -> _State:
+        s = _State(g=st["g"], stag=st["stag"], T_q16=st["T_q16"], epoch_ref=st["epoch_ref"],
+                   accepted=st["accepted"])
+        for name in ("w_op", "w_k", "u_op", "v_op", "u_k", "v_k"):
+            arr = getattr(s, name)
+            for i, v in enumerate(st[name]):
+                arr[i] = int(v)
+        s.cur = _i32p(st["cur"])
+        s.cur_f = st["cur_f"].ctypes.data_as(C.POINTER(C.c_int64))
+        s.best = _i32p(st["best"])
+        s.best_f = st["best_f"].ctypes.data_as(C.POINTER(C.c_int64))
+        return s
+
+    @staticmethod
+    def _read_back(s: _State, st: dict):
+        st["g"], st["stag"], st["T_q16"] = int(s.g), int(s.stag), int(s.T_q16)
+        st["epoch_ref"], st["accepted"] = int(s.epoch_ref), int(s.accepted)
+        for name, dt in (("w_op", np.uint32), ("w_k", np.uint32), ("u_op", np.uint64),
+                         ("v_op", np.uint64), ("u_k", np.uint64), ("v_k", np.uint64)):
+            st[name] = np.array(list(getattr(s, name)), dtype=dt)
+
+    def new_state(self, P: int) -> dict:
+        n = self.n
+        return {"g": 0, "stag": 0, "T_q16": 0, "epoch_ref": 0, "accepted": 0,
+                "w_op": np.zeros(N_OPS, np.uint32), "w_k": np.zeros(3, np.uint32),
+                "u_op": np.zeros(N_OPS, np.uint64), "v_op": np.zeros(N_OPS, np.uint64),
+                "u_k": np.zeros(3, np.uint64), "v_k": np.zeros(3, np.uint64),
+                "cur": np.zeros((P, n), np.int32), "cur_f": np.zeros(P, np.int64),
+                "best": np.zeros((P, n), np.int32), "best_f": np.zeros(P, np.int64)}
+
+    def init(self, params) -> dict:
+        st = self.new_state(params.population)
+        s = self._state_struct(st)
+        pp = _params(params)
+        lib().or_init(self.h, C.byref(pp), C.byref(s))
+        self._read_back(s, st)
+        return st
+
+    def run(self, params, st: dict, n_gens: int) -> dict:
+        """Advance ``st`` (modified in place and returned) by ``n_gens`` generations."""
+        for k in ("cur", "best"):
+            st[k] = np.ascontiguousarray(st[k], dtype=np.int32)
+        for k in ("cur_f", "best_f"):
+            st[k] = np.ascontiguousarray(st[k], dtype=np.int64)
+        s = self._state_struct(st)
+        pp = _params(params)
+        lib().or_run(self.h, C.byref(pp), C.byref(s), n_gens)
+        self._read_back(s, st)
+        return st
+
+    def aos_update(self, params, st: dict, inst_best_now: int, op_mask=None) -> dict:
+        s = self._state_struct(st)
+        pp = _params(params)
+        m = self.effective_mask(params.op_mask if op_mask is None else op_mask)
+        lib().or_aos_update(C.byref(pp), m, C.byref(s), inst_best_now)
+        self._read_back(s, st)
+        return st
+
+    def solve(self, params) -> dict:
+        st = self.init(params)
+        return self.run(params, st, params.generations)
+
+
+def best_of(st: dict):
+    """(objective, index) of the best solution: min over (best_f, index)."""
+    i = int(np.argmin(st["best_f"]))   # argmin returns the first minimum
+    return int(st["best_f"][i]), i

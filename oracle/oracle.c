@@ -1,0 +1,572 @@
+/* oracle.c -- plain CPU reference of the population-parallel local search of
+ * cuGenOpt (arXiv 2603.19163).
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the
+ * benchmark's CPU-baseline leg; never by the product library.  It shares no
+ * source with the HIP path.  Everything is written from the paper's
+ * definitions in the most direct form:
+ *   - each candidate is a real copy of the solution with its k operators
+ *     applied in order (Alg. 1, "copy(s)" then "execute sigma_i on s_t");
+ *   - every objective is recomputed in full from its definition (Alg. 1,
+ *     "evaluate s_t; delta_t = f(s_t) - f(s)");
+ *   - argmin, acceptance, AOS statistics, cooling (Alg. 1), the EMA weight
+ *     update with clamp, normalisation and stagnation reset (Eq. ema, Alg. 2,
+ *     Sec. "Stagnation Detection"), oversampled initialisation with row/column
+ *     sum heuristics (Sec. "Population Management").
+ * Where the paper leaves a choice open (random source, integer objectives,
+ * tie-breaks, the meaning of "batch", constants of the AOS update) the code
+ * follows the readings listed in the design doc's table of readings; each such
+ * place is marked "reading:".
+ */
+#include "oracle.h"
+#include "exp_tables.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+enum { K_TSP = 1, K_QAP = 2, K_KNAP = 3, K_VRPTW = 4, K_COLOR = 5 };
+enum { OP_2OPT = 0, OP_SWAP = 1, OP_INSERT = 2, OP_OROPT = 3, OP_FLIP = 4, OP_RESET = 5 };
+
+struct or_inst {
+  or_inst_desc d;
+  int32_t *dist;   /* TSP: n x n; VRPTW: (n+1) x (n+1) */
+  int32_t dn;      /* side of dist */
+  int64_t lambda;  /* knapsack penalty weight */
+};
+
+/* ------------------------------------------------------------------ RNG
+ * reading: the paper only says rand(); the oracle uses Philox4x32-10
+ * (Salmon et al., "Parallel random numbers: as easy as 1, 2, 3", SC'11). */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    uint32_t n1 = (uint32_t)p1;
+    uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    uint32_t n3 = (uint32_t)p0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void draw(const or_params *p, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                 uint32_t r[4]) {
+  uint32_t ctr[4] = {c0, c1, c2, c3};
+  uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
+  or_philox4x32_10(ctr, key, r);
+}
+
+/* floor(w * m / 2^32): an integer in [0, m) */
+static uint32_t rmap(uint32_t w, uint32_t m) { return (uint32_t)(((uint64_t)w * m) >> 32); }
+
+/* Weighted choice from Q16 weights: u = floor(u16 * S / 2^16), smallest i with u < cumsum_i. */
+static int wpick(uint32_t u16, const uint32_t *w, int cnt) {
+  uint64_t s = 0;
+  for (int i = 0; i < cnt; ++i) s += w[i];
+  uint64_t u = ((uint64_t)u16 * s) >> 16;
+  uint64_t c = 0;
+  for (int i = 0; i < cnt; ++i) {
+    c += w[i];
+    if (u < c) return i;
+  }
+  return cnt - 1;
+}
+
+/* ------------------------------------------------------------ distances */
+uint64_t or_isqrt(uint64_t v) {  /* digit-by-digit integer square root */
+  uint64_t res = 0, bit = (uint64_t)1 << 62;
+  while (bit > v) bit >>= 2;
+  while (bit) {
+    if (v >= res + bit) { v -= res + bit; res = (res >> 1) + bit; }
+    else res >>= 1;
+    bit >>= 2;
+  }
+  return res;
+}
+
+/* reading: integer objective; distance = nearest integer of the Euclidean
+ * distance, floor(sqrt(s) + 1/2) = (isqrt(4 s) + 1) / 2 exactly. */
+int32_t or_nint_dist(int32_t x1, int32_t y1, int32_t x2, int32_t y2) {
+  int64_t dx = (int64_t)x1 - x2, dy = (int64_t)y1 - y2;
+  uint64_t s = (uint64_t)(dx * dx + dy * dy);
+  return (int32_t)((or_isqrt(4 * s) + 1) >> 1);
+}
+
+int32_t or_dist(const or_inst *in, int32_t u, int32_t v) {
+  return in->dist[(int64_t)u * in->dn + v];
+}
+
+/* ------------------------------------------------------------ instances */
+or_inst *or_inst_new(const or_inst_desc *d) {
+  if (!d || d->n < 1 || !d->a) return NULL;
+  or_inst *in = (or_inst *)calloc(1, sizeof(or_inst));
+  in->d = *d;
+  int n = d->n;
+  if (d->kind == K_TSP) {
+    in->dn = n;
+    in->dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        in->dist[(int64_t)i * n + j] =
+            d->a_is_coords ? or_nint_dist(d->a[2 * i], d->a[2 * i + 1], d->a[2 * j], d->a[2 * j + 1])
+                           : d->a[(int64_t)i * n + j];
+  } else if (d->kind == K_VRPTW) {
+    if (!d->b) { free(in); return NULL; }
+    int m = n + 1;
+    in->dn = m;
+    in->dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j)
+        in->dist[(int64_t)i * m + j] =
+            or_nint_dist(d->a[2 * i], d->a[2 * i + 1], d->a[2 * j], d->a[2 * j + 1]);
+  } else if (d->kind == K_QAP || d->kind == K_KNAP) {
+    if (!d->b) { free(in); return NULL; }
+    if (d->kind == K_KNAP) {
+      int64_t mv = 0;
+      for (int i = 0; i < n; ++i) if (d->b[i] > mv) mv = d->b[i];
+      /* reading: penalty weight lambda = max value + 1, so an overweight
+       * selection is always worse than dropping an item */
+      in->lambda = mv + 1;
+    }
+  } else if (d->kind == K_COLOR) {
+    if (d->ub < d->lb) { free(in); return NULL; }
+  } else {
+    free(in);
+    return NULL;
+  }
+  return in;
+}
+
+void or_inst_free(or_inst *in) {
+  if (!in) return;
+  free(in->dist);
+  free(in);
+}
+
+/* ------------------------------------------------------------ objectives
+ * All minimised, int64, recomputed from the definition. */
+static int64_t obj_tsp(const or_inst *in, const int32_t *x) {
+  int n = in->d.n;
+  int64_t f = 0;
+  for (int i = 0; i < n; ++i) f += or_dist(in, x[i], x[(i + 1) % n]);
+  return f;
+}
+
+static int64_t obj_qap(const or_inst *in, const int32_t *x) {
+  int n = in->d.n;
+  const int32_t *F = in->d.a, *D = in->d.b;
+  int64_t f = 0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      f += (int64_t)F[(int64_t)i * n + j] * D[(int64_t)x[i] * n + x[j]];
+  return f;
+}
+
+static int64_t obj_knap(const or_inst *in, const int32_t *x) {
+  int n = in->d.n;
+  int64_t W = 0, V = 0;
+  for (int i = 0; i < n; ++i)
+    if (x[i]) { W += in->d.a[i]; V += in->d.b[i]; }
+  int64_t over = W - in->d.capacity;
+  return -V + in->lambda * (over > 0 ? over : 0);
+}
+
+/* reading: giant tour over customers 1..n, split greedily into routes by
+ * capacity; wait until ready, lateness penalised 100 per unit, each vehicle
+ * beyond the fleet 10000. */
+static int64_t obj_vrptw(const or_inst *in, const int32_t *x) {
+  int n = in->d.n;
+  const int32_t *dem = in->d.b, *ready = in->d.b + (n + 1), *due = in->d.b + 2 * (n + 1);
+  int64_t dist = 0, late = 0, t = 0, load = 0;
+  int routes = 0, prev = 0;
+  for (int p = 0; p < n; ++p) {
+    int c = x[p] + 1;
+    if (routes == 0 || load + dem[c] > in->d.capacity) {
+      if (routes > 0) {
+        int64_t back = or_dist(in, prev, 0);
+        dist += back; t += back;
+        if (t > in->d.horizon) late += t - in->d.horizon;
+      }
+      routes++; load = 0; t = 0; prev = 0;
+    }
+    int64_t dd = or_dist(in, prev, c);
+    dist += dd; t += dd;
+    if (t < ready[c]) t = ready[c];
+    if (t > due[c]) late += t - due[c];
+    t += in->d.service_time;
+    load += dem[c];
+    prev = c;
+  }
+  if (routes > 0) {
+    int64_t back = or_dist(in, prev, 0);
+    dist += back; t += back;
+    if (t > in->d.horizon) late += t - in->d.horizon;
+  }
+  int64_t extra = routes - in->d.vehicles;
+  return dist + 100 * late + 10000 * (extra > 0 ? extra : 0);
+}
+
+static int64_t obj_color(const or_inst *in, const int32_t *x) {
+  int64_t f = 0;
+  for (int e = 0; e < in->d.n_edges; ++e)
+    f += x[in->d.a[2 * e]] == x[in->d.a[2 * e + 1]];
+  return f;
+}
+
+int64_t or_objective(const or_inst *in, const int32_t *x) {
+  switch (in->d.kind) {
+    case K_TSP: return obj_tsp(in, x);
+    case K_QAP: return obj_qap(in, x);
+    case K_KNAP: return obj_knap(in, x);
+    case K_VRPTW: return obj_vrptw(in, x);
+    default: return obj_color(in, x);
+  }
+}
+
+/* ------------------------------------------------------------ operators
+ * Tab. "operators": element level swap / insert / reverse (permutation),
+ * flip (binary), random_reset (integer); segment level or-opt.
+ * Applied to a real array.  Returns the op id that was applied. */
+static void reverse_range(int32_t *x, int lo, int hi) {
+  while (lo < hi) { int32_t t = x[lo]; x[lo] = x[hi]; x[hi] = t; ++lo; --hi; }
+}
+
+int or_apply_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2, uint32_t w3) {
+  int n = in->d.n;
+  if (op == OP_FLIP) { x[rmap(w1, n)] ^= 1; return op; }
+  if (op == OP_RESET) {
+    uint32_t i = rmap(w1, n);
+    x[i] = in->d.lb + (int32_t)rmap(w2, (uint32_t)(in->d.ub - in->d.lb + 1));
+    return op;
+  }
+  if (n < 2) return op;                      /* every permutation move is the identity */
+  if (op == OP_2OPT || op == OP_SWAP) {
+    uint32_t i = rmap(w1, n), j = rmap(w2, n - 1);
+    j += (j >= i);
+    if (op == OP_SWAP) { int32_t t = x[i]; x[i] = x[j]; x[j] = t; }
+    else reverse_range(x, i < j ? i : j, i < j ? j : i);   /* reverse = 2-opt */
+    return op;
+  }
+  /* insert (segment length 1) and or-opt (length 2 or 3, orientation kept):
+   * remove s[i..i+L-1] and put it back so that it starts at index q */
+  int L = (op == OP_INSERT) ? 1 : 2 + (int)rmap(w3, 2);
+  if (L > n - 1) L = n - 1;
+  uint32_t i = rmap(w1, (uint32_t)(n - L + 1));
+  uint32_t q = rmap(w2, (uint32_t)(n - L));
+  q += (q >= i);
+  int32_t seg[3];
+  for (int s = 0; s < L; ++s) seg[s] = x[i + s];
+  int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * n);
+  int m = 0;
+  for (int p = 0; p < n; ++p)
+    if (p < (int)i || p >= (int)i + L) tmp[m++] = x[p];   /* the remainder, n-L items */
+  int o = 0;
+  for (int p = 0; p < n - L + 1; ++p) {
+    if (p == (int)q) for (int s = 0; s < L; ++s) x[o++] = seg[s];
+    if (p < n - L) x[o++] = tmp[p];
+  }
+  free(tmp);
+  return op;
+}
+
+/* ------------------------------------------------------------ encodings */
+static uint32_t encoding_ops(int kind) {
+  if (kind == K_KNAP) return 1u << OP_FLIP;
+  if (kind == K_COLOR) return 1u << OP_RESET;
+  return (1u << OP_2OPT) | (1u << OP_SWAP) | (1u << OP_INSERT) | (1u << OP_OROPT);
+}
+
+uint32_t or_effective_mask(const or_inst *in, uint32_t op_mask) {
+  uint32_t e = encoding_ops(in->d.kind);
+  return op_mask ? (op_mask & e) : e;
+}
+
+static int enabled_list(uint32_t mask, int *ids) {
+  int c = 0;
+  for (int i = 0; i < OR_MAX_OPS; ++i) if (mask & (1u << i)) ids[c++] = i;
+  return c;
+}
+
+/* Sec. "Problem-Profile-Driven Prior Strategy", Tab. "weight_preset":
+ * O(1) operators start at 1.0; or-opt at 0.8 / 0.7 / 0.3 for n <= 100,
+ * <= 250, > 250; then the weights are normalised (Q16). */
+void or_initial_weights(const or_inst *in, uint32_t op_mask, uint32_t w[OR_MAX_OPS]) {
+  uint32_t m = or_effective_mask(in, op_mask);
+  int n = in->d.n;
+  uint64_t raw[OR_MAX_OPS] = {0}, s = 0;
+  for (int i = 0; i < OR_MAX_OPS; ++i) {
+    if (!(m & (1u << i))) continue;
+    raw[i] = 65536;
+    if (i == OP_OROPT) raw[i] = n <= 100 ? 52429 : (n <= 250 ? 45875 : 19661);
+    s += raw[i];
+  }
+  for (int i = 0; i < OR_MAX_OPS; ++i) {
+    if (!(m & (1u << i))) { w[i] = 0; continue; }
+    uint64_t v = (raw[i] << 16) / s;
+    w[i] = (uint32_t)(v < 1 ? 1 : v);
+  }
+}
+
+/* ------------------------------------------------------------ acceptance
+ * Alg. 1: accept if delta < 0 or rand() < e^{-delta/T}.  reading: delta = 0
+ * always accepted (e^0 = 1); e^{-x} taken from two integer tables on
+ * z = floor(delta * 2^24 / T_q16) = floor(256 * delta / T). */
+uint32_t or_accept_threshold(uint64_t delta, uint64_t t_q16, int *reject) {
+  *reject = 0;
+  if (t_q16 == 0) { *reject = 1; return 0; }
+  uint64_t z = (delta << 24) / t_q16;
+  if (z >= 4096) { *reject = 1; return 0; }
+  return (uint32_t)(((uint64_t)OR_EXP_HI[z >> 8] * OR_EXP_LO[z & 255]) >> 31);
+}
+
+/* Alg. 1: T <- alpha T, with T in Q16 and alpha in Q32: floor(T * alpha / 2^32). */
+uint64_t or_cool(uint64_t t, uint32_t alpha) {
+  uint64_t hi = t >> 32, lo = t & 0xFFFFFFFFu;
+  return hi * alpha + ((lo * alpha) >> 32);
+}
+
+/* ------------------------------------------------------------ AOS update
+ * Eq. ema: w <- a w + (1-a)(v/(u+eps) + w_floor); clamp to [w_floor, 1];
+ * normalise; Alg. 2 also updates the K-step weights the same way and resets
+ * them to (0.8, 0.15, 0.05) after stagnation. */
+static void ema_group(const or_params *p, uint32_t *w, const uint64_t *u, const uint64_t *v,
+                      const int *ids, int cnt) {
+  uint64_t A = p->aos_alpha_q16, FL = p->w_floor_q16, s = 0;
+  for (int c = 0; c < cnt; ++c) {
+    int i = ids[c];
+    uint64_t r = (v[i] << 16) / (u[i] + 1);
+    uint64_t nw = (A * w[i] + (65536 - A) * (r + FL)) >> 16;
+    if (nw < FL) nw = FL;
+    if (nw > 65536) nw = 65536;
+    w[i] = (uint32_t)nw;
+    s += nw;
+  }
+  for (int c = 0; c < cnt; ++c) {
+    int i = ids[c];
+    uint64_t nw = ((uint64_t)w[i] << 16) / s;
+    w[i] = (uint32_t)(nw < 1 ? 1 : nw);
+  }
+}
+
+static const uint32_t WK_DEFAULT[3] = {52429, 9830, 3277};
+
+void or_aos_update(const or_params *p, uint32_t mask, or_state *st, int64_t inst_best_now) {
+  int ids[OR_MAX_OPS];
+  int cnt = enabled_list(mask, ids);
+  ema_group(p, st->w_op, st->u_op, st->v_op, ids, cnt);
+  int kid[3] = {0, 1, 2};
+  ema_group(p, st->w_k, st->u_k, st->v_k, kid, 3);
+  /* reading: "consecutive no-improvement" counted in epochs of the instance best */
+  if (inst_best_now < st->epoch_ref) st->stag = 0;
+  else st->stag++;
+  st->epoch_ref = inst_best_now;
+  if (st->stag >= p->stagnation_epochs) {
+    memcpy(st->w_k, WK_DEFAULT, sizeof(WK_DEFAULT));
+    st->stag = 0;
+  }
+  memset(st->u_op, 0, sizeof(st->u_op));
+  memset(st->v_op, 0, sizeof(st->v_op));
+  memset(st->u_k, 0, sizeof(st->u_k));
+  memset(st->v_k, 0, sizeof(st->v_k));
+}
+
+/* ------------------------------------------------------------ init
+ * Sec. "Attribute-Agnostic Heuristic Initialization": row sums and column
+ * sums of every n x n data matrix, sorted ascending and descending, give four
+ * permutations per matrix.  reading: ties keep the smaller index first. */
+typedef struct { int64_t k; int32_t i; } kv;
+static int kv_cmp(const void *a, const void *b) {
+  const kv *x = (const kv *)a, *y = (const kv *)b;
+  if (x->k != y->k) return x->k < y->k ? -1 : 1;
+  return x->i < y->i ? -1 : (x->i > y->i);
+}
+
+static int sum_perms(const int32_t *M, int n, int stride, int32_t *out) {
+  kv *t = (kv *)malloc(sizeof(kv) * n);
+  for (int rc = 0; rc < 2; ++rc) {          /* rows, then columns */
+    for (int dir = 0; dir < 2; ++dir) {     /* ascending, then descending */
+      for (int i = 0; i < n; ++i) {
+        int64_t s = 0;
+        for (int j = 0; j < n; ++j)
+          s += rc == 0 ? M[(int64_t)i * stride + j] : M[(int64_t)j * stride + i];
+        t[i].k = dir == 0 ? s : -s;
+        t[i].i = i;
+      }
+      qsort(t, n, sizeof(kv), kv_cmp);
+      for (int i = 0; i < n; ++i) out[i] = t[i].i;
+      out += n;
+    }
+  }
+  free(t);
+  return 4;
+}
+
+int or_heuristic_perms(const or_inst *in, int32_t *out, int cap) {
+  int n = in->d.n, c = 0;
+  if (in->d.kind == K_TSP) {
+    if (cap >= 4) c += sum_perms(in->dist, n, n, out);
+  } else if (in->d.kind == K_QAP) {
+    if (cap >= 8) {
+      c += sum_perms(in->d.a, n, n, out);
+      c += sum_perms(in->d.b, n, n, out + (size_t)4 * n);
+    }
+  } else if (in->d.kind == K_VRPTW) {
+    /* the customer block of the travel-time matrix */
+    if (cap >= 4) c += sum_perms(in->dist + in->dn + 1, n, in->dn, out);
+  }
+  return c;
+}
+
+typedef struct { int64_t f; int32_t q; } fq;
+static int fq_cmp(const void *a, const void *b) {
+  const fq *x = (const fq *)a, *y = (const fq *)b;
+  if (x->f != y->f) return x->f < y->f ? -1 : 1;
+  return x->q < y->q ? -1 : (x->q > y->q);
+}
+
+/* Sec. "Oversample Initialization": K*P candidates, evaluated, best P kept.
+ * reading: heuristic solutions take the first pool slots, the rest are
+ * random; ties in f keep the lower pool index. */
+int or_init(const or_inst *in, const or_params *p, or_state *st) {
+  int n = in->d.n, P = p->population;
+  int Q = p->oversample_k * P;
+  int32_t *pool = (int32_t *)malloc(sizeof(int32_t) * (size_t)Q * n);
+  int32_t *heur = (int32_t *)malloc(sizeof(int32_t) * (size_t)8 * n);
+  int H = or_heuristic_perms(in, heur, 8);
+  if (H > Q) H = Q;
+  uint32_t key = in->d.key;
+  for (int q = 0; q < Q; ++q) {
+    int32_t *x = pool + (size_t)q * n;
+    if (q < H) { memcpy(x, heur + (size_t)q * n, sizeof(int32_t) * n); continue; }
+    uint32_t r[4];
+    if (in->d.kind == K_KNAP || in->d.kind == K_COLOR) {
+      for (int i = 0; i < n; ++i) {
+        draw(p, 0xFFFFFFFFu, (uint32_t)q, (uint32_t)(i >> 2), key, r);
+        uint32_t w = r[i & 3];
+        x[i] = in->d.kind == K_KNAP ? (int32_t)(w >> 31)
+                                    : in->d.lb + (int32_t)rmap(w, (uint32_t)(in->d.ub - in->d.lb + 1));
+      }
+    } else {  /* Fisher-Yates from the identity */
+      for (int i = 0; i < n; ++i) x[i] = i;
+      for (int i = n - 1; i >= 1; --i) {
+        draw(p, 0xFFFFFFFFu, (uint32_t)q, (uint32_t)(i >> 2), key, r);
+        uint32_t j = rmap(r[i & 3], (uint32_t)(i + 1));
+        int32_t t = x[i]; x[i] = x[j]; x[j] = t;
+      }
+    }
+  }
+  fq *ord = (fq *)malloc(sizeof(fq) * Q);
+  for (int q = 0; q < Q; ++q) { ord[q].f = or_objective(in, pool + (size_t)q * n); ord[q].q = q; }
+  qsort(ord, Q, sizeof(fq), fq_cmp);
+  for (int s = 0; s < P; ++s) {
+    memcpy(st->cur + (size_t)s * n, pool + (size_t)ord[s].q * n, sizeof(int32_t) * n);
+    memcpy(st->best + (size_t)s * n, pool + (size_t)ord[s].q * n, sizeof(int32_t) * n);
+    st->cur_f[s] = st->best_f[s] = ord[s].f;
+  }
+  st->g = 0;
+  st->stag = 0;
+  st->epoch_ref = ord[0].f;
+  if (p->t0_q16) st->T_q16 = p->t0_q16;
+  else {  /* reading: T0 = a quarter of the mean per-element cost of the best start */
+    uint64_t a = (uint64_t)(ord[0].f < 0 ? -ord[0].f : ord[0].f);
+    st->T_q16 = ((a << 16) / (uint64_t)n) >> 2;
+  }
+  or_initial_weights(in, p->op_mask, st->w_op);
+  memcpy(st->w_k, WK_DEFAULT, sizeof(WK_DEFAULT));
+  memset(st->u_op, 0, sizeof(st->u_op));
+  memset(st->v_op, 0, sizeof(st->v_op));
+  memset(st->u_k, 0, sizeof(st->u_k));
+  memset(st->v_k, 0, sizeof(st->v_k));
+  st->accepted = 0;
+  free(ord);
+  free(heur);
+  free(pool);
+  return 0;
+}
+
+/* ------------------------------------------------------------ generations
+ * Alg. 1 for every solution of the population, then cooling; after every
+ * epoch of E generations the AOS update of Alg. 2.  reading: the RNG counter
+ * of candidate t, operator slot m, is (g, solution, 4t + m, instance key);
+ * the acceptance draw uses (g, solution, 0xFFFFFFFF, instance key). */
+int or_run(const or_inst *in, const or_params *p, or_state *st, uint32_t n_gens) {
+  int n = in->d.n, P = p->population, C = p->candidates;
+  uint32_t mask = or_effective_mask(in, p->op_mask);
+  int ids[OR_MAX_OPS];
+  int nids = enabled_list(mask, ids);
+  uint32_t wl[OR_MAX_OPS];
+  int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * n);
+  int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * n);
+  uint32_t key = in->d.key;
+  for (uint32_t it = 0; it < n_gens; ++it) {
+    uint32_t g = st->g;
+    for (int sol = 0; sol < P; ++sol) {
+      int32_t *x = st->cur + (size_t)sol * n;
+      for (int c = 0; c < nids; ++c) wl[c] = st->w_op[ids[c]];
+      int64_t best_d = 0;
+      int best_t = -1, best_k = 0, best_ops[3] = {0, 0, 0};
+      for (int t = 0; t < C; ++t) {
+        memcpy(tmp, x, sizeof(int32_t) * n);           /* s_t <- copy(s) */
+        uint32_t r[4];
+        draw(p, g, (uint32_t)sol, (uint32_t)t << 2, key, r);
+        int k = 1 + wpick(r[0] >> 16, st->w_k, 3);      /* k_t from w_K */
+        int ops[3];
+        for (int m = 0; m < k; ++m) {
+          if (m > 0) draw(p, g, (uint32_t)sol, ((uint32_t)t << 2) | (uint32_t)m, key, r);
+          ops[m] = ids[wpick(r[0] & 0xFFFFu, wl, nids)];  /* sigma_i from R.w */
+          or_apply_op(in, tmp, ops[m], r[1], r[2], r[3]);
+        }
+        int64_t d = or_objective(in, tmp) - st->cur_f[sol];
+        if (p->credit == 0) {  /* reading: every candidate credits its operators */
+          for (int m = 0; m < k; ++m) { st->u_op[ops[m]]++; if (d < 0) st->v_op[ops[m]]++; }
+          st->u_k[k - 1]++;
+          if (d < 0) st->v_k[k - 1]++;
+        }
+        if (best_t < 0 || d < best_d) {   /* argmin; ties keep the lowest t */
+          best_d = d; best_t = t; best_k = k;
+          memcpy(best_ops, ops, sizeof(ops));
+          memcpy(cand, tmp, sizeof(int32_t) * n);
+        }
+      }
+      int acc = 0;
+      if (best_d <= 0) acc = 1;
+      else {
+        int rej;
+        uint32_t thr = or_accept_threshold((uint64_t)best_d, st->T_q16, &rej);
+        if (!rej) {
+          uint32_t r[4];
+          draw(p, g, (uint32_t)sol, 0xFFFFFFFFu, key, r);
+          acc = (r[0] >> 1) < thr;
+        }
+      }
+      if (acc) {
+        if (p->credit == 1) {   /* reading R2: only the accepted move is credited */
+          for (int m = 0; m < best_k; ++m) { st->u_op[best_ops[m]]++; if (best_d < 0) st->v_op[best_ops[m]]++; }
+          st->u_k[best_k - 1]++;
+          if (best_d < 0) st->v_k[best_k - 1]++;
+        }
+        memcpy(x, cand, sizeof(int32_t) * n);
+        st->cur_f[sol] += best_d;
+        st->accepted++;
+        if (st->cur_f[sol] < st->best_f[sol]) {
+          st->best_f[sol] = st->cur_f[sol];
+          memcpy(st->best + (size_t)sol * n, x, sizeof(int32_t) * n);
+        }
+      }
+    }
+    st->T_q16 = or_cool(st->T_q16, p->alpha_q32);
+    if ((g + 1) % p->epoch == 0) {
+      int64_t ib = st->best_f[0];
+      for (int s = 1; s < P; ++s) if (st->best_f[s] < ib) ib = st->best_f[s];
+      or_aos_update(p, mask, st, ib);
+    }
+    st->g = g + 1;
+  }
+  free(cand);
+  free(tmp);
+  return 0;
+}

@@ -1,0 +1,67 @@
+/* oracle.h -- plain CPU reference of the population-parallel local search
+ * (cuGenOpt, arXiv 2603.19163, Alg. 1 per-generation evolution, Alg. 2 / Eq. ema
+ * adaptive operator selection, Sec. "Population Management" initialisation).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library includes, links or
+ * calls this code; only tests, the smoke check and the benchmark's CPU-baseline
+ * leg load liboracle.so.  It is deliberately slow: every candidate is a real
+ * copy of the solution, every objective a full recomputation from its
+ * definition.
+ */
+#ifndef GX_ORACLE_H
+#define GX_ORACLE_H
+#include <stdint.h>
+
+#define OR_MAX_OPS 6
+
+typedef struct {
+  int32_t kind, n;
+  const int32_t *a, *b;
+  int32_t a_is_coords, capacity, vehicles, service_time, horizon, lb, ub, n_edges;
+  uint32_t key;
+} or_inst_desc;
+
+typedef struct {
+  uint64_t seed;
+  uint32_t generations, population, candidates, op_mask;
+  uint64_t t0_q16;
+  uint32_t alpha_q32, epoch, aos_alpha_q16, w_floor_q16, stagnation_epochs, credit, oversample_k;
+  uint32_t pad_;
+} or_params;
+
+/* Epoch-boundary state of one solve.  Arrays are caller-owned. */
+typedef struct {
+  uint32_t g, stag;
+  uint64_t T_q16;
+  int64_t epoch_ref;                  /* instance best at the start of the epoch */
+  uint32_t w_op[OR_MAX_OPS], w_k[3];
+  uint32_t pad_;
+  uint64_t u_op[OR_MAX_OPS], v_op[OR_MAX_OPS], u_k[3], v_k[3]; /* current-epoch counts */
+  uint64_t accepted;                  /* accepted moves over the whole run */
+  int32_t *cur;                       /* P x n */
+  int64_t *cur_f;                     /* P     */
+  int32_t *best;                      /* P x n */
+  int64_t *best_f;                    /* P     */
+} or_state;
+
+typedef struct or_inst or_inst;
+
+void    or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+int32_t or_nint_dist(int32_t x1, int32_t y1, int32_t x2, int32_t y2);
+uint64_t or_isqrt(uint64_t v);
+uint32_t or_accept_threshold(uint64_t delta, uint64_t t_q16, int *reject_outright);
+uint64_t or_cool(uint64_t t_q16, uint32_t alpha_q32);
+
+or_inst *or_inst_new(const or_inst_desc *d);   /* NULL on invalid input */
+void     or_inst_free(or_inst *);
+int64_t  or_objective(const or_inst *, const int32_t *x);
+int32_t  or_dist(const or_inst *, int32_t u, int32_t v);  /* TSP / VRPTW distances */
+int      or_apply_op(const or_inst *, int32_t *x, int op, uint32_t w1, uint32_t w2, uint32_t w3);
+void     or_initial_weights(const or_inst *, uint32_t op_mask, uint32_t w_op[OR_MAX_OPS]);
+void     or_aos_update(const or_params *, uint32_t op_mask, or_state *st, int64_t inst_best_now);
+int      or_heuristic_perms(const or_inst *, int32_t *out, int cap); /* returns count */
+int      or_init(const or_inst *, const or_params *, or_state *st);
+int      or_run(const or_inst *, const or_params *, or_state *st, uint32_t n_gens);
+uint32_t or_effective_mask(const or_inst *, uint32_t op_mask);
+
+#endif

@@ -1,0 +1,236 @@
+"""Seeded synthetic workloads shared by the oracle and the HIP path.
+
+This module only *makes inputs*: integer instance data, solve parameters and
+request streams.  It holds none of the method's arithmetic (no objective, no
+distance rule, no move, no acceptance test); each side computes those itself.
+
+Problem kinds follow the paper's three encodings (Sec. "Encoding Types"):
+permutation (TSP, QAP, VRPTW giant tour), binary (0/1 knapsack) and bounded
+integer (graph colouring).  The benchmark datasets the paper evaluates on
+(TSPLIB, QAPLIB, Solomon, Pisinger) are not available; the generators below
+stand in for them with the shapes, sizes and value ranges of the workloads
+this project measures.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from fractions import Fraction
+
+import numpy as np
+
+# ---- problem kinds and operator ids (shared vocabulary, no arithmetic) ----
+TSP, QAP, KNAPSACK, VRPTW, INTCOLOR = 1, 2, 3, 4, 5
+KIND_NAMES = {TSP: "tsp", QAP: "qap", KNAPSACK: "knapsack", VRPTW: "vrptw", INTCOLOR: "intcolor"}
+
+OP_2OPT, OP_SWAP, OP_INSERT, OP_OROPT, OP_FLIP, OP_RESET = 0, 1, 2, 3, 4, 5
+OP_NAMES = ["2opt", "swap", "insert", "oropt", "flip", "reset"]
+N_OPS = 6
+PERM_OPS = (1 << OP_2OPT) | (1 << OP_SWAP) | (1 << OP_INSERT) | (1 << OP_OROPT)
+BIN_OPS = 1 << OP_FLIP
+INT_OPS = 1 << OP_RESET
+
+ENCODING_OF = {TSP: "perm", QAP: "perm", VRPTW: "perm", KNAPSACK: "binary", INTCOLOR: "integer"}
+
+
+@dataclass
+class Instance:
+    """One problem's integer data, laid out the way the C interfaces take it.
+
+    TSP      a = coords (n,2) if a_is_coords else distance matrix (n,n); b unused
+    QAP      a = flow F (n,n), b = distance D (n,n), both symmetric
+    KNAPSACK a = weights (n,), b = values (n,), capacity
+    VRPTW    n = customers; a = coords (n+1,2) with the depot at row 0;
+             b = (3, n+1): demand, ready time, due time; capacity, vehicles,
+             service_time, horizon
+    INTCOLOR a = edge list (n_edges, 2); values in [lb, ub]
+    """
+    kind: int
+    n: int
+    a: np.ndarray
+    b: np.ndarray | None = None
+    a_is_coords: int = 0
+    capacity: int = 0
+    vehicles: int = 0
+    service_time: int = 0
+    horizon: int = 0
+    lb: int = 0
+    ub: int = 0
+    n_edges: int = 0
+    key: int = 0
+
+    def __post_init__(self):
+        self.a = np.ascontiguousarray(self.a, dtype=np.int32)
+        if self.b is not None:
+            self.b = np.ascontiguousarray(self.b, dtype=np.int32)
+
+    @property
+    def encoding(self) -> str:
+        return ENCODING_OF[self.kind]
+
+
+@dataclass
+class Params:
+    """Integer-only solve parameters (0 selects the documented default)."""
+    seed: int = 42
+    generations: int = 2000
+    population: int = 64
+    candidates: int = 128
+    op_mask: int = 0
+    t0_q16: int = 0
+    alpha_q32: int = 0
+    epoch: int = 10
+    aos_alpha_q16: int = 49152
+    w_floor_q16: int = 1024
+    stagnation_epochs: int = 5
+    credit: int = 0            # 0: every candidate credits its ops, 1: accepted move only
+    oversample_k: int = 4
+
+    def with_(self, **kw) -> "Params":
+        return replace(self, **kw)
+
+
+def alpha_q32_for(generations: int, final_ratio: Fraction = Fraction(1, 1000)) -> int:
+    """Cooling factor in Q32 so that T shrinks by ``final_ratio`` over the run.
+
+    A schedule choice of the harness (the paper leaves alpha open), computed
+    once here and handed to both sides as the same integer.
+    """
+    from decimal import Decimal, getcontext, ROUND_HALF_EVEN
+    getcontext().prec = 60
+    r = Decimal(final_ratio.numerator) / Decimal(final_ratio.denominator)
+    a = (r.ln() / Decimal(generations)).exp() * (Decimal(2) ** 32)
+    v = int(a.to_integral_value(rounding=ROUND_HALF_EVEN))
+    return min(v, 2**32 - 1)
+
+
+# ---------------------------------------------------------------- generators
+def _rng(*ids) -> np.random.Generator:
+    return np.random.default_rng([int(x) & 0xFFFFFFFF for x in ids] + [20260319])
+
+
+def tsp_uniform(n: int, inst_id: int = 0, key: int | None = None) -> Instance:
+    """TSP with integer coordinates uniform in [0,10000]^2."""
+    r = _rng(1, n, inst_id)
+    xy = r.integers(0, 10001, size=(n, 2))
+    return Instance(TSP, n, xy, a_is_coords=1, key=inst_id if key is None else key)
+
+
+def tsp_clustered(n: int, inst_id: int = 0, clusters: int = 20, sigma: float = 300.0,
+                  key: int | None = None) -> Instance:
+    """TSP with points drawn around ``clusters`` Gaussian centres (stand-in for pcb442)."""
+    r = _rng(2, n, inst_id)
+    centres = r.uniform(0, 10000, size=(clusters, 2))
+    lab = r.integers(0, clusters, size=n)
+    xy = np.clip(np.rint(centres[lab] + r.normal(0, sigma, size=(n, 2))), 0, 10000)
+    return Instance(TSP, n, xy.astype(np.int32), a_is_coords=1,
+                    key=inst_id if key is None else key)
+
+
+def tsp_circle(n: int, radius: int = 4000, key: int = 0) -> Instance:
+    """Planted TSP: points at equal angles on a circle; the angular order is optimal."""
+    ang = 2.0 * np.pi * np.arange(n) / n
+    xy = np.rint(np.stack([5000 + radius * np.cos(ang), 5000 + radius * np.sin(ang)], 1))
+    return Instance(TSP, n, xy.astype(np.int32), a_is_coords=1, key=key)
+
+
+def tsp_matrix(mat: np.ndarray, key: int = 0) -> Instance:
+    mat = np.asarray(mat, dtype=np.int32)
+    return Instance(TSP, mat.shape[0], mat, a_is_coords=0, key=key)
+
+
+def qap_random(n: int, inst_id: int = 0, key: int | None = None) -> Instance:
+    """QAP: symmetric flow U[0,9] and distance U[1,99], zero diagonals."""
+    r = _rng(3, n, inst_id)
+    F = r.integers(0, 10, size=(n, n))
+    D = r.integers(1, 100, size=(n, n))
+    F = np.triu(F, 1); F = F + F.T
+    D = np.triu(D, 1); D = D + D.T
+    return Instance(QAP, n, F, D, key=inst_id if key is None else key)
+
+
+def knapsack_random(n: int, inst_id: int = 0, key: int | None = None) -> Instance:
+    """0/1 knapsack: weights and values U[1,100], capacity half the total weight."""
+    r = _rng(4, n, inst_id)
+    w = r.integers(1, 101, size=n)
+    v = r.integers(1, 101, size=n)
+    return Instance(KNAPSACK, n, w, v, capacity=int(w.sum()) // 2,
+                    key=inst_id if key is None else key)
+
+
+def vrptw_random(n: int = 100, inst_id: int = 0, key: int | None = None,
+                 capacity: int = 200, vehicles: int = 25, service: int = 10,
+                 horizon: int = 1000) -> Instance:
+    """VRPTW: depot at (50,50); half the customers uniform in [0,100]^2, half in
+    5 Gaussian clusters; demand U[1,50]; windows of width U[30,120] that a
+    direct depot round trip can serve.  (Stand-in for the Solomon sets.)"""
+    r = _rng(5, n, inst_id)
+    nu = n // 2
+    uni = r.integers(0, 101, size=(nu, 2)).astype(float)
+    cen = r.uniform(10, 90, size=(5, 2))
+    lab = r.integers(0, 5, size=n - nu)
+    clu = np.clip(np.rint(cen[lab] + r.normal(0, 5.0, size=(n - nu, 2))), 0, 100)
+    xy = np.vstack([[50.0, 50.0], uni, clu]).astype(np.int32)
+    demand = np.concatenate([[0], r.integers(1, 51, size=n)])
+    width = r.integers(30, 121, size=n)
+    # travel-time estimate used only to place the windows (generator-side,
+    # rounded up so every window is reachable from the depot)
+    far = np.ceil(np.hypot(xy[1:, 0] - 50.0, xy[1:, 1] - 50.0)).astype(np.int64)
+    hi = np.maximum(far, horizon - service - far - width)
+    ready = far + np.floor(r.uniform(0, 1, size=n) * (hi - far + 1)).astype(np.int64)
+    due = ready + width
+    b = np.stack([demand,
+                  np.concatenate([[0], ready]),
+                  np.concatenate([[horizon], due])]).astype(np.int32)
+    return Instance(VRPTW, n, xy, b, capacity=capacity, vehicles=vehicles,
+                    service_time=service, horizon=horizon,
+                    key=inst_id if key is None else key)
+
+
+def color_planted(n: int, k: int = 3, m: int | None = None, inst_id: int = 0,
+                  key: int | None = None) -> Instance:
+    """Integer-encoding test problem: a random k-partite graph (so a proper
+    colouring with f=0 exists), colours in [0, k-1]."""
+    r = _rng(6, n, inst_id)
+    part = r.integers(0, k, size=n)
+    m = 3 * n if m is None else m
+    edges = set()
+    tries = 0
+    while len(edges) < m and tries < 50 * m:
+        tries += 1
+        u, v = (int(x) for x in r.integers(0, n, size=2))
+        if u == v or part[u] == part[v]:
+            continue
+        edges.add((min(u, v), max(u, v)))
+    e = np.array(sorted(edges), dtype=np.int32).reshape(-1, 2)
+    return Instance(INTCOLOR, n, e, lb=0, ub=k - 1, n_edges=e.shape[0],
+                    key=inst_id if key is None else key)
+
+
+# ------------------------------------------------------------ named workloads
+PAPER_SEEDS = (42, 123, 456, 789, 2024)
+
+
+def c1_small_tsp(inst_id: int = 0) -> tuple[Instance, Params]:
+    """TSP n=50 uniform, P=64, C=128, 2000 generations, ops {2-opt, swap, or-opt}."""
+    inst = tsp_uniform(50, inst_id)
+    p = Params(seed=PAPER_SEEDS[inst_id % 5], generations=2000, population=64,
+               candidates=128,
+               op_mask=(1 << OP_2OPT) | (1 << OP_SWAP) | (1 << OP_OROPT),
+               alpha_q32=alpha_q32_for(2000))
+    return inst, p
+
+
+def c2_tsp442(population: int, generations: int = 200_000, seed: int = 42) -> tuple[Instance, Params]:
+    """Clustered TSP n=442 (20 clusters, sigma 300), all four permutation ops."""
+    inst = tsp_clustered(442, 0)
+    p = Params(seed=seed, generations=generations, population=population, candidates=128,
+               op_mask=PERM_OPS, alpha_q32=alpha_q32_for(generations))
+    return inst, p
+
+
+def c3_vrptw(seed: int = 42, generations: int = 5000, population: int = 64) -> tuple[Instance, Params]:
+    inst = vrptw_random(100, 0)
+    p = Params(seed=seed, generations=generations, population=population, candidates=128,
+               op_mask=PERM_OPS, alpha_q32=alpha_q32_for(generations))
+    return inst, p
