@@ -1,0 +1,167 @@
+"""Benchmark: move evaluations per second of the population-parallel local
+search on a 442-city clustered TSP, on one MI355X.
+
+One step = one whole solve through the C interface: initialisation
+(oversampled pool, heuristics, selection), all generations (sampling, delta
+evaluation, argmin, acceptance, application, AOS statistics and epoch weight
+updates, cooling) and the fetch of the best tour.  The instance is uploaded to
+HBM before the timed region.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--generations 200000]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "move evals/s on 442-node TSP; mixed-stream solves/s + p50/p99 vs plain"
+
+# LDS bytes one operator step reads during delta evaluation, per staging of the
+# distances: tour entries are 2 bytes; a distance is one int16 matrix entry
+# (LDS_D16) or two 8-byte coordinate pairs (LDS_XY); for GLB_* the distances
+# come through L2 and only the tour is LDS traffic.
+#   2-opt: 4 tour + 4 distances; swap: 6 tour + 8 distances;
+#   insert / or-opt: 6 tour + 6 distances.
+_TOUR = {0: 4, 1: 6, 2: 6, 3: 6}
+_DIST = {0: 4, 1: 8, 2: 6, 3: 6}
+_DIST_BYTES = {1: 2, 2: 16, 3: 0, 4: 0}
+STAGE_NAMES = {1: "int16 distances in LDS", 2: "coordinates in LDS, exact distance recomputed",
+               3: "int16 distances through L2", 4: "int32 distances through L2"}
+
+LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz = 78,643 GB/s
+
+
+def lds_bytes(op_steps, stage):
+    return sum(op_steps[o] * (2 * _TOUR[o] + _DIST_BYTES[stage] * _DIST[o]) for o in range(4))
+
+
+def cpu_baseline(inst, params, seconds: float):
+    """The oracle as it stands, single thread, on a bounded sample: the full
+    population of the same solve for as many generations as fit in about
+    `seconds` (after a 1-generation probe)."""
+    import oracle
+    o = oracle.OracleInstance(inst)
+    st = o.init(params)
+    t = time.perf_counter()
+    o.run(params, st, 1)
+    t1 = time.perf_counter() - t
+    g = max(1, int(seconds / max(t1, 1e-6)) - 1)
+    t = time.perf_counter()
+    o.run(params, st, g)
+    dt = time.perf_counter() - t
+    evals = params.population * params.candidates * g
+    return {"value": evals / dt, "unit": "move evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"same instance and population P={params.population}, C={params.candidates}, "
+                      f"generations {1}..{1 + g} of the solve ({evals} move evals, {dt:.1f} s); "
+                      f"full-recompute objective per candidate"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--generations", type=int, default=200_000)
+    ap.add_argument("--population", type=int, default=0, help="0: autosized")
+    ap.add_argument("--staging", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                          "instances and requests shard across GPUs without exchange, "
+                          "so N > 1 is not measured here"}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    from paper_2603_19163_amd import gx
+
+    inst, p = synth.c2_tsp442(population=0, generations=args.generations)
+    p = p.with_(staging=args.staging)
+    stream = torch.cuda.Stream()
+    ctx = gx.gx_create(0, stream)
+    dev = gx.gx_get_device_info(ctx)
+    h = gx.gx_instance_upload(ctx, inst)
+    P = args.population or gx.gx_autosize_population(ctx, h, p)
+    p = p.with_(population=P)
+
+    def step():
+        job = gx.gx_solve(ctx, h, p)
+        sol, f = gx.gx_fetch_best(ctx, job, inst.n)
+        info = gx.gx_job_info_get(ctx, job)
+        gx.gx_job_free(ctx, job)
+        return f, info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, best = [], None
+    for _ in range(args.steps):
+        best, info = step()
+        infos.append(info)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    evals = sum(i["move_evals"] for i in infos)
+    value = evals / dt
+    stage = infos[-1]["staging"]
+    launches = sum(i["evolve_launches"] for i in infos)
+    ev_ms = sum(i["evolve_ms"] for i in infos)
+    avg_launch_s = ev_ms / 1e3 / launches
+    bytes_total = sum(lds_bytes(i["op_steps"], stage) for i in infos)
+    achieved = bytes_total / launches / avg_launch_s / 1e9
+    k_tot = [sum(i["k_count"][k] for i in infos) for k in range(3)]
+    steps_per_eval = sum((k + 1) * k_tot[k] for k in range(3)) / max(1, sum(k_tot))
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "move evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"TSP n=442, 20 Gaussian clusters (sigma 300) in [0,10000]^2; population "
+                        f"P={P} (autosized, one 64-lane workgroup each), C=128 candidates, "
+                        f"{args.generations} generations, ops 2-opt/swap/insert/or-opt, "
+                        f"AOS epoch 10; {STAGE_NAMES.get(stage, stage)}",
+            "population": P, "candidates": p.candidates, "generations": args.generations,
+            "staging": stage, "device": dev["arch"], "cus": dev["cus"],
+            "best_tour": best, "op_steps_per_eval": round(steps_per_eval, 4),
+        },
+        "roofline": {
+            "bound": "lds",
+            "kernel": "k_evolve<TSP>",
+            "achieved": achieved,
+            "peak": LDS_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / LDS_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_ms": avg_launch_s * 1e3,
+            "launches": launches,
+            "algorithmic_bytes_per_launch": bytes_total / launches,
+        },
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(inst, p, args.cpu_seconds)
+    gx.gx_instance_free(ctx, h)
+    gx.gx_destroy(ctx)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,216 @@
+/* gx.h -- C interface of the MI355X population-parallel local-search engine.
+ *
+ * The engine runs the per-generation evolution step of cuGenOpt (arXiv
+ * 2603.19163, Alg. 1): one HIP workgroup evolves one solution of a
+ * permutation, binary or integer encoding; each generation samples C
+ * composite moves (k in {1,2,3} operators, Tab. "operators"), evaluates their
+ * exact integer objective deltas against instance data staged in LDS, takes
+ * the wavefront argmin, applies simulated-annealing acceptance and collects
+ * adaptive-operator-selection statistics; every E generations the operator
+ * and K-step weights are updated (Eq. ema, Alg. 2).  Initialisation follows
+ * Sec. "Population Management" (oversampled pool with row/column-sum
+ * heuristics).  All arithmetic is integer, and all randomness comes from a
+ * counter-based generator keyed by (seed) with counter (generation, solution,
+ * candidate/slot, instance key), so results are bit-reproducible and
+ * independent of launch shape, batching and scheduling.
+ *
+ * Conventions
+ *  - Every call returns gx_status (GX_OK = 0, negative on error) and never
+ *    throws; gx_last_error(ctx) describes the last failure on that context.
+ *  - The caller owns every host buffer it passes; the library owns every
+ *    device allocation it makes and frees it in the matching *_free call or
+ *    in gx_destroy.
+ *  - All work is ordered on the context's HIP stream (the stream given to
+ *    gx_create, or one the context creates).  Calls that return results to
+ *    host memory synchronise that stream first.
+ *  - A gx_ctx is not thread-safe; use one context per host thread.
+ *  - The library never falls back to a CPU path: without a usable gfx950
+ *    device gx_create fails with GX_E_DEVICE.
+ */
+#ifndef GX_H
+#define GX_H
+#include <stddef.h>
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gx_status;
+enum {
+  GX_OK = 0,
+  GX_E_INVALID = -1,      /* an argument is out of its documented domain */
+  GX_E_UNSUPPORTED = -2,  /* valid, but beyond this build's kernel limits */
+  GX_E_NOMEM = -3,        /* device or host allocation failed */
+  GX_E_DEVICE = -4,       /* a HIP runtime error (message in gx_last_error) */
+  GX_E_NOT_READY = -5,    /* gx_poll: work still running */
+  GX_E_BUSY = -6,         /* admission refused for now (server) */
+  GX_E_CANCELLED = -7
+};
+
+/* Problem kinds; the encoding follows from the kind (Sec. "Encoding Types"). */
+typedef enum {
+  GX_TSP = 1,       /* permutation; symmetric travelling salesman */
+  GX_QAP = 2,       /* permutation; quadratic assignment, p[i] = location of facility i */
+  GX_KNAPSACK = 3,  /* binary; 0/1 knapsack, penalised overweight */
+  GX_VRPTW = 4,     /* permutation of customers (giant tour) split into routes */
+  GX_INTCOLOR = 5   /* integer in [lb, ub]; graph colouring (monochromatic edges) */
+} gx_problem;
+
+/* Operator ids (bit i of op_mask enables operator i). */
+enum {
+  GX_OP_2OPT = 1u << 0,    /* segment reversal */
+  GX_OP_SWAP = 1u << 1,
+  GX_OP_INSERT = 1u << 2,  /* move one element */
+  GX_OP_OROPT = 1u << 3,   /* move a block of 2 or 3 elements, orientation kept */
+  GX_OP_FLIP = 1u << 4,    /* binary: flip one bit */
+  GX_OP_RESET = 1u << 5    /* integer: draw a new value in [lb, ub] */
+};
+
+/* Where a TSP instance's distances live during the evolve kernel. */
+enum {
+  GX_STAGE_AUTO = 0,
+  GX_STAGE_LDS_D16 = 1,  /* int16 distance matrix copied into LDS (n <= 181) */
+  GX_STAGE_LDS_XY = 2,   /* coordinates in LDS, exact integer distance recomputed */
+  GX_STAGE_GLB_D16 = 3,  /* int16 distance matrix read through L2 */
+  GX_STAGE_GLB_D32 = 4   /* int32 distance matrix read through L2 */
+};
+
+typedef struct gx_ctx gx_ctx;
+typedef struct gx_instance gx_instance;
+typedef struct gx_job gx_job;
+
+/* Create a context on device `device_ordinal`.  `hip_stream` is a hipStream_t
+ * to order all work on, or NULL for a stream the context creates and owns.
+ * Fails with GX_E_DEVICE if the device is not a gfx950. */
+gx_status gx_create(int device_ordinal, void *hip_stream, gx_ctx **out);
+/* Free every device allocation of the context (instances, jobs) and the context. */
+gx_status gx_destroy(gx_ctx *ctx);
+/* Text of the last error on `ctx` (valid until the next call on it); never NULL. */
+const char *gx_last_error(const gx_ctx *ctx);
+
+typedef struct {
+  int32_t cus;                 /* compute units */
+  int32_t lds_per_block;       /* bytes of LDS one workgroup may use */
+  int32_t wave_size;
+  int32_t l2_bytes;
+  char arch[64];
+} gx_device_info;
+gx_status gx_get_device_info(gx_ctx *ctx, gx_device_info *out);
+
+/* Instance description.  All arrays are int32, row-major, in host memory
+ * (is_device_ptr = 0) or device memory on the context's device
+ * (is_device_ptr = 1); they are copied before gx_instance_upload returns.
+ *   TSP      a = coordinates n x 2 (a_is_coords = 1) or a symmetric distance
+ *            matrix n x n with zero diagonal and entries in [0, 2^24)
+ *            (a_is_coords = 0).  Distance between coordinates is the nearest
+ *            integer of the Euclidean distance.  Coordinates in [0, 2^14).
+ *   QAP      a = flow F n x n, b = distance D n x n, both symmetric, entries
+ *            in [0, 2^14); f(p) = sum_ij F[i][j] D[p_i][p_j].  n <= 64.
+ *   KNAPSACK a = weights (n), b = values (n), entries in [0, 2^20];
+ *            f(x) = -sum v x + (max v + 1) * max(0, sum w x - capacity).
+ *   VRPTW    n = number of customers; a = coordinates (n+1) x 2, depot in
+ *            row 0; b = demand, ready, due, each (n+1) (3 x (n+1) array);
+ *            capacity, vehicles, service_time, horizon.  Customers are
+ *            visited in tour order and a new route opens whenever the load
+ *            would exceed capacity; f = distance + 100 * total lateness
+ *            + 10000 * max(0, routes - vehicles).  n <= 250; coordinates in
+ *            [0, 2^14), demand in [0, capacity], times in [0, 2^19].
+ *   INTCOLOR a = edge list n_edges x 2 (no self loops); values in [lb, ub];
+ *            f = number of edges whose ends share a value.
+ * instance_key enters every random counter of solves on this instance: keep
+ * it stable for a request, independent of where it runs in a batch. */
+typedef struct {
+  int32_t kind, n, is_device_ptr;
+  const int32_t *a, *b;
+  int32_t a_is_coords, capacity, vehicles, service_time, horizon, lb, ub, n_edges;
+  uint32_t instance_key;
+} gx_instance_desc;
+gx_status gx_instance_upload(gx_ctx *ctx, const gx_instance_desc *desc, gx_instance **out);
+gx_status gx_instance_free(gx_ctx *ctx, gx_instance *inst);
+
+/* Solve parameters; integer only; 0 selects the default in brackets.
+ *  seed            key of the counter-based generator
+ *  generations     generations G to run (>= 1 for gx_solve)
+ *  population      P solutions, one workgroup each [0: sized from the device]
+ *  candidates      C sampled composite moves per solution per generation [128], <= 65536
+ *  op_mask         GX_OP_* bits [all operators of the encoding]
+ *  t0_q16          initial temperature, Q16 [a quarter of |f|/n of the best start]
+ *  alpha_q32       cooling factor per generation, Q32 (required, >= 1)
+ *  aos_epoch       generations E between AOS weight updates [10]
+ *  aos_alpha_q16   EMA factor of the weight update, Q16 [49152 = 0.75]
+ *  w_floor_q16     weight floor, Q16 [1024 = 1/64]
+ *  stagnation_epochs  epochs without improvement of the instance best before
+ *                  the K-step weights reset to (0.8, 0.15, 0.05) [5]
+ *  aos_credit      0 every candidate credits its operators, 1 only the accepted move [0]
+ *  oversample_k    pool of oversample_k * P starting solutions [4]
+ *  staging         GX_STAGE_* for TSP [GX_STAGE_AUTO] */
+typedef struct {
+  uint64_t seed;
+  uint32_t generations, population, candidates, op_mask;
+  uint64_t t0_q16;
+  uint32_t alpha_q32, aos_epoch, aos_alpha_q16, w_floor_q16;
+  uint32_t stagnation_epochs, aos_credit, oversample_k, staging;
+} gx_solve_params;
+
+/* Population the library would use for P = 0 on this instance. */
+gx_status gx_autosize_population(gx_ctx *ctx, const gx_instance *inst, const gx_solve_params *p,
+                                 uint32_t *population_out);
+
+/* Allocate a job and run the initialisation (oversampled pool, heuristics,
+ * selection of the best P, initial temperature and weights) on the stream. */
+gx_status gx_job_create(gx_ctx *ctx, const gx_instance *inst, const gx_solve_params *p, gx_job **out);
+/* Enqueue `n_generations` more generations (asynchronous). */
+gx_status gx_job_advance(gx_ctx *ctx, gx_job *job, uint32_t n_generations);
+/* gx_job_create followed by gx_job_advance(generations). */
+gx_status gx_solve(gx_ctx *ctx, const gx_instance *inst, const gx_solve_params *p, gx_job **out);
+/* Wait for everything enqueued on the context's stream. */
+gx_status gx_wait(gx_ctx *ctx, gx_job *job);
+/* GX_OK if the job's enqueued work has finished, GX_E_NOT_READY otherwise. */
+gx_status gx_poll(gx_ctx *ctx, gx_job *job);
+/* Best solution found (minimum of (best objective, solution index)) into
+ * solution_out[capacity >= n]; synchronises the stream. */
+gx_status gx_fetch_best(gx_ctx *ctx, gx_job *job, int32_t *solution_out, int32_t capacity,
+                        int64_t *objective_out);
+
+typedef struct {
+  uint32_t population, candidates, generations_done, staging;
+  uint64_t move_evals;        /* P * C * generations run */
+  uint64_t accepted;
+  uint32_t evolve_launches;   /* evolve-kernel launches so far */
+  float evolve_ms;            /* device time between the first and last evolve launch of the
+                                 last gx_job_advance (HIP events on the context stream) */
+  uint64_t op_steps[6];       /* operator steps evaluated over the run, per operator id */
+  uint64_t k_count[3];        /* candidates with k = 1, 2, 3 operators over the run */
+} gx_job_info;
+gx_status gx_job_info_get(gx_ctx *ctx, gx_job *job, gx_job_info *out);
+
+/* Scalars of the job state at a generation boundary. */
+typedef struct {
+  uint32_t g, stag;
+  uint64_t T_q16;
+  int64_t epoch_ref;          /* instance best at the start of the current epoch */
+  uint32_t w_op[6], w_k[3], pad_;
+  uint64_t u_op[6], v_op[6], u_k[3], v_k[3];   /* statistics of the current epoch */
+  uint64_t accepted;
+} gx_state_scalars;
+/* Copy the job state to host buffers (any array may be NULL); synchronises.
+ * cur and best are P x n int32, cur_f and best_f P int64. */
+gx_status gx_snapshot(gx_ctx *ctx, gx_job *job, gx_state_scalars *sc, int32_t *cur, int64_t *cur_f,
+                      int32_t *best, int64_t *best_f);
+gx_status gx_job_free(gx_ctx *ctx, gx_job *job);
+
+/* Batched solve: `count` instances with their own parameters, run together
+ * in one persistent launch per AOS epoch (the launch sequence is captured
+ * into a HIP graph).  Each job's result equals the result of gx_solve on the
+ * same instance and parameters.  jobs_out[i] receives job i. */
+gx_status gx_solve_batch(gx_ctx *ctx, const gx_instance *const *insts, const gx_solve_params *params,
+                         int32_t count, gx_job **jobs_out);
+
+/* Exponential tables of the acceptance test (host copies, for checking):
+ * hi[i] = round(2^31 e^-i) for i < 16, lo[j] = round(2^31 e^-(j/256)) for j < 256. */
+gx_status gx_exp_tables(uint32_t hi[16], uint32_t lo[256]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

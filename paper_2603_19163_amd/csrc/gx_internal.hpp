@@ -1,0 +1,101 @@
+// gx_internal.hpp -- device-resident structures shared by the kernels and the
+// host runtime of the gx engine (not part of the public C interface).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gx {
+
+constexpr int kWave = 64;
+constexpr int kOps = 6;
+constexpr int kMaxQapN = 64;
+constexpr int kMaxVrpN = 250;
+constexpr int kMaxCoord = 1 << 14;
+constexpr int64_t kDeltaBias = int64_t(1) << 47;   // argmin key = ((delta + bias) << 16) | t
+
+enum Kind : int32_t { KTSP = 1, KQAP = 2, KKNAP = 3, KVRP = 4, KCOLOR = 5 };
+enum Op : int32_t { O2OPT = 0, OSWAP = 1, OINS = 2, OOROPT = 3, OFLIP = 4, ORESET = 5 };
+enum Stage : int32_t { SAUTO = 0, SLDS16 = 1, SLDSXY = 2, SGLB16 = 3, SGLB32 = 4 };
+
+// One uploaded instance.  All pointers are device pointers owned by the instance.
+struct DevInst {
+  int32_t kind, n, dn, n_edges;
+  int32_t capacity, vehicles, service, horizon;
+  int32_t lb, ub, has_xy, pad0;
+  int64_t lambda;             // knapsack penalty weight
+  const int32_t *xy;          // TSP n x 2 / VRPTW (n+1) x 2 coordinates
+  const int16_t *d16;         // TSP n x n / VRPTW dn x dn distances (int16)
+  const int32_t *d32;         // TSP n x n distances (int32)
+  const int16_t *qf, *qd;     // QAP flow / distance (int16)
+  const int32_t *kw, *kv;     // knapsack weights / values
+  const int32_t *dem, *rdy, *due;  // VRPTW
+  const int32_t *adj_off, *adj;    // colouring CSR (both directions)
+  const int32_t *edges;            // colouring edge list
+};
+
+// One solve.  Scalars below `g` change as the solve runs; the last workgroup of
+// every launch publishes them (see finish_launch in the kernels).
+struct DevJob {
+  const DevInst *inst;
+  uint64_t seed;
+  uint64_t t0_param;
+  uint32_t P, C, G, E;
+  uint32_t op_mask, credit, aos_A, w_floor;
+  uint32_t stag_limit, key, alpha, Q;     // Q = oversample pool size
+  uint32_t stage, lds_bytes, pad1, pad2;
+  // ---- mutable state
+  uint32_t g, g_stop, stag, done;
+  uint64_t T;
+  int64_t epoch_ref, inst_best;
+  uint32_t w_op[kOps], w_k[3], pad3;
+  unsigned long long u_op[kOps], v_op[kOps], u_k[3], v_k[3];
+  unsigned long long accepted;
+  unsigned long long tot_u_op[kOps], tot_u_k[3];   // whole-run usage counts
+  // ---- arrays (device)
+  int32_t *cur, *best;        // P x n
+  int64_t *cur_f, *best_f;    // P
+  int32_t *pool;              // Q x n
+  int64_t *pool_f;            // Q
+  int64_t *sums;              // 2 x n heuristic row/column sums
+  int32_t *best_out;          // n
+  int64_t best_out_f;
+  int32_t best_idx, pad4;
+};
+
+// LDS bytes one evolve workgroup needs for this instance and staging.
+inline uint32_t lds_bytes_for(int kind, int n, int stage) {
+  auto al = [](uint32_t b) { return (b + 15u) & ~15u; };
+  uint32_t un = (uint32_t)n;
+  switch (kind) {
+    case KTSP: {
+      uint32_t b = 2 * al(2 * un);
+      if (stage == SLDS16) b += al(2 * un * un);
+      else if (stage == SLDSXY) b += al(8 * un);
+      return b;
+    }
+    case KQAP: return 2 * al(2 * un) + 2 * al(2 * un * un) + al(2 * kWave * un);
+    case KKNAP: return al(un) + 2 * al(4 * un);
+    case KVRP: return 2 * al(2 * un) + al(2 * (un + 1) * (un + 1)) + 3 * al(4 * (un + 1));
+    default: return al(2 * un) + al(4 * (un + 1));   // + adjacency, added by the caller
+  }
+}
+
+}  // namespace gx
+
+// Launch wrappers implemented in gx_kernels.hip.
+namespace gxk {
+hipError_t set_exp_tables(const uint32_t *hi, const uint32_t *lo);
+hipError_t build_tsp_d16_from_xy(const int32_t *xy, int n, int16_t *d16, hipStream_t s);
+hipError_t build_d32_from_xy(const int32_t *xy, int n, int32_t *d32, hipStream_t s);
+hipError_t init_jobs(gx::DevJob *jobs, int count, uint32_t max_q, int max_n, int max_heur_mats,
+                     hipStream_t s);
+hipError_t set_stop(gx::DevJob *jobs, int count, uint32_t add, int use_total, hipStream_t s);
+hipError_t evolve_plain(gx::DevJob *job, int kind, int stage, uint32_t P, uint32_t lds,
+                        hipStream_t s);
+hipError_t evolve_items(gx::DevJob *jobs, const uint2 *items, uint32_t n_items, uint32_t grid,
+                        uint32_t lds, hipStream_t s);
+hipError_t fetch_best(gx::DevJob *jobs, int count, hipStream_t s);
+hipError_t prepare_kernel_attrs(uint32_t max_lds);
+hipError_t occupancy_plain(int kind, int stage, uint32_t lds, int *blocks_per_cu);
+hipError_t occupancy_items(uint32_t lds, int *blocks_per_cu);
+}  // namespace gxk

@@ -1,0 +1,1178 @@
+// gx_kernels.hip -- gfx950 kernels of the population-parallel local search.
+//
+// One 64-lane workgroup (a single wavefront) evolves one solution (paper,
+// Sec. "GPU Parallelization Strategy": one block per solution).  Per
+// generation (Alg. 1) every lane samples ceil(C/64) composite moves, evaluates
+// their exact integer deltas against the solution and instance data held in
+// LDS, the wave takes the lexicographic argmin of (delta, candidate) with DPP
+// shuffles, and the acceptance test, the move application and the AOS
+// bookkeeping follow in wave-uniform control flow.  Candidates are never
+// copied: a composite of k <= 3 operators is a chain of position maps, and a
+// position of the candidate is read as s[psi_1(psi_2(psi_3(p)))].
+//
+// A launch runs the generations up to the next AOS epoch boundary for every
+// solution of every job it covers; the last workgroup of a job to finish
+// folds the job's statistics into the EMA weight update (Eq. ema, Alg. 2).
+#include "gx_internal.hpp"
+
+using namespace gx;
+
+__constant__ uint32_t c_exp_hi[16];
+__constant__ uint32_t c_exp_lo[256];
+
+namespace {
+
+// ------------------------------------------------------------------ RNG
+// Philox4x32-10 (Salmon et al., SC'11); counter (generation, solution,
+// 4*candidate + slot, instance key), key = the 64-bit seed.
+__device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1, uint32_t r[4]) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    c0 = hi1 ^ c1 ^ k0;
+    c1 = lo1;
+    c2 = hi0 ^ c3 ^ k1;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  r[0] = c0; r[1] = c1; r[2] = c2; r[3] = c3;
+}
+
+// integer in [0, m) from a 32-bit draw: floor(w * m / 2^32)
+__device__ __forceinline__ uint32_t rmap(uint32_t w, uint32_t m) { return __umulhi(w, m); }
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x; }
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+  return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+
+// Wave-uniform parameters of one job.
+struct Uni {
+  uint32_t n, C, key, k0, k1, credit, alpha;
+  int32_t lb, ub;
+  uint32_t w[kOps], sw;
+  uint32_t wk[3], swk;
+};
+
+struct Step {
+  int op, a, b, c;
+};
+
+// weighted choice from Q16 weights: u = floor(u16 * S / 2^16); smallest i with u < cumsum_i
+__device__ __forceinline__ int pick_op(uint32_t u16, const Uni &U) {
+  const uint32_t u = (uint32_t)(((uint64_t)u16 * U.sw) >> 16);
+  uint32_t c = U.w[0];
+  int r = (c <= u);
+  c += U.w[1]; r += (c <= u);
+  c += U.w[2]; r += (c <= u);
+  c += U.w[3]; r += (c <= u);
+  c += U.w[4]; r += (c <= u);
+  return r;
+}
+
+// ENC: 0 permutation, 1 binary, 2 integer
+template <int ENC>
+__device__ __forceinline__ Step make_step(int op, uint32_t r1, uint32_t r2, uint32_t r3, const Uni &U) {
+  Step s;
+  s.op = op;
+  s.c = 0;
+  const uint32_t n = U.n;
+  if (ENC == 0) {
+    if (n < 2) {
+      s.a = s.b = 0;
+    } else if (op == O2OPT || op == OSWAP) {
+      const uint32_t i = rmap(r1, n);
+      uint32_t j = rmap(r2, n - 1);
+      j += (j >= i);
+      s.a = (int)min(i, j);
+      s.b = (int)max(i, j);
+    } else {
+      uint32_t L = (op == OINS) ? 1u : 2u + rmap(r3, 2u);
+      L = min(L, n - 1);
+      const uint32_t i = rmap(r1, n - L + 1);
+      uint32_t q = rmap(r2, n - L);
+      q += (q >= i);
+      s.a = (int)i;
+      s.b = (int)q;
+      s.c = (int)L;
+    }
+  } else if (ENC == 1) {
+    s.a = (int)rmap(r1, n);
+    s.b = 0;
+  } else {
+    s.a = (int)rmap(r1, n);
+    s.b = U.lb + (int)rmap(r2, (uint32_t)(U.ub - U.lb + 1));
+  }
+  return s;
+}
+
+// Sample candidate t of generation g (Alg. 1: k from w_K, then k operators
+// from the operator weights).  Returns k.
+template <int ENC>
+__device__ __forceinline__ int sample(const Uni &U, uint32_t g, uint32_t sol, uint32_t t, Step st[3]) {
+  uint32_t r[4];
+  philox(g, sol, t << 2, U.key, U.k0, U.k1, r);
+  const uint32_t u = (uint32_t)(((uint64_t)(r[0] >> 16) * U.swk) >> 16);
+  const int k = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
+  st[0] = make_step<ENC>(pick_op(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+  if (k > 1) {
+    philox(g, sol, (t << 2) | 1u, U.key, U.k0, U.k1, r);
+    st[1] = make_step<ENC>(pick_op(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+  }
+  if (k > 2) {
+    philox(g, sol, (t << 2) | 2u, U.key, U.k0, U.k1, r);
+    st[2] = make_step<ENC>(pick_op(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+  }
+  return k;
+}
+
+// Position map of one permutation step: the element at position p after the
+// step was at psi(p) before it.
+__device__ __forceinline__ int psi(const Step &s, int p) {
+  if (s.op == O2OPT) return (p >= s.a && p <= s.b) ? s.a + s.b - p : p;
+  if (s.op == OSWAP) return p == s.a ? s.b : (p == s.b ? s.a : p);
+  const int i = s.a, q = s.b, L = s.c;
+  if (q < i) {
+    if (p < q || p >= i + L) return p;
+    return p < q + L ? i + (p - q) : p - L;
+  }
+  if (p < i || p >= q + L) return p;
+  return p < q ? p + L : i + (p - q);
+}
+
+// position in the current solution of position p after the first m steps
+__device__ __forceinline__ int chain(const Step *st, int m, int p) {
+  if (m > 2) p = psi(st[2], p);
+  if (m > 1) p = psi(st[1], p);
+  if (m > 0) p = psi(st[0], p);
+  return p;
+}
+
+// ------------------------------------------------------------ statistics
+struct LStats {
+  uint32_t u[kOps], v[kOps], uk[3], vk[3];
+};
+
+template <int ENC>
+__device__ __forceinline__ void credit(LStats &S, const Step *st, int k, bool imp) {
+  constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
+  constexpr int hi = ENC == 0 ? OOROPT : lo;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    if (m < k) {
+#pragma unroll
+      for (int o = lo; o <= hi; ++o) {
+        const uint32_t hit = st[m].op == o;
+        S.u[o] += hit;
+        S.v[o] += hit & (uint32_t)imp;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const uint32_t hit = (k == q + 1);
+    S.uk[q] += hit;
+    S.vk[q] += hit & (uint32_t)imp;
+  }
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_min(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long w = __shfl_xor(v, o, 64);
+    v = w < v ? w : v;
+  }
+  return v;
+}
+
+// ------------------------------------------------------------ acceptance, cooling
+// Alg. 1: accept when delta < 0 or rand() < e^{-delta/T}; delta = 0 is
+// accepted.  e^{-delta/T} comes from the integer tables at z = floor(256
+// delta / T) (T in Q16), compared with a 31-bit draw.
+__device__ __forceinline__ bool accept_worse(int64_t ds, uint64_t T, uint32_t g, uint32_t sol, const Uni &U) {
+  if (T == 0) return false;
+  const uint64_t z = ((uint64_t)ds << 24) / T;
+  if (z >= 4096) return false;
+  const uint32_t p = (uint32_t)(((uint64_t)c_exp_hi[z >> 8] * c_exp_lo[z & 255]) >> 31);
+  uint32_t r[4];
+  philox(g, sol, 0xFFFFFFFFu, U.key, U.k0, U.k1, r);
+  return (r[0] >> 1) < p;
+}
+
+// T <- floor(T * alpha / 2^32) in 64-bit pieces (Alg. 1, T <- alpha T)
+__device__ __forceinline__ uint64_t cool(uint64_t t, uint32_t a) {
+  return (t >> 32) * a + (((t & 0xFFFFFFFFull) * a) >> 32);
+}
+
+// ------------------------------------------------------------ LDS staging
+__device__ __forceinline__ uint32_t al16(uint32_t b) { return (b + 15u) & ~15u; }
+
+// copy `bytes` (rounded up to 16; both buffers padded to 16) global -> LDS
+__device__ __forceinline__ void stage16(void *dst, const void *src, uint32_t bytes) {
+  const uint4 *s = (const uint4 *)src;
+  uint4 *d = (uint4 *)dst;
+  const uint32_t cnt = al16(bytes) >> 4;
+  for (uint32_t i = lane_id(); i < cnt; i += kWave) d[i] = s[i];
+}
+
+// exact nearest-integer Euclidean distance for coordinates in [0, 2^14):
+// (isqrt(4 s) + 1) / 2 with the float estimate of the root corrected by one
+// step either way
+__device__ __forceinline__ int nint_dist(int2 p, int2 q) {
+  const int dx = p.x - q.x, dy = p.y - q.y;
+  const uint32_t s4 = 4u * (uint32_t)(dx * dx + dy * dy);
+  uint32_t r = (uint32_t)sqrtf((float)s4);
+  r -= (r * r > s4);
+  r += ((r + 1) * (r + 1) <= s4);
+  return (int)((r + 1) >> 1);
+}
+
+struct DistL16 {
+  const int16_t *d;
+  int n;
+  __device__ __forceinline__ int operator()(int a, int b) const { return d[a * n + b]; }
+};
+struct DistXY {
+  const int2 *xy;
+  __device__ __forceinline__ int operator()(int a, int b) const { return nint_dist(xy[a], xy[b]); }
+};
+struct DistG16 {
+  const int16_t *__restrict__ d;
+  int n;
+  __device__ __forceinline__ int operator()(int a, int b) const { return d[a * n + b]; }
+};
+struct DistG32 {
+  const int32_t *__restrict__ d;
+  int n;
+  __device__ __forceinline__ int operator()(int a, int b) const { return d[a * n + b]; }
+};
+
+// ------------------------------------------------------------ permutation apply
+__device__ __forceinline__ void perm_apply(uint16_t *&cur, uint16_t *&nxt, int n, const Step *st, int k) {
+  for (int p = lane_id(); p < n; p += kWave) nxt[p] = cur[chain(st, k, p)];
+  __syncthreads();
+  uint16_t *t = cur;
+  cur = nxt;
+  nxt = t;
+}
+
+__device__ __forceinline__ void perm_store(const uint16_t *cur, int n, int32_t *dst) {
+  for (int p = lane_id(); p < n; p += kWave) dst[p] = cur[p];
+}
+
+// ------------------------------------------------------------ TSP
+// delta of step m on the tour after steps 0..m-1 (symmetric distances)
+template <class DF>
+__device__ __forceinline__ int tsp_step(const Step *st, int m, const uint16_t *tour, int n, const DF &D) {
+  const Step s = st[m];
+  auto X = [&](int p) -> int { return tour[chain(st, m, p)]; };
+  if (s.op == O2OPT) {  // reverse [lo, hi]: edges (lo-1, lo) and (hi, hi+1) change
+    const int lo = s.a, hi = s.b;
+    if (hi - lo >= n - 1) return 0;
+    const int a = X(lo == 0 ? n - 1 : lo - 1), b = X(lo), c = X(hi), d = X(hi == n - 1 ? 0 : hi + 1);
+    return D(a, c) + D(b, d) - D(a, b) - D(c, d);
+  }
+  if (s.op == OSWAP) {  // edges lo-1, lo, hi-1, hi (positional, deduplicated)
+    const int lo = s.a, hi = s.b;
+    const bool wrap = (lo == 0 && hi == n - 1), adj = (hi == lo + 1);
+    const int vl = X(lo), vh = X(hi);
+    const int vm = X(lo == 0 ? n - 1 : lo - 1), vlp = X(lo + 1);
+    const int vhm = X(hi - 1), vhp = X(hi == n - 1 ? 0 : hi + 1);
+    int d = D(wrap ? vl : vm, vh) - D(vm, vl);
+    d += D(vh, adj ? vl : vlp) - D(vl, vlp);
+    if (!adj) d += D(vhm, vl) - D(vhm, vh);
+    if (!wrap) d += D(vl, vhp) - D(vh, vhp);
+    return d;
+  }
+  // insert / or-opt: block [i, i+L) moved to start at q; three edges change,
+  // unless the move is a rotation of the whole tour
+  const int i = s.a, q = s.b, L = s.c;
+  if (L == 0) return 0;
+  if ((q < i && q == 0 && i + L == n) || (q > i && i == 0 && q + L == n)) return 0;
+  const int xi = X(i), xe = X(i + L - 1);
+  const int xim = X(i == 0 ? n - 1 : i - 1);
+  const int xn = X(i + L == n ? 0 : i + L);
+  if (q < i) {
+    const int xqm = X(q == 0 ? n - 1 : q - 1), xq = X(q);
+    return D(xqm, xi) + D(xe, xq) + D(xim, xn) - D(xqm, xq) - D(xim, xi) - D(xe, xn);
+  }
+  const int xql = X(q + L - 1), xqn = X(q + L == n ? 0 : q + L);
+  return D(xim, xn) + D(xql, xi) + D(xe, xqn) - D(xim, xi) - D(xe, xn) - D(xql, xqn);
+}
+
+template <class DF>
+struct TspK {
+  static constexpr int ENC = 0;
+  uint16_t *cur, *nxt;
+  int n;
+  DF D;
+  __device__ __forceinline__ int64_t delta(const Step *st, int k, int64_t) const {
+    if (n < 2) return 0;
+    int d = tsp_step(st, 0, cur, n, D);
+    if (k > 1) d += tsp_step(st, 1, cur, n, D);
+    if (k > 2) d += tsp_step(st, 2, cur, n, D);
+    return d;
+  }
+  __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, n, st, k); }
+  __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
+};
+
+// ------------------------------------------------------------ QAP
+// delta = sum_{a in X} sum_b m_b F[a][b] (D[y_a][y_b] - D[x_a][x_b]), X the
+// changed positions, y the candidate, m_b = 1 inside X and 2 outside (F, D symmetric)
+struct QapK {
+  static constexpr int ENC = 0;
+  uint16_t *cur, *nxt;
+  int n;
+  const int16_t *F, *D;
+  uint16_t *xr;  // candidate rows, element b of lane l at xr[b * 64 + l]
+  __device__ __forceinline__ int64_t delta(const Step *st, int k, int64_t) const {
+    if (n < 2) return 0;
+    const uint32_t l = lane_id();
+    uint64_t mask = 0;
+    for (int p = 0; p < n; ++p) {
+      const int v = cur[chain(st, k, p)];
+      xr[p * kWave + l] = (uint16_t)v;
+      mask |= (uint64_t)(v != cur[p]) << p;
+    }
+    int64_t d = 0;
+    uint64_t rem = mask;
+    while (rem) {
+      const int a = __builtin_ctzll(rem);
+      rem &= rem - 1;
+      const int xa = cur[a], ya = xr[a * kWave + l];
+      const int16_t *Fa = F + a * n, *Dy = D + ya * n, *Dx = D + xa * n;
+      int64_t acc = 0;
+      for (int b = 0; b < n; ++b) {
+        const int t = Fa[b] * (Dy[xr[b * kWave + l]] - Dx[cur[b]]);
+        acc += ((mask >> b) & 1) ? t : 2 * t;
+      }
+      d += acc;
+    }
+    return d;
+  }
+  __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, n, st, k); }
+  __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
+};
+
+// ------------------------------------------------------------ VRPTW (giant tour)
+struct VrpK {
+  static constexpr int ENC = 0;
+  uint16_t *cur, *nxt;
+  int n, dn, cap, veh, svc, hor;
+  const int16_t *D;
+  const int32_t *dem, *rdy, *due;
+  __device__ __forceinline__ int64_t eval(const Step *st, int k) const {
+    int64_t dist = 0, late = 0;
+    int t = 0, load = 0, routes = 0, prev = 0;
+    for (int p = 0; p < n; ++p) {
+      const int c = cur[chain(st, k, p)] + 1;
+      const int q = dem[c];
+      if (routes == 0 || load + q > cap) {
+        if (routes > 0) {
+          const int back = D[prev * dn];
+          dist += back;
+          t += back;
+          late += max(0, t - hor);
+        }
+        ++routes;
+        load = 0;
+        t = 0;
+        prev = 0;
+      }
+      const int dd = D[prev * dn + c];
+      dist += dd;
+      t = max(t + dd, rdy[c]);
+      late += max(0, t - due[c]);
+      t += svc;
+      load += q;
+      prev = c;
+    }
+    if (routes > 0) {
+      const int back = D[prev * dn];
+      dist += back;
+      t += back;
+      late += max(0, t - hor);
+    }
+    return dist + 100 * late + 10000 * (int64_t)max(0, routes - veh);
+  }
+  __device__ __forceinline__ int64_t delta(const Step *st, int k, int64_t f) const {
+    return eval(st, k) - f;
+  }
+  __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, n, st, k); }
+  __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
+};
+
+// ------------------------------------------------------------ 0/1 knapsack
+struct KnapK {
+  static constexpr int ENC = 1;
+  uint8_t *bits;
+  const int32_t *w, *v;
+  int n;
+  int64_t W, V, cap, lam;
+  __device__ __forceinline__ void dwv(const Step *st, int k, int64_t &dW, int64_t &dV) const {
+    dW = 0;
+    dV = 0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      if (m < k) {
+        const int i = st[m].a;
+        int b = bits[i];
+        if (m > 0 && st[0].a == i) b ^= 1;
+        if (m > 1 && st[1].a == i) b ^= 1;
+        const int sg = b ? -1 : 1;
+        dW += sg * w[i];
+        dV += sg * v[i];
+      }
+    }
+  }
+  __device__ __forceinline__ int64_t fval(int64_t W2, int64_t V2) const {
+    const int64_t over = W2 - cap;
+    return -V2 + lam * (over > 0 ? over : 0);
+  }
+  __device__ __forceinline__ int64_t delta(const Step *st, int k, int64_t f) const {
+    int64_t dW, dV;
+    dwv(st, k, dW, dV);
+    return fval(W + dW, V + dV) - f;
+  }
+  __device__ __forceinline__ void apply(const Step *st, int k) {
+    int64_t dW, dV;
+    dwv(st, k, dW, dV);
+    W += dW;
+    V += dV;
+    if (lane_id() == 0)
+      for (int m = 0; m < k; ++m) bits[st[m].a] ^= 1;
+    __syncthreads();
+  }
+  __device__ __forceinline__ void store(int32_t *dst) const {
+    for (int p = lane_id(); p < n; p += kWave) dst[p] = bits[p];
+  }
+};
+
+// ------------------------------------------------------------ integer colouring
+struct ColorK {
+  static constexpr int ENC = 2;
+  int16_t *val;
+  const int32_t *off, *adj;
+  int n;
+  __device__ __forceinline__ int vb(const Step *st, int m, int p) const {
+    int v = val[p];
+    if (m > 0 && st[0].a == p) v = st[0].b;
+    if (m > 1 && st[1].a == p) v = st[1].b;
+    return v;
+  }
+  __device__ __forceinline__ int64_t delta(const Step *st, int k, int64_t) const {
+    int d = 0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      if (m < k) {
+        const int i = st[m].a, nv = st[m].b, ov = vb(st, m, i);
+        for (int e = off[i]; e < off[i + 1]; ++e) {
+          const int vj = vb(st, m, adj[e]);
+          d += (nv == vj) - (ov == vj);
+        }
+      }
+    }
+    return d;
+  }
+  __device__ __forceinline__ void apply(const Step *st, int k) {
+    if (lane_id() == 0)
+      for (int m = 0; m < k; ++m) val[st[m].a] = (int16_t)st[m].b;
+    __syncthreads();
+  }
+  __device__ __forceinline__ void store(int32_t *dst) const {
+    for (int p = lane_id(); p < n; p += kWave) dst[p] = val[p];
+  }
+};
+
+// ------------------------------------------------------------ generation loop
+template <class KD>
+__device__ __forceinline__ void run_gens(KD &kd, const Uni &U, int32_t *best_row, uint32_t sol, uint32_t g0,
+                                         uint32_t g1, uint64_t &T, int64_t &f, int64_t &bf, LStats &S,
+                                         uint32_t &nacc) {
+  constexpr int ENC = KD::ENC;
+  const uint32_t lane = lane_id();
+  const uint32_t NR = (U.C + kWave - 1) / kWave;
+  for (uint32_t g = g0; g < g1; ++g) {
+    unsigned long long bk = ~0ull;
+    for (uint32_t r = 0; r < NR; ++r) {
+      const uint32_t t = r * kWave + lane;
+      if (t < U.C) {
+        Step st[3];
+        const int k = sample<ENC>(U, g, sol, t, st);
+        const int64_t d = kd.delta(st, k, f);
+        if (U.credit == 0) credit<ENC>(S, st, k, d < 0);
+        const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | t;
+        bk = key < bk ? key : bk;
+      }
+    }
+    bk = uni64(wave_min(bk));
+    const uint32_t ts = (uint32_t)(bk & 0xFFFFu);
+    const int64_t ds = (int64_t)(bk >> 16) - kDeltaBias;
+    bool acc = ds <= 0;
+    if (!acc) acc = accept_worse(ds, T, g, sol, U);
+    if (acc) {
+      Step st[3];
+      const int k = sample<ENC>(U, g, sol, ts, st);
+      if (U.credit == 1 && lane == 0) credit<ENC>(S, st, k, ds < 0);
+      kd.apply(st, k);
+      f += ds;
+      ++nacc;
+      if (f < bf) {
+        bf = f;
+        kd.store(best_row);
+      }
+    }
+    T = cool(T, U.alpha);
+  }
+}
+
+// ------------------------------------------------------------ epoch close
+// Eq. ema per enabled operator and per K-step, clamp to [floor, 1], normalise;
+// stagnation of the instance best resets the K-step weights (Alg. 2).
+__device__ void ema_group(uint32_t *w, const unsigned long long *u, const unsigned long long *v, uint32_t mask,
+                          int cnt, uint32_t A, uint32_t FL) {
+  uint64_t s = 0;
+  for (int i = 0; i < cnt; ++i) {
+    if (!(mask & (1u << i))) continue;
+    const uint64_t uu = __hip_atomic_load(&u[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t vv = __hip_atomic_load(&v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t r = (vv << 16) / (uu + 1);
+    uint64_t nw = ((uint64_t)A * w[i] + (uint64_t)(65536 - A) * (r + FL)) >> 16;
+    nw = nw < FL ? FL : (nw > 65536 ? 65536 : nw);
+    w[i] = (uint32_t)nw;
+    s += nw;
+  }
+  for (int i = 0; i < cnt; ++i) {
+    if (!(mask & (1u << i))) continue;
+    const uint64_t nw = ((uint64_t)w[i] << 16) / s;
+    w[i] = (uint32_t)(nw < 1 ? 1 : nw);
+  }
+}
+
+__device__ void epoch_close(DevJob *J, uint32_t g1, uint64_t T_end) {
+  if (g1 % J->E == 0) {
+    ema_group(J->w_op, J->u_op, J->v_op, J->op_mask, kOps, J->aos_A, J->w_floor);
+    ema_group(J->w_k, J->u_k, J->v_k, 7u, 3, J->aos_A, J->w_floor);
+    const int64_t ib = (int64_t)__hip_atomic_load((unsigned long long *)&J->inst_best, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+    if (ib < J->epoch_ref) J->stag = 0;
+    else J->stag += 1;
+    J->epoch_ref = ib;
+    if (J->stag >= J->stag_limit) {
+      J->w_k[0] = 52429; J->w_k[1] = 9830; J->w_k[2] = 3277;
+      J->stag = 0;
+    }
+    for (int i = 0; i < kOps; ++i) {
+      __hip_atomic_store(&J->u_op[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&J->v_op[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    for (int i = 0; i < 3; ++i) {
+      __hip_atomic_store(&J->u_k[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&J->v_k[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  J->T = T_end;
+  J->g = g1;
+  __hip_atomic_store(&J->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int ENC>
+__device__ void finish_launch(DevJob *J, const LStats &S, uint32_t nacc, int64_t bf, uint32_t g1, uint64_t T_end) {
+  constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
+  constexpr int hi = ENC == 0 ? OOROPT : lo;
+  uint32_t u[kOps] = {0}, v[kOps] = {0}, uk[3], vk[3];
+#pragma unroll
+  for (int o = lo; o <= hi; ++o) {
+    u[o] = wave_sum(S.u[o]);
+    v[o] = wave_sum(S.v[o]);
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    uk[q] = wave_sum(S.uk[q]);
+    vk[q] = wave_sum(S.vk[q]);
+  }
+  if (lane_id() == 0) {
+    for (int o = lo; o <= hi; ++o) {
+      if (u[o]) atomicAdd(&J->u_op[o], (unsigned long long)u[o]);
+      if (v[o]) atomicAdd(&J->v_op[o], (unsigned long long)v[o]);
+    }
+    for (int q = 0; q < 3; ++q) {
+      if (uk[q]) atomicAdd(&J->u_k[q], (unsigned long long)uk[q]);
+      if (vk[q]) atomicAdd(&J->v_k[q], (unsigned long long)vk[q]);
+    }
+    if (J->credit == 0) {   // whole-run operator usage of the evaluated candidates
+      for (int o = lo; o <= hi; ++o)
+        if (u[o]) atomicAdd(&J->tot_u_op[o], (unsigned long long)u[o]);
+      for (int q = 0; q < 3; ++q)
+        if (uk[q]) atomicAdd(&J->tot_u_k[q], (unsigned long long)uk[q]);
+    }
+    if (nacc) atomicAdd(&J->accepted, (unsigned long long)nacc);
+    atomicMin((long long *)&J->inst_best, (long long)bf);
+    __threadfence();
+    const uint32_t prev = atomicAdd(&J->done, 1u);
+    if (prev == J->P - 1) {
+      __threadfence();
+      epoch_close(J, g1, T_end);
+      __threadfence();
+    }
+  }
+}
+
+// ------------------------------------------------------------ one workgroup
+template <int KIND, int STAGE>
+__device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
+  const uint32_t g0 = uni(J->g), gstop = uni(J->g_stop);
+  if (g0 >= gstop) return;
+  const uint32_t E = J->E;
+  const uint32_t g1 = min(gstop, (g0 / E + 1) * E);
+  const DevInst *I = J->inst;
+  const int n = I->n;
+  Uni U;
+  U.n = (uint32_t)n;
+  U.C = J->C;
+  U.key = J->key;
+  U.k0 = (uint32_t)J->seed;
+  U.k1 = (uint32_t)(J->seed >> 32);
+  U.credit = J->credit;
+  U.alpha = J->alpha;
+  U.lb = I->lb;
+  U.ub = I->ub;
+  U.sw = 0;
+#pragma unroll
+  for (int i = 0; i < kOps; ++i) {
+    U.w[i] = J->w_op[i];
+    U.sw += U.w[i];
+  }
+  U.swk = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    U.wk[i] = J->w_k[i];
+    U.swk += U.wk[i];
+  }
+  uint64_t T = J->T;
+  int64_t f = J->cur_f[sol], bf = J->best_f[sol];
+  LStats S = {};
+  uint32_t nacc = 0;
+  const uint32_t lane = lane_id();
+  int32_t *cur_g = J->cur + (size_t)sol * n;
+  int32_t *best_row = J->best + (size_t)sol * n;
+
+  if constexpr (KIND == KTSP || KIND == KQAP || KIND == KVRP) {
+    uint16_t *t0 = (uint16_t *)lds;
+    uint16_t *t1 = (uint16_t *)(lds + al16(2 * n));
+    char *rest = lds + 2 * al16(2 * n);
+    for (int p = lane; p < n; p += kWave) t0[p] = (uint16_t)cur_g[p];
+    if constexpr (KIND == KTSP) {
+      if constexpr (STAGE == SLDS16) {
+        stage16(rest, I->d16, 2u * n * n);
+        __syncthreads();
+        TspK<DistL16> kd{t0, t1, n, DistL16{(const int16_t *)rest, n}};
+        run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        perm_store(kd.cur, n, cur_g);
+      } else if constexpr (STAGE == SLDSXY) {
+        stage16(rest, I->xy, 8u * n);
+        __syncthreads();
+        TspK<DistXY> kd{t0, t1, n, DistXY{(const int2 *)rest}};
+        run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        perm_store(kd.cur, n, cur_g);
+      } else if constexpr (STAGE == SGLB16) {
+        __syncthreads();
+        TspK<DistG16> kd{t0, t1, n, DistG16{I->d16, n}};
+        run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        perm_store(kd.cur, n, cur_g);
+      } else {
+        __syncthreads();
+        TspK<DistG32> kd{t0, t1, n, DistG32{I->d32, n}};
+        run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        perm_store(kd.cur, n, cur_g);
+      }
+    } else if constexpr (KIND == KQAP) {
+      int16_t *F = (int16_t *)rest;
+      int16_t *D = (int16_t *)(rest + al16(2 * n * n));
+      uint16_t *xr = (uint16_t *)(rest + 2 * al16(2 * n * n));
+      stage16(F, I->qf, 2u * n * n);
+      stage16(D, I->qd, 2u * n * n);
+      __syncthreads();
+      QapK kd{t0, t1, n, F, D, xr};
+      run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+      perm_store(kd.cur, n, cur_g);
+    } else {
+      const int dn = n + 1;
+      int16_t *D = (int16_t *)rest;
+      int32_t *dem = (int32_t *)(rest + al16(2 * dn * dn));
+      int32_t *rdy = dem + al16(4 * dn) / 4;
+      int32_t *due = rdy + al16(4 * dn) / 4;
+      stage16(D, I->d16, 2u * dn * dn);
+      stage16(dem, I->dem, 4u * dn);
+      stage16(rdy, I->rdy, 4u * dn);
+      stage16(due, I->due, 4u * dn);
+      __syncthreads();
+      VrpK kd{t0, t1, n, dn, I->capacity, I->vehicles, I->service, I->horizon, D, dem, rdy, due};
+      run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+      perm_store(kd.cur, n, cur_g);
+    }
+  } else if constexpr (KIND == KKNAP) {
+    uint8_t *bits = (uint8_t *)lds;
+    int32_t *w = (int32_t *)(lds + al16(n));
+    int32_t *v = w + al16(4 * n) / 4;
+    int64_t pw = 0, pv = 0;
+    for (int p = lane; p < n; p += kWave) {
+      const int b = cur_g[p];
+      bits[p] = (uint8_t)b;
+      pw += b ? I->kw[p] : 0;
+      pv += b ? I->kv[p] : 0;
+    }
+    stage16(w, I->kw, 4u * n);
+    stage16(v, I->kv, 4u * n);
+    const int64_t W = wave_sum64(pw), V = wave_sum64(pv);
+    __syncthreads();
+    KnapK kd{bits, w, v, n, (int64_t)uni64((uint64_t)W), (int64_t)uni64((uint64_t)V), I->capacity, I->lambda};
+    run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+    kd.store(cur_g);
+  } else {
+    int16_t *val = (int16_t *)lds;
+    int32_t *off = (int32_t *)(lds + al16(2 * n));
+    int32_t *adj = off + al16(4 * (n + 1)) / 4;
+    for (int p = lane; p < n; p += kWave) val[p] = (int16_t)cur_g[p];
+    stage16(off, I->adj_off, 4u * (n + 1));
+    stage16(adj, I->adj, 8u * I->n_edges);
+    __syncthreads();
+    ColorK kd{val, off, adj, n};
+    run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+    kd.store(cur_g);
+  }
+  if (lane == 0) {
+    J->cur_f[sol] = f;
+    J->best_f[sol] = bf;
+  }
+  constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : 0);
+  finish_launch<ENC>(J, S, nacc, bf, g1, T);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ evolve kernels
+template <int KIND, int STAGE>
+__global__ __launch_bounds__(64) void k_evolve(DevJob *job) {
+  extern __shared__ __align__(16) char lds[];
+  evolve_wg<KIND, STAGE>(job, blockIdx.x, lds);
+}
+
+// Persistent walk over (job, solution) work items of many jobs of any kinds.
+__global__ __launch_bounds__(64) void k_evolve_items(DevJob *jobs, const uint2 *items, uint32_t n_items) {
+  extern __shared__ __align__(16) char lds[];
+  for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const uint2 w = items[it];
+    DevJob *J = jobs + w.x;
+    const int kind = J->inst->kind;
+    const int stage = (int)J->stage;
+    if (kind == KTSP) {
+      if (stage == SLDS16) evolve_wg<KTSP, SLDS16>(J, w.y, lds);
+      else if (stage == SLDSXY) evolve_wg<KTSP, SLDSXY>(J, w.y, lds);
+      else if (stage == SGLB16) evolve_wg<KTSP, SGLB16>(J, w.y, lds);
+      else evolve_wg<KTSP, SGLB32>(J, w.y, lds);
+    } else if (kind == KQAP) {
+      evolve_wg<KQAP, 0>(J, w.y, lds);
+    } else if (kind == KKNAP) {
+      evolve_wg<KKNAP, 0>(J, w.y, lds);
+    } else if (kind == KVRP) {
+      evolve_wg<KVRP, 0>(J, w.y, lds);
+    } else {
+      evolve_wg<KCOLOR, 0>(J, w.y, lds);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ initialisation
+namespace {
+
+__device__ __forceinline__ int glb_tsp_dist(const DevInst *I, int a, int b) {
+  const int n = I->n;
+  if (I->d16) return I->d16[a * n + b];
+  if (I->d32) return I->d32[a * n + b];
+  const int2 *xy = (const int2 *)I->xy;
+  return nint_dist(xy[a], xy[b]);
+}
+
+// full objective of one solution, by its definition (initial pool only)
+__device__ int64_t full_objective(const DevInst *I, const int32_t *x) {
+  const int n = I->n;
+  if (I->kind == KTSP) {
+    int64_t f = 0;
+    for (int i = 0; i < n; ++i) f += glb_tsp_dist(I, x[i], x[i + 1 == n ? 0 : i + 1]);
+    return f;
+  }
+  if (I->kind == KQAP) {
+    int64_t f = 0;
+    for (int i = 0; i < n; ++i) {
+      const int16_t *Fi = I->qf + i * n, *Dr = I->qd + x[i] * n;
+      for (int j = 0; j < n; ++j) f += (int64_t)Fi[j] * Dr[x[j]];
+    }
+    return f;
+  }
+  if (I->kind == KKNAP) {
+    int64_t W = 0, V = 0;
+    for (int i = 0; i < n; ++i)
+      if (x[i]) {
+        W += I->kw[i];
+        V += I->kv[i];
+      }
+    const int64_t over = W - I->capacity;
+    return -V + I->lambda * (over > 0 ? over : 0);
+  }
+  if (I->kind == KVRP) {
+    const int dn = I->dn;
+    int64_t dist = 0, late = 0;
+    int t = 0, load = 0, routes = 0, prev = 0;
+    for (int p = 0; p < n; ++p) {
+      const int c = x[p] + 1;
+      if (routes == 0 || load + I->dem[c] > I->capacity) {
+        if (routes > 0) {
+          const int back = I->d16[prev * dn];
+          dist += back;
+          t += back;
+          late += max(0, t - I->horizon);
+        }
+        ++routes;
+        load = 0;
+        t = 0;
+        prev = 0;
+      }
+      const int dd = I->d16[prev * dn + c];
+      dist += dd;
+      t = max(t + dd, I->rdy[c]);
+      late += max(0, t - I->due[c]);
+      t += I->service;
+      load += I->dem[c];
+      prev = c;
+    }
+    if (routes > 0) {
+      const int back = I->d16[prev * dn];
+      dist += back;
+      t += back;
+      late += max(0, t - I->horizon);
+    }
+    return dist + 100 * late + 10000 * (int64_t)max(0, routes - I->vehicles);
+  }
+  int64_t f = 0;
+  for (int e = 0; e < I->n_edges; ++e) f += x[I->edges[2 * e]] == x[I->edges[2 * e + 1]];
+  return f;
+}
+
+__device__ __forceinline__ int heur_mats(int kind) {
+  return kind == KQAP ? 2 : ((kind == KTSP || kind == KVRP) ? 1 : 0);
+}
+
+// entry (i, j) of heuristic data matrix `mat` (Sec. heuristic init: any n x n data matrix)
+__device__ __forceinline__ int64_t heur_entry(const DevInst *I, int mat, int i, int j) {
+  if (I->kind == KTSP) return glb_tsp_dist(I, i, j);
+  if (I->kind == KQAP) return mat == 0 ? I->qf[i * I->n + j] : I->qd[i * I->n + j];
+  return I->d16[(i + 1) * I->dn + (j + 1)];
+}
+
+}  // namespace
+
+// row / column sums of each data matrix, sorted ascending and descending
+// (ties by index) -> four permutations per matrix in pool slots 4*mat ..
+__global__ __launch_bounds__(256) void k_init_heur(DevJob *jobs) {
+  DevJob *J = jobs + blockIdx.x;
+  const DevInst *I = J->inst;
+  const int mat = blockIdx.y;
+  if (mat >= heur_mats(I->kind)) return;
+  const int base = 4 * mat;
+  if ((uint32_t)base >= J->Q) return;
+  const int n = I->n;
+  int64_t *rs = J->sums + (size_t)mat * 2 * n, *cs = rs + n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    int64_t r = 0, c = 0;
+    for (int j = 0; j < n; ++j) {
+      r += heur_entry(I, mat, i, j);
+      c += heur_entry(I, mat, j, i);
+    }
+    rs[i] = r;
+    cs[i] = c;
+  }
+  __syncthreads();
+  for (int h = 0; h < 4; ++h) {
+    if ((uint32_t)(base + h) >= J->Q) break;
+    const int64_t *s = h < 2 ? rs : cs;
+    const int64_t sg = (h & 1) ? -1 : 1;
+    int32_t *row = J->pool + (size_t)(base + h) * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int64_t ki = sg * s[i];
+      int rank = 0;
+      for (int j = 0; j < n; ++j) {
+        const int64_t kj = sg * s[j];
+        rank += (kj < ki) || (kj == ki && j < i);
+      }
+      row[rank] = i;
+    }
+  }
+}
+
+// random members of the pool: Fisher-Yates from the identity, random bits, or
+// uniform integers; draw i comes from word (i mod 4) of the block with counter
+// (0xFFFFFFFF, pool index, i / 4, instance key)
+__global__ __launch_bounds__(64) void k_init_random(DevJob *jobs) {
+  DevJob *J = jobs + blockIdx.y;
+  const DevInst *I = J->inst;
+  const uint32_t q = blockIdx.x * 64 + threadIdx.x;
+  const uint32_t H = min((uint32_t)(4 * heur_mats(I->kind)), J->Q);
+  if (q < H || q >= J->Q) return;
+  const int n = I->n;
+  int32_t *x = J->pool + (size_t)q * n;
+  const uint32_t k0 = (uint32_t)J->seed, k1 = (uint32_t)(J->seed >> 32);
+  uint32_t r[4];
+  if (I->kind == KKNAP || I->kind == KCOLOR) {
+    for (int i = 0; i < n; ++i) {
+      if ((i & 3) == 0) philox(0xFFFFFFFFu, q, (uint32_t)(i >> 2), J->key, k0, k1, r);
+      const uint32_t w = r[i & 3];
+      x[i] = I->kind == KKNAP ? (int32_t)(w >> 31) : I->lb + (int32_t)rmap(w, (uint32_t)(I->ub - I->lb + 1));
+    }
+  } else {
+    for (int i = 0; i < n; ++i) x[i] = i;
+    for (int i = n - 1; i >= 1; --i) {
+      if (i == n - 1 || (i & 3) == 3) philox(0xFFFFFFFFu, q, (uint32_t)(i >> 2), J->key, k0, k1, r);
+      const uint32_t j = rmap(r[i & 3], (uint32_t)(i + 1));
+      const int32_t t = x[i];
+      x[i] = x[j];
+      x[j] = t;
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void k_init_eval(DevJob *jobs) {
+  DevJob *J = jobs + blockIdx.y;
+  const uint32_t q = blockIdx.x * 64 + threadIdx.x;
+  if (q >= J->Q) return;
+  J->pool_f[q] = full_objective(J->inst, J->pool + (size_t)q * J->inst->n);
+}
+
+// keep the P best of the pool, ordered by (f, pool index)
+__global__ __launch_bounds__(64) void k_init_select(DevJob *jobs) {
+  DevJob *J = jobs + blockIdx.y;
+  const uint32_t q = blockIdx.x * 64 + threadIdx.x;
+  if (q >= J->Q) return;
+  const int64_t fq = J->pool_f[q];
+  uint32_t rank = 0;
+  for (uint32_t o = 0; o < J->Q; ++o) {
+    const int64_t fo = J->pool_f[o];
+    rank += (fo < fq) || (fo == fq && o < q);
+  }
+  if (rank >= J->P) return;
+  const int n = J->inst->n;
+  const int32_t *src = J->pool + (size_t)q * n;
+  int32_t *c = J->cur + (size_t)rank * n, *b = J->best + (size_t)rank * n;
+  for (int i = 0; i < n; ++i) {
+    c[i] = src[i];
+    b[i] = src[i];
+  }
+  J->cur_f[rank] = fq;
+  J->best_f[rank] = fq;
+}
+
+// initial temperature, weights (Tab. weight_preset) and counters
+__global__ void k_init_final(DevJob *jobs, int count) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= count) return;
+  DevJob *J = jobs + j;
+  const int n = J->inst->n;
+  const int64_t f0 = J->cur_f[0];
+  if (J->t0_param) J->T = J->t0_param;
+  else {
+    const uint64_t a = (uint64_t)(f0 < 0 ? -f0 : f0);
+    J->T = ((a << 16) / (uint64_t)n) >> 2;
+  }
+  uint64_t raw[kOps], s = 0;
+  for (int i = 0; i < kOps; ++i) {
+    raw[i] = 0;
+    if (!(J->op_mask & (1u << i))) continue;
+    raw[i] = 65536;
+    if (i == OOROPT) raw[i] = n <= 100 ? 52429 : (n <= 250 ? 45875 : 19661);
+    s += raw[i];
+  }
+  for (int i = 0; i < kOps; ++i) {
+    if (!raw[i]) {
+      J->w_op[i] = 0;
+      continue;
+    }
+    const uint64_t v = (raw[i] << 16) / s;
+    J->w_op[i] = (uint32_t)(v < 1 ? 1 : v);
+  }
+  J->w_k[0] = 52429; J->w_k[1] = 9830; J->w_k[2] = 3277;
+  for (int i = 0; i < kOps; ++i) J->u_op[i] = J->v_op[i] = 0;
+  for (int i = 0; i < 3; ++i) J->u_k[i] = J->v_k[i] = 0;
+  for (int i = 0; i < kOps; ++i) J->tot_u_op[i] = 0;
+  for (int i = 0; i < 3; ++i) J->tot_u_k[i] = 0;
+  J->g = 0;
+  J->g_stop = 0;
+  J->stag = 0;
+  J->done = 0;
+  J->accepted = 0;
+  J->epoch_ref = f0;
+  J->inst_best = f0;
+}
+
+__global__ void k_set_stop(DevJob *jobs, int count, uint32_t add, int use_total) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= count) return;
+  DevJob *J = jobs + j;
+  J->g_stop = use_total ? J->G : J->g_stop + add;
+}
+
+// best solution of each job: min of (best_f, index)
+__global__ __launch_bounds__(64) void k_best(DevJob *jobs) {
+  DevJob *J = jobs + blockIdx.x;
+  const uint32_t lane = threadIdx.x;
+  int64_t bf = INT64_MAX;
+  uint32_t bi = 0xFFFFFFFFu;
+  for (uint32_t s = lane; s < J->P; s += 64) {
+    const int64_t f = J->best_f[s];
+    if (f < bf) {
+      bf = f;
+      bi = s;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int64_t of = __shfl_xor(bf, o, 64);
+    const uint32_t oi = __shfl_xor(bi, o, 64);
+    if (of < bf || (of == bf && oi < bi)) {
+      bf = of;
+      bi = oi;
+    }
+  }
+  const int n = J->inst->n;
+  const int32_t *src = J->best + (size_t)bi * n;
+  for (int p = lane; p < n; p += 64) J->best_out[p] = src[p];
+  if (lane == 0) {
+    J->best_out_f = bf;
+    J->best_idx = (int32_t)bi;
+  }
+}
+
+__global__ void k_build_d16(const int32_t *xy, int n, int16_t *d16) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  const int2 *p = (const int2 *)xy;
+  d16[idx] = (int16_t)nint_dist(p[i], p[j]);
+}
+
+__global__ void k_build_d32(const int32_t *xy, int n, int32_t *d32) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int i = (int)(idx / n), j = (int)(idx % n);
+  const int2 *p = (const int2 *)xy;
+  d32[idx] = nint_dist(p[i], p[j]);
+}
+
+// ------------------------------------------------------------ launch wrappers
+namespace gxk {
+
+hipError_t set_exp_tables(const uint32_t *hi, const uint32_t *lo) {
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_exp_hi), hi, 16 * sizeof(uint32_t));
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_exp_lo), lo, 256 * sizeof(uint32_t));
+}
+
+hipError_t build_tsp_d16_from_xy(const int32_t *xy, int n, int16_t *d16, hipStream_t s) {
+  const int64_t tot = (int64_t)n * n;
+  hipLaunchKernelGGL(k_build_d16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, xy, n, d16);
+  return hipGetLastError();
+}
+
+hipError_t build_d32_from_xy(const int32_t *xy, int n, int32_t *d32, hipStream_t s) {
+  const int64_t tot = (int64_t)n * n;
+  hipLaunchKernelGGL(k_build_d32, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, xy, n, d32);
+  return hipGetLastError();
+}
+
+hipError_t init_jobs(DevJob *jobs, int count, uint32_t max_q, int, int max_heur_mats, hipStream_t s) {
+  if (max_heur_mats > 0)
+    hipLaunchKernelGGL(k_init_heur, dim3(count, max_heur_mats), dim3(256), 0, s, jobs);
+  const dim3 g((max_q + 63) / 64, count);
+  hipLaunchKernelGGL(k_init_random, g, dim3(64), 0, s, jobs);
+  hipLaunchKernelGGL(k_init_eval, g, dim3(64), 0, s, jobs);
+  hipLaunchKernelGGL(k_init_select, g, dim3(64), 0, s, jobs);
+  hipLaunchKernelGGL(k_init_final, dim3((count + 63) / 64), dim3(64), 0, s, jobs, count);
+  return hipGetLastError();
+}
+
+hipError_t set_stop(DevJob *jobs, int count, uint32_t add, int use_total, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_stop, dim3((count + 63) / 64), dim3(64), 0, s, jobs, count, add, use_total);
+  return hipGetLastError();
+}
+
+static const void *plain_kernel(int kind, int stage) {
+  switch (kind) {
+    case KTSP:
+      switch (stage) {
+        case SLDS16: return (const void *)k_evolve<KTSP, SLDS16>;
+        case SLDSXY: return (const void *)k_evolve<KTSP, SLDSXY>;
+        case SGLB16: return (const void *)k_evolve<KTSP, SGLB16>;
+        default: return (const void *)k_evolve<KTSP, SGLB32>;
+      }
+    case KQAP: return (const void *)k_evolve<KQAP, 0>;
+    case KKNAP: return (const void *)k_evolve<KKNAP, 0>;
+    case KVRP: return (const void *)k_evolve<KVRP, 0>;
+    default: return (const void *)k_evolve<KCOLOR, 0>;
+  }
+}
+
+hipError_t prepare_kernel_attrs(uint32_t max_lds) {
+  const int kinds[][2] = {{KTSP, SLDS16}, {KTSP, SLDSXY}, {KTSP, SGLB16}, {KTSP, SGLB32},
+                          {KQAP, 0},      {KKNAP, 0},     {KVRP, 0},      {KCOLOR, 0}};
+  for (auto &k : kinds) {
+    hipError_t e = hipFuncSetAttribute(plain_kernel(k[0], k[1]), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)max_lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipFuncSetAttribute((const void *)k_evolve_items, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)max_lds);
+}
+
+hipError_t evolve_plain(DevJob *job, int kind, int stage, uint32_t P, uint32_t lds, hipStream_t s) {
+  void *args[] = {&job};
+  return hipLaunchKernel(plain_kernel(kind, stage), dim3(P), dim3(64), args, lds, s);
+}
+
+hipError_t evolve_items(DevJob *jobs, const uint2 *items, uint32_t n_items, uint32_t grid, uint32_t lds,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_evolve_items, dim3(grid), dim3(64), lds, s, jobs, items, n_items);
+  return hipGetLastError();
+}
+
+hipError_t fetch_best(DevJob *jobs, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_best, dim3(count), dim3(64), 0, s, jobs);
+  return hipGetLastError();
+}
+
+hipError_t occupancy_items(uint32_t lds, int *blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)k_evolve_items, 64, lds);
+}
+
+hipError_t occupancy_plain(int kind, int stage, uint32_t lds, int *blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, plain_kernel(kind, stage), 64, lds);
+}
+
+}  // namespace gxk

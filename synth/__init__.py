@@ -85,6 +85,7 @@ class Params:
     stagnation_epochs: int = 5
     credit: int = 0            # 0: every candidate credits its ops, 1: accepted move only
     oversample_k: int = 4
+    staging: int = 0           # TSP distance staging (0 = library's choice)
 
     def with_(self, **kw) -> "Params":
         return replace(self, **kw)

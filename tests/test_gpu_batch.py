@@ -1,0 +1,82 @@
+"""Batched solve: many instances of uneven size and kind in one persistent
+launch per epoch.  Each job's final state must equal the oracle's solve of the
+same instance and parameters, bit for bit (and therefore the plain solver's)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2603_19163_amd import gx
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ["g", "stag", "T_q16", "epoch_ref", "accepted", "w_op", "w_k", "u_op", "v_op", "u_k", "v_k",
+        "cur", "cur_f", "best", "best_f"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gx.gx_create(0)
+    yield c
+    gx.gx_destroy(c)
+
+
+def mixed(count_tsp=6, count_qap=4, G=30):
+    r = np.random.default_rng(17)
+    insts, params = [], []
+    for i in range(count_tsp):
+        n = int(r.integers(20, 61))
+        insts.append(synth.tsp_uniform(n, 100 + i, key=i))
+        params.append(synth.Params(seed=10**6 + i, generations=G, population=int(r.integers(2, 7)),
+                                   candidates=128, alpha_q32=synth.alpha_q32_for(G),
+                                   staging=int(r.integers(1, 3))))
+    for i in range(count_qap):
+        n = int(r.integers(12, 21))
+        insts.append(synth.qap_random(n, 200 + i, key=count_tsp + i))
+        params.append(synth.Params(seed=10**6 + count_tsp + i, generations=G + 7 * i,
+                                   population=int(r.integers(2, 6)), candidates=96,
+                                   alpha_q32=synth.alpha_q32_for(G)))
+    k = len(insts)
+    insts.append(synth.knapsack_random(50, 300, key=k))
+    params.append(synth.Params(seed=5, generations=G, population=3, alpha_q32=synth.alpha_q32_for(G)))
+    insts.append(synth.vrptw_random(15, 301, key=k + 1))
+    params.append(synth.Params(seed=6, generations=G - 4, population=3, alpha_q32=synth.alpha_q32_for(G)))
+    insts.append(synth.color_planted(25, 3, inst_id=302, key=k + 2))
+    params.append(synth.Params(seed=7, generations=G, population=4, alpha_q32=synth.alpha_q32_for(G)))
+    return insts, params
+
+
+def test_batch_equals_oracle_per_job(ctx):
+    insts, params = mixed()
+    handles = [gx.gx_instance_upload(ctx, i) for i in insts]
+    print(f"[batch] {len(insts)} jobs", flush=True)
+    jobs = gx.gx_solve_batch(ctx, handles, params)
+    gx.gx_wait(ctx, jobs[0])
+    for i, (inst, p, job) in enumerate(zip(insts, params, jobs)):
+        g = gx.gx_snapshot(ctx, job, p.population, inst.n)
+        o = oracle.OracleInstance(inst).solve(p)
+        for k in KEYS:
+            assert np.array_equal(np.asarray(g[k]), np.asarray(o[k])), (i, inst.kind, k)
+        sol, f = gx.gx_fetch_best(ctx, job, inst.n)
+        fo, io = oracle.best_of(o)
+        assert f == fo and np.array_equal(sol, o["best"][io])
+    for j in jobs:
+        gx.gx_job_free(ctx, j)
+    for h in handles:
+        gx.gx_instance_free(ctx, h)
+
+
+def test_batch_equals_plain_solver(ctx):
+    insts, params = mixed(3, 2, G=120)      # 120 generations: graph-replayed launches
+    handles = [gx.gx_instance_upload(ctx, i) for i in insts]
+    jobs = gx.gx_solve_batch(ctx, handles, params)
+    batched = [gx.gx_fetch_best(ctx, j, i.n) for j, i in zip(jobs, insts)]
+    for h, inst, p, (sol, f) in zip(handles, insts, params, batched):
+        job = gx.gx_solve(ctx, h, p)
+        s2, f2 = gx.gx_fetch_best(ctx, job, inst.n)
+        assert f == f2 and np.array_equal(sol, s2)
+        gx.gx_job_free(ctx, job)
+    for j in jobs:
+        gx.gx_job_free(ctx, j)
+    for h in handles:
+        gx.gx_instance_free(ctx, h)
