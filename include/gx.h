@@ -206,6 +206,49 @@ gx_status gx_job_free(gx_ctx *ctx, gx_job *job);
 gx_status gx_solve_batch(gx_ctx *ctx, const gx_instance *const *insts, const gx_solve_params *params,
                          int32_t count, gx_job **jobs_out);
 
+/* ---- Serving: continuous batching of solve requests.
+ * A server owns a device arena and a scheduler thread.  Requests are admitted
+ * in arrival order as soon as their device footprint (instance data, solution
+ * state, initial pool) fits the arena and a resident slot is free; requests
+ * that do not fit wait without blocking smaller ones behind them.  Every
+ * scheduling quantum advances every resident request by one AOS epoch in one
+ * fused launch over all their solutions, so requests that arrive while others
+ * run overlap with them on the device.  Finished requests return their best
+ * solution and free their memory.  A result depends only on the request
+ * (instance, parameters, seed, instance key), never on what else is resident,
+ * so it equals gx_solve on the same request. */
+typedef struct gx_server gx_server;
+typedef struct {
+  uint64_t hbm_budget_bytes;   /* arena for resident requests [1 GiB] */
+  uint32_t max_resident;       /* requests resident at once [1024] */
+  uint32_t max_lds_bytes;      /* LDS per workgroup a request may need [65536] */
+} gx_server_cfg;
+typedef struct {
+  uint64_t submitted, admitted, completed, cancelled;
+  uint64_t quanta, move_evals;
+  uint32_t resident, pending;
+  uint64_t arena_used_bytes, arena_bytes;
+  double busy_seconds;         /* wall time with at least one request resident */
+} gx_server_stats;
+/* Start a server on the context's device (it uses a stream of its own). */
+gx_status gx_server_create(gx_ctx *ctx, const gx_server_cfg *cfg, gx_server **out);
+/* Thread-safe.  Copies the instance (host pointers only); validates it and the
+ * parameters (population must be given, >= 1); GX_E_UNSUPPORTED if the request
+ * can never fit the arena or the LDS limit.  *ticket identifies the request. */
+gx_status gx_server_submit(gx_server *srv, const gx_instance_desc *desc, const gx_solve_params *p,
+                           uint64_t *ticket);
+/* Thread-safe.  GX_E_NOT_READY while queued or running; GX_E_CANCELLED after a
+ * cancel; GX_OK with the best solution (capacity >= n), its objective, and the
+ * submit and completion times (steady clock, ns).  A completed or cancelled
+ * ticket is forgotten after it has been reported once (then GX_E_INVALID). */
+gx_status gx_server_poll(gx_server *srv, uint64_t ticket, int32_t *solution_out, int32_t capacity,
+                         int64_t *objective_out, uint64_t *t_submit_ns, uint64_t *t_done_ns);
+/* Thread-safe.  Drops a queued or running request; other requests are unaffected. */
+gx_status gx_server_cancel(gx_server *srv, uint64_t ticket);
+gx_status gx_server_stats_get(gx_server *srv, gx_server_stats *out);
+/* Stops the scheduler, waits for in-flight work and frees the arena. */
+gx_status gx_server_destroy(gx_server *srv);
+
 /* Exponential tables of the acceptance test (host copies, for checking):
  * hi[i] = round(2^31 e^-i) for i < 16, lo[j] = round(2^31 e^-(j/256)) for j < 256. */
 gx_status gx_exp_tables(uint32_t hi[16], uint32_t lo[256]);

@@ -118,6 +118,204 @@ void free_bufs(std::vector<void *> &b) {
   b.clear();
 }
 
+
+// ------------------------------------------------------------ instance staging
+// prepare_instance validates a description and builds the host-side arrays
+// (int16 conversions, CSR); place_instance lays them out in one device block,
+// builds derived distance matrices with a kernel and writes the DevInst record
+// at the end of the block.
+enum Field { F_XY, F_D16, F_D32, F_QF, F_QD, F_KW, F_KV, F_DEM, F_RDY, F_DUE, F_ADJOFF, F_ADJ, F_EDGES };
+
+struct HostArr {
+  int field;
+  size_t bytes;
+  std::vector<char> data;   // empty: built on the device
+};
+
+struct Prepared {
+  DevInst h{};
+  std::vector<HostArr> arrs;
+  int build_d16_side = 0;   // > 0: d16 (side x side) from the coordinates
+  int max_d = 0;
+  uint32_t key = 0;
+  size_t dev_bytes() const {
+    size_t b = 0;
+    for (const auto &a : arrs) b += pad16(a.bytes) + 16;
+    return b + pad16(sizeof(DevInst)) + 16;
+  }
+};
+
+template <class T>
+void add_arr(Prepared &pr, int field, const std::vector<T> &v) {
+  HostArr a{field, v.size() * sizeof(T), {}};
+  a.data.resize(a.bytes);
+  if (a.bytes) memcpy(a.data.data(), v.data(), a.bytes);
+  pr.arrs.push_back(std::move(a));
+}
+
+void add_built(Prepared &pr, int field, size_t bytes) { pr.arrs.push_back(HostArr{field, bytes, {}}); }
+
+gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, bool tsp_d16) {
+  const int n = d->n;
+  if (n < 1) return fail(c, GX_E_INVALID, "n must be >= 1 (got %d)", n);
+  DevInst &h = pr.h;
+  h.kind = d->kind;
+  h.n = n;
+  h.lb = d->lb;
+  h.ub = d->ub;
+  h.capacity = d->capacity;
+  h.vehicles = d->vehicles;
+  h.service = d->service_time;
+  h.horizon = d->horizon;
+  h.n_edges = d->n_edges;
+  pr.key = d->instance_key;
+  std::vector<int32_t> A, B;
+  gx_status st = GX_OK;
+  double fbound = 0;
+  if (d->kind == KTSP) {
+    if (n > 65535) return fail(c, GX_E_UNSUPPORTED, "TSP n <= 65535");
+    if (d->a_is_coords) {
+      if ((st = to_host(c, d, d->a, (size_t)2 * n, A))) return st;
+      for (int32_t v : A)
+        if (v < 0 || v >= kMaxCoord) return fail(c, GX_E_INVALID, "coordinates must lie in [0, 16384)");
+      add_arr(pr, F_XY, A);
+      h.has_xy = 1;
+      if (tsp_d16 && n <= 4096) {
+        add_built(pr, F_D16, (size_t)2 * n * n);
+        pr.build_d16_side = n;
+      }
+      pr.max_d = 23171;
+    } else {
+      if ((st = to_host(c, d, d->a, (size_t)n * n, A))) return st;
+      int mx = 0;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          const int32_t v = A[(size_t)i * n + j];
+          if (v < 0 || v >= (1 << 24) || v != A[(size_t)j * n + i] || (i == j && v != 0))
+            return fail(c, GX_E_INVALID, "TSP matrix must be symmetric, zero-diagonal, in [0, 2^24)");
+          mx = std::max(mx, v);
+        }
+      pr.max_d = mx;
+      add_arr(pr, F_D32, A);
+      if (mx < 32768) add_arr(pr, F_D16, std::vector<int16_t>(A.begin(), A.end()));
+    }
+    fbound = 6.0 * n * (double)std::max(pr.max_d, 1);
+  } else if (d->kind == KQAP) {
+    if (n > kMaxQapN) return fail(c, GX_E_UNSUPPORTED, "QAP n <= %d", kMaxQapN);
+    if ((st = to_host(c, d, d->a, (size_t)n * n, A)) || (st = to_host(c, d, d->b, (size_t)n * n, B))) return st;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const size_t ij = (size_t)i * n + j, ji = (size_t)j * n + i;
+        if (A[ij] < 0 || A[ij] >= 16384 || B[ij] < 0 || B[ij] >= 16384 || A[ij] != A[ji] || B[ij] != B[ji])
+          return fail(c, GX_E_INVALID, "QAP matrices must be symmetric with entries in [0, 16384)");
+      }
+    add_arr(pr, F_QF, std::vector<int16_t>(A.begin(), A.end()));
+    add_arr(pr, F_QD, std::vector<int16_t>(B.begin(), B.end()));
+    fbound = 4.0 * n * n * 16384.0 * 16384.0;
+  } else if (d->kind == KKNAP) {
+    if (n > 16384) return fail(c, GX_E_UNSUPPORTED, "knapsack n <= 16384");
+    if ((st = to_host(c, d, d->a, (size_t)n, A)) || (st = to_host(c, d, d->b, (size_t)n, B))) return st;
+    int64_t mv = 0, sw = 0, sv = 0;
+    for (int i = 0; i < n; ++i) {
+      if (A[i] < 0 || A[i] > (1 << 20) || B[i] < 0 || B[i] > (1 << 20))
+        return fail(c, GX_E_INVALID, "knapsack weights and values must lie in [0, 2^20]");
+      mv = std::max<int64_t>(mv, B[i]);
+      sw += A[i];
+      sv += B[i];
+    }
+    if (d->capacity < 0) return fail(c, GX_E_INVALID, "capacity must be >= 0");
+    h.lambda = mv + 1;
+    add_arr(pr, F_KW, A);
+    add_arr(pr, F_KV, B);
+    fbound = 4.0 * ((double)sv + (double)h.lambda * (double)sw);
+  } else if (d->kind == KVRP) {
+    if (n > kMaxVrpN) return fail(c, GX_E_UNSUPPORTED, "VRPTW n <= %d", kMaxVrpN);
+    const int m = n + 1;
+    if ((st = to_host(c, d, d->a, (size_t)2 * m, A)) || (st = to_host(c, d, d->b, (size_t)3 * m, B))) return st;
+    for (int32_t v : A)
+      if (v < 0 || v >= kMaxCoord) return fail(c, GX_E_INVALID, "coordinates must lie in [0, 16384)");
+    if (d->capacity < 1 || d->vehicles < 1 || d->service_time < 0 || d->service_time > (1 << 16) ||
+        d->horizon < 0 || d->horizon > (1 << 19))
+      return fail(c, GX_E_INVALID, "VRPTW capacity, vehicles >= 1; service <= 2^16; horizon in [0, 2^19]");
+    for (int i = 0; i < m; ++i) {
+      const int32_t q = B[i], r = B[m + i], u = B[2 * m + i];
+      if (q < 0 || q > d->capacity || r < 0 || u < 0 || r > (1 << 19) || u > (1 << 19))
+        return fail(c, GX_E_INVALID, "VRPTW demand in [0, capacity], times in [0, 2^19]");
+    }
+    h.dn = m;
+    add_arr(pr, F_XY, A);
+    h.has_xy = 1;
+    add_built(pr, F_D16, (size_t)2 * m * m);
+    pr.build_d16_side = m;
+    add_arr(pr, F_DEM, std::vector<int32_t>(B.begin(), B.begin() + m));
+    add_arr(pr, F_RDY, std::vector<int32_t>(B.begin() + m, B.begin() + 2 * m));
+    add_arr(pr, F_DUE, std::vector<int32_t>(B.begin() + 2 * m, B.end()));
+    fbound = 4.0 * (m * 23171.0 + 100.0 * m * (m * 23171.0 + (1 << 19) + (double)m * (1 << 16)) + 10000.0 * m);
+  } else if (d->kind == KCOLOR) {
+    if (n > 32767) return fail(c, GX_E_UNSUPPORTED, "colouring n <= 32767");
+    if (d->lb > d->ub || d->lb < -32768 || d->ub > 32767)
+      return fail(c, GX_E_INVALID, "colouring needs -32768 <= lb <= ub <= 32767");
+    if (d->n_edges < 0 || d->n_edges > (1 << 20)) return fail(c, GX_E_INVALID, "n_edges in [0, 2^20]");
+    if ((st = to_host(c, d, d->a, (size_t)2 * d->n_edges, A))) return st;
+    std::vector<int32_t> off(n + 1, 0), adj((size_t)2 * d->n_edges);
+    for (int e = 0; e < d->n_edges; ++e) {
+      const int u = A[2 * e], v = A[2 * e + 1];
+      if (u < 0 || v < 0 || u >= n || v >= n || u == v)
+        return fail(c, GX_E_INVALID, "edge %d out of range or a self loop", e);
+      off[u + 1]++;
+      off[v + 1]++;
+    }
+    for (int i = 0; i < n; ++i) off[i + 1] += off[i];
+    std::vector<int32_t> fill(off.begin(), off.end() - 1);
+    for (int e = 0; e < d->n_edges; ++e) {
+      const int u = A[2 * e], v = A[2 * e + 1];
+      adj[fill[u]++] = v;
+      adj[fill[v]++] = u;
+    }
+    add_arr(pr, F_ADJOFF, off);
+    add_arr(pr, F_ADJ, adj);
+    add_arr(pr, F_EDGES, A);
+    fbound = 4.0 * d->n_edges + 4;
+  } else {
+    return fail(c, GX_E_INVALID, "unknown problem kind %d", d->kind);
+  }
+  if (fbound >= std::ldexp(1.0, 45)) return fail(c, GX_E_UNSUPPORTED, "objective range exceeds 2^45");
+  return GX_OK;
+}
+
+gx_status place_instance(gx_ctx *c, Prepared &pr, char *base, hipStream_t s, DevInst *out_h, DevInst **out_d) {
+  DevInst h = pr.h;
+  char *q = base;
+  for (const auto &a : pr.arrs) {
+    char *dst = q;
+    q += pad16(a.bytes) + 16;
+    if (!a.data.empty()) HIPCHK(c, hipMemcpyAsync(dst, a.data.data(), a.bytes, hipMemcpyHostToDevice, s));
+    switch (a.field) {
+      case F_XY: h.xy = (const int32_t *)dst; break;
+      case F_D16: h.d16 = (const int16_t *)dst; break;
+      case F_D32: h.d32 = (const int32_t *)dst; break;
+      case F_QF: h.qf = (const int16_t *)dst; break;
+      case F_QD: h.qd = (const int16_t *)dst; break;
+      case F_KW: h.kw = (const int32_t *)dst; break;
+      case F_KV: h.kv = (const int32_t *)dst; break;
+      case F_DEM: h.dem = (const int32_t *)dst; break;
+      case F_RDY: h.rdy = (const int32_t *)dst; break;
+      case F_DUE: h.due = (const int32_t *)dst; break;
+      case F_ADJOFF: h.adj_off = (const int32_t *)dst; break;
+      case F_ADJ: h.adj = (const int32_t *)dst; break;
+      default: h.edges = (const int32_t *)dst; break;
+    }
+  }
+  if (pr.build_d16_side > 0) HIPCHK(c, gxk::build_tsp_d16_from_xy(h.xy, pr.build_d16_side, (int16_t *)h.d16, s));
+  DevInst *dd = (DevInst *)q;
+  *out_h = h;
+  // the record is copied from pr.h's twin kept alive by the caller until the stream syncs
+  pr.h = h;
+  HIPCHK(c, hipMemcpyAsync(dd, &pr.h, sizeof(DevInst), hipMemcpyHostToDevice, s));
+  *out_d = dd;
+  return GX_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -189,183 +387,26 @@ gx_status gx_instance_free(gx_ctx *c, gx_instance *in) {
 gx_status gx_instance_upload(gx_ctx *c, const gx_instance_desc *d, gx_instance **out) {
   if (!c || !d || !out) return fail(c, GX_E_INVALID, "null argument");
   *out = nullptr;
-  const int n = d->n;
-  if (n < 1) return fail(c, GX_E_INVALID, "n must be >= 1 (got %d)", n);
   HIPCHK(c, hipSetDevice(c->dev));
+  Prepared pr;
+  gx_status st = prepare_instance(c, d, pr, true);
+  if (st) return st;
   gx_instance *in = new gx_instance();
-  DevInst &h = in->h;
-  h.kind = d->kind;
-  h.n = n;
-  h.lb = d->lb;
-  h.ub = d->ub;
-  h.capacity = d->capacity;
-  h.vehicles = d->vehicles;
-  h.service = d->service_time;
-  h.horizon = d->horizon;
-  h.n_edges = d->n_edges;
-  std::vector<int32_t> A, B;
-  gx_status st = GX_OK;
-  auto bail = [&](gx_status s) {
+  char *base = nullptr;
+  if ((st = dalloc(c, in->bufs, &base, pr.dev_bytes()))) {
+    delete in;
+    return st;
+  }
+  DevInst *dd = nullptr;
+  if ((st = place_instance(c, pr, base, c->stream, &in->h, &dd)) ||
+      (st = hipStreamSynchronize(c->stream) == hipSuccess ? GX_OK : fail(c, GX_E_DEVICE, "instance staging failed"))) {
     free_bufs(in->bufs);
     delete in;
-    return s;
-  };
-  auto up = [&](void *dst, const void *src, size_t bytes) -> gx_status {
-    HIPCHK(c, hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
-    return GX_OK;
-  };
-  double fbound = 0;
-  if (d->kind == KTSP) {
-    if (n > 65535) return bail(fail(c, GX_E_UNSUPPORTED, "TSP n <= 65535"));
-    if (d->a_is_coords) {
-      if ((st = to_host(c, d, d->a, (size_t)2 * n, A))) return bail(st);
-      for (int32_t v : A)
-        if (v < 0 || v >= kMaxCoord) return bail(fail(c, GX_E_INVALID, "coordinates must lie in [0, 16384)"));
-      int32_t *xy;
-      if ((st = dalloc(c, in->bufs, &xy, (size_t)8 * n)) || (st = up(xy, A.data(), (size_t)8 * n))) return bail(st);
-      h.xy = xy;
-      h.has_xy = 1;
-      if (n <= 4096) {
-        int16_t *d16;
-        if ((st = dalloc(c, in->bufs, &d16, (size_t)2 * n * n))) return bail(st);
-        HIPCHK(c, gxk::build_tsp_d16_from_xy(xy, n, d16, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        h.d16 = d16;
-      }
-      in->max_d = 23171;
-    } else {
-      if ((st = to_host(c, d, d->a, (size_t)n * n, A))) return bail(st);
-      int mx = 0;
-      for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
-          const int32_t v = A[(size_t)i * n + j];
-          if (v < 0 || v >= (1 << 24) || v != A[(size_t)j * n + i] || (i == j && v != 0))
-            return bail(fail(c, GX_E_INVALID, "TSP matrix must be symmetric, zero-diagonal, in [0, 2^24)"));
-          mx = std::max(mx, v);
-        }
-      in->max_d = mx;
-      int32_t *d32;
-      if ((st = dalloc(c, in->bufs, &d32, (size_t)4 * n * n)) || (st = up(d32, A.data(), (size_t)4 * n * n)))
-        return bail(st);
-      h.d32 = d32;
-      if (mx < 32768) {
-        std::vector<int16_t> s16(A.begin(), A.end());
-        int16_t *d16;
-        if ((st = dalloc(c, in->bufs, &d16, (size_t)2 * n * n)) || (st = up(d16, s16.data(), (size_t)2 * n * n)))
-          return bail(st);
-        h.d16 = d16;
-      }
-    }
-    fbound = 6.0 * n * (double)std::max(in->max_d, 1);
-  } else if (d->kind == KQAP) {
-    if (n > kMaxQapN) return bail(fail(c, GX_E_UNSUPPORTED, "QAP n <= %d", kMaxQapN));
-    if ((st = to_host(c, d, d->a, (size_t)n * n, A)) || (st = to_host(c, d, d->b, (size_t)n * n, B))) return bail(st);
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        const size_t ij = (size_t)i * n + j, ji = (size_t)j * n + i;
-        if (A[ij] < 0 || A[ij] >= 16384 || B[ij] < 0 || B[ij] >= 16384 || A[ij] != A[ji] || B[ij] != B[ji])
-          return bail(fail(c, GX_E_INVALID, "QAP matrices must be symmetric with entries in [0, 16384)"));
-      }
-    std::vector<int16_t> F(A.begin(), A.end()), D(B.begin(), B.end());
-    int16_t *qf, *qd;
-    if ((st = dalloc(c, in->bufs, &qf, (size_t)2 * n * n)) || (st = dalloc(c, in->bufs, &qd, (size_t)2 * n * n)) ||
-        (st = up(qf, F.data(), (size_t)2 * n * n)) || (st = up(qd, D.data(), (size_t)2 * n * n)))
-      return bail(st);
-    h.qf = qf;
-    h.qd = qd;
-    fbound = 4.0 * n * n * 16384.0 * 16384.0;
-  } else if (d->kind == KKNAP) {
-    if (n > 16384) return bail(fail(c, GX_E_UNSUPPORTED, "knapsack n <= 16384"));
-    if ((st = to_host(c, d, d->a, (size_t)n, A)) || (st = to_host(c, d, d->b, (size_t)n, B))) return bail(st);
-    int64_t mv = 0, sw = 0, sv = 0;
-    for (int i = 0; i < n; ++i) {
-      if (A[i] < 0 || A[i] > (1 << 20) || B[i] < 0 || B[i] > (1 << 20))
-        return bail(fail(c, GX_E_INVALID, "knapsack weights and values must lie in [0, 2^20]"));
-      mv = std::max<int64_t>(mv, B[i]);
-      sw += A[i];
-      sv += B[i];
-    }
-    if (d->capacity < 0) return bail(fail(c, GX_E_INVALID, "capacity must be >= 0"));
-    h.lambda = mv + 1;
-    int32_t *kw, *kv;
-    if ((st = dalloc(c, in->bufs, &kw, (size_t)4 * n)) || (st = dalloc(c, in->bufs, &kv, (size_t)4 * n)) ||
-        (st = up(kw, A.data(), (size_t)4 * n)) || (st = up(kv, B.data(), (size_t)4 * n)))
-      return bail(st);
-    h.kw = kw;
-    h.kv = kv;
-    fbound = 4.0 * ((double)sv + (double)h.lambda * (double)sw);
-  } else if (d->kind == KVRP) {
-    if (n > kMaxVrpN) return bail(fail(c, GX_E_UNSUPPORTED, "VRPTW n <= %d", kMaxVrpN));
-    const int m = n + 1;
-    if ((st = to_host(c, d, d->a, (size_t)2 * m, A)) || (st = to_host(c, d, d->b, (size_t)3 * m, B))) return bail(st);
-    for (int32_t v : A)
-      if (v < 0 || v >= kMaxCoord) return bail(fail(c, GX_E_INVALID, "coordinates must lie in [0, 16384)"));
-    for (int i = 0; i < m; ++i) {
-      const int32_t q = B[i], r = B[m + i], u = B[2 * m + i];
-      if (q < 0 || q > d->capacity || r < 0 || u < 0 || r > (1 << 19) || u > (1 << 19))
-        return bail(fail(c, GX_E_INVALID, "VRPTW demand in [0, capacity], times in [0, 2^19]"));
-    }
-    if (d->capacity < 1 || d->vehicles < 1 || d->service_time < 0 || d->service_time > (1 << 16) ||
-        d->horizon < 0 || d->horizon > (1 << 19))
-      return bail(fail(c, GX_E_INVALID, "VRPTW capacity, vehicles >= 1; service <= 2^16; horizon in [0, 2^19]"));
-    h.dn = m;
-    int32_t *xy, *dem, *rdy, *due;
-    int16_t *d16;
-    if ((st = dalloc(c, in->bufs, &xy, (size_t)8 * m)) || (st = up(xy, A.data(), (size_t)8 * m)) ||
-        (st = dalloc(c, in->bufs, &d16, (size_t)2 * m * m)) || (st = dalloc(c, in->bufs, &dem, (size_t)4 * m)) ||
-        (st = dalloc(c, in->bufs, &rdy, (size_t)4 * m)) || (st = dalloc(c, in->bufs, &due, (size_t)4 * m)) ||
-        (st = up(dem, B.data(), (size_t)4 * m)) || (st = up(rdy, B.data() + m, (size_t)4 * m)) ||
-        (st = up(due, B.data() + 2 * m, (size_t)4 * m)))
-      return bail(st);
-    HIPCHK(c, gxk::build_tsp_d16_from_xy(xy, m, d16, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    h.xy = xy;
-    h.has_xy = 1;
-    h.d16 = d16;
-    h.dem = dem;
-    h.rdy = rdy;
-    h.due = due;
-    fbound = 4.0 * (m * 23171.0 + 100.0 * m * (m * 23171.0 + (1 << 19) + (double)m * (1 << 16)) + 10000.0 * m);
-  } else if (d->kind == KCOLOR) {
-    if (n > 32767) return bail(fail(c, GX_E_UNSUPPORTED, "colouring n <= 32767"));
-    if (d->lb > d->ub || d->lb < -32768 || d->ub > 32767)
-      return bail(fail(c, GX_E_INVALID, "colouring needs -32768 <= lb <= ub <= 32767"));
-    if (d->n_edges < 0 || d->n_edges > (1 << 20)) return bail(fail(c, GX_E_INVALID, "n_edges in [0, 2^20]"));
-    if ((st = to_host(c, d, d->a, (size_t)2 * d->n_edges, A))) return bail(st);
-    std::vector<int32_t> off(n + 1, 0), adj((size_t)2 * d->n_edges);
-    for (int e = 0; e < d->n_edges; ++e) {
-      const int u = A[2 * e], v = A[2 * e + 1];
-      if (u < 0 || v < 0 || u >= n || v >= n || u == v)
-        return bail(fail(c, GX_E_INVALID, "edge %d out of range or a self loop", e));
-      off[u + 1]++;
-      off[v + 1]++;
-    }
-    for (int i = 0; i < n; ++i) off[i + 1] += off[i];
-    std::vector<int32_t> fill(off.begin(), off.end() - 1);
-    for (int e = 0; e < d->n_edges; ++e) {
-      const int u = A[2 * e], v = A[2 * e + 1];
-      adj[fill[u]++] = v;
-      adj[fill[v]++] = u;
-    }
-    int32_t *po, *pa, *pe;
-    if ((st = dalloc(c, in->bufs, &po, (size_t)4 * (n + 1))) || (st = up(po, off.data(), (size_t)4 * (n + 1))) ||
-        (st = dalloc(c, in->bufs, &pa, std::max<size_t>(16, adj.size() * 4))) ||
-        (st = dalloc(c, in->bufs, &pe, std::max<size_t>(16, A.size() * 4))))
-      return bail(st);
-    if (!adj.empty() && ((st = up(pa, adj.data(), adj.size() * 4)) || (st = up(pe, A.data(), A.size() * 4))))
-      return bail(st);
-    h.adj_off = po;
-    h.adj = pa;
-    h.edges = pe;
-    fbound = 4.0 * d->n_edges + 4;
-  } else {
-    return bail(fail(c, GX_E_INVALID, "unknown problem kind %d", d->kind));
+    return st;
   }
-  if (fbound >= std::ldexp(1.0, 45)) return bail(fail(c, GX_E_UNSUPPORTED, "objective range exceeds 2^45"));
-  DevInst *dd;
-  if ((st = dalloc(c, in->bufs, &dd, sizeof(DevInst))) || (st = up(dd, &h, sizeof(DevInst)))) return bail(st);
   in->d = dd;
-  in->key = d->instance_key;
+  in->key = pr.key;
+  in->max_d = pr.max_d;
   c->insts.push_back(in);
   *out = in;
   return GX_OK;
@@ -375,26 +416,39 @@ gx_status gx_instance_upload(gx_ctx *c, const gx_instance_desc *d, gx_instance *
 
 namespace {
 
-uint32_t resolve_stage(const gx_instance *in, uint32_t req) {
-  if (in->h.kind != KTSP) return 0;
+// What job setup needs to know about an instance (uploaded or prepared).
+struct InstInfo {
+  DevInst h;            // host copy (device pointers may be null before placement)
+  DevInst *d;           // device record (null before placement)
+  bool has_d16, has_d32, has_xy;
+  uint32_t key;
+};
+
+InstInfo info_of(const gx_instance *in) {
+  return InstInfo{in->h, in->d, in->h.d16 != nullptr, in->h.d32 != nullptr, in->h.has_xy != 0, in->key};
+}
+
+uint32_t resolve_stage(const InstInfo &ii, uint32_t req) {
+  if (ii.h.kind != KTSP) return 0;
   if (req != SAUTO) return req;
-  const int n = in->h.n;
-  if (n <= 128 && in->h.d16) return SLDS16;
-  if (in->h.has_xy) return SLDSXY;
-  if (in->h.d16) return SGLB16;
+  const int n = ii.h.n;
+  if (n <= 128 && ii.has_d16) return SLDS16;
+  if (ii.has_xy) return SLDSXY;
+  if (ii.has_d16) return SGLB16;
   return SGLB32;
 }
 
-uint32_t job_lds(const gx_instance *in, uint32_t stage) {
-  uint32_t b = lds_bytes_for(in->h.kind, in->h.n, (int)stage);
-  if (in->h.kind == KCOLOR) b += (uint32_t)pad16((size_t)8 * in->h.n_edges);
+uint32_t job_lds(const InstInfo &ii, uint32_t stage) {
+  uint32_t b = lds_bytes_for(ii.h.kind, ii.h.n, (int)stage);
+  if (ii.h.kind == KCOLOR) b += (uint32_t)pad16((size_t)8 * ii.h.n_edges);
   return std::max<uint32_t>(b, 16);
 }
 
 // Validate parameters and fill the constant part of a DevJob.
-gx_status fill_job(gx_ctx *c, gx_instance *in, const gx_solve_params *p, DevJob &h, uint32_t P_auto) {
+gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJob &h, uint32_t P_auto,
+                   uint32_t lds_limit) {
   if (!p) return fail(c, GX_E_INVALID, "null parameters");
-  const uint32_t mask = p->op_mask ? (p->op_mask & encoding_ops(in->h.kind)) : encoding_ops(in->h.kind);
+  const uint32_t mask = p->op_mask ? (p->op_mask & encoding_ops(ii.h.kind)) : encoding_ops(ii.h.kind);
   if (!mask) return fail(c, GX_E_INVALID, "op_mask enables no operator of this encoding");
   if (p->alpha_q32 == 0) return fail(c, GX_E_INVALID, "alpha_q32 is required");
   const uint32_t C = p->candidates ? p->candidates : 128;
@@ -411,17 +465,17 @@ gx_status fill_job(gx_ctx *c, gx_instance *in, const gx_solve_params *p, DevJob 
   const uint32_t K = p->oversample_k ? p->oversample_k : 4;
   if ((uint64_t)K * P > (1u << 22)) return fail(c, GX_E_UNSUPPORTED, "oversample pool <= 2^22");
   if (p->staging > SGLB32) return fail(c, GX_E_INVALID, "unknown staging %u", p->staging);
-  const uint32_t stage = resolve_stage(in, p->staging);
-  if (in->h.kind == KTSP) {
-    if ((stage == SLDS16 || stage == SGLB16) && !in->h.d16)
+  const uint32_t stage = resolve_stage(ii, p->staging);
+  if (ii.h.kind == KTSP) {
+    if ((stage == SLDS16 || stage == SGLB16) && !ii.has_d16)
       return fail(c, GX_E_UNSUPPORTED, "no int16 distance matrix for this instance");
-    if (stage == SLDSXY && !in->h.has_xy) return fail(c, GX_E_UNSUPPORTED, "coordinates-in-LDS needs coordinates");
+    if (stage == SLDSXY && !ii.has_xy) return fail(c, GX_E_UNSUPPORTED, "coordinates-in-LDS needs coordinates");
   }
-  const uint32_t lds = job_lds(in, stage);
-  if (lds > c->max_lds)
-    return fail(c, GX_E_UNSUPPORTED, "instance needs %u bytes of LDS per workgroup (device has %u)", lds, c->max_lds);
+  const uint32_t lds = job_lds(ii, stage);
+  if (lds > lds_limit)
+    return fail(c, GX_E_UNSUPPORTED, "instance needs %u bytes of LDS per workgroup (limit %u)", lds, lds_limit);
   memset(&h, 0, sizeof h);
-  h.inst = in->d;
+  h.inst = ii.d;
   h.seed = p->seed;
   h.t0_param = p->t0_q16;
   h.P = P;
@@ -433,12 +487,37 @@ gx_status fill_job(gx_ctx *c, gx_instance *in, const gx_solve_params *p, DevJob 
   h.aos_A = A;
   h.w_floor = FL;
   h.stag_limit = p->stagnation_epochs ? p->stagnation_epochs : 5;
-  h.key = in->key;
+  h.key = ii.key;
   h.alpha = p->alpha_q32;
   h.Q = K * P;
   h.stage = stage;
   h.lds_bytes = lds;
   return GX_OK;
+}
+
+int heur_mats_of(int kind) { return kind == KQAP ? 2 : ((kind == KTSP || kind == KVRP) ? 1 : 0); }
+
+// bytes of the per-job device arrays, laid out by carve_job
+size_t job_array_bytes(size_t n, size_t P, size_t Q) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return 2 * al(4 * n * P) + 2 * al(8 * P) + al(4 * n * Q) + al(8 * Q) + al(32 * n) + al(4 * n);
+}
+
+void carve_job(DevJob &h, char *q, size_t n) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  auto take = [&](size_t bytes) {
+    char *r = q;
+    q += al(bytes);
+    return r;
+  };
+  h.cur = (int32_t *)take(4 * n * h.P);
+  h.best = (int32_t *)take(4 * n * h.P);
+  h.cur_f = (int64_t *)take(8 * (size_t)h.P);
+  h.best_f = (int64_t *)take(8 * (size_t)h.P);
+  h.pool = (int32_t *)take(4 * n * h.Q);
+  h.pool_f = (int64_t *)take(8 * (size_t)h.Q);
+  h.sums = (int64_t *)take(32 * n);
+  h.best_out = (int32_t *)take(4 * n);
 }
 
 gx_status ensure_d32(gx_ctx *c, gx_instance *in) {
@@ -504,8 +583,9 @@ extern "C" {
 
 gx_status gx_autosize_population(gx_ctx *c, const gx_instance *in, const gx_solve_params *p, uint32_t *out) {
   if (!c || !in || !out) return fail(c, GX_E_INVALID, "null argument");
-  const uint32_t stage = resolve_stage(in, p ? p->staging : 0);
-  const uint32_t lds = job_lds(in, stage);
+  const InstInfo ii = info_of(in);
+  const uint32_t stage = resolve_stage(ii, p ? p->staging : 0);
+  const uint32_t lds = job_lds(ii, stage);
   int occ = 0;
   HIPCHK(c, gxk::occupancy_plain(in->h.kind, (int)stage, lds, &occ));
   occ = std::max(1, std::min(occ, 8));
@@ -530,7 +610,7 @@ gx_status gx_job_create(gx_ctx *c, const gx_instance *cin, const gx_solve_params
     delete j;
     return s;
   };
-  if ((st = fill_job(c, in, p, h, P_auto))) return bail(st);
+  if ((st = fill_job(c, info_of(in), p, h, P_auto, c->max_lds))) return bail(st);
   if (h.stage == SGLB32 && (st = ensure_d32(c, in))) return bail(st);
   const size_t n = (size_t)in->h.n;
   if ((st = dalloc(c, j->bufs, &h.cur, 4 * n * h.P)) || (st = dalloc(c, j->bufs, &h.best, 4 * n * h.P)) ||
@@ -541,7 +621,7 @@ gx_status gx_job_create(gx_ctx *c, const gx_instance *cin, const gx_solve_params
     return bail(st);
   if (hipMemcpy(j->d, &h, sizeof(DevJob), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(c, GX_E_DEVICE, "job upload failed"));
-  const int mats = in->h.kind == KQAP ? 2 : ((in->h.kind == KTSP || in->h.kind == KVRP) ? 1 : 0);
+  const int mats = heur_mats_of(in->h.kind);
   hipError_t e = gxk::init_jobs(j->d, 1, h.Q, (int)n, mats, c->stream);
   if (e != hipSuccess) return bail(fail(c, GX_E_DEVICE, "init launch: %s", hipGetErrorString(e)));
   if (hipEventCreate(&j->ev0) != hipSuccess || hipEventCreate(&j->ev1) != hipSuccess)
@@ -712,7 +792,6 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
   uint32_t max_q = 0, max_lds = 16, L = 0;
   int max_n = 1, max_mats = 0;
   size_t n_items = 0;
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   for (int i = 0; i < count; ++i) {
     gx_instance *in = const_cast<gx_instance *>(insts[i]);
     if (!in) return fail(c, GX_E_INVALID, "instance %d is null", i);
@@ -721,15 +800,18 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
     uint32_t P_auto = 0;
     gx_status st;
     if (!p->population && (st = gx_autosize_population(c, in, p, &P_auto))) return st;
-    if ((st = fill_job(c, in, p, hj[i], P_auto))) return fail(c, st, "job %d: %s", i, c->err.c_str());
+    if ((st = fill_job(c, info_of(in), p, hj[i], P_auto, c->max_lds))) {
+      const std::string m = c->err;
+      return fail(c, st, "job %d: %s", i, m.c_str());
+    }
     if (hj[i].stage == SGLB32 && (st = ensure_d32(c, in))) return st;
     const size_t n = (size_t)in->h.n, P = hj[i].P, Q = hj[i].Q;
     off[i] = total;
-    total += 2 * al(4 * n * P) + 2 * al(8 * P) + al(4 * n * Q) + al(8 * Q) + al(32 * n) + al(4 * n);
+    total += job_array_bytes(n, P, Q);
     max_q = std::max(max_q, hj[i].Q);
     max_lds = std::max(max_lds, hj[i].lds_bytes);
     max_n = std::max(max_n, in->h.n);
-    max_mats = std::max(max_mats, in->h.kind == KQAP ? 2 : ((in->h.kind == KTSP || in->h.kind == KVRP) ? 1 : 0));
+    max_mats = std::max(max_mats, heur_mats_of(in->h.kind));
     L = std::max(L, chunks_between(0, hj[i].G, hj[i].E));
     n_items += P;
   }
@@ -764,23 +846,7 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
   for (size_t k = 0; k < n_items; ++k) items[k] = it[k].second;
   if (hipMalloc((void **)&b->items, sizeof(uint2) * n_items) != hipSuccess)
     return bail(fail(c, GX_E_NOMEM, "batch work items"));
-  for (int i = 0; i < count; ++i) {
-    const size_t n = (size_t)insts[i]->h.n, P = hj[i].P, Q = hj[i].Q;
-    char *q = arena + off[i];
-    auto take = [&](size_t bytes) {
-      char *r = q;
-      q += al(bytes);
-      return r;
-    };
-    hj[i].cur = (int32_t *)take(4 * n * P);
-    hj[i].best = (int32_t *)take(4 * n * P);
-    hj[i].cur_f = (int64_t *)take(8 * P);
-    hj[i].best_f = (int64_t *)take(8 * P);
-    hj[i].pool = (int32_t *)take(4 * n * Q);
-    hj[i].pool_f = (int64_t *)take(8 * Q);
-    hj[i].sums = (int64_t *)take(32 * n);
-    hj[i].best_out = (int32_t *)take(4 * n);
-  }
+  for (int i = 0; i < count; ++i) carve_job(hj[i], arena + off[i], (size_t)insts[i]->h.n);
   HIPCHK(c, hipMemcpy(b->jobs_d, hj.data(), sizeof(DevJob) * count, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(b->items, items.data(), sizeof(uint2) * n_items, hipMemcpyHostToDevice));
   HIPCHK(c, gxk::init_jobs(b->jobs_d, count, max_q, max_n, max_mats, c->stream));
@@ -821,6 +887,450 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
     c->jobs.push_back(made[i]);
     jobs_out[i] = made[i];
   }
+  return GX_OK;
+}
+
+}  // extern "C"
+
+// ==================================================================== serving
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+namespace {
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+// First-fit allocator over one contiguous region (offsets only), 256-byte granules.
+class Arena {
+ public:
+  explicit Arena(size_t cap = 0) { reset(cap); }
+  void reset(size_t cap) {
+    free_.clear();
+    cap_ = cap & ~size_t(255);
+    used_ = 0;
+    if (cap_) free_[0] = cap_;
+  }
+  bool alloc(size_t bytes, size_t *off) {
+    bytes = (bytes + 255) & ~size_t(255);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes, start = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[start] = rest;
+      used_ += bytes;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    used_ -= bytes;
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t used() const { return used_; }
+  size_t cap() const { return cap_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t cap_ = 0, used_ = 0;
+};
+
+enum ReqState { RQ_PENDING, RQ_RESIDENT, RQ_FETCHING, RQ_DONE, RQ_CANCELLED };
+
+struct SrvReq {
+  uint64_t ticket = 0, t_submit = 0, t_done = 0;
+  int state = RQ_PENDING;
+  bool cancel = false;
+  Prepared pr;
+  DevJob hj{};
+  size_t inst_bytes = 0, bytes = 0, off = 0, pin_off = 0;
+  int slot = -1, n = 0;
+  uint32_t g = 0;
+  hipEvent_t ev = nullptr;
+  std::vector<int32_t> sol;
+  int64_t f = 0;
+  double cost = 0;
+};
+
+}  // namespace
+
+struct gx_server {
+  gx_ctx *c = nullptr;
+  gx_ctx vctx;   // validation messages (guarded by mu)
+  gx_server_cfg cfg{};
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<SrvReq *> pending;
+  std::unordered_map<uint64_t, SrvReq *> reqs;
+  uint64_t next_ticket = 1;
+  std::vector<SrvReq *> slots;
+  std::vector<int> free_slots;
+  DevJob *jobs_d = nullptr;
+  uint2 *items_d[2] = {nullptr, nullptr};
+  uint2 *items_h[2] = {nullptr, nullptr};
+  hipEvent_t items_ev[2] = {nullptr, nullptr};
+  size_t items_cap = 0;
+  char *arena_d = nullptr;
+  Arena arena;
+  char *pin = nullptr;
+  Arena pin_arena;
+  hipStream_t s = nullptr;
+  std::thread th;
+  std::atomic<bool> stop{false};
+  gx_server_stats st{};
+  std::string err;
+};
+
+namespace {
+
+gx_status srv_grow_items(gx_server *S, size_t need) {
+  if (need <= S->items_cap) return GX_OK;
+  size_t cap = std::max<size_t>(need, 2 * S->items_cap);
+  for (int b = 0; b < 2; ++b) {
+    if (S->items_ev[b]) (void)hipEventSynchronize(S->items_ev[b]);
+    (void)hipFree(S->items_d[b]);
+    (void)hipHostFree(S->items_h[b]);
+    S->items_d[b] = nullptr;
+    S->items_h[b] = nullptr;
+    if (hipMalloc((void **)&S->items_d[b], cap * sizeof(uint2)) != hipSuccess ||
+        hipHostMalloc((void **)&S->items_h[b], cap * sizeof(uint2), 0) != hipSuccess)
+      return GX_E_NOMEM;
+  }
+  S->items_cap = cap;
+  return GX_OK;
+}
+
+// Place an admitted request into its arena block and start its initialisation.
+gx_status srv_stage(gx_server *S, SrvReq *r) {
+  char *base = S->arena_d + r->off;
+  DevInst hh;
+  DevInst *dd = nullptr;
+  gx_status st = place_instance(&S->vctx, r->pr, base, S->s, &hh, &dd);
+  if (st) return st;
+  r->hj.inst = dd;
+  carve_job(r->hj, base + r->inst_bytes, (size_t)r->n);
+  if (hipMemcpyAsync(S->jobs_d + r->slot, &r->hj, sizeof(DevJob), hipMemcpyHostToDevice, S->s) != hipSuccess ||
+      gxk::init_jobs(S->jobs_d + r->slot, 1, r->hj.Q, r->n, heur_mats_of(r->pr.h.kind), S->s) != hipSuccess ||
+      gxk::set_stop(S->jobs_d + r->slot, 1, 0, 1, S->s) != hipSuccess)
+    return GX_E_DEVICE;
+  r->g = 0;
+  return GX_OK;
+}
+
+void srv_release(gx_server *S, SrvReq *r) {   // caller holds mu
+  S->arena.release(r->off, r->bytes);
+  if (r->pin_off != (size_t)-1) S->pin_arena.release(r->pin_off, 4 * (size_t)r->n + 8);
+  S->slots[r->slot] = nullptr;
+  S->free_slots.push_back(r->slot);
+  r->slot = -1;
+}
+
+void server_loop(gx_server *S) {
+  (void)hipSetDevice(S->c->dev);
+  int buf = 0;
+  uint64_t busy_since = 0;
+  std::vector<SrvReq *> admitted, active;
+  while (!S->stop.load()) {
+    admitted.clear();
+    bool any_resident = false;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      for (auto it = S->pending.begin(); it != S->pending.end() && !S->free_slots.empty();) {
+        SrvReq *r = *it;
+        size_t off = 0, poff = 0;
+        if (!S->arena.alloc(r->bytes, &off)) {
+          ++it;   // does not fit now; smaller requests behind it may
+          continue;
+        }
+        if (!S->pin_arena.alloc(4 * (size_t)r->n + 8, &poff)) {
+          S->arena.release(off, r->bytes);
+          ++it;
+          continue;
+        }
+        r->off = off;
+        r->pin_off = poff;
+        r->slot = S->free_slots.back();
+        S->free_slots.pop_back();
+        S->slots[r->slot] = r;
+        r->state = RQ_RESIDENT;
+        S->st.admitted++;
+        admitted.push_back(r);
+        it = S->pending.erase(it);
+      }
+      for (SrvReq *r : S->slots)
+        if (r) any_resident = true;
+      if (!any_resident && S->pending.empty()) {
+        if (busy_since) {
+          S->st.busy_seconds += (now_ns() - busy_since) * 1e-9;
+          busy_since = 0;
+        }
+        S->cv.wait_for(lk, std::chrono::milliseconds(2));
+        continue;
+      }
+    }
+    if (!busy_since) busy_since = now_ns();
+    for (SrvReq *r : admitted)
+      if (srv_stage(S, r) != GX_OK) r->cancel = true;   // staging failure: reported as cancelled
+    // ---- one quantum: every resident running request advances one epoch chunk
+    active.clear();
+    uint32_t max_lds = 16;
+    size_t n_items = 0;
+    for (SrvReq *r : S->slots)
+      if (r && r->state == RQ_RESIDENT && !r->cancel && r->g < r->hj.G) {
+        active.push_back(r);
+        max_lds = std::max(max_lds, r->hj.lds_bytes);
+        n_items += r->hj.P;
+      }
+    if (!active.empty() && srv_grow_items(S, n_items) == GX_OK) {
+      std::stable_sort(active.begin(), active.end(), [](SrvReq *a, SrvReq *b) { return a->cost > b->cost; });
+      (void)hipEventSynchronize(S->items_ev[buf]);
+      uint2 *h = S->items_h[buf];
+      size_t k = 0;
+      for (SrvReq *r : active)
+        for (uint32_t sl = 0; sl < r->hj.P; ++sl) h[k++] = make_uint2((uint32_t)r->slot, sl);
+      int occ = 1;
+      (void)gxk::occupancy_items(max_lds, &occ);
+      const uint32_t grid = (uint32_t)std::min<size_t>(n_items, (size_t)S->c->info.cus * std::max(1, occ));
+      (void)hipMemcpyAsync(S->items_d[buf], h, n_items * sizeof(uint2), hipMemcpyHostToDevice, S->s);
+      (void)gxk::evolve_items(S->jobs_d, S->items_d[buf], (uint32_t)n_items, grid, max_lds, S->s);
+      (void)hipEventRecord(S->items_ev[buf], S->s);
+      buf ^= 1;
+      uint64_t evals = 0;
+      for (SrvReq *r : active) {
+        const uint32_t E = r->hj.E;
+        const uint32_t ng = (uint32_t)std::min<uint64_t>(r->hj.G, ((uint64_t)r->g / E + 1) * E);
+        evals += (uint64_t)r->hj.P * r->hj.C * (ng - r->g);
+        r->g = ng;
+        if (r->g == r->hj.G) {   // finished: fetch the best solution asynchronously
+          (void)gxk::fetch_best(S->jobs_d + r->slot, 1, S->s);
+          char *dst = S->pin + r->pin_off;
+          (void)hipMemcpyAsync(dst, r->hj.best_out, 4 * (size_t)r->n, hipMemcpyDeviceToHost, S->s);
+          (void)hipMemcpyAsync(dst + 4 * (size_t)r->n, (char *)(S->jobs_d + r->slot) + offsetof(DevJob, best_out_f),
+                               8, hipMemcpyDeviceToHost, S->s);
+          (void)hipEventRecord(r->ev, S->s);
+          r->state = RQ_FETCHING;
+        }
+      }
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->st.quanta++;
+      S->st.move_evals += evals;
+    }
+    // cancelled residents: retire after the work enqueued so far has drained
+    for (SrvReq *r : S->slots)
+      if (r && r->cancel && r->state == RQ_RESIDENT) {
+        (void)hipEventRecord(r->ev, S->s);
+        r->state = RQ_FETCHING;
+      }
+    // completions
+    bool waited = active.empty();
+    for (SrvReq *r : S->slots) {
+      if (!r || r->state != RQ_FETCHING) continue;
+      hipError_t q = waited ? hipEventSynchronize(r->ev) : hipEventQuery(r->ev);
+      if (q != hipSuccess) continue;
+      std::lock_guard<std::mutex> lk(S->mu);
+      if (!r->cancel) {
+        const char *src = S->pin + r->pin_off;
+        r->sol.assign((const int32_t *)src, (const int32_t *)src + r->n);
+        memcpy(&r->f, src + 4 * (size_t)r->n, 8);
+        r->state = RQ_DONE;
+        S->st.completed++;
+      } else {
+        r->state = RQ_CANCELLED;
+        S->st.cancelled++;
+      }
+      r->t_done = now_ns();
+      srv_release(S, r);
+    }
+  }
+  (void)hipStreamSynchronize(S->s);
+}
+
+}  // namespace
+
+extern "C" {
+
+gx_status gx_server_create(gx_ctx *c, const gx_server_cfg *cfg, gx_server **out) {
+  if (!c || !out) return fail(c, GX_E_INVALID, "null argument");
+  *out = nullptr;
+  HIPCHK(c, hipSetDevice(c->dev));
+  gx_server *S = new gx_server();
+  S->c = c;
+  S->vctx.dev = c->dev;
+  S->vctx.info = c->info;
+  S->vctx.max_lds = c->max_lds;
+  S->cfg.hbm_budget_bytes = cfg && cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (1ull << 30);
+  S->cfg.max_resident = cfg && cfg->max_resident ? cfg->max_resident : 1024;
+  S->cfg.max_lds_bytes = cfg && cfg->max_lds_bytes ? std::min(cfg->max_lds_bytes, c->max_lds) : std::min(65536u, c->max_lds);
+  auto bail = [&](const char *what) {
+    (void)hipFree(S->arena_d);
+    (void)hipFree(S->jobs_d);
+    (void)hipHostFree(S->pin);
+    if (S->s) (void)hipStreamDestroy(S->s);
+    delete S;
+    return fail(c, GX_E_NOMEM, "server: %s", what);
+  };
+  if (hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) != hipSuccess) return bail("stream");
+  if (hipMalloc((void **)&S->arena_d, S->cfg.hbm_budget_bytes) != hipSuccess) return bail("arena");
+  S->arena.reset(S->cfg.hbm_budget_bytes);
+  if (hipMalloc((void **)&S->jobs_d, sizeof(DevJob) * S->cfg.max_resident) != hipSuccess) return bail("job table");
+  const size_t pin_bytes = std::max<size_t>(16u << 20, (size_t)S->cfg.max_resident * 4096);
+  if (hipHostMalloc((void **)&S->pin, pin_bytes, 0) != hipSuccess) return bail("pinned results");
+  S->pin_arena.reset(pin_bytes);
+  for (int b = 0; b < 2; ++b)
+    if (hipEventCreateWithFlags(&S->items_ev[b], hipEventDisableTiming) != hipSuccess) return bail("events");
+  if (srv_grow_items(S, 4096) != GX_OK) return bail("work items");
+  S->slots.assign(S->cfg.max_resident, nullptr);
+  for (int i = (int)S->cfg.max_resident - 1; i >= 0; --i) S->free_slots.push_back(i);
+  S->st.arena_bytes = S->arena.cap();
+  S->th = std::thread(server_loop, S);
+  *out = S;
+  return GX_OK;
+}
+
+gx_status gx_server_submit(gx_server *S, const gx_instance_desc *d, const gx_solve_params *p, uint64_t *ticket) {
+  if (!S || !d || !p || !ticket) return GX_E_INVALID;
+  if (d->is_device_ptr) return GX_E_INVALID;
+  SrvReq *r = new SrvReq();
+  std::unique_lock<std::mutex> lk(S->mu);
+  gx_status st = prepare_instance(&S->vctx, d, r->pr, false);
+  if (!st && p->population == 0) st = fail(&S->vctx, GX_E_INVALID, "served requests need a population");
+  if (!st && p->generations == 0) st = fail(&S->vctx, GX_E_INVALID, "generations must be >= 1");
+  if (!st) {
+    InstInfo ii{r->pr.h, nullptr, false, false, r->pr.h.has_xy != 0, r->pr.key};
+    for (const auto &a : r->pr.arrs) {
+      ii.has_d16 |= a.field == F_D16;
+      ii.has_d32 |= a.field == F_D32;
+    }
+    st = fill_job(&S->vctx, ii, p, r->hj, 0, S->cfg.max_lds_bytes);
+    if (!st && r->hj.stage == SGLB32 && !ii.has_d32) st = fail(&S->vctx, GX_E_UNSUPPORTED, "int32 staging needs a matrix");
+  }
+  if (st) {
+    S->err = S->vctx.err;
+    delete r;
+    return st;
+  }
+  r->n = r->pr.h.n;
+  r->inst_bytes = (r->pr.dev_bytes() + 255) & ~size_t(255);
+  r->bytes = r->inst_bytes + job_array_bytes((size_t)r->n, r->hj.P, r->hj.Q);
+  if (r->bytes > S->arena.cap() || 4 * (size_t)r->n + 8 > S->pin_arena.cap()) {
+    S->err = "request larger than the server arena";
+    delete r;
+    return GX_E_UNSUPPORTED;
+  }
+  const double n = r->n;
+  r->cost = (r->pr.h.kind == KQAP ? 4.0 * n * n / 3.0 : (r->pr.h.kind == KVRP ? 8.0 * n : n)) * r->hj.C;
+  if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
+    delete r;
+    return GX_E_DEVICE;
+  }
+  r->ticket = S->next_ticket++;
+  r->t_submit = now_ns();
+  S->reqs[r->ticket] = r;
+  S->pending.push_back(r);
+  S->st.submitted++;
+  *ticket = r->ticket;
+  lk.unlock();
+  S->cv.notify_one();
+  return GX_OK;
+}
+
+gx_status gx_server_poll(gx_server *S, uint64_t ticket, int32_t *sol, int32_t cap, int64_t *obj, uint64_t *t_sub,
+                         uint64_t *t_done) {
+  if (!S) return GX_E_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return GX_E_INVALID;
+  SrvReq *r = it->second;
+  if (r->state == RQ_CANCELLED) {
+    S->reqs.erase(it);
+    (void)hipEventDestroy(r->ev);
+    delete r;
+    return GX_E_CANCELLED;
+  }
+  if (r->state != RQ_DONE) return GX_E_NOT_READY;
+  if (sol && cap < r->n) return GX_E_INVALID;
+  if (sol) memcpy(sol, r->sol.data(), 4 * (size_t)r->n);
+  if (obj) *obj = r->f;
+  if (t_sub) *t_sub = r->t_submit;
+  if (t_done) *t_done = r->t_done;
+  S->reqs.erase(it);
+  (void)hipEventDestroy(r->ev);
+  delete r;
+  return GX_OK;
+}
+
+gx_status gx_server_cancel(gx_server *S, uint64_t ticket) {
+  if (!S) return GX_E_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return GX_E_INVALID;
+  SrvReq *r = it->second;
+  if (r->state == RQ_PENDING) {
+    S->pending.erase(std::remove(S->pending.begin(), S->pending.end(), r), S->pending.end());
+    r->state = RQ_CANCELLED;
+    S->st.cancelled++;
+  } else if (r->state == RQ_RESIDENT || r->state == RQ_FETCHING) {
+    r->cancel = true;
+  }
+  return GX_OK;
+}
+
+gx_status gx_server_stats_get(gx_server *S, gx_server_stats *out) {
+  if (!S || !out) return GX_E_INVALID;
+  std::lock_guard<std::mutex> lk(S->mu);
+  *out = S->st;
+  out->pending = (uint32_t)S->pending.size();
+  uint32_t res = 0;
+  for (SrvReq *r : S->slots) res += r != nullptr;
+  out->resident = res;
+  out->arena_used_bytes = S->arena.used();
+  out->arena_bytes = S->arena.cap();
+  return GX_OK;
+}
+
+gx_status gx_server_destroy(gx_server *S) {
+  if (!S) return GX_E_INVALID;
+  S->stop.store(true);
+  S->cv.notify_all();
+  if (S->th.joinable()) S->th.join();
+  (void)hipStreamSynchronize(S->s);
+  for (auto &kv : S->reqs) {
+    (void)hipEventDestroy(kv.second->ev);
+    delete kv.second;
+  }
+  for (int b = 0; b < 2; ++b) {
+    (void)hipFree(S->items_d[b]);
+    (void)hipHostFree(S->items_h[b]);
+    (void)hipEventDestroy(S->items_ev[b]);
+  }
+  (void)hipFree(S->arena_d);
+  (void)hipFree(S->jobs_d);
+  (void)hipHostFree(S->pin);
+  (void)hipStreamDestroy(S->s);
+  delete S;
   return GX_OK;
 }
 

@@ -23,7 +23,8 @@ N_OPS = 6
 EXPORTED = ["gx_create", "gx_destroy", "gx_last_error", "gx_get_device_info", "gx_instance_upload",
             "gx_instance_free", "gx_autosize_population", "gx_job_create", "gx_job_advance", "gx_solve",
             "gx_wait", "gx_poll", "gx_fetch_best", "gx_job_info_get", "gx_snapshot", "gx_job_free",
-            "gx_solve_batch", "gx_exp_tables"]
+            "gx_solve_batch", "gx_exp_tables", "gx_server_create", "gx_server_submit", "gx_server_poll",
+            "gx_server_cancel", "gx_server_stats_get", "gx_server_destroy"]
 
 
 class GxError(RuntimeError):
@@ -59,6 +60,17 @@ class gx_job_info(C.Structure):
                 ("move_evals", C.c_uint64), ("accepted", C.c_uint64),
                 ("evolve_launches", C.c_uint32), ("evolve_ms", C.c_float),
                 ("op_steps", C.c_uint64 * N_OPS), ("k_count", C.c_uint64 * 3)]
+
+
+class gx_server_cfg(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_resident", C.c_uint32), ("max_lds_bytes", C.c_uint32)]
+
+
+class gx_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("admitted", C.c_uint64), ("completed", C.c_uint64),
+                ("cancelled", C.c_uint64), ("quanta", C.c_uint64), ("move_evals", C.c_uint64),
+                ("resident", C.c_uint32), ("pending", C.c_uint32), ("arena_used_bytes", C.c_uint64),
+                ("arena_bytes", C.c_uint64), ("busy_seconds", C.c_double)]
 
 
 class gx_state_scalars(C.Structure):
@@ -99,6 +111,14 @@ def lib():
             "gx_job_free": ([vp, vp], i32),
             "gx_solve_batch": ([vp, pp, C.POINTER(gx_solve_params), i32, pp], i32),
             "gx_exp_tables": ([C.POINTER(u32), C.POINTER(u32)], i32),
+            "gx_server_create": ([vp, C.POINTER(gx_server_cfg), pp], i32),
+            "gx_server_submit": ([vp, C.POINTER(gx_instance_desc), C.POINTER(gx_solve_params),
+                                  C.POINTER(C.c_uint64)], i32),
+            "gx_server_poll": ([vp, C.c_uint64, vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_uint64),
+                                C.POINTER(C.c_uint64)], i32),
+            "gx_server_cancel": ([vp, C.c_uint64], i32),
+            "gx_server_stats_get": ([vp, C.POINTER(gx_server_stats)], i32),
+            "gx_server_destroy": ([vp], i32),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -278,3 +298,57 @@ def gx_solve_batch(ctx, insts, params_list):
     _check(ctx, lib().gx_solve_batch(ctx, C.cast(arr, C.POINTER(C.c_void_p)), pars, count,
                                      C.cast(jobs, C.POINTER(C.c_void_p))))
     return [C.c_void_p(j) for j in jobs]
+
+
+# ------------------------------------------------------------------ serving
+def gx_server_create(ctx, hbm_budget_bytes=0, max_resident=0, max_lds_bytes=0):
+    cfg = gx_server_cfg(hbm_budget_bytes=hbm_budget_bytes, max_resident=max_resident,
+                        max_lds_bytes=max_lds_bytes)
+    out = C.c_void_p()
+    _check(ctx, lib().gx_server_create(ctx, C.byref(cfg), C.byref(out)))
+    return out
+
+
+def gx_server_submit(srv, inst, params) -> int:
+    """Thread-safe; returns the ticket.  Raises GxError on a rejected request."""
+    keep = []
+    d = _desc(inst, keep)
+    pp = _params(params)
+    t = C.c_uint64()
+    st = lib().gx_server_submit(srv, C.byref(d), C.byref(pp), C.byref(t))
+    if st != GX_OK:
+        raise GxError(st, "request rejected")
+    return int(t.value)
+
+
+def gx_server_poll(srv, ticket: int, n: int):
+    """None while not ready; otherwise (solution, objective, t_submit_ns, t_done_ns).
+    Raises GxError(GX_E_CANCELLED) for a cancelled request."""
+    sol = np.zeros(n, np.int32)
+    f, ts, td = C.c_int64(), C.c_uint64(), C.c_uint64()
+    st = lib().gx_server_poll(srv, ticket, sol.ctypes.data, n, C.byref(f), C.byref(ts), C.byref(td))
+    if st == GX_E_NOT_READY:
+        return None
+    if st != GX_OK:
+        raise GxError(st, f"ticket {ticket}")
+    return sol, int(f.value), int(ts.value), int(td.value)
+
+
+def gx_server_cancel(srv, ticket: int):
+    st = lib().gx_server_cancel(srv, ticket)
+    if st != GX_OK:
+        raise GxError(st, f"ticket {ticket}")
+
+
+def gx_server_stats_get(srv) -> dict:
+    s = gx_server_stats()
+    st = lib().gx_server_stats_get(srv, C.byref(s))
+    if st != GX_OK:
+        raise GxError(st, "stats")
+    return {k: getattr(s, k) for k, _ in gx_server_stats._fields_}
+
+
+def gx_server_destroy(srv):
+    st = lib().gx_server_destroy(srv)
+    if st != GX_OK:
+        raise GxError(st, "destroy")
