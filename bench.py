@@ -72,6 +72,15 @@ def main():
     ap.add_argument("--staging", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["tsp442", "batched", "served"], default="tsp442",
+                    help="tsp442: the benchmark line; batched / served: the systems patterns")
+    ap.add_argument("--instances", type=int, default=4096, help="batched: number of instances")
+    ap.add_argument("--batch-generations", type=int, default=5000)
+    ap.add_argument("--plain-sample", type=int, default=32, help="batched/served: requests solved alone")
+    ap.add_argument("--rate", type=float, default=2000.0, help="served: offered requests/s")
+    ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
+    ap.add_argument("--served-generations", type=int, default=10000)
+    ap.add_argument("--served-population", type=int, default=4)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -90,6 +99,11 @@ def main():
                           "instances and requests shard across GPUs without exchange, "
                           "so N > 1 is not measured here"}))
         sys.exit(2)
+
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "served":
+        return bench_served(args)
 
     import torch
     import synth
@@ -172,6 +186,152 @@ def main():
     gx.gx_instance_free(ctx, h)
     gx.gx_destroy(ctx)
     print(json.dumps(line), flush=True)
+
+
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def bench_batched(args):
+    """Batched pattern: TSP n U[20,200] (3/4) and QAP n U[12,40] (1/4) in one
+    gx_solve_batch (persistent fused launch per epoch, graph-replayed), against
+    the plain solver on a sample of the same instances."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2603_19163_amd import autotune, gx
+
+    ctx = gx.gx_create(0, torch.cuda.Stream())
+    cus = gx.gx_get_device_info(ctx)["cus"]
+    count, G = args.instances, args.batch_generations
+    r = np.random.default_rng([4, count, 20260319])
+    n_tsp = count * 3 // 4
+    insts = []
+    for i in range(count):
+        if i < n_tsp:
+            insts.append(synth.tsp_uniform(int(r.integers(20, 201)), 10_000 + i, key=i))
+        else:
+            insts.append(synth.qap_random(int(r.integers(12, 41)), 20_000 + i, key=i))
+    P = autotune.fill_population(ctx, count)
+    samples = {}
+    for inst in insts:
+        samples.setdefault(autotune.bucket_of(inst.kind, inst.n), inst)
+    alpha = synth.alpha_q32_for(G)
+    staging = autotune.tune_buckets(
+        ctx, samples, lambda i: synth.Params(seed=1, generations=50, population=P, alpha_q32=alpha))
+    params = [synth.Params(seed=10**6 + i, generations=G, population=P, candidates=128, alpha_q32=alpha,
+                           staging=staging[autotune.bucket_of(inst.kind, inst.n)])
+              for i, inst in enumerate(insts)]
+    handles = [gx.gx_instance_upload(ctx, i) for i in insts]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    jobs = gx.gx_solve_batch(ctx, handles, params)
+    gx.gx_wait(ctx, jobs[0])
+    dt = time.perf_counter() - t0
+    results = [gx.gx_fetch_best(ctx, j, i.n) for j, i in zip(jobs, insts)]
+    evals = sum(p.population * p.candidates * p.generations for p in params)
+    # plain solver: the same requests one at a time, on an evenly spaced sample
+    idx = np.linspace(0, count - 1, min(args.plain_sample, count)).astype(int)
+    t1 = time.perf_counter()
+    same = 0
+    for i in idx:
+        job = gx.gx_solve(ctx, handles[i], params[i])
+        sol, f = gx.gx_fetch_best(ctx, job, insts[i].n)
+        same += int(f == results[i][1] and np.array_equal(sol, results[i][0]))
+        gx.gx_job_free(ctx, job)
+    plain_dt = (time.perf_counter() - t1) / len(idx)
+    for j in jobs:
+        gx.gx_job_free(ctx, j)
+    gx.gx_destroy(ctx)
+    print(json.dumps({
+        "metric": "batched solves/s", "value": count / dt, "unit": "solves/s",
+        "move_evals_per_s": evals / dt, "seconds": dt,
+        "plain_solves_per_s": 1.0 / plain_dt, "speedup_vs_plain": plain_dt * count / dt,
+        "plain_sample": int(len(idx)), "plain_identical": same,
+        "config": {"workload": f"{count} instances: {n_tsp} TSP n U[20,200] + {count - n_tsp} QAP n "
+                               f"U[12,40]; P={P} each (sized to fill {cus} CUs), "
+                               f"C=128, {G} generations; staging per bucket {sorted(set(staging.values()))}",
+                   "population": P, "generations": G},
+    }), flush=True)
+
+
+def bench_served(args):
+    """Served pattern: Poisson arrivals of mixed TSP n U[20,500], QAP n U[12,50]
+    and knapsack n U[100,1000] requests into gx_server; p50/p99 latency and
+    completed solves/s, against the plain solver on a sample."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2603_19163_amd import gx
+
+    ctx = gx.gx_create(0, torch.cuda.Stream())
+    G, P = args.served_generations, args.served_population
+    alpha = synth.alpha_q32_for(G)
+    r = np.random.default_rng([5, 789, 20260319])
+    n_req = int(args.rate * args.duration)
+    gaps = r.exponential(1.0 / args.rate, size=n_req)
+    reqs = []
+    for i in range(n_req):
+        kind = int(r.integers(0, 3))
+        if kind == 0:
+            inst = synth.tsp_uniform(int(r.integers(20, 501)), 30_000 + i, key=i)
+        elif kind == 1:
+            inst = synth.qap_random(int(r.integers(12, 51)), 40_000 + i, key=i)
+        else:
+            inst = synth.knapsack_random(int(r.integers(100, 1001)), 50_000 + i, key=i)
+        reqs.append((inst, synth.Params(seed=int(r.integers(0, 2**40)), generations=G, population=P,
+                                        candidates=128, alpha_q32=alpha)))
+    srv = gx.gx_server_create(ctx, hbm_budget_bytes=8 << 30, max_resident=8192)
+    tickets = []
+    t0 = time.perf_counter()
+    t_next = t0
+    for (inst, p), gap in zip(reqs, gaps):
+        t_next += gap
+        while time.perf_counter() < t_next:
+            pass
+        tickets.append(gx.gx_server_submit(srv, inst, p))
+    t_sub_end = time.perf_counter()
+    lat, done, results = [], 0, {}
+    deadline = time.perf_counter() + 600
+    pending = set(range(n_req))
+    while pending and time.perf_counter() < deadline:
+        for k in list(pending):
+            res = gx.gx_server_poll(srv, tickets[k], reqs[k][0].n)
+            if res is not None:
+                results[k] = res
+                lat.append((res[3] - res[2]) * 1e-9)
+                pending.discard(k)
+        time.sleep(0.001)
+    t_end = time.perf_counter()
+    stats = gx.gx_server_stats_get(srv)
+    gx.gx_server_destroy(srv)
+    idx = [k for k in np.linspace(0, n_req - 1, min(args.plain_sample, n_req)).astype(int) if k in results]
+    same, plain_lat = 0, []
+    for k in idx:
+        inst, p = reqs[k]
+        h = gx.gx_instance_upload(ctx, inst)
+        t = time.perf_counter()
+        job = gx.gx_solve(ctx, h, p)
+        sol, f = gx.gx_fetch_best(ctx, job, inst.n)
+        plain_lat.append(time.perf_counter() - t)
+        same += int(f == results[k][1] and np.array_equal(sol, results[k][0]))
+        gx.gx_job_free(ctx, job)
+        gx.gx_instance_free(ctx, h)
+    gx.gx_destroy(ctx)
+    print(json.dumps({
+        "metric": "served solves/s", "value": len(results) / (t_end - t0), "unit": "solves/s",
+        "offered_rate": args.rate, "submitted": n_req, "completed": len(results),
+        "arrival_seconds": t_sub_end - t0, "drain_seconds": t_end - t_sub_end,
+        "p50_s": _pct(lat, 50), "p99_s": _pct(lat, 99),
+        "move_evals_per_s": stats["move_evals"] / max(stats["busy_seconds"], 1e-9),
+        "plain_p50_s": _pct(plain_lat, 50), "plain_p99_s": _pct(plain_lat, 99),
+        "plain_solves_per_s_sequential": len(plain_lat) / max(sum(plain_lat), 1e-9),
+        "plain_identical": same, "plain_sample": len(idx),
+        "server": stats,
+        "config": {"workload": f"Poisson {args.rate}/s for {args.duration}s: TSP n U[20,500], QAP n "
+                               f"U[12,50], knapsack n U[100,1000]; P={P}, C=128, {G} generations each"},
+    }), flush=True)
 
 
 if __name__ == "__main__":

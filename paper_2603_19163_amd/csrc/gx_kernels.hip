@@ -29,8 +29,9 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
                                        uint32_t k0, uint32_t k1, uint32_t r[4]) {
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
     c0 = hi1 ^ c1 ^ k0;
     c1 = lo1;
     c2 = hi0 ^ c3 ^ k1;
@@ -234,13 +235,14 @@ __device__ __forceinline__ void stage16(void *dst, const void *src, uint32_t byt
 
 // exact nearest-integer Euclidean distance for coordinates in [0, 2^14):
 // (isqrt(4 s) + 1) / 2 with the float estimate of the root corrected by one
-// step either way
+// step either way.  |dx|, |dy| < 2^14 and the root < 2^16, so every product
+// fits the full-rate 24-bit multiplier.
 __device__ __forceinline__ int nint_dist(int2 p, int2 q) {
   const int dx = p.x - q.x, dy = p.y - q.y;
-  const uint32_t s4 = 4u * (uint32_t)(dx * dx + dy * dy);
+  const uint32_t s4 = 4u * (uint32_t)(__mul24(dx, dx) + __mul24(dy, dy));
   uint32_t r = (uint32_t)sqrtf((float)s4);
-  r -= (r * r > s4);
-  r += ((r + 1) * (r + 1) <= s4);
+  r -= (__umul24(r, r) > s4);
+  r += (__umul24(r + 1, r + 1) <= s4);
   return (int)((r + 1) >> 1);
 }
 
