@@ -35,10 +35,44 @@ STAGE_NAMES = {1: "int16 distances in LDS", 2: "coordinates in LDS, exact distan
                3: "int16 distances through L2", 4: "int32 distances through L2"}
 
 LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz = 78,643 GB/s
+# 32-bit vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39,322 G lane-ops/s
+ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+
+# Algorithmic integer/float operations (per lane) of one move evaluation:
+#   per operator step: one Philox4x32-10 block (10 rounds x (2 widening multiplies
+#   + 4 xors) = 60), sampling of the operator and its positions (12), and the
+#   delta: per distance 14 ops for the exact recomputation from coordinates
+#   (2 sub, 2 mul, add, shift, 2 convert, sqrt, 2 x (mul, compare), add+shift)
+#   or 1 (address) for a stored matrix, plus one add per distance and one
+#   address per tour read;
+#   per candidate: k choice 3, key and running min 4.
+_PHILOX_OPS, _SAMPLE_OPS, _CAND_OPS = 60, 12, 7
+_DIST_OPS = {1: 1, 2: 14, 3: 1, 4: 1}
 
 
 def lds_bytes(op_steps, stage):
     return sum(op_steps[o] * (2 * _TOUR[o] + _DIST_BYTES[stage] * _DIST[o]) for o in range(4))
+
+
+def alu_ops(op_steps, evals, stage):
+    per_step = {o: _PHILOX_OPS + _SAMPLE_OPS + _DIST[o] * (_DIST_OPS[stage] + 1) + _TOUR[o] for o in range(4)}
+    return sum(op_steps[o] * per_step[o] for o in range(4)) + _CAND_OPS * evals
+
+
+def measured_traffic(path=os.path.join(ROOT, "profiles", "k_evolve_tsp442_traffic.md")):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel source (else None)."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2603_19163_amd", "csrc", "gx_kernels.hip")
+    try:
+        with open(path) as fh:
+            lines = dict(l.strip().split(": ", 1) for l in fh if ": " in l and l.startswith("- "))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if lines.get("- kernel_source_sha256") != sha:
+            return None
+        return float(lines["- hbm_bytes_per_launch"]), int(lines["- population"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(inst, params, seconds: float):
@@ -143,7 +177,11 @@ def main():
     ev_ms = sum(i["evolve_ms"] for i in infos)
     avg_launch_s = ev_ms / 1e3 / launches
     bytes_total = sum(lds_bytes(i["op_steps"], stage) for i in infos)
-    achieved = bytes_total / launches / avg_launch_s / 1e9
+    lds_achieved = bytes_total / launches / avg_launch_s / 1e9
+    ops_total = sum(alu_ops(i["op_steps"], i["move_evals"], stage) for i in infos)
+    achieved = ops_total / launches / avg_launch_s / 1e9
+    tr = measured_traffic()
+    traffic = tr[0] if tr and tr[1] == P else None
     k_tot = [sum(i["k_count"][k] for i in infos) for k in range(3)]
     steps_per_eval = sum((k + 1) * k_tot[k] for k in range(3)) / max(1, sum(k_tot))
     line = {
@@ -169,16 +207,20 @@ def main():
             "best_tour": best, "op_steps_per_eval": round(steps_per_eval, 4),
         },
         "roofline": {
-            "bound": "lds",
+            "bound": "alu",
             "kernel": "k_evolve<TSP>",
             "achieved": achieved,
-            "peak": LDS_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / LDS_PEAK_GBS,
-            "traffic": None,
+            "peak": ALU_PEAK_GOPS,
+            "unit": "G lane-ops/s",
+            "frac": achieved / ALU_PEAK_GOPS,
+            "traffic": traffic,
             "avg_launch_ms": avg_launch_s * 1e3,
             "launches": launches,
-            "algorithmic_bytes_per_launch": bytes_total / launches,
+            "algorithmic_ops_per_launch": ops_total / launches,
+        },
+        "roofline_lds": {
+            "achieved": lds_achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
+            "frac": lds_achieved / LDS_PEAK_GBS, "algorithmic_bytes_per_launch": bytes_total / launches,
         },
     }
     if not args.no_cpu_baseline:

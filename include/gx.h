@@ -131,7 +131,7 @@ gx_status gx_instance_free(gx_ctx *ctx, gx_instance *inst);
 /* Solve parameters; integer only; 0 selects the default in brackets.
  *  seed            key of the counter-based generator
  *  generations     generations G to run (>= 1 for gx_solve)
- *  population      P solutions, one workgroup each [0: sized from the device]
+ *  population      P solutions, one workgroup each [0: CUs x resident workgroups per CU]
  *  candidates      C sampled composite moves per solution per generation [128], <= 65536
  *  op_mask         GX_OP_* bits [all operators of the encoding]
  *  t0_q16          initial temperature, Q16 [a quarter of |f|/n of the best start]

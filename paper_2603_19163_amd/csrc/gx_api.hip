@@ -588,7 +588,8 @@ gx_status gx_autosize_population(gx_ctx *c, const gx_instance *in, const gx_solv
   const uint32_t lds = job_lds(ii, stage);
   int occ = 0;
   HIPCHK(c, gxk::occupancy_plain(in->h.kind, (int)stage, lds, &occ));
-  occ = std::max(1, std::min(occ, 8));
+  // every CU filled to the residency the kernel's registers and LDS allow
+  occ = std::max(1, std::min(occ, 32));
   *out = (uint32_t)(c->info.cus * occ);
   return GX_OK;
 }

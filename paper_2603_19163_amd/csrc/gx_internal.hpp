@@ -62,21 +62,22 @@ struct DevJob {
   int32_t best_idx, pad4;
 };
 
-// LDS bytes one evolve workgroup needs for this instance and staging.
+// LDS bytes one evolve workgroup needs for this instance and staging: the
+// candidate tables (4608 bytes) followed by the solution and instance data.
 inline uint32_t lds_bytes_for(int kind, int n, int stage) {
   auto al = [](uint32_t b) { return (b + 15u) & ~15u; };
-  uint32_t un = (uint32_t)n;
+  const uint32_t un = (uint32_t)n, tables = 4608;
   switch (kind) {
     case KTSP: {
-      uint32_t b = 2 * al(2 * un);
+      uint32_t b = tables + 2 * al(2 * un);
       if (stage == SLDS16) b += al(2 * un * un);
-      else if (stage == SLDSXY) b += al(8 * un);
+      else if (stage == SLDSXY) b += al(4 * un);
       return b;
     }
-    case KQAP: return 2 * al(2 * un) + 2 * al(2 * un * un) + al(2 * kWave * un);
-    case KKNAP: return al(un) + 2 * al(4 * un);
-    case KVRP: return 2 * al(2 * un) + al(2 * (un + 1) * (un + 1)) + 3 * al(4 * (un + 1));
-    default: return al(2 * un) + al(4 * (un + 1));   // + adjacency, added by the caller
+    case KQAP: return tables + 2 * al(2 * un) + 2 * al(2 * un * un) + al(2 * kWave * un);
+    case KKNAP: return tables + al(un) + 2 * al(4 * un);
+    case KVRP: return tables + 2 * al(2 * un) + al(2 * (un + 1) * (un + 1)) + 3 * al(4 * (un + 1));
+    default: return tables + al(2 * un) + al(4 * (un + 1));   // + adjacency, added by the caller
   }
 }
 

@@ -237,10 +237,11 @@ __device__ __forceinline__ void stage16(void *dst, const void *src, uint32_t byt
 // (isqrt(4 s) + 1) / 2 with the float estimate of the root corrected by one
 // step either way.  |dx|, |dy| < 2^14 and the root < 2^16, so every product
 // fits the full-rate 24-bit multiplier.
-__device__ __forceinline__ int nint_dist(int2 p, int2 q) {
-  const int dx = p.x - q.x, dy = p.y - q.y;
+template <class V2>
+__device__ __forceinline__ int nint_dist(V2 p, V2 q) {
+  const int dx = (int)p.x - (int)q.x, dy = (int)p.y - (int)q.y;
   const uint32_t s4 = 4u * (uint32_t)(__mul24(dx, dx) + __mul24(dy, dy));
-  uint32_t r = (uint32_t)sqrtf((float)s4);
+  uint32_t r = (uint32_t)__builtin_amdgcn_sqrtf((float)s4);
   r -= (__umul24(r, r) > s4);
   r += (__umul24(r + 1, r + 1) <= s4);
   return (int)((r + 1) >> 1);
@@ -251,8 +252,8 @@ struct DistL16 {
   int n;
   __device__ __forceinline__ int operator()(int a, int b) const { return d[a * n + b]; }
 };
-struct DistXY {
-  const int2 *xy;
+struct DistXY {   // coordinates as int16 pairs (they lie in [0, 2^14))
+  const short2 *xy;
   __device__ __forceinline__ int operator()(int a, int b) const { return nint_dist(xy[a], xy[b]); }
 };
 struct DistG16 {
@@ -504,26 +505,324 @@ struct ColorK {
   }
 };
 
+// ------------------------------------------------------------ TSP, step-major
+// Every TSP operator is one or two "pattern" steps that share one delta
+// formula: 2-opt is a reversal, a swap of non-adjacent positions is the
+// reversal of [lo, hi] followed by that of [lo+1, hi-1], insert / or-opt is a
+// block move.  Per chunk of 128 candidates the wave draws all first steps,
+// then the extra steps of the candidates with k >= 2 compacted onto the lanes,
+// builds the list of pattern steps grouped by their position in the composite,
+// evaluates it with all lanes busy, and sums each candidate's delta with LDS
+// atomics.  Draws, moves and deltas are those of the per-candidate
+// formulation; only the order of evaluation differs.
+constexpr int kChunk = 128;
+constexpr uint32_t kTspScratch = kChunk * 3 * 4 + kChunk * 3 + kChunk + kChunk * 4 + kChunk * 6 * 2 + kChunk * 2 * 2;
+static_assert(kTspScratch == 4608, "lds_bytes_for() reserves 4608 bytes of candidate tables");
+
+struct TspScratch {
+  uint32_t *sab;   // a | b << 16 of step m of candidate t at [3t + m]
+  uint8_t *sop;    // op | L << 4
+  uint8_t *sk;     // k of candidate t
+  int32_t *del;    // delta accumulators
+  uint16_t *lst;   // pattern steps: t | m << 8 | sub << 10
+  uint16_t *dl;    // extra draws: t | m << 8
+  __device__ void carve(char *p) {
+    sab = (uint32_t *)p;
+    p += kChunk * 3 * 4;
+    del = (int32_t *)p;
+    p += kChunk * 4;
+    lst = (uint16_t *)p;
+    p += kChunk * 6 * 2;
+    dl = (uint16_t *)p;
+    p += kChunk * 2 * 2;
+    sop = (uint8_t *)p;
+    p += kChunk * 3;
+    sk = (uint8_t *)p;
+  }
+};
+
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// number of pattern steps of an operator
+__device__ __forceinline__ int n_patterns(int op, int a, int b) { return (op == OSWAP && b - a >= 2) ? 2 : 1; }
+
+// Position map of one pattern step as two adjacent pieces:
+// p in [s1, e1) -> m1 * p + o1, p in [e1, e2) -> p + o2, otherwise p.
+struct PMap {
+  int s1, e1, e2, m1, o1, o2;
+};
+
+__device__ __forceinline__ PMap pmap(int op, int a, int b, int L, int sub) {
+  PMap M;
+  if (op >= OINS) {           // block [a, a+L) moved to start at b
+    if (b < a) {
+      M.s1 = b; M.e1 = b + L; M.e2 = a + L; M.m1 = 1; M.o1 = a - b; M.o2 = -L;
+    } else {
+      M.s1 = a; M.e1 = b; M.e2 = b + L; M.m1 = 1; M.o1 = L; M.o2 = a - b;
+    }
+  } else {                    // reversal of [a + sub, b - sub]
+    const int lo = a + sub, hi = b - sub;
+    M.s1 = lo; M.e1 = hi + 1; M.e2 = hi + 1; M.m1 = -1; M.o1 = lo + hi; M.o2 = 0;
+  }
+  return M;
+}
+
+__device__ __forceinline__ int papply(const PMap &M, int p) {
+  const bool in = (uint32_t)(p - M.s1) < (uint32_t)(M.e2 - M.s1);
+  const int v = p < M.e1 ? __mul24(M.m1, p) + M.o1 : p + M.o2;
+  return in ? v : p;
+}
+
+__device__ __forceinline__ void unpack_step(const TspScratch &W, int t, int m, int &op, int &a, int &b, int &L) {
+  const uint32_t ab = W.sab[3 * t + m];
+  const uint32_t ol = W.sop[3 * t + m];
+  a = (int)(ab & 0xFFFFu);
+  b = (int)(ab >> 16);
+  op = (int)(ol & 15u);
+  L = (int)(ol >> 4);
+}
+
+// Draw the composite moves of candidates [c0, c0 + cn): the first step of
+// every candidate on its own lane (t = c0 + r*64 + lane), then the extra steps
+// of the candidates with k >= 2 and k >= 3 compacted onto consecutive lanes,
+// so that the wave computes about as many Philox blocks as there are steps.
+// Steps land in the LDS tables; kk[r] receives k of the lane's candidates.
+template <int ENC>
+__device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, uint32_t g, uint32_t sol, uint32_t c0,
+                                           uint32_t cn, int kk[2]) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const uint32_t tl = r * kWave + lane;
+    kk[r] = 0;
+    if (tl < cn) {
+      uint32_t w[4];
+      philox(g, sol, (c0 + tl) << 2, U.key, U.k0, U.k1, w);
+      const uint32_t u = (uint32_t)(((uint64_t)(w[0] >> 16) * U.swk) >> 16);
+      kk[r] = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
+      const Step st = make_step<ENC>(pick_op(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
+      W.sab[3 * tl] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
+      W.sop[3 * tl] = (uint8_t)(st.op | (st.c << 4));
+      W.del[tl] = 0;
+    }
+  }
+  uint32_t nx = 0;
+#pragma unroll
+  for (int m = 1; m < 3; ++m)
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const bool need = kk[r] > m;
+      const unsigned long long mk = __ballot(need);
+      if (need) W.dl[nx + lanes_below(mk)] = (uint16_t)((r * kWave + lane) | (m << 8));
+      nx += (uint32_t)__popcll(mk);
+    }
+  __syncthreads();
+  for (uint32_t j = lane; j < nx; j += kWave) {
+    const uint32_t e = W.dl[j], tl = e & 0xFFu, m = e >> 8;
+    uint32_t w[4];
+    philox(g, sol, ((c0 + tl) << 2) | m, U.key, U.k0, U.k1, w);
+    const Step st = make_step<ENC>(pick_op(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
+    W.sab[3 * tl + m] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
+    W.sop[3 * tl + m] = (uint8_t)(st.op | (st.c << 4));
+  }
+  __syncthreads();
+}
+
+// step m of candidate t from the tables (integer values are stored as int16)
+template <int ENC>
+__device__ __forceinline__ Step load_step(const TspScratch &W, int t, int m) {
+  const uint32_t ab = W.sab[3 * t + m];
+  const uint32_t ol = W.sop[3 * t + m];
+  Step st;
+  st.a = (int)(ab & 0xFFFFu);
+  st.b = ENC == 2 ? (int)(int16_t)(ab >> 16) : (int)(ab >> 16);
+  st.op = (int)(ol & 15u);
+  st.c = (int)(ol >> 4);
+  return st;
+}
+
+// delta of pattern step `sub` of operator m of candidate t, on the tour after
+// all earlier pattern steps of that candidate
+template <class DF>
+__device__ __forceinline__ int pattern_delta(const TspScratch &W, const uint16_t *tour, int n, const DF &D,
+                                             int t, int m, int sub) {
+  int op, a, b, L;
+  unpack_step(W, t, m, op, a, b, L);
+  const bool mv = op >= OINS, qlt = b < a;
+  const int lo = a + sub, hi = b - sub;
+  bool zero;
+  if (mv) zero = (L == 0) || (qlt && b == 0 && a + L == n) || (!qlt && a == 0 && b + L == n);
+  else zero = hi - lo >= n - 1;
+  int r[6];
+  r[0] = mv ? (qlt ? b - 1 : a - 1) : lo - 1;
+  r[1] = mv ? (qlt ? b : a) : lo;
+  r[2] = mv ? (qlt ? a - 1 : a + L - 1) : lo;
+  r[3] = mv ? (qlt ? a : a + L) : hi;
+  r[4] = mv ? (qlt ? a + L - 1 : b + L - 1) : hi;
+  r[5] = mv ? (qlt ? a + L : b + L) : hi + 1;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) r[i] += r[i] < 0 ? n : (r[i] >= n ? -n : 0);
+  // map back through the earlier pattern steps, latest first
+  if (sub) {
+    const PMap M = pmap(op, a, b, L, 0);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) r[i] = papply(M, r[i]);
+  }
+  for (int mm = m - 1; mm >= 0; --mm) {
+    int o2, a2, b2, L2;
+    unpack_step(W, t, mm, o2, a2, b2, L2);
+    if (n_patterns(o2, a2, b2) == 2) {
+      const PMap M = pmap(o2, a2, b2, L2, 1);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) r[i] = papply(M, r[i]);
+    }
+    const PMap M = pmap(o2, a2, b2, L2, 0);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) r[i] = papply(M, r[i]);
+  }
+  int v[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) v[i] = tour[r[i]];
+  const int d = D(v[0], v[3]) - D(v[0], v[1]) + D(v[4], v[1]) - D(v[2], v[3]) + D(v[2], v[5]) - D(v[4], v[5]);
+  return zero ? 0 : d;
+}
+
+template <class DF>
+__device__ __forceinline__ void tsp_run(uint16_t *&cur, uint16_t *&nxt, int n, const DF &D, const TspScratch &W,
+                                        const Uni &U, int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1,
+                                        uint64_t &T, int64_t &f, int64_t &bf, LStats &S, uint32_t &nacc) {
+  const uint32_t lane = lane_id();
+  for (uint32_t g = g0; g < g1; ++g) {
+    unsigned long long bk = ~0ull;
+    for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
+      const uint32_t cn = min((uint32_t)kChunk, U.C - c0);
+      int kk[2];
+      draw_chunk<0>(W, U, g, sol, c0, cn, kk);
+      // ---- pattern-step list, grouped by (operator slot, pattern step)
+      uint32_t nq = 0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        if (!__ballot(kk[0] > m || kk[1] > m)) break;
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub)
+#pragma unroll
+          for (int r = 0; r < 2; ++r) {
+            const uint32_t tl = r * kWave + lane;
+            bool need = kk[r] > m;
+            if (need && sub) {
+              int op, a, b, L;
+              unpack_step(W, (int)tl, m, op, a, b, L);
+              need = n_patterns(op, a, b) == 2;
+            }
+            const unsigned long long mk = __ballot(need);
+            if (need) W.lst[nq + lanes_below(mk)] = (uint16_t)(tl | (m << 8) | (sub << 10));
+            nq += (uint32_t)__popcll(mk);
+          }
+      }
+      __syncthreads();
+      if (n >= 2) {
+        for (uint32_t j = lane; j < nq; j += kWave) {
+          const uint32_t e = W.lst[j];
+          const int d = pattern_delta(W, cur, n, D, (int)(e & 0xFFu), (int)((e >> 8) & 3u), (int)(e >> 10));
+          if (d) atomicAdd(&W.del[e & 0xFFu], d);
+        }
+      }
+      __syncthreads();
+      // ---- keys and statistics (wave-wide counts: S is uniform on this path)
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const uint32_t tl = r * kWave + lane;
+        const bool valid = tl < cn;
+        const int64_t d = valid ? (int64_t)W.del[tl] : 0;
+        if (U.credit == 0) {
+          const bool imp = valid && d < 0;
+#pragma unroll
+          for (int m = 0; m < 3; ++m) {
+            const int op = (valid && kk[r] > m) ? (int)(W.sop[3 * tl + m] & 15u) : -1;
+#pragma unroll
+            for (int o = 0; o < 4; ++o) {
+              S.u[o] += (uint32_t)__popcll(__ballot(op == o));
+              S.v[o] += (uint32_t)__popcll(__ballot(op == o && imp));
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            S.uk[q] += (uint32_t)__popcll(__ballot(valid && kk[r] == q + 1));
+            S.vk[q] += (uint32_t)__popcll(__ballot(valid && kk[r] == q + 1 && imp));
+          }
+        }
+        if (valid) {
+          const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | (c0 + tl);
+          bk = key < bk ? key : bk;
+        }
+      }
+      __syncthreads();
+    }
+    bk = uni64(wave_min(bk));
+    const uint32_t ts = (uint32_t)(bk & 0xFFFFu);
+    const int64_t ds = (int64_t)(bk >> 16) - kDeltaBias;
+    bool acc = ds <= 0;
+    if (!acc) acc = accept_worse(ds, T, g, sol, U);
+    if (acc) {
+      Step st[3];
+      const int k = sample<0>(U, g, sol, ts, st);
+      if (U.credit == 1) {   // wave-uniform counts on this path
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+          for (int o = 0; o < 4; ++o) {
+            const uint32_t hit = m < k && st[m].op == o;
+            S.u[o] += hit;
+            S.v[o] += hit & (uint32_t)(ds < 0);
+          }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          S.uk[q] += (uint32_t)(k == q + 1);
+          S.vk[q] += (uint32_t)(k == q + 1 && ds < 0);
+        }
+      }
+      perm_apply(cur, nxt, n, st, k);
+      f += ds;
+      ++nacc;
+      if (f < bf) {
+        bf = f;
+        perm_store(cur, n, best_row);
+      }
+    }
+    T = cool(T, U.alpha);
+  }
+}
+
 // ------------------------------------------------------------ generation loop
 template <class KD>
-__device__ __forceinline__ void run_gens(KD &kd, const Uni &U, int32_t *best_row, uint32_t sol, uint32_t g0,
-                                         uint32_t g1, uint64_t &T, int64_t &f, int64_t &bf, LStats &S,
+__device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni &U, int32_t *best_row, uint32_t sol,
+                                         uint32_t g0, uint32_t g1, uint64_t &T, int64_t &f, int64_t &bf, LStats &S,
                                          uint32_t &nacc) {
   constexpr int ENC = KD::ENC;
   const uint32_t lane = lane_id();
-  const uint32_t NR = (U.C + kWave - 1) / kWave;
   for (uint32_t g = g0; g < g1; ++g) {
     unsigned long long bk = ~0ull;
-    for (uint32_t r = 0; r < NR; ++r) {
-      const uint32_t t = r * kWave + lane;
-      if (t < U.C) {
-        Step st[3];
-        const int k = sample<ENC>(U, g, sol, t, st);
-        const int64_t d = kd.delta(st, k, f);
-        if (U.credit == 0) credit<ENC>(S, st, k, d < 0);
-        const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | t;
-        bk = key < bk ? key : bk;
+    for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
+      const uint32_t cn = min((uint32_t)kChunk, U.C - c0);
+      int kk[2];
+      draw_chunk<ENC>(W, U, g, sol, c0, cn, kk);
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const uint32_t tl = r * kWave + lane;
+        if (tl < cn) {
+          Step st[3];
+          st[0] = load_step<ENC>(W, (int)tl, 0);
+          st[1] = kk[r] > 1 ? load_step<ENC>(W, (int)tl, 1) : st[0];
+          st[2] = kk[r] > 2 ? load_step<ENC>(W, (int)tl, 2) : st[0];
+          const int64_t d = kd.delta(st, kk[r], f);
+          if (U.credit == 0) credit<ENC>(S, st, kk[r], d < 0);
+          const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | (c0 + tl);
+          bk = key < bk ? key : bk;
+        }
       }
+      __syncthreads();
     }
     bk = uni64(wave_min(bk));
     const uint32_t ts = (uint32_t)(bk & 0xFFFFu);
@@ -596,20 +895,22 @@ __device__ void epoch_close(DevJob *J, uint32_t g1, uint64_t T_end) {
   __hip_atomic_store(&J->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int ENC>
+// S holds per-lane counts (summed here over the wave) or, with UNIFORM,
+// counts that are already wave totals.
+template <int ENC, bool UNIFORM>
 __device__ void finish_launch(DevJob *J, const LStats &S, uint32_t nacc, int64_t bf, uint32_t g1, uint64_t T_end) {
   constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
   constexpr int hi = ENC == 0 ? OOROPT : lo;
   uint32_t u[kOps] = {0}, v[kOps] = {0}, uk[3], vk[3];
 #pragma unroll
   for (int o = lo; o <= hi; ++o) {
-    u[o] = wave_sum(S.u[o]);
-    v[o] = wave_sum(S.v[o]);
+    u[o] = UNIFORM ? S.u[o] : wave_sum(S.u[o]);
+    v[o] = UNIFORM ? S.v[o] : wave_sum(S.v[o]);
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    uk[q] = wave_sum(S.uk[q]);
-    vk[q] = wave_sum(S.vk[q]);
+    uk[q] = UNIFORM ? S.uk[q] : wave_sum(S.uk[q]);
+    vk[q] = UNIFORM ? S.vk[q] : wave_sum(S.vk[q]);
   }
   if (lane_id() == 0) {
     for (int o = lo; o <= hi; ++o) {
@@ -676,36 +977,34 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
   const uint32_t lane = lane_id();
   int32_t *cur_g = J->cur + (size_t)sol * n;
   int32_t *best_row = J->best + (size_t)sol * n;
+  // LDS: candidate tables first, then the solution and the instance data
+  TspScratch W;
+  W.carve(lds);
+  char *const base = lds + kTspScratch;
 
   if constexpr (KIND == KTSP || KIND == KQAP || KIND == KVRP) {
-    uint16_t *t0 = (uint16_t *)lds;
-    uint16_t *t1 = (uint16_t *)(lds + al16(2 * n));
-    char *rest = lds + 2 * al16(2 * n);
+    uint16_t *t0 = (uint16_t *)base;
+    uint16_t *t1 = (uint16_t *)(base + al16(2 * n));
+    char *rest = base + 2 * al16(2 * n);
     for (int p = lane; p < n; p += kWave) t0[p] = (uint16_t)cur_g[p];
     if constexpr (KIND == KTSP) {
       if constexpr (STAGE == SLDS16) {
         stage16(rest, I->d16, 2u * n * n);
         __syncthreads();
-        TspK<DistL16> kd{t0, t1, n, DistL16{(const int16_t *)rest, n}};
-        run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
-        perm_store(kd.cur, n, cur_g);
+        tsp_run(t0, t1, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       } else if constexpr (STAGE == SLDSXY) {
-        stage16(rest, I->xy, 8u * n);
+        short2 *xy = (short2 *)rest;
+        for (int p = lane; p < n; p += kWave) xy[p] = make_short2((short)I->xy[2 * p], (short)I->xy[2 * p + 1]);
         __syncthreads();
-        TspK<DistXY> kd{t0, t1, n, DistXY{(const int2 *)rest}};
-        run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
-        perm_store(kd.cur, n, cur_g);
+        tsp_run(t0, t1, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       } else if constexpr (STAGE == SGLB16) {
         __syncthreads();
-        TspK<DistG16> kd{t0, t1, n, DistG16{I->d16, n}};
-        run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
-        perm_store(kd.cur, n, cur_g);
+        tsp_run(t0, t1, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       } else {
         __syncthreads();
-        TspK<DistG32> kd{t0, t1, n, DistG32{I->d32, n}};
-        run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
-        perm_store(kd.cur, n, cur_g);
+        tsp_run(t0, t1, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       }
+      perm_store(t0, n, cur_g);
     } else if constexpr (KIND == KQAP) {
       int16_t *F = (int16_t *)rest;
       int16_t *D = (int16_t *)(rest + al16(2 * n * n));
@@ -714,7 +1013,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       stage16(D, I->qd, 2u * n * n);
       __syncthreads();
       QapK kd{t0, t1, n, F, D, xr};
-      run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+      run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       perm_store(kd.cur, n, cur_g);
     } else {
       const int dn = n + 1;
@@ -728,12 +1027,12 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       stage16(due, I->due, 4u * dn);
       __syncthreads();
       VrpK kd{t0, t1, n, dn, I->capacity, I->vehicles, I->service, I->horizon, D, dem, rdy, due};
-      run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+      run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       perm_store(kd.cur, n, cur_g);
     }
   } else if constexpr (KIND == KKNAP) {
-    uint8_t *bits = (uint8_t *)lds;
-    int32_t *w = (int32_t *)(lds + al16(n));
+    uint8_t *bits = (uint8_t *)base;
+    int32_t *w = (int32_t *)(base + al16(n));
     int32_t *v = w + al16(4 * n) / 4;
     int64_t pw = 0, pv = 0;
     for (int p = lane; p < n; p += kWave) {
@@ -744,21 +1043,21 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     }
     stage16(w, I->kw, 4u * n);
     stage16(v, I->kv, 4u * n);
-    const int64_t W = wave_sum64(pw), V = wave_sum64(pv);
+    const int64_t Wsum = wave_sum64(pw), Vsum = wave_sum64(pv);
     __syncthreads();
-    KnapK kd{bits, w, v, n, (int64_t)uni64((uint64_t)W), (int64_t)uni64((uint64_t)V), I->capacity, I->lambda};
-    run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+    KnapK kd{bits, w, v, n, (int64_t)uni64((uint64_t)Wsum), (int64_t)uni64((uint64_t)Vsum), I->capacity, I->lambda};
+    run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
     kd.store(cur_g);
   } else {
-    int16_t *val = (int16_t *)lds;
-    int32_t *off = (int32_t *)(lds + al16(2 * n));
+    int16_t *val = (int16_t *)base;
+    int32_t *off = (int32_t *)(base + al16(2 * n));
     int32_t *adj = off + al16(4 * (n + 1)) / 4;
     for (int p = lane; p < n; p += kWave) val[p] = (int16_t)cur_g[p];
     stage16(off, I->adj_off, 4u * (n + 1));
     stage16(adj, I->adj, 8u * I->n_edges);
     __syncthreads();
     ColorK kd{val, off, adj, n};
-    run_gens(kd, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+    run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
     kd.store(cur_g);
   }
   if (lane == 0) {
@@ -766,7 +1065,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     J->best_f[sol] = bf;
   }
   constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : 0);
-  finish_launch<ENC>(J, S, nacc, bf, g1, T);
+  finish_launch<ENC, KIND == KTSP>(J, S, nacc, bf, g1, T);
 }
 
 }  // namespace
