@@ -194,6 +194,26 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
   return v;
 }
 
+// Wave-wide minimum of a 32-bit value with DPP moves only (no LDS path):
+// pairs, quads, half rows, rows, then row 0 -> 1 and row 2 -> 3 (row_bcast:15)
+// and rows 0-1 -> 2-3 (row_bcast:31); lane 63 ends with the minimum.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x140, 0xF, 0xF, false));  // row_mirror
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+  v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// wave-wide minimum of a 64-bit key, high word first (result is uniform)
+__device__ __forceinline__ unsigned long long wave_min_key(unsigned long long k) {
+  const uint32_t hi = wave_min_u32((uint32_t)(k >> 32));
+  const uint32_t lo = wave_min_u32((uint32_t)(k >> 32) == hi ? (uint32_t)k : 0xFFFFFFFFu);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 __device__ __forceinline__ unsigned long long wave_min(unsigned long long v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {
@@ -516,29 +536,19 @@ struct ColorK {
 // atomics.  Draws, moves and deltas are those of the per-candidate
 // formulation; only the order of evaluation differs.
 constexpr int kChunk = 128;
-constexpr uint32_t kTspScratch = kChunk * 3 * 4 + kChunk * 3 + kChunk + kChunk * 4 + kChunk * 6 * 2 + kChunk * 2 * 2;
+constexpr uint32_t kTspScratch = kChunk * 3 * 4 + kChunk * 4 + kChunk * 6 * 2 + kChunk * 2 * 2 + kChunk * 3 + kChunk;
 static_assert(kTspScratch == 4608, "lds_bytes_for() reserves 4608 bytes of candidate tables");
 
+// Dynamic LDS of the evolve kernels; the candidate tables sit at fixed offsets
+// from its start (so their addresses are compile-time constants).
+extern __shared__ __align__(16) char gx_lds[];
+
 struct TspScratch {
-  uint32_t *sab;   // a | b << 16 of step m of candidate t at [3t + m]
-  uint8_t *sop;    // op | L << 4
-  uint8_t *sk;     // k of candidate t
-  int32_t *del;    // delta accumulators
-  uint16_t *lst;   // pattern steps: t | m << 8 | sub << 10
-  uint16_t *dl;    // extra draws: t | m << 8
-  __device__ void carve(char *p) {
-    sab = (uint32_t *)p;
-    p += kChunk * 3 * 4;
-    del = (int32_t *)p;
-    p += kChunk * 4;
-    lst = (uint16_t *)p;
-    p += kChunk * 6 * 2;
-    dl = (uint16_t *)p;
-    p += kChunk * 2 * 2;
-    sop = (uint8_t *)p;
-    p += kChunk * 3;
-    sk = (uint8_t *)p;
-  }
+  __device__ __forceinline__ uint32_t *sab() const { return (uint32_t *)gx_lds; }         // a | b << 16 at [3t + m]
+  __device__ __forceinline__ int32_t *del() const { return (int32_t *)(gx_lds + 1536); }  // delta accumulators
+  __device__ __forceinline__ uint16_t *lst() const { return (uint16_t *)(gx_lds + 2048); } // t | m << 8 | sub << 10
+  __device__ __forceinline__ uint16_t *dl() const { return (uint16_t *)(gx_lds + 3584); }  // extra draws t | m << 8
+  __device__ __forceinline__ uint8_t *sop() const { return (uint8_t *)(gx_lds + 4096); }   // op | L << 4 at [3t + m]
 };
 
 __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
@@ -576,8 +586,8 @@ __device__ __forceinline__ int papply(const PMap &M, int p) {
 }
 
 __device__ __forceinline__ void unpack_step(const TspScratch &W, int t, int m, int &op, int &a, int &b, int &L) {
-  const uint32_t ab = W.sab[3 * t + m];
-  const uint32_t ol = W.sop[3 * t + m];
+  const uint32_t ab = W.sab()[3 * t + m];
+  const uint32_t ol = W.sop()[3 * t + m];
   a = (int)(ab & 0xFFFFu);
   b = (int)(ab >> 16);
   op = (int)(ol & 15u);
@@ -603,9 +613,9 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
       const uint32_t u = (uint32_t)(((uint64_t)(w[0] >> 16) * U.swk) >> 16);
       kk[r] = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
       const Step st = make_step<ENC>(pick_op(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
-      W.sab[3 * tl] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
-      W.sop[3 * tl] = (uint8_t)(st.op | (st.c << 4));
-      W.del[tl] = 0;
+      W.sab()[3 * tl] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
+      W.sop()[3 * tl] = (uint8_t)(st.op | (st.c << 4));
+      W.del()[tl] = 0;
     }
   }
   uint32_t nx = 0;
@@ -615,17 +625,17 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
     for (int r = 0; r < 2; ++r) {
       const bool need = kk[r] > m;
       const unsigned long long mk = __ballot(need);
-      if (need) W.dl[nx + lanes_below(mk)] = (uint16_t)((r * kWave + lane) | (m << 8));
+      if (need) W.dl()[nx + lanes_below(mk)] = (uint16_t)((r * kWave + lane) | (m << 8));
       nx += (uint32_t)__popcll(mk);
     }
   __syncthreads();
   for (uint32_t j = lane; j < nx; j += kWave) {
-    const uint32_t e = W.dl[j], tl = e & 0xFFu, m = e >> 8;
+    const uint32_t e = W.dl()[j], tl = e & 0xFFu, m = e >> 8;
     uint32_t w[4];
     philox(g, sol, ((c0 + tl) << 2) | m, U.key, U.k0, U.k1, w);
     const Step st = make_step<ENC>(pick_op(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
-    W.sab[3 * tl + m] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
-    W.sop[3 * tl + m] = (uint8_t)(st.op | (st.c << 4));
+    W.sab()[3 * tl + m] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
+    W.sop()[3 * tl + m] = (uint8_t)(st.op | (st.c << 4));
   }
   __syncthreads();
 }
@@ -633,8 +643,8 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
 // step m of candidate t from the tables (integer values are stored as int16)
 template <int ENC>
 __device__ __forceinline__ Step load_step(const TspScratch &W, int t, int m) {
-  const uint32_t ab = W.sab[3 * t + m];
-  const uint32_t ol = W.sop[3 * t + m];
+  const uint32_t ab = W.sab()[3 * t + m];
+  const uint32_t ol = W.sop()[3 * t + m];
   Step st;
   st.a = (int)(ab & 0xFFFFu);
   st.b = ENC == 2 ? (int)(int16_t)(ab >> 16) : (int)(ab >> 16);
@@ -717,16 +727,16 @@ __device__ __forceinline__ void tsp_run(uint16_t *&cur, uint16_t *&nxt, int n, c
               need = n_patterns(op, a, b) == 2;
             }
             const unsigned long long mk = __ballot(need);
-            if (need) W.lst[nq + lanes_below(mk)] = (uint16_t)(tl | (m << 8) | (sub << 10));
+            if (need) W.lst()[nq + lanes_below(mk)] = (uint16_t)(tl | (m << 8) | (sub << 10));
             nq += (uint32_t)__popcll(mk);
           }
       }
       __syncthreads();
       if (n >= 2) {
         for (uint32_t j = lane; j < nq; j += kWave) {
-          const uint32_t e = W.lst[j];
+          const uint32_t e = W.lst()[j];
           const int d = pattern_delta(W, cur, n, D, (int)(e & 0xFFu), (int)((e >> 8) & 3u), (int)(e >> 10));
-          if (d) atomicAdd(&W.del[e & 0xFFu], d);
+          if (d) atomicAdd(&W.del()[e & 0xFFu], d);
         }
       }
       __syncthreads();
@@ -735,12 +745,12 @@ __device__ __forceinline__ void tsp_run(uint16_t *&cur, uint16_t *&nxt, int n, c
       for (int r = 0; r < 2; ++r) {
         const uint32_t tl = r * kWave + lane;
         const bool valid = tl < cn;
-        const int64_t d = valid ? (int64_t)W.del[tl] : 0;
+        const int64_t d = valid ? (int64_t)W.del()[tl] : 0;
         if (U.credit == 0) {
           const bool imp = valid && d < 0;
 #pragma unroll
           for (int m = 0; m < 3; ++m) {
-            const int op = (valid && kk[r] > m) ? (int)(W.sop[3 * tl + m] & 15u) : -1;
+            const int op = (valid && kk[r] > m) ? (int)(W.sop()[3 * tl + m] & 15u) : -1;
 #pragma unroll
             for (int o = 0; o < 4; ++o) {
               S.u[o] += (uint32_t)__popcll(__ballot(op == o));
@@ -760,7 +770,7 @@ __device__ __forceinline__ void tsp_run(uint16_t *&cur, uint16_t *&nxt, int n, c
       }
       __syncthreads();
     }
-    bk = uni64(wave_min(bk));
+    bk = wave_min_key(bk);
     const uint32_t ts = (uint32_t)(bk & 0xFFFFu);
     const int64_t ds = (int64_t)(bk >> 16) - kDeltaBias;
     bool acc = ds <= 0;
@@ -824,7 +834,7 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
       }
       __syncthreads();
     }
-    bk = uni64(wave_min(bk));
+    bk = wave_min_key(bk);
     const uint32_t ts = (uint32_t)(bk & 0xFFFFu);
     const int64_t ds = (int64_t)(bk >> 16) - kDeltaBias;
     bool acc = ds <= 0;
@@ -978,8 +988,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
   int32_t *cur_g = J->cur + (size_t)sol * n;
   int32_t *best_row = J->best + (size_t)sol * n;
   // LDS: candidate tables first, then the solution and the instance data
-  TspScratch W;
-  W.carve(lds);
+  const TspScratch W;
   char *const base = lds + kTspScratch;
 
   if constexpr (KIND == KTSP || KIND == KQAP || KIND == KVRP) {
@@ -1073,13 +1082,12 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
 // ------------------------------------------------------------ evolve kernels
 template <int KIND, int STAGE>
 __global__ __launch_bounds__(64) void k_evolve(DevJob *job) {
-  extern __shared__ __align__(16) char lds[];
-  evolve_wg<KIND, STAGE>(job, blockIdx.x, lds);
+  evolve_wg<KIND, STAGE>(job, blockIdx.x, gx_lds);
 }
 
 // Persistent walk over (job, solution) work items of many jobs of any kinds.
 __global__ __launch_bounds__(64) void k_evolve_items(DevJob *jobs, const uint2 *items, uint32_t n_items) {
-  extern __shared__ __align__(16) char lds[];
+  char *lds = gx_lds;
   for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
     const uint2 w = items[it];
     DevJob *J = jobs + w.x;
