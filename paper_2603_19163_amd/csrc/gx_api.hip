@@ -500,7 +500,7 @@ int heur_mats_of(int kind) { return kind == KQAP ? 2 : ((kind == KTSP || kind ==
 // bytes of the per-job device arrays, laid out by carve_job
 size_t job_array_bytes(size_t n, size_t P, size_t Q) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  return 2 * al(4 * n * P) + 2 * al(8 * P) + al(4 * n * Q) + al(8 * Q) + al(32 * n) + al(4 * n);
+  return 2 * al(4 * n * P) + 2 * al(8 * P) + al(4 * n * Q) + al(8 * Q) + al(32 * n) + al(4 * n) + al(4 * 19 * P);
 }
 
 void carve_job(DevJob &h, char *q, size_t n) {
@@ -518,6 +518,7 @@ void carve_job(DevJob &h, char *q, size_t n) {
   h.pool_f = (int64_t *)take(8 * (size_t)h.Q);
   h.sums = (int64_t *)take(32 * n);
   h.best_out = (int32_t *)take(4 * n);
+  h.counts = (uint32_t *)take(4 * 19 * (size_t)h.P);
 }
 
 gx_status ensure_d32(gx_ctx *c, gx_instance *in) {
@@ -618,7 +619,7 @@ gx_status gx_job_create(gx_ctx *c, const gx_instance *cin, const gx_solve_params
       (st = dalloc(c, j->bufs, &h.cur_f, (size_t)8 * h.P)) || (st = dalloc(c, j->bufs, &h.best_f, (size_t)8 * h.P)) ||
       (st = dalloc(c, j->bufs, &h.pool, 4 * n * h.Q)) || (st = dalloc(c, j->bufs, &h.pool_f, (size_t)8 * h.Q)) ||
       (st = dalloc(c, j->bufs, &h.sums, 32 * n)) || (st = dalloc(c, j->bufs, &h.best_out, 4 * n)) ||
-      (st = dalloc(c, j->bufs, &j->d, sizeof(DevJob))))
+      (st = dalloc(c, j->bufs, &h.counts, (size_t)4 * 19 * h.P)) || (st = dalloc(c, j->bufs, &j->d, sizeof(DevJob))))
     return bail(st);
   if (hipMemcpy(j->d, &h, sizeof(DevJob), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(c, GX_E_DEVICE, "job upload failed"));
@@ -646,7 +647,10 @@ gx_status gx_job_advance(gx_ctx *c, gx_job *j, uint32_t ng) {
   const int kind = j->inst->h.kind, stage = (int)j->h.stage;
   const uint32_t P = j->h.P, lds = j->h.lds_bytes;
   hipStream_t s = c->stream;
-  gx_status st = enqueue_launches(c, j, L, [=]() { return gxk::evolve_plain(dj, kind, stage, P, lds, s); });
+  gx_status st = enqueue_launches(c, j, L, [=]() {
+    const hipError_t e = gxk::evolve_plain(dj, kind, stage, P, lds, s);
+    return e != hipSuccess ? e : gxk::epoch(dj, nullptr, 1, s);
+  });
   if (st) return st;
   HIPCHK(c, hipEventRecord(j->ev1, c->stream));
   j->timed = true;
@@ -876,7 +880,11 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
   const uint2 *itd = b->items;
   const uint32_t ni = (uint32_t)n_items, lds = max_lds;
   hipStream_t s = c->stream;
-  gx_status st = enqueue_launches(c, lead, L, [=]() { return gxk::evolve_items(jd, itd, ni, grid, lds, s); });
+  const uint32_t njobs = (uint32_t)count;
+  gx_status st = enqueue_launches(c, lead, L, [=]() {
+    const hipError_t e = gxk::evolve_items(jd, itd, ni, grid, lds, s);
+    return e != hipSuccess ? e : gxk::epoch(jd, nullptr, njobs, s);
+  });
   if (st) {
     for (gx_job *j : made) delete j;
     return bail(st);
@@ -992,6 +1000,8 @@ struct gx_server {
   DevJob *jobs_d = nullptr;
   uint2 *items_d[2] = {nullptr, nullptr};
   uint2 *items_h[2] = {nullptr, nullptr};
+  uint32_t *slots_d[2] = {nullptr, nullptr};   // resident slots advanced by a quantum
+  uint32_t *slots_h[2] = {nullptr, nullptr};
   hipEvent_t items_ev[2] = {nullptr, nullptr};
   size_t items_cap = 0;
   char *arena_d = nullptr;
@@ -1115,8 +1125,12 @@ void server_loop(gx_server *S) {
       int occ = 1;
       (void)gxk::occupancy_items(max_lds, &occ);
       const uint32_t grid = (uint32_t)std::min<size_t>(n_items, (size_t)S->c->info.cus * std::max(1, occ));
+      uint32_t *sl = S->slots_h[buf];
+      for (size_t a = 0; a < active.size(); ++a) sl[a] = (uint32_t)active[a]->slot;
       (void)hipMemcpyAsync(S->items_d[buf], h, n_items * sizeof(uint2), hipMemcpyHostToDevice, S->s);
+      (void)hipMemcpyAsync(S->slots_d[buf], sl, active.size() * sizeof(uint32_t), hipMemcpyHostToDevice, S->s);
       (void)gxk::evolve_items(S->jobs_d, S->items_d[buf], (uint32_t)n_items, grid, max_lds, S->s);
+      (void)gxk::epoch(S->jobs_d, S->slots_d[buf], (uint32_t)active.size(), S->s);
       (void)hipEventRecord(S->items_ev[buf], S->s);
       buf ^= 1;
       uint64_t evals = 0;
@@ -1203,6 +1217,10 @@ gx_status gx_server_create(gx_ctx *c, const gx_server_cfg *cfg, gx_server **out)
   for (int b = 0; b < 2; ++b)
     if (hipEventCreateWithFlags(&S->items_ev[b], hipEventDisableTiming) != hipSuccess) return bail("events");
   if (srv_grow_items(S, 4096) != GX_OK) return bail("work items");
+  for (int b = 0; b < 2; ++b)
+    if (hipMalloc((void **)&S->slots_d[b], 4 * (size_t)S->cfg.max_resident) != hipSuccess ||
+        hipHostMalloc((void **)&S->slots_h[b], 4 * (size_t)S->cfg.max_resident, 0) != hipSuccess)
+      return bail("slot lists");
   S->slots.assign(S->cfg.max_resident, nullptr);
   for (int i = (int)S->cfg.max_resident - 1; i >= 0; --i) S->free_slots.push_back(i);
   S->st.arena_bytes = S->arena.cap();
@@ -1325,6 +1343,8 @@ gx_status gx_server_destroy(gx_server *S) {
   for (int b = 0; b < 2; ++b) {
     (void)hipFree(S->items_d[b]);
     (void)hipHostFree(S->items_h[b]);
+    (void)hipFree(S->slots_d[b]);
+    (void)hipHostFree(S->slots_h[b]);
     (void)hipEventDestroy(S->items_ev[b]);
   }
   (void)hipFree(S->arena_d);

@@ -58,6 +58,7 @@ struct DevJob {
   int64_t *pool_f;            // Q
   int64_t *sums;              // 2 x n heuristic row/column sums
   int32_t *best_out;          // n
+  uint32_t *counts;           // 19 x P per-launch counts of each workgroup
   int64_t best_out_f;
   int32_t best_idx, pad4;
 };
@@ -96,6 +97,7 @@ hipError_t evolve_plain(gx::DevJob *job, int kind, int stage, uint32_t P, uint32
 hipError_t evolve_items(gx::DevJob *jobs, const uint2 *items, uint32_t n_items, uint32_t grid,
                         uint32_t lds, hipStream_t s);
 hipError_t fetch_best(gx::DevJob *jobs, int count, hipStream_t s);
+hipError_t epoch(gx::DevJob *jobs, const uint32_t *idx, uint32_t count, hipStream_t s);
 hipError_t prepare_kernel_attrs(uint32_t max_lds);
 hipError_t occupancy_plain(int kind, int stage, uint32_t lds, int *blocks_per_cu);
 hipError_t occupancy_items(uint32_t lds, int *blocks_per_cu);

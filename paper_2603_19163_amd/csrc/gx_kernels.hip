@@ -15,6 +15,8 @@
 // folds the job's statistics into the EMA weight update (Eq. ema, Alg. 2).
 #include "gx_internal.hpp"
 
+#include <climits>
+
 using namespace gx;
 
 __constant__ uint32_t c_exp_hi[16];
@@ -64,15 +66,19 @@ struct Step {
   int op, a, b, c;
 };
 
-// weighted choice from Q16 weights: u = floor(u16 * S / 2^16); smallest i with u < cumsum_i
+// weighted choice from Q16 weights: u = floor(u16 * S / 2^16); smallest i with
+// u < cumsum_i.  An encoding's operators are contiguous ids (permutations 0-3,
+// binary 4, integer 5) and the others have weight 0, so only the encoding's
+// own cumulative sums matter.
+template <int ENC>
 __device__ __forceinline__ int pick_op(uint32_t u16, const Uni &U) {
+  if (ENC == 1) return OFLIP;
+  if (ENC == 2) return ORESET;
   const uint32_t u = (uint32_t)(((uint64_t)u16 * U.sw) >> 16);
   uint32_t c = U.w[0];
   int r = (c <= u);
   c += U.w[1]; r += (c <= u);
   c += U.w[2]; r += (c <= u);
-  c += U.w[3]; r += (c <= u);
-  c += U.w[4]; r += (c <= u);
   return r;
 }
 
@@ -120,14 +126,14 @@ __device__ __forceinline__ int sample(const Uni &U, uint32_t g, uint32_t sol, ui
   philox(g, sol, t << 2, U.key, U.k0, U.k1, r);
   const uint32_t u = (uint32_t)(((uint64_t)(r[0] >> 16) * U.swk) >> 16);
   const int k = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
-  st[0] = make_step<ENC>(pick_op(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+  st[0] = make_step<ENC>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
   if (k > 1) {
     philox(g, sol, (t << 2) | 1u, U.key, U.k0, U.k1, r);
-    st[1] = make_step<ENC>(pick_op(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+    st[1] = make_step<ENC>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
   }
   if (k > 2) {
     philox(g, sol, (t << 2) | 2u, U.key, U.k0, U.k1, r);
-    st[2] = make_step<ENC>(pick_op(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+    st[2] = make_step<ENC>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
   }
   return k;
 }
@@ -612,7 +618,7 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
       philox(g, sol, (c0 + tl) << 2, U.key, U.k0, U.k1, w);
       const uint32_t u = (uint32_t)(((uint64_t)(w[0] >> 16) * U.swk) >> 16);
       kk[r] = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
-      const Step st = make_step<ENC>(pick_op(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
+      const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
       W.sab()[3 * tl] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
       W.sop()[3 * tl] = (uint8_t)(st.op | (st.c << 4));
       W.del()[tl] = 0;
@@ -633,7 +639,7 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
     const uint32_t e = W.dl()[j], tl = e & 0xFFu, m = e >> 8;
     uint32_t w[4];
     philox(g, sol, ((c0 + tl) << 2) | m, U.key, U.k0, U.k1, w);
-    const Step st = make_step<ENC>(pick_op(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
+    const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
     W.sab()[3 * tl + m] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
     W.sop()[3 * tl + m] = (uint8_t)(st.op | (st.c << 4));
   }
@@ -863,9 +869,7 @@ __device__ void ema_group(uint32_t *w, const unsigned long long *u, const unsign
   uint64_t s = 0;
   for (int i = 0; i < cnt; ++i) {
     if (!(mask & (1u << i))) continue;
-    const uint64_t uu = __hip_atomic_load(&u[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t vv = __hip_atomic_load(&v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint64_t r = (vv << 16) / (uu + 1);
+    const uint64_t r = ((uint64_t)v[i] << 16) / (u[i] + 1);
     uint64_t nw = ((uint64_t)A * w[i] + (uint64_t)(65536 - A) * (r + FL)) >> 16;
     nw = nw < FL ? FL : (nw > 65536 ? 65536 : nw);
     w[i] = (uint32_t)nw;
@@ -878,12 +882,97 @@ __device__ void ema_group(uint32_t *w, const unsigned long long *u, const unsign
   }
 }
 
-__device__ void epoch_close(DevJob *J, uint32_t g1, uint64_t T_end) {
-  if (g1 % J->E == 0) {
+// Per-launch counts of one workgroup, written to its own slots (no atomics):
+// slot i of solution s at counts[i * P + s]; i = 0..5 uses and 6..11
+// improvements per operator, 12..14 uses and 15..17 improvements per k, 18
+// accepted moves.  S holds per-lane counts (summed here over the wave) or,
+// with UNIFORM, counts that are already wave totals.
+constexpr int kCountSlots = 19;
+
+template <int ENC, bool UNIFORM>
+__device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LStats &S, uint32_t nacc) {
+  constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
+  constexpr int hi = ENC == 0 ? OOROPT : lo;
+  const uint32_t lane = lane_id();
+  uint32_t mine = 0;
+#pragma unroll
+  for (int o = lo; o <= hi; ++o) {
+    const uint32_t u = UNIFORM ? S.u[o] : wave_sum(S.u[o]);
+    const uint32_t v = UNIFORM ? S.v[o] : wave_sum(S.v[o]);
+    mine = lane == (uint32_t)o ? u : mine;
+    mine = lane == (uint32_t)(6 + o) ? v : mine;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const uint32_t uk = UNIFORM ? S.uk[q] : wave_sum(S.uk[q]);
+    const uint32_t vk = UNIFORM ? S.vk[q] : wave_sum(S.vk[q]);
+    mine = lane == (uint32_t)(12 + q) ? uk : mine;
+    mine = lane == (uint32_t)(15 + q) ? vk : mine;
+  }
+  mine = lane == 18u ? nacc : mine;
+  if (lane < (uint32_t)kCountSlots) J->counts[(size_t)lane * J->P + sol] = mine;
+}
+
+}  // namespace
+
+// After each evolve launch: fold the workgroups' counts of every job into its
+// epoch statistics, the instance best and the temperature, and at an epoch
+// boundary apply the AOS update (one workgroup per job; the kernel boundary
+// orders it after every evolve workgroup).
+__global__ __launch_bounds__(256) void k_epoch(DevJob *jobs, const uint32_t *idx) {
+  DevJob *J = jobs + (idx ? idx[blockIdx.x] : blockIdx.x);
+  const uint32_t g0 = J->g, gstop = J->g_stop;
+  if (g0 >= gstop) return;
+  const uint32_t E = J->E, P = J->P;
+  const uint32_t g1 = min(gstop, (g0 / E + 1) * E);
+  const uint32_t tid = threadIdx.x;
+  unsigned long long acc[kCountSlots];
+#pragma unroll
+  for (int i = 0; i < kCountSlots; ++i) acc[i] = 0;
+  long long mn = LLONG_MAX;
+  for (uint32_t s2 = tid; s2 < P; s2 += blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < kCountSlots; ++i) acc[i] += J->counts[(size_t)i * P + s2];
+    mn = min(mn, (long long)J->best_f[s2]);
+  }
+  __shared__ unsigned long long part[kCountSlots][4];
+  __shared__ long long pmin[4];
+#pragma unroll
+  for (int i = 0; i < kCountSlots; ++i) {
+    unsigned long long v = acc[i];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((tid & 63) == 0) part[i][tid >> 6] = v;
+  }
+  for (int o = 32; o > 0; o >>= 1) mn = min(mn, (long long)__shfl_xor(mn, o, 64));
+  if ((tid & 63) == 0) pmin[tid >> 6] = mn;
+  __syncthreads();
+  if (tid != 0) return;
+  const int nw = (blockDim.x + 63) / 64;
+  unsigned long long t[kCountSlots];
+  for (int i = 0; i < kCountSlots; ++i) {
+    t[i] = 0;
+    for (int w = 0; w < nw; ++w) t[i] += part[i][w];
+  }
+  for (int w = 0; w < nw; ++w) mn = min(mn, pmin[w]);
+  for (int o = 0; o < kOps; ++o) {
+    J->u_op[o] += t[o];
+    J->v_op[o] += t[6 + o];
+    if (J->credit == 0) J->tot_u_op[o] += t[o];
+  }
+  for (int q = 0; q < 3; ++q) {
+    J->u_k[q] += t[12 + q];
+    J->v_k[q] += t[15 + q];
+    if (J->credit == 0) J->tot_u_k[q] += t[12 + q];
+  }
+  J->accepted += t[18];
+  if (mn < J->inst_best) J->inst_best = mn;
+  uint64_t T = J->T;
+  for (uint32_t g = g0; g < g1; ++g) T = cool(T, J->alpha);
+  J->T = T;
+  if (g1 % E == 0) {
     ema_group(J->w_op, J->u_op, J->v_op, J->op_mask, kOps, J->aos_A, J->w_floor);
     ema_group(J->w_k, J->u_k, J->v_k, 7u, 3, J->aos_A, J->w_floor);
-    const int64_t ib = (int64_t)__hip_atomic_load((unsigned long long *)&J->inst_best, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t ib = J->inst_best;
     if (ib < J->epoch_ref) J->stag = 0;
     else J->stag += 1;
     J->epoch_ref = ib;
@@ -891,63 +980,13 @@ __device__ void epoch_close(DevJob *J, uint32_t g1, uint64_t T_end) {
       J->w_k[0] = 52429; J->w_k[1] = 9830; J->w_k[2] = 3277;
       J->stag = 0;
     }
-    for (int i = 0; i < kOps; ++i) {
-      __hip_atomic_store(&J->u_op[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&J->v_op[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    for (int i = 0; i < 3; ++i) {
-      __hip_atomic_store(&J->u_k[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&J->v_k[i], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    for (int i = 0; i < kOps; ++i) J->u_op[i] = J->v_op[i] = 0;
+    for (int i = 0; i < 3; ++i) J->u_k[i] = J->v_k[i] = 0;
   }
-  J->T = T_end;
   J->g = g1;
-  __hip_atomic_store(&J->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// S holds per-lane counts (summed here over the wave) or, with UNIFORM,
-// counts that are already wave totals.
-template <int ENC, bool UNIFORM>
-__device__ void finish_launch(DevJob *J, const LStats &S, uint32_t nacc, int64_t bf, uint32_t g1, uint64_t T_end) {
-  constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
-  constexpr int hi = ENC == 0 ? OOROPT : lo;
-  uint32_t u[kOps] = {0}, v[kOps] = {0}, uk[3], vk[3];
-#pragma unroll
-  for (int o = lo; o <= hi; ++o) {
-    u[o] = UNIFORM ? S.u[o] : wave_sum(S.u[o]);
-    v[o] = UNIFORM ? S.v[o] : wave_sum(S.v[o]);
-  }
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    uk[q] = UNIFORM ? S.uk[q] : wave_sum(S.uk[q]);
-    vk[q] = UNIFORM ? S.vk[q] : wave_sum(S.vk[q]);
-  }
-  if (lane_id() == 0) {
-    for (int o = lo; o <= hi; ++o) {
-      if (u[o]) atomicAdd(&J->u_op[o], (unsigned long long)u[o]);
-      if (v[o]) atomicAdd(&J->v_op[o], (unsigned long long)v[o]);
-    }
-    for (int q = 0; q < 3; ++q) {
-      if (uk[q]) atomicAdd(&J->u_k[q], (unsigned long long)uk[q]);
-      if (vk[q]) atomicAdd(&J->v_k[q], (unsigned long long)vk[q]);
-    }
-    if (J->credit == 0) {   // whole-run operator usage of the evaluated candidates
-      for (int o = lo; o <= hi; ++o)
-        if (u[o]) atomicAdd(&J->tot_u_op[o], (unsigned long long)u[o]);
-      for (int q = 0; q < 3; ++q)
-        if (uk[q]) atomicAdd(&J->tot_u_k[q], (unsigned long long)uk[q]);
-    }
-    if (nacc) atomicAdd(&J->accepted, (unsigned long long)nacc);
-    atomicMin((long long *)&J->inst_best, (long long)bf);
-    __threadfence();
-    const uint32_t prev = atomicAdd(&J->done, 1u);
-    if (prev == J->P - 1) {
-      __threadfence();
-      epoch_close(J, g1, T_end);
-      __threadfence();
-    }
-  }
-}
+namespace {
 
 // ------------------------------------------------------------ one workgroup
 template <int KIND, int STAGE>
@@ -1074,7 +1113,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     J->best_f[sol] = bf;
   }
   constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : 0);
-  finish_launch<ENC, KIND == KTSP>(J, S, nacc, bf, g1, T);
+  write_counts<ENC, KIND == KTSP>(J, sol, S, nacc);
 }
 
 }  // namespace
@@ -1468,6 +1507,11 @@ hipError_t evolve_plain(DevJob *job, int kind, int stage, uint32_t P, uint32_t l
 hipError_t evolve_items(DevJob *jobs, const uint2 *items, uint32_t n_items, uint32_t grid, uint32_t lds,
                         hipStream_t s) {
   hipLaunchKernelGGL(k_evolve_items, dim3(grid), dim3(64), lds, s, jobs, items, n_items);
+  return hipGetLastError();
+}
+
+hipError_t epoch(DevJob *jobs, const uint32_t *idx, uint32_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_epoch, dim3(count), dim3(256), 0, s, jobs, idx);
   return hipGetLastError();
 }
 
