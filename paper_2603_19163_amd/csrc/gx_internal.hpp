@@ -64,20 +64,23 @@ struct DevJob {
 };
 
 // LDS bytes one evolve workgroup needs for this instance and staging: the
-// candidate tables (4608 bytes) followed by the solution and instance data.
+// candidate tables (3968 bytes) followed by the solution and instance data.
+// Permutations of up to 1984 elements use one tour buffer (moves are applied
+// through the tables); longer ones a second buffer.
 inline uint32_t lds_bytes_for(int kind, int n, int stage) {
   auto al = [](uint32_t b) { return (b + 15u) & ~15u; };
-  const uint32_t un = (uint32_t)n, tables = 4608;
+  const uint32_t un = (uint32_t)n, tables = 3968;
+  const uint32_t tours = (n <= 1984 ? 1 : 2) * al(2 * un);
   switch (kind) {
     case KTSP: {
-      uint32_t b = tables + 2 * al(2 * un);
+      uint32_t b = tables + tours;
       if (stage == SLDS16) b += al(2 * un * un);
       else if (stage == SLDSXY) b += al(4 * un);
       return b;
     }
-    case KQAP: return tables + 2 * al(2 * un) + 2 * al(2 * un * un) + al(2 * kWave * un);
+    case KQAP: return tables + tours + 2 * al(2 * un * un) + al(2 * kWave * un);
     case KKNAP: return tables + al(un) + 2 * al(4 * un);
-    case KVRP: return tables + 2 * al(2 * un) + al(2 * (un + 1) * (un + 1)) + 3 * al(4 * (un + 1));
+    case KVRP: return tables + tours + al(2 * (un + 1) * (un + 1)) + 3 * al(4 * (un + 1));
     default: return tables + al(2 * un) + al(4 * (un + 1));   // + adjacency, added by the caller
   }
 }

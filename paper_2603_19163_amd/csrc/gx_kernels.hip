@@ -294,12 +294,13 @@ struct DistG32 {
 };
 
 // ------------------------------------------------------------ permutation apply
-__device__ __forceinline__ void perm_apply(uint16_t *&cur, uint16_t *&nxt, int n, const Step *st, int k) {
-  for (int p = lane_id(); p < n; p += kWave) nxt[p] = cur[chain(st, k, p)];
+// new solution into `tmp` (the candidate tables, dead at this point, or a
+// second buffer for long permutations), then back into `cur`
+__device__ __forceinline__ void perm_apply(uint16_t *cur, uint16_t *tmp, int n, const Step *st, int k) {
+  for (int p = lane_id(); p < n; p += kWave) tmp[p] = cur[chain(st, k, p)];
   __syncthreads();
-  uint16_t *t = cur;
-  cur = nxt;
-  nxt = t;
+  for (int p = lane_id(); p < n; p += kWave) cur[p] = tmp[p];
+  __syncthreads();
 }
 
 __device__ __forceinline__ void perm_store(const uint16_t *cur, int n, int32_t *dst) {
@@ -542,8 +543,9 @@ struct ColorK {
 // atomics.  Draws, moves and deltas are those of the per-candidate
 // formulation; only the order of evaluation differs.
 constexpr int kChunk = 128;
-constexpr uint32_t kTspScratch = kChunk * 3 * 4 + kChunk * 4 + kChunk * 6 * 2 + kChunk * 2 * 2 + kChunk * 3 + kChunk;
-static_assert(kTspScratch == 4608, "lds_bytes_for() reserves 4608 bytes of candidate tables");
+constexpr uint32_t kTspScratch = kChunk * 3 * 4 + kChunk * 4 + kChunk * 6 * 2 + kChunk * 3;
+static_assert(kTspScratch == 3968, "lds_bytes_for() reserves 3968 bytes of candidate tables");
+constexpr int kOneBufferN = kTspScratch / 2;
 
 // Dynamic LDS of the evolve kernels; the candidate tables sit at fixed offsets
 // from its start (so their addresses are compile-time constants).
@@ -553,8 +555,9 @@ struct TspScratch {
   __device__ __forceinline__ uint32_t *sab() const { return (uint32_t *)gx_lds; }         // a | b << 16 at [3t + m]
   __device__ __forceinline__ int32_t *del() const { return (int32_t *)(gx_lds + 1536); }  // delta accumulators
   __device__ __forceinline__ uint16_t *lst() const { return (uint16_t *)(gx_lds + 2048); } // t | m << 8 | sub << 10
-  __device__ __forceinline__ uint16_t *dl() const { return (uint16_t *)(gx_lds + 3584); }  // extra draws t | m << 8
-  __device__ __forceinline__ uint8_t *sop() const { return (uint8_t *)(gx_lds + 4096); }   // op | L << 4 at [3t + m]
+  // extra draws t | m << 8; used only before the pattern list is built
+  __device__ __forceinline__ uint16_t *dl() const { return (uint16_t *)(gx_lds + 2048); }
+  __device__ __forceinline__ uint8_t *sop() const { return (uint8_t *)(gx_lds + 3584); }   // op | L << 4 at [3t + m]
 };
 
 __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
@@ -706,7 +709,7 @@ __device__ __forceinline__ int pattern_delta(const TspScratch &W, const uint16_t
 }
 
 template <class DF>
-__device__ __forceinline__ void tsp_run(uint16_t *&cur, uint16_t *&nxt, int n, const DF &D, const TspScratch &W,
+__device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, int n, const DF &D, const TspScratch &W,
                                         const Uni &U, int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1,
                                         uint64_t &T, int64_t &f, int64_t &bf, LStats &S, uint32_t &nacc) {
   const uint32_t lane = lane_id();
@@ -1031,9 +1034,11 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
   char *const base = lds + kTspScratch;
 
   if constexpr (KIND == KTSP || KIND == KQAP || KIND == KVRP) {
+    // one tour buffer; the move application writes through the candidate
+    // tables (room for 1984 entries) or, for longer tours, a second buffer
     uint16_t *t0 = (uint16_t *)base;
-    uint16_t *t1 = (uint16_t *)(base + al16(2 * n));
-    char *rest = base + 2 * al16(2 * n);
+    uint16_t *t1 = n <= kOneBufferN ? (uint16_t *)lds : (uint16_t *)(base + al16(2 * n));
+    char *rest = base + (n <= kOneBufferN ? 1 : 2) * al16(2 * n);
     for (int p = lane; p < n; p += kWave) t0[p] = (uint16_t)cur_g[p];
     if constexpr (KIND == KTSP) {
       if constexpr (STAGE == SLDS16) {
