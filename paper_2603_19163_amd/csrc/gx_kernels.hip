@@ -213,6 +213,27 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// Wave-wide sum of a 64-bit value with DPP moves only (the same pattern as
+// wave_min_u32; the row broadcasts add into rows 1, 3 and then 2, 3 only, the
+// other rows add zero); the sum is uniform.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROW_MASK, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROW_MASK, 0xF, false);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+  v += dpp64<0xB1, 0xF>(v);
+  v += dpp64<0x4E, 0xF>(v);
+  v += dpp64<0x141, 0xF>(v);
+  v += dpp64<0x140, 0xF>(v);
+  v += dpp64<0x142, 0xA>(v);
+  v += dpp64<0x143, 0xC>(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // wave-wide minimum of a 64-bit key, high word first (result is uniform)
 __device__ __forceinline__ unsigned long long wave_min_key(unsigned long long k) {
   const uint32_t hi = wave_min_u32((uint32_t)(k >> 32));
@@ -235,7 +256,15 @@ __device__ __forceinline__ unsigned long long wave_min(unsigned long long v) {
 // delta / T) (T in Q16), compared with a 31-bit draw.
 __device__ __forceinline__ bool accept_worse(int64_t ds, uint64_t T, uint32_t g, uint32_t sol, const Uni &U) {
   if (T == 0) return false;
-  const uint64_t z = ((uint64_t)ds << 24) / T;
+  // z = floor(num / T) without a 64-bit integer division: the double quotient
+  // is within 2^-37 of num / T whenever it is below 4097, so its floor is off
+  // by at most one, and one integer correction each way makes z exact.
+  const uint64_t num = (uint64_t)ds << 24;
+  const double qd = (double)num / (double)T;
+  if (qd >= 4097.0) return false;
+  uint64_t z = (uint64_t)qd;
+  if (__umul64hi(z, T) != 0 || z * T > num) --z;
+  if (num - z * T >= T) ++z;
   if (z >= 4096) return false;
   const uint32_t p = (uint32_t)(((uint64_t)c_exp_hi[z >> 8] * c_exp_lo[z & 255]) >> 31);
   uint32_t r[4];
@@ -261,12 +290,21 @@ __device__ __forceinline__ void stage16(void *dst, const void *src, uint32_t byt
 
 // exact nearest-integer Euclidean distance for coordinates in [0, 2^14):
 // (isqrt(4 s) + 1) / 2 with the float estimate of the root corrected by one
-// step either way.  |dx|, |dy| < 2^14 and the root < 2^16, so every product
-// fits the full-rate 24-bit multiplier.
+// step either way.  |dx|, |dy| < 2^14 fit int16 lanes (s = dx^2 + dy^2 is one
+// packed subtract and one 2-term dot product for int16 coordinates) and the
+// root < 2^16, so the corrections fit the full-rate 24-bit multiplier.
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t sq_norm(short2 p, short2 q) {   // packed difference, 2-term dot
+  const s16x2 d = __builtin_bit_cast(s16x2, p) - __builtin_bit_cast(s16x2, q);
+  return (uint32_t)__builtin_amdgcn_sdot2(d, d, 0, false);
+}
+__device__ __forceinline__ uint32_t sq_norm(int2 p, int2 q) {
+  const int dx = p.x - q.x, dy = p.y - q.y;
+  return (uint32_t)(__mul24(dx, dx) + __mul24(dy, dy));
+}
 template <class V2>
 __device__ __forceinline__ int nint_dist(V2 p, V2 q) {
-  const int dx = (int)p.x - (int)q.x, dy = (int)p.y - (int)q.y;
-  const uint32_t s4 = 4u * (uint32_t)(__mul24(dx, dx) + __mul24(dy, dy));
+  const uint32_t s4 = 4u * sq_norm(p, q);
   uint32_t r = (uint32_t)__builtin_amdgcn_sqrtf((float)s4);
   r -= (__umul24(r, r) > s4);
   r += (__umul24(r + 1, r + 1) <= s4);
@@ -557,7 +595,7 @@ struct TspScratch {
   __device__ __forceinline__ uint16_t *lst() const { return (uint16_t *)(gx_lds + 2048); } // t | m << 8 | sub << 10
   // extra draws t | m << 8; used only before the pattern list is built
   __device__ __forceinline__ uint16_t *dl() const { return (uint16_t *)(gx_lds + 2048); }
-  __device__ __forceinline__ uint8_t *sop() const { return (uint8_t *)(gx_lds + 3584); }   // op | L << 4 at [3t + m]
+  __device__ __forceinline__ uint8_t *sop() const { return (uint8_t *)(gx_lds + 3584); }   // op | L << 4 at [3t + m], k << 6 at m = 0
 };
 
 __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
@@ -574,17 +612,16 @@ struct PMap {
 };
 
 __device__ __forceinline__ PMap pmap(int op, int a, int b, int L, int sub) {
+  // block [a, a+L) moved to start at b, or reversal of [a + sub, b - sub]
+  const bool mv = op >= OINS, qlt = b < a;
+  const int lo = a + sub, hi = b - sub;
   PMap M;
-  if (op >= OINS) {           // block [a, a+L) moved to start at b
-    if (b < a) {
-      M.s1 = b; M.e1 = b + L; M.e2 = a + L; M.m1 = 1; M.o1 = a - b; M.o2 = -L;
-    } else {
-      M.s1 = a; M.e1 = b; M.e2 = b + L; M.m1 = 1; M.o1 = L; M.o2 = a - b;
-    }
-  } else {                    // reversal of [a + sub, b - sub]
-    const int lo = a + sub, hi = b - sub;
-    M.s1 = lo; M.e1 = hi + 1; M.e2 = hi + 1; M.m1 = -1; M.o1 = lo + hi; M.o2 = 0;
-  }
+  M.s1 = mv ? min(a, b) : lo;
+  M.e1 = mv ? (qlt ? b + L : b) : hi + 1;
+  M.e2 = mv ? max(a, b) + L : hi + 1;
+  M.m1 = mv ? 1 : -1;
+  M.o1 = mv ? (qlt ? a - b : L) : lo + hi;
+  M.o2 = mv ? (qlt ? -L : a - b) : 0;
   return M;
 }
 
@@ -600,7 +637,7 @@ __device__ __forceinline__ void unpack_step(const TspScratch &W, int t, int m, i
   a = (int)(ab & 0xFFFFu);
   b = (int)(ab >> 16);
   op = (int)(ol & 15u);
-  L = (int)(ol >> 4);
+  L = (int)((ol >> 4) & 3u);
 }
 
 // Draw the composite moves of candidates [c0, c0 + cn): the first step of
@@ -623,7 +660,7 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
       kk[r] = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
       const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
       W.sab()[3 * tl] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
-      W.sop()[3 * tl] = (uint8_t)(st.op | (st.c << 4));
+      W.sop()[3 * tl] = (uint8_t)(st.op | (st.c << 4) | (kk[r] << 6));
       W.del()[tl] = 0;
     }
   }
@@ -658,7 +695,7 @@ __device__ __forceinline__ Step load_step(const TspScratch &W, int t, int m) {
   st.a = (int)(ab & 0xFFFFu);
   st.b = ENC == 2 ? (int)(int16_t)(ab >> 16) : (int)(ab >> 16);
   st.op = (int)(ol & 15u);
-  st.c = (int)(ol >> 4);
+  st.c = (int)((ol >> 4) & 3u);
   return st;
 }
 
@@ -669,20 +706,24 @@ __device__ __forceinline__ int pattern_delta(const TspScratch &W, const uint16_t
                                              int t, int m, int sub) {
   int op, a, b, L;
   unpack_step(W, t, m, op, a, b, L);
-  const bool mv = op >= OINS, qlt = b < a;
-  const int lo = a + sub, hi = b - sub;
-  bool zero;
-  if (mv) zero = (L == 0) || (qlt && b == 0 && a + L == n) || (!qlt && a == 0 && b + L == n);
-  else zero = hi - lo >= n - 1;
+  // Every pattern reads the tour at (X-1, X, r2, r3, Z-1, Z): a block move
+  // cuts before X = min(i, q), before B and before Z = max(i, q) + L, with
+  // B = i (q < i) or i + L (q > i), so (r2, r3) = (B-1, B); a reversal of
+  // [lo, hi] has X = lo, Z = hi + 1 and (r2, r3) = (lo, hi), whose two terms
+  // cancel.  Only X-1 and Z can leave [0, n).  A pattern with X = 0 and
+  // Z = n (a full reversal or a rotation), or a move of length 0, is zero.
+  const bool mv = op >= OINS;
+  const int X = mv ? min(a, b) : a + sub;
+  const int Z = mv ? max(a, b) + L : b - sub + 1;
+  const int B = a + (b < a ? 0 : L);
+  const bool zero = (X == 0 && Z == n) || (mv && L == 0);
   int r[6];
-  r[0] = mv ? (qlt ? b - 1 : a - 1) : lo - 1;
-  r[1] = mv ? (qlt ? b : a) : lo;
-  r[2] = mv ? (qlt ? a - 1 : a + L - 1) : lo;
-  r[3] = mv ? (qlt ? a : a + L) : hi;
-  r[4] = mv ? (qlt ? a + L - 1 : b + L - 1) : hi;
-  r[5] = mv ? (qlt ? a + L : b + L) : hi + 1;
-#pragma unroll
-  for (int i = 0; i < 6; ++i) r[i] += r[i] < 0 ? n : (r[i] >= n ? -n : 0);
+  r[0] = (X == 0 ? n : X) - 1;
+  r[1] = X;
+  r[2] = mv ? B - 1 : X;
+  r[3] = mv ? B : Z - 1;
+  r[4] = Z - 1;
+  r[5] = Z == n ? 0 : Z;
   // map back through the earlier pattern steps, latest first
   if (sub) {
     const PMap M = pmap(op, a, b, L, 0);
@@ -708,11 +749,32 @@ __device__ __forceinline__ int pattern_delta(const TspScratch &W, const uint16_t
   return zero ? 0 : d;
 }
 
+// Adds the wave-wide sums of per-lane byte counters (field i at bits 8i) to
+// the uniform counts u[i] and v[i]; even and odd bytes are widened to 16-bit
+// fields first so that the 64-lane sums cannot carry into a neighbour.
+__device__ __forceinline__ void fold_byte_counts(uint32_t *u, uint32_t *v, uint32_t cu, uint32_t cv, int fields) {
+  const uint32_t ue = uni(wave_sum(cu & 0x00FF00FFu)), uo = uni(wave_sum((cu >> 8) & 0x00FF00FFu));
+  const uint32_t ve = uni(wave_sum(cv & 0x00FF00FFu)), vo = uni(wave_sum((cv >> 8) & 0x00FF00FFu));
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (i >= fields) break;
+    const int sh = (i >> 1) << 4;
+    u[i] += ((i & 1 ? uo : ue) >> sh) & 0xFFFFu;
+    v[i] += ((i & 1 ? vo : ve) >> sh) & 0xFFFFu;
+  }
+}
+
 template <class DF>
 __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, int n, const DF &D, const TspScratch &W,
                                         const Uni &U, int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1,
                                         uint64_t &T, int64_t &f, int64_t &bf, LStats &S, uint32_t &nacc) {
   const uint32_t lane = lane_id();
+  // Per-lane use and improvement counts of the four operators and of k = 1..3
+  // in byte fields (operator o at bits 8o, k at bits 8(k-1)); a chunk of
+  // candidates adds at most 6 to a field of a lane, so the fields are folded
+  // into the wave-wide counts of S every 42 chunks and at the end.
+  uint32_t cu_op = 0, cv_op = 0, cu_k = 0, cv_k = 0, since_fold = 0;
+  const uint32_t c_last = (U.C - 1) / kChunk * kChunk;
   for (uint32_t g = g0; g < g1; ++g) {
     unsigned long long bk = ~0ull;
     for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
@@ -749,33 +811,34 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, int n, con
         }
       }
       __syncthreads();
-      // ---- keys and statistics (wave-wide counts: S is uniform on this path)
+      // ---- keys and per-lane statistics (byte counters, folded into S below)
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const uint32_t tl = r * kWave + lane;
         const bool valid = tl < cn;
         const int64_t d = valid ? (int64_t)W.del()[tl] : 0;
-        if (U.credit == 0) {
-          const bool imp = valid && d < 0;
+        if (U.credit == 0 && valid) {
+          const bool imp = d < 0;
 #pragma unroll
           for (int m = 0; m < 3; ++m) {
-            const int op = (valid && kk[r] > m) ? (int)(W.sop()[3 * tl + m] & 15u) : -1;
-#pragma unroll
-            for (int o = 0; o < 4; ++o) {
-              S.u[o] += (uint32_t)__popcll(__ballot(op == o));
-              S.v[o] += (uint32_t)__popcll(__ballot(op == o && imp));
-            }
+            const uint32_t inc = kk[r] > m ? 1u << ((W.sop()[3 * tl + m] & 15u) << 3) : 0u;
+            cu_op += inc;
+            cv_op += imp ? inc : 0u;
           }
-#pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            S.uk[q] += (uint32_t)__popcll(__ballot(valid && kk[r] == q + 1));
-            S.vk[q] += (uint32_t)__popcll(__ballot(valid && kk[r] == q + 1 && imp));
-          }
+          const uint32_t inck = 1u << ((kk[r] - 1) << 3);
+          cu_k += inck;
+          cv_k += imp ? inck : 0u;
         }
         if (valid) {
           const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | (c0 + tl);
           bk = key < bk ? key : bk;
         }
+      }
+      if (++since_fold == 42) {
+        fold_byte_counts(S.u, S.v, cu_op, cv_op, 4);
+        fold_byte_counts(S.uk, S.vk, cu_k, cv_k, 3);
+        cu_op = cv_op = cu_k = cv_k = 0;
+        since_fold = 0;
       }
       __syncthreads();
     }
@@ -785,8 +848,19 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, int n, con
     bool acc = ds <= 0;
     if (!acc) acc = accept_worse(ds, T, g, sol, U);
     if (acc) {
+      // the steps of the winner: from the tables when it was drawn in the
+      // last chunk (they still hold that chunk), else drawn again
       Step st[3];
-      const int k = sample<0>(U, g, sol, ts, st);
+      int k;
+      if (ts >= c_last) {
+        const int tl = (int)(ts - c_last);
+        k = (int)(W.sop()[3 * tl] >> 6);
+        st[0] = load_step<0>(W, tl, 0);
+        st[1] = load_step<0>(W, tl, 1);
+        st[2] = load_step<0>(W, tl, 2);
+      } else {
+        k = sample<0>(U, g, sol, ts, st);
+      }
       if (U.credit == 1) {   // wave-uniform counts on this path
 #pragma unroll
         for (int m = 0; m < 3; ++m)
@@ -812,6 +886,8 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, int n, con
     }
     T = cool(T, U.alpha);
   }
+  fold_byte_counts(S.u, S.v, cu_op, cv_op, 4);
+  fold_byte_counts(S.uk, S.vk, cu_k, cv_k, 3);
 }
 
 // ------------------------------------------------------------ generation loop
@@ -865,6 +941,18 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
 }
 
 // ------------------------------------------------------------ epoch close
+// floor(num / den) for den > 0, exact: a double quotient below 2^24 is within
+// 2^-27 of num / den, so its floor is off by at most one and one integer
+// correction each way fixes it; larger quotients take the integer division.
+__device__ __forceinline__ uint64_t udiv_q24(uint64_t num, uint64_t den) {
+  const double qd = (double)num / (double)den;
+  if (qd >= 16777216.0) return num / den;
+  uint64_t q = (uint64_t)qd;
+  if (__umul64hi(q, den) != 0 || q * den > num) --q;
+  if (num - q * den >= den) ++q;
+  return q;
+}
+
 // Eq. ema per enabled operator and per K-step, clamp to [floor, 1], normalise;
 // stagnation of the instance best resets the K-step weights (Alg. 2).
 __device__ void ema_group(uint32_t *w, const unsigned long long *u, const unsigned long long *v, uint32_t mask,
@@ -872,7 +960,7 @@ __device__ void ema_group(uint32_t *w, const unsigned long long *u, const unsign
   uint64_t s = 0;
   for (int i = 0; i < cnt; ++i) {
     if (!(mask & (1u << i))) continue;
-    const uint64_t r = ((uint64_t)v[i] << 16) / (u[i] + 1);
+    const uint64_t r = udiv_q24((uint64_t)v[i] << 16, u[i] + 1);
     uint64_t nw = ((uint64_t)A * w[i] + (uint64_t)(65536 - A) * (r + FL)) >> 16;
     nw = nw < FL ? FL : (nw > 65536 ? 65536 : nw);
     w[i] = (uint32_t)nw;
@@ -880,7 +968,7 @@ __device__ void ema_group(uint32_t *w, const unsigned long long *u, const unsign
   }
   for (int i = 0; i < cnt; ++i) {
     if (!(mask & (1u << i))) continue;
-    const uint64_t nw = ((uint64_t)w[i] << 16) / s;
+    const uint64_t nw = udiv_q24((uint64_t)w[i] << 16, s);
     w[i] = (uint32_t)(nw < 1 ? 1 : nw);
   }
 }
@@ -920,43 +1008,68 @@ __device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LSta
 
 // After each evolve launch: fold the workgroups' counts of every job into its
 // epoch statistics, the instance best and the temperature, and at an epoch
-// boundary apply the AOS update (one workgroup per job; the kernel boundary
-// orders it after every evolve workgroup).
+// boundary apply the AOS update (the kernel boundary orders it after every
+// evolve workgroup).  Grid (jobs, parts): workgroup (j, y) sums the counts of solutions y*256+t,
+// stepping by parts*256, and leaves one row of partial sums; the last
+// workgroup of the job to arrive combines the rows and updates the job.
 __global__ __launch_bounds__(256) void k_epoch(DevJob *jobs, const uint32_t *idx) {
   DevJob *J = jobs + (idx ? idx[blockIdx.x] : blockIdx.x);
   const uint32_t g0 = J->g, gstop = J->g_stop;
   if (g0 >= gstop) return;
-  const uint32_t E = J->E, P = J->P;
+  const uint32_t E = J->E, P = J->P, parts = gridDim.y, part = blockIdx.y;
   const uint32_t g1 = min(gstop, (g0 / E + 1) * E);
   const uint32_t tid = threadIdx.x;
   unsigned long long acc[kCountSlots];
 #pragma unroll
   for (int i = 0; i < kCountSlots; ++i) acc[i] = 0;
   long long mn = LLONG_MAX;
-  for (uint32_t s2 = tid; s2 < P; s2 += blockDim.x) {
+  for (uint32_t s2 = part * 256 + tid; s2 < P; s2 += parts * 256) {
 #pragma unroll
     for (int i = 0; i < kCountSlots; ++i) acc[i] += J->counts[(size_t)i * P + s2];
     mn = min(mn, (long long)J->best_f[s2]);
   }
-  __shared__ unsigned long long part[kCountSlots][4];
+  __shared__ unsigned long long part_sum[kCountSlots][4];
   __shared__ long long pmin[4];
+  __shared__ uint32_t last;
+  // signed minimum through the unsigned order of v ^ 2^63
+  constexpr unsigned long long kSign = 1ull << 63;
 #pragma unroll
   for (int i = 0; i < kCountSlots; ++i) {
-    unsigned long long v = acc[i];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    if ((tid & 63) == 0) part[i][tid >> 6] = v;
+    const unsigned long long v = wave_sum_u64(acc[i]);
+    if ((tid & 63) == 0) part_sum[i][tid >> 6] = v;
   }
-  for (int o = 32; o > 0; o >>= 1) mn = min(mn, (long long)__shfl_xor(mn, o, 64));
+  mn = (long long)(wave_min_key((unsigned long long)mn ^ kSign) ^ kSign);
   if ((tid & 63) == 0) pmin[tid >> 6] = mn;
   __syncthreads();
-  if (tid != 0) return;
-  const int nw = (blockDim.x + 63) / 64;
-  unsigned long long t[kCountSlots];
-  for (int i = 0; i < kCountSlots; ++i) {
-    t[i] = 0;
-    for (int w = 0; w < nw; ++w) t[i] += part[i][w];
+  if (tid < (uint32_t)kEpochSlots) {
+    unsigned long long v;
+    if (tid < (uint32_t)kCountSlots) {
+      v = part_sum[tid][0] + part_sum[tid][1] + part_sum[tid][2] + part_sum[tid][3];
+    } else {
+      v = (unsigned long long)min(min(pmin[0], pmin[1]), min(pmin[2], pmin[3]));
+    }
+    J->epart[(size_t)part * kEpochSlots + tid] = v;
   }
-  for (int w = 0; w < nw; ++w) mn = min(mn, pmin[w]);
+  __syncthreads();
+  if (tid == 0) {
+    __threadfence();
+    last = atomicAdd(&J->arrive, 1u) == parts - 1;
+  }
+  __syncthreads();
+  if (!last || tid >= 64) return;
+  __threadfence();
+  // wave 0 of the last workgroup: lane y holds row y
+  unsigned long long t[kCountSlots];
+  mn = LLONG_MAX;
+#pragma unroll
+  for (int i = 0; i < kCountSlots; ++i)
+    t[i] = wave_sum_u64(tid < parts ? J->epart[(size_t)tid * kEpochSlots + i] : 0ull);
+  {
+    const long long v = tid < parts ? (long long)J->epart[(size_t)tid * kEpochSlots + kCountSlots] : LLONG_MAX;
+    mn = (long long)(wave_min_key((unsigned long long)v ^ kSign) ^ kSign);
+  }
+  if (tid != 0) return;
+  J->arrive = 0;
   for (int o = 0; o < kOps; ++o) {
     J->u_op[o] += t[o];
     J->v_op[o] += t[6 + o];
@@ -1515,8 +1628,8 @@ hipError_t evolve_items(DevJob *jobs, const uint2 *items, uint32_t n_items, uint
   return hipGetLastError();
 }
 
-hipError_t epoch(DevJob *jobs, const uint32_t *idx, uint32_t count, hipStream_t s) {
-  hipLaunchKernelGGL(k_epoch, dim3(count), dim3(256), 0, s, jobs, idx);
+hipError_t epoch(DevJob *jobs, const uint32_t *idx, uint32_t count, uint32_t parts, hipStream_t s) {
+  hipLaunchKernelGGL(k_epoch, dim3(count, parts), dim3(256), 0, s, jobs, idx);
   return hipGetLastError();
 }
 
