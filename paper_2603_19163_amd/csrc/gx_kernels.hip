@@ -611,16 +611,15 @@ struct PMap {
   int s1, e1, e2, m1, o1, o2;
 };
 
-__device__ __forceinline__ PMap pmap(int op, int a, int b, int L, int sub) {
-  // block [a, a+L) moved to start at b, or reversal of [a + sub, b - sub]
+__device__ __forceinline__ PMap pmap(int op, int a, int b, int L) {
+  // block [a, a+L) moved to start at b, or reversal of [a, b]
   const bool mv = op >= OINS, qlt = b < a;
-  const int lo = a + sub, hi = b - sub;
   PMap M;
-  M.s1 = mv ? min(a, b) : lo;
-  M.e1 = mv ? (qlt ? b + L : b) : hi + 1;
-  M.e2 = mv ? max(a, b) + L : hi + 1;
+  M.s1 = mv ? min(a, b) : a;
+  M.e1 = mv ? (qlt ? b + L : b) : b + 1;
+  M.e2 = mv ? max(a, b) + L : b + 1;
   M.m1 = mv ? 1 : -1;
-  M.o1 = mv ? (qlt ? a - b : L) : lo + hi;
+  M.o1 = mv ? (qlt ? a - b : L) : a + b;
   M.o2 = mv ? (qlt ? -L : a - b) : 0;
   return M;
 }
@@ -699,9 +698,18 @@ __device__ __forceinline__ Step load_step(const TspScratch &W, int t, int m) {
   return st;
 }
 
+// position before a step of the element at position p after it: a swap
+// exchanges a and b; a reversal or a block move is the map of its pattern
+__device__ __forceinline__ int step_map(int op, int a, int b, int L, int p) {
+  const int pm = papply(pmap(op, a, b, L), p);
+  const int sw = p == a ? b : (p == b ? a : p);
+  return op == OSWAP ? sw : pm;
+}
+
 // delta of pattern step `sub` of operator m of candidate t, on the tour after
-// all earlier pattern steps of that candidate
-template <class DF>
+// all earlier steps of that candidate (MAPPED: m >= 1, whose read positions
+// are mapped back through steps m-1 .. 0)
+template <bool MAPPED, class DF>
 __device__ __forceinline__ int pattern_delta(const TspScratch &W, const uint16_t *tour, int n, const DF &D,
                                              int t, int m, int sub) {
   int op, a, b, L;
@@ -712,35 +720,27 @@ __device__ __forceinline__ int pattern_delta(const TspScratch &W, const uint16_t
   // [lo, hi] has X = lo, Z = hi + 1 and (r2, r3) = (lo, hi), whose two terms
   // cancel.  Only X-1 and Z can leave [0, n).  A pattern with X = 0 and
   // Z = n (a full reversal or a rotation), or a move of length 0, is zero.
+  // The second reversal of a swap (a, b), [a+1, b-1] after [a, b], reads
+  // positions b, b-1, b-1, a+1, a+1, a of the tour before the swap.
   const bool mv = op >= OINS;
-  const int X = mv ? min(a, b) : a + sub;
-  const int Z = mv ? max(a, b) + L : b - sub + 1;
+  const int X = mv ? min(a, b) : a;
+  const int Z = mv ? max(a, b) + L : b + 1;
   const int B = a + (b < a ? 0 : L);
-  const bool zero = (X == 0 && Z == n) || (mv && L == 0);
+  const bool zero = !sub && ((X == 0 && Z == n) || (mv && L == 0));
   int r[6];
-  r[0] = (X == 0 ? n : X) - 1;
-  r[1] = X;
-  r[2] = mv ? B - 1 : X;
-  r[3] = mv ? B : Z - 1;
-  r[4] = Z - 1;
-  r[5] = Z == n ? 0 : Z;
-  // map back through the earlier pattern steps, latest first
-  if (sub) {
-    const PMap M = pmap(op, a, b, L, 0);
+  r[0] = sub ? b : (X == 0 ? n : X) - 1;
+  r[1] = sub ? b - 1 : X;
+  r[2] = sub ? b - 1 : (mv ? B - 1 : X);
+  r[3] = sub ? a + 1 : (mv ? B : Z - 1);
+  r[4] = sub ? a + 1 : Z - 1;
+  r[5] = sub ? a : (Z == n ? 0 : Z);
+  if (MAPPED) {
+    for (int mm = m - 1; mm >= 0; --mm) {
+      int o2, a2, b2, L2;
+      unpack_step(W, t, mm, o2, a2, b2, L2);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) r[i] = papply(M, r[i]);
-  }
-  for (int mm = m - 1; mm >= 0; --mm) {
-    int o2, a2, b2, L2;
-    unpack_step(W, t, mm, o2, a2, b2, L2);
-    if (n_patterns(o2, a2, b2) == 2) {
-      const PMap M = pmap(o2, a2, b2, L2, 1);
-#pragma unroll
-      for (int i = 0; i < 6; ++i) r[i] = papply(M, r[i]);
+      for (int i = 0; i < 6; ++i) r[i] = step_map(o2, a2, b2, L2, r[i]);
     }
-    const PMap M = pmap(o2, a2, b2, L2, 0);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) r[i] = papply(M, r[i]);
   }
   int v[6];
 #pragma unroll
@@ -781,10 +781,12 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, int n, con
       const uint32_t cn = min((uint32_t)kChunk, U.C - c0);
       int kk[2];
       draw_chunk<0>(W, U, g, sol, c0, cn, kk);
-      // ---- pattern-step list, grouped by (operator slot, pattern step)
-      uint32_t nq = 0;
+      // ---- pattern-step list, grouped by (operator slot, pattern step);
+      // entries [0, nq0) belong to first steps and need no position map
+      uint32_t nq = 0, nq0 = 0;
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
+        if (m == 1) nq0 = nq;
         if (!__ballot(kk[0] > m || kk[1] > m)) break;
 #pragma unroll
         for (int sub = 0; sub < 2; ++sub)
@@ -804,9 +806,14 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, int n, con
       }
       __syncthreads();
       if (n >= 2) {
-        for (uint32_t j = lane; j < nq; j += kWave) {
+        for (uint32_t j = lane; j < nq0; j += kWave) {
           const uint32_t e = W.lst()[j];
-          const int d = pattern_delta(W, cur, n, D, (int)(e & 0xFFu), (int)((e >> 8) & 3u), (int)(e >> 10));
+          const int d = pattern_delta<false>(W, cur, n, D, (int)(e & 0xFFu), 0, (int)(e >> 10));
+          if (d) atomicAdd(&W.del()[e & 0xFFu], d);
+        }
+        for (uint32_t j = nq0 + lane; j < nq; j += kWave) {
+          const uint32_t e = W.lst()[j];
+          const int d = pattern_delta<true>(W, cur, n, D, (int)(e & 0xFFu), (int)((e >> 8) & 3u), (int)(e >> 10));
           if (d) atomicAdd(&W.del()[e & 0xFFu], d);
         }
       }
