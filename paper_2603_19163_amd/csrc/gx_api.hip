@@ -500,8 +500,7 @@ int heur_mats_of(int kind) { return kind == KQAP ? 2 : ((kind == KTSP || kind ==
 // bytes of the per-job device arrays, laid out by carve_job
 size_t job_array_bytes(size_t n, size_t P, size_t Q) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  return 2 * al(4 * n * P) + 2 * al(8 * P) + al(4 * n * Q) + al(8 * Q) + al(32 * n) + al(4 * n) + al(4 * 19 * P) +
-         al(8 * kEpochSlots * kEpochParts);
+  return 2 * al(4 * n * P) + 2 * al(8 * P) + al(4 * n * Q) + al(8 * Q) + al(32 * n) + al(4 * n) + al(8 * kShards * kEpochSlots);
 }
 
 void carve_job(DevJob &h, char *q, size_t n) {
@@ -519,8 +518,7 @@ void carve_job(DevJob &h, char *q, size_t n) {
   h.pool_f = (int64_t *)take(8 * (size_t)h.Q);
   h.sums = (int64_t *)take(32 * n);
   h.best_out = (int32_t *)take(4 * n);
-  h.counts = (uint32_t *)take(4 * 19 * (size_t)h.P);
-  h.epart = (unsigned long long *)take(8 * kEpochSlots * kEpochParts);
+  h.shard = (unsigned long long *)take(8 * kShards * kEpochSlots);
 }
 
 gx_status ensure_d32(gx_ctx *c, gx_instance *in) {
@@ -621,8 +619,7 @@ gx_status gx_job_create(gx_ctx *c, const gx_instance *cin, const gx_solve_params
       (st = dalloc(c, j->bufs, &h.cur_f, (size_t)8 * h.P)) || (st = dalloc(c, j->bufs, &h.best_f, (size_t)8 * h.P)) ||
       (st = dalloc(c, j->bufs, &h.pool, 4 * n * h.Q)) || (st = dalloc(c, j->bufs, &h.pool_f, (size_t)8 * h.Q)) ||
       (st = dalloc(c, j->bufs, &h.sums, 32 * n)) || (st = dalloc(c, j->bufs, &h.best_out, 4 * n)) ||
-      (st = dalloc(c, j->bufs, &h.counts, (size_t)4 * 19 * h.P)) ||
-      (st = dalloc(c, j->bufs, &h.epart, (size_t)8 * kEpochSlots * kEpochParts)) ||
+      (st = dalloc(c, j->bufs, &h.shard, (size_t)8 * kShards * kEpochSlots)) ||
       (st = dalloc(c, j->bufs, &j->d, sizeof(DevJob))))
     return bail(st);
   if (hipMemcpy(j->d, &h, sizeof(DevJob), hipMemcpyHostToDevice) != hipSuccess)
@@ -649,11 +646,11 @@ gx_status gx_job_advance(gx_ctx *c, gx_job *j, uint32_t ng) {
   HIPCHK(c, hipEventRecord(j->ev0, c->stream));
   DevJob *dj = j->d;
   const int kind = j->inst->h.kind, stage = (int)j->h.stage;
-  const uint32_t P = j->h.P, lds = j->h.lds_bytes, parts = epoch_parts(P);
+  const uint32_t P = j->h.P, lds = j->h.lds_bytes;
   hipStream_t s = c->stream;
   gx_status st = enqueue_launches(c, j, L, [=]() {
     const hipError_t e = gxk::evolve_plain(dj, kind, stage, P, lds, s);
-    return e != hipSuccess ? e : gxk::epoch(dj, nullptr, 1, parts, s);
+    return e != hipSuccess ? e : gxk::epoch(dj, nullptr, 1, s);
   });
   if (st) return st;
   HIPCHK(c, hipEventRecord(j->ev1, c->stream));
@@ -885,12 +882,9 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
   const uint32_t ni = (uint32_t)n_items, lds = max_lds;
   hipStream_t s = c->stream;
   const uint32_t njobs = (uint32_t)count;
-  uint32_t max_p = 1;
-  for (int i = 0; i < count; ++i) max_p = std::max(max_p, hj[i].P);
-  const uint32_t parts = epoch_parts(max_p);
   gx_status st = enqueue_launches(c, lead, L, [=]() {
     const hipError_t e = gxk::evolve_items(jd, itd, ni, grid, lds, s);
-    return e != hipSuccess ? e : gxk::epoch(jd, nullptr, njobs, parts, s);
+    return e != hipSuccess ? e : gxk::epoch(jd, nullptr, njobs, s);
   });
   if (st) {
     for (gx_job *j : made) delete j;
@@ -1114,13 +1108,12 @@ void server_loop(gx_server *S) {
       if (srv_stage(S, r) != GX_OK) r->cancel = true;   // staging failure: reported as cancelled
     // ---- one quantum: every resident running request advances one epoch chunk
     active.clear();
-    uint32_t max_lds = 16, max_p = 1;
+    uint32_t max_lds = 16;
     size_t n_items = 0;
     for (SrvReq *r : S->slots)
       if (r && r->state == RQ_RESIDENT && !r->cancel && r->g < r->hj.G) {
         active.push_back(r);
         max_lds = std::max(max_lds, r->hj.lds_bytes);
-        max_p = std::max(max_p, r->hj.P);
         n_items += r->hj.P;
       }
     if (!active.empty() && srv_grow_items(S, n_items) == GX_OK) {
@@ -1138,7 +1131,7 @@ void server_loop(gx_server *S) {
       (void)hipMemcpyAsync(S->items_d[buf], h, n_items * sizeof(uint2), hipMemcpyHostToDevice, S->s);
       (void)hipMemcpyAsync(S->slots_d[buf], sl, active.size() * sizeof(uint32_t), hipMemcpyHostToDevice, S->s);
       (void)gxk::evolve_items(S->jobs_d, S->items_d[buf], (uint32_t)n_items, grid, max_lds, S->s);
-      (void)gxk::epoch(S->jobs_d, S->slots_d[buf], (uint32_t)active.size(), epoch_parts(max_p), S->s);
+      (void)gxk::epoch(S->jobs_d, S->slots_d[buf], (uint32_t)active.size(), S->s);
       (void)hipEventRecord(S->items_ev[buf], S->s);
       buf ^= 1;
       uint64_t evals = 0;

@@ -8,15 +8,12 @@ namespace gx {
 
 constexpr int kWave = 64;
 constexpr int kOps = 6;
-// The epoch kernel reduces the per-workgroup counts in up to kEpochParts
-// workgroups per job; each leaves kEpochSlots partial sums (19 counts and
-// the smallest best objective) for the last one to combine.
-constexpr int kEpochParts = 32;
+// Each evolve workgroup adds its per-launch counts (19 of them) into one of
+// kShards rows of kEpochSlots 64-bit accumulators, picked by its solution
+// index, and lowers the row's smallest best objective (slot 19); the epoch
+// kernel folds the rows and clears them for the next launch.
+constexpr int kShards = 64;
 constexpr int kEpochSlots = 20;
-inline uint32_t epoch_parts(uint32_t P) {
-  const uint32_t b = (P + 255) / 256;
-  return b < 1 ? 1 : (b > (uint32_t)kEpochParts ? (uint32_t)kEpochParts : b);
-}
 constexpr int kMaxQapN = 64;
 constexpr int kMaxVrpN = 250;
 constexpr int kMaxCoord = 1 << 14;
@@ -56,7 +53,7 @@ struct DevJob {
   uint32_t g, g_stop, stag, done;
   uint64_t T;
   int64_t epoch_ref, inst_best;
-  uint32_t w_op[kOps], w_k[3], arrive;   // arrive: epoch workgroups done this launch
+  uint32_t w_op[kOps], w_k[3], pad3;
   unsigned long long u_op[kOps], v_op[kOps], u_k[3], v_k[3];
   unsigned long long accepted;
   unsigned long long tot_u_op[kOps], tot_u_k[3];   // whole-run usage counts
@@ -67,8 +64,7 @@ struct DevJob {
   int64_t *pool_f;            // Q
   int64_t *sums;              // 2 x n heuristic row/column sums
   int32_t *best_out;          // n
-  uint32_t *counts;           // 19 x P per-launch counts of each workgroup
-  unsigned long long *epart;  // kEpochParts x kEpochSlots partial sums of the epoch kernel
+  unsigned long long *shard;  // kShards x kEpochSlots per-launch accumulators
   int64_t best_out_f;
   int32_t best_idx, pad4;
 };
@@ -110,7 +106,7 @@ hipError_t evolve_plain(gx::DevJob *job, int kind, int stage, uint32_t P, uint32
 hipError_t evolve_items(gx::DevJob *jobs, const uint2 *items, uint32_t n_items, uint32_t grid,
                         uint32_t lds, hipStream_t s);
 hipError_t fetch_best(gx::DevJob *jobs, int count, hipStream_t s);
-hipError_t epoch(gx::DevJob *jobs, const uint32_t *idx, uint32_t count, uint32_t parts, hipStream_t s);
+hipError_t epoch(gx::DevJob *jobs, const uint32_t *idx, uint32_t count, hipStream_t s);
 hipError_t prepare_kernel_attrs(uint32_t max_lds);
 hipError_t occupancy_plain(int kind, int stage, uint32_t lds, int *blocks_per_cu);
 hipError_t occupancy_items(uint32_t lds, int *blocks_per_cu);

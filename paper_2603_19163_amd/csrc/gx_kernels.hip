@@ -980,15 +980,17 @@ __device__ void ema_group(uint32_t *w, const unsigned long long *u, const unsign
   }
 }
 
-// Per-launch counts of one workgroup, written to its own slots (no atomics):
-// slot i of solution s at counts[i * P + s]; i = 0..5 uses and 6..11
-// improvements per operator, 12..14 uses and 15..17 improvements per k, 18
-// accepted moves.  S holds per-lane counts (summed here over the wave) or,
-// with UNIFORM, counts that are already wave totals.
+// Per-launch counts of one workgroup, added into the accumulator row of its
+// solution (row sol mod kShards): slots 0..5 uses and 6..11 improvements per
+// operator, 12..14 uses and 15..17 improvements per k, 18 accepted moves, and
+// the row minimum of the workgroup's best objective in slot 19.  S holds
+// per-lane counts (summed here over the wave) or, with UNIFORM, counts that
+// are already wave totals.  The atomics need no fence: the epoch kernel reads
+// the rows after the kernel boundary.
 constexpr int kCountSlots = 19;
 
 template <int ENC, bool UNIFORM>
-__device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LStats &S, uint32_t nacc) {
+__device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LStats &S, uint32_t nacc, int64_t bf) {
   constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
   constexpr int hi = ENC == 0 ? OOROPT : lo;
   const uint32_t lane = lane_id();
@@ -1008,75 +1010,39 @@ __device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LSta
     mine = lane == (uint32_t)(15 + q) ? vk : mine;
   }
   mine = lane == 18u ? nacc : mine;
-  if (lane < (uint32_t)kCountSlots) J->counts[(size_t)lane * J->P + sol] = mine;
+  unsigned long long *row = J->shard + (size_t)(sol & (kShards - 1)) * kEpochSlots;
+  if (lane < (uint32_t)kCountSlots && mine) atomicAdd(&row[lane], (unsigned long long)mine);
+  if (lane == (uint32_t)kCountSlots) atomicMin((long long *)&row[kCountSlots], (long long)bf);
 }
 
 }  // namespace
 
-// After each evolve launch: fold the workgroups' counts of every job into its
+// After each evolve launch: fold the accumulator rows of every job into its
 // epoch statistics, the instance best and the temperature, and at an epoch
 // boundary apply the AOS update (the kernel boundary orders it after every
-// evolve workgroup).  Grid (jobs, parts): workgroup (j, y) sums the counts of solutions y*256+t,
-// stepping by parts*256, and leaves one row of partial sums; the last
-// workgroup of the job to arrive combines the rows and updates the job.
-__global__ __launch_bounds__(256) void k_epoch(DevJob *jobs, const uint32_t *idx) {
+// evolve workgroup).  One wave per job; lane l folds and clears row l.
+static_assert(kShards == kWave, "one accumulator row per lane");
+__global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx) {
   DevJob *J = jobs + (idx ? idx[blockIdx.x] : blockIdx.x);
   const uint32_t g0 = J->g, gstop = J->g_stop;
   if (g0 >= gstop) return;
-  const uint32_t E = J->E, P = J->P, parts = gridDim.y, part = blockIdx.y;
+  const uint32_t E = J->E;
   const uint32_t g1 = min(gstop, (g0 / E + 1) * E);
   const uint32_t tid = threadIdx.x;
-  unsigned long long acc[kCountSlots];
+  unsigned long long *row = J->shard + (size_t)tid * kEpochSlots;
+  unsigned long long v[kEpochSlots];
 #pragma unroll
-  for (int i = 0; i < kCountSlots; ++i) acc[i] = 0;
-  long long mn = LLONG_MAX;
-  for (uint32_t s2 = part * 256 + tid; s2 < P; s2 += parts * 256) {
+  for (int i = 0; i < kEpochSlots; ++i) v[i] = row[i];
 #pragma unroll
-    for (int i = 0; i < kCountSlots; ++i) acc[i] += J->counts[(size_t)i * P + s2];
-    mn = min(mn, (long long)J->best_f[s2]);
-  }
-  __shared__ unsigned long long part_sum[kCountSlots][4];
-  __shared__ long long pmin[4];
-  __shared__ uint32_t last;
+  for (int i = 0; i < kCountSlots; ++i) row[i] = 0;
+  row[kCountSlots] = (unsigned long long)LLONG_MAX;
+  unsigned long long t[kCountSlots];
+#pragma unroll
+  for (int i = 0; i < kCountSlots; ++i) t[i] = wave_sum_u64(v[i]);
   // signed minimum through the unsigned order of v ^ 2^63
   constexpr unsigned long long kSign = 1ull << 63;
-#pragma unroll
-  for (int i = 0; i < kCountSlots; ++i) {
-    const unsigned long long v = wave_sum_u64(acc[i]);
-    if ((tid & 63) == 0) part_sum[i][tid >> 6] = v;
-  }
-  mn = (long long)(wave_min_key((unsigned long long)mn ^ kSign) ^ kSign);
-  if ((tid & 63) == 0) pmin[tid >> 6] = mn;
-  __syncthreads();
-  if (tid < (uint32_t)kEpochSlots) {
-    unsigned long long v;
-    if (tid < (uint32_t)kCountSlots) {
-      v = part_sum[tid][0] + part_sum[tid][1] + part_sum[tid][2] + part_sum[tid][3];
-    } else {
-      v = (unsigned long long)min(min(pmin[0], pmin[1]), min(pmin[2], pmin[3]));
-    }
-    J->epart[(size_t)part * kEpochSlots + tid] = v;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    last = atomicAdd(&J->arrive, 1u) == parts - 1;
-  }
-  __syncthreads();
-  if (!last || tid >= 64) return;
-  __threadfence();
-  // wave 0 of the last workgroup: lane y holds row y
-  unsigned long long t[kCountSlots];
-  mn = LLONG_MAX;
-#pragma unroll
-  for (int i = 0; i < kCountSlots; ++i)
-    t[i] = wave_sum_u64(tid < parts ? J->epart[(size_t)tid * kEpochSlots + i] : 0ull);
-  {
-    const long long v = tid < parts ? (long long)J->epart[(size_t)tid * kEpochSlots + kCountSlots] : LLONG_MAX;
-    mn = (long long)(wave_min_key((unsigned long long)v ^ kSign) ^ kSign);
-  }
+  const long long mn = (long long)(wave_min_key(v[kCountSlots] ^ kSign) ^ kSign);
   if (tid != 0) return;
-  J->arrive = 0;
   for (int o = 0; o < kOps; ++o) {
     J->u_op[o] += t[o];
     J->v_op[o] += t[6 + o];
@@ -1238,7 +1204,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     J->best_f[sol] = bf;
   }
   constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : 0);
-  write_counts<ENC, KIND == KTSP>(J, sol, S, nacc);
+  write_counts<ENC, KIND == KTSP>(J, sol, S, nacc, bf);
 }
 
 }  // namespace
@@ -1492,6 +1458,10 @@ __global__ void k_init_final(DevJob *jobs, int count) {
     J->w_op[i] = (uint32_t)(v < 1 ? 1 : v);
   }
   J->w_k[0] = 52429; J->w_k[1] = 9830; J->w_k[2] = 3277;
+  for (int r = 0; r < kShards; ++r) {
+    for (int i = 0; i < kCountSlots; ++i) J->shard[r * kEpochSlots + i] = 0;
+    J->shard[r * kEpochSlots + kCountSlots] = (unsigned long long)LLONG_MAX;
+  }
   for (int i = 0; i < kOps; ++i) J->u_op[i] = J->v_op[i] = 0;
   for (int i = 0; i < 3; ++i) J->u_k[i] = J->v_k[i] = 0;
   for (int i = 0; i < kOps; ++i) J->tot_u_op[i] = 0;
@@ -1635,8 +1605,8 @@ hipError_t evolve_items(DevJob *jobs, const uint2 *items, uint32_t n_items, uint
   return hipGetLastError();
 }
 
-hipError_t epoch(DevJob *jobs, const uint32_t *idx, uint32_t count, uint32_t parts, hipStream_t s) {
-  hipLaunchKernelGGL(k_epoch, dim3(count, parts), dim3(256), 0, s, jobs, idx);
+hipError_t epoch(DevJob *jobs, const uint32_t *idx, uint32_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_epoch, dim3(count), dim3(64), 0, s, jobs, idx);
   return hipGetLastError();
 }
 
