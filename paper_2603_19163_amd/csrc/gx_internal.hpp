@@ -81,7 +81,7 @@ inline uint32_t lds_bytes_for(int kind, int n, int stage) {
     case KTSP: {
       uint32_t b = tables + tours;
       if (stage == SLDS16) b += al(2 * un * un);
-      else if (stage == SLDSXY) b += al(4 * un);
+      else if (stage == SLDSXY) b += al(4 * un) + al(2 * un);   // coordinates, edge lengths
       return b;
     }
     case KQAP: return tables + tours + 2 * al(2 * un * un) + al(2 * kWave * un);

@@ -311,96 +311,66 @@ __device__ __forceinline__ int nint_dist(V2 p, V2 q) {
   return (int)((r + 1) >> 1);
 }
 
+// kEdges: the tour's edge lengths are kept in LDS (distances that are
+// computed rather than looked up)
 struct DistL16 {
+  static constexpr bool kEdges = false;
   const int16_t *d;
   int n;
   __device__ __forceinline__ int operator()(int a, int b) const { return d[a * n + b]; }
 };
 struct DistXY {   // coordinates as int16 pairs (they lie in [0, 2^14))
+  static constexpr bool kEdges = true;
   const short2 *xy;
   __device__ __forceinline__ int operator()(int a, int b) const { return nint_dist(xy[a], xy[b]); }
 };
 struct DistG16 {
+  static constexpr bool kEdges = false;
   const int16_t *__restrict__ d;
   int n;
   __device__ __forceinline__ int operator()(int a, int b) const { return d[a * n + b]; }
 };
 struct DistG32 {
+  static constexpr bool kEdges = false;
   const int32_t *__restrict__ d;
   int n;
   __device__ __forceinline__ int operator()(int a, int b) const { return d[a * n + b]; }
 };
 
 // ------------------------------------------------------------ permutation apply
-// new solution into `tmp` (the candidate tables, dead at this point, or a
-// second buffer for long permutations), then back into `cur`
-__device__ __forceinline__ void perm_apply(uint16_t *cur, uint16_t *tmp, int n, const Step *st, int k) {
-  for (int p = lane_id(); p < n; p += kWave) tmp[p] = cur[chain(st, k, p)];
+// The positions a composite move changes lie in [lo, hi], the hull of its
+// steps' ranges: [a, b] for a reversal or a swap, [min(i, q), max(i, q) + L - 1]
+// for a block move (empty when lo > hi).
+__device__ __forceinline__ void move_range(const Step *st, int k, int &lo, int &hi) {
+  lo = 0x7FFFFFFF;
+  hi = -1;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    if (m < k) {
+      const bool mv = st[m].op >= OINS;
+      lo = min(lo, mv ? min(st[m].a, st[m].b) : st[m].a);
+      hi = max(hi, mv ? max(st[m].a, st[m].b) + st[m].c - 1 : st[m].b);
+    }
+  }
+}
+
+// new solution on [lo, hi] into `tmp` (the candidate tables, dead at this
+// point, or a second buffer for long permutations), then back into `cur`
+__device__ __forceinline__ void perm_apply(uint16_t *cur, uint16_t *tmp, const Step *st, int k, int lo, int hi) {
+  for (int p = lo + (int)lane_id(); p <= hi; p += kWave) tmp[p] = cur[chain(st, k, p)];
   __syncthreads();
-  for (int p = lane_id(); p < n; p += kWave) cur[p] = tmp[p];
+  for (int p = lo + (int)lane_id(); p <= hi; p += kWave) cur[p] = tmp[p];
   __syncthreads();
+}
+__device__ __forceinline__ void perm_apply(uint16_t *cur, uint16_t *tmp, const Step *st, int k) {
+  int lo, hi;
+  move_range(st, k, lo, hi);
+  perm_apply(cur, tmp, st, k, lo, hi);
 }
 
 __device__ __forceinline__ void perm_store(const uint16_t *cur, int n, int32_t *dst) {
   for (int p = lane_id(); p < n; p += kWave) dst[p] = cur[p];
 }
-
-// ------------------------------------------------------------ TSP
-// delta of step m on the tour after steps 0..m-1 (symmetric distances)
-template <class DF>
-__device__ __forceinline__ int tsp_step(const Step *st, int m, const uint16_t *tour, int n, const DF &D) {
-  const Step s = st[m];
-  auto X = [&](int p) -> int { return tour[chain(st, m, p)]; };
-  if (s.op == O2OPT) {  // reverse [lo, hi]: edges (lo-1, lo) and (hi, hi+1) change
-    const int lo = s.a, hi = s.b;
-    if (hi - lo >= n - 1) return 0;
-    const int a = X(lo == 0 ? n - 1 : lo - 1), b = X(lo), c = X(hi), d = X(hi == n - 1 ? 0 : hi + 1);
-    return D(a, c) + D(b, d) - D(a, b) - D(c, d);
-  }
-  if (s.op == OSWAP) {  // edges lo-1, lo, hi-1, hi (positional, deduplicated)
-    const int lo = s.a, hi = s.b;
-    const bool wrap = (lo == 0 && hi == n - 1), adj = (hi == lo + 1);
-    const int vl = X(lo), vh = X(hi);
-    const int vm = X(lo == 0 ? n - 1 : lo - 1), vlp = X(lo + 1);
-    const int vhm = X(hi - 1), vhp = X(hi == n - 1 ? 0 : hi + 1);
-    int d = D(wrap ? vl : vm, vh) - D(vm, vl);
-    d += D(vh, adj ? vl : vlp) - D(vl, vlp);
-    if (!adj) d += D(vhm, vl) - D(vhm, vh);
-    if (!wrap) d += D(vl, vhp) - D(vh, vhp);
-    return d;
-  }
-  // insert / or-opt: block [i, i+L) moved to start at q; three edges change,
-  // unless the move is a rotation of the whole tour
-  const int i = s.a, q = s.b, L = s.c;
-  if (L == 0) return 0;
-  if ((q < i && q == 0 && i + L == n) || (q > i && i == 0 && q + L == n)) return 0;
-  const int xi = X(i), xe = X(i + L - 1);
-  const int xim = X(i == 0 ? n - 1 : i - 1);
-  const int xn = X(i + L == n ? 0 : i + L);
-  if (q < i) {
-    const int xqm = X(q == 0 ? n - 1 : q - 1), xq = X(q);
-    return D(xqm, xi) + D(xe, xq) + D(xim, xn) - D(xqm, xq) - D(xim, xi) - D(xe, xn);
-  }
-  const int xql = X(q + L - 1), xqn = X(q + L == n ? 0 : q + L);
-  return D(xim, xn) + D(xql, xi) + D(xe, xqn) - D(xim, xi) - D(xe, xn) - D(xql, xqn);
-}
-
-template <class DF>
-struct TspK {
-  static constexpr int ENC = 0;
-  uint16_t *cur, *nxt;
-  int n;
-  DF D;
-  __device__ __forceinline__ int64_t delta(const Step *st, int k, int64_t) const {
-    if (n < 2) return 0;
-    int d = tsp_step(st, 0, cur, n, D);
-    if (k > 1) d += tsp_step(st, 1, cur, n, D);
-    if (k > 2) d += tsp_step(st, 2, cur, n, D);
-    return d;
-  }
-  __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, n, st, k); }
-  __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
-};
 
 // ------------------------------------------------------------ QAP
 // delta = sum_{a in X} sum_b m_b F[a][b] (D[y_a][y_b] - D[x_a][x_b]), X the
@@ -436,7 +406,7 @@ struct QapK {
     }
     return d;
   }
-  __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, n, st, k); }
+  __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, st, k); }
   __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
 };
 
@@ -484,7 +454,7 @@ struct VrpK {
   __device__ __forceinline__ int64_t delta(const Step *st, int k, int64_t f) const {
     return eval(st, k) - f;
   }
-  __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, n, st, k); }
+  __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, st, k); }
   __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
 };
 
@@ -749,6 +719,65 @@ __device__ __forceinline__ int pattern_delta(const TspScratch &W, const uint16_t
   return zero ? 0 : d;
 }
 
+// Edge lengths of the tour: el[p] = D(tour[p], tour[p + 1 mod n]) for the
+// positions p in [lo, hi] taken modulo n (lo may be -1).
+template <class DF>
+__device__ __forceinline__ void edges_fill(uint16_t *el, const uint16_t *tour, int n, const DF &D, int lo, int hi) {
+  for (int p = lo + (int)lane_id(); p <= hi; p += kWave) {
+    const int q = p < 0 ? p + n : p;
+    el[q] = (uint16_t)D(tour[q], tour[q + 1 == n ? 0 : q + 1]);
+  }
+}
+
+// Delta of the first step of candidate t, on the current tour, with every
+// operator in one form: up to four new edges (position pairs q) and up to
+// four removed edges (e: positions e, e + 1), read from the edge lengths when
+// they are kept.  A reversal of [lo, hi] replaces edges lo-1 and hi; a swap
+// of lo < hi replaces lo-1, lo, hi-1 and hi, except that an adjacent swap is
+// the reversal of [lo, hi] and a swap of positions 0 and n-1 (neighbours on
+// the cycle) gives the same cycle as the reversal of [1, n-2]; a block move
+// replaces the edges before its cuts X, B and Z.  Zero patterns as in
+// pattern_delta.
+template <class DF>
+__device__ __forceinline__ int first_step_delta(const TspScratch &W, const uint16_t *tour, const uint16_t *el, int n,
+                                                const DF &D, int t) {
+  int op, a, b, L;
+  unpack_step(W, t, 0, op, a, b, L);
+  const bool mv = op >= OINS;
+  const bool adj = op == OSWAP && b - a == 1;
+  const bool cyc = op == OSWAP && !adj && a == 0 && b == n - 1;
+  const bool sw = op == OSWAP && !adj && !cyc;
+  const int lo = cyc ? 1 : a, hi = cyc ? n - 2 : b;
+  const int P = lo == 0 ? n - 1 : lo - 1, N = hi == n - 1 ? 0 : hi + 1;
+  const int X = min(a, b), Z = max(a, b) + L, B = a + (b < a ? 0 : L);
+  const int Xm = X == 0 ? n - 1 : X - 1, Zw = Z == n ? 0 : Z;
+  const bool zero = mv ? (L == 0 || (X == 0 && Z == n)) : (!sw && lo == 0 && hi == n - 1);
+  int q[8], e[4];
+  q[0] = mv ? Xm : P;
+  q[1] = mv ? B : hi;
+  q[2] = mv ? Z - 1 : (sw ? hi : lo);
+  q[3] = mv ? X : (sw ? lo + 1 : N);
+  q[4] = mv ? B - 1 : (sw ? hi - 1 : lo);
+  q[5] = mv ? Zw : lo;
+  q[6] = mv ? X : lo;
+  q[7] = mv ? X : (sw ? N : lo);
+  e[0] = mv ? Xm : P;
+  e[1] = mv ? B - 1 : (sw ? lo : hi);
+  e[2] = mv ? Z - 1 : (sw ? hi - 1 : lo);
+  e[3] = mv ? X : (sw ? hi : lo);
+  const int n_new = mv ? 3 : (sw ? 4 : 2);
+  int d = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int dn = D(tour[q[2 * i]], tour[q[2 * i + 1]]);
+    int dold;
+    if constexpr (DF::kEdges) dold = el[e[i]];
+    else dold = D(tour[e[i]], tour[e[i] + 1 == n ? 0 : e[i] + 1]);
+    d += i < n_new ? dn - dold : 0;
+  }
+  return zero ? 0 : d;
+}
+
 // Adds the wave-wide sums of per-lane byte counters (field i at bits 8i) to
 // the uniform counts u[i] and v[i]; even and odd bytes are widened to 16-bit
 // fields first so that the 64-lane sums cannot carry into a neighbour.
@@ -765,7 +794,7 @@ __device__ __forceinline__ void fold_byte_counts(uint32_t *u, uint32_t *v, uint3
 }
 
 template <class DF>
-__device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, int n, const DF &D, const TspScratch &W,
+__device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *el, int n, const DF &D, const TspScratch &W,
                                         const Uni &U, int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1,
                                         uint64_t &T, int64_t &f, int64_t &bf, LStats &S, uint32_t &nacc) {
   const uint32_t lane = lane_id();
@@ -775,18 +804,28 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, int n, con
   // into the wave-wide counts of S every 42 chunks and at the end.
   uint32_t cu_op = 0, cv_op = 0, cu_k = 0, cv_k = 0, since_fold = 0;
   const uint32_t c_last = (U.C - 1) / kChunk * kChunk;
+  if constexpr (DF::kEdges) {
+    edges_fill(el, cur, n, D, 0, n - 1);
+    __syncthreads();
+  }
   for (uint32_t g = g0; g < g1; ++g) {
     unsigned long long bk = ~0ull;
     for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
       const uint32_t cn = min((uint32_t)kChunk, U.C - c0);
       int kk[2];
       draw_chunk<0>(W, U, g, sol, c0, cn, kk);
-      // ---- pattern-step list, grouped by (operator slot, pattern step);
-      // entries [0, nq0) belong to first steps and need no position map
-      uint32_t nq = 0, nq0 = 0;
+      // ---- first steps: one per candidate, on its own lane
+      int d0[2];
 #pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        if (m == 1) nq0 = nq;
+      for (int r = 0; r < 2; ++r) {
+        const uint32_t tl = r * kWave + lane;
+        d0[r] = (tl < cn && n >= 2) ? first_step_delta(W, cur, el, n, D, (int)tl) : 0;
+      }
+      // ---- later steps of k >= 2 candidates: (candidate, step, pattern)
+      // entries, grouped by step, evaluated through the position maps
+      uint32_t nq = 0;
+#pragma unroll
+      for (int m = 1; m < 3; ++m) {
         if (!__ballot(kk[0] > m || kk[1] > m)) break;
 #pragma unroll
         for (int sub = 0; sub < 2; ++sub)
@@ -806,12 +845,7 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, int n, con
       }
       __syncthreads();
       if (n >= 2) {
-        for (uint32_t j = lane; j < nq0; j += kWave) {
-          const uint32_t e = W.lst()[j];
-          const int d = pattern_delta<false>(W, cur, n, D, (int)(e & 0xFFu), 0, (int)(e >> 10));
-          if (d) atomicAdd(&W.del()[e & 0xFFu], d);
-        }
-        for (uint32_t j = nq0 + lane; j < nq; j += kWave) {
+        for (uint32_t j = lane; j < nq; j += kWave) {
           const uint32_t e = W.lst()[j];
           const int d = pattern_delta<true>(W, cur, n, D, (int)(e & 0xFFu), (int)((e >> 8) & 3u), (int)(e >> 10));
           if (d) atomicAdd(&W.del()[e & 0xFFu], d);
@@ -823,7 +857,7 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, int n, con
       for (int r = 0; r < 2; ++r) {
         const uint32_t tl = r * kWave + lane;
         const bool valid = tl < cn;
-        const int64_t d = valid ? (int64_t)W.del()[tl] : 0;
+        const int64_t d = valid ? (int64_t)(d0[r] + W.del()[tl]) : 0;
         if (U.credit == 0 && valid) {
           const bool imp = d < 0;
 #pragma unroll
@@ -883,7 +917,15 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, int n, con
           S.vk[q] += (uint32_t)(k == q + 1 && ds < 0);
         }
       }
-      perm_apply(cur, nxt, n, st, k);
+      int lo, hi;
+      move_range(st, k, lo, hi);
+      perm_apply(cur, nxt, st, k, lo, hi);
+      if constexpr (DF::kEdges) {
+        if (lo <= hi) {
+          edges_fill(el, cur, n, D, lo - 1, hi);
+          __syncthreads();
+        }
+      }
       f += ds;
       ++nacc;
       if (f < bf) {
@@ -962,7 +1004,7 @@ __device__ __forceinline__ uint64_t udiv_q24(uint64_t num, uint64_t den) {
 
 // Eq. ema per enabled operator and per K-step, clamp to [floor, 1], normalise;
 // stagnation of the instance best resets the K-step weights (Alg. 2).
-__device__ void ema_group(uint32_t *w, const unsigned long long *u, const unsigned long long *v, uint32_t mask,
+__device__ __forceinline__ void ema_group(uint32_t *w, const unsigned long long *u, const unsigned long long *v, uint32_t mask,
                           int cnt, uint32_t A, uint32_t FL) {
   uint64_t s = 0;
   for (int i = 0; i < cnt; ++i) {
@@ -1028,6 +1070,29 @@ __global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx)
   if (g0 >= gstop) return;
   const uint32_t E = J->E;
   const uint32_t g1 = min(gstop, (g0 / E + 1) * E);
+  // the job state in registers first (one batch of loads, no store between)
+  unsigned long long u_op[kOps], v_op[kOps], tu_op[kOps], u_k[3], v_k[3], tu_k[3];
+  uint32_t w_op[kOps], w_k[3];
+#pragma unroll
+  for (int o = 0; o < kOps; ++o) {
+    u_op[o] = J->u_op[o];
+    v_op[o] = J->v_op[o];
+    tu_op[o] = J->tot_u_op[o];
+    w_op[o] = J->w_op[o];
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    u_k[q] = J->u_k[q];
+    v_k[q] = J->v_k[q];
+    tu_k[q] = J->tot_u_k[q];
+    w_k[q] = J->w_k[q];
+  }
+  const uint32_t credit = J->credit, alpha = J->alpha, op_mask = J->op_mask, aos_A = J->aos_A;
+  const uint32_t w_floor = J->w_floor, stag_limit = J->stag_limit;
+  uint32_t stag = J->stag;
+  uint64_t T = J->T;
+  int64_t inst_best = J->inst_best, epoch_ref = J->epoch_ref;
+  const unsigned long long accepted = J->accepted;
   const uint32_t tid = threadIdx.x;
   unsigned long long *row = J->shard + (size_t)tid * kEpochSlots;
   unsigned long long v[kEpochSlots];
@@ -1043,35 +1108,54 @@ __global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx)
   constexpr unsigned long long kSign = 1ull << 63;
   const long long mn = (long long)(wave_min_key(v[kCountSlots] ^ kSign) ^ kSign);
   if (tid != 0) return;
+#pragma unroll
   for (int o = 0; o < kOps; ++o) {
-    J->u_op[o] += t[o];
-    J->v_op[o] += t[6 + o];
-    if (J->credit == 0) J->tot_u_op[o] += t[o];
+    u_op[o] += t[o];
+    v_op[o] += t[6 + o];
+    if (credit == 0) tu_op[o] += t[o];
   }
+#pragma unroll
   for (int q = 0; q < 3; ++q) {
-    J->u_k[q] += t[12 + q];
-    J->v_k[q] += t[15 + q];
-    if (J->credit == 0) J->tot_u_k[q] += t[12 + q];
+    u_k[q] += t[12 + q];
+    v_k[q] += t[15 + q];
+    if (credit == 0) tu_k[q] += t[12 + q];
   }
-  J->accepted += t[18];
-  if (mn < J->inst_best) J->inst_best = mn;
-  uint64_t T = J->T;
-  for (uint32_t g = g0; g < g1; ++g) T = cool(T, J->alpha);
-  J->T = T;
+  if (mn < inst_best) inst_best = mn;
+  for (uint32_t g = g0; g < g1; ++g) T = cool(T, alpha);
   if (g1 % E == 0) {
-    ema_group(J->w_op, J->u_op, J->v_op, J->op_mask, kOps, J->aos_A, J->w_floor);
-    ema_group(J->w_k, J->u_k, J->v_k, 7u, 3, J->aos_A, J->w_floor);
-    const int64_t ib = J->inst_best;
-    if (ib < J->epoch_ref) J->stag = 0;
-    else J->stag += 1;
-    J->epoch_ref = ib;
-    if (J->stag >= J->stag_limit) {
-      J->w_k[0] = 52429; J->w_k[1] = 9830; J->w_k[2] = 3277;
-      J->stag = 0;
+    ema_group(w_op, u_op, v_op, op_mask, kOps, aos_A, w_floor);
+    ema_group(w_k, u_k, v_k, 7u, 3, aos_A, w_floor);
+    if (inst_best < epoch_ref) stag = 0;
+    else stag += 1;
+    epoch_ref = inst_best;
+    if (stag >= stag_limit) {
+      w_k[0] = 52429; w_k[1] = 9830; w_k[2] = 3277;
+      stag = 0;
     }
-    for (int i = 0; i < kOps; ++i) J->u_op[i] = J->v_op[i] = 0;
-    for (int i = 0; i < 3; ++i) J->u_k[i] = J->v_k[i] = 0;
+#pragma unroll
+    for (int i = 0; i < kOps; ++i) u_op[i] = v_op[i] = 0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) u_k[i] = v_k[i] = 0;
   }
+#pragma unroll
+  for (int o = 0; o < kOps; ++o) {
+    J->u_op[o] = u_op[o];
+    J->v_op[o] = v_op[o];
+    J->tot_u_op[o] = tu_op[o];
+    J->w_op[o] = w_op[o];
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    J->u_k[q] = u_k[q];
+    J->v_k[q] = v_k[q];
+    J->tot_u_k[q] = tu_k[q];
+    J->w_k[q] = w_k[q];
+  }
+  J->accepted = accepted + t[18];
+  J->inst_best = inst_best;
+  J->epoch_ref = epoch_ref;
+  J->stag = stag;
+  J->T = T;
   J->g = g1;
 }
 
@@ -1130,18 +1214,19 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       if constexpr (STAGE == SLDS16) {
         stage16(rest, I->d16, 2u * n * n);
         __syncthreads();
-        tsp_run(t0, t1, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        tsp_run(t0, t1, nullptr, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       } else if constexpr (STAGE == SLDSXY) {
         short2 *xy = (short2 *)rest;
+        uint16_t *el = (uint16_t *)(rest + al16(4 * n));
         for (int p = lane; p < n; p += kWave) xy[p] = make_short2((short)I->xy[2 * p], (short)I->xy[2 * p + 1]);
         __syncthreads();
-        tsp_run(t0, t1, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        tsp_run(t0, t1, el, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       } else if constexpr (STAGE == SGLB16) {
         __syncthreads();
-        tsp_run(t0, t1, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        tsp_run(t0, t1, nullptr, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       } else {
         __syncthreads();
-        tsp_run(t0, t1, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        tsp_run(t0, t1, nullptr, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       }
       perm_store(t0, n, cur_g);
     } else if constexpr (KIND == KQAP) {
