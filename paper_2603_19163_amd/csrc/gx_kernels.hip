@@ -289,10 +289,11 @@ __device__ __forceinline__ void stage16(void *dst, const void *src, uint32_t byt
 }
 
 // exact nearest-integer Euclidean distance for coordinates in [0, 2^14):
-// (isqrt(4 s) + 1) / 2 with the float estimate of the root corrected by one
-// step either way.  |dx|, |dy| < 2^14 fit int16 lanes (s = dx^2 + dy^2 is one
-// packed subtract and one 2-term dot product for int16 coordinates) and the
-// root < 2^16, so the corrections fit the full-rate 24-bit multiplier.
+// (isqrt(4 s) + 1) / 2 from a float estimate of the root that is never above
+// it and at most one below, corrected by one upward step.  |dx|, |dy| < 2^14
+// fit int16 lanes (s = dx^2 + dy^2 is one packed subtract and one 2-term dot
+// product for int16 coordinates) and the root < 2^16, so the correction fits
+// the full-rate 24-bit multiplier.
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t sq_norm(short2 p, short2 q) {   // packed difference, 2-term dot
   const s16x2 d = __builtin_bit_cast(s16x2, p) - __builtin_bit_cast(s16x2, q);
@@ -304,10 +305,13 @@ __device__ __forceinline__ uint32_t sq_norm(int2 p, int2 q) {
 }
 template <class V2>
 __device__ __forceinline__ int nint_dist(V2 p, V2 q) {
-  const uint32_t s4 = 4u * sq_norm(p, q);
-  uint32_t r = (uint32_t)__builtin_amdgcn_sqrtf((float)s4);
-  r -= (__umul24(r, r) > s4);
-  r += (__umul24(r + 1, r + 1) <= s4);
+  const uint32_t s = sq_norm(p, q), s4 = 4u * s;
+  // y = 2 sqrt(s) (1 - 2^-19) rounded: the float conversion, root and product
+  // err by < 4 * 2^-24 relative, so y < 2 sqrt(s) and y > 2 sqrt(s) - 0.1
+  // (2 sqrt(s) < 2^16): floor(y) is isqrt(4 s) or one below it
+  const float y = __builtin_amdgcn_sqrtf((float)s) * 1.99999618530273438f;
+  const uint32_t r0 = (uint32_t)y;
+  const uint32_t r = r0 + (__umul24(r0 + 1, r0 + 1) <= s4);
   return (int)((r + 1) >> 1);
 }
 
