@@ -90,24 +90,18 @@ __device__ __forceinline__ Step make_step(int op, uint32_t r1, uint32_t r2, uint
   s.c = 0;
   const uint32_t n = U.n;
   if (ENC == 0) {
-    if (n < 2) {
-      s.a = s.b = 0;
-    } else if (op == O2OPT || op == OSWAP) {
-      const uint32_t i = rmap(r1, n);
-      uint32_t j = rmap(r2, n - 1);
-      j += (j >= i);
-      s.a = (int)min(i, j);
-      s.b = (int)max(i, j);
-    } else {
-      uint32_t L = (op == OINS) ? 1u : 2u + rmap(r3, 2u);
-      L = min(L, n - 1);
-      const uint32_t i = rmap(r1, n - L + 1);
-      uint32_t q = rmap(r2, n - L);
-      q += (q >= i);
-      s.a = (int)i;
-      s.b = (int)q;
-      s.c = (int)L;
-    }
+    // 2-opt / swap: two distinct positions i, j of n, ordered; insert /
+    // or-opt: block length L, start i of n - L + 1, target q != i of n - L + 1
+    // (one code path for both, selecting the ranges)
+    const bool rv = op < OINS;
+    const uint32_t L = rv ? 0u : min((op == OINS) ? 1u : 2u + rmap(r3, 2u), n - 1);
+    const uint32_t i = rmap(r1, rv ? n : n - L + 1);
+    uint32_t j = rmap(r2, rv ? n - 1 : n - L);
+    j += (j >= i);
+    s.a = (int)(rv ? min(i, j) : i);
+    s.b = (int)(rv ? max(i, j) : j);
+    s.c = (int)L;
+    if (n < 2) s.a = s.b = s.c = 0;
   } else if (ENC == 1) {
     s.a = (int)rmap(r1, n);
     s.b = 0;
@@ -579,29 +573,37 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
 // number of pattern steps of an operator
 __device__ __forceinline__ int n_patterns(int op, int a, int b) { return (op == OSWAP && b - a >= 2) ? 2 : 1; }
 
-// Position map of one pattern step as two adjacent pieces:
-// p in [s1, e1) -> m1 * p + o1, p in [e1, e2) -> p + o2, otherwise p.
-struct PMap {
-  int s1, e1, e2, m1, o1, o2;
+// Position map of one step (the element at position p after the step was at
+// position map(p) before it), as up to three pieces inside [s1, s1 + len):
+// p < e1 -> o1, p < e1b -> o2, else -o1 added to p, or to -p for a reversal
+// (neg = -1); positions outside the range are fixed.  Only a swap reaches the
+// third piece.
+//   reversal of [a, b]:  p -> a + b - p;
+//   swap of a < b:        a -> b, b -> a;
+//   block [i, i+L) moved to start at q: [q, q+L) -> +(i-q) and [q+L, i+L)
+//   -> -L when q < i; [i, q) -> +L and [q, q+L) -> +(i-q) when q > i.
+struct SMap {
+  int s1, len, e1, e1b, neg, o1, o2;
 };
 
-__device__ __forceinline__ PMap pmap(int op, int a, int b, int L) {
-  // block [a, a+L) moved to start at b, or reversal of [a, b]
-  const bool mv = op >= OINS, qlt = b < a;
-  PMap M;
+__device__ __forceinline__ SMap smap(int op, int a, int b, int L) {
+  const bool mv = op >= OINS, sw = op == OSWAP, qlt = b < a;
+  SMap M;
   M.s1 = mv ? min(a, b) : a;
-  M.e1 = mv ? (qlt ? b + L : b) : b + 1;
-  M.e2 = mv ? max(a, b) + L : b + 1;
-  M.m1 = mv ? 1 : -1;
-  M.o1 = mv ? (qlt ? a - b : L) : a + b;
+  M.len = (mv ? max(a, b) + L : b + 1) - M.s1;
+  M.e1 = mv ? (qlt ? b + L : b) : (sw ? a + 1 : b + 1);
+  M.e1b = mv ? max(a, b) + L : b;
+  M.neg = (mv || sw) ? 0 : -1;
+  M.o1 = mv ? (qlt ? a - b : L) : (sw ? b - a : a + b);
   M.o2 = mv ? (qlt ? -L : a - b) : 0;
   return M;
 }
 
-__device__ __forceinline__ int papply(const PMap &M, int p) {
-  const bool in = (uint32_t)(p - M.s1) < (uint32_t)(M.e2 - M.s1);
-  const int v = p < M.e1 ? __mul24(M.m1, p) + M.o1 : p + M.o2;
-  return in ? v : p;
+__device__ __forceinline__ int sapply(const SMap &M, int p) {
+  const int t = (p ^ M.neg) - M.neg;
+  const int off = p < M.e1 ? M.o1 : (p < M.e1b ? M.o2 : -M.o1);
+  const bool in = (uint32_t)(p - M.s1) < (uint32_t)M.len;
+  return in ? t + off : p;
 }
 
 __device__ __forceinline__ void unpack_step(const TspScratch &W, int t, int m, int &op, int &a, int &b, int &L) {
@@ -672,14 +674,6 @@ __device__ __forceinline__ Step load_step(const TspScratch &W, int t, int m) {
   return st;
 }
 
-// position before a step of the element at position p after it: a swap
-// exchanges a and b; a reversal or a block move is the map of its pattern
-__device__ __forceinline__ int step_map(int op, int a, int b, int L, int p) {
-  const int pm = papply(pmap(op, a, b, L), p);
-  const int sw = p == a ? b : (p == b ? a : p);
-  return op == OSWAP ? sw : pm;
-}
-
 // delta of pattern step `sub` of operator m of candidate t, on the tour after
 // all earlier steps of that candidate (MAPPED: m >= 1, whose read positions
 // are mapped back through steps m-1 .. 0)
@@ -712,8 +706,9 @@ __device__ __forceinline__ int pattern_delta(const TspScratch &W, const uint16_t
     for (int mm = m - 1; mm >= 0; --mm) {
       int o2, a2, b2, L2;
       unpack_step(W, t, mm, o2, a2, b2, L2);
+      const SMap M = smap(o2, a2, b2, L2);
 #pragma unroll
-      for (int i = 0; i < 6; ++i) r[i] = step_map(o2, a2, b2, L2, r[i]);
+      for (int i = 0; i < 6; ++i) r[i] = sapply(M, r[i]);
     }
   }
   int v[6];
@@ -734,14 +729,19 @@ __device__ __forceinline__ void edges_fill(uint16_t *el, const uint16_t *tour, i
 }
 
 // Delta of the first step of candidate t, on the current tour, with every
-// operator in one form: up to four new edges (position pairs q) and up to
-// four removed edges (e: positions e, e + 1), read from the edge lengths when
-// they are kept.  A reversal of [lo, hi] replaces edges lo-1 and hi; a swap
-// of lo < hi replaces lo-1, lo, hi-1 and hi, except that an adjacent swap is
-// the reversal of [lo, hi] and a swap of positions 0 and n-1 (neighbours on
-// the cycle) gives the same cycle as the reversal of [1, n-2]; a block move
-// replaces the edges before its cuts X, B and Z.  Zero patterns as in
-// pattern_delta.
+// operator in one form over six tour positions u0..u5: new edges
+// (u0,u1), (u1,u2) or (u2,u5), (u3,u4), (u4,u5) and removed edges e0..e3
+// (positions e, e + 1), read from the edge lengths when they are kept.
+//   swap lo < hi:  u = (lo-1, hi, lo+1, hi-1, lo, hi+1), all four pairs,
+//                  removed edges lo-1, lo, hi-1, hi;
+//   reversal of [lo, hi]: the same positions, pairs 0 and 3, removed edges
+//                  lo-1 and hi (an adjacent swap is the reversal of [lo, hi];
+//                  a swap of positions 0 and n-1, neighbours on the cycle,
+//                  gives the same cycle as the reversal of [1, n-2]);
+//   block move with cuts X, B, Z (see pattern_delta):
+//                  u = (X-1, B, B-1, Z-1, X, Z), pairs 0, 1 (as (u2,u5)) and 2,
+//                  removed edges X-1, B-1, Z-1.
+// Zero patterns as in pattern_delta.
 template <class DF>
 __device__ __forceinline__ int first_step_delta(const TspScratch &W, const uint16_t *tour, const uint16_t *el, int n,
                                                 const DF &D, int t) {
@@ -756,29 +756,35 @@ __device__ __forceinline__ int first_step_delta(const TspScratch &W, const uint1
   const int X = min(a, b), Z = max(a, b) + L, B = a + (b < a ? 0 : L);
   const int Xm = X == 0 ? n - 1 : X - 1, Zw = Z == n ? 0 : Z;
   const bool zero = mv ? (L == 0 || (X == 0 && Z == n)) : (!sw && lo == 0 && hi == n - 1);
-  int q[8], e[4];
-  q[0] = mv ? Xm : P;
-  q[1] = mv ? B : hi;
-  q[2] = mv ? Z - 1 : (sw ? hi : lo);
-  q[3] = mv ? X : (sw ? lo + 1 : N);
-  q[4] = mv ? B - 1 : (sw ? hi - 1 : lo);
-  q[5] = mv ? Zw : lo;
-  q[6] = mv ? X : lo;
-  q[7] = mv ? X : (sw ? N : lo);
-  e[0] = mv ? Xm : P;
-  e[1] = mv ? B - 1 : (sw ? lo : hi);
-  e[2] = mv ? Z - 1 : (sw ? hi - 1 : lo);
-  e[3] = mv ? X : (sw ? hi : lo);
-  const int n_new = mv ? 3 : (sw ? 4 : 2);
-  int d = 0;
+  int u[6], e[4];
+  u[0] = mv ? Xm : P;
+  u[1] = mv ? B : hi;
+  u[2] = mv ? B - 1 : lo + 1;
+  u[3] = mv ? Z - 1 : hi - 1;
+  u[4] = mv ? X : lo;
+  u[5] = mv ? Zw : N;
+  e[0] = u[0];
+  e[1] = mv ? B - 1 : lo;
+  e[2] = mv ? Z - 1 : hi - 1;
+  e[3] = hi;
+  int c[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) c[i] = tour[u[i]];
+  const int d0 = D(c[0], c[1]);
+  const int d1 = D(mv ? c[2] : c[1], mv ? c[5] : c[2]);
+  const int d2 = D(c[3], c[4]);
+  const int d3 = D(c[4], c[5]);
+  int o[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int dn = D(tour[q[2 * i]], tour[q[2 * i + 1]]);
-    int dold;
-    if constexpr (DF::kEdges) dold = el[e[i]];
-    else dold = D(tour[e[i]], tour[e[i] + 1 == n ? 0 : e[i] + 1]);
-    d += i < n_new ? dn - dold : 0;
+    if constexpr (DF::kEdges) o[i] = el[e[i]];
+    else o[i] = D(tour[e[i]], tour[e[i] + 1 == n ? 0 : e[i] + 1]);
   }
+  // pairs used: swap all, reversal 0 and 3, block move 0, 1, 2
+  const bool mid = mv || sw, last = !mv;
+  int d = d0 - o[0];
+  d += mid ? d1 - o[1] + d2 - o[2] : 0;
+  d += last ? d3 - o[3] : 0;
   return zero ? 0 : d;
 }
 
