@@ -283,11 +283,12 @@ __device__ __forceinline__ void stage16(void *dst, const void *src, uint32_t byt
 }
 
 // exact nearest-integer Euclidean distance for coordinates in [0, 2^14):
-// (isqrt(4 s) + 1) / 2 from a float estimate of the root that is never above
-// it and at most one below, corrected by one upward step.  |dx|, |dy| < 2^14
-// fit int16 lanes (s = dx^2 + dy^2 is one packed subtract and one 2-term dot
-// product for int16 coordinates) and the root < 2^16, so the correction fits
-// the full-rate 24-bit multiplier.
+// nint(sqrt(s)) = floor(sqrt(s) + 1/2), which equals (isqrt(4 s) + 1) / 2, is
+// the k with k(k-1) < s <= k(k+1).  A float estimate that is never above
+// sqrt(s) + 1/2 and at most 0.05 below it gives k or k - 1, and one test
+// against k(k+1) decides.  |dx|, |dy| < 2^14 fit int16 lanes (s = dx^2 + dy^2
+// is one packed subtract and one 2-term dot product for int16 coordinates) and
+// k < 2^15, so the test fits the full-rate 24-bit multiplier.
 typedef short s16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t sq_norm(short2 p, short2 q) {   // packed difference, 2-term dot
   const s16x2 d = __builtin_bit_cast(s16x2, p) - __builtin_bit_cast(s16x2, q);
@@ -299,14 +300,13 @@ __device__ __forceinline__ uint32_t sq_norm(int2 p, int2 q) {
 }
 template <class V2>
 __device__ __forceinline__ int nint_dist(V2 p, V2 q) {
-  const uint32_t s = sq_norm(p, q), s4 = 4u * s;
-  // y = 2 sqrt(s) (1 - 2^-19) rounded: the float conversion, root and product
-  // err by < 4 * 2^-24 relative, so y < 2 sqrt(s) and y > 2 sqrt(s) - 0.1
-  // (2 sqrt(s) < 2^16): floor(y) is isqrt(4 s) or one below it
-  const float y = __builtin_amdgcn_sqrtf((float)s) * 1.99999618530273438f;
-  const uint32_t r0 = (uint32_t)y;
-  const uint32_t r = r0 + (__umul24(r0 + 1, r0 + 1) <= s4);
-  return (int)((r + 1) >> 1);
+  const uint32_t s = sq_norm(p, q);
+  // sqrt(s) (1 - 2^-19) + 1/2 in float: the conversion, root and fused
+  // multiply-add err by < 4 * 2^-24 relative, far less than the 2^-19 shrink
+  // (k <= 23170, so the shrink stays below 0.05)
+  const float y = __builtin_fmaf(__builtin_amdgcn_sqrtf((float)s), 0.99999809265136719f, 0.5f);
+  const uint32_t k0 = (uint32_t)y;
+  return (int)(k0 + (s > __umul24(k0, k0) + k0));
 }
 
 // kEdges: the tour's edge lengths are kept in LDS (distances that are
