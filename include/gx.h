@@ -222,6 +222,8 @@ typedef struct {
   uint64_t hbm_budget_bytes;   /* arena for resident requests [1 GiB] */
   uint32_t max_resident;       /* requests resident at once [1024] */
   uint32_t max_lds_bytes;      /* LDS per workgroup a request may need [65536] */
+  uint32_t max_items;          /* solutions (workgroups) resident at once; further
+                                  requests wait in arrival order [40 x CUs] */
 } gx_server_cfg;
 typedef struct {
   uint64_t submitted, admitted, completed, cancelled;

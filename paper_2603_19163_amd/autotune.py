@@ -29,13 +29,17 @@ def _rate(ctx, inst_handle, params, generations):
         gx.gx_job_free(ctx, job)
 
 
-def tune_tsp_staging(ctx, inst, params, generations: int = 200, stages=STAGES_TSP):
-    """Time every TSP staging the instance supports; returns (best stage, {stage: evals/s})."""
+def tune_tsp_staging(ctx, inst, params, generations: int = 200, stages=STAGES_TSP, population: int = 0):
+    """Time every TSP staging the instance supports with the device full of
+    this instance's workgroups (population, default 20 per CU: a batch or a
+    server keeps the device that full, and a staging's LDS footprint decides
+    how many workgroups a CU holds); returns (best stage, {stage: evals/s})."""
     h = gx.gx_instance_upload(ctx, inst)
     table = {}
+    P = population or 20 * gx.gx_get_device_info(ctx)["cus"]
     try:
         for st in stages:
-            p = params.with_(staging=st, generations=generations)
+            p = params.with_(staging=st, generations=generations, population=P)
             try:
                 table[st] = _rate(ctx, h, p, generations)
             except gx.GxError as e:
@@ -55,7 +59,7 @@ def bucket_of(kind: int, n: int) -> str:
     return f"{kind}:big"
 
 
-def tune_buckets(ctx, samples, params_for, generations: int = 100, cache: bool = True):
+def tune_buckets(ctx, samples, params_for, generations: int = 20, cache: bool = True):
     """samples: {bucket: representative instance}; params_for(inst) -> Params.
     Returns {bucket: staging} for TSP buckets (other kinds have one staging)."""
     known = {}
@@ -80,9 +84,10 @@ def tune_buckets(ctx, samples, params_for, generations: int = 100, cache: bool =
     return out
 
 
-def fill_population(ctx, count: int, blocks_per_cu: int = 8, p_min: int = 1, p_max: int = 64) -> int:
+def fill_population(ctx, count: int, blocks_per_cu: int = 20, p_min: int = 1, p_max: int = 64) -> int:
     """Population per instance so that `count` instances fill the device with
-    about `blocks_per_cu` resident 64-lane workgroups per CU."""
+    about `blocks_per_cu` resident 64-lane workgroups per CU (the evolve
+    kernels hold 20 per CU at their register and LDS use)."""
     cus = gx.gx_get_device_info(ctx)["cus"]
     want = cus * blocks_per_cu
     p = max(p_min, min(p_max, (want + count - 1) // count))

@@ -16,10 +16,21 @@
 
 using namespace gx;
 
+// Side streams for the concurrent launches of one epoch's work-item groups:
+// the groups fork from the main stream through one event and join back
+// through one event each (also inside a captured graph).
+constexpr int kMaxGroups = 8;
+struct Fan {
+  hipStream_t side[kMaxGroups - 1] = {};
+  hipEvent_t fork = nullptr, join[kMaxGroups - 1] = {};
+  bool ready = false;
+};
+
 struct gx_ctx {
   int dev = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  Fan fan;
   std::string err;
   gx_device_info info{};
   uint32_t max_lds = 0;
@@ -57,6 +68,7 @@ struct gx_batch {
   DevJob *jobs_d = nullptr;
   void *arena = nullptr;
   uint2 *items = nullptr;
+  uint32_t *next = nullptr;   // work-item counters, one per group
 };
 
 namespace {
@@ -431,9 +443,13 @@ InstInfo info_of(const gx_instance *in) {
 uint32_t resolve_stage(const InstInfo &ii, uint32_t req) {
   if (ii.h.kind != KTSP) return 0;
   if (req != SAUTO) return req;
+  // Coordinates in LDS keep the footprint at 6n + 2n bytes, so a CU holds
+  // as many workgroups as its registers allow; an int16 matrix in LDS
+  // (2n^2 bytes) cuts that to a few per CU at n ~ 100, which costs more than
+  // the exact distance recomputation saves.
   const int n = ii.h.n;
-  if (n <= 128 && ii.has_d16) return SLDS16;
   if (ii.has_xy) return SLDSXY;
+  if (n <= 128 && ii.has_d16) return SLDS16;
   if (ii.has_d16) return SGLB16;
   return SGLB32;
 }
@@ -548,6 +564,92 @@ bool graphs_disabled() {
   return e && *e && *e != '0';
 }
 
+bool fan_disabled() {
+  const char *e = getenv("GX_SERIAL_GROUPS");
+  return e && *e && *e != '0';
+}
+
+hipError_t fan_init(Fan &f) {
+  if (f.ready) return hipSuccess;
+  hipError_t e = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming);
+  for (int g = 0; e == hipSuccess && g < kMaxGroups - 1; ++g) {
+    e = hipStreamCreateWithFlags(&f.side[g], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&f.join[g], hipEventDisableTiming);
+  }
+  f.ready = e == hipSuccess;
+  return e;
+}
+
+void fan_free(Fan &f) {
+  for (int g = 0; g < kMaxGroups - 1; ++g) {
+    if (f.side[g]) (void)hipStreamDestroy(f.side[g]);
+    if (f.join[g]) (void)hipEventDestroy(f.join[g]);
+    f.side[g] = nullptr;
+    f.join[g] = nullptr;
+  }
+  if (f.fork) (void)hipEventDestroy(f.fork);
+  f.fork = nullptr;
+  f.ready = false;
+}
+
+// The work items of one epoch launch, grouped by (kind, staging): every group
+// is one launch of that group's kernel (its own registers and LDS), items
+// heaviest first within the group.
+struct Group {
+  int kind, stage;
+  uint32_t off, count, lds, grid;
+};
+struct ItemRec {
+  int kind, stage;
+  uint32_t lds;
+  double cost;
+  uint2 item;
+};
+
+gx_status make_groups(gx_ctx *c, std::vector<ItemRec> &recs, uint2 *items, std::vector<Group> &gs) {
+  std::stable_sort(recs.begin(), recs.end(), [](const ItemRec &x, const ItemRec &y) {
+    if (x.kind != y.kind) return x.kind < y.kind;
+    if (x.stage != y.stage) return x.stage < y.stage;
+    return x.cost > y.cost;
+  });
+  gs.clear();
+  for (size_t k = 0; k < recs.size(); ++k) {
+    const ItemRec &r = recs[k];
+    items[k] = r.item;
+    if (gs.empty() || gs.back().kind != r.kind || gs.back().stage != r.stage) {
+      if ((int)gs.size() == kMaxGroups) return fail(c, GX_E_UNSUPPORTED, "more than %d work-item groups", kMaxGroups);
+      gs.push_back(Group{r.kind, r.stage, (uint32_t)k, 0, 16, 0});
+    }
+    gs.back().count++;
+    gs.back().lds = std::max(gs.back().lds, r.lds);
+  }
+  for (Group &g : gs) {
+    int occ = 0;
+    HIPCHK(c, gxk::occupancy_group(g.kind, g.stage, g.lds, &occ));
+    g.grid = (uint32_t)std::min<size_t>(g.count, (size_t)c->info.cus * (size_t)std::max(1, occ));
+  }
+  return GX_OK;
+}
+
+// One epoch chunk of every group: concurrent launches on the side streams
+// (or one after the other on s), then the epoch kernel, which also clears the
+// groups' work-item counters.
+hipError_t launch_groups(const Fan &f, const std::vector<Group> &gs, DevJob *jobs, const uint2 *items,
+                         uint32_t *next, const uint32_t *idx, uint32_t njobs, hipStream_t s) {
+  const bool fan = gs.size() > 1 && f.ready && !fan_disabled();
+  hipError_t e = fan ? hipEventRecord(f.fork, s) : hipSuccess;
+  for (size_t g = 0; e == hipSuccess && g < gs.size(); ++g) {
+    hipStream_t sg = (fan && g > 0) ? f.side[g - 1] : s;
+    if (fan && g > 0) e = hipStreamWaitEvent(sg, f.fork, 0);
+    if (e == hipSuccess)
+      e = gxk::evolve_group(gs[g].kind, gs[g].stage, jobs, items + gs[g].off, gs[g].count, next + g, gs[g].grid,
+                            gs[g].lds, sg);
+    if (e == hipSuccess && fan && g > 0) e = hipEventRecord(f.join[g - 1], sg);
+  }
+  for (size_t g = 1; e == hipSuccess && fan && g < gs.size(); ++g) e = hipStreamWaitEvent(s, f.join[g - 1], 0);
+  return e != hipSuccess ? e : gxk::epoch(jobs, idx, njobs, next, (uint32_t)gs.size(), s);
+}
+
 // Enqueue L identical evolve launches; a run of 64 is captured once into a
 // graph and replayed (every launch reads its generation window from the job).
 template <class Launch>
@@ -650,7 +752,7 @@ gx_status gx_job_advance(gx_ctx *c, gx_job *j, uint32_t ng) {
   hipStream_t s = c->stream;
   gx_status st = enqueue_launches(c, j, L, [=]() {
     const hipError_t e = gxk::evolve_plain(dj, kind, stage, P, lds, s);
-    return e != hipSuccess ? e : gxk::epoch(dj, nullptr, 1, s);
+    return e != hipSuccess ? e : gxk::epoch(dj, nullptr, 1, nullptr, 0, s);
   });
   if (st) return st;
   HIPCHK(c, hipEventRecord(j->ev1, c->stream));
@@ -761,6 +863,7 @@ static void release_batch(gx_batch *b) {
   (void)hipFree(b->arena);
   (void)hipFree(b->jobs_d);
   (void)hipFree(b->items);
+  (void)hipFree(b->next);
   delete b;
 }
 
@@ -783,6 +886,7 @@ gx_status gx_destroy(gx_ctx *c) {
   (void)hipStreamSynchronize(c->stream);
   while (!c->jobs.empty()) gx_job_free(c, c->jobs.back());
   while (!c->insts.empty()) gx_instance_free(c, c->insts.back());
+  fan_free(c->fan);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
   return GX_OK;
@@ -795,7 +899,7 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
   std::vector<DevJob> hj((size_t)count);
   std::vector<size_t> off((size_t)count);
   size_t total = 0;
-  uint32_t max_q = 0, max_lds = 16, L = 0;
+  uint32_t max_q = 0, L = 0;
   int max_n = 1, max_mats = 0;
   size_t n_items = 0;
   for (int i = 0; i < count; ++i) {
@@ -815,7 +919,6 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
     off[i] = total;
     total += job_array_bytes(n, P, Q);
     max_q = std::max(max_q, hj[i].Q);
-    max_lds = std::max(max_lds, hj[i].lds_bytes);
     max_n = std::max(max_n, in->h.n);
     max_mats = std::max(max_mats, heur_mats_of(in->h.kind));
     L = std::max(L, chunks_between(0, hj[i].G, hj[i].E));
@@ -827,6 +930,7 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
     (void)hipFree(b->arena);
     (void)hipFree(b->jobs_d);
     (void)hipFree(b->items);
+    (void)hipFree(b->next);
     delete b;
     return s;
   };
@@ -835,9 +939,9 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
   b->arena = arena;
   if (hipMalloc((void **)&b->jobs_d, sizeof(DevJob) * count) != hipSuccess)
     return bail(fail(c, GX_E_NOMEM, "batch job table"));
-  // work items, heaviest solutions first so that the tail of a launch is short
-  std::vector<std::pair<double, uint2>> it;
-  it.reserve(n_items);
+  // work items, grouped by kind and staging, heaviest solutions first
+  std::vector<ItemRec> recs;
+  recs.reserve(n_items);
   for (int i = 0; i < count; ++i) {
     const DevInst &ih = insts[i]->h;
     const double n = ih.n;
@@ -845,21 +949,23 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
     if (ih.kind == KQAP) cost = 4.0 * n * n / 3.0;
     else if (ih.kind == KVRP) cost = 8.0 * n;
     cost *= (double)hj[i].C * (double)hj[i].G;
-    for (uint32_t s2 = 0; s2 < hj[i].P; ++s2) it.push_back({-cost, make_uint2((uint32_t)i, s2)});
+    for (uint32_t s2 = 0; s2 < hj[i].P; ++s2)
+      recs.push_back(ItemRec{ih.kind, (int)hj[i].stage, hj[i].lds_bytes, cost, make_uint2((uint32_t)i, s2)});
   }
-  std::stable_sort(it.begin(), it.end(), [](const auto &x, const auto &y) { return x.first < y.first; });
   std::vector<uint2> items(n_items);
-  for (size_t k = 0; k < n_items; ++k) items[k] = it[k].second;
-  if (hipMalloc((void **)&b->items, sizeof(uint2) * n_items) != hipSuccess)
+  std::vector<Group> groups;
+  gx_status gst = make_groups(c, recs, items.data(), groups);
+  if (gst) return bail(gst);
+  if (hipMalloc((void **)&b->items, sizeof(uint2) * n_items) != hipSuccess ||
+      hipMalloc((void **)&b->next, sizeof(uint32_t) * kMaxGroups) != hipSuccess)
     return bail(fail(c, GX_E_NOMEM, "batch work items"));
+  HIPCHK(c, hipMemsetAsync(b->next, 0, sizeof(uint32_t) * kMaxGroups, c->stream));
+  if (groups.size() > 1) HIPCHK(c, fan_init(c->fan));
   for (int i = 0; i < count; ++i) carve_job(hj[i], arena + off[i], (size_t)insts[i]->h.n);
   HIPCHK(c, hipMemcpy(b->jobs_d, hj.data(), sizeof(DevJob) * count, hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(b->items, items.data(), sizeof(uint2) * n_items, hipMemcpyHostToDevice));
   HIPCHK(c, gxk::init_jobs(b->jobs_d, count, max_q, max_n, max_mats, c->stream));
   HIPCHK(c, gxk::set_stop(b->jobs_d, count, 0, 1, c->stream));
-  int occ = 0;
-  HIPCHK(c, gxk::occupancy_items(max_lds, &occ));
-  const uint32_t grid = (uint32_t)std::min<size_t>(n_items, (size_t)c->info.cus * std::max(1, occ));
   // handles
   std::vector<gx_job *> made;
   for (int i = 0; i < count; ++i) {
@@ -879,12 +985,12 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
   HIPCHK(c, hipEventRecord(lead->ev0, c->stream));
   DevJob *jd = b->jobs_d;
   const uint2 *itd = b->items;
-  const uint32_t ni = (uint32_t)n_items, lds = max_lds;
+  uint32_t *next = b->next;
   hipStream_t s = c->stream;
   const uint32_t njobs = (uint32_t)count;
+  const Fan *fan = &c->fan;
   gx_status st = enqueue_launches(c, lead, L, [=]() {
-    const hipError_t e = gxk::evolve_items(jd, itd, ni, grid, lds, s);
-    return e != hipSuccess ? e : gxk::epoch(jd, nullptr, njobs, s);
+    return launch_groups(*fan, groups, jd, itd, next, nullptr, njobs, s);
   });
   if (st) {
     for (gx_job *j : made) delete j;
@@ -977,7 +1083,7 @@ struct SrvReq {
   Prepared pr;
   DevJob hj{};
   size_t inst_bytes = 0, bytes = 0, off = 0, pin_off = 0;
-  int slot = -1, n = 0;
+  int slot = -1, n = 0, kind = 0;
   uint32_t g = 0;
   hipEvent_t ev = nullptr;
   std::vector<int32_t> sol;
@@ -1005,6 +1111,10 @@ struct gx_server {
   uint32_t *slots_h[2] = {nullptr, nullptr};
   hipEvent_t items_ev[2] = {nullptr, nullptr};
   size_t items_cap = 0;
+  uint32_t *next = nullptr;   // work-item counters, one per group
+  uint64_t resident_items = 0;   // solutions of the resident requests (guarded by mu)
+  Fan fan;
+  gx_ctx gctx;                // device facts and messages of the scheduler thread
   char *arena_d = nullptr;
   Arena arena;
   char *pin = nullptr;
@@ -1057,6 +1167,7 @@ void srv_release(gx_server *S, SrvReq *r) {   // caller holds mu
   if (r->pin_off != (size_t)-1) S->pin_arena.release(r->pin_off, 4 * (size_t)r->n + 8);
   S->slots[r->slot] = nullptr;
   S->free_slots.push_back(r->slot);
+  S->resident_items -= r->hj.P;
   r->slot = -1;
 }
 
@@ -1065,6 +1176,8 @@ void server_loop(gx_server *S) {
   int buf = 0;
   uint64_t busy_since = 0;
   std::vector<SrvReq *> admitted, active;
+  std::vector<ItemRec> recs;
+  std::vector<Group> groups;
   while (!S->stop.load()) {
     admitted.clear();
     bool any_resident = false;
@@ -1072,6 +1185,9 @@ void server_loop(gx_server *S) {
       std::unique_lock<std::mutex> lk(S->mu);
       for (auto it = S->pending.begin(); it != S->pending.end() && !S->free_slots.empty();) {
         SrvReq *r = *it;
+        // enough solutions resident to fill the device: later requests queue
+        // in arrival order instead of slowing down every resident one
+        if (S->resident_items + r->hj.P > S->cfg.max_items && S->resident_items > 0) break;
         size_t off = 0, poff = 0;
         if (!S->arena.alloc(r->bytes, &off)) {
           ++it;   // does not fit now; smaller requests behind it may
@@ -1088,6 +1204,7 @@ void server_loop(gx_server *S) {
         S->free_slots.pop_back();
         S->slots[r->slot] = r;
         r->state = RQ_RESIDENT;
+        S->resident_items += r->hj.P;
         S->st.admitted++;
         admitted.push_back(r);
         it = S->pending.erase(it);
@@ -1108,30 +1225,26 @@ void server_loop(gx_server *S) {
       if (srv_stage(S, r) != GX_OK) r->cancel = true;   // staging failure: reported as cancelled
     // ---- one quantum: every resident running request advances one epoch chunk
     active.clear();
-    uint32_t max_lds = 16;
     size_t n_items = 0;
     for (SrvReq *r : S->slots)
       if (r && r->state == RQ_RESIDENT && !r->cancel && r->g < r->hj.G) {
         active.push_back(r);
-        max_lds = std::max(max_lds, r->hj.lds_bytes);
         n_items += r->hj.P;
       }
     if (!active.empty() && srv_grow_items(S, n_items) == GX_OK) {
-      std::stable_sort(active.begin(), active.end(), [](SrvReq *a, SrvReq *b) { return a->cost > b->cost; });
       (void)hipEventSynchronize(S->items_ev[buf]);
-      uint2 *h = S->items_h[buf];
-      size_t k = 0;
+      recs.clear();
       for (SrvReq *r : active)
-        for (uint32_t sl = 0; sl < r->hj.P; ++sl) h[k++] = make_uint2((uint32_t)r->slot, sl);
-      int occ = 1;
-      (void)gxk::occupancy_items(max_lds, &occ);
-      const uint32_t grid = (uint32_t)std::min<size_t>(n_items, (size_t)S->c->info.cus * std::max(1, occ));
+        for (uint32_t sl = 0; sl < r->hj.P; ++sl)
+          recs.push_back(ItemRec{r->kind, (int)r->hj.stage, r->hj.lds_bytes, r->cost, make_uint2((uint32_t)r->slot, sl)});
+      uint2 *h = S->items_h[buf];
+      if (make_groups(&S->gctx, recs, h, groups) != GX_OK) groups.clear();
       uint32_t *sl = S->slots_h[buf];
       for (size_t a = 0; a < active.size(); ++a) sl[a] = (uint32_t)active[a]->slot;
       (void)hipMemcpyAsync(S->items_d[buf], h, n_items * sizeof(uint2), hipMemcpyHostToDevice, S->s);
       (void)hipMemcpyAsync(S->slots_d[buf], sl, active.size() * sizeof(uint32_t), hipMemcpyHostToDevice, S->s);
-      (void)gxk::evolve_items(S->jobs_d, S->items_d[buf], (uint32_t)n_items, grid, max_lds, S->s);
-      (void)gxk::epoch(S->jobs_d, S->slots_d[buf], (uint32_t)active.size(), S->s);
+      (void)launch_groups(S->fan, groups, S->jobs_d, S->items_d[buf], S->next, S->slots_d[buf],
+                          (uint32_t)active.size(), S->s);
       (void)hipEventRecord(S->items_ev[buf], S->s);
       buf ^= 1;
       uint64_t evals = 0;
@@ -1200,15 +1313,25 @@ gx_status gx_server_create(gx_ctx *c, const gx_server_cfg *cfg, gx_server **out)
   S->cfg.hbm_budget_bytes = cfg && cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : (1ull << 30);
   S->cfg.max_resident = cfg && cfg->max_resident ? cfg->max_resident : 1024;
   S->cfg.max_lds_bytes = cfg && cfg->max_lds_bytes ? std::min(cfg->max_lds_bytes, c->max_lds) : std::min(65536u, c->max_lds);
+  S->cfg.max_items = cfg && cfg->max_items ? cfg->max_items : 40u * c->info.cus;
+  S->gctx.dev = c->dev;
+  S->gctx.info = c->info;
+  S->gctx.max_lds = c->max_lds;
   auto bail = [&](const char *what) {
     (void)hipFree(S->arena_d);
     (void)hipFree(S->jobs_d);
+    (void)hipFree(S->next);
     (void)hipHostFree(S->pin);
+    fan_free(S->fan);
     if (S->s) (void)hipStreamDestroy(S->s);
     delete S;
     return fail(c, GX_E_NOMEM, "server: %s", what);
   };
   if (hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) != hipSuccess) return bail("stream");
+  if (fan_init(S->fan) != hipSuccess) return bail("side streams");
+  if (hipMalloc((void **)&S->next, sizeof(uint32_t) * kMaxGroups) != hipSuccess ||
+      hipMemset(S->next, 0, sizeof(uint32_t) * kMaxGroups) != hipSuccess)
+    return bail("work-item counters");
   if (hipMalloc((void **)&S->arena_d, S->cfg.hbm_budget_bytes) != hipSuccess) return bail("arena");
   S->arena.reset(S->cfg.hbm_budget_bytes);
   if (hipMalloc((void **)&S->jobs_d, sizeof(DevJob) * S->cfg.max_resident) != hipSuccess) return bail("job table");
@@ -1262,6 +1385,7 @@ gx_status gx_server_submit(gx_server *S, const gx_instance_desc *d, const gx_sol
   }
   const double n = r->n;
   r->cost = (r->pr.h.kind == KQAP ? 4.0 * n * n / 3.0 : (r->pr.h.kind == KVRP ? 8.0 * n : n)) * r->hj.C;
+  r->kind = r->pr.h.kind;
   if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
     delete r;
     return GX_E_DEVICE;
@@ -1350,7 +1474,9 @@ gx_status gx_server_destroy(gx_server *S) {
   }
   (void)hipFree(S->arena_d);
   (void)hipFree(S->jobs_d);
+  (void)hipFree(S->next);
   (void)hipHostFree(S->pin);
+  fan_free(S->fan);
   (void)hipStreamDestroy(S->s);
   delete S;
   return GX_OK;

@@ -84,7 +84,7 @@ inline uint32_t lds_bytes_for(int kind, int n, int stage) {
       else if (stage == SLDSXY) b += al(4 * un) + al(2 * un);   // coordinates, edge lengths
       return b;
     }
-    case KQAP: return tables + tours + 2 * al(2 * un * un) + al(2 * kWave * un);
+    case KQAP: return tables + tours + 2 * al(2 * un * un) + 2 * al(2 * kWave * un);   // F, D, candidates, entries
     case KKNAP: return tables + al(un) + 2 * al(4 * un);
     case KVRP: return tables + tours + al(2 * (un + 1) * (un + 1)) + 3 * al(4 * (un + 1));
     default: return tables + al(2 * un) + al(4 * (un + 1));   // + adjacency, added by the caller
@@ -103,11 +103,12 @@ hipError_t init_jobs(gx::DevJob *jobs, int count, uint32_t max_q, int max_n, int
 hipError_t set_stop(gx::DevJob *jobs, int count, uint32_t add, int use_total, hipStream_t s);
 hipError_t evolve_plain(gx::DevJob *job, int kind, int stage, uint32_t P, uint32_t lds,
                         hipStream_t s);
-hipError_t evolve_items(gx::DevJob *jobs, const uint2 *items, uint32_t n_items, uint32_t grid,
-                        uint32_t lds, hipStream_t s);
+hipError_t evolve_group(int kind, int stage, gx::DevJob *jobs, const uint2 *items, uint32_t n_items, uint32_t *next,
+                        uint32_t grid, uint32_t lds, hipStream_t s);
 hipError_t fetch_best(gx::DevJob *jobs, int count, hipStream_t s);
-hipError_t epoch(gx::DevJob *jobs, const uint32_t *idx, uint32_t count, hipStream_t s);
+hipError_t epoch(gx::DevJob *jobs, const uint32_t *idx, uint32_t count, uint32_t *next, uint32_t n_next,
+                 hipStream_t s);
 hipError_t prepare_kernel_attrs(uint32_t max_lds);
 hipError_t occupancy_plain(int kind, int stage, uint32_t lds, int *blocks_per_cu);
-hipError_t occupancy_items(uint32_t lds, int *blocks_per_cu);
+hipError_t occupancy_group(int kind, int stage, uint32_t lds, int *blocks_per_cu);
 }  // namespace gxk

@@ -373,44 +373,10 @@ __device__ __forceinline__ void perm_store(const uint16_t *cur, int n, int32_t *
 // ------------------------------------------------------------ QAP
 // delta = sum_{a in X} sum_b m_b F[a][b] (D[y_a][y_b] - D[x_a][x_b]), X the
 // changed positions, y the candidate, m_b = 1 inside X and 2 outside (F, D symmetric)
-struct QapK {
-  static constexpr int ENC = 0;
-  uint16_t *cur, *nxt;
-  int n;
-  const int16_t *F, *D;
-  uint16_t *xr;  // candidate rows, element b of lane l at xr[b * 64 + l]
-  __device__ __forceinline__ int64_t delta(const Step *st, int k, int64_t) const {
-    if (n < 2) return 0;
-    const uint32_t l = lane_id();
-    uint64_t mask = 0;
-    for (int p = 0; p < n; ++p) {
-      const int v = cur[chain(st, k, p)];
-      xr[p * kWave + l] = (uint16_t)v;
-      mask |= (uint64_t)(v != cur[p]) << p;
-    }
-    int64_t d = 0;
-    uint64_t rem = mask;
-    while (rem) {
-      const int a = __builtin_ctzll(rem);
-      rem &= rem - 1;
-      const int xa = cur[a], ya = xr[a * kWave + l];
-      const int16_t *Fa = F + a * n, *Dy = D + ya * n, *Dx = D + xa * n;
-      int64_t acc = 0;
-      for (int b = 0; b < n; ++b) {
-        const int t = Fa[b] * (Dy[xr[b * kWave + l]] - Dx[cur[b]]);
-        acc += ((mask >> b) & 1) ? t : 2 * t;
-      }
-      d += acc;
-    }
-    return d;
-  }
-  __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, st, k); }
-  __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
-};
-
 // ------------------------------------------------------------ VRPTW (giant tour)
 struct VrpK {
   static constexpr int ENC = 0;
+  static constexpr bool kRound = false;
   uint16_t *cur, *nxt;
   int n, dn, cap, veh, svc, hor;
   const int16_t *D;
@@ -459,6 +425,7 @@ struct VrpK {
 // ------------------------------------------------------------ 0/1 knapsack
 struct KnapK {
   static constexpr int ENC = 1;
+  static constexpr bool kRound = false;
   uint8_t *bits;
   const int32_t *w, *v;
   int n;
@@ -494,7 +461,9 @@ struct KnapK {
     W += dW;
     V += dV;
     if (lane_id() == 0)
-      for (int m = 0; m < k; ++m) bits[st[m].a] ^= 1;
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+        if (m < k) bits[st[m].a] ^= 1;
     __syncthreads();
   }
   __device__ __forceinline__ void store(int32_t *dst) const {
@@ -505,6 +474,7 @@ struct KnapK {
 // ------------------------------------------------------------ integer colouring
 struct ColorK {
   static constexpr int ENC = 2;
+  static constexpr bool kRound = false;
   int16_t *val;
   const int32_t *off, *adj;
   int n;
@@ -530,7 +500,9 @@ struct ColorK {
   }
   __device__ __forceinline__ void apply(const Step *st, int k) {
     if (lane_id() == 0)
-      for (int m = 0; m < k; ++m) val[st[m].a] = (int16_t)st[m].b;
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+        if (m < k) val[st[m].a] = (int16_t)st[m].b;
     __syncthreads();
   }
   __device__ __forceinline__ void store(int32_t *dst) const {
@@ -950,6 +922,73 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
 }
 
 // ------------------------------------------------------------ generation loop
+// ------------------------------------------------------------ QAP
+struct QapK {
+  static constexpr int ENC = 0;
+  static constexpr bool kRound = true;
+  uint16_t *cur, *nxt;
+  int n;
+  const int16_t *F, *D;
+  uint16_t *xr;    // candidate solutions, element b of lane l at xr[b * 64 + l]
+  uint16_t *list;  // (candidate, changed position) entries of a round
+  // Deltas of the 64 candidates of a round (one per lane, k = 0 for an empty
+  // lane), wave-collective.  f(y) - f(x) over the changed positions M of a
+  // candidate: for every a in M, sum over b of F[a][b] (D[y_a][y_b] -
+  // D[x_a][x_b]), counted once for b in M and twice otherwise (F and D are
+  // symmetric).  The (candidate, a) entries are listed and shared by all
+  // lanes, so the work follows the total number of changed positions rather
+  // than the largest one in the wave.
+  __device__ __forceinline__ int64_t delta_round(const Step *st, int k) const {
+    const uint32_t l = lane_id();
+    unsigned long long *masks = (unsigned long long *)(gx_lds + 2048);
+    long long *dsum = (long long *)(gx_lds + 2560);
+    SMap M[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      M[m] = smap(st[m].op, st[m].a, st[m].b, st[m].c);
+      if (m >= k) M[m].len = 0;   // identity
+    }
+    uint64_t mask = 0;
+#pragma unroll 2
+    for (int p = 0; p < n; ++p) {
+      const int q = sapply(M[0], sapply(M[1], sapply(M[2], p)));
+      const int v = cur[q];
+      xr[p * kWave + l] = (uint16_t)v;
+      mask |= (uint64_t)(v != cur[p]) << p;
+    }
+    const uint32_t cnt = (uint32_t)__popcll(mask);
+    uint32_t incl = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const uint32_t v = __shfl_up(incl, o, kWave);
+      incl += l >= (uint32_t)o ? v : 0u;
+    }
+    const uint32_t base = incl - cnt, total = uni(__shfl(incl, kWave - 1, kWave));
+    masks[l] = mask;
+    dsum[l] = 0;
+    for (int p = 0; p < n; ++p)
+      if ((mask >> p) & 1) list[base + __popcll(mask & ((1ull << p) - 1))] = (uint16_t)(l | (p << 6));
+    __syncthreads();
+    for (uint32_t e = l; e < total; e += kWave) {
+      const uint32_t en = list[e], t = en & 63u, a = en >> 6;
+      const uint64_t mt = masks[t];
+      const int ya = xr[a * kWave + t], xa = cur[a];
+      const int16_t *Fa = F + a * n, *Dy = D + ya * n, *Dx = D + xa * n;
+      int64_t acc = 0;
+#pragma unroll 4
+      for (int b = 0; b < n; ++b) {
+        const int tt = Fa[b] * (Dy[xr[b * kWave + t]] - Dx[cur[b]]);
+        acc += ((mt >> b) & 1) ? tt : 2 * tt;
+      }
+      atomicAdd((unsigned long long *)&dsum[t], (unsigned long long)acc);
+    }
+    __syncthreads();
+    return dsum[l];
+  }
+  __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, st, k); }
+  __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
+};
+
 template <class KD>
 __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni &U, int32_t *best_row, uint32_t sol,
                                          uint32_t g0, uint32_t g1, uint64_t &T, int64_t &f, int64_t &bf, LStats &S,
@@ -965,7 +1004,21 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const uint32_t tl = r * kWave + lane;
-        if (tl < cn) {
+        const bool valid = tl < cn;
+        if constexpr (KD::kRound) {   // wave-collective evaluation of the round's candidates
+          if (!__ballot(valid)) continue;
+          Step st[3];
+          st[0] = load_step<ENC>(W, (int)tl, 0);
+          st[1] = load_step<ENC>(W, (int)tl, 1);
+          st[2] = load_step<ENC>(W, (int)tl, 2);
+          const int k = valid ? kk[r] : 0;
+          const int64_t d = kd.delta_round(st, k);
+          if (valid) {
+            if (U.credit == 0) credit<ENC>(S, st, k, d < 0);
+            const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | (c0 + tl);
+            bk = key < bk ? key : bk;
+          }
+        } else if (valid) {
           Step st[3];
           st[0] = load_step<ENC>(W, (int)tl, 0);
           st[1] = kk[r] > 1 ? load_step<ENC>(W, (int)tl, 1) : st[0];
@@ -1074,7 +1127,8 @@ __device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LSta
 // boundary apply the AOS update (the kernel boundary orders it after every
 // evolve workgroup).  One wave per job; lane l folds and clears row l.
 static_assert(kShards == kWave, "one accumulator row per lane");
-__global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx) {
+__global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx, uint32_t *next, uint32_t n_next) {
+  if (blockIdx.x == 0 && threadIdx.x < n_next) next[threadIdx.x] = 0;   // work-item counters of the launch
   DevJob *J = jobs + (idx ? idx[blockIdx.x] : blockIdx.x);
   const uint32_t g0 = J->g, gstop = J->g_stop;
   if (g0 >= gstop) return;
@@ -1243,10 +1297,11 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       int16_t *F = (int16_t *)rest;
       int16_t *D = (int16_t *)(rest + al16(2 * n * n));
       uint16_t *xr = (uint16_t *)(rest + 2 * al16(2 * n * n));
+      uint16_t *list = (uint16_t *)(rest + 2 * al16(2 * n * n) + al16(2 * kWave * n));
       stage16(F, I->qf, 2u * n * n);
       stage16(D, I->qd, 2u * n * n);
       __syncthreads();
-      QapK kd{t0, t1, n, F, D, xr};
+      QapK kd{t0, t1, n, F, D, xr, list};
       run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       perm_store(kd.cur, n, cur_g);
     } else {
@@ -1310,28 +1365,20 @@ __global__ __launch_bounds__(64) void k_evolve(DevJob *job) {
   evolve_wg<KIND, STAGE>(job, blockIdx.x, gx_lds);
 }
 
-// Persistent walk over (job, solution) work items of many jobs of any kinds.
-__global__ __launch_bounds__(64) void k_evolve_items(DevJob *jobs, const uint2 *items, uint32_t n_items) {
-  char *lds = gx_lds;
-  for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+// Persistent walk over the (job, solution) work items of one (kind, staging)
+// group of many jobs: each workgroup takes the next item from the group's
+// counter until the list is done, so workgroups that finish early take more.
+// The epoch kernel clears the counter after the launch.
+template <int KIND, int STAGE>
+__global__ __launch_bounds__(64) void k_evolve_group(DevJob *jobs, const uint2 *items, uint32_t n_items,
+                                                     uint32_t *next) {
+  for (;;) {
+    uint32_t it = 0;
+    if (lane_id() == 0) it = atomicAdd(next, 1u);
+    it = uni(it);
+    if (it >= n_items) break;
     const uint2 w = items[it];
-    DevJob *J = jobs + w.x;
-    const int kind = J->inst->kind;
-    const int stage = (int)J->stage;
-    if (kind == KTSP) {
-      if (stage == SLDS16) evolve_wg<KTSP, SLDS16>(J, w.y, lds);
-      else if (stage == SLDSXY) evolve_wg<KTSP, SLDSXY>(J, w.y, lds);
-      else if (stage == SGLB16) evolve_wg<KTSP, SGLB16>(J, w.y, lds);
-      else evolve_wg<KTSP, SGLB32>(J, w.y, lds);
-    } else if (kind == KQAP) {
-      evolve_wg<KQAP, 0>(J, w.y, lds);
-    } else if (kind == KKNAP) {
-      evolve_wg<KKNAP, 0>(J, w.y, lds);
-    } else if (kind == KVRP) {
-      evolve_wg<KVRP, 0>(J, w.y, lds);
-    } else {
-      evolve_wg<KCOLOR, 0>(J, w.y, lds);
-    }
+    evolve_wg<KIND, STAGE>(jobs + w.x, w.y, gx_lds);
     __syncthreads();
   }
 }
@@ -1677,6 +1724,22 @@ static const void *plain_kernel(int kind, int stage) {
   }
 }
 
+static const void *group_kernel(int kind, int stage) {
+  switch (kind) {
+    case KTSP:
+      switch (stage) {
+        case SLDS16: return (const void *)k_evolve_group<KTSP, SLDS16>;
+        case SLDSXY: return (const void *)k_evolve_group<KTSP, SLDSXY>;
+        case SGLB16: return (const void *)k_evolve_group<KTSP, SGLB16>;
+        default: return (const void *)k_evolve_group<KTSP, SGLB32>;
+      }
+    case KQAP: return (const void *)k_evolve_group<KQAP, 0>;
+    case KKNAP: return (const void *)k_evolve_group<KKNAP, 0>;
+    case KVRP: return (const void *)k_evolve_group<KVRP, 0>;
+    default: return (const void *)k_evolve_group<KCOLOR, 0>;
+  }
+}
+
 hipError_t prepare_kernel_attrs(uint32_t max_lds) {
   const int kinds[][2] = {{KTSP, SLDS16}, {KTSP, SLDSXY}, {KTSP, SGLB16}, {KTSP, SGLB32},
                           {KQAP, 0},      {KKNAP, 0},     {KVRP, 0},      {KCOLOR, 0}};
@@ -1685,8 +1748,12 @@ hipError_t prepare_kernel_attrs(uint32_t max_lds) {
                                        (int)max_lds);
     if (e != hipSuccess) return e;
   }
-  return hipFuncSetAttribute((const void *)k_evolve_items, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)max_lds);
+  for (auto &k : kinds) {
+    hipError_t e = hipFuncSetAttribute(group_kernel(k[0], k[1]), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)max_lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t evolve_plain(DevJob *job, int kind, int stage, uint32_t P, uint32_t lds, hipStream_t s) {
@@ -1694,14 +1761,15 @@ hipError_t evolve_plain(DevJob *job, int kind, int stage, uint32_t P, uint32_t l
   return hipLaunchKernel(plain_kernel(kind, stage), dim3(P), dim3(64), args, lds, s);
 }
 
-hipError_t evolve_items(DevJob *jobs, const uint2 *items, uint32_t n_items, uint32_t grid, uint32_t lds,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(k_evolve_items, dim3(grid), dim3(64), lds, s, jobs, items, n_items);
-  return hipGetLastError();
+hipError_t evolve_group(int kind, int stage, DevJob *jobs, const uint2 *items, uint32_t n_items, uint32_t *next,
+                        uint32_t grid, uint32_t lds, hipStream_t s) {
+  void *args[] = {&jobs, &items, &n_items, &next};
+  return hipLaunchKernel(group_kernel(kind, stage), dim3(grid), dim3(64), args, lds, s);
 }
 
-hipError_t epoch(DevJob *jobs, const uint32_t *idx, uint32_t count, hipStream_t s) {
-  hipLaunchKernelGGL(k_epoch, dim3(count), dim3(64), 0, s, jobs, idx);
+hipError_t epoch(DevJob *jobs, const uint32_t *idx, uint32_t count, uint32_t *next, uint32_t n_next,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_epoch, dim3(count), dim3(64), 0, s, jobs, idx, next, n_next);
   return hipGetLastError();
 }
 
@@ -1710,8 +1778,8 @@ hipError_t fetch_best(DevJob *jobs, int count, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t occupancy_items(uint32_t lds, int *blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)k_evolve_items, 64, lds);
+hipError_t occupancy_group(int kind, int stage, uint32_t lds, int *blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, group_kernel(kind, stage), 64, lds);
 }
 
 hipError_t occupancy_plain(int kind, int stage, uint32_t lds, int *blocks_per_cu) {

@@ -63,7 +63,8 @@ class gx_job_info(C.Structure):
 
 
 class gx_server_cfg(C.Structure):
-    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_resident", C.c_uint32), ("max_lds_bytes", C.c_uint32)]
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_resident", C.c_uint32), ("max_lds_bytes", C.c_uint32),
+                ("max_items", C.c_uint32)]
 
 
 class gx_server_stats(C.Structure):
@@ -301,9 +302,9 @@ def gx_solve_batch(ctx, insts, params_list):
 
 
 # ------------------------------------------------------------------ serving
-def gx_server_create(ctx, hbm_budget_bytes=0, max_resident=0, max_lds_bytes=0):
+def gx_server_create(ctx, hbm_budget_bytes=0, max_resident=0, max_lds_bytes=0, max_items=0):
     cfg = gx_server_cfg(hbm_budget_bytes=hbm_budget_bytes, max_resident=max_resident,
-                        max_lds_bytes=max_lds_bytes)
+                        max_lds_bytes=max_lds_bytes, max_items=max_items)
     out = C.c_void_p()
     _check(ctx, lib().gx_server_create(ctx, C.byref(cfg), C.byref(out)))
     return out

@@ -67,7 +67,9 @@ def test_batch_equals_oracle_per_job(ctx):
 
 
 def test_batch_equals_plain_solver(ctx):
-    insts, params = mixed(3, 2, G=120)      # 120 generations: graph-replayed launches
+    # 700 generations: 70 epoch launches, the first 64 replayed from a captured
+    # graph whose (kind, staging) groups run on side streams
+    insts, params = mixed(3, 2, G=700)
     handles = [gx.gx_instance_upload(ctx, i) for i in insts]
     jobs = gx.gx_solve_batch(ctx, handles, params)
     batched = [gx.gx_fetch_best(ctx, j, i.n) for j, i in zip(jobs, insts)]

@@ -133,3 +133,18 @@ def test_rejections(ctx):
         gx.gx_server_submit(srv, synth.tsp_uniform(400, 0),
                             synth.Params(population=256, generations=10, alpha_q32=5))
     gx.gx_server_destroy(srv)
+
+
+def test_item_cap_queues_in_order(ctx):
+    # at most 8 solutions resident: requests of P = 4 run two at a time
+    reqs = requests(9, seed=13)
+    srv = gx.gx_server_create(ctx, hbm_budget_bytes=256 << 20, max_resident=64, max_items=8)
+    tickets = [gx.gx_server_submit(srv, i, p) for i, p in reqs]
+    n_of = {t: i.n for t, (i, _) in zip(tickets, reqs)}
+    res = wait_all(srv, tickets, n_of)
+    stats = gx.gx_server_stats_get(srv)
+    gx.gx_server_destroy(srv)
+    assert stats["completed"] == len(reqs)
+    for t, (inst, p) in zip(tickets, reqs):
+        s2, f2 = plain(ctx, inst, p)
+        assert res[t][1] == f2 and np.array_equal(res[t][0], s2), (inst.kind, inst.n)
