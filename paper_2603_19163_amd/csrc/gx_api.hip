@@ -1083,13 +1083,31 @@ struct SrvReq {
   Prepared pr;
   DevJob hj{};
   size_t inst_bytes = 0, bytes = 0, off = 0, pin_off = 0;
-  int slot = -1, n = 0, kind = 0;
+  int slot = -1, n = 0, kind = 0, lane = 0;
   uint32_t g = 0;
   hipEvent_t ev = nullptr;
   std::vector<int32_t> sol;
   int64_t f = 0;
   double cost = 0;
 };
+
+// One lane per (kind, staging): its requests advance one epoch chunk per
+// quantum on the lane's own stream, so lanes of cheap requests are not held to
+// the pace of expensive ones.  Work-item lists are double-buffered.
+struct SrvLane {
+  hipStream_t s = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  uint2 *items_d[2] = {nullptr, nullptr}, *items_h[2] = {nullptr, nullptr};
+  uint32_t *slots_d[2] = {nullptr, nullptr}, *slots_h[2] = {nullptr, nullptr};
+  size_t items_cap = 0, slots_cap = 0;
+  int buf = 0;
+  bool wait_staged = false;
+};
+
+int lane_of(int kind, int stage) {
+  if (kind == KTSP) return std::min(std::max(stage, 1), 4) - 1;
+  return kind == KQAP ? 4 : (kind == KKNAP ? 5 : (kind == KVRP ? 6 : 7));
+}
 
 }  // namespace
 
@@ -1105,15 +1123,11 @@ struct gx_server {
   std::vector<SrvReq *> slots;
   std::vector<int> free_slots;
   DevJob *jobs_d = nullptr;
-  uint2 *items_d[2] = {nullptr, nullptr};
-  uint2 *items_h[2] = {nullptr, nullptr};
-  uint32_t *slots_d[2] = {nullptr, nullptr};   // resident slots advanced by a quantum
-  uint32_t *slots_h[2] = {nullptr, nullptr};
-  hipEvent_t items_ev[2] = {nullptr, nullptr};
-  size_t items_cap = 0;
-  uint32_t *next = nullptr;   // work-item counters, one per group
+  SrvLane lanes[kMaxGroups];
+  uint32_t *next = nullptr;   // work-item counters, one per lane
+  hipEvent_t staged = nullptr;   // after the initialisation of newly admitted requests
+  hipEvent_t drain[kMaxGroups] = {};   // lane tails, for retiring a cancelled request
   uint64_t resident_items = 0;   // solutions of the resident requests (guarded by mu)
-  Fan fan;
   gx_ctx gctx;                // device facts and messages of the scheduler thread
   char *arena_d = nullptr;
   Arena arena;
@@ -1128,21 +1142,48 @@ struct gx_server {
 
 namespace {
 
-gx_status srv_grow_items(gx_server *S, size_t need) {
-  if (need <= S->items_cap) return GX_OK;
-  size_t cap = std::max<size_t>(need, 2 * S->items_cap);
-  for (int b = 0; b < 2; ++b) {
-    if (S->items_ev[b]) (void)hipEventSynchronize(S->items_ev[b]);
-    (void)hipFree(S->items_d[b]);
-    (void)hipHostFree(S->items_h[b]);
-    S->items_d[b] = nullptr;
-    S->items_h[b] = nullptr;
-    if (hipMalloc((void **)&S->items_d[b], cap * sizeof(uint2)) != hipSuccess ||
-        hipHostMalloc((void **)&S->items_h[b], cap * sizeof(uint2), 0) != hipSuccess)
-      return GX_E_NOMEM;
+gx_status lane_grow(SrvLane &L, size_t items, size_t slots) {
+  if (items > L.items_cap) {
+    const size_t cap = std::max<size_t>(items, 2 * L.items_cap);
+    for (int b = 0; b < 2; ++b) {
+      (void)hipEventSynchronize(L.ev[b]);
+      (void)hipFree(L.items_d[b]);
+      (void)hipHostFree(L.items_h[b]);
+      L.items_d[b] = nullptr;
+      L.items_h[b] = nullptr;
+      if (hipMalloc((void **)&L.items_d[b], cap * sizeof(uint2)) != hipSuccess ||
+          hipHostMalloc((void **)&L.items_h[b], cap * sizeof(uint2), 0) != hipSuccess)
+        return GX_E_NOMEM;
+    }
+    L.items_cap = cap;
   }
-  S->items_cap = cap;
+  if (slots > L.slots_cap) {
+    const size_t cap = std::max<size_t>(slots, 2 * L.slots_cap);
+    for (int b = 0; b < 2; ++b) {
+      (void)hipEventSynchronize(L.ev[b]);
+      (void)hipFree(L.slots_d[b]);
+      (void)hipHostFree(L.slots_h[b]);
+      L.slots_d[b] = nullptr;
+      L.slots_h[b] = nullptr;
+      if (hipMalloc((void **)&L.slots_d[b], cap * sizeof(uint32_t)) != hipSuccess ||
+          hipHostMalloc((void **)&L.slots_h[b], cap * sizeof(uint32_t), 0) != hipSuccess)
+        return GX_E_NOMEM;
+    }
+    L.slots_cap = cap;
+  }
   return GX_OK;
+}
+
+void lane_free(SrvLane &L) {
+  for (int b = 0; b < 2; ++b) {
+    (void)hipFree(L.items_d[b]);
+    (void)hipHostFree(L.items_h[b]);
+    (void)hipFree(L.slots_d[b]);
+    (void)hipHostFree(L.slots_h[b]);
+    if (L.ev[b]) (void)hipEventDestroy(L.ev[b]);
+  }
+  if (L.s) (void)hipStreamDestroy(L.s);
+  L = SrvLane{};
 }
 
 // Place an admitted request into its arena block and start its initialisation.
@@ -1173,9 +1214,8 @@ void srv_release(gx_server *S, SrvReq *r) {   // caller holds mu
 
 void server_loop(gx_server *S) {
   (void)hipSetDevice(S->c->dev);
-  int buf = 0;
   uint64_t busy_since = 0;
-  std::vector<SrvReq *> admitted, active;
+  std::vector<SrvReq *> admitted, by_lane[kMaxGroups];
   std::vector<ItemRec> recs;
   std::vector<Group> groups;
   while (!S->stop.load()) {
@@ -1221,64 +1261,82 @@ void server_loop(gx_server *S) {
       }
     }
     if (!busy_since) busy_since = now_ns();
-    for (SrvReq *r : admitted)
-      if (srv_stage(S, r) != GX_OK) r->cancel = true;   // staging failure: reported as cancelled
-    // ---- one quantum: every resident running request advances one epoch chunk
-    active.clear();
-    size_t n_items = 0;
+    if (!admitted.empty()) {
+      for (SrvReq *r : admitted)
+        if (srv_stage(S, r) != GX_OK) r->cancel = true;   // staging failure: reported as cancelled
+      (void)hipEventRecord(S->staged, S->s);
+      for (SrvLane &L : S->lanes) L.wait_staged = true;
+    }
+    // ---- quanta: every lane whose older work-item buffer is free advances its
+    // running requests by one epoch chunk
+    for (auto &v : by_lane) v.clear();
     for (SrvReq *r : S->slots)
-      if (r && r->state == RQ_RESIDENT && !r->cancel && r->g < r->hj.G) {
-        active.push_back(r);
-        n_items += r->hj.P;
-      }
-    if (!active.empty() && srv_grow_items(S, n_items) == GX_OK) {
-      (void)hipEventSynchronize(S->items_ev[buf]);
+      if (r && r->state == RQ_RESIDENT && !r->cancel && r->g < r->hj.G) by_lane[r->lane].push_back(r);
+    bool progressed = false;
+    uint64_t evals = 0, quanta = 0;
+    for (int li = 0; li < kMaxGroups; ++li) {
+      SrvLane &L = S->lanes[li];
+      std::vector<SrvReq *> &act = by_lane[li];
+      if (act.empty() || hipEventQuery(L.ev[L.buf]) != hipSuccess) continue;
+      size_t n_items = 0;
+      for (SrvReq *r : act) n_items += r->hj.P;
+      if (lane_grow(L, n_items, act.size()) != GX_OK) continue;
+      const int b = L.buf;
       recs.clear();
-      for (SrvReq *r : active)
+      for (SrvReq *r : act)
         for (uint32_t sl = 0; sl < r->hj.P; ++sl)
           recs.push_back(ItemRec{r->kind, (int)r->hj.stage, r->hj.lds_bytes, r->cost, make_uint2((uint32_t)r->slot, sl)});
-      uint2 *h = S->items_h[buf];
-      if (make_groups(&S->gctx, recs, h, groups) != GX_OK) groups.clear();
-      uint32_t *sl = S->slots_h[buf];
-      for (size_t a = 0; a < active.size(); ++a) sl[a] = (uint32_t)active[a]->slot;
-      (void)hipMemcpyAsync(S->items_d[buf], h, n_items * sizeof(uint2), hipMemcpyHostToDevice, S->s);
-      (void)hipMemcpyAsync(S->slots_d[buf], sl, active.size() * sizeof(uint32_t), hipMemcpyHostToDevice, S->s);
-      (void)launch_groups(S->fan, groups, S->jobs_d, S->items_d[buf], S->next, S->slots_d[buf],
-                          (uint32_t)active.size(), S->s);
-      (void)hipEventRecord(S->items_ev[buf], S->s);
-      buf ^= 1;
-      uint64_t evals = 0;
-      for (SrvReq *r : active) {
+      if (make_groups(&S->gctx, recs, L.items_h[b], groups) != GX_OK || groups.size() != 1) continue;
+      for (size_t a = 0; a < act.size(); ++a) L.slots_h[b][a] = (uint32_t)act[a]->slot;
+      if (L.wait_staged) {
+        (void)hipStreamWaitEvent(L.s, S->staged, 0);
+        L.wait_staged = false;
+      }
+      (void)hipMemcpyAsync(L.items_d[b], L.items_h[b], n_items * sizeof(uint2), hipMemcpyHostToDevice, L.s);
+      (void)hipMemcpyAsync(L.slots_d[b], L.slots_h[b], act.size() * sizeof(uint32_t), hipMemcpyHostToDevice, L.s);
+      const Group &g = groups[0];
+      (void)gxk::evolve_group(g.kind, g.stage, S->jobs_d, L.items_d[b], g.count, S->next + li, g.grid, g.lds, L.s);
+      (void)gxk::epoch(S->jobs_d, L.slots_d[b], (uint32_t)act.size(), S->next + li, 1, L.s);
+      for (SrvReq *r : act) {
         const uint32_t E = r->hj.E;
         const uint32_t ng = (uint32_t)std::min<uint64_t>(r->hj.G, ((uint64_t)r->g / E + 1) * E);
         evals += (uint64_t)r->hj.P * r->hj.C * (ng - r->g);
         r->g = ng;
         if (r->g == r->hj.G) {   // finished: fetch the best solution asynchronously
-          (void)gxk::fetch_best(S->jobs_d + r->slot, 1, S->s);
+          (void)gxk::fetch_best(S->jobs_d + r->slot, 1, L.s);
           char *dst = S->pin + r->pin_off;
-          (void)hipMemcpyAsync(dst, r->hj.best_out, 4 * (size_t)r->n, hipMemcpyDeviceToHost, S->s);
+          (void)hipMemcpyAsync(dst, r->hj.best_out, 4 * (size_t)r->n, hipMemcpyDeviceToHost, L.s);
           (void)hipMemcpyAsync(dst + 4 * (size_t)r->n, (char *)(S->jobs_d + r->slot) + offsetof(DevJob, best_out_f),
-                               8, hipMemcpyDeviceToHost, S->s);
-          (void)hipEventRecord(r->ev, S->s);
+                               8, hipMemcpyDeviceToHost, L.s);
+          (void)hipEventRecord(r->ev, L.s);
           r->state = RQ_FETCHING;
         }
       }
+      (void)hipEventRecord(L.ev[b], L.s);
+      L.buf ^= 1;
+      progressed = true;
+      ++quanta;
+    }
+    if (quanta) {
       std::lock_guard<std::mutex> lk(S->mu);
-      S->st.quanta++;
+      S->st.quanta += quanta;
       S->st.move_evals += evals;
     }
-    // cancelled residents: retire after the work enqueued so far has drained
+    // cancelled residents: retire after all work enqueued so far has drained
     for (SrvReq *r : S->slots)
       if (r && r->cancel && r->state == RQ_RESIDENT) {
+        for (int li = 0; li < kMaxGroups; ++li) {
+          (void)hipEventRecord(S->drain[li], S->lanes[li].s);
+          (void)hipStreamWaitEvent(S->s, S->drain[li], 0);
+        }
         (void)hipEventRecord(r->ev, S->s);
         r->state = RQ_FETCHING;
       }
     // completions
-    bool waited = active.empty();
+    bool done_any = false;
     for (SrvReq *r : S->slots) {
       if (!r || r->state != RQ_FETCHING) continue;
-      hipError_t q = waited ? hipEventSynchronize(r->ev) : hipEventQuery(r->ev);
-      if (q != hipSuccess) continue;
+      if (hipEventQuery(r->ev) != hipSuccess) continue;
       std::lock_guard<std::mutex> lk(S->mu);
       if (!r->cancel) {
         const char *src = S->pin + r->pin_off;
@@ -1292,8 +1350,11 @@ void server_loop(gx_server *S) {
       }
       r->t_done = now_ns();
       srv_release(S, r);
+      done_any = true;
     }
+    if (!progressed && !done_any) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
+  for (SrvLane &L : S->lanes) (void)hipStreamSynchronize(L.s);
   (void)hipStreamSynchronize(S->s);
 }
 
@@ -1322,13 +1383,24 @@ gx_status gx_server_create(gx_ctx *c, const gx_server_cfg *cfg, gx_server **out)
     (void)hipFree(S->jobs_d);
     (void)hipFree(S->next);
     (void)hipHostFree(S->pin);
-    fan_free(S->fan);
+    for (SrvLane &L : S->lanes) lane_free(L);
+    for (hipEvent_t &e : S->drain)
+      if (e) (void)hipEventDestroy(e);
+    if (S->staged) (void)hipEventDestroy(S->staged);
     if (S->s) (void)hipStreamDestroy(S->s);
     delete S;
     return fail(c, GX_E_NOMEM, "server: %s", what);
   };
   if (hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) != hipSuccess) return bail("stream");
-  if (fan_init(S->fan) != hipSuccess) return bail("side streams");
+  if (hipEventCreateWithFlags(&S->staged, hipEventDisableTiming) != hipSuccess) return bail("events");
+  for (int li = 0; li < kMaxGroups; ++li) {
+    SrvLane &L = S->lanes[li];
+    if (hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&L.ev[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&L.ev[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&S->drain[li], hipEventDisableTiming) != hipSuccess)
+      return bail("lane streams");
+  }
   if (hipMalloc((void **)&S->next, sizeof(uint32_t) * kMaxGroups) != hipSuccess ||
       hipMemset(S->next, 0, sizeof(uint32_t) * kMaxGroups) != hipSuccess)
     return bail("work-item counters");
@@ -1338,13 +1410,6 @@ gx_status gx_server_create(gx_ctx *c, const gx_server_cfg *cfg, gx_server **out)
   const size_t pin_bytes = std::max<size_t>(16u << 20, (size_t)S->cfg.max_resident * 4096);
   if (hipHostMalloc((void **)&S->pin, pin_bytes, 0) != hipSuccess) return bail("pinned results");
   S->pin_arena.reset(pin_bytes);
-  for (int b = 0; b < 2; ++b)
-    if (hipEventCreateWithFlags(&S->items_ev[b], hipEventDisableTiming) != hipSuccess) return bail("events");
-  if (srv_grow_items(S, 4096) != GX_OK) return bail("work items");
-  for (int b = 0; b < 2; ++b)
-    if (hipMalloc((void **)&S->slots_d[b], 4 * (size_t)S->cfg.max_resident) != hipSuccess ||
-        hipHostMalloc((void **)&S->slots_h[b], 4 * (size_t)S->cfg.max_resident, 0) != hipSuccess)
-      return bail("slot lists");
   S->slots.assign(S->cfg.max_resident, nullptr);
   for (int i = (int)S->cfg.max_resident - 1; i >= 0; --i) S->free_slots.push_back(i);
   S->st.arena_bytes = S->arena.cap();
@@ -1386,6 +1451,7 @@ gx_status gx_server_submit(gx_server *S, const gx_instance_desc *d, const gx_sol
   const double n = r->n;
   r->cost = (r->pr.h.kind == KQAP ? 4.0 * n * n / 3.0 : (r->pr.h.kind == KVRP ? 8.0 * n : n)) * r->hj.C;
   r->kind = r->pr.h.kind;
+  r->lane = lane_of(r->kind, (int)r->hj.stage);
   if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
     delete r;
     return GX_E_DEVICE;
@@ -1465,18 +1531,13 @@ gx_status gx_server_destroy(gx_server *S) {
     (void)hipEventDestroy(kv.second->ev);
     delete kv.second;
   }
-  for (int b = 0; b < 2; ++b) {
-    (void)hipFree(S->items_d[b]);
-    (void)hipHostFree(S->items_h[b]);
-    (void)hipFree(S->slots_d[b]);
-    (void)hipHostFree(S->slots_h[b]);
-    (void)hipEventDestroy(S->items_ev[b]);
-  }
+  for (SrvLane &L : S->lanes) lane_free(L);
+  for (hipEvent_t e : S->drain) (void)hipEventDestroy(e);
+  (void)hipEventDestroy(S->staged);
   (void)hipFree(S->arena_d);
   (void)hipFree(S->jobs_d);
   (void)hipFree(S->next);
   (void)hipHostFree(S->pin);
-  fan_free(S->fan);
   (void)hipStreamDestroy(S->s);
   delete S;
   return GX_OK;
