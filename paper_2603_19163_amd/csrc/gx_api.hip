@@ -19,7 +19,12 @@ using namespace gx;
 // Side streams for the concurrent launches of one epoch's work-item groups:
 // the groups fork from the main stream through one event and join back
 // through one event each (also inside a captured graph).
-constexpr int kMaxGroups = 8;
+// Work items are grouped by (kind, staging, LDS class): a launch reserves the
+// LDS of its largest item for every workgroup, so small instances of a kind
+// get a launch of their own with more workgroups per CU.
+constexpr int kLdsClasses = 4;
+constexpr int kMaxGroups = 16;
+inline int lds_class(uint32_t lds) { return lds <= 8192 ? 0 : (lds <= 16384 ? 1 : (lds <= 32768 ? 2 : 3)); }
 struct Fan {
   hipStream_t side[kMaxGroups - 1] = {};
   hipEvent_t fork = nullptr, join[kMaxGroups - 1] = {};
@@ -221,6 +226,8 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
         if (A[ij] < 0 || A[ij] >= 16384 || B[ij] < 0 || B[ij] >= 16384 || A[ij] != A[ji] || B[ij] != B[ji])
           return fail(c, GX_E_INVALID, "QAP matrices must be symmetric with entries in [0, 16384)");
       }
+    const int64_t mf = *std::max_element(A.begin(), A.end()), md = *std::max_element(B.begin(), B.end());
+    h.qap_sums32 = (int64_t)n * mf * md < (int64_t(1) << 31);
     add_arr(pr, F_QF, std::vector<int16_t>(A.begin(), A.end()));
     add_arr(pr, F_QD, std::vector<int16_t>(B.begin(), B.end()));
     fbound = 4.0 * n * n * 16384.0 * 16384.0;
@@ -610,15 +617,18 @@ gx_status make_groups(gx_ctx *c, std::vector<ItemRec> &recs, uint2 *items, std::
   std::stable_sort(recs.begin(), recs.end(), [](const ItemRec &x, const ItemRec &y) {
     if (x.kind != y.kind) return x.kind < y.kind;
     if (x.stage != y.stage) return x.stage < y.stage;
+    const int cx = lds_class(x.lds), cy = lds_class(y.lds);
+    if (cx != cy) return cx < cy;
     return x.cost > y.cost;
   });
   gs.clear();
   for (size_t k = 0; k < recs.size(); ++k) {
     const ItemRec &r = recs[k];
     items[k] = r.item;
-    if (gs.empty() || gs.back().kind != r.kind || gs.back().stage != r.stage) {
+    if (gs.empty() || gs.back().kind != r.kind || gs.back().stage != r.stage ||
+        lds_class(gs.back().lds) != lds_class(r.lds)) {
       if ((int)gs.size() == kMaxGroups) return fail(c, GX_E_UNSUPPORTED, "more than %d work-item groups", kMaxGroups);
-      gs.push_back(Group{r.kind, r.stage, (uint32_t)k, 0, 16, 0});
+      gs.push_back(Group{r.kind, r.stage, (uint32_t)k, 0, std::max<uint32_t>(16, r.lds), 0});
     }
     gs.back().count++;
     gs.back().lds = std::max(gs.back().lds, r.lds);
@@ -1104,9 +1114,12 @@ struct SrvLane {
   bool wait_staged = false;
 };
 
-int lane_of(int kind, int stage) {
-  if (kind == KTSP) return std::min(std::max(stage, 1), 4) - 1;
-  return kind == KQAP ? 4 : (kind == KKNAP ? 5 : (kind == KVRP ? 6 : 7));
+// lanes: (kind, staging) x LDS class
+constexpr int kLanes = 8 * kLdsClasses;
+int lane_of(int kind, int stage, uint32_t lds) {
+  const int ks = kind == KTSP ? std::min(std::max(stage, 1), 4) - 1
+                              : (kind == KQAP ? 4 : (kind == KKNAP ? 5 : (kind == KVRP ? 6 : 7)));
+  return ks * kLdsClasses + lds_class(lds);
 }
 
 }  // namespace
@@ -1123,10 +1136,10 @@ struct gx_server {
   std::vector<SrvReq *> slots;
   std::vector<int> free_slots;
   DevJob *jobs_d = nullptr;
-  SrvLane lanes[kMaxGroups];
+  SrvLane lanes[kLanes];
   uint32_t *next = nullptr;   // work-item counters, one per lane
   hipEvent_t staged = nullptr;   // after the initialisation of newly admitted requests
-  hipEvent_t drain[kMaxGroups] = {};   // lane tails, for retiring a cancelled request
+  hipEvent_t drain[kLanes] = {};   // lane tails, for retiring a cancelled request
   uint64_t resident_items = 0;   // solutions of the resident requests (guarded by mu)
   gx_ctx gctx;                // device facts and messages of the scheduler thread
   char *arena_d = nullptr;
@@ -1174,6 +1187,16 @@ gx_status lane_grow(SrvLane &L, size_t items, size_t slots) {
   return GX_OK;
 }
 
+void lane_free(SrvLane &L);
+
+hipError_t lane_init(SrvLane &L) {   // streams and events of a lane, on its first use
+  hipError_t e = hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&L.ev[0], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&L.ev[1], hipEventDisableTiming);
+  if (e != hipSuccess) lane_free(L);
+  return e;
+}
+
 void lane_free(SrvLane &L) {
   for (int b = 0; b < 2; ++b) {
     (void)hipFree(L.items_d[b]);
@@ -1215,7 +1238,7 @@ void srv_release(gx_server *S, SrvReq *r) {   // caller holds mu
 void server_loop(gx_server *S) {
   (void)hipSetDevice(S->c->dev);
   uint64_t busy_since = 0;
-  std::vector<SrvReq *> admitted, by_lane[kMaxGroups];
+  std::vector<SrvReq *> admitted, by_lane[kLanes];
   std::vector<ItemRec> recs;
   std::vector<Group> groups;
   while (!S->stop.load()) {
@@ -1274,10 +1297,12 @@ void server_loop(gx_server *S) {
       if (r && r->state == RQ_RESIDENT && !r->cancel && r->g < r->hj.G) by_lane[r->lane].push_back(r);
     bool progressed = false;
     uint64_t evals = 0, quanta = 0;
-    for (int li = 0; li < kMaxGroups; ++li) {
+    for (int li = 0; li < kLanes; ++li) {
       SrvLane &L = S->lanes[li];
       std::vector<SrvReq *> &act = by_lane[li];
-      if (act.empty() || hipEventQuery(L.ev[L.buf]) != hipSuccess) continue;
+      if (act.empty()) continue;
+      if (!L.s && lane_init(L) != hipSuccess) continue;
+      if (hipEventQuery(L.ev[L.buf]) != hipSuccess) continue;
       size_t n_items = 0;
       for (SrvReq *r : act) n_items += r->hj.P;
       if (lane_grow(L, n_items, act.size()) != GX_OK) continue;
@@ -1325,7 +1350,8 @@ void server_loop(gx_server *S) {
     // cancelled residents: retire after all work enqueued so far has drained
     for (SrvReq *r : S->slots)
       if (r && r->cancel && r->state == RQ_RESIDENT) {
-        for (int li = 0; li < kMaxGroups; ++li) {
+        for (int li = 0; li < kLanes; ++li) {
+          if (!S->lanes[li].s) continue;
           (void)hipEventRecord(S->drain[li], S->lanes[li].s);
           (void)hipStreamWaitEvent(S->s, S->drain[li], 0);
         }
@@ -1354,7 +1380,8 @@ void server_loop(gx_server *S) {
     }
     if (!progressed && !done_any) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
-  for (SrvLane &L : S->lanes) (void)hipStreamSynchronize(L.s);
+  for (SrvLane &L : S->lanes)
+    if (L.s) (void)hipStreamSynchronize(L.s);
   (void)hipStreamSynchronize(S->s);
 }
 
@@ -1393,16 +1420,10 @@ gx_status gx_server_create(gx_ctx *c, const gx_server_cfg *cfg, gx_server **out)
   };
   if (hipStreamCreateWithFlags(&S->s, hipStreamNonBlocking) != hipSuccess) return bail("stream");
   if (hipEventCreateWithFlags(&S->staged, hipEventDisableTiming) != hipSuccess) return bail("events");
-  for (int li = 0; li < kMaxGroups; ++li) {
-    SrvLane &L = S->lanes[li];
-    if (hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&L.ev[0], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&L.ev[1], hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&S->drain[li], hipEventDisableTiming) != hipSuccess)
-      return bail("lane streams");
-  }
-  if (hipMalloc((void **)&S->next, sizeof(uint32_t) * kMaxGroups) != hipSuccess ||
-      hipMemset(S->next, 0, sizeof(uint32_t) * kMaxGroups) != hipSuccess)
+  for (int li = 0; li < kLanes; ++li)
+    if (hipEventCreateWithFlags(&S->drain[li], hipEventDisableTiming) != hipSuccess) return bail("events");
+  if (hipMalloc((void **)&S->next, sizeof(uint32_t) * kLanes) != hipSuccess ||
+      hipMemset(S->next, 0, sizeof(uint32_t) * kLanes) != hipSuccess)
     return bail("work-item counters");
   if (hipMalloc((void **)&S->arena_d, S->cfg.hbm_budget_bytes) != hipSuccess) return bail("arena");
   S->arena.reset(S->cfg.hbm_budget_bytes);
@@ -1451,7 +1472,7 @@ gx_status gx_server_submit(gx_server *S, const gx_instance_desc *d, const gx_sol
   const double n = r->n;
   r->cost = (r->pr.h.kind == KQAP ? 4.0 * n * n / 3.0 : (r->pr.h.kind == KVRP ? 8.0 * n : n)) * r->hj.C;
   r->kind = r->pr.h.kind;
-  r->lane = lane_of(r->kind, (int)r->hj.stage);
+  r->lane = lane_of(r->kind, (int)r->hj.stage, r->hj.lds_bytes);
   if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
     delete r;
     return GX_E_DEVICE;

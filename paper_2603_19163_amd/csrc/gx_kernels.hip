@@ -928,16 +928,53 @@ struct QapK {
   static constexpr bool kRound = true;
   uint16_t *cur, *nxt;
   int n;
-  const int16_t *F, *D;
+  int32_t *FG;     // F[a][b] | D[x_a][x_b] << 16 for the current solution x
+  const int16_t *D;
   uint16_t *xr;    // candidate solutions, element b of lane l at xr[b * 64 + l]
   uint16_t *list;  // (candidate, changed position) entries of a round
+  bool sums32;
+  // FG for rows and columns [lo, hi] (all of it for lo = 0, hi = n - 1)
+  __device__ __forceinline__ void refresh(int lo, int hi) {
+    const int w = hi - lo + 1;
+    for (int i = (int)lane_id(); i < w * n; i += kWave) {
+      const int a = lo + i / n, b = i - (a - lo) * n;
+      int32_t *e1 = FG + a * n + b, *e2 = FG + b * n + a;
+      *e1 = (*e1 & 0xFFFF) | ((int32_t)D[cur[a] * n + cur[b]] << 16);
+      *e2 = (*e2 & 0xFFFF) | ((int32_t)D[cur[b] * n + cur[a]] << 16);
+    }
+    __syncthreads();
+  }
   // Deltas of the 64 candidates of a round (one per lane, k = 0 for an empty
   // lane), wave-collective.  f(y) - f(x) over the changed positions M of a
   // candidate: for every a in M, sum over b of F[a][b] (D[y_a][y_b] -
   // D[x_a][x_b]), counted once for b in M and twice otherwise (F and D are
   // symmetric).  The (candidate, a) entries are listed and shared by all
   // lanes, so the work follows the total number of changed positions rather
-  // than the largest one in the wave.
+  // than the largest one in the wave; F[a][b] and D[x_a][x_b] come in one read.
+  // The entries: for (t, a), with T(b) = F[a][b] (D[y_a][y_b] - D[x_a][x_b])
+  // (|T| < 2^28), the sum over all b twice minus the sum over b in M once.
+  // ACC is int32 when n * max F * max D < 2^31.
+  template <class ACC>
+  __device__ __forceinline__ void entries(uint32_t l, uint32_t total, const unsigned long long *masks,
+                                          long long *dsum) const {
+    for (uint32_t e = l; e < total; e += kWave) {
+      const uint32_t en = list[e], t = en & 63u, a = en >> 6;
+      const uint64_t mt = masks[t];
+      const int ya = xr[a * kWave + t];
+      const int32_t *FGa = FG + a * n;
+      const int16_t *Dy = D + ya * n;
+      ACC all = 0, in = 0;
+#pragma unroll 4
+      for (int b = 0; b < n; ++b) {
+        const int32_t fg = FGa[b];
+        const int tt = __mul24((int)(int16_t)fg, Dy[xr[b * kWave + t]] - (fg >> 16));
+        all += tt;
+        in += ((mt >> b) & 1) ? tt : 0;
+      }
+      const int64_t acc = 2 * (int64_t)all - (int64_t)in;
+      atomicAdd((unsigned long long *)&dsum[t], (unsigned long long)acc);
+    }
+  }
   __device__ __forceinline__ int64_t delta_round(const Step *st, int k) const {
     const uint32_t l = lane_id();
     unsigned long long *masks = (unsigned long long *)(gx_lds + 2048);
@@ -969,23 +1006,17 @@ struct QapK {
     for (int p = 0; p < n; ++p)
       if ((mask >> p) & 1) list[base + __popcll(mask & ((1ull << p) - 1))] = (uint16_t)(l | (p << 6));
     __syncthreads();
-    for (uint32_t e = l; e < total; e += kWave) {
-      const uint32_t en = list[e], t = en & 63u, a = en >> 6;
-      const uint64_t mt = masks[t];
-      const int ya = xr[a * kWave + t], xa = cur[a];
-      const int16_t *Fa = F + a * n, *Dy = D + ya * n, *Dx = D + xa * n;
-      int64_t acc = 0;
-#pragma unroll 4
-      for (int b = 0; b < n; ++b) {
-        const int tt = Fa[b] * (Dy[xr[b * kWave + t]] - Dx[cur[b]]);
-        acc += ((mt >> b) & 1) ? tt : 2 * tt;
-      }
-      atomicAdd((unsigned long long *)&dsum[t], (unsigned long long)acc);
-    }
+    if (sums32) entries<int32_t>(l, total, masks, dsum);
+    else entries<int64_t>(l, total, masks, dsum);
     __syncthreads();
     return dsum[l];
   }
-  __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, st, k); }
+  __device__ __forceinline__ void apply(const Step *st, int k) {
+    int lo, hi;
+    move_range(st, k, lo, hi);
+    perm_apply(cur, nxt, st, k, lo, hi);
+    if (lo <= hi) refresh(lo, hi);
+  }
   __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
 };
 
@@ -1294,14 +1325,15 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       }
       perm_store(t0, n, cur_g);
     } else if constexpr (KIND == KQAP) {
-      int16_t *F = (int16_t *)rest;
-      int16_t *D = (int16_t *)(rest + al16(2 * n * n));
-      uint16_t *xr = (uint16_t *)(rest + 2 * al16(2 * n * n));
-      uint16_t *list = (uint16_t *)(rest + 2 * al16(2 * n * n) + al16(2 * kWave * n));
-      stage16(F, I->qf, 2u * n * n);
+      int32_t *FG = (int32_t *)rest;
+      int16_t *D = (int16_t *)(rest + al16(4 * n * n));
+      uint16_t *xr = (uint16_t *)(rest + al16(4 * n * n) + al16(2 * n * n));
+      uint16_t *list = (uint16_t *)(rest + al16(4 * n * n) + al16(2 * n * n) + al16(2 * kWave * n));
       stage16(D, I->qd, 2u * n * n);
+      for (int i = lane; i < n * n; i += kWave) FG[i] = (uint16_t)I->qf[i];
       __syncthreads();
-      QapK kd{t0, t1, n, F, D, xr, list};
+      QapK kd{t0, t1, n, FG, D, xr, list, I->qap_sums32 != 0};
+      kd.refresh(0, n - 1);
       run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       perm_store(kd.cur, n, cur_g);
     } else {
