@@ -115,6 +115,10 @@ def main():
     ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
     ap.add_argument("--served-generations", type=int, default=10000)
     ap.add_argument("--served-population", type=int, default=4)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="tsp442: skip the batched and served measurements appended to the line")
+    ap.add_argument("--mixed-duration", type=float, default=3.0,
+                    help="tsp442: seconds of served arrivals measured for the line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -135,9 +139,11 @@ def main():
         sys.exit(2)
 
     if args.workload == "batched":
-        return bench_batched(args)
+        print(json.dumps(bench_batched(args)), flush=True)
+        return
     if args.workload == "served":
-        return bench_served(args)
+        print(json.dumps(bench_served(args)), flush=True)
+        return
 
     import torch
     import synth
@@ -227,6 +233,15 @@ def main():
         line["cpu_baseline"] = cpu_baseline(inst, p, args.cpu_seconds)
     gx.gx_instance_free(ctx, h)
     gx.gx_destroy(ctx)
+    if not args.no_mixed:
+        # the second half of the metric: the batched configuration (4096
+        # instances) and the served stream (2000 requests/s, a shorter window),
+        # each against the plain solver on a sample of the same requests
+        mixed = argparse.Namespace(**vars(args))
+        mixed.plain_sample = 8
+        mixed.duration = args.mixed_duration
+        line["batched"] = bench_batched(mixed)
+        line["mixed_stream"] = bench_served(mixed)
     print(json.dumps(line), flush=True)
 
 
@@ -286,7 +301,7 @@ def bench_batched(args):
     for j in jobs:
         gx.gx_job_free(ctx, j)
     gx.gx_destroy(ctx)
-    print(json.dumps({
+    return {
         "metric": "batched solves/s", "value": count / dt, "unit": "solves/s",
         "move_evals_per_s": evals / dt, "seconds": dt,
         "plain_solves_per_s": 1.0 / plain_dt, "speedup_vs_plain": plain_dt * count / dt,
@@ -294,8 +309,8 @@ def bench_batched(args):
         "config": {"workload": f"{count} instances: {n_tsp} TSP n U[20,200] + {count - n_tsp} QAP n "
                                f"U[12,40]; P={P} each (sized to fill {cus} CUs), "
                                f"C=128, {G} generations; staging per bucket {sorted(set(staging.values()))}",
-                   "population": P, "generations": G},
-    }), flush=True)
+                   "population": P, "generations": G, "staging_per_bucket": staging},
+    }
 
 
 def bench_served(args):
@@ -361,8 +376,10 @@ def bench_served(args):
         gx.gx_job_free(ctx, job)
         gx.gx_instance_free(ctx, h)
     gx.gx_destroy(ctx)
-    print(json.dumps({
+    offered = args.rate * args.served_population * 128 * G
+    return {
         "metric": "served solves/s", "value": len(results) / (t_end - t0), "unit": "solves/s",
+        "offered_move_evals_per_s": offered,
         "offered_rate": args.rate, "submitted": n_req, "completed": len(results),
         "arrival_seconds": t_sub_end - t0, "drain_seconds": t_end - t_sub_end,
         "p50_s": _pct(lat, 50), "p99_s": _pct(lat, 99),
@@ -373,7 +390,7 @@ def bench_served(args):
         "server": stats,
         "config": {"workload": f"Poisson {args.rate}/s for {args.duration}s: TSP n U[20,500], QAP n "
                                f"U[12,50], knapsack n U[100,1000]; P={P}, C=128, {G} generations each"},
-    }), flush=True)
+    }
 
 
 if __name__ == "__main__":
