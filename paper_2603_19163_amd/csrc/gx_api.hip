@@ -227,7 +227,7 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
           return fail(c, GX_E_INVALID, "QAP matrices must be symmetric with entries in [0, 16384)");
       }
     const int64_t mf = *std::max_element(A.begin(), A.end()), md = *std::max_element(B.begin(), B.end());
-    h.qap_sums32 = (int64_t)n * mf * md < (int64_t(1) << 31);
+    h.qap_sums32 = 2 * (int64_t)n * mf * md < (int64_t(1) << 31);
     add_arr(pr, F_QF, std::vector<int16_t>(A.begin(), A.end()));
     add_arr(pr, F_QD, std::vector<int16_t>(B.begin(), B.end()));
     fbound = 4.0 * n * n * 16384.0 * 16384.0;

@@ -28,7 +28,7 @@ struct DevInst {
   int32_t kind, n, dn, n_edges;
   int32_t capacity, vehicles, service, horizon;
   int32_t lb, ub, has_xy;
-  int32_t qap_sums32;         // QAP: n * max F * max D < 2^31 (delta row sums fit int32)
+  int32_t qap_sums32;         // QAP: 2 n * max F * max D < 2^31 (delta row and pair sums fit int32)
   int64_t lambda;             // knapsack penalty weight
   const int32_t *xy;          // TSP n x 2 / VRPTW (n+1) x 2 coordinates
   const int16_t *d16;         // TSP n x n / VRPTW dn x dn distances (int16)
@@ -85,7 +85,10 @@ inline uint32_t lds_bytes_for(int kind, int n, int stage) {
       else if (stage == SLDSXY) b += al(4 * un) + al(2 * un);   // coordinates, edge lengths
       return b;
     }
-    case KQAP: return tables + tours + al(4 * un * un) + al(2 * un * un) + 2 * al(2 * kWave * un);   // F|D(x), D, candidates, entries
+    case KQAP: {   // F and D(x) rows padded to 8, row constants, entry segments and lists
+      const uint32_t np = (un + 7u) & ~7u;
+      return tables + tours + 2 * al(2 * un * np) + al(8 * un) + 4 * kWave + al(kWave * un) + al(2 * kWave * un);
+    }
     case KKNAP: return tables + al(un) + 2 * al(4 * un);
     case KVRP: return tables + tours + al(2 * (un + 1) * (un + 1)) + 3 * al(4 * (un + 1));
     default: return tables + al(2 * un) + al(4 * (un + 1));   // + adjacency, added by the caller

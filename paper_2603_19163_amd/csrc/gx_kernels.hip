@@ -923,75 +923,157 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
 
 // ------------------------------------------------------------ generation loop
 // ------------------------------------------------------------ QAP
+// Positions changed by one step (a superset is enough for the delta below):
+// a reversal of [a, b] moves every position but its middle one, a swap two,
+// a block move the range [min(i, q), max(i, q) + L).
+__device__ __forceinline__ uint64_t range_bits(int lo, int hi) {   // bits lo..hi, empty for lo > hi
+  return lo > hi ? 0ull : (2ull << hi) - (1ull << lo);
+}
+__device__ __forceinline__ uint64_t step_bits(const Step &s) {
+  if (s.op == OSWAP) return s.a == s.b ? 0ull : (1ull << s.a) | (1ull << s.b);
+  if (s.op < OINS) {
+    const uint64_t mid = ((s.a + s.b) & 1) ? 0ull : 1ull << ((s.a + s.b) >> 1);
+    return range_bits(s.a, s.b) & ~mid;
+  }
+  return (s.c == 0 || s.a == s.b) ? 0ull : range_bits(min(s.a, s.b), max(s.a, s.b) + s.c - 1);
+}
+
+// A step's position map in 8 bytes (every field of a map over n <= 64 fits a byte).
+__device__ __forceinline__ uint2 smap_pack(const SMap &M) {
+  const uint32_t lo = (uint32_t)(M.s1 & 255) | (uint32_t)(M.len & 255) << 8 | (uint32_t)(M.e1 & 255) << 16 |
+                      (uint32_t)(M.e1b & 255) << 24;
+  const uint32_t hi = (uint32_t)(M.neg & 255) | (uint32_t)(M.o1 & 255) << 8 | (uint32_t)(M.o2 & 255) << 16;
+  return make_uint2(lo, hi);
+}
+__device__ __forceinline__ SMap smap_unpack(uint2 v) {
+  SMap M;
+  M.s1 = (int)(int8_t)(v.x & 255u);
+  M.len = (int)(int8_t)((v.x >> 8) & 255u);
+  M.e1 = (int)(int8_t)((v.x >> 16) & 255u);
+  M.e1b = (int)(int8_t)(v.x >> 24);
+  M.neg = (int)(int8_t)(v.y & 255u);
+  M.o1 = (int)(int8_t)((v.y >> 8) & 255u);
+  M.o2 = (int)(int8_t)((v.y >> 16) & 255u);
+  return M;
+}
+
+// f(x) = sum_{a,b} F[a][b] D[x_a][x_b] with F and D symmetric.  For a
+// candidate y = x o q that agrees with x outside a position set M (any
+// superset of the changed positions), splitting the pairs by membership in M
+// gives
+//   delta = sum_{a in M} ( 2 G_a + sum_{b in M} F[a][b] S_ab ),
+//   G_a   = sum_b F[a][b] (D[y_a][x_b] - D[x_a][x_b]),
+//   S_ab  = D[y_a][y_b] - D[y_a][x_b] - D[x_a][y_b] + D[x_a][x_b]   (S_ab = S_ba).
+// With DX[v][c] = D[v][x_c] kept for the current solution and
+// R_a = sum_b F[a][b] DX[x_a][b], G_a = <F row a, DX row y_a> - R_a: a dense
+// row product (int16 pairs, 2-term dot products), and y_b = x at q_b makes
+// D[y_a][y_b] = DX[y_a][q_b].  The pair sum runs over unordered pairs.
 struct QapK {
   static constexpr int ENC = 0;
   static constexpr bool kRound = true;
   uint16_t *cur, *nxt;
-  int n;
-  int32_t *FG;     // F[a][b] | D[x_a][x_b] << 16 for the current solution x
-  const int16_t *D;
-  uint16_t *xr;    // candidate solutions, element b of lane l at xr[b * 64 + l]
-  uint16_t *list;  // (candidate, changed position) entries of a round
-  bool sums32;
-  // FG for rows and columns [lo, hi] (all of it for lo = 0, hi = n - 1)
-  __device__ __forceinline__ void refresh(int lo, int hi) {
-    const int w = hi - lo + 1;
-    for (int i = (int)lane_id(); i < w * n; i += kWave) {
-      const int a = lo + i / n, b = i - (a - lo) * n;
-      int32_t *e1 = FG + a * n + b, *e2 = FG + b * n + a;
-      *e1 = (*e1 & 0xFFFF) | ((int32_t)D[cur[a] * n + cur[b]] << 16);
-      *e2 = (*e2 & 0xFFFF) | ((int32_t)D[cur[b] * n + cur[a]] << 16);
+  int n, np;             // np: n rounded up to 8 (row stride of F and DX)
+  const int16_t *F;      // F[a][b] at a * np + b, zero for b >= n
+  int16_t *DX;           // D[v][x_c] at v * np + c, zero for c >= n
+  long long *R;          // R_a
+  const int16_t *Dg;     // D in global memory, n x n
+  uint32_t *seg;         // per candidate of a round: first entry | count << 16
+  uint8_t *tv;           // candidate of each entry
+  uint16_t *ent;         // position a | q_a << 6 of each entry
+  bool sums32;           // 2 n max F max D < 2^31: row products and pair sums fit int32
+
+  // <F row a, DX row v> over np columns
+  template <class ACC>
+  __device__ __forceinline__ ACC row_dot(int a, int v) const {
+    const uint4 *fa = (const uint4 *)(F + a * np), *dv = (const uint4 *)(DX + v * np);
+    ACC acc = 0;
+#pragma unroll 2
+    for (int i = 0; i < (np >> 3); ++i) {
+      const uint4 f = fa[i], d = dv[i];
+      int s = sizeof(ACC) == 4 ? (int)acc : 0;   // 8 products < 2^31 for entries < 2^14
+      s = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, f.x), __builtin_bit_cast(s16x2, d.x), s, false);
+      s = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, f.y), __builtin_bit_cast(s16x2, d.y), s, false);
+      s = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, f.z), __builtin_bit_cast(s16x2, d.z), s, false);
+      s = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, f.w), __builtin_bit_cast(s16x2, d.w), s, false);
+      if constexpr (sizeof(ACC) == 4) acc = s;
+      else acc += s;
     }
+    return acc;
+  }
+  // R for every row, after DX or the solution changed
+  __device__ __forceinline__ void rows() {
+    const int a = (int)lane_id();
+    if (a < n) R[a] = sums32 ? (long long)row_dot<int32_t>(a, cur[a]) : row_dot<int64_t>(a, cur[a]);
     __syncthreads();
   }
-  // Deltas of the 64 candidates of a round (one per lane, k = 0 for an empty
-  // lane), wave-collective.  f(y) - f(x) over the changed positions M of a
-  // candidate: for every a in M, sum over b of F[a][b] (D[y_a][y_b] -
-  // D[x_a][x_b]), counted once for b in M and twice otherwise (F and D are
-  // symmetric).  The (candidate, a) entries are listed and shared by all
-  // lanes, so the work follows the total number of changed positions rather
-  // than the largest one in the wave; F[a][b] and D[x_a][x_b] come in one read.
-  // The entries: for (t, a), with T(b) = F[a][b] (D[y_a][y_b] - D[x_a][x_b])
-  // (|T| < 2^28), the sum over all b twice minus the sum over b in M once.
-  // ACC is int32 when n * max F * max D < 2^31.
+  // DX columns [lo, hi] from the current solution (lanes are columns)
+  __device__ __forceinline__ void refresh(int lo, int hi) {
+    const int c = lo + (int)lane_id();
+    if (c <= hi) {
+      const int16_t *col = Dg + cur[c];
+#pragma unroll 8
+      for (int v = 0; v < n; ++v) DX[v * np + c] = col[v * n];
+    }
+    __syncthreads();
+    rows();
+  }
+  // F and DX for the current solution; `tmp` holds 2 n^2 bytes (16-padded)
+  __device__ __forceinline__ void setup(const int16_t *Fg, int16_t *tmp) {
+    const int c = (int)lane_id();
+    stage16(tmp, Fg, 2u * n * n);
+    __syncthreads();
+    if (c < np)
+      for (int a = 0; a < n; ++a) ((int16_t *)F)[a * np + c] = c < n ? tmp[a * n + c] : (int16_t)0;
+    __syncthreads();
+    stage16(tmp, Dg, 2u * n * n);
+    __syncthreads();
+    if (c < np) {
+      const int xc = c < n ? cur[c] : 0;
+      for (int v = 0; v < n; ++v) DX[v * np + c] = c < n ? tmp[v * n + xc] : (int16_t)0;
+    }
+    __syncthreads();
+    rows();
+  }
+
   template <class ACC>
-  __device__ __forceinline__ void entries(uint32_t l, uint32_t total, const unsigned long long *masks,
-                                          long long *dsum) const {
+  __device__ __forceinline__ void entries(uint32_t l, uint32_t total, long long *dsum) const {
     for (uint32_t e = l; e < total; e += kWave) {
-      const uint32_t en = list[e], t = en & 63u, a = en >> 6;
-      const uint64_t mt = masks[t];
-      const int ya = xr[a * kWave + t];
-      const int32_t *FGa = FG + a * n;
-      const int16_t *Dy = D + ya * n;
-      ACC all = 0, in = 0;
-#pragma unroll 4
-      for (int b = 0; b < n; ++b) {
-        const int32_t fg = FGa[b];
-        const int tt = __mul24((int)(int16_t)fg, Dy[xr[b * kWave + t]] - (fg >> 16));
-        all += tt;
-        in += ((mt >> b) & 1) ? tt : 0;
+      const uint32_t t = tv[e], en = ent[e], a = en & 63u, q = en >> 6;
+      const uint32_t sg = seg[t], base = sg & 0xFFFFu, cnt = sg >> 16;
+      const int ya = cur[q], xa = cur[a];
+      const int16_t *Dy = DX + ya * np, *Dx = DX + xa * np, *Fa = F + a * np;
+      const long long G = (long long)row_dot<ACC>((int)a, ya) - R[a];
+      // diagonal term, then the pairs (e, e + s) for s = 1 .. (cnt - 1) / 2
+      // around the candidate's entries, plus the opposite entry once when
+      // cnt is even
+      ACC c1 = (ACC)Fa[a] * (ACC)(Dy[q] - 2 * Dy[a] + Dx[a]), c2 = 0;
+      const uint32_t i = e - base, h = (cnt - 1) >> 1;
+      const uint32_t steps = h + ((cnt & 1) == 0 && 2 * i < cnt ? 1u : 0u);
+      uint32_t ii = i;
+      for (uint32_t s = 0; s < steps; ++s) {
+        ii = ii + 1 == cnt ? 0u : ii + 1;
+        const uint32_t eb = ent[base + ii], b = eb & 63u, qb = eb >> 6;
+        const int S = Dy[qb] - Dy[b] - Dx[qb] + Dx[b];
+        c2 += (ACC)(Fa[b] * S);
       }
-      const int64_t acc = 2 * (int64_t)all - (int64_t)in;
-      atomicAdd((unsigned long long *)&dsum[t], (unsigned long long)acc);
+      atomicAdd((unsigned long long *)&dsum[t], (unsigned long long)(2 * G + (long long)c1 + 2 * (long long)c2));
     }
   }
+  // Deltas of the 64 candidates of a round (one per lane, k = 0 for an empty
+  // lane), wave-collective: the (candidate, position) entries of all lanes are
+  // listed and shared, so the work follows the total number of changed
+  // positions rather than the largest one in the wave.
   __device__ __forceinline__ int64_t delta_round(const Step *st, int k) const {
     const uint32_t l = lane_id();
-    unsigned long long *masks = (unsigned long long *)(gx_lds + 2048);
-    long long *dsum = (long long *)(gx_lds + 2560);
-    SMap M[3];
+    long long *dsum = (long long *)(gx_lds + 1536);
+    uint2 *maps = (uint2 *)(gx_lds + 2048);
+    uint64_t mask = 0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      M[m] = smap(st[m].op, st[m].a, st[m].b, st[m].c);
-      if (m >= k) M[m].len = 0;   // identity
-    }
-    uint64_t mask = 0;
-#pragma unroll 2
-    for (int p = 0; p < n; ++p) {
-      const int q = sapply(M[0], sapply(M[1], sapply(M[2], p)));
-      const int v = cur[q];
-      xr[p * kWave + l] = (uint16_t)v;
-      mask |= (uint64_t)(v != cur[p]) << p;
+      SMap M = smap(st[m].op, st[m].a, st[m].b, st[m].c);
+      if (m >= k) M.len = 0;   // identity
+      maps[3 * l + m] = smap_pack(M);
+      mask |= m < k ? step_bits(st[m]) : 0ull;
     }
     const uint32_t cnt = (uint32_t)__popcll(mask);
     uint32_t incl = cnt;
@@ -1001,13 +1083,25 @@ struct QapK {
       incl += l >= (uint32_t)o ? v : 0u;
     }
     const uint32_t base = incl - cnt, total = uni(__shfl(incl, kWave - 1, kWave));
-    masks[l] = mask;
+    seg[l] = base | cnt << 16;
     dsum[l] = 0;
-    for (int p = 0; p < n; ++p)
-      if ((mask >> p) & 1) list[base + __popcll(mask & ((1ull << p) - 1))] = (uint16_t)(l | (p << 6));
+    for (uint32_t j = base; mask; ++j) {
+      tv[j] = (uint8_t)l;
+      ent[j] = (uint16_t)__builtin_ctzll(mask);
+      mask &= mask - 1;
+    }
     __syncthreads();
-    if (sums32) entries<int32_t>(l, total, masks, dsum);
-    else entries<int64_t>(l, total, masks, dsum);
+    // q_a of every entry through the candidate's maps
+    for (uint32_t e = l; e < total; e += kWave) {
+      const uint32_t t = tv[e];
+      const int a = ent[e];
+      const SMap M0 = smap_unpack(maps[3 * t]), M1 = smap_unpack(maps[3 * t + 1]), M2 = smap_unpack(maps[3 * t + 2]);
+      const int q = sapply(M0, sapply(M1, sapply(M2, a)));
+      ent[e] = (uint16_t)(a | q << 6);
+    }
+    __syncthreads();
+    if (sums32) entries<int32_t>(l, total, dsum);
+    else entries<int64_t>(l, total, dsum);
     __syncthreads();
     return dsum[l];
   }
@@ -1325,15 +1419,16 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       }
       perm_store(t0, n, cur_g);
     } else if constexpr (KIND == KQAP) {
-      int32_t *FG = (int32_t *)rest;
-      int16_t *D = (int16_t *)(rest + al16(4 * n * n));
-      uint16_t *xr = (uint16_t *)(rest + al16(4 * n * n) + al16(2 * n * n));
-      uint16_t *list = (uint16_t *)(rest + al16(4 * n * n) + al16(2 * n * n) + al16(2 * kWave * n));
-      stage16(D, I->qd, 2u * n * n);
-      for (int i = lane; i < n * n; i += kWave) FG[i] = (uint16_t)I->qf[i];
+      const int np = (n + 7) & ~7;
+      int16_t *F = (int16_t *)rest;
+      int16_t *DX = (int16_t *)(rest + al16(2 * n * np));
+      long long *R = (long long *)(rest + 2 * al16(2 * n * np));
+      uint32_t *seg = (uint32_t *)(rest + 2 * al16(2 * n * np) + al16(8 * n));
+      uint8_t *tv = (uint8_t *)(rest + 2 * al16(2 * n * np) + al16(8 * n) + 4 * kWave);
+      uint16_t *ent = (uint16_t *)(rest + 2 * al16(2 * n * np) + al16(8 * n) + 4 * kWave + al16(kWave * n));
+      QapK kd{t0, t1, n, np, F, DX, R, I->qd, seg, tv, ent, I->qap_sums32 != 0};
       __syncthreads();
-      QapK kd{t0, t1, n, FG, D, xr, list, I->qap_sums32 != 0};
-      kd.refresh(0, n - 1);
+      kd.setup(I->qf, (int16_t *)tv);   // the entry lists (192 n bytes) stage the matrices
       run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       perm_store(kd.cur, n, cur_g);
     } else {

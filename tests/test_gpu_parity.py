@@ -124,6 +124,29 @@ def test_accepted_only_credit(ctx):
           [30], "credit=1")
 
 
+def _qap_wide(n, seed):
+    """QAP with entries up to 2^14 - 1 and non-zero diagonals: the delta sums
+    leave int32, so the 64-bit accumulation path runs."""
+    r = np.random.default_rng([seed, n, 20260319])
+    F = r.integers(0, 16384, (n, n))
+    D = r.integers(0, 16384, (n, n))
+    F = np.triu(F) + np.triu(F, 1).T
+    D = np.triu(D) + np.triu(D, 1).T
+    return synth.Instance(synth.QAP, n, F, D, key=seed)
+
+
+def test_qap_wide_values(ctx):
+    check(ctx, _qap_wide(21, 3), P(seed=6, population=4, candidates=128, G=30, op_mask=synth.PERM_OPS),
+          [10, 20], "qap wide values")
+
+
+@pytest.mark.parametrize("n", [37, 48])
+def test_qap_ragged_rows(ctx, n):
+    # rows padded to a multiple of 8 (37 -> 40) and an exact multiple (48)
+    check(ctx, synth.qap_random(n, 5, key=n), P(seed=n, population=3, candidates=128, G=25, op_mask=synth.PERM_OPS),
+          [25], f"qap n={n}")
+
+
 def test_greedy_and_random_walk_limits(ctx):
     check(ctx, synth.tsp_uniform(25, 5, key=1), P(seed=2, population=3, candidates=64, G=20, t0_q16=1), [20], "greedy")
     check(ctx, synth.knapsack_random(40, 5, key=1),
