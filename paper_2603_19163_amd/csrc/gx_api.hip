@@ -228,6 +228,7 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
       }
     const int64_t mf = *std::max_element(A.begin(), A.end()), md = *std::max_element(B.begin(), B.end());
     h.qap_sums32 = 2 * (int64_t)n * mf * md < (int64_t(1) << 31);
+    h.qap_h16 = (int64_t)n * mf * md < (int64_t(1) << 16);
     add_arr(pr, F_QF, std::vector<int16_t>(A.begin(), A.end()));
     add_arr(pr, F_QD, std::vector<int16_t>(B.begin(), B.end()));
     fbound = 4.0 * n * n * 16384.0 * 16384.0;
@@ -448,6 +449,7 @@ InstInfo info_of(const gx_instance *in) {
 }
 
 uint32_t resolve_stage(const InstInfo &ii, uint32_t req) {
+  if (ii.h.kind == KQAP) return ii.h.qap_h16 ? 1u : 0u;   // 16-bit row sums when they fit
   if (ii.h.kind != KTSP) return 0;
   if (req != SAUTO) return req;
   // Coordinates in LDS keep the footprint at 6n + 2n bytes, so a CU holds
@@ -1115,10 +1117,10 @@ struct SrvLane {
 };
 
 // lanes: (kind, staging) x LDS class
-constexpr int kLanes = 8 * kLdsClasses;
+constexpr int kLanes = 9 * kLdsClasses;
 int lane_of(int kind, int stage, uint32_t lds) {
   const int ks = kind == KTSP ? std::min(std::max(stage, 1), 4) - 1
-                              : (kind == KQAP ? 4 : (kind == KKNAP ? 5 : (kind == KVRP ? 6 : 7)));
+                              : (kind == KQAP ? 4 + (stage == 1) : (kind == KKNAP ? 6 : (kind == KVRP ? 7 : 8)));
   return ks * kLdsClasses + lds_class(lds);
 }
 

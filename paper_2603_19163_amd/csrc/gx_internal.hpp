@@ -15,6 +15,7 @@ constexpr int kOps = 6;
 constexpr int kShards = 64;
 constexpr int kEpochSlots = 20;
 constexpr int kMaxQapN = 64;
+constexpr uint32_t kQapListPerN = 24;   // QAP entry-list capacity per window: 24 n entries
 constexpr int kMaxVrpN = 250;
 constexpr int kMaxCoord = 1 << 14;
 constexpr int64_t kDeltaBias = int64_t(1) << 47;   // argmin key = ((delta + bias) << 16) | t
@@ -29,6 +30,7 @@ struct DevInst {
   int32_t capacity, vehicles, service, horizon;
   int32_t lb, ub, has_xy;
   int32_t qap_sums32;         // QAP: 2 n * max F * max D < 2^31 (delta row and pair sums fit int32)
+  int32_t qap_h16, pad_q;     // QAP: n * max F * max D < 2^16 (row sums H fit 16 bits: staging 1)
   int64_t lambda;             // knapsack penalty weight
   const int32_t *xy;          // TSP n x 2 / VRPTW (n+1) x 2 coordinates
   const int16_t *d16;         // TSP n x n / VRPTW dn x dn distances (int16)
@@ -85,9 +87,10 @@ inline uint32_t lds_bytes_for(int kind, int n, int stage) {
       else if (stage == SLDSXY) b += al(4 * un) + al(2 * un);   // coordinates, edge lengths
       return b;
     }
-    case KQAP: {   // F and D(x) rows padded to 8, row constants, entry segments and lists
-      const uint32_t np = (un + 7u) & ~7u;
-      return tables + tours + 2 * al(2 * un * np) + al(8 * un) + 4 * kWave + al(kWave * un) + al(2 * kWave * un);
+    case KQAP: {   // F and D(x) rows padded to 8, row sums H (16-bit for staging 1), segments, lists
+      const uint32_t np = (un + 7u) & ~7u, lst = kQapListPerN * un;   // entry-list capacity per window
+      return tables + tours + 2 * al(2 * un * np) + al((stage == 1 ? 2u : 4u) * un * un) + 8 * kWave + al(lst) +
+             al(2 * lst);
     }
     case KKNAP: return tables + al(un) + 2 * al(4 * un);
     case KVRP: return tables + tours + al(2 * (un + 1) * (un + 1)) + 3 * al(4 * (un + 1));

@@ -16,6 +16,7 @@
 #include "gx_internal.hpp"
 
 #include <climits>
+#include <type_traits>
 
 using namespace gx;
 
@@ -962,12 +963,16 @@ __device__ __forceinline__ SMap smap_unpack(uint2 v) {
 // superset of the changed positions), splitting the pairs by membership in M
 // gives
 //   delta = sum_{a in M} ( 2 G_a + sum_{b in M} F[a][b] S_ab ),
-//   G_a   = sum_b F[a][b] (D[y_a][x_b] - D[x_a][x_b]),
-//   S_ab  = D[y_a][y_b] - D[y_a][x_b] - D[x_a][y_b] + D[x_a][x_b]   (S_ab = S_ba).
-// With DX[v][c] = D[v][x_c] kept for the current solution and
-// R_a = sum_b F[a][b] DX[x_a][b], G_a = <F row a, DX row y_a> - R_a: a dense
-// row product (int16 pairs, 2-term dot products), and y_b = x at q_b makes
-// D[y_a][y_b] = DX[y_a][q_b].  The pair sum runs over unordered pairs.
+//   G_a   = sum_b F[a][b] (D[y_a][x_b] - D[x_a][x_b]) = H[a][y_a] - H[a][x_a],
+//   S_ab  = D[y_a][y_b] - D[y_a][x_b] - D[x_a][y_b] + D[x_a][x_b]   (S_ab = S_ba),
+// with DX[v][c] = D[v][x_c] and H[a][v] = sum_b F[a][b] DX[v][b] kept for the
+// current solution x (a move changes the columns of DX in its range, and H by
+// F times the column differences), and D[y_a][y_b] = DX[y_a][q_b].  The pair
+// sum runs over unordered pairs.  H entries lie in [0, n max F max D]: 16-bit
+// storage when that is below 2^16 (HT = uint16_t), else 32-bit.  When the
+// sums can leave int32 (wide entries), H is not kept: G_a is the row product
+// <F row a, DX row y_a> minus R_a = <F row a, DX row x_a> in 64-bit arithmetic.
+template <class HT>
 struct QapK {
   static constexpr int ENC = 0;
   static constexpr bool kRound = true;
@@ -975,12 +980,14 @@ struct QapK {
   int n, np;             // np: n rounded up to 8 (row stride of F and DX)
   const int16_t *F;      // F[a][b] at a * np + b, zero for b >= n
   int16_t *DX;           // D[v][x_c] at v * np + c, zero for c >= n
-  long long *R;          // R_a
-  const int16_t *Dg;     // D in global memory, n x n
-  uint32_t *seg;         // per candidate of a round: first entry | count << 16
+  HT *H;                 // H[a][v] at a * n + v (int32 sums)
+  long long *R;          // R_a (64-bit sums), in the space of H
+  const int16_t *Dg;     // D in global memory (n x n)
+  uint32_t *seg;         // per candidate of a window: first entry | count << 16
+  uint32_t *rb;          // first entry of the candidate of each rank
   uint8_t *tv;           // candidate of each entry
-  uint16_t *ent;         // position a | q_a << 6 of each entry
-  bool sums32;           // 2 n max F max D < 2^31: row products and pair sums fit int32
+  uint16_t *ent;         // byte offsets 2a | 2q_a << 8 of each entry (position a)
+  bool sums32;           // 2 n max F max D < 2^31: H, G and the pair sums fit int32
 
   // <F row a, DX row v> over np columns
   template <class ACC>
@@ -1000,26 +1007,21 @@ struct QapK {
     }
     return acc;
   }
-  // R for every row, after DX or the solution changed
-  __device__ __forceinline__ void rows() {
-    const int a = (int)lane_id();
-    if (a < n) R[a] = sums32 ? (long long)row_dot<int32_t>(a, cur[a]) : row_dot<int64_t>(a, cur[a]);
-    __syncthreads();
-  }
-  // DX columns [lo, hi] from the current solution (lanes are columns)
-  __device__ __forceinline__ void refresh(int lo, int hi) {
-    const int c = lo + (int)lane_id();
-    if (c <= hi) {
-      const int16_t *col = Dg + cur[c];
-#pragma unroll 8
-      for (int v = 0; v < n; ++v) DX[v * np + c] = col[v * n];
+  // H (int32 sums) or R (64-bit sums) from F and DX; lane v < n owns column v of H
+  __device__ __forceinline__ void build_sums() {
+    const int v = (int)lane_id();
+    if (sums32) {
+      if (v < n)
+        for (int a = 0; a < n; ++a) H[a * n + v] = (HT)row_dot<int32_t>(a, v);
+    } else if (v < n) {
+      R[v] = row_dot<int64_t>(v, cur[v]);
     }
     __syncthreads();
-    rows();
   }
-  // F and DX for the current solution; `tmp` holds 2 n^2 bytes (16-padded)
-  __device__ __forceinline__ void setup(const int16_t *Fg, int16_t *tmp) {
+  // F and DX for the current solution, staged through the space of H
+  __device__ __forceinline__ void setup(const int16_t *Fg) {
     const int c = (int)lane_id();
+    int16_t *tmp = (int16_t *)H;   // holds 2 n^2 bytes (16-padded)
     stage16(tmp, Fg, 2u * n * n);
     __syncthreads();
     if (c < np)
@@ -1032,29 +1034,45 @@ struct QapK {
       for (int v = 0; v < n; ++v) DX[v * np + c] = c < n ? tmp[v * n + xc] : (int16_t)0;
     }
     __syncthreads();
-    rows();
+    build_sums();
   }
 
   template <class ACC>
   __device__ __forceinline__ void entries(uint32_t l, uint32_t total, long long *dsum) const {
     for (uint32_t e = l; e < total; e += kWave) {
-      const uint32_t t = tv[e], en = ent[e], a = en & 63u, q = en >> 6;
+      const uint32_t t = tv[e], en = ent[e], a = (en & 255u) >> 1, q = en >> 9;
       const uint32_t sg = seg[t], base = sg & 0xFFFFu, cnt = sg >> 16;
       const int ya = cur[q], xa = cur[a];
       const int16_t *Dy = DX + ya * np, *Dx = DX + xa * np, *Fa = F + a * np;
-      const long long G = (long long)row_dot<ACC>((int)a, ya) - R[a];
+      long long G;
+      if constexpr (sizeof(ACC) == 4) G = (long long)((int)H[a * n + ya] - (int)H[a * n + xa]);
+      else G = row_dot<int64_t>((int)a, ya) - R[a];
       // diagonal term, then the pairs (e, e + s) for s = 1 .. (cnt - 1) / 2
       // around the candidate's entries, plus the opposite entry once when
       // cnt is even
       ACC c1 = (ACC)Fa[a] * (ACC)(Dy[q] - 2 * Dy[a] + Dx[a]), c2 = 0;
       const uint32_t i = e - base, h = (cnt - 1) >> 1;
       const uint32_t steps = h + ((cnt & 1) == 0 && 2 * i < cnt ? 1u : 0u);
-      uint32_t ii = i;
-      for (uint32_t s = 0; s < steps; ++s) {
-        ii = ii + 1 == cnt ? 0u : ii + 1;
-        const uint32_t eb = ent[base + ii], b = eb & 63u, qb = eb >> 6;
-        const int S = Dy[qb] - Dy[b] - Dx[qb] + Dx[b];
-        c2 += (ACC)(Fa[b] * S);
+      // four pairs per pass, so that their reads are in flight together; a
+      // pass past the last pair reads entries of the candidate and adds nothing
+      // (entries hold byte offsets into the int16 rows)
+      const char *Fab = (const char *)Fa, *Dyb = (const char *)Dy, *Dxb = (const char *)Dx;
+      const uint16_t *ec = ent + base;
+      uint32_t jj = i;
+      for (uint32_t s = 0; s < steps; s += 4) {
+        uint32_t eb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          jj = jj + 1 == cnt ? 0u : jj + 1;
+          eb[u] = ec[jj];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {   // loads on every lane, masked sum (no branch around them)
+          const uint32_t ob = eb[u] & 255u, oq = eb[u] >> 8;
+          const int S = *(const int16_t *)(Dyb + oq) - *(const int16_t *)(Dyb + ob) - *(const int16_t *)(Dxb + oq) +
+                        *(const int16_t *)(Dxb + ob);
+          c2 += (ACC)((*(const int16_t *)(Fab + ob) * S) & -(int)(s + u < steps));
+        }
       }
       atomicAdd((unsigned long long *)&dsum[t], (unsigned long long)(2 * G + (long long)c1 + 2 * (long long)c2));
     }
@@ -1062,64 +1080,167 @@ struct QapK {
   // Deltas of the 64 candidates of a round (one per lane, k = 0 for an empty
   // lane), wave-collective: the (candidate, position) entries of all lanes are
   // listed and shared, so the work follows the total number of changed
-  // positions rather than the largest one in the wave.
-  __device__ __forceinline__ int64_t delta_round(const Step *st, int k) const {
+  // positions rather than the largest one in the wave.  Candidates with more
+  // changed positions are listed first, so that the entries processed
+  // together belong to candidates with similar pair counts; a round with more
+  // entries than the list holds is processed in windows of whole candidates.
+  __device__ __forceinline__ int64_t delta_round(const TspScratch &W, int tl, int k) const {
     const uint32_t l = lane_id();
     long long *dsum = (long long *)(gx_lds + 1536);
+    uint32_t *tmp = (uint32_t *)dsum;
     uint2 *maps = (uint2 *)(gx_lds + 2048);
+    const uint32_t cap = kQapListPerN * (uint32_t)n;
     uint64_t mask = 0;
+    {
+      Step st[3];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-      SMap M = smap(st[m].op, st[m].a, st[m].b, st[m].c);
-      if (m >= k) M.len = 0;   // identity
-      maps[3 * l + m] = smap_pack(M);
-      mask |= m < k ? step_bits(st[m]) : 0ull;
+      for (int m = 0; m < 3; ++m) st[m] = load_step<ENC>(W, tl, m);
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        SMap M = smap(st[m].op, st[m].a, st[m].b, st[m].c);
+        if (m >= k) M.len = 0;   // identity
+        maps[3 * l + m] = smap_pack(M);
+        mask |= m < k ? step_bits(st[m]) : 0ull;
+      }
     }
     const uint32_t cnt = (uint32_t)__popcll(mask);
-    uint32_t incl = cnt;
+    const uint32_t cls = cnt >= 24 ? 0u : (cnt >= 12 ? 1u : (cnt >= 6 ? 2u : (cnt >= 3 ? 3u : 4u)));
+    uint32_t rank = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < 5; ++c) {
+      const unsigned long long mc = __ballot(cls == c);
+      rank += c < cls ? (uint32_t)__popcll(mc) : (c == cls ? lanes_below(mc) : 0u);
+    }
+    tmp[rank] = cnt;
+    __syncthreads();
+    const uint32_t cr = tmp[l];   // lanes in rank order from here
+    uint32_t incl = cr;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
       const uint32_t v = __shfl_up(incl, o, kWave);
       incl += l >= (uint32_t)o ? v : 0u;
     }
-    const uint32_t base = incl - cnt, total = uni(__shfl(incl, kWave - 1, kWave));
-    seg[l] = base | cnt << 16;
+    rb[l] = incl - cr;
+    __syncthreads();
+    const uint32_t base = rb[rank];
     dsum[l] = 0;
-    for (uint32_t j = base; mask; ++j) {
-      tv[j] = (uint8_t)l;
-      ent[j] = (uint16_t)__builtin_ctzll(mask);
-      mask &= mask - 1;
+    for (uint32_t r0 = 0; r0 < (uint32_t)kWave;) {
+      // the window: ranks r0 .. r1-1, as many whole candidates as the list holds
+      const uint32_t wb = uni(__shfl(incl - cr, r0, kWave));
+      const unsigned long long mw = __ballot(l >= r0 && incl - wb <= cap);
+      const uint32_t r1 = r0 + (uint32_t)__popcll(mw);
+      const uint32_t total = uni(__shfl(incl, r1 - 1, kWave)) - wb;
+      const bool mine = rank >= r0 && rank < r1;
+      if (mine) {
+        seg[l] = (base - wb) | cnt << 16;
+        uint64_t mm = mask;
+        for (uint32_t j = base - wb; mm; ++j) {
+          tv[j] = (uint8_t)l;
+          ent[j] = (uint16_t)(2 * __builtin_ctzll(mm));
+          mm &= mm - 1;
+        }
+      }
+      __syncthreads();
+      // q_a of every entry through the candidate's maps
+      for (uint32_t e = l; e < total; e += kWave) {
+        const uint32_t t = tv[e];
+        const int a = ent[e] >> 1;
+        const SMap M0 = smap_unpack(maps[3 * t]), M1 = smap_unpack(maps[3 * t + 1]), M2 = smap_unpack(maps[3 * t + 2]);
+        const int q = sapply(M0, sapply(M1, sapply(M2, a)));
+        ent[e] = (uint16_t)(2 * a | (2 * q) << 8);
+      }
+      __syncthreads();
+      if (sums32) entries<int32_t>(l, total, dsum);
+      else entries<int64_t>(l, total, dsum);
+      __syncthreads();
+      r0 = r1;
     }
-    __syncthreads();
-    // q_a of every entry through the candidate's maps
-    for (uint32_t e = l; e < total; e += kWave) {
-      const uint32_t t = tv[e];
-      const int a = ent[e];
-      const SMap M0 = smap_unpack(maps[3 * t]), M1 = smap_unpack(maps[3 * t + 1]), M2 = smap_unpack(maps[3 * t + 2]);
-      const int q = sapply(M0, sapply(M1, sapply(M2, a)));
-      ent[e] = (uint16_t)(a | q << 6);
-    }
-    __syncthreads();
-    if (sums32) entries<int32_t>(l, total, dsum);
-    else entries<int64_t>(l, total, dsum);
-    __syncthreads();
     return dsum[l];
   }
+  // Accepted move: the DX columns of the move's range for the new solution,
+  // and H[a][v] changed by sum_b F[a][b] (new - old DX[v][b]).
   __device__ __forceinline__ void apply(const Step *st, int k) {
     int lo, hi;
     move_range(st, k, lo, hi);
     perm_apply(cur, nxt, st, k, lo, hi);
-    if (lo <= hi) refresh(lo, hi);
+    if (lo > hi) return;
+    const int v = (int)lane_id();
+    if (sums32) {
+      if (v < n) {
+        const int16_t *dcol = Dg + v * n;
+        for (int b0 = lo & ~7; b0 <= hi; b0 += 8) {
+          int nv[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) {
+            const int b = b0 + i;
+            nv[i] = (b >= lo && b <= hi) ? dcol[cur[b]] : 0;
+          }
+          uint32_t dp[4];
+#pragma unroll
+          for (int i = 0; i < 8; i += 2) {
+            int d2[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+              const int b = b0 + i + u;
+              d2[u] = 0;
+              if (b >= lo && b <= hi) {
+                d2[u] = nv[i + u] - DX[v * np + b];
+                DX[v * np + b] = (int16_t)nv[i + u];
+              }
+            }
+            dp[i >> 1] = (uint32_t)(d2[0] & 0xFFFF) | (uint32_t)d2[1] << 16;
+          }
+          for (int a = 0; a < n; ++a) {
+            const uint4 f = *(const uint4 *)(F + a * np + b0);
+            int s = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, f.x), __builtin_bit_cast(s16x2, dp[0]), 0, false);
+            s = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, f.y), __builtin_bit_cast(s16x2, dp[1]), s, false);
+            s = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, f.z), __builtin_bit_cast(s16x2, dp[2]), s, false);
+            s = __builtin_amdgcn_sdot2(__builtin_bit_cast(s16x2, f.w), __builtin_bit_cast(s16x2, dp[3]), s, false);
+            H[a * n + v] = (HT)((int)H[a * n + v] + s);
+          }
+        }
+      }
+      __syncthreads();
+    } else {
+      if (v < n) {
+        const int16_t *dcol = Dg + v * n;
+        for (int b = lo; b <= hi; ++b) DX[v * np + b] = dcol[cur[b]];
+      }
+      __syncthreads();
+      build_sums();
+    }
   }
   __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
 };
+
+// Byte-field counts of one lane: operator o (relative to the encoding's first
+// operator) at bits 8o of cu/cv, k at bits 8(k-1) of cuk/cvk.
+template <int ENC>
+__device__ __forceinline__ void credit_bytes(uint32_t &cu, uint32_t &cv, uint32_t &cuk, uint32_t &cvk, const Step *st,
+                                             int k, bool imp) {
+  constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const uint32_t inc = m < k ? 1u << ((st[m].op - lo) << 3) : 0u;
+    cu += inc;
+    cv += imp ? inc : 0u;
+  }
+  const uint32_t inck = 1u << ((k - 1) << 3);
+  cuk += inck;
+  cvk += imp ? inck : 0u;
+}
 
 template <class KD>
 __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni &U, int32_t *best_row, uint32_t sol,
                                          uint32_t g0, uint32_t g1, uint64_t &T, int64_t &f, int64_t &bf, LStats &S,
                                          uint32_t &nacc) {
   constexpr int ENC = KD::ENC;
+  constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
+  constexpr int nf = ENC == 0 ? 4 : 1;
   const uint32_t lane = lane_id();
+  // per-lane byte counts (a chunk adds at most 6 to a field of a lane),
+  // folded into the wave-uniform counts of S every 42 chunks and at the end
+  uint32_t cu = 0, cv = 0, cuk = 0, cvk = 0, since_fold = 0;
   for (uint32_t g = g0; g < g1; ++g) {
     unsigned long long bk = ~0ull;
     for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
@@ -1132,14 +1253,15 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
         const bool valid = tl < cn;
         if constexpr (KD::kRound) {   // wave-collective evaluation of the round's candidates
           if (!__ballot(valid)) continue;
-          Step st[3];
-          st[0] = load_step<ENC>(W, (int)tl, 0);
-          st[1] = load_step<ENC>(W, (int)tl, 1);
-          st[2] = load_step<ENC>(W, (int)tl, 2);
           const int k = valid ? kk[r] : 0;
-          const int64_t d = kd.delta_round(st, k);
+          const int64_t d = kd.delta_round(W, (int)tl, k);
           if (valid) {
-            if (U.credit == 0) credit<ENC>(S, st, k, d < 0);
+            if (U.credit == 0) {   // the steps again from the tables: fewer registers live across the round
+              Step st[3];
+#pragma unroll
+              for (int m = 0; m < 3; ++m) st[m].op = (int)(W.sop()[3 * tl + m] & 15u);
+              credit_bytes<ENC>(cu, cv, cuk, cvk, st, k, d < 0);
+            }
             const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | (c0 + tl);
             bk = key < bk ? key : bk;
           }
@@ -1149,10 +1271,16 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
           st[1] = kk[r] > 1 ? load_step<ENC>(W, (int)tl, 1) : st[0];
           st[2] = kk[r] > 2 ? load_step<ENC>(W, (int)tl, 2) : st[0];
           const int64_t d = kd.delta(st, kk[r], f);
-          if (U.credit == 0) credit<ENC>(S, st, kk[r], d < 0);
+          if (U.credit == 0) credit_bytes<ENC>(cu, cv, cuk, cvk, st, kk[r], d < 0);
           const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | (c0 + tl);
           bk = key < bk ? key : bk;
         }
+      }
+      if (++since_fold == 42) {
+        fold_byte_counts(S.u + lo, S.v + lo, cu, cv, nf);
+        fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
+        cu = cv = cuk = cvk = 0;
+        since_fold = 0;
       }
       __syncthreads();
     }
@@ -1164,7 +1292,7 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
     if (acc) {
       Step st[3];
       const int k = sample<ENC>(U, g, sol, ts, st);
-      if (U.credit == 1 && lane == 0) credit<ENC>(S, st, k, ds < 0);
+      if (U.credit == 1) credit<ENC>(S, st, k, ds < 0);   // the same on every lane
       kd.apply(st, k);
       f += ds;
       ++nacc;
@@ -1175,6 +1303,8 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
     }
     T = cool(T, U.alpha);
   }
+  fold_byte_counts(S.u + lo, S.v + lo, cu, cv, nf);
+  fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
 
 // ------------------------------------------------------------ epoch close
@@ -1419,16 +1549,22 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       }
       perm_store(t0, n, cur_g);
     } else if constexpr (KIND == KQAP) {
+      // F and DX rows padded to 8, then H (2 or 4 n^2 bytes: 16-bit entries
+      // for STAGE 1), the per-window candidate segments, the first entry of
+      // each rank, and the entry lists
+      using HT = typename std::conditional<STAGE == 1, uint16_t, int32_t>::type;
       const int np = (n + 7) & ~7;
       int16_t *F = (int16_t *)rest;
       int16_t *DX = (int16_t *)(rest + al16(2 * n * np));
-      long long *R = (long long *)(rest + 2 * al16(2 * n * np));
-      uint32_t *seg = (uint32_t *)(rest + 2 * al16(2 * n * np) + al16(8 * n));
-      uint8_t *tv = (uint8_t *)(rest + 2 * al16(2 * n * np) + al16(8 * n) + 4 * kWave);
-      uint16_t *ent = (uint16_t *)(rest + 2 * al16(2 * n * np) + al16(8 * n) + 4 * kWave + al16(kWave * n));
-      QapK kd{t0, t1, n, np, F, DX, R, I->qd, seg, tv, ent, I->qap_sums32 != 0};
+      char *sums = rest + 2 * al16(2 * n * np);
+      char *lists = sums + al16((uint32_t)sizeof(HT) * n * n);
+      uint32_t *seg = (uint32_t *)lists;
+      uint32_t *rb = seg + kWave;
+      uint8_t *tv = (uint8_t *)(rb + kWave);
+      uint16_t *ent = (uint16_t *)((char *)tv + al16(kQapListPerN * n));
+      QapK<HT> kd{t0, t1, n, np, F, DX, (HT *)sums, (long long *)sums, I->qd, seg, rb, tv, ent, I->qap_sums32 != 0};
       __syncthreads();
-      kd.setup(I->qf, (int16_t *)tv);   // the entry lists (192 n bytes) stage the matrices
+      kd.setup(I->qf);
       run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       perm_store(kd.cur, n, cur_g);
     } else {
@@ -1481,7 +1617,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     J->best_f[sol] = bf;
   }
   constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : 0);
-  write_counts<ENC, KIND == KTSP>(J, sol, S, nacc, bf);
+  write_counts<ENC, true>(J, sol, S, nacc, bf);
 }
 
 }  // namespace
@@ -1844,7 +1980,7 @@ static const void *plain_kernel(int kind, int stage) {
         case SGLB16: return (const void *)k_evolve<KTSP, SGLB16>;
         default: return (const void *)k_evolve<KTSP, SGLB32>;
       }
-    case KQAP: return (const void *)k_evolve<KQAP, 0>;
+    case KQAP: return stage == 1 ? (const void *)k_evolve<KQAP, 1> : (const void *)k_evolve<KQAP, 0>;
     case KKNAP: return (const void *)k_evolve<KKNAP, 0>;
     case KVRP: return (const void *)k_evolve<KVRP, 0>;
     default: return (const void *)k_evolve<KCOLOR, 0>;
@@ -1860,7 +1996,7 @@ static const void *group_kernel(int kind, int stage) {
         case SGLB16: return (const void *)k_evolve_group<KTSP, SGLB16>;
         default: return (const void *)k_evolve_group<KTSP, SGLB32>;
       }
-    case KQAP: return (const void *)k_evolve_group<KQAP, 0>;
+    case KQAP: return stage == 1 ? (const void *)k_evolve_group<KQAP, 1> : (const void *)k_evolve_group<KQAP, 0>;
     case KKNAP: return (const void *)k_evolve_group<KKNAP, 0>;
     case KVRP: return (const void *)k_evolve_group<KVRP, 0>;
     default: return (const void *)k_evolve_group<KCOLOR, 0>;
@@ -1869,7 +2005,7 @@ static const void *group_kernel(int kind, int stage) {
 
 hipError_t prepare_kernel_attrs(uint32_t max_lds) {
   const int kinds[][2] = {{KTSP, SLDS16}, {KTSP, SLDSXY}, {KTSP, SGLB16}, {KTSP, SGLB32},
-                          {KQAP, 0},      {KKNAP, 0},     {KVRP, 0},      {KCOLOR, 0}};
+                          {KQAP, 0},      {KQAP, 1},      {KKNAP, 0},     {KVRP, 0},      {KCOLOR, 0}};
   for (auto &k : kinds) {
     hipError_t e = hipFuncSetAttribute(plain_kernel(k[0], k[1]), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)max_lds);
