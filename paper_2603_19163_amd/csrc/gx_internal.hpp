@@ -87,10 +87,11 @@ inline uint32_t lds_bytes_for(int kind, int n, int stage) {
       else if (stage == SLDSXY) b += al(4 * un) + al(2 * un);   // coordinates, edge lengths
       return b;
     }
-    case KQAP: {   // F and D(x) rows padded to 8, row sums H (16-bit for staging 1), segments, lists
+    case KQAP: {   // F and D(x) rows padded to 8, row sums H (16-bit for staging 1), the two waves'
+                   // chunk minima, wave 1's maps, then per wave: deltas, segments, entry lists
       const uint32_t np = (un + 7u) & ~7u, lst = kQapListPerN * un;   // entry-list capacity per window
-      return tables + tours + 2 * al(2 * un * np) + al((stage == 1 ? 2u : 4u) * un * un) + 8 * kWave + al(lst) +
-             al(2 * lst);
+      return tables + tours + 2 * al(2 * un * np) + al((stage == 1 ? 2u : 4u) * un * un) + 16 + 24 * kWave +
+             2 * (16 * kWave + al(lst) + al(2 * lst));
     }
     case KKNAP: return tables + al(un) + 2 * al(4 * un);
     case KVRP: return tables + tours + al(2 * (un + 1) * (un + 1)) + 3 * al(4 * (un + 1));

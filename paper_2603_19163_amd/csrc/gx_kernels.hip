@@ -48,7 +48,18 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
 // integer in [0, m) from a 32-bit draw: floor(w * m / 2^32)
 __device__ __forceinline__ uint32_t rmap(uint32_t w, uint32_t m) { return __umulhi(w, m); }
 
-__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x; }
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
+// threads of an evolve workgroup: two wavefronts for QAP (they share the
+// solution and split the delta entries), one for the other kinds
+template <int KIND>
+constexpr int kThreads = KIND == KQAP ? 128 : 64;
+// LDS written by this wave visible to all of its lanes (a wave's LDS accesses
+// are performed in order; this only keeps the compiler from reordering them)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ uint64_t uni64(uint64_t v) {
@@ -593,38 +604,41 @@ __device__ __forceinline__ void unpack_step(const TspScratch &W, int t, int m, i
 // of the candidates with k >= 2 and k >= 3 compacted onto consecutive lanes,
 // so that the wave computes about as many Philox blocks as there are steps.
 // Steps land in the LDS tables; kk[r] receives k of the lane's candidates.
-template <int ENC>
+template <int ENC, int RN = 2>
 __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, uint32_t g, uint32_t sol, uint32_t c0,
-                                           uint32_t cn, int kk[2]) {
+                                           uint32_t cn, int kk[RN], uint32_t rb = 0) {
+  // rounds rb .. rb + RN - 1 of the chunk (64 candidates each) on this wave;
+  // its extra-step list at dl + 128 rb
   const uint32_t lane = lane_id();
+  uint16_t *dl = W.dl() + 128 * rb;
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const uint32_t tl = r * kWave + lane;
-    kk[r] = 0;
+  for (int rr = 0; rr < RN; ++rr) {
+    const uint32_t tl = (rb + rr) * kWave + lane;
+    kk[rr] = 0;
     if (tl < cn) {
       uint32_t w[4];
       philox(g, sol, (c0 + tl) << 2, U.key, U.k0, U.k1, w);
       const uint32_t u = (uint32_t)(((uint64_t)(w[0] >> 16) * U.swk) >> 16);
-      kk[r] = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
+      kk[rr] = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
       const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
       W.sab()[3 * tl] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
-      W.sop()[3 * tl] = (uint8_t)(st.op | (st.c << 4) | (kk[r] << 6));
-      W.del()[tl] = 0;
+      W.sop()[3 * tl] = (uint8_t)(st.op | (st.c << 4) | (kk[rr] << 6));
+      if constexpr (RN == 2) W.del()[tl] = 0;
     }
   }
   uint32_t nx = 0;
 #pragma unroll
   for (int m = 1; m < 3; ++m)
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const bool need = kk[r] > m;
+    for (int rr = 0; rr < RN; ++rr) {
+      const bool need = kk[rr] > m;
       const unsigned long long mk = __ballot(need);
-      if (need) W.dl()[nx + lanes_below(mk)] = (uint16_t)((r * kWave + lane) | (m << 8));
+      if (need) dl[nx + lanes_below(mk)] = (uint16_t)(((rb + rr) * kWave + lane) | (m << 8));
       nx += (uint32_t)__popcll(mk);
     }
   __syncthreads();
   for (uint32_t j = lane; j < nx; j += kWave) {
-    const uint32_t e = W.dl()[j], tl = e & 0xFFu, m = e >> 8;
+    const uint32_t e = dl[j], tl = e & 0xFFu, m = e >> 8;
     uint32_t w[4];
     philox(g, sol, ((c0 + tl) << 2) | m, U.key, U.k0, U.k1, w);
     const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
@@ -983,10 +997,14 @@ struct QapK {
   HT *H;                 // H[a][v] at a * n + v (int32 sums)
   long long *R;          // R_a (64-bit sums), in the space of H
   const int16_t *Dg;     // D in global memory (n x n)
-  uint32_t *seg;         // per candidate of a window: first entry | count << 16
-  uint32_t *rb;          // first entry of the candidate of each rank
-  uint8_t *tv;           // candidate of each entry
-  uint16_t *ent;         // byte offsets 2a | 2q_a << 8 of each entry (position a)
+  // this wave's round: the candidates' maps and deltas, per-window candidate
+  // segments (first entry | count << 16), first entry of each rank, and the
+  // entry lists (candidate; byte offsets 2a | 2q_a << 8 of position a)
+  uint2 *maps;
+  long long *dsum;
+  uint32_t *seg, *rb;
+  uint8_t *tv;
+  uint16_t *ent;
   bool sums32;           // 2 n max F max D < 2^31: H, G and the pair sums fit int32
 
   // <F row a, DX row v> over np columns
@@ -1009,11 +1027,11 @@ struct QapK {
   }
   // H (int32 sums) or R (64-bit sums) from F and DX; lane v < n owns column v of H
   __device__ __forceinline__ void build_sums() {
-    const int v = (int)lane_id();
+    const int v = (int)lane_id(), wv = (int)(threadIdx.x >> 6);
     if (sums32) {
       if (v < n)
-        for (int a = 0; a < n; ++a) H[a * n + v] = (HT)row_dot<int32_t>(a, v);
-    } else if (v < n) {
+        for (int a = wv; a < n; a += kThreads<KQAP> / kWave) H[a * n + v] = (HT)row_dot<int32_t>(a, v);
+    } else if (v < n && wv == 0) {
       R[v] = row_dot<int64_t>(v, cur[v]);
     }
     __syncthreads();
@@ -1038,8 +1056,8 @@ struct QapK {
   }
 
   template <class ACC>
-  __device__ __forceinline__ void entries(uint32_t l, uint32_t total, long long *dsum) const {
-    for (uint32_t e = l; e < total; e += kWave) {
+  __device__ __forceinline__ void entries(uint32_t total) const {
+    for (uint32_t e = lane_id(); e < total; e += kWave) {
       const uint32_t t = tv[e], en = ent[e], a = (en & 255u) >> 1, q = en >> 9;
       const uint32_t sg = seg[t], base = sg & 0xFFFFu, cnt = sg >> 16;
       const int ya = cur[q], xa = cur[a];
@@ -1078,17 +1096,17 @@ struct QapK {
     }
   }
   // Deltas of the 64 candidates of a round (one per lane, k = 0 for an empty
-  // lane), wave-collective: the (candidate, position) entries of all lanes are
-  // listed and shared, so the work follows the total number of changed
-  // positions rather than the largest one in the wave.  Candidates with more
-  // changed positions are listed first, so that the entries processed
-  // together belong to candidates with similar pair counts; a round with more
-  // entries than the list holds is processed in windows of whole candidates.
+  // lane), collective over this wave alone (the two waves of the workgroup
+  // evaluate one round each, on their own lists): the (candidate, position)
+  // entries of all lanes are listed and shared, so the work follows the total
+  // number of changed positions rather than the largest one in the wave.
+  // Candidates with more changed positions are listed first, so that the
+  // entries processed together belong to candidates with similar pair
+  // counts; a round with more entries than the list holds is processed in
+  // windows of whole candidates.
   __device__ __forceinline__ int64_t delta_round(const TspScratch &W, int tl, int k) const {
     const uint32_t l = lane_id();
-    long long *dsum = (long long *)(gx_lds + 1536);
     uint32_t *tmp = (uint32_t *)dsum;
-    uint2 *maps = (uint2 *)(gx_lds + 2048);
     const uint32_t cap = kQapListPerN * (uint32_t)n;
     uint64_t mask = 0;
     {
@@ -1112,7 +1130,7 @@ struct QapK {
       rank += c < cls ? (uint32_t)__popcll(mc) : (c == cls ? lanes_below(mc) : 0u);
     }
     tmp[rank] = cnt;
-    __syncthreads();
+    wave_sync();
     const uint32_t cr = tmp[l];   // lanes in rank order from here
     uint32_t incl = cr;
 #pragma unroll
@@ -1121,7 +1139,7 @@ struct QapK {
       incl += l >= (uint32_t)o ? v : 0u;
     }
     rb[l] = incl - cr;
-    __syncthreads();
+    wave_sync();
     const uint32_t base = rb[rank];
     dsum[l] = 0;
     for (uint32_t r0 = 0; r0 < (uint32_t)kWave;) {
@@ -1140,7 +1158,7 @@ struct QapK {
           mm &= mm - 1;
         }
       }
-      __syncthreads();
+      wave_sync();
       // q_a of every entry through the candidate's maps
       for (uint32_t e = l; e < total; e += kWave) {
         const uint32_t t = tv[e];
@@ -1149,13 +1167,15 @@ struct QapK {
         const int q = sapply(M0, sapply(M1, sapply(M2, a)));
         ent[e] = (uint16_t)(2 * a | (2 * q) << 8);
       }
-      __syncthreads();
-      if (sums32) entries<int32_t>(l, total, dsum);
-      else entries<int64_t>(l, total, dsum);
-      __syncthreads();
+      wave_sync();
+      if (sums32) entries<int32_t>(total);
+      else entries<int64_t>(total);
+      wave_sync();
       r0 = r1;
     }
-    return dsum[l];
+    const int64_t d = dsum[l];
+    wave_sync();
+    return d;
   }
   // Accepted move: the DX columns of the move's range for the new solution,
   // and H[a][v] changed by sum_b F[a][b] (new - old DX[v][b]).
@@ -1165,8 +1185,9 @@ struct QapK {
     perm_apply(cur, nxt, st, k, lo, hi);
     if (lo > hi) return;
     const int v = (int)lane_id();
+    const bool w0 = threadIdx.x < (uint32_t)kWave;
     if (sums32) {
-      if (v < n) {
+      if (v < n && w0) {
         const int16_t *dcol = Dg + v * n;
         for (int b0 = lo & ~7; b0 <= hi; b0 += 8) {
           int nv[8];
@@ -1202,7 +1223,7 @@ struct QapK {
       }
       __syncthreads();
     } else {
-      if (v < n) {
+      if (v < n && w0) {
         const int16_t *dcol = Dg + v * n;
         for (int b = lo; b <= hi; ++b) DX[v * np + b] = dcol[cur[b]];
       }
@@ -1251,21 +1272,7 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
       for (int r = 0; r < 2; ++r) {
         const uint32_t tl = r * kWave + lane;
         const bool valid = tl < cn;
-        if constexpr (KD::kRound) {   // wave-collective evaluation of the round's candidates
-          if (!__ballot(valid)) continue;
-          const int k = valid ? kk[r] : 0;
-          const int64_t d = kd.delta_round(W, (int)tl, k);
-          if (valid) {
-            if (U.credit == 0) {   // the steps again from the tables: fewer registers live across the round
-              Step st[3];
-#pragma unroll
-              for (int m = 0; m < 3; ++m) st[m].op = (int)(W.sop()[3 * tl + m] & 15u);
-              credit_bytes<ENC>(cu, cv, cuk, cvk, st, k, d < 0);
-            }
-            const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | (c0 + tl);
-            bk = key < bk ? key : bk;
-          }
-        } else if (valid) {
+        if (valid) {
           Step st[3];
           st[0] = load_step<ENC>(W, (int)tl, 0);
           st[1] = kk[r] > 1 ? load_step<ENC>(W, (int)tl, 1) : st[0];
@@ -1304,6 +1311,74 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
     T = cool(T, U.alpha);
   }
   fold_byte_counts(S.u + lo, S.v + lo, cu, cv, nf);
+  fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
+}
+
+// Generations of a kind evaluated round by round (QAP): the workgroup's two
+// waves each draw and evaluate one round of 64 candidates of every chunk,
+// then agree on the chunk minimum through LDS; acceptance and the move are
+// the same on both (the move's shared state is written by wave 0 or
+// identically by both).  Each wave counts its own candidates; the accepted
+// count is wave 0's.
+template <class KD>
+__device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Uni &U, int32_t *best_row, uint32_t sol,
+                                           uint32_t g0, uint32_t g1, uint64_t &T, int64_t &f, int64_t &bf, LStats &S,
+                                           uint32_t &nacc, unsigned long long *xk) {
+  constexpr int ENC = KD::ENC;
+  const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
+  uint32_t cu = 0, cv = 0, cuk = 0, cvk = 0, since_fold = 0;
+  for (uint32_t g = g0; g < g1; ++g) {
+    unsigned long long bk = ~0ull;
+    for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
+      const uint32_t cn = min((uint32_t)kChunk, U.C - c0);
+      int kk[1];
+      draw_chunk<ENC, 1>(W, U, g, sol, c0, cn, kk, wv);
+      const uint32_t tl = wv * kWave + lane;
+      const bool valid = tl < cn;
+      if (__ballot(valid)) {
+        const int k = valid ? kk[0] : 0;
+        const int64_t d = kd.delta_round(W, (int)tl, k);
+        if (valid) {
+          if (U.credit == 0) {   // the steps again from the tables: fewer registers live across the round
+            Step st[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) st[m].op = (int)(W.sop()[3 * tl + m] & 15u);
+            credit_bytes<ENC>(cu, cv, cuk, cvk, st, k, d < 0);
+          }
+          const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | (c0 + tl);
+          bk = key < bk ? key : bk;
+        }
+      }
+      if (++since_fold == 84) {   // one candidate per lane per chunk: at most 3 per field
+        fold_byte_counts(S.u, S.v, cu, cv, 4);
+        fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
+        cu = cv = cuk = cvk = 0;
+        since_fold = 0;
+      }
+      __syncthreads();
+    }
+    xk[wv] = wave_min_key(bk);
+    __syncthreads();
+    bk = xk[0] < xk[1] ? xk[0] : xk[1];
+    const uint32_t ts = (uint32_t)(bk & 0xFFFFu);
+    const int64_t ds = (int64_t)(bk >> 16) - kDeltaBias;
+    bool acc = ds <= 0;
+    if (!acc) acc = accept_worse(ds, T, g, sol, U);
+    if (acc) {
+      Step st[3];
+      const int k = sample<ENC>(U, g, sol, ts, st);
+      if (U.credit == 1 && wv == 0) credit<ENC>(S, st, k, ds < 0);   // the same on every lane of wave 0
+      kd.apply(st, k);
+      f += ds;
+      nacc += wv == 0;
+      if (f < bf) {
+        bf = f;
+        if (wv == 0) kd.store(best_row);
+      }
+    }
+    T = cool(T, U.alpha);
+  }
+  fold_byte_counts(S.u, S.v, cu, cv, 4);
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
 
@@ -1550,23 +1625,31 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       perm_store(t0, n, cur_g);
     } else if constexpr (KIND == KQAP) {
       // F and DX rows padded to 8, then H (2 or 4 n^2 bytes: 16-bit entries
-      // for STAGE 1), the per-window candidate segments, the first entry of
-      // each rank, and the entry lists
+      // for STAGE 1), the chunk minima of the two waves, wave 1's maps, and
+      // per wave: deltas, window segments, first entry of each rank, entry
+      // lists.  Wave 0's maps sit in the candidate tables (free during rounds).
       using HT = typename std::conditional<STAGE == 1, uint16_t, int32_t>::type;
       const int np = (n + 7) & ~7;
+      const uint32_t wv = threadIdx.x >> 6;
       int16_t *F = (int16_t *)rest;
       int16_t *DX = (int16_t *)(rest + al16(2 * n * np));
       char *sums = rest + 2 * al16(2 * n * np);
-      char *lists = sums + al16((uint32_t)sizeof(HT) * n * n);
-      uint32_t *seg = (uint32_t *)lists;
-      uint32_t *rb = seg + kWave;
-      uint8_t *tv = (uint8_t *)(rb + kWave);
+      unsigned long long *xk = (unsigned long long *)(sums + al16((uint32_t)sizeof(HT) * n * n));
+      uint2 *maps1 = (uint2 *)(xk + 2);
+      const uint32_t per_wave = 8 * kWave + 8 * kWave + al16(kQapListPerN * n) + al16(2 * kQapListPerN * n);
+      char *mine = (char *)(maps1 + 3 * kWave) + wv * per_wave;
+      long long *dsum = (long long *)mine;
+      uint32_t *seg = (uint32_t *)(mine + 8 * kWave);
+      uint32_t *rbk = seg + kWave;
+      uint8_t *tv = (uint8_t *)(rbk + kWave);
       uint16_t *ent = (uint16_t *)((char *)tv + al16(kQapListPerN * n));
-      QapK<HT> kd{t0, t1, n, np, F, DX, (HT *)sums, (long long *)sums, I->qd, seg, rb, tv, ent, I->qap_sums32 != 0};
+      uint2 *maps = wv == 0 ? (uint2 *)(lds + 2048) : maps1;
+      QapK<HT> kd{t0, t1, n, np, F, DX, (HT *)sums, (long long *)sums, I->qd, maps, dsum, seg, rbk, tv, ent,
+                  I->qap_sums32 != 0};
       __syncthreads();
       kd.setup(I->qf);
-      run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
-      perm_store(kd.cur, n, cur_g);
+      round_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk);
+      if (wv == 0) perm_store(kd.cur, n, cur_g);
     } else {
       const int dn = n + 1;
       int16_t *D = (int16_t *)rest;
@@ -1612,19 +1695,19 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
     kd.store(cur_g);
   }
-  if (lane == 0) {
+  if (threadIdx.x == 0) {
     J->cur_f[sol] = f;
     J->best_f[sol] = bf;
   }
   constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : 0);
-  write_counts<ENC, true>(J, sol, S, nacc, bf);
+  write_counts<ENC, true>(J, sol, S, nacc, bf);   // every wave adds the counts of its own candidates
 }
 
 }  // namespace
 
 // ------------------------------------------------------------ evolve kernels
 template <int KIND, int STAGE>
-__global__ __launch_bounds__(64) void k_evolve(DevJob *job) {
+__global__ __launch_bounds__(kThreads<KIND>) void k_evolve(DevJob *job) {
   evolve_wg<KIND, STAGE>(job, blockIdx.x, gx_lds);
 }
 
@@ -1633,11 +1716,17 @@ __global__ __launch_bounds__(64) void k_evolve(DevJob *job) {
 // counter until the list is done, so workgroups that finish early take more.
 // The epoch kernel clears the counter after the launch.
 template <int KIND, int STAGE>
-__global__ __launch_bounds__(64) void k_evolve_group(DevJob *jobs, const uint2 *items, uint32_t n_items,
-                                                     uint32_t *next) {
+__global__ __launch_bounds__(kThreads<KIND>) __attribute__((amdgpu_waves_per_eu(3))) void k_evolve_group(DevJob *jobs, const uint2 *items, uint32_t n_items,
+                                                                 uint32_t *next) {
   for (;;) {
     uint32_t it = 0;
-    if (lane_id() == 0) it = atomicAdd(next, 1u);
+    if (threadIdx.x == 0) it = atomicAdd(next, 1u);
+    if constexpr (kThreads<KIND> > kWave) {   // to every wave of the workgroup (LDS is dead between items)
+      if (threadIdx.x == 0) *(volatile uint32_t *)gx_lds = it;
+      __syncthreads();
+      it = *(volatile uint32_t *)gx_lds;
+      __syncthreads();
+    }
     it = uni(it);
     if (it >= n_items) break;
     const uint2 w = items[it];
@@ -2019,15 +2108,17 @@ hipError_t prepare_kernel_attrs(uint32_t max_lds) {
   return hipSuccess;
 }
 
+static int threads_of(int kind) { return kind == KQAP ? kThreads<KQAP> : kWave; }
+
 hipError_t evolve_plain(DevJob *job, int kind, int stage, uint32_t P, uint32_t lds, hipStream_t s) {
   void *args[] = {&job};
-  return hipLaunchKernel(plain_kernel(kind, stage), dim3(P), dim3(64), args, lds, s);
+  return hipLaunchKernel(plain_kernel(kind, stage), dim3(P), dim3(threads_of(kind)), args, lds, s);
 }
 
 hipError_t evolve_group(int kind, int stage, DevJob *jobs, const uint2 *items, uint32_t n_items, uint32_t *next,
                         uint32_t grid, uint32_t lds, hipStream_t s) {
   void *args[] = {&jobs, &items, &n_items, &next};
-  return hipLaunchKernel(group_kernel(kind, stage), dim3(grid), dim3(64), args, lds, s);
+  return hipLaunchKernel(group_kernel(kind, stage), dim3(grid), dim3(threads_of(kind)), args, lds, s);
 }
 
 hipError_t epoch(DevJob *jobs, const uint32_t *idx, uint32_t count, uint32_t *next, uint32_t n_next,
@@ -2042,11 +2133,11 @@ hipError_t fetch_best(DevJob *jobs, int count, hipStream_t s) {
 }
 
 hipError_t occupancy_group(int kind, int stage, uint32_t lds, int *blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, group_kernel(kind, stage), 64, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, group_kernel(kind, stage), threads_of(kind), lds);
 }
 
 hipError_t occupancy_plain(int kind, int stage, uint32_t lds, int *blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, plain_kernel(kind, stage), 64, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, plain_kernel(kind, stage), threads_of(kind), lds);
 }
 
 }  // namespace gxk
