@@ -115,6 +115,8 @@ def main():
     ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
     ap.add_argument("--served-generations", type=int, default=10000)
     ap.add_argument("--served-population", type=int, default=4)
+    ap.add_argument("--served-kinds", default="tsp,qap,knapsack",
+                    help="served: request kinds drawn uniformly (subset of tsp,qap,knapsack)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="tsp442: skip the batched and served measurements appended to the line")
     ap.add_argument("--mixed-duration", type=float, default=3.0,
@@ -329,8 +331,10 @@ def bench_served(args):
     n_req = int(args.rate * args.duration)
     gaps = r.exponential(1.0 / args.rate, size=n_req)
     reqs = []
+    names = {"tsp": 0, "qap": 1, "knapsack": 2}
+    kinds = [names[k] for k in args.served_kinds.split(",")]
     for i in range(n_req):
-        kind = int(r.integers(0, 3))
+        kind = kinds[int(r.integers(0, len(kinds)))]
         if kind == 0:
             inst = synth.tsp_uniform(int(r.integers(20, 501)), 30_000 + i, key=i)
         elif kind == 1:
@@ -389,7 +393,8 @@ def bench_served(args):
         "plain_identical": same, "plain_sample": len(idx),
         "server": stats,
         "config": {"workload": f"Poisson {args.rate}/s for {args.duration}s: TSP n U[20,500], QAP n "
-                               f"U[12,50], knapsack n U[100,1000]; P={P}, C=128, {G} generations each"},
+                               f"U[12,50], knapsack n U[100,1000] (kinds {args.served_kinds}); P={P}, C=128, "
+                               f"{G} generations each"},
     }
 
 
