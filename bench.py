@@ -119,6 +119,8 @@ def main():
                     help="served: request kinds drawn uniformly (subset of tsp,qap,knapsack)")
     ap.add_argument("--no-mixed", action="store_true",
                     help="tsp442: skip the batched and served measurements appended to the line")
+    ap.add_argument("--sustained-rate", type=float, default=800.0,
+                    help="tsp442: offered rate of the second served measurement (below capacity)")
     ap.add_argument("--mixed-duration", type=float, default=3.0,
                     help="tsp442: seconds of served arrivals measured for the line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -244,6 +246,11 @@ def main():
         mixed.duration = args.mixed_duration
         line["batched"] = bench_batched(mixed)
         line["mixed_stream"] = bench_served(mixed)
+        # the same stream at a rate this device sustains for the mix, so that
+        # p50/p99 show service time rather than a growing backlog
+        sustained = argparse.Namespace(**vars(mixed))
+        sustained.rate = args.sustained_rate
+        line["mixed_stream_sustained"] = bench_served(sustained)
     print(json.dumps(line), flush=True)
 
 
