@@ -140,6 +140,23 @@ def test_qap_wide_values(ctx):
           [10, 20], "qap wide values")
 
 
+def test_qap_medium_values(ctx):
+    # n max F max D above 2^16 but 2 n max F max D below 2^31: 32-bit row sums H
+    r = np.random.default_rng([7, 25, 20260319])
+    F = r.integers(0, 1000, (25, 25))
+    D = r.integers(0, 1000, (25, 25))
+    inst = synth.Instance(synth.QAP, 25, np.triu(F) + np.triu(F, 1).T, np.triu(D) + np.triu(D, 1).T, key=31)
+    check(ctx, inst, P(seed=9, population=4, candidates=128, G=30, op_mask=synth.PERM_OPS), [15, 15], "qap medium values")
+
+
+def test_qap_long_moves_in_windows(ctx):
+    # reversals and block moves on a short permutation change most positions:
+    # a round's entries exceed the 24n list and are evaluated in several windows
+    ops = (1 << synth.OP_2OPT) | (1 << synth.OP_OROPT)
+    check(ctx, synth.qap_random(9, 4, key=9), P(seed=3, population=3, candidates=200, G=20, op_mask=ops), [20],
+          "qap windows")
+
+
 @pytest.mark.parametrize("n", [37, 48])
 def test_qap_ragged_rows(ctx, n):
     # rows padded to a multiple of 8 (37 -> 40) and an exact multiple (48)
