@@ -303,13 +303,32 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
   return GX_OK;
 }
 
-gx_status place_instance(gx_ctx *c, Prepared &pr, char *base, hipStream_t s, DevInst *out_h, DevInst **out_d) {
+// Copies the instance arrays and its record into the device block at `base`;
+// with `stage` (pinned host memory of staging_bytes(pr)) the copies go through
+// it, so that they are asynchronous.
+size_t staging_bytes(const Prepared &pr) {
+  size_t b = pad16(sizeof(DevInst));
+  for (const auto &a : pr.arrs) b += pad16(a.bytes);
+  return b;
+}
+
+gx_status place_instance(gx_ctx *c, Prepared &pr, char *base, hipStream_t s, DevInst *out_h, DevInst **out_d,
+                         char *stage = nullptr) {
   DevInst h = pr.h;
   char *q = base;
+  char *sp = stage ? stage + pad16(sizeof(DevInst)) : nullptr;
   for (const auto &a : pr.arrs) {
     char *dst = q;
     q += pad16(a.bytes) + 16;
-    if (!a.data.empty()) HIPCHK(c, hipMemcpyAsync(dst, a.data.data(), a.bytes, hipMemcpyHostToDevice, s));
+    if (!a.data.empty()) {
+      const void *src = a.data.data();
+      if (sp) {
+        memcpy(sp, src, a.bytes);
+        src = sp;
+        sp += pad16(a.bytes);
+      }
+      HIPCHK(c, hipMemcpyAsync(dst, src, a.bytes, hipMemcpyHostToDevice, s));
+    }
     switch (a.field) {
       case F_XY: h.xy = (const int32_t *)dst; break;
       case F_D16: h.d16 = (const int16_t *)dst; break;
@@ -331,7 +350,12 @@ gx_status place_instance(gx_ctx *c, Prepared &pr, char *base, hipStream_t s, Dev
   *out_h = h;
   // the record is copied from pr.h's twin kept alive by the caller until the stream syncs
   pr.h = h;
-  HIPCHK(c, hipMemcpyAsync(dd, &pr.h, sizeof(DevInst), hipMemcpyHostToDevice, s));
+  const void *rec = &pr.h;
+  if (stage) {
+    memcpy(stage, &pr.h, sizeof(DevInst));
+    rec = stage;
+  }
+  HIPCHK(c, hipMemcpyAsync(dd, rec, sizeof(DevInst), hipMemcpyHostToDevice, s));
   *out_d = dd;
   return GX_OK;
 }
@@ -1095,6 +1119,7 @@ struct SrvReq {
   Prepared pr;
   DevJob hj{};
   size_t inst_bytes = 0, bytes = 0, off = 0, pin_off = 0;
+  size_t pin_bytes = 0;   // pinned block: result (4n + 8), then staging of the instance and the job record
   int slot = -1, n = 0, kind = 0, lane = 0;
   uint32_t g = 0;
   hipEvent_t ev = nullptr;
@@ -1215,13 +1240,18 @@ void lane_free(SrvLane &L) {
 // Place an admitted request into its arena block and start its initialisation.
 gx_status srv_stage(gx_server *S, SrvReq *r) {
   char *base = S->arena_d + r->off;
+  // host-side copies go through the request's pinned block (after its result
+  // area), so the scheduler thread never waits on a pageable copy
+  char *stage = S->pin + r->pin_off + pad16(4 * (size_t)r->n + 8);
   DevInst hh;
   DevInst *dd = nullptr;
-  gx_status st = place_instance(&S->vctx, r->pr, base, S->s, &hh, &dd);
+  gx_status st = place_instance(&S->vctx, r->pr, base, S->s, &hh, &dd, stage);
   if (st) return st;
   r->hj.inst = dd;
   carve_job(r->hj, base + r->inst_bytes, (size_t)r->n);
-  if (hipMemcpyAsync(S->jobs_d + r->slot, &r->hj, sizeof(DevJob), hipMemcpyHostToDevice, S->s) != hipSuccess ||
+  char *jrec = stage + staging_bytes(r->pr);
+  memcpy(jrec, &r->hj, sizeof(DevJob));
+  if (hipMemcpyAsync(S->jobs_d + r->slot, jrec, sizeof(DevJob), hipMemcpyHostToDevice, S->s) != hipSuccess ||
       gxk::init_jobs(S->jobs_d + r->slot, 1, r->hj.Q, r->n, heur_mats_of(r->pr.h.kind), S->s) != hipSuccess ||
       gxk::set_stop(S->jobs_d + r->slot, 1, 0, 1, S->s) != hipSuccess)
     return GX_E_DEVICE;
@@ -1231,7 +1261,7 @@ gx_status srv_stage(gx_server *S, SrvReq *r) {
 
 void srv_release(gx_server *S, SrvReq *r) {   // caller holds mu
   S->arena.release(r->off, r->bytes);
-  if (r->pin_off != (size_t)-1) S->pin_arena.release(r->pin_off, 4 * (size_t)r->n + 8);
+  if (r->pin_off != (size_t)-1) S->pin_arena.release(r->pin_off, r->pin_bytes);
   S->slots[r->slot] = nullptr;
   S->free_slots.push_back(r->slot);
   S->resident_items -= r->hj.P;
@@ -1259,7 +1289,7 @@ void server_loop(gx_server *S) {
           ++it;   // does not fit now; smaller requests behind it may
           continue;
         }
-        if (!S->pin_arena.alloc(4 * (size_t)r->n + 8, &poff)) {
+        if (!S->pin_arena.alloc(r->pin_bytes, &poff)) {
           S->arena.release(off, r->bytes);
           ++it;
           continue;
@@ -1436,7 +1466,8 @@ gx_status gx_server_create(gx_ctx *c, const gx_server_cfg *cfg, gx_server **out)
   if (hipMalloc((void **)&S->arena_d, S->cfg.hbm_budget_bytes) != hipSuccess) return bail("arena");
   S->arena.reset(S->cfg.hbm_budget_bytes);
   if (hipMalloc((void **)&S->jobs_d, sizeof(DevJob) * S->cfg.max_resident) != hipSuccess) return bail("job table");
-  const size_t pin_bytes = std::max<size_t>(16u << 20, (size_t)S->cfg.max_resident * 4096);
+  // per resident request: its result and the staging copy of its instance
+  const size_t pin_bytes = std::max<size_t>(64u << 20, (size_t)S->cfg.max_resident * 16384);
   if (hipHostMalloc((void **)&S->pin, pin_bytes, 0) != hipSuccess) return bail("pinned results");
   S->pin_arena.reset(pin_bytes);
   S->slots.assign(S->cfg.max_resident, nullptr);
@@ -1472,7 +1503,8 @@ gx_status gx_server_submit(gx_server *S, const gx_instance_desc *d, const gx_sol
   r->n = r->pr.h.n;
   r->inst_bytes = (r->pr.dev_bytes() + 255) & ~size_t(255);
   r->bytes = r->inst_bytes + job_array_bytes((size_t)r->n, r->hj.P, r->hj.Q);
-  if (r->bytes > S->arena.cap() || 4 * (size_t)r->n + 8 > S->pin_arena.cap()) {
+  r->pin_bytes = pad16(4 * (size_t)r->n + 8) + staging_bytes(r->pr) + pad16(sizeof(DevJob));
+  if (r->bytes > S->arena.cap() || r->pin_bytes > S->pin_arena.cap()) {
     S->err = "request larger than the server arena";
     delete r;
     return GX_E_UNSUPPORTED;
