@@ -1143,7 +1143,11 @@ struct SrvLane {
 
 // lanes: (kind, staging) x LDS class
 constexpr int kLanes = 9 * kLdsClasses;
-constexpr int kQuantumEpochs = 4;   // epoch chunks a lane advances per quantum
+// epoch chunks a lane advances per quantum: the launches and the host's
+// turnaround are paid once per quantum, and a newly admitted request joins at
+// its lane's next quantum.  An epoch of TSP, knapsack or colouring takes tens
+// of microseconds, one of QAP or VRPTW several times more.
+inline int quantum_epochs(int kind) { return (kind == KQAP || kind == KVRP) ? 4 : 16; }
 int lane_of(int kind, int stage, uint32_t lds) {
   const int ks = kind == KTSP ? std::min(std::max(stage, 1), 4) - 1
                               : (kind == KQAP ? 4 + (stage == 1) : (kind == KKNAP ? 6 : (kind == KVRP ? 7 : 8)));
@@ -1353,16 +1357,16 @@ void server_loop(gx_server *S) {
       (void)hipMemcpyAsync(L.items_d[b], L.items_h[b], n_items * sizeof(uint2), hipMemcpyHostToDevice, L.s);
       (void)hipMemcpyAsync(L.slots_d[b], L.slots_h[b], act.size() * sizeof(uint32_t), hipMemcpyHostToDevice, L.s);
       const Group &g = groups[0];
-      // kQuantumEpochs epoch chunks per quantum: launch and host turnaround
-      // are paid once per quantum; requests that finish inside it skip the
-      // remaining launches (their generation window is empty)
-      for (int q = 0; q < kQuantumEpochs; ++q) {
+      // requests that finish inside the quantum skip its remaining launches
+      // (their generation window is empty)
+      const int qe = quantum_epochs(g.kind);
+      for (int q = 0; q < qe; ++q) {
         (void)gxk::evolve_group(g.kind, g.stage, S->jobs_d, L.items_d[b], g.count, S->next + li, g.grid, g.lds, L.s);
         (void)gxk::epoch(S->jobs_d, L.slots_d[b], (uint32_t)act.size(), S->next + li, 1, L.s);
       }
       for (SrvReq *r : act) {
         const uint32_t E = r->hj.E;
-        const uint32_t ng = (uint32_t)std::min<uint64_t>(r->hj.G, ((uint64_t)r->g / E + kQuantumEpochs) * E);
+        const uint32_t ng = (uint32_t)std::min<uint64_t>(r->hj.G, ((uint64_t)r->g / E + qe) * E);
         evals += (uint64_t)r->hj.P * r->hj.C * (ng - r->g);
         r->g = ng;
         if (r->g == r->hj.G) {   // finished: fetch the best solution asynchronously
