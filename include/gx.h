@@ -213,8 +213,9 @@ gx_status gx_solve_batch(gx_ctx *ctx, const gx_instance *const *insts, const gx_
  * that do not fit wait without blocking smaller ones behind them.  Requests
  * are grouped into lanes by kind, staging and LDS class, each lane with its own
  * stream; a lane's scheduling quantum advances every resident request of the
- * lane by four AOS epochs, each one fused launch over all their solutions, so
- * requests that arrive while others run overlap with them on the device.  Finished requests return their best
+ * lane by several AOS epochs (16 for TSP, knapsack and colouring, 4 for QAP and
+ * VRPTW), each one fused launch over all their solutions, so requests that
+ * arrive while others run overlap with them on the device.  Finished requests return their best
  * solution and free their memory.  A result depends only on the request
  * (instance, parameters, seed, instance key), never on what else is resident,
  * so it equals gx_solve on the same request. */
