@@ -42,8 +42,8 @@ struct DevInst {
   const int32_t *edges;            // colouring edge list
 };
 
-// One solve.  Scalars below `g` change as the solve runs; the last workgroup of
-// every launch publishes them (see finish_launch in the kernels).
+// One solve.  Scalars below `g` change as the solve runs; the epoch kernel
+// after every evolve launch updates them.
 struct DevJob {
   const DevInst *inst;
   uint64_t seed;

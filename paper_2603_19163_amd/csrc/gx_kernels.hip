@@ -1,18 +1,20 @@
 // gx_kernels.hip -- gfx950 kernels of the population-parallel local search.
 //
-// One 64-lane workgroup (a single wavefront) evolves one solution (paper,
-// Sec. "GPU Parallelization Strategy": one block per solution).  Per
-// generation (Alg. 1) every lane samples ceil(C/64) composite moves, evaluates
-// their exact integer deltas against the solution and instance data held in
-// LDS, the wave takes the lexicographic argmin of (delta, candidate) with DPP
-// shuffles, and the acceptance test, the move application and the AOS
-// bookkeeping follow in wave-uniform control flow.  Candidates are never
-// copied: a composite of k <= 3 operators is a chain of position maps, and a
-// position of the candidate is read as s[psi_1(psi_2(psi_3(p)))].
+// One workgroup evolves one solution (paper, Sec. "GPU Parallelization
+// Strategy": one block per solution): a single 64-lane wavefront, or two for
+// QAP, whose deltas are LDS-gather heavy.  Per generation (Alg. 1) every lane
+// samples ceil(C/64) composite moves, evaluates their exact integer deltas
+// against the solution and instance data held in LDS, the wave takes the
+// lexicographic argmin of (delta, candidate) with DPP shuffles, and the
+// acceptance test, the move application and the AOS bookkeeping follow in
+// uniform control flow.  Candidates are never copied: a composite of k <= 3
+// operators is a chain of position maps, and a position of the candidate is
+// read as s[psi_1(psi_2(psi_3(p)))].
 //
 // A launch runs the generations up to the next AOS epoch boundary for every
-// solution of every job it covers; the last workgroup of a job to finish
-// folds the job's statistics into the EMA weight update (Eq. ema, Alg. 2).
+// solution of every job it covers; each workgroup adds its operator counts
+// into one of the job's accumulator rows, and the epoch kernel that follows
+// the launch folds them into the EMA weight update (Eq. ema, Alg. 2).
 #include "gx_internal.hpp"
 
 #include <climits>
