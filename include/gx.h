@@ -143,13 +143,31 @@ gx_status gx_instance_free(gx_ctx *ctx, gx_instance *inst);
  *                  the K-step weights reset to (0.8, 0.15, 0.05) [5]
  *  aos_credit      0 every candidate credits its operators, 1 only the accepted move [0]
  *  oversample_k    pool of oversample_k * P starting solutions [4]
- *  staging         GX_STAGE_* for TSP [GX_STAGE_AUTO] */
+ *  staging         GX_STAGE_* for TSP [GX_STAGE_AUTO]
+ * Island model and elite injection (paper, Sec. "Island Model and Elite
+ * Injection"), applied at the end of an AOS epoch e, after the weight update:
+ *  islands         I islands of P / I consecutive solutions (P a multiple of
+ *                  I, at least 2 per island, I <= 64) [0: one population]
+ *  migrate_epochs  migration when e is a multiple of it [0: never]: the
+ *                  elites (best-so-far solutions) replace the worst current
+ *                  solutions of the receiving islands, all chosen before the
+ *                  first copy; mode 0 ring (island i's best to island i+1),
+ *                  1 top-N (the population's N best to every island), 2 hybrid
+ *                  (ring when e / migrate_epochs is odd, top-N when even) [0]
+ *  migrate_n       N of top-N, <= 8 and below the island size [1]
+ *  elite_epochs    elite injection when e is a multiple of it: the
+ *                  population's best replaces its worst [0: never]
+ * "best" is the smallest (best objective, index), "worst" the largest
+ * (current objective, index); a replaced solution takes the elite as its
+ * current solution, and as its own best when that improves it. */
 typedef struct {
   uint64_t seed;
   uint32_t generations, population, candidates, op_mask;
   uint64_t t0_q16;
   uint32_t alpha_q32, aos_epoch, aos_alpha_q16, w_floor_q16;
   uint32_t stagnation_epochs, aos_credit, oversample_k, staging;
+  uint32_t islands, migrate_epochs, migrate_mode, migrate_n;
+  uint32_t elite_epochs, reserved;
 } gx_solve_params;
 
 /* Population the library would use for P = 0 on this instance. */

@@ -48,7 +48,9 @@ class _Params(C.Structure):
                 ("candidates", C.c_uint32), ("op_mask", C.c_uint32), ("t0_q16", C.c_uint64),
                 ("alpha_q32", C.c_uint32), ("epoch", C.c_uint32), ("aos_alpha_q16", C.c_uint32),
                 ("w_floor_q16", C.c_uint32), ("stagnation_epochs", C.c_uint32),
-                ("credit", C.c_uint32), ("oversample_k", C.c_uint32), ("pad_", C.c_uint32)]
+                ("credit", C.c_uint32), ("oversample_k", C.c_uint32), ("islands", C.c_uint32),
+                ("migrate_epochs", C.c_uint32), ("migrate_mode", C.c_uint32), ("migrate_n", C.c_uint32),
+                ("elite_epochs", C.c_uint32)]
 
 
 class _State(C.Structure):
@@ -88,6 +90,7 @@ def lib():
         L.or_apply_op.argtypes = [C.c_void_p, P64, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32]
         L.or_initial_weights.argtypes = [C.c_void_p, C.c_uint32, P32]
         L.or_aos_update.argtypes = [C.POINTER(_Params), C.c_uint32, C.POINTER(_State), C.c_int64]
+        L.or_migrate.argtypes = [C.POINTER(_Params), C.c_int, C.POINTER(_State), C.c_uint32]
         L.or_heuristic_perms.argtypes = [C.c_void_p, P64, C.c_int]
         L.or_heuristic_perms.restype = C.c_int
         L.or_init.argtypes = [C.c_void_p, C.POINTER(_Params), C.POINTER(_State)]
@@ -137,7 +140,9 @@ def _params(p) -> _Params:
                    epoch=p.epoch or 10, aos_alpha_q16=p.aos_alpha_q16 or 49152,
                    w_floor_q16=p.w_floor_q16 or 1024,
                    stagnation_epochs=p.stagnation_epochs or 5, credit=p.credit,
-                   oversample_k=p.oversample_k or 4)
+                   oversample_k=p.oversample_k or 4, islands=p.islands,
+                   migrate_epochs=p.migrate_epochs, migrate_mode=p.migrate_mode,
+                   migrate_n=p.migrate_n, elite_epochs=p.elite_epochs)
 
 
 class OracleInstance:
@@ -248,6 +253,14 @@ class OracleInstance:
         pp = _params(params)
         m = self.effective_mask(params.op_mask if op_mask is None else op_mask)
         lib().or_aos_update(C.byref(pp), m, C.byref(s), inst_best_now)
+        self._read_back(s, st)
+        return st
+
+    def migrate(self, params, st: dict, epoch: int) -> dict:
+        """Migration and elite injection at the end of epoch `epoch` (1-based)."""
+        s = self._state_struct(st)
+        pp = _params(params)
+        lib().or_migrate(C.byref(pp), self.n, C.byref(s), epoch)
         self._read_back(s, st)
         return st
 

@@ -374,6 +374,95 @@ void or_aos_update(const or_params *p, uint32_t mask, or_state *st, int64_t inst
   memset(st->v_k, 0, sizeof(st->v_k));
 }
 
+/* ------------------------------------------------------------ islands
+ * Sec. "Island Model and Elite Injection".  Readings: island i holds the
+ * consecutive solutions [i S, (i+1) S), S = P / I.  At the end of epoch e
+ * (after the AOS update) with e % migrate_epochs == 0, elites -- best-so-far
+ * solutions -- replace the worst current solutions of the receiving islands;
+ * every source and every target is chosen on the state before the first copy:
+ *   ring:   the best of island i replaces the worst of island (i + 1) mod I;
+ *   top-N:  the N best of the population replace the N worst of every island
+ *           (the k-th best the k-th worst);
+ *   hybrid: ring at odd-numbered migrations (e / migrate_epochs odd), top-N
+ *           at even ones.
+ * Elite injection (e % elite_epochs == 0, after the migration): the best of
+ * the population replaces its worst.  best = smallest (best_f, index); worst
+ * = largest (cur_f, index).  A replaced solution takes the elite's vector and
+ * objective as its current solution, and as its own best when it improves it. */
+static void mig_put(or_state *st, int n, int tgt, const int32_t *vec, int64_t f) {
+  memcpy(st->cur + (size_t)tgt * n, vec, sizeof(int32_t) * n);
+  st->cur_f[tgt] = f;
+  if (f < st->best_f[tgt]) {
+    st->best_f[tgt] = f;
+    memcpy(st->best + (size_t)tgt * n, vec, sizeof(int32_t) * n);
+  }
+}
+
+static int in_list(const int *l, int cnt, int v) {
+  for (int i = 0; i < cnt; ++i) if (l[i] == v) return 1;
+  return 0;
+}
+
+/* the cnt best of [lo, hi) by (best_f, index), in that order */
+static void best_of_range(const or_state *st, int lo, int hi, int cnt, int *out) {
+  for (int k = 0; k < cnt; ++k) {
+    int b = -1;
+    for (int s = lo; s < hi; ++s)
+      if (!in_list(out, k, s) && (b < 0 || st->best_f[s] < st->best_f[b])) b = s;
+    out[k] = b;
+  }
+}
+
+/* the cnt worst of [lo, hi) by (cur_f, index), worst first */
+static void worst_of_range(const or_state *st, int lo, int hi, int cnt, int *out) {
+  for (int k = 0; k < cnt; ++k) {
+    int w = -1;
+    for (int s = lo; s < hi; ++s)
+      if (!in_list(out, k, s) && (w < 0 || st->cur_f[s] >= st->cur_f[w])) w = s;
+    out[k] = w;
+  }
+}
+
+void or_migrate(const or_params *p, int n, or_state *st, uint32_t e) {
+  const int P = (int)p->population;
+  const int I = p->islands > 1 ? (int)p->islands : 1, S = P / I;
+  if (p->migrate_epochs && e % p->migrate_epochs == 0 && I >= 2) {
+    int mode = (int)p->migrate_mode;
+    if (mode == 2) mode = ((e / p->migrate_epochs) & 1) ? 0 : 1;
+    const int N = mode == 0 ? 1 : (p->migrate_n ? (int)p->migrate_n : 1);
+    const int n_src = mode == 0 ? I : N;
+    int *src = (int *)malloc(sizeof(int) * n_src), *tgt = (int *)malloc(sizeof(int) * I * N);
+    int32_t *vec = (int32_t *)malloc(sizeof(int32_t) * (size_t)n_src * n);
+    int64_t *f = (int64_t *)malloc(sizeof(int64_t) * n_src);
+    if (mode == 0) {
+      for (int i = 0; i < I; ++i) {
+        best_of_range(st, i * S, (i + 1) * S, 1, &src[i]);
+        const int j = (i + 1) % I;
+        worst_of_range(st, j * S, (j + 1) * S, 1, &tgt[i]);
+      }
+    } else {
+      best_of_range(st, 0, P, N, src);
+      for (int i = 0; i < I; ++i) worst_of_range(st, i * S, (i + 1) * S, N, &tgt[i * N]);
+    }
+    for (int k = 0; k < n_src; ++k) {   /* sources read before any copy */
+      memcpy(vec + (size_t)k * n, st->best + (size_t)src[k] * n, sizeof(int32_t) * n);
+      f[k] = st->best_f[src[k]];
+    }
+    if (mode == 0)
+      for (int i = 0; i < I; ++i) mig_put(st, n, tgt[i], vec + (size_t)i * n, f[i]);
+    else
+      for (int i = 0; i < I; ++i)
+        for (int k = 0; k < N; ++k) mig_put(st, n, tgt[i * N + k], vec + (size_t)k * n, f[k]);
+    free(src); free(tgt); free(vec); free(f);
+  }
+  if (p->elite_epochs && e % p->elite_epochs == 0) {
+    int b, w;
+    best_of_range(st, 0, P, 1, &b);
+    worst_of_range(st, 0, P, 1, &w);
+    if (w != b) mig_put(st, n, w, st->best + (size_t)b * n, st->best_f[b]);
+  }
+}
+
 /* ------------------------------------------------------------ init
  * Sec. "Attribute-Agnostic Heuristic Initialization": row sums and column
  * sums of every n x n data matrix, sorted ascending and descending, give four
@@ -563,6 +652,7 @@ int or_run(const or_inst *in, const or_params *p, or_state *st, uint32_t n_gens)
       int64_t ib = st->best_f[0];
       for (int s = 1; s < P; ++s) if (st->best_f[s] < ib) ib = st->best_f[s];
       or_aos_update(p, mask, st, ib);
+      or_migrate(p, n, st, (g + 1) / p->epoch);
     }
     st->g = g + 1;
   }

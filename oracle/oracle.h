@@ -26,7 +26,10 @@ typedef struct {
   uint32_t generations, population, candidates, op_mask;
   uint64_t t0_q16;
   uint32_t alpha_q32, epoch, aos_alpha_q16, w_floor_q16, stagnation_epochs, credit, oversample_k;
-  uint32_t pad_;
+  /* Sec. "Island Model and Elite Injection": islands (0 or 1: none), migration
+   * every migrate_epochs epochs (0: never) in mode 0 ring, 1 top-N, 2 hybrid,
+   * N = migrate_n (0: 1), elite injection every elite_epochs epochs (0: never) */
+  uint32_t islands, migrate_epochs, migrate_mode, migrate_n, elite_epochs;
 } or_params;
 
 /* Epoch-boundary state of one solve.  Arrays are caller-owned. */
@@ -59,6 +62,7 @@ int32_t  or_dist(const or_inst *, int32_t u, int32_t v);  /* TSP / VRPTW distanc
 int      or_apply_op(const or_inst *, int32_t *x, int op, uint32_t w1, uint32_t w2, uint32_t w3);
 void     or_initial_weights(const or_inst *, uint32_t op_mask, uint32_t w_op[OR_MAX_OPS]);
 void     or_aos_update(const or_params *, uint32_t op_mask, or_state *st, int64_t inst_best_now);
+void     or_migrate(const or_params *, int n, or_state *st, uint32_t epoch);  /* epoch: 1-based count */
 int      or_heuristic_perms(const or_inst *, int32_t *out, int cap); /* returns count */
 int      or_init(const or_inst *, const or_params *, or_state *st);
 int      or_run(const or_inst *, const or_params *, or_state *st, uint32_t n_gens);

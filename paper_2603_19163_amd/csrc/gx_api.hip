@@ -514,6 +514,12 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
   const uint32_t K = p->oversample_k ? p->oversample_k : 4;
   if ((uint64_t)K * P > (1u << 22)) return fail(c, GX_E_UNSUPPORTED, "oversample pool <= 2^22");
   if (p->staging > SGLB32) return fail(c, GX_E_INVALID, "unknown staging %u", p->staging);
+  const uint32_t isl = p->islands > 1 ? p->islands : 1;
+  if (isl > 1 && (isl > 64 || P % isl != 0 || P / isl < 2))
+    return fail(c, GX_E_INVALID, "islands <= 64 dividing the population into islands of >= 2 (P = %u)", P);
+  if (p->migrate_mode > 2) return fail(c, GX_E_INVALID, "migrate_mode is 0 (ring), 1 (top-N) or 2 (hybrid)");
+  const uint32_t mig_n = p->migrate_n ? p->migrate_n : 1;
+  if (mig_n > 8 || (isl > 1 && mig_n >= P / isl)) return fail(c, GX_E_INVALID, "migrate_n <= 8 and below the island size");
   const uint32_t stage = resolve_stage(ii, p->staging);
   if (ii.h.kind == KTSP) {
     if ((stage == SLDS16 || stage == SGLB16) && !ii.has_d16)
@@ -541,6 +547,11 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
   h.Q = K * P;
   h.stage = stage;
   h.lds_bytes = lds;
+  h.islands = isl;
+  h.mig_epochs = p->migrate_epochs;
+  h.mig_mode = p->migrate_mode;
+  h.mig_n = mig_n;
+  h.elite_epochs = p->elite_epochs;
   return GX_OK;
 }
 

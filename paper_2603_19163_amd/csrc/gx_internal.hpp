@@ -51,7 +51,8 @@ struct DevJob {
   uint32_t P, C, G, E;
   uint32_t op_mask, credit, aos_A, w_floor;
   uint32_t stag_limit, key, alpha, Q;     // Q = oversample pool size
-  uint32_t stage, lds_bytes, pad1, pad2;
+  uint32_t stage, lds_bytes, islands, mig_epochs;   // island model: see gx_solve_params
+  uint32_t mig_mode, mig_n, elite_epochs, pad1;
   // ---- mutable state
   uint32_t g, g_stop, stag, done;
   uint64_t T;

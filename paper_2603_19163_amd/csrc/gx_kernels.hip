@@ -1454,6 +1454,113 @@ __device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LSta
 
 }  // namespace
 
+// ------------------------------------------------------------ islands
+// Island model and elite injection (paper, Sec. "Island Model and Elite
+// Injection") at the end of epoch e, by the epoch kernel's wave: island i
+// holds solutions [i S, (i+1) S); elites (best-so-far solutions) replace the
+// worst current solutions of the receiving islands, every source and target
+// chosen before the first copy (ring: island i's best to island i+1; top-N:
+// the population's N best to every island; hybrid: ring when e / interval is
+// odd, top-N when even); then elite injection puts the population's best in
+// place of its worst.  best = smallest (best f, index), worst = largest
+// (current f, index).  Sources are staged in the job's pool rows (free after
+// the initialisation); each lane copies the same elements in both passes.
+constexpr int kMaxIslands = 64, kMaxMigN = 8;
+
+__device__ __forceinline__ bool listed(const int *l, int cnt, int v) {
+  bool in = false;
+  for (int i = 0; i < cnt; ++i) in |= l[i] == v;
+  return in;
+}
+
+// smallest (v[s], s) over [lo, hi) \ ex (MIN) or largest (MIN = false)
+template <bool MIN>
+__device__ int wave_pick(const int64_t *v, int lo, int hi, const int *ex, int nex) {
+  constexpr unsigned long long kSign = 1ull << 63;
+  unsigned long long bk = ~0ull;   // key of the value, smaller is better
+  uint32_t bs = 0xFFFFFFFFu;       // key of the index, smaller is better
+  for (int s = lo + (int)lane_id(); s < hi; s += kWave) {
+    if (listed(ex, nex, s)) continue;
+    const unsigned long long k = MIN ? ((unsigned long long)v[s] ^ kSign) : ~((unsigned long long)v[s] ^ kSign);
+    const uint32_t ks = MIN ? (uint32_t)s : ~(uint32_t)s;
+    if (k < bk || (k == bk && ks < bs)) {
+      bk = k;
+      bs = ks;
+    }
+  }
+  const unsigned long long m = wave_min_key(bk);
+  const uint32_t r = wave_min_u32(bk == m ? bs : 0xFFFFFFFFu);
+  return (int)(MIN ? r : ~r);
+}
+
+// solution t takes vector src (n entries, read by each lane at its own
+// elements) with objective f as its current one, and as its best when better
+__device__ void mig_put(DevJob *J, int n, int t, const int32_t *src, int64_t f) {
+  int32_t *c = J->cur + (size_t)t * n, *b = J->best + (size_t)t * n;
+  const bool better = f < J->best_f[t];
+  for (int p = (int)lane_id(); p < n; p += kWave) {
+    const int32_t x = src[p];
+    c[p] = x;
+    if (better) b[p] = x;
+  }
+  if (lane_id() == 0) {
+    J->cur_f[t] = f;
+    if (better) J->best_f[t] = f;
+  }
+}
+
+__device__ void migrate_wave(DevJob *J, uint32_t e) {
+  __shared__ int s_src[kMaxIslands], s_tgt[kMaxIslands * kMaxMigN];
+  __shared__ long long s_f[kMaxIslands];
+  const int P = (int)J->P, n = J->inst->n, I = (int)J->islands, S = P / I;
+  if (J->mig_epochs && e % J->mig_epochs == 0 && I >= 2) {
+    int mode = (int)J->mig_mode;
+    if (mode == 2) mode = ((e / J->mig_epochs) & 1) ? 0 : 1;
+    const int N = mode == 0 ? 1 : (int)J->mig_n, n_src = mode == 0 ? I : N;
+    int chosen[kMaxMigN];
+    if (mode == 0) {
+      for (int i = 0; i < I; ++i) {
+        const int j = i + 1 == I ? 0 : i + 1;
+        const int src = wave_pick<true>(J->best_f, i * S, (i + 1) * S, chosen, 0);
+        const int tgt = wave_pick<false>(J->cur_f, j * S, (j + 1) * S, chosen, 0);
+        if (lane_id() == 0) {
+          s_src[i] = src;
+          s_tgt[i] = tgt;
+        }
+      }
+    } else {
+      for (int k = 0; k < N; ++k) {
+        chosen[k] = wave_pick<true>(J->best_f, 0, P, chosen, k);
+        if (lane_id() == 0) s_src[k] = chosen[k];
+      }
+      for (int i = 0; i < I; ++i)
+        for (int k = 0; k < N; ++k) {
+          chosen[k] = wave_pick<false>(J->cur_f, i * S, (i + 1) * S, chosen, k);
+          if (lane_id() == 0) s_tgt[i * N + k] = chosen[k];
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < n_src; ++k) {   // sources first, into the pool rows
+      const int src = s_src[k];
+      for (int p = (int)lane_id(); p < n; p += kWave) J->pool[(size_t)k * n + p] = J->best[(size_t)src * n + p];
+      if (lane_id() == 0) s_f[k] = J->best_f[src];
+    }
+    __syncthreads();
+    if (mode == 0)
+      for (int i = 0; i < I; ++i) mig_put(J, n, s_tgt[i], J->pool + (size_t)i * n, s_f[i]);
+    else
+      for (int i = 0; i < I; ++i)
+        for (int k = 0; k < N; ++k) mig_put(J, n, s_tgt[i * N + k], J->pool + (size_t)k * n, s_f[k]);
+    __threadfence();   // objectives written by lane 0, read by every lane below
+  }
+  if (J->elite_epochs && e % J->elite_epochs == 0) {
+    int none[1];
+    const int b = wave_pick<true>(J->best_f, 0, P, none, 0);
+    const int w = wave_pick<false>(J->cur_f, 0, P, none, 0);
+    if (w != b) mig_put(J, n, w, J->best + (size_t)b * n, J->best_f[b]);
+  }
+}
+
 // After each evolve launch: fold the accumulator rows of every job into its
 // epoch statistics, the instance best and the temperature, and at an epoch
 // boundary apply the AOS update (the kernel boundary orders it after every
@@ -1503,6 +1610,7 @@ __global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx,
   // signed minimum through the unsigned order of v ^ 2^63
   constexpr unsigned long long kSign = 1ull << 63;
   const long long mn = (long long)(wave_min_key(v[kCountSlots] ^ kSign) ^ kSign);
+  if (g1 % E == 0 && (J->mig_epochs | J->elite_epochs)) migrate_wave(J, g1 / E);
   if (tid != 0) return;
 #pragma unroll
   for (int o = 0; o < kOps; ++o) {

@@ -46,7 +46,9 @@ class gx_solve_params(C.Structure):
                 ("candidates", C.c_uint32), ("op_mask", C.c_uint32), ("t0_q16", C.c_uint64),
                 ("alpha_q32", C.c_uint32), ("aos_epoch", C.c_uint32), ("aos_alpha_q16", C.c_uint32),
                 ("w_floor_q16", C.c_uint32), ("stagnation_epochs", C.c_uint32),
-                ("aos_credit", C.c_uint32), ("oversample_k", C.c_uint32), ("staging", C.c_uint32)]
+                ("aos_credit", C.c_uint32), ("oversample_k", C.c_uint32), ("staging", C.c_uint32),
+                ("islands", C.c_uint32), ("migrate_epochs", C.c_uint32), ("migrate_mode", C.c_uint32),
+                ("migrate_n", C.c_uint32), ("elite_epochs", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class gx_device_info(C.Structure):
@@ -214,7 +216,10 @@ def _params(p) -> gx_solve_params:
                            t0_q16=p.t0_q16, alpha_q32=p.alpha_q32, aos_epoch=p.epoch,
                            aos_alpha_q16=p.aos_alpha_q16, w_floor_q16=p.w_floor_q16,
                            stagnation_epochs=p.stagnation_epochs, aos_credit=p.credit,
-                           oversample_k=p.oversample_k, staging=getattr(p, "staging", 0))
+                           oversample_k=p.oversample_k, staging=getattr(p, "staging", 0),
+                           islands=getattr(p, "islands", 0), migrate_epochs=getattr(p, "migrate_epochs", 0),
+                           migrate_mode=getattr(p, "migrate_mode", 0), migrate_n=getattr(p, "migrate_n", 0),
+                           elite_epochs=getattr(p, "elite_epochs", 0))
 
 
 def gx_autosize_population(ctx, inst, params) -> int:

@@ -86,6 +86,11 @@ class Params:
     credit: int = 0            # 0: every candidate credits its ops, 1: accepted move only
     oversample_k: int = 4
     staging: int = 0           # TSP distance staging (0 = library's choice)
+    islands: int = 0           # island model: 0 or 1 = one population
+    migrate_epochs: int = 0    # migration every this many epochs (0 = never)
+    migrate_mode: int = 0      # 0 ring, 1 global top-N, 2 hybrid
+    migrate_n: int = 0         # N of top-N (0 = 1)
+    elite_epochs: int = 0      # elite injection every this many epochs (0 = never)
 
     def with_(self, **kw) -> "Params":
         return replace(self, **kw)

@@ -164,6 +164,20 @@ def test_qap_ragged_rows(ctx, n):
           [25], f"qap n={n}")
 
 
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_island_migration_and_elite_injection(ctx, mode):
+    # migrations every epoch (hybrid alternates), elite injection every second
+    p = P(seed=17, population=12, candidates=64, G=60, islands=4, migrate_epochs=1, migrate_mode=mode,
+          migrate_n=2, elite_epochs=2)
+    check(ctx, synth.tsp_uniform(25, 6, key=21), p, [20, 20, 20], f"islands mode {mode}")
+
+
+def test_islands_on_two_wave_qap(ctx):
+    p = P(seed=19, population=8, candidates=128, G=40, islands=2, migrate_epochs=1, migrate_mode=1,
+          migrate_n=2, elite_epochs=1, op_mask=synth.PERM_OPS)
+    check(ctx, synth.qap_random(16, 7, key=23), p, [20, 20], "qap islands")
+
+
 def test_greedy_and_random_walk_limits(ctx):
     check(ctx, synth.tsp_uniform(25, 5, key=1), P(seed=2, population=3, candidates=64, G=20, t0_q16=1), [20], "greedy")
     check(ctx, synth.knapsack_random(40, 5, key=1),
@@ -226,6 +240,11 @@ def test_invalid_arguments_are_rejected(ctx):
     bad = synth.Instance(synth.TSP, 3, np.array([[0, 1, 2], [1, 0, 5], [3, 5, 0]]), key=0)
     with pytest.raises(gx.GxError):
         gx.gx_instance_upload(ctx, bad)          # not symmetric
+    for bad_p in (P(seed=1, population=10, G=10, islands=4), P(seed=1, population=8, G=10, islands=4, migrate_mode=3),
+                  P(seed=1, population=8, G=10, islands=4, migrate_n=2), P(seed=1, population=130, G=10, islands=65)):
+        with pytest.raises(gx.GxError) as e:
+            gx.gx_solve(ctx, h, bad_p)
+        assert e.value.status == gx.GX_E_INVALID
     with pytest.raises(gx.GxError) as e:
         gx.gx_instance_upload(ctx, synth.qap_random(70, 0))
     assert e.value.status == gx.GX_E_UNSUPPORTED
