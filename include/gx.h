@@ -63,7 +63,9 @@ enum {
   GX_OP_INSERT = 1u << 2,  /* move one element */
   GX_OP_OROPT = 1u << 3,   /* move a block of 2 or 3 elements, orientation kept */
   GX_OP_FLIP = 1u << 4,    /* binary: flip one bit */
-  GX_OP_RESET = 1u << 5    /* integer: draw a new value in [lb, ub] */
+  GX_OP_SEGFLIP = 1u << 5, /* binary: flip L = 2..7 consecutive bits */
+  GX_OP_RESET = 1u << 6,   /* integer: draw a new value in [lb, ub] */
+  GX_OP_SEGRESET = 1u << 7 /* integer: set L = 2..7 consecutive elements to one new value */
 };
 
 /* Where a TSP instance's distances live during the evolve kernel. */
@@ -197,7 +199,7 @@ typedef struct {
   uint32_t evolve_launches;   /* evolve-kernel launches so far */
   float evolve_ms;            /* device time between the first and last evolve launch of the
                                  last gx_job_advance (HIP events on the context stream) */
-  uint64_t op_steps[6];       /* operator steps evaluated over the run, per operator id */
+  uint64_t op_steps[8];       /* operator steps evaluated over the run, per operator id */
   uint64_t k_count[3];        /* candidates with k = 1, 2, 3 operators over the run */
 } gx_job_info;
 gx_status gx_job_info_get(gx_ctx *ctx, gx_job *job, gx_job_info *out);
@@ -207,8 +209,8 @@ typedef struct {
   uint32_t g, stag;
   uint64_t T_q16;
   int64_t epoch_ref;          /* instance best at the start of the current epoch */
-  uint32_t w_op[6], w_k[3], pad_;
-  uint64_t u_op[6], v_op[6], u_k[3], v_k[3];   /* statistics of the current epoch */
+  uint32_t w_op[8], w_k[3], pad_;
+  uint64_t u_op[8], v_op[8], u_k[3], v_k[3];   /* statistics of the current epoch */
   uint64_t accepted;
 } gx_state_scalars;
 /* Copy the job state to host buffers (any array may be NULL); synchronises.

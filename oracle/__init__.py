@@ -22,7 +22,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-N_OPS = 6
+N_OPS = 8
 
 
 def build(force: bool = False) -> str:

@@ -25,7 +25,8 @@
 #include <string.h>
 
 enum { K_TSP = 1, K_QAP = 2, K_KNAP = 3, K_VRPTW = 4, K_COLOR = 5 };
-enum { OP_2OPT = 0, OP_SWAP = 1, OP_INSERT = 2, OP_OROPT = 3, OP_FLIP = 4, OP_RESET = 5 };
+enum { OP_2OPT = 0, OP_SWAP = 1, OP_INSERT = 2, OP_OROPT = 3, OP_FLIP = 4, OP_SEGFLIP = 5, OP_RESET = 6,
+       OP_SEGRESET = 7 };
 
 struct or_inst {
   or_inst_desc d;
@@ -243,6 +244,21 @@ int or_apply_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2,
     x[i] = in->d.lb + (int32_t)rmap(w2, (uint32_t)(in->d.ub - in->d.lb + 1));
     return op;
   }
+  /* Tab. operators, segment level: seg_flip flips, seg_reset sets to one new
+   * value, the L consecutive elements starting at a.  reading: L = 2 +
+   * floor(w3 * 6 / 2^32) (2..7), at most n; a = floor(w1 * (n - L + 1) / 2^32); the
+   * value as for random_reset */
+  if (op == OP_SEGFLIP || op == OP_SEGRESET) {
+    uint32_t L = 2 + rmap(w3, 6);
+    if (L > (uint32_t)n) L = (uint32_t)n;
+    const uint32_t a = rmap(w1, (uint32_t)n - L + 1);
+    const int32_t v = in->d.lb + (int32_t)rmap(w2, (uint32_t)(in->d.ub - in->d.lb + 1));
+    for (uint32_t p = a; p < a + L; ++p) {
+      if (op == OP_SEGFLIP) x[p] ^= 1;
+      else x[p] = v;
+    }
+    return op;
+  }
   if (n < 2) return op;                      /* every permutation move is the identity */
   if (op == OP_2OPT || op == OP_SWAP) {
     uint32_t i = rmap(w1, n), j = rmap(w2, n - 1);
@@ -275,8 +291,8 @@ int or_apply_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2,
 
 /* ------------------------------------------------------------ encodings */
 static uint32_t encoding_ops(int kind) {
-  if (kind == K_KNAP) return 1u << OP_FLIP;
-  if (kind == K_COLOR) return 1u << OP_RESET;
+  if (kind == K_KNAP) return (1u << OP_FLIP) | (1u << OP_SEGFLIP);
+  if (kind == K_COLOR) return (1u << OP_RESET) | (1u << OP_SEGRESET);
   return (1u << OP_2OPT) | (1u << OP_SWAP) | (1u << OP_INSERT) | (1u << OP_OROPT);
 }
 

@@ -12,7 +12,7 @@
 #define GX_ORACLE_H
 #include <stdint.h>
 
-#define OR_MAX_OPS 6
+#define OR_MAX_OPS 8
 
 typedef struct {
   int32_t kind, n;

@@ -7,13 +7,13 @@
 namespace gx {
 
 constexpr int kWave = 64;
-constexpr int kOps = 6;
+constexpr int kOps = 8;
 // Each evolve workgroup adds its per-launch counts (19 of them) into one of
 // kShards rows of kEpochSlots 64-bit accumulators, picked by its solution
 // index, and lowers the row's smallest best objective (slot 19); the epoch
 // kernel folds the rows and clears them for the next launch.
 constexpr int kShards = 64;
-constexpr int kEpochSlots = 20;
+constexpr int kEpochSlots = 2 * kOps + 8;   // counts (uses, improvements per operator and k; accepted), minimum
 constexpr int kMaxQapN = 64;
 constexpr uint32_t kQapListPerN = 24;   // QAP entry-list capacity per window: 24 n entries
 constexpr int kMaxVrpN = 250;
@@ -21,7 +21,8 @@ constexpr int kMaxCoord = 1 << 14;
 constexpr int64_t kDeltaBias = int64_t(1) << 47;   // argmin key = ((delta + bias) << 16) | t
 
 enum Kind : int32_t { KTSP = 1, KQAP = 2, KKNAP = 3, KVRP = 4, KCOLOR = 5 };
-enum Op : int32_t { O2OPT = 0, OSWAP = 1, OINS = 2, OOROPT = 3, OFLIP = 4, ORESET = 5 };
+// operator ids: permutation 0-3, binary 4-5, integer 6-7 (contiguous per encoding)
+enum Op : int32_t { O2OPT = 0, OSWAP = 1, OINS = 2, OOROPT = 3, OFLIP = 4, OSFLIP = 5, ORESET = 6, OSRESET = 7 };
 enum Stage : int32_t { SAUTO = 0, SLDS16 = 1, SLDSXY = 2, SGLB16 = 3, SGLB32 = 4 };
 
 // One uploaded instance.  All pointers are device pointers owned by the instance.

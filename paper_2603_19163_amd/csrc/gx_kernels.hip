@@ -82,12 +82,15 @@ struct Step {
 
 // weighted choice from Q16 weights: u = floor(u16 * S / 2^16); smallest i with
 // u < cumsum_i.  An encoding's operators are contiguous ids (permutations 0-3,
-// binary 4, integer 5) and the others have weight 0, so only the encoding's
-// own cumulative sums matter.
+// binary 4-5, integer 6-7) and the others have weight 0, so only the
+// encoding's own cumulative sums matter.
 template <int ENC>
 __device__ __forceinline__ int pick_op(uint32_t u16, const Uni &U) {
-  if (ENC == 1) return OFLIP;
-  if (ENC == 2) return ORESET;
+  if (ENC != 0) {
+    constexpr int lo = ENC == 1 ? OFLIP : ORESET;
+    const uint32_t u = (uint32_t)(((uint64_t)u16 * U.sw) >> 16);
+    return lo + (U.w[lo] <= u);
+  }
   const uint32_t u = (uint32_t)(((uint64_t)u16 * U.sw) >> 16);
   uint32_t c = U.w[0];
   int r = (c <= u);
@@ -116,12 +119,14 @@ __device__ __forceinline__ Step make_step(int op, uint32_t r1, uint32_t r2, uint
     s.b = (int)(rv ? max(i, j) : j);
     s.c = (int)L;
     if (n < 2) s.a = s.b = s.c = 0;
-  } else if (ENC == 1) {
-    s.a = (int)rmap(r1, n);
-    s.b = 0;
   } else {
-    s.a = (int)rmap(r1, n);
-    s.b = U.lb + (int)rmap(r2, (uint32_t)(U.ub - U.lb + 1));
+    // flip / random reset: one element; seg_flip / seg_reset: L = 2..7
+    // consecutive elements (at most n) from a; a step covers [a, a + c)
+    const bool seg = op == OSFLIP || op == OSRESET;
+    const uint32_t L = seg ? min(2u + rmap(r3, 6u), n) : 1u;
+    s.a = (int)rmap(r1, n - L + 1);
+    s.b = ENC == 1 ? 0 : U.lb + (int)rmap(r2, (uint32_t)(U.ub - U.lb + 1));
+    s.c = (int)L;
   }
   return s;
 }
@@ -176,7 +181,7 @@ struct LStats {
 template <int ENC>
 __device__ __forceinline__ void credit(LStats &S, const Step *st, int k, bool imp) {
   constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
-  constexpr int hi = ENC == 0 ? OOROPT : lo;
+  constexpr int hi = ENC == 0 ? OOROPT : lo + 1;
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     if (m < k) {
@@ -444,19 +449,22 @@ struct KnapK {
   const int32_t *w, *v;
   int n;
   int64_t W, V, cap, lam;
+  // step m flips the bits [a, a + c); a bit's value before step m is its
+  // stored value flipped by every earlier step that covers it
   __device__ __forceinline__ void dwv(const Step *st, int k, int64_t &dW, int64_t &dV) const {
     dW = 0;
     dV = 0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       if (m < k) {
-        const int i = st[m].a;
-        int b = bits[i];
-        if (m > 0 && st[0].a == i) b ^= 1;
-        if (m > 1 && st[1].a == i) b ^= 1;
-        const int sg = b ? -1 : 1;
-        dW += sg * w[i];
-        dV += sg * v[i];
+        for (int i = st[m].a; i < st[m].a + st[m].c; ++i) {
+          int b = bits[i];
+          if (m > 0 && (uint32_t)(i - st[0].a) < (uint32_t)st[0].c) b ^= 1;
+          if (m > 1 && (uint32_t)(i - st[1].a) < (uint32_t)st[1].c) b ^= 1;
+          const int sg = b ? -1 : 1;
+          dW += sg * w[i];
+          dV += sg * v[i];
+        }
       }
     }
   }
@@ -477,7 +485,8 @@ struct KnapK {
     if (lane_id() == 0)
 #pragma unroll
       for (int m = 0; m < 3; ++m)
-        if (m < k) bits[st[m].a] ^= 1;
+        if (m < k)
+          for (int i = st[m].a; i < st[m].a + st[m].c; ++i) bits[i] ^= 1;
     __syncthreads();
   }
   __device__ __forceinline__ void store(int32_t *dst) const {
@@ -492,21 +501,30 @@ struct ColorK {
   int16_t *val;
   const int32_t *off, *adj;
   int n;
-  __device__ __forceinline__ int vb(const Step *st, int m, int p) const {
+  // value of p while step m sets position i: after the earlier steps
+  // (each sets [a, a + c) to b) and the positions of step m before i
+  __device__ __forceinline__ int vb(const Step *st, int m, int i, int p) const {
     int v = val[p];
-    if (m > 0 && st[0].a == p) v = st[0].b;
-    if (m > 1 && st[1].a == p) v = st[1].b;
+    if (m > 0 && (uint32_t)(p - st[0].a) < (uint32_t)st[0].c) v = st[0].b;
+    if (m > 1 && (uint32_t)(p - st[1].a) < (uint32_t)st[1].c) v = st[1].b;
+    if (p >= st[m].a && p < i) v = st[m].b;
     return v;
   }
+  // the positions of every step change one at a time, in order: each change
+  // moves the count by the neighbours that match the new value minus those
+  // that matched the old one
   __device__ __forceinline__ int64_t delta(const Step *st, int k, int64_t) const {
     int d = 0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       if (m < k) {
-        const int i = st[m].a, nv = st[m].b, ov = vb(st, m, i);
-        for (int e = off[i]; e < off[i + 1]; ++e) {
-          const int vj = vb(st, m, adj[e]);
-          d += (nv == vj) - (ov == vj);
+        const int nv = st[m].b;
+        for (int i = st[m].a; i < st[m].a + st[m].c; ++i) {
+          const int ov = vb(st, m, i, i);
+          for (int e = off[i]; e < off[i + 1]; ++e) {
+            const int vj = vb(st, m, i, adj[e]);
+            d += (nv == vj) - (ov == vj);
+          }
         }
       }
     }
@@ -516,7 +534,8 @@ struct ColorK {
     if (lane_id() == 0)
 #pragma unroll
       for (int m = 0; m < 3; ++m)
-        if (m < k) val[st[m].a] = (int16_t)st[m].b;
+        if (m < k)
+          for (int i = st[m].a; i < st[m].a + st[m].c; ++i) val[i] = (int16_t)st[m].b;
     __syncthreads();
   }
   __device__ __forceinline__ void store(int32_t *dst) const {
@@ -549,7 +568,7 @@ struct TspScratch {
   __device__ __forceinline__ uint16_t *lst() const { return (uint16_t *)(gx_lds + 2048); } // t | m << 8 | sub << 10
   // extra draws t | m << 8; used only before the pattern list is built
   __device__ __forceinline__ uint16_t *dl() const { return (uint16_t *)(gx_lds + 2048); }
-  __device__ __forceinline__ uint8_t *sop() const { return (uint8_t *)(gx_lds + 3584); }   // op | L << 4 at [3t + m], k << 6 at m = 0
+  __device__ __forceinline__ uint8_t *sop() const { return (uint8_t *)(gx_lds + 3584); }   // op | L << 3 at [3t + m], k << 6 at m = 0
 };
 
 __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
@@ -597,8 +616,8 @@ __device__ __forceinline__ void unpack_step(const TspScratch &W, int t, int m, i
   const uint32_t ol = W.sop()[3 * t + m];
   a = (int)(ab & 0xFFFFu);
   b = (int)(ab >> 16);
-  op = (int)(ol & 15u);
-  L = (int)((ol >> 4) & 3u);
+  op = (int)(ol & 7u);
+  L = (int)((ol >> 3) & 7u);
 }
 
 // Draw the composite moves of candidates [c0, c0 + cn): the first step of
@@ -624,7 +643,7 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
       kk[rr] = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
       const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
       W.sab()[3 * tl] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
-      W.sop()[3 * tl] = (uint8_t)(st.op | (st.c << 4) | (kk[rr] << 6));
+      W.sop()[3 * tl] = (uint8_t)(st.op | (st.c << 3) | (kk[rr] << 6));
       if constexpr (RN == 2) W.del()[tl] = 0;
     }
   }
@@ -645,7 +664,7 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
     philox(g, sol, ((c0 + tl) << 2) | m, U.key, U.k0, U.k1, w);
     const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
     W.sab()[3 * tl + m] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
-    W.sop()[3 * tl + m] = (uint8_t)(st.op | (st.c << 4));
+    W.sop()[3 * tl + m] = (uint8_t)(st.op | (st.c << 3));
   }
   __syncthreads();
 }
@@ -658,8 +677,8 @@ __device__ __forceinline__ Step load_step(const TspScratch &W, int t, int m) {
   Step st;
   st.a = (int)(ab & 0xFFFFu);
   st.b = ENC == 2 ? (int)(int16_t)(ab >> 16) : (int)(ab >> 16);
-  st.op = (int)(ol & 15u);
-  st.c = (int)((ol >> 4) & 3u);
+  st.op = (int)(ol & 7u);
+  st.c = (int)((ol >> 3) & 7u);
   return st;
 }
 
@@ -861,7 +880,7 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
           const bool imp = d < 0;
 #pragma unroll
           for (int m = 0; m < 3; ++m) {
-            const uint32_t inc = kk[r] > m ? 1u << ((W.sop()[3 * tl + m] & 15u) << 3) : 0u;
+            const uint32_t inc = kk[r] > m ? 1u << ((W.sop()[3 * tl + m] & 7u) << 3) : 0u;
             cu_op += inc;
             cv_op += imp ? inc : 0u;
           }
@@ -1259,7 +1278,7 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
                                          uint32_t &nacc) {
   constexpr int ENC = KD::ENC;
   constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
-  constexpr int nf = ENC == 0 ? 4 : 1;
+  constexpr int nf = ENC == 0 ? 4 : 2;
   const uint32_t lane = lane_id();
   // per-lane byte counts (a chunk adds at most 6 to a field of a lane),
   // folded into the wave-uniform counts of S every 42 chunks and at the end
@@ -1344,7 +1363,7 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
           if (U.credit == 0) {   // the steps again from the tables: fewer registers live across the round
             Step st[3];
 #pragma unroll
-            for (int m = 0; m < 3; ++m) st[m].op = (int)(W.sop()[3 * tl + m] & 15u);
+            for (int m = 0; m < 3; ++m) st[m].op = (int)(W.sop()[3 * tl + m] & 7u);
             credit_bytes<ENC>(cu, cv, cuk, cvk, st, k, d < 0);
           }
           const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | (c0 + tl);
@@ -1418,18 +1437,19 @@ __device__ __forceinline__ void ema_group(uint32_t *w, const unsigned long long 
 }
 
 // Per-launch counts of one workgroup, added into the accumulator row of its
-// solution (row sol mod kShards): slots 0..5 uses and 6..11 improvements per
-// operator, 12..14 uses and 15..17 improvements per k, 18 accepted moves, and
-// the row minimum of the workgroup's best objective in slot 19.  S holds
+// solution (row sol mod kShards): slots [0, kOps) uses and [kOps, 2 kOps)
+// improvements per operator, the next 3 uses and 3 improvements per k, then
+// accepted moves, and the row minimum of the workgroup's best objective in
+// slot kCountSlots.  S holds
 // per-lane counts (summed here over the wave) or, with UNIFORM, counts that
 // are already wave totals.  The atomics need no fence: the epoch kernel reads
 // the rows after the kernel boundary.
-constexpr int kCountSlots = 19;
+constexpr int kCountSlots = 2 * kOps + 7;   // uses, improvements per operator and per k, accepted
 
 template <int ENC, bool UNIFORM>
 __device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LStats &S, uint32_t nacc, int64_t bf) {
   constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
-  constexpr int hi = ENC == 0 ? OOROPT : lo;
+  constexpr int hi = ENC == 0 ? OOROPT : lo + 1;
   const uint32_t lane = lane_id();
   uint32_t mine = 0;
 #pragma unroll
@@ -1437,16 +1457,16 @@ __device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LSta
     const uint32_t u = UNIFORM ? S.u[o] : wave_sum(S.u[o]);
     const uint32_t v = UNIFORM ? S.v[o] : wave_sum(S.v[o]);
     mine = lane == (uint32_t)o ? u : mine;
-    mine = lane == (uint32_t)(6 + o) ? v : mine;
+    mine = lane == (uint32_t)(kOps + o) ? v : mine;
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const uint32_t uk = UNIFORM ? S.uk[q] : wave_sum(S.uk[q]);
     const uint32_t vk = UNIFORM ? S.vk[q] : wave_sum(S.vk[q]);
-    mine = lane == (uint32_t)(12 + q) ? uk : mine;
-    mine = lane == (uint32_t)(15 + q) ? vk : mine;
+    mine = lane == (uint32_t)(2 * kOps + q) ? uk : mine;
+    mine = lane == (uint32_t)(2 * kOps + 3 + q) ? vk : mine;
   }
-  mine = lane == 18u ? nacc : mine;
+  mine = lane == (uint32_t)(2 * kOps + 6) ? nacc : mine;
   unsigned long long *row = J->shard + (size_t)(sol & (kShards - 1)) * kEpochSlots;
   if (lane < (uint32_t)kCountSlots && mine) atomicAdd(&row[lane], (unsigned long long)mine);
   if (lane == (uint32_t)kCountSlots) atomicMin((long long *)&row[kCountSlots], (long long)bf);
@@ -1615,14 +1635,14 @@ __global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx,
 #pragma unroll
   for (int o = 0; o < kOps; ++o) {
     u_op[o] += t[o];
-    v_op[o] += t[6 + o];
+    v_op[o] += t[kOps + o];
     if (credit == 0) tu_op[o] += t[o];
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    u_k[q] += t[12 + q];
-    v_k[q] += t[15 + q];
-    if (credit == 0) tu_k[q] += t[12 + q];
+    u_k[q] += t[2 * kOps + q];
+    v_k[q] += t[2 * kOps + 3 + q];
+    if (credit == 0) tu_k[q] += t[2 * kOps + q];
   }
   if (mn < inst_best) inst_best = mn;
   for (uint32_t g = g0; g < g1; ++g) T = cool(T, alpha);
@@ -1655,7 +1675,7 @@ __global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx,
     J->tot_u_k[q] = tu_k[q];
     J->w_k[q] = w_k[q];
   }
-  J->accepted = accepted + t[18];
+  J->accepted = accepted + t[2 * kOps + 6];
   J->inst_best = inst_best;
   J->epoch_ref = epoch_ref;
   J->stag = stag;

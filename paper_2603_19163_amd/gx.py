@@ -18,7 +18,7 @@ GX_OK, GX_E_INVALID, GX_E_UNSUPPORTED, GX_E_NOMEM, GX_E_DEVICE, GX_E_NOT_READY, 
 STATUS_NAMES = {0: "GX_OK", -1: "GX_E_INVALID", -2: "GX_E_UNSUPPORTED", -3: "GX_E_NOMEM",
                 -4: "GX_E_DEVICE", -5: "GX_E_NOT_READY", -6: "GX_E_BUSY", -7: "GX_E_CANCELLED"}
 STAGE_AUTO, STAGE_LDS_D16, STAGE_LDS_XY, STAGE_GLB_D16, STAGE_GLB_D32 = 0, 1, 2, 3, 4
-N_OPS = 6
+N_OPS = 8
 
 EXPORTED = ["gx_create", "gx_destroy", "gx_last_error", "gx_get_device_info", "gx_instance_upload",
             "gx_instance_free", "gx_autosize_population", "gx_job_create", "gx_job_advance", "gx_solve",

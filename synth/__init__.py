@@ -23,12 +23,12 @@ import numpy as np
 TSP, QAP, KNAPSACK, VRPTW, INTCOLOR = 1, 2, 3, 4, 5
 KIND_NAMES = {TSP: "tsp", QAP: "qap", KNAPSACK: "knapsack", VRPTW: "vrptw", INTCOLOR: "intcolor"}
 
-OP_2OPT, OP_SWAP, OP_INSERT, OP_OROPT, OP_FLIP, OP_RESET = 0, 1, 2, 3, 4, 5
-OP_NAMES = ["2opt", "swap", "insert", "oropt", "flip", "reset"]
-N_OPS = 6
+OP_2OPT, OP_SWAP, OP_INSERT, OP_OROPT, OP_FLIP, OP_SEGFLIP, OP_RESET, OP_SEGRESET = 0, 1, 2, 3, 4, 5, 6, 7
+OP_NAMES = ["2opt", "swap", "insert", "oropt", "flip", "segflip", "reset", "segreset"]
+N_OPS = 8
 PERM_OPS = (1 << OP_2OPT) | (1 << OP_SWAP) | (1 << OP_INSERT) | (1 << OP_OROPT)
-BIN_OPS = 1 << OP_FLIP
-INT_OPS = 1 << OP_RESET
+BIN_OPS = (1 << OP_FLIP) | (1 << OP_SEGFLIP)
+INT_OPS = (1 << OP_RESET) | (1 << OP_SEGRESET)
 
 ENCODING_OF = {TSP: "perm", QAP: "perm", VRPTW: "perm", KNAPSACK: "binary", INTCOLOR: "integer"}
 

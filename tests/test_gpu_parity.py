@@ -178,6 +178,18 @@ def test_islands_on_two_wave_qap(ctx):
     check(ctx, synth.qap_random(16, 7, key=23), p, [20, 20], "qap islands")
 
 
+@pytest.mark.parametrize("mask", ["segment", "both"])
+def test_segment_operators(ctx, mask):
+    # seg_flip / seg_reset alone and with the element operators, composite
+    # moves of up to three overlapping segments
+    kmask = (1 << synth.OP_SEGFLIP) | ((1 << synth.OP_FLIP) if mask == "both" else 0)
+    cmask = (1 << synth.OP_SEGRESET) | ((1 << synth.OP_RESET) if mask == "both" else 0)
+    check(ctx, synth.knapsack_random(40, 4, key=31), P(seed=23, population=4, candidates=128, G=30, op_mask=kmask),
+          [15, 15], f"knapsack {mask}")
+    check(ctx, synth.color_planted(24, 3, key=33), P(seed=29, population=4, candidates=128, G=30, op_mask=cmask),
+          [15, 15], f"colouring {mask}")
+
+
 def test_greedy_and_random_walk_limits(ctx):
     check(ctx, synth.tsp_uniform(25, 5, key=1), P(seed=2, population=3, candidates=64, G=20, t0_q16=1), [20], "greedy")
     check(ctx, synth.knapsack_random(40, 5, key=1),

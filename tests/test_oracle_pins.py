@@ -115,7 +115,7 @@ def test_aos_update_worked_example():
 def test_aos_single_op_and_bounds():
     inst = synth.knapsack_random(30)
     o = oracle.OracleInstance(inst)
-    p = synth.Params(population=1)
+    p = synth.Params(population=1, op_mask=1 << synth.OP_FLIP)
     st = o.new_state(1)
     st["w_op"][4] = 65536
     st["w_k"][:] = [52429, 9830, 3277]
@@ -155,7 +155,7 @@ def test_operator_worked_examples():
     for c in gold("operators.json")["cases"]:
         n = c["n"]
         if c.get("zeros"):
-            if c["op"] == "flip":
+            if c["op"] in ("flip", "segflip"):
                 inst = synth.Instance(synth.KNAPSACK, n, np.ones(n), np.ones(n), capacity=n)
             else:
                 inst = synth.Instance(synth.INTCOLOR, n, np.array([[0, 1]]), lb=c["lb"], ub=c["ub"], n_edges=1)
@@ -437,3 +437,25 @@ def test_planted_circle_is_found():
                      alpha_q32=synth.alpha_q32_for(600))
     st = o.solve(p)
     assert oracle.best_of(st)[0] == o.objective(np.arange(24))
+
+
+@pytest.mark.parametrize("kind", ["knap", "color"])
+def test_segment_ops_keep_encoding_and_shape(kind):
+    n = 12
+    inst = (synth.knapsack_random(n, 0) if kind == "knap"
+            else synth.Instance(synth.INTCOLOR, n, np.array([[0, 1]]), lb=-2, ub=3, n_edges=1))
+    o = oracle.OracleInstance(inst)
+    op = synth.OP_SEGFLIP if kind == "knap" else synth.OP_SEGRESET
+    r = np.random.default_rng(3)
+    for _ in range(300):
+        x = (r.integers(0, 2, n) if kind == "knap" else r.integers(-2, 4, n)).astype(np.int32)
+        w = [int(v) for v in r.integers(0, 2**32, 3, dtype=np.uint64)]
+        y = o.apply_op(x, op, *w)
+        L = min(2 + (w[2] * 6 >> 32), n)
+        a = w[0] * (n - L + 1) >> 32
+        changed = np.nonzero(x != y)[0]
+        assert set(changed) <= set(range(a, a + L))
+        if kind == "knap":
+            assert list(changed) == list(range(a, a + L)) and set(y) <= {0, 1}
+        else:
+            assert len(set(y[a:a + L])) == 1 and -2 <= y.min() and y.max() <= 3
