@@ -8,10 +8,10 @@ namespace gx {
 
 constexpr int kWave = 64;
 constexpr int kOps = 8;
-// Each evolve workgroup adds its per-launch counts (19 of them) into one of
-// kShards rows of kEpochSlots 64-bit accumulators, picked by its solution
-// index, and lowers the row's smallest best objective (slot 19); the epoch
-// kernel folds the rows and clears them for the next launch.
+// Each evolve workgroup adds its per-launch counts (2 kOps + 7 of them) into
+// one of kShards rows of kEpochSlots 64-bit accumulators, picked by its
+// solution index, and lowers the row's smallest best objective (the last
+// slot); the epoch kernel folds the rows and clears them for the next launch.
 constexpr int kShards = 64;
 constexpr int kEpochSlots = 2 * kOps + 8;   // counts (uses, improvements per operator and k; accepted), minimum
 constexpr int kMaxQapN = 64;
