@@ -82,3 +82,34 @@ def test_batch_equals_plain_solver(ctx):
         gx.gx_job_free(ctx, j)
     for h in handles:
         gx.gx_instance_free(ctx, h)
+
+
+def test_autotuner_choices_are_valid_and_result_neutral(ctx):
+    """The tuner returns a supported staging per TSP bucket (0 for other
+    kinds), and a batch solved with the tuned stagings gives the same results
+    as with the default staging: the knob it turns never changes a trajectory."""
+    from paper_2603_19163_amd import autotune
+    insts = [synth.tsp_uniform(40, 31, key=1), synth.tsp_uniform(150, 32, key=2), synth.qap_random(20, 33, key=3)]
+    samples = {autotune.bucket_of(i.kind, i.n): i for i in insts}
+    alpha = synth.alpha_q32_for(200)
+    staging = autotune.tune_buckets(ctx, samples, lambda i: synth.Params(seed=1, generations=50, alpha_q32=alpha),
+                                    generations=20, cache=False)
+    assert set(staging) == set(samples)
+    for b, st in staging.items():
+        assert st in ((1, 2, 3, 4) if b.startswith("1:") else (0,)), (b, st)
+    hs = [gx.gx_instance_upload(ctx, i) for i in insts]
+    out = []
+    for tuned in (False, True):
+        params = [synth.Params(seed=7 + k, generations=60, population=3, candidates=96, alpha_q32=alpha,
+                               staging=staging[autotune.bucket_of(i.kind, i.n)] if tuned else 0)
+                  for k, i in enumerate(insts)]
+        jobs = gx.gx_solve_batch(ctx, hs, params)
+        gx.gx_wait(ctx, jobs[0])
+        res = [gx.gx_fetch_best(ctx, j, i.n) for j, i in zip(jobs, insts)]
+        for j in jobs:
+            gx.gx_job_free(ctx, j)
+        out.append(res)
+    for (s0, f0), (s1, f1) in zip(*out):
+        assert f0 == f1 and np.array_equal(s0, s1)
+    for h in hs:
+        gx.gx_instance_free(ctx, h)
