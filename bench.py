@@ -106,8 +106,9 @@ def main():
     ap.add_argument("--staging", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["tsp442", "batched", "served"], default="tsp442",
-                    help="tsp442: the benchmark line; batched / served: the systems patterns")
+    ap.add_argument("--workload", choices=["tsp442", "batched", "served", "kinds"], default="tsp442",
+                    help="tsp442: the benchmark line; batched / served: the systems patterns; "
+                         "kinds: one solve per encoding, operator set and island setting")
     ap.add_argument("--instances", type=int, default=4096, help="batched: number of instances")
     ap.add_argument("--batch-generations", type=int, default=5000)
     ap.add_argument("--plain-sample", type=int, default=32, help="batched/served: requests solved alone")
@@ -147,6 +148,9 @@ def main():
         return
     if args.workload == "served":
         print(json.dumps(bench_served(args)), flush=True)
+        return
+    if args.workload == "kinds":
+        print(json.dumps(bench_kinds(args)), flush=True)
         return
 
     import torch
@@ -328,6 +332,68 @@ def bench_batched(args):
                                f"C=128, {G} generations; staging per bucket {sorted(set(staging.values()))}",
                    "population": P, "generations": G, "staging_per_bucket": staging},
     }
+
+
+def bench_kinds(args):
+    """Plain-solver throughput of every problem kind and encoding, with and
+    without the segment operators, and of the 442-city TSP with the island
+    model on (ring, global top-N and hybrid migration plus elite injection)
+    against the same solve with one population.  One timed solve per row
+    after one untimed solve of the same row."""
+    import torch
+    import synth
+    from paper_2603_19163_amd import gx
+
+    ctx = gx.gx_create(0, torch.cuda.Stream())
+    g442 = 20_000
+
+    def tsp442(**kw):
+        inst, p = synth.c2_tsp442(population=0, generations=g442)
+        return inst, p.with_(**kw)
+
+    def one(inst, p, G):
+        return inst, synth.Params(seed=42, generations=G, population=p, candidates=128,
+                                  alpha_q32=synth.alpha_q32_for(G))
+
+    isl = dict(islands=16, migrate_epochs=5, elite_epochs=10)
+    rows = [
+        ("tsp442", "TSP n=442 clustered, all permutation ops, one population", tsp442()),
+        ("tsp442_islands_ring", "same, 16 islands, ring migration every 5 epochs, elite every 10",
+         tsp442(**isl, migrate_mode=0)),
+        ("tsp442_islands_topn", "same, 16 islands, global top-4 migration every 5 epochs, elite every 10",
+         tsp442(**isl, migrate_mode=1, migrate_n=4)),
+        ("tsp442_islands_hybrid", "same, 16 islands, hybrid migration every 5 epochs, elite every 10",
+         tsp442(**isl, migrate_mode=2, migrate_n=4)),
+        ("tsp50", "TSP n=50 uniform, P=64, 2-opt/swap/or-opt, 2000 generations", synth.c1_small_tsp(0)),
+        ("vrptw100", "VRPTW 100 customers, giant tour + split, P=64, 5000 generations", synth.c3_vrptw()),
+        ("qap50", "QAP n=50, P=1024, 2000 generations", one(synth.qap_random(50, 7), 1024, 2000)),
+    ]
+    kp_inst, kp = one(synth.knapsack_random(1000, 7), 2048, 5000)
+    rows += [("knapsack1000_flip", "0/1 knapsack n=1000, P=2048, flip only, 5000 generations",
+              (kp_inst, kp.with_(op_mask=1 << synth.OP_FLIP))),
+             ("knapsack1000_flip_segflip", "same, flip + seg_flip", (kp_inst, kp.with_(op_mask=synth.BIN_OPS)))]
+    co_inst, co = one(synth.color_planted(1000, 3, inst_id=7), 2048, 5000)
+    rows += [("color1000_reset", "planted 3-colouring n=1000 (integer encoding), P=2048, reset only, 5000 generations",
+              (co_inst, co.with_(op_mask=1 << synth.OP_RESET))),
+             ("color1000_reset_segreset", "same, reset + seg_reset", (co_inst, co.with_(op_mask=synth.INT_OPS)))]
+    out = []
+    for name, what, (inst, p) in rows:
+        h = gx.gx_instance_upload(ctx, inst)
+        if p.population == 0:
+            p = p.with_(population=gx.gx_autosize_population(ctx, h, p))
+        for rep in range(2):
+            job = gx.gx_solve(ctx, h, p)
+            _, f = gx.gx_fetch_best(ctx, job, inst.n)
+            info = gx.gx_job_info_get(ctx, job)
+            gx.gx_job_free(ctx, job)
+        gx.gx_instance_free(ctx, h)
+        s = info["evolve_ms"] / 1e3
+        out.append({"row": name, "workload": what, "population": p.population,
+                    "move_evals_per_s": info["move_evals"] / s, "avg_launch_us": s * 1e6 / info["evolve_launches"],
+                    "best": int(f), "op_steps": {synth.OP_NAMES[o]: int(info["op_steps"][o])
+                                                 for o in range(len(synth.OP_NAMES)) if info["op_steps"][o]}})
+    gx.gx_destroy(ctx)
+    return {"metric": "move evals/s per problem kind", "unit": "move evals/s", "rows": out}
 
 
 def bench_served(args):

@@ -555,6 +555,10 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
   return GX_OK;
 }
 
+// whether a job's epoch ends can exchange solutions (island migration or
+// elite injection): its epoch kernel then runs the wide variant
+bool migrates(const DevJob &h) { return (h.mig_epochs && h.islands >= 2) || h.elite_epochs; }
+
 int heur_mats_of(int kind) { return kind == KQAP ? 2 : ((kind == KTSP || kind == KVRP) ? 1 : 0); }
 
 // bytes of the per-job device arrays, laid out by carve_job
@@ -682,7 +686,7 @@ gx_status make_groups(gx_ctx *c, std::vector<ItemRec> &recs, uint2 *items, std::
 // (or one after the other on s), then the epoch kernel, which also clears the
 // groups' work-item counters.
 hipError_t launch_groups(const Fan &f, const std::vector<Group> &gs, DevJob *jobs, const uint2 *items,
-                         uint32_t *next, const uint32_t *idx, uint32_t njobs, hipStream_t s) {
+                         uint32_t *next, const uint32_t *idx, uint32_t njobs, bool mig, hipStream_t s) {
   const bool fan = gs.size() > 1 && f.ready && !fan_disabled();
   hipError_t e = fan ? hipEventRecord(f.fork, s) : hipSuccess;
   for (size_t g = 0; e == hipSuccess && g < gs.size(); ++g) {
@@ -694,7 +698,7 @@ hipError_t launch_groups(const Fan &f, const std::vector<Group> &gs, DevJob *job
     if (e == hipSuccess && fan && g > 0) e = hipEventRecord(f.join[g - 1], sg);
   }
   for (size_t g = 1; e == hipSuccess && fan && g < gs.size(); ++g) e = hipStreamWaitEvent(s, f.join[g - 1], 0);
-  return e != hipSuccess ? e : gxk::epoch(jobs, idx, njobs, next, (uint32_t)gs.size(), s);
+  return e != hipSuccess ? e : gxk::epoch(jobs, idx, njobs, next, (uint32_t)gs.size(), mig, s);
 }
 
 // Enqueue L identical evolve launches; a run of 64 is captured once into a
@@ -796,10 +800,11 @@ gx_status gx_job_advance(gx_ctx *c, gx_job *j, uint32_t ng) {
   DevJob *dj = j->d;
   const int kind = j->inst->h.kind, stage = (int)j->h.stage;
   const uint32_t P = j->h.P, lds = j->h.lds_bytes;
+  const bool mig = migrates(j->h);
   hipStream_t s = c->stream;
   gx_status st = enqueue_launches(c, j, L, [=]() {
     const hipError_t e = gxk::evolve_plain(dj, kind, stage, P, lds, s);
-    return e != hipSuccess ? e : gxk::epoch(dj, nullptr, 1, nullptr, 0, s);
+    return e != hipSuccess ? e : gxk::epoch(dj, nullptr, 1, nullptr, 0, mig, s);
   });
   if (st) return st;
   HIPCHK(c, hipEventRecord(j->ev1, c->stream));
@@ -1036,8 +1041,10 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
   hipStream_t s = c->stream;
   const uint32_t njobs = (uint32_t)count;
   const Fan *fan = &c->fan;
+  bool mig = false;
+  for (int i = 0; i < count; ++i) mig |= migrates(hj[i]);
   gx_status st = enqueue_launches(c, lead, L, [=]() {
-    return launch_groups(*fan, groups, jd, itd, next, nullptr, njobs, s);
+    return launch_groups(*fan, groups, jd, itd, next, nullptr, njobs, mig, s);
   });
   if (st) {
     for (gx_job *j : made) delete j;
@@ -1371,9 +1378,11 @@ void server_loop(gx_server *S) {
       // requests that finish inside the quantum skip its remaining launches
       // (their generation window is empty)
       const int qe = quantum_epochs(g.kind);
+      bool mig = false;
+      for (SrvReq *r : act) mig |= migrates(r->hj);
       for (int q = 0; q < qe; ++q) {
         (void)gxk::evolve_group(g.kind, g.stage, S->jobs_d, L.items_d[b], g.count, S->next + li, g.grid, g.lds, L.s);
-        (void)gxk::epoch(S->jobs_d, L.slots_d[b], (uint32_t)act.size(), S->next + li, 1, L.s);
+        (void)gxk::epoch(S->jobs_d, L.slots_d[b], (uint32_t)act.size(), S->next + li, 1, mig, L.s);
       }
       for (SrvReq *r : act) {
         const uint32_t E = r->hj.E;

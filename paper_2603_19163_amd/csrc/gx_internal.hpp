@@ -116,7 +116,8 @@ hipError_t evolve_plain(gx::DevJob *job, int kind, int stage, uint32_t P, uint32
 hipError_t evolve_group(int kind, int stage, gx::DevJob *jobs, const uint2 *items, uint32_t n_items, uint32_t *next,
                         uint32_t grid, uint32_t lds, hipStream_t s);
 hipError_t fetch_best(gx::DevJob *jobs, int count, hipStream_t s);
-hipError_t epoch(gx::DevJob *jobs, const uint32_t *idx, uint32_t count, uint32_t *next, uint32_t n_next,
+// mig: some job of the launch may migrate or inject its elite (island model)
+hipError_t epoch(gx::DevJob *jobs, const uint32_t *idx, uint32_t count, uint32_t *next, uint32_t n_next, bool mig,
                  hipStream_t s);
 hipError_t prepare_kernel_attrs(uint32_t max_lds);
 hipError_t occupancy_plain(int kind, int stage, uint32_t lds, int *blocks_per_cu);

@@ -395,7 +395,6 @@ __device__ __forceinline__ void perm_store(const uint16_t *cur, int n, int32_t *
 // ------------------------------------------------------------ VRPTW (giant tour)
 struct VrpK {
   static constexpr int ENC = 0;
-  static constexpr bool kRound = false;
   uint16_t *cur, *nxt;
   int n, dn, cap, veh, svc, hor;
   const int16_t *D;
@@ -444,7 +443,6 @@ struct VrpK {
 // ------------------------------------------------------------ 0/1 knapsack
 struct KnapK {
   static constexpr int ENC = 1;
-  static constexpr bool kRound = false;
   uint8_t *bits;
   const int32_t *w, *v;
   int n;
@@ -497,7 +495,6 @@ struct KnapK {
 // ------------------------------------------------------------ integer colouring
 struct ColorK {
   static constexpr int ENC = 2;
-  static constexpr bool kRound = false;
   int16_t *val;
   const int32_t *off, *adj;
   int n;
@@ -1010,7 +1007,6 @@ __device__ __forceinline__ SMap smap_unpack(uint2 v) {
 template <class HT>
 struct QapK {
   static constexpr int ENC = 0;
-  static constexpr bool kRound = true;
   uint16_t *cur, *nxt;
   int n, np;             // np: n rounded up to 8 (row stride of F and DX)
   const int16_t *F;      // F[a][b] at a * np + b, zero for b >= n
@@ -1476,16 +1472,17 @@ __device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LSta
 
 // ------------------------------------------------------------ islands
 // Island model and elite injection (paper, Sec. "Island Model and Elite
-// Injection") at the end of epoch e, by the epoch kernel's wave: island i
-// holds solutions [i S, (i+1) S); elites (best-so-far solutions) replace the
-// worst current solutions of the receiving islands, every source and target
-// chosen before the first copy (ring: island i's best to island i+1; top-N:
-// the population's N best to every island; hybrid: ring when e / interval is
-// odd, top-N when even); then elite injection puts the population's best in
-// place of its worst.  best = smallest (best f, index), worst = largest
-// (current f, index).  Sources are staged in the job's pool rows (free after
-// the initialisation); each lane copies the same elements in both passes.
-constexpr int kMaxIslands = 64, kMaxMigN = 8;
+// Injection") at the end of epoch e, by the epoch kernel's workgroup (16 waves
+// for jobs that migrate): island i holds solutions [i S, (i+1) S); elites
+// (best-so-far solutions) replace the worst current solutions of the
+// receiving islands, every source and target chosen before the first copy
+// (ring: island i's best to island i+1; top-N: the population's N best to
+// every island; hybrid: ring when e / interval is odd, top-N when even); then
+// elite injection puts the population's best in place of its worst.  best =
+// smallest (best f, index), worst = largest (current f, index).  Sources are
+// staged in the job's pool rows (free after the initialisation).  Per-island
+// choices are spread over the waves; copies over every thread of the group.
+constexpr int kMaxIslands = 64, kMaxMigN = 8, kEpochWide = 1024;
 
 __device__ __forceinline__ bool listed(const int *l, int cnt, int v) {
   bool in = false;
@@ -1493,106 +1490,198 @@ __device__ __forceinline__ bool listed(const int *l, int cnt, int v) {
   return in;
 }
 
-// smallest (v[s], s) over [lo, hi) \ ex (MIN) or largest (MIN = false)
+// Pick keys: smaller (value key, index key) is preferred; MIN: smallest
+// (v, s), else largest (v, s).
+// The values are read eight strides at a time (independent loads in flight
+// together: the scan is bound by memory latency, not bandwidth).
 template <bool MIN>
-__device__ int wave_pick(const int64_t *v, int lo, int hi, const int *ex, int nex) {
+__device__ __forceinline__ void pick_scan(const int64_t *v, int lo, int hi, const int *ex, int nex, int first,
+                                          int stride, unsigned long long &bk, uint32_t &bs) {
   constexpr unsigned long long kSign = 1ull << 63;
-  unsigned long long bk = ~0ull;   // key of the value, smaller is better
-  uint32_t bs = 0xFFFFFFFFu;       // key of the index, smaller is better
-  for (int s = lo + (int)lane_id(); s < hi; s += kWave) {
-    if (listed(ex, nex, s)) continue;
-    const unsigned long long k = MIN ? ((unsigned long long)v[s] ^ kSign) : ~((unsigned long long)v[s] ^ kSign);
-    const uint32_t ks = MIN ? (uint32_t)s : ~(uint32_t)s;
-    if (k < bk || (k == bk && ks < bs)) {
-      bk = k;
-      bs = ks;
+  constexpr int kB = 8;
+  bk = ~0ull;
+  bs = 0xFFFFFFFFu;
+  for (int s0 = lo + first; s0 < hi; s0 += kB * stride) {
+    int64_t x[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) x[u] = s0 + u * stride < hi ? v[s0 + u * stride] : 0;
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int s = s0 + u * stride;
+      if (s >= hi || listed(ex, nex, s)) continue;
+      const unsigned long long k = MIN ? ((unsigned long long)x[u] ^ kSign) : ~((unsigned long long)x[u] ^ kSign);
+      const uint32_t ks = MIN ? (uint32_t)s : ~(uint32_t)s;
+      if (k < bk || (k == bk && ks < bs)) {
+        bk = k;
+        bs = ks;
+      }
     }
   }
+}
+
+// dst[e] = src(e) for e in [0, total), over every thread of the workgroup,
+// four elements per thread in flight (loads first, then stores)
+template <class SRC, class DST>
+__device__ __forceinline__ void group_copy(int total, const SRC &src, const DST &dst) {
+  const int st = (int)blockDim.x;
+  for (int e0 = (int)threadIdx.x; e0 < total; e0 += 4 * st) {
+    int32_t x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = e0 + u * st < total ? src(e0 + u * st) : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (e0 + u * st < total) dst(e0 + u * st, x[u]);
+  }
+}
+
+// wave-wide lexicographic minimum of (bk, bs); uniform
+__device__ __forceinline__ void wave_min_pair(unsigned long long &bk, uint32_t &bs) {
   const unsigned long long m = wave_min_key(bk);
-  const uint32_t r = wave_min_u32(bk == m ? bs : 0xFFFFFFFFu);
-  return (int)(MIN ? r : ~r);
+  bs = wave_min_u32(bk == m ? bs : 0xFFFFFFFFu);
+  bk = m;
 }
 
-// solution t takes vector src (n entries, read by each lane at its own
-// elements) with objective f as its current one, and as its best when better
-__device__ void mig_put(DevJob *J, int n, int t, const int32_t *src, int64_t f) {
-  int32_t *c = J->cur + (size_t)t * n, *b = J->best + (size_t)t * n;
-  const bool better = f < J->best_f[t];
-  for (int p = (int)lane_id(); p < n; p += kWave) {
-    const int32_t x = src[p];
-    c[p] = x;
-    if (better) b[p] = x;
-  }
+// smallest (v[s], s) over [lo, hi) \ ex (MIN) or largest (MIN = false), by one wave
+template <bool MIN>
+__device__ int wave_pick(const int64_t *v, int lo, int hi, const int *ex, int nex) {
+  unsigned long long bk;
+  uint32_t bs;
+  pick_scan<MIN>(v, lo, hi, ex, nex, (int)lane_id(), kWave, bk, bs);
+  wave_min_pair(bk, bs);
+  return (int)(MIN ? bs : ~bs);
+}
+
+// the same by the whole workgroup (every thread calls it; result uniform)
+template <bool MIN>
+__device__ int block_pick(const int64_t *v, int lo, int hi, const int *ex, int nex) {
+  __shared__ unsigned long long s_k[kEpochWide / kWave];
+  __shared__ uint32_t s_s[kEpochWide / kWave];
+  const int nw = (int)(blockDim.x / kWave), w = (int)(threadIdx.x / kWave);
+  unsigned long long bk;
+  uint32_t bs;
+  pick_scan<MIN>(v, lo, hi, ex, nex, (int)threadIdx.x, (int)blockDim.x, bk, bs);
+  wave_min_pair(bk, bs);
   if (lane_id() == 0) {
-    J->cur_f[t] = f;
-    if (better) J->best_f[t] = f;
+    s_k[w] = bk;
+    s_s[w] = bs;
   }
+  __syncthreads();
+  bk = ~0ull;
+  bs = 0xFFFFFFFFu;
+  for (int i = 0; i < nw; ++i)
+    if (s_k[i] < bk || (s_k[i] == bk && s_s[i] < bs)) {
+      bk = s_k[i];
+      bs = s_s[i];
+    }
+  __syncthreads();   // s_k, s_s free for the next call
+  return (int)(MIN ? bs : ~bs);
 }
 
-__device__ void migrate_wave(DevJob *J, uint32_t e) {
-  __shared__ int s_src[kMaxIslands], s_tgt[kMaxIslands * kMaxMigN];
-  __shared__ long long s_f[kMaxIslands];
+// Scratch of the migration in the epoch kernel's dynamic LDS (launches that
+// may migrate only): per (target, source) pair its target, source vector,
+// objective and whether it improves the target's best; per source its solution.
+struct MigLds {
+  int tgt[kMaxIslands * kMaxMigN];
+  int better[kMaxIslands * kMaxMigN];
+  long long f[kMaxIslands * kMaxMigN];
+  const int32_t *row[kMaxIslands * kMaxMigN];
+  int src[kMaxIslands];
+};
+
+// Copies for `npairs` (target, source row) pairs in M: target t takes the
+// n-vector row as its current solution and objective f, and as its best when
+// f is below its best objective (decided for every pair before any copy).
+// Targets are distinct and no source row is a target's row.  All threads of
+// the workgroup take part.
+__device__ void mig_copy(DevJob *J, int n, int npairs, MigLds &M) {
+  for (int q = (int)threadIdx.x; q < npairs; q += (int)blockDim.x) M.better[q] = M.f[q] < J->best_f[M.tgt[q]];
+  __syncthreads();
+  group_copy(
+      npairs * n, [&](int e) { return M.row[e / n][e % n]; },
+      [&](int e, int32_t x) {
+        const int q = e / n, p = e - q * n;
+        const size_t o = (size_t)M.tgt[q] * n + p;
+        J->cur[o] = x;
+        if (M.better[q]) J->best[o] = x;
+      });
+  for (int q = (int)threadIdx.x; q < npairs; q += (int)blockDim.x) {
+    J->cur_f[M.tgt[q]] = M.f[q];
+    if (M.better[q]) J->best_f[M.tgt[q]] = M.f[q];
+  }
+  // vectors and objectives visible to the next choice: the workgroup's
+  // waves share one CU, so the barrier's workgroup-scope ordering suffices (a
+  // device-scope fence here would write the whole L2 back each time)
+  __syncthreads();
+}
+
+__device__ void migrate_block(DevJob *J, uint32_t e, MigLds &M) {
   const int P = (int)J->P, n = J->inst->n, I = (int)J->islands, S = P / I;
+  const int nw = (int)(blockDim.x / kWave), w = (int)(threadIdx.x / kWave);
   if (J->mig_epochs && e % J->mig_epochs == 0 && I >= 2) {
     int mode = (int)J->mig_mode;
     if (mode == 2) mode = ((e / J->mig_epochs) & 1) ? 0 : 1;
     const int N = mode == 0 ? 1 : (int)J->mig_n, n_src = mode == 0 ? I : N;
     int chosen[kMaxMigN];
-    if (mode == 0) {
-      for (int i = 0; i < I; ++i) {
+    if (mode == 0) {   // island i's best and island i+1's worst, islands spread over the waves
+      for (int i = w; i < I; i += nw) {
         const int j = i + 1 == I ? 0 : i + 1;
         const int src = wave_pick<true>(J->best_f, i * S, (i + 1) * S, chosen, 0);
         const int tgt = wave_pick<false>(J->cur_f, j * S, (j + 1) * S, chosen, 0);
         if (lane_id() == 0) {
-          s_src[i] = src;
-          s_tgt[i] = tgt;
+          M.src[i] = src;
+          M.tgt[i] = tgt;
         }
       }
-    } else {
+    } else {           // the population's N best, then each island's N worst
       for (int k = 0; k < N; ++k) {
-        chosen[k] = wave_pick<true>(J->best_f, 0, P, chosen, k);
-        if (lane_id() == 0) s_src[k] = chosen[k];
+        chosen[k] = block_pick<true>(J->best_f, 0, P, chosen, k);
+        if (threadIdx.x == 0) M.src[k] = chosen[k];
       }
-      for (int i = 0; i < I; ++i)
+      for (int i = w; i < I; i += nw)
         for (int k = 0; k < N; ++k) {
           chosen[k] = wave_pick<false>(J->cur_f, i * S, (i + 1) * S, chosen, k);
-          if (lane_id() == 0) s_tgt[i * N + k] = chosen[k];
+          if (lane_id() == 0) M.tgt[i * N + k] = chosen[k];
         }
     }
     __syncthreads();
-    for (int k = 0; k < n_src; ++k) {   // sources first, into the pool rows
-      const int src = s_src[k];
-      for (int p = (int)lane_id(); p < n; p += kWave) J->pool[(size_t)k * n + p] = J->best[(size_t)src * n + p];
-      if (lane_id() == 0) s_f[k] = J->best_f[src];
+    // sources staged first (pool row k holds source k), then every pair's
+    // row and objective: ring pair i takes island i's best, top-N pair i N + k
+    // the k-th best
+    group_copy(
+        n_src * n, [&](int x) { return J->best[(size_t)M.src[x / n] * n + x % n]; },
+        [&](int x, int32_t y) { J->pool[x] = y; });
+    const int npairs = I * N;
+    for (int q = (int)threadIdx.x; q < npairs; q += (int)blockDim.x) {
+      const int k = mode == 0 ? q : q % N;
+      M.row[q] = J->pool + (size_t)k * n;
+      M.f[q] = J->best_f[M.src[k]];
     }
     __syncthreads();
-    if (mode == 0)
-      for (int i = 0; i < I; ++i) mig_put(J, n, s_tgt[i], J->pool + (size_t)i * n, s_f[i]);
-    else
-      for (int i = 0; i < I; ++i)
-        for (int k = 0; k < N; ++k) mig_put(J, n, s_tgt[i * N + k], J->pool + (size_t)k * n, s_f[k]);
-    __threadfence();   // objectives written by lane 0, read by every lane below
+    mig_copy(J, n, npairs, M);
   }
   if (J->elite_epochs && e % J->elite_epochs == 0) {
     int none[1];
-    const int b = wave_pick<true>(J->best_f, 0, P, none, 0);
-    const int w = wave_pick<false>(J->cur_f, 0, P, none, 0);
-    if (w != b) mig_put(J, n, w, J->best + (size_t)b * n, J->best_f[b]);
+    const int b = block_pick<true>(J->best_f, 0, P, none, 0);
+    const int wst = block_pick<false>(J->cur_f, 0, P, none, 0);
+    if (wst != b) {
+      if (threadIdx.x == 0) {
+        M.tgt[0] = wst;
+        M.row[0] = J->best + (size_t)b * n;
+        M.f[0] = J->best_f[b];
+      }
+      __syncthreads();
+      mig_copy(J, n, 1, M);
+    }
   }
 }
 
 // After each evolve launch: fold the accumulator rows of every job into its
 // epoch statistics, the instance best and the temperature, and at an epoch
 // boundary apply the AOS update (the kernel boundary orders it after every
-// evolve workgroup).  One wave per job; lane l folds and clears row l.
+// evolve workgroup).  Wave 0 of the job's workgroup; lane l folds and clears
+// row l.  The launch covered generations [g0, g1).
 static_assert(kShards == kWave, "one accumulator row per lane");
-__global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx, uint32_t *next, uint32_t n_next) {
-  if (blockIdx.x == 0 && threadIdx.x < n_next) next[threadIdx.x] = 0;   // work-item counters of the launch
-  DevJob *J = jobs + (idx ? idx[blockIdx.x] : blockIdx.x);
-  const uint32_t g0 = J->g, gstop = J->g_stop;
-  if (g0 >= gstop) return;
-  const uint32_t E = J->E;
-  const uint32_t g1 = min(gstop, (g0 / E + 1) * E);
+__device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, uint32_t g1) {
   // the job state in registers first (one batch of loads, no store between)
   unsigned long long u_op[kOps], v_op[kOps], tu_op[kOps], u_k[3], v_k[3], tu_k[3];
   uint32_t w_op[kOps], w_k[3];
@@ -1630,7 +1719,6 @@ __global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx,
   // signed minimum through the unsigned order of v ^ 2^63
   constexpr unsigned long long kSign = 1ull << 63;
   const long long mn = (long long)(wave_min_key(v[kCountSlots] ^ kSign) ^ kSign);
-  if (g1 % E == 0 && (J->mig_epochs | J->elite_epochs)) migrate_wave(J, g1 / E);
   if (tid != 0) return;
 #pragma unroll
   for (int o = 0; o < kOps; ++o) {
@@ -1681,6 +1769,31 @@ __global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx,
   J->stag = stag;
   J->T = T;
   J->g = g1;
+}
+
+__global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx, uint32_t *next, uint32_t n_next) {
+  if (blockIdx.x == 0 && threadIdx.x < n_next) next[threadIdx.x] = 0;   // work-item counters of the launch
+  DevJob *J = jobs + (idx ? idx[blockIdx.x] : blockIdx.x);
+  const uint32_t g0 = J->g, gstop = J->g_stop;
+  if (g0 >= gstop) return;
+  const uint32_t E = J->E;
+  epoch_fold(J, g0, E, min(gstop, (g0 / E + 1) * E));
+}
+
+// The epoch kernel of launches in which a job may migrate or inject its elite
+// (kEpochWide threads per job, MigLds in dynamic LDS).  The exchange at an
+// epoch end comes before the fold; the two touch disjoint state.
+__global__ __launch_bounds__(kEpochWide) void k_epoch_mig(DevJob *jobs, const uint32_t *idx, uint32_t *next,
+                                                          uint32_t n_next) {
+  if (blockIdx.x == 0 && threadIdx.x < n_next) next[threadIdx.x] = 0;
+  DevJob *J = jobs + (idx ? idx[blockIdx.x] : blockIdx.x);
+  const uint32_t g0 = J->g, gstop = J->g_stop, E = J->E;
+  __syncthreads();   // every wave has read g before wave 0 advances it
+  if (g0 >= gstop) return;
+  const uint32_t g1 = min(gstop, (g0 / E + 1) * E);
+  if (g1 % E == 0 && (J->mig_epochs | J->elite_epochs)) migrate_block(J, g1 / E, *(MigLds *)gx_lds);
+  if (threadIdx.x >= kWave) return;
+  epoch_fold(J, g0, E, g1);
 }
 
 namespace {
@@ -2251,9 +2364,12 @@ hipError_t evolve_group(int kind, int stage, DevJob *jobs, const uint2 *items, u
   return hipLaunchKernel(group_kernel(kind, stage), dim3(grid), dim3(threads_of(kind)), args, lds, s);
 }
 
-hipError_t epoch(DevJob *jobs, const uint32_t *idx, uint32_t count, uint32_t *next, uint32_t n_next,
+hipError_t epoch(DevJob *jobs, const uint32_t *idx, uint32_t count, uint32_t *next, uint32_t n_next, bool mig,
                  hipStream_t s) {
-  hipLaunchKernelGGL(k_epoch, dim3(count), dim3(64), 0, s, jobs, idx, next, n_next);
+  if (mig)
+    hipLaunchKernelGGL(k_epoch_mig, dim3(count), dim3(kEpochWide), sizeof(MigLds), s, jobs, idx, next, n_next);
+  else
+    hipLaunchKernelGGL(k_epoch, dim3(count), dim3(64), 0, s, jobs, idx, next, n_next);
   return hipGetLastError();
 }
 

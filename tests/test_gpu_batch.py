@@ -66,6 +66,33 @@ def test_batch_equals_oracle_per_job(ctx):
         gx.gx_instance_free(ctx, h)
 
 
+def test_batch_with_islands_equals_oracle(ctx):
+    # jobs with island migration or elite injection next to jobs without:
+    # the whole launch takes the migrating epoch kernel
+    G = 40
+    a = synth.alpha_q32_for(G)
+    insts = [synth.tsp_uniform(30, 401, key=1), synth.qap_random(14, 402, key=2),
+             synth.knapsack_random(60, 403, key=3), synth.tsp_uniform(22, 404, key=4)]
+    params = [synth.Params(seed=11, generations=G, population=8, candidates=64, alpha_q32=a, islands=4,
+                           migrate_epochs=1, migrate_mode=0, elite_epochs=2),
+              synth.Params(seed=12, generations=G, population=6, candidates=96, alpha_q32=a, islands=2,
+                           migrate_epochs=2, migrate_mode=1, migrate_n=2),
+              synth.Params(seed=13, generations=G, population=4, candidates=64, alpha_q32=a, elite_epochs=1),
+              synth.Params(seed=14, generations=G - 10, population=3, candidates=64, alpha_q32=a)]
+    handles = [gx.gx_instance_upload(ctx, i) for i in insts]
+    jobs = gx.gx_solve_batch(ctx, handles, params)
+    gx.gx_wait(ctx, jobs[0])
+    for i, (inst, p, job) in enumerate(zip(insts, params, jobs)):
+        g = gx.gx_snapshot(ctx, job, p.population, inst.n)
+        o = oracle.OracleInstance(inst).solve(p)
+        for k in KEYS:
+            assert np.array_equal(np.asarray(g[k]), np.asarray(o[k])), (i, inst.kind, k)
+    for j in jobs:
+        gx.gx_job_free(ctx, j)
+    for h in handles:
+        gx.gx_instance_free(ctx, h)
+
+
 def test_batch_equals_plain_solver(ctx):
     # 700 generations: 70 epoch launches, the first 64 replayed from a captured
     # graph whose (kind, staging) groups run on side streams

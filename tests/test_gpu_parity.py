@@ -172,6 +172,16 @@ def test_island_migration_and_elite_injection(ctx, mode):
     check(ctx, synth.tsp_uniform(25, 6, key=21), p, [20, 20, 20], f"islands mode {mode}")
 
 
+@pytest.mark.parametrize("islands,mode,mig_n", [(32, 0, 1), (20, 1, 2), (24, 2, 1)])
+def test_more_islands_than_epoch_waves(ctx, islands, mode, mig_n):
+    # more islands than the 16 waves of the epoch kernel's workgroup: each
+    # wave chooses for several islands; migrations and elite injection every epoch
+    P_ = islands * (2 if islands == 32 else 3)
+    p = P(seed=37, population=P_, candidates=64, G=30, islands=islands, migrate_epochs=1, migrate_mode=mode,
+          migrate_n=mig_n, elite_epochs=1)
+    check(ctx, synth.tsp_uniform(21, 9, key=25), p, [10, 20], f"{islands} islands mode {mode}")
+
+
 def test_islands_on_two_wave_qap(ctx):
     p = P(seed=19, population=8, candidates=128, G=40, islands=2, migrate_epochs=1, migrate_mode=1,
           migrate_n=2, elite_epochs=1, op_mask=synth.PERM_OPS)

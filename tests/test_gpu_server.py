@@ -96,6 +96,28 @@ def test_served_results_equal_alone(ctx):
         assert res[t][1] == oracle.best_of(o)[0]
 
 
+def test_served_islands_equal_alone(ctx):
+    # requests with island migration and elite injection share lane quanta
+    # with requests without; each result equals the plain solve
+    reqs = requests(9, seed=13)
+    for i in range(0, 9, 2):
+        inst, p = reqs[i]
+        reqs[i] = (inst, p.with_(population=8, islands=4, migrate_epochs=1, migrate_mode=i % 3, migrate_n=1,
+                                 elite_epochs=2))
+    srv = gx.gx_server_create(ctx, hbm_budget_bytes=256 << 20, max_resident=64)
+    tickets, n_of = [], {}
+    for inst, p in reqs:
+        t = gx.gx_server_submit(srv, inst, p)
+        tickets.append((t, inst, p))
+        n_of[t] = inst.n
+    res = wait_all(srv, [t for t, _, _ in tickets], n_of)
+    gx.gx_server_destroy(srv)
+    for t, inst, p in tickets:
+        sol, f, _, _ = res[t]
+        s2, f2 = plain(ctx, inst, p)
+        assert f == f2 and np.array_equal(sol, s2), (inst.kind, inst.n, p.islands)
+
+
 def test_admission_backpressure_and_cancel(ctx):
     reqs = requests(8, seed=9)
     # an arena that holds only a few requests at a time forces queueing
