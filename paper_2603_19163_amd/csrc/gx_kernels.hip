@@ -47,6 +47,31 @@ __device__ __forceinline__ void philox(uint32_t c0, uint32_t c1, uint32_t c2, ui
   r[0] = c0; r[1] = c1; r[2] = c2; r[3] = c3;
 }
 
+// The same block for per-lane counters with a wave-uniform key: each round's
+// two three-way XORs are single v_bitop3_b32 instructions (truth table 0x96),
+// which the compiler does not form by itself; the round keys stay scalar.
+__device__ __forceinline__ uint32_t xor3_vvs(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+__device__ __forceinline__ void philox_lane(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                            uint32_t k0, uint32_t k1, uint32_t r[4]) {
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0, p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+    const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
+    c0 = xor3_vvs(hi1, c1, k0);
+    c1 = lo1;
+    c2 = xor3_vvs(hi0, c3, k1);
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  r[0] = c0; r[1] = c1; r[2] = c2; r[3] = c3;
+}
+
 // integer in [0, m) from a 32-bit draw: floor(w * m / 2^32)
 __device__ __forceinline__ uint32_t rmap(uint32_t w, uint32_t m) { return __umulhi(w, m); }
 
@@ -635,7 +660,7 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
     kk[rr] = 0;
     if (tl < cn) {
       uint32_t w[4];
-      philox(g, sol, (c0 + tl) << 2, U.key, U.k0, U.k1, w);
+      philox_lane(g, sol, (c0 + tl) << 2, U.key, U.k0, U.k1, w);
       const uint32_t u = (uint32_t)(((uint64_t)(w[0] >> 16) * U.swk) >> 16);
       kk[rr] = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
       const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
@@ -658,7 +683,7 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
   for (uint32_t j = lane; j < nx; j += kWave) {
     const uint32_t e = dl[j], tl = e & 0xFFu, m = e >> 8;
     uint32_t w[4];
-    philox(g, sol, ((c0 + tl) << 2) | m, U.key, U.k0, U.k1, w);
+    philox_lane(g, sol, ((c0 + tl) << 2) | m, U.key, U.k0, U.k1, w);
     const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
     W.sab()[3 * tl + m] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
     W.sop()[3 * tl + m] = (uint8_t)(st.op | (st.c << 3));
