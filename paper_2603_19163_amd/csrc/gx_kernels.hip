@@ -334,9 +334,14 @@ __device__ __forceinline__ void stage16(void *dst, const void *src, uint32_t byt
 // is one packed subtract and one 2-term dot product for int16 coordinates) and
 // k < 2^15, so the test fits the full-rate 24-bit multiplier.
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+// (the dot product in its three-operand form with an inline zero: the
+// intrinsic becomes the two-operand form, which needs the zero copied into
+// its destination first)
 __device__ __forceinline__ uint32_t sq_norm(short2 p, short2 q) {   // packed difference, 2-term dot
   const s16x2 d = __builtin_bit_cast(s16x2, p) - __builtin_bit_cast(s16x2, q);
-  return (uint32_t)__builtin_amdgcn_sdot2(d, d, 0, false);
+  uint32_t r;
+  asm("v_dot2_i32_i16 %0, %1, %1, 0" : "=v"(r) : "v"(__builtin_bit_cast(uint32_t, d)));
+  return r;
 }
 __device__ __forceinline__ uint32_t sq_norm(int2 p, int2 q) {
   const int dx = p.x - q.x, dy = p.y - q.y;
