@@ -275,14 +275,8 @@ def bench_batched(args):
     ctx = gx.gx_create(0, torch.cuda.Stream())
     cus = gx.gx_get_device_info(ctx)["cus"]
     count, G = args.instances, args.batch_generations
-    r = np.random.default_rng([4, count, 20260319])
     n_tsp = count * 3 // 4
-    insts = []
-    for i in range(count):
-        if i < n_tsp:
-            insts.append(synth.tsp_uniform(int(r.integers(20, 201)), 10_000 + i, key=i))
-        else:
-            insts.append(synth.qap_random(int(r.integers(12, 41)), 20_000 + i, key=i))
+    insts = synth.c4_batched_instances(count)
     P = autotune.fill_population(ctx, count)
     samples = {}
     for inst in insts:
@@ -407,23 +401,10 @@ def bench_served(args):
 
     ctx = gx.gx_create(0, torch.cuda.Stream())
     G, P = args.served_generations, args.served_population
-    alpha = synth.alpha_q32_for(G)
-    r = np.random.default_rng([5, 789, 20260319])
-    n_req = int(args.rate * args.duration)
-    gaps = r.exponential(1.0 / args.rate, size=n_req)
-    reqs = []
     names = {"tsp": 0, "qap": 1, "knapsack": 2}
     kinds = [names[k] for k in args.served_kinds.split(",")]
-    for i in range(n_req):
-        kind = kinds[int(r.integers(0, len(kinds)))]
-        if kind == 0:
-            inst = synth.tsp_uniform(int(r.integers(20, 501)), 30_000 + i, key=i)
-        elif kind == 1:
-            inst = synth.qap_random(int(r.integers(12, 51)), 40_000 + i, key=i)
-        else:
-            inst = synth.knapsack_random(int(r.integers(100, 1001)), 50_000 + i, key=i)
-        reqs.append((inst, synth.Params(seed=int(r.integers(0, 2**40)), generations=G, population=P,
-                                        candidates=128, alpha_q32=alpha)))
+    reqs, gaps = synth.c5_requests(args.rate, args.duration, kinds, G, P)
+    n_req = len(reqs)
     srv = gx.gx_server_create(ctx, hbm_budget_bytes=8 << 30, max_resident=8192)
     tickets = []
     t0 = time.perf_counter()

@@ -235,6 +235,44 @@ def c2_tsp442(population: int, generations: int = 200_000, seed: int = 42) -> tu
     return inst, p
 
 
+def c4_batched_instances(count: int = 4096) -> list[Instance]:
+    """Batched workload: the first three quarters TSP n U[20,200] (uniform
+    coordinates), the rest QAP n U[12,40]; instance key = index."""
+    r = np.random.default_rng([4, count, 20260319])
+    n_tsp = count * 3 // 4
+    out = []
+    for i in range(count):
+        if i < n_tsp:
+            out.append(tsp_uniform(int(r.integers(20, 201)), 10_000 + i, key=i))
+        else:
+            out.append(qap_random(int(r.integers(12, 41)), 20_000 + i, key=i))
+    return out
+
+
+def c5_requests(rate: float, duration: float, kinds=(0, 1, 2), generations: int = 10_000,
+                population: int = 4):
+    """Served workload: int(rate * duration) requests with exponential gaps
+    (Poisson arrivals at `rate`), each of a kind drawn from `kinds` (0 TSP n
+    U[20,500], 1 QAP n U[12,50], 2 knapsack n U[100,1000]) with its own seed.
+    Returns (requests [(instance, params)], gaps in seconds)."""
+    r = np.random.default_rng([5, 789, 20260319])
+    n_req = int(rate * duration)
+    gaps = r.exponential(1.0 / rate, size=n_req)
+    alpha = alpha_q32_for(generations)
+    reqs = []
+    for i in range(n_req):
+        kind = kinds[int(r.integers(0, len(kinds)))]
+        if kind == 0:
+            inst = tsp_uniform(int(r.integers(20, 501)), 30_000 + i, key=i)
+        elif kind == 1:
+            inst = qap_random(int(r.integers(12, 51)), 40_000 + i, key=i)
+        else:
+            inst = knapsack_random(int(r.integers(100, 1001)), 50_000 + i, key=i)
+        reqs.append((inst, Params(seed=int(r.integers(0, 2**40)), generations=generations, population=population,
+                                  candidates=128, alpha_q32=alpha)))
+    return reqs, gaps
+
+
 def c3_vrptw(seed: int = 42, generations: int = 5000, population: int = 64) -> tuple[Instance, Params]:
     inst = vrptw_random(100, 0)
     p = Params(seed=seed, generations=generations, population=population, candidates=128,
