@@ -74,14 +74,18 @@ struct DevJob {
   int32_t best_idx, pad4;
 };
 
+// Permutations of up to kOneBufferN elements are rewritten through the first
+// 2 kOneBufferN bytes of the candidate tables when a move is applied (the
+// tables are dead then; the bytes above hold the TSP run's counters); longer
+// ones through a second tour buffer.
+constexpr int kOneBufferN = 1536;
+
 // LDS bytes one evolve workgroup needs for this instance and staging: the
 // candidate tables (3968 bytes) followed by the solution and instance data.
-// Permutations of up to 1984 elements use one tour buffer (moves are applied
-// through the tables); longer ones a second buffer.
 inline uint32_t lds_bytes_for(int kind, int n, int stage) {
   auto al = [](uint32_t b) { return (b + 15u) & ~15u; };
   const uint32_t un = (uint32_t)n, tables = 3968;
-  const uint32_t tours = (n <= 1984 ? 1 : 2) * al(2 * un);
+  const uint32_t tours = (n <= kOneBufferN ? 1 : 2) * al(2 * un);
   switch (kind) {
     case KTSP: {
       uint32_t b = tables + tours;

@@ -281,15 +281,6 @@ __device__ __forceinline__ unsigned long long wave_min_key(unsigned long long k)
   return ((unsigned long long)hi << 32) | lo;
 }
 
-__device__ __forceinline__ unsigned long long wave_min(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long w = __shfl_xor(v, o, 64);
-    v = w < v ? w : v;
-  }
-  return v;
-}
-
 // ------------------------------------------------------------ acceptance, cooling
 // Alg. 1: accept when delta < 0 or rand() < e^{-delta/T}; delta = 0 is
 // accepted.  e^{-delta/T} comes from the integer tables at z = floor(256
@@ -585,7 +576,12 @@ struct ColorK {
 constexpr int kChunk = 128;
 constexpr uint32_t kTspScratch = kChunk * 3 * 4 + kChunk * 4 + kChunk * 6 * 2 + kChunk * 3;
 static_assert(kTspScratch == 3968, "lds_bytes_for() reserves 3968 bytes of candidate tables");
-constexpr int kOneBufferN = kTspScratch / 2;
+// The pattern list holds at most 2 x 2 entries per candidate of a chunk
+// (steps 2 and 3, two patterns each): 1024 bytes from offset 2048; the rest of
+// its 1536 bytes, up to the operator table at 3584, is free on the TSP path
+// (a move's rewrite through the tables stays below it).
+constexpr uint32_t kTspStatsOff = 2048 + kChunk * 2 * 2 * 2;
+static_assert(2 * kOneBufferN <= (int)kTspStatsOff, "tour rewrite below the TSP counters");
 
 // Dynamic LDS of the evolve kernels; the candidate tables sit at fixed offsets
 // from its start (so their addresses are compile-time constants).
@@ -850,6 +846,14 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
   // candidates adds at most 6 to a field of a lane, so the fields are folded
   // into the wave-wide counts of S every 42 chunks and at the end.
   uint32_t cu_op = 0, cv_op = 0, cu_k = 0, cv_k = 0, since_fold = 0;
+  // The wave-wide counts live in the unused tail of the pattern-list table
+  // during the run (fewer scalar registers held across the generation loop)
+  // and are added into S at the end.
+  LStats &SL = *(LStats *)(gx_lds + kTspStatsOff);
+  static_assert(sizeof(LStats) % 4 == 0 && sizeof(LStats) / 4 <= kWave, "one word per lane");
+  static_assert(kTspStatsOff + sizeof(LStats) <= 3584, "inside the free tail of the pattern list");
+  if (lane < sizeof(LStats) / 4) ((uint32_t *)&SL)[lane] = 0u;
+  wave_sync();
   const uint32_t c_last = (U.C - 1) / kChunk * kChunk;
   if constexpr (DF::kEdges) {
     edges_fill(el, cur, n, D, 0, n - 1);
@@ -923,8 +927,8 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
         }
       }
       if (++since_fold == 42) {
-        fold_byte_counts(S.u, S.v, cu_op, cv_op, 4);
-        fold_byte_counts(S.uk, S.vk, cu_k, cv_k, 3);
+        fold_byte_counts(SL.u, SL.v, cu_op, cv_op, 4);
+        fold_byte_counts(SL.uk, SL.vk, cu_k, cv_k, 3);
         cu_op = cv_op = cu_k = cv_k = 0;
         since_fold = 0;
       }
@@ -955,13 +959,13 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
 #pragma unroll
           for (int o = 0; o < 4; ++o) {
             const uint32_t hit = m < k && st[m].op == o;
-            S.u[o] += hit;
-            S.v[o] += hit & (uint32_t)(ds < 0);
+            SL.u[o] += hit;
+            SL.v[o] += hit & (uint32_t)(ds < 0);
           }
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          S.uk[q] += (uint32_t)(k == q + 1);
-          S.vk[q] += (uint32_t)(k == q + 1 && ds < 0);
+          SL.uk[q] += (uint32_t)(k == q + 1);
+          SL.vk[q] += (uint32_t)(k == q + 1 && ds < 0);
         }
       }
       int lo, hi;
@@ -982,8 +986,19 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
     }
     T = cool(T, U.alpha);
   }
-  fold_byte_counts(S.u, S.v, cu_op, cv_op, 4);
-  fold_byte_counts(S.uk, S.vk, cu_k, cv_k, 3);
+  fold_byte_counts(SL.u, SL.v, cu_op, cv_op, 4);
+  fold_byte_counts(SL.uk, SL.vk, cu_k, cv_k, 3);
+  wave_sync();
+#pragma unroll
+  for (int o = 0; o < 4; ++o) {
+    S.u[o] += SL.u[o];
+    S.v[o] += SL.v[o];
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    S.uk[q] += SL.uk[q];
+    S.vk[q] += SL.vk[q];
+  }
 }
 
 // ------------------------------------------------------------ generation loop
@@ -1874,7 +1889,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
 
   if constexpr (KIND == KTSP || KIND == KQAP || KIND == KVRP) {
     // one tour buffer; the move application writes through the candidate
-    // tables (room for 1984 entries) or, for longer tours, a second buffer
+    // tables (kOneBufferN entries) or, for longer tours, a second buffer
     uint16_t *t0 = (uint16_t *)base;
     uint16_t *t1 = n <= kOneBufferN ? (uint16_t *)lds : (uint16_t *)(base + al16(2 * n));
     char *rest = base + (n <= kOneBufferN ? 1 : 2) * al16(2 * n);

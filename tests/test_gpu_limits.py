@@ -46,6 +46,13 @@ def P(G, **kw):
     return synth.Params(generations=G, alpha_q32=synth.alpha_q32_for(G), **kw)
 
 
+@pytest.mark.parametrize("n", [1536, 1537])
+def test_tsp_tour_buffer_boundary(ctx, n):
+    # 1536: the longest tour rewritten through the candidate tables (up to the
+    # byte below the run's counters); 1537: the shortest with a second buffer
+    windowed(ctx, synth.tsp_uniform(n, 5, key=11), P(400, seed=9, population=8, staging=2), 30, 20, f"tsp{n}")
+
+
 def test_tsp_2000_coordinates_in_lds(ctx):
     windowed(ctx, synth.tsp_uniform(2000, 3, key=1), P(1000, seed=3, population=16, staging=2), 40, 12, "tsp2000")
 
