@@ -114,9 +114,14 @@ gx_status gx_get_device_info(gx_ctx *ctx, gx_device_info *out);
  *            row 0; b = demand, ready, due, each (n+1) (3 x (n+1) array);
  *            capacity, vehicles, service_time, horizon.  Customers are
  *            visited in tour order and a new route opens whenever the load
- *            would exceed capacity; f = distance + 100 * total lateness
- *            + 10000 * max(0, routes - vehicles).  n <= 250; coordinates in
- *            [0, 2^14), demand in [0, capacity], times in [0, 2^19].
+ *            would exceed capacity; f = wD * distance + wR * routes
+ *            + wM * (length of the longest route) + 100 * total lateness
+ *            + 10000 * max(0, routes - vehicles), with (wD, wR, wM) =
+ *            obj_weights (paper, Sec. "Multi-Objective Optimization Modes":
+ *            the weighted mode over distance, vehicle count and the longest
+ *            route; each weight in [0, 2^20]; all zero means (1, 0, 0), the
+ *            single objective).  n <= 250; coordinates in [0, 2^14), demand
+ *            in [0, capacity], times in [0, 2^19].
  *   INTCOLOR a = edge list n_edges x 2 (no self loops); values in [lb, ub];
  *            f = number of edges whose ends share a value.
  * instance_key enters every random counter of solves on this instance: keep
@@ -126,6 +131,7 @@ typedef struct {
   const int32_t *a, *b;
   int32_t a_is_coords, capacity, vehicles, service_time, horizon, lb, ub, n_edges;
   uint32_t instance_key;
+  int32_t obj_weights[3];   /* VRPTW objective weights (above); zero for the other kinds */
 } gx_instance_desc;
 gx_status gx_instance_upload(gx_ctx *ctx, const gx_instance_desc *desc, gx_instance **out);
 gx_status gx_instance_free(gx_ctx *ctx, gx_instance *inst);

@@ -40,7 +40,8 @@ class _Desc(C.Structure):
                 ("a", C.POINTER(C.c_int32)), ("b", C.POINTER(C.c_int32)),
                 ("a_is_coords", C.c_int32), ("capacity", C.c_int32), ("vehicles", C.c_int32),
                 ("service_time", C.c_int32), ("horizon", C.c_int32), ("lb", C.c_int32),
-                ("ub", C.c_int32), ("n_edges", C.c_int32), ("key", C.c_uint32)]
+                ("ub", C.c_int32), ("n_edges", C.c_int32), ("key", C.c_uint32),
+                ("obj_w", C.c_int32 * 3)]
 
 
 class _Params(C.Structure):
@@ -156,7 +157,8 @@ class OracleInstance:
                   b=_i32p(self._b) if self._b is not None else C.POINTER(C.c_int32)(),
                   a_is_coords=inst.a_is_coords, capacity=inst.capacity, vehicles=inst.vehicles,
                   service_time=inst.service_time, horizon=inst.horizon, lb=inst.lb, ub=inst.ub,
-                  n_edges=inst.n_edges, key=inst.key & 0xFFFFFFFF)
+                  n_edges=inst.n_edges, key=inst.key & 0xFFFFFFFF,
+                  obj_w=(C.c_int32 * 3)(*getattr(inst, "obj_weights", (0, 0, 0))))
         self._desc = d
         self.h = lib().or_inst_new(C.byref(d))
         if not self.h:

@@ -117,6 +117,7 @@ or_inst *or_inst_new(const or_inst_desc *d) {
                            : d->a[(int64_t)i * n + j];
   } else if (d->kind == K_VRPTW) {
     if (!d->b) { free(in); return NULL; }
+    if (d->obj_w[0] == 0 && d->obj_w[1] == 0 && d->obj_w[2] == 0) in->d.obj_w[0] = 1;
     int m = n + 1;
     in->dn = m;
     in->dist = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * m);
@@ -178,24 +179,28 @@ static int64_t obj_knap(const or_inst *in, const int32_t *x) {
 
 /* reading: giant tour over customers 1..n, split greedily into routes by
  * capacity; wait until ready, lateness penalised 100 per unit, each vehicle
- * beyond the fleet 10000. */
+ * beyond the fleet 10000.  Sec. "Multi-Objective Optimization Modes", weighted
+ * mode: the three objectives (total distance, number of routes, length of the
+ * longest route) enter with the instance's integer weights; the default
+ * (1, 0, 0) is the single distance objective. */
 static int64_t obj_vrptw(const or_inst *in, const int32_t *x) {
   int n = in->d.n;
   const int32_t *dem = in->d.b, *ready = in->d.b + (n + 1), *due = in->d.b + 2 * (n + 1);
-  int64_t dist = 0, late = 0, t = 0, load = 0;
+  int64_t dist = 0, late = 0, t = 0, load = 0, route_len = 0, longest = 0;
   int routes = 0, prev = 0;
   for (int p = 0; p < n; ++p) {
     int c = x[p] + 1;
     if (routes == 0 || load + dem[c] > in->d.capacity) {
       if (routes > 0) {
         int64_t back = or_dist(in, prev, 0);
-        dist += back; t += back;
+        dist += back; t += back; route_len += back;
         if (t > in->d.horizon) late += t - in->d.horizon;
+        if (route_len > longest) longest = route_len;
       }
-      routes++; load = 0; t = 0; prev = 0;
+      routes++; load = 0; t = 0; prev = 0; route_len = 0;
     }
     int64_t dd = or_dist(in, prev, c);
-    dist += dd; t += dd;
+    dist += dd; t += dd; route_len += dd;
     if (t < ready[c]) t = ready[c];
     if (t > due[c]) late += t - due[c];
     t += in->d.service_time;
@@ -204,11 +209,13 @@ static int64_t obj_vrptw(const or_inst *in, const int32_t *x) {
   }
   if (routes > 0) {
     int64_t back = or_dist(in, prev, 0);
-    dist += back; t += back;
+    dist += back; t += back; route_len += back;
     if (t > in->d.horizon) late += t - in->d.horizon;
+    if (route_len > longest) longest = route_len;
   }
   int64_t extra = routes - in->d.vehicles;
-  return dist + 100 * late + 10000 * (extra > 0 ? extra : 0);
+  return (int64_t)in->d.obj_w[0] * dist + (int64_t)in->d.obj_w[1] * routes + (int64_t)in->d.obj_w[2] * longest +
+         100 * late + 10000 * (extra > 0 ? extra : 0);
 }
 
 static int64_t obj_color(const or_inst *in, const int32_t *x) {

@@ -19,6 +19,7 @@ typedef struct {
   const int32_t *a, *b;
   int32_t a_is_coords, capacity, vehicles, service_time, horizon, lb, ub, n_edges;
   uint32_t key;
+  int32_t obj_w[3];   /* VRPTW: weights of distance, routes, longest route; all 0 = (1, 0, 0) */
 } or_inst_desc;
 
 typedef struct {

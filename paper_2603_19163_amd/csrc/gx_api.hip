@@ -186,6 +186,8 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
   h.horizon = d->horizon;
   h.n_edges = d->n_edges;
   pr.key = d->instance_key;
+  if (d->kind != KVRP && (d->obj_weights[0] | d->obj_weights[1] | d->obj_weights[2]))
+    return fail(c, GX_E_INVALID, "objective weights apply to VRPTW only");
   std::vector<int32_t> A, B;
   gx_status st = GX_OK;
   double fbound = 0;
@@ -262,6 +264,13 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
       if (q < 0 || q > d->capacity || r < 0 || u < 0 || r > (1 << 19) || u > (1 << 19))
         return fail(c, GX_E_INVALID, "VRPTW demand in [0, capacity], times in [0, 2^19]");
     }
+    const int32_t *w = d->obj_weights;
+    for (int i = 0; i < 3; ++i)
+      if (w[i] < 0 || w[i] > (1 << 20)) return fail(c, GX_E_INVALID, "VRPTW objective weights must lie in [0, 2^20]");
+    const bool dflt = w[0] == 0 && w[1] == 0 && w[2] == 0;
+    h.vw_d = dflt ? 1 : w[0];
+    h.vw_r = dflt ? 0 : w[1];
+    h.vw_m = dflt ? 0 : w[2];
     h.dn = m;
     add_arr(pr, F_XY, A);
     h.has_xy = 1;
@@ -270,7 +279,8 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
     add_arr(pr, F_DEM, std::vector<int32_t>(B.begin(), B.begin() + m));
     add_arr(pr, F_RDY, std::vector<int32_t>(B.begin() + m, B.begin() + 2 * m));
     add_arr(pr, F_DUE, std::vector<int32_t>(B.begin() + 2 * m, B.end()));
-    fbound = 4.0 * (m * 23171.0 + 100.0 * m * (m * 23171.0 + (1 << 19) + (double)m * (1 << 16)) + 10000.0 * m);
+    fbound = 4.0 * ((h.vw_d + h.vw_m) * m * 23171.0 + (double)h.vw_r * m +
+                    100.0 * m * (m * 23171.0 + (1 << 19) + (double)m * (1 << 16)) + 10000.0 * m);
   } else if (d->kind == KCOLOR) {
     if (n > 32767) return fail(c, GX_E_UNSUPPORTED, "colouring n <= 32767");
     if (d->lb > d->ub || d->lb < -32768 || d->ub > 32767)

@@ -32,6 +32,7 @@ struct DevInst {
   int32_t lb, ub, has_xy;
   int32_t qap_sums32;         // QAP: 2 n * max F * max D < 2^31 (delta row and pair sums fit int32)
   int32_t qap_h16, pad_q;     // QAP: n * max F * max D < 2^16 (row sums H fit 16 bits: staging 1)
+  int32_t vw_d, vw_r, vw_m, pad_v;   // VRPTW objective weights: distance, routes, longest route
   int64_t lambda;             // knapsack penalty weight
   const int32_t *xy;          // TSP n x 2 / VRPTW (n+1) x 2 coordinates
   const int16_t *d16;         // TSP n x n / VRPTW dn x dn distances (int16)

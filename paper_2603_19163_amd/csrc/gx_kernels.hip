@@ -416,15 +416,25 @@ __device__ __forceinline__ void perm_store(const uint16_t *cur, int n, int32_t *
 // delta = sum_{a in X} sum_b m_b F[a][b] (D[y_a][y_b] - D[x_a][x_b]), X the
 // changed positions, y the candidate, m_b = 1 inside X and 2 outside (F, D symmetric)
 // ------------------------------------------------------------ VRPTW (giant tour)
+// Objective of a split giant tour: weighted distance, route count and
+// longest route (the weighted multi-objective mode; default weights (1, 0, 0))
+// plus the lateness and fleet penalties.
+__device__ __forceinline__ int64_t vrp_objective(const DevInst *I, int64_t dist, int routes, int64_t longest,
+                                                 int64_t late) {
+  return (int64_t)I->vw_d * dist + (int64_t)I->vw_r * routes + (int64_t)I->vw_m * longest + 100 * late +
+         10000 * (int64_t)max(0, routes - I->vehicles);
+}
+
 struct VrpK {
   static constexpr int ENC = 0;
   uint16_t *cur, *nxt;
   int n, dn, cap, veh, svc, hor;
   const int16_t *D;
   const int32_t *dem, *rdy, *due;
+  const DevInst *I;
   __device__ __forceinline__ int64_t eval(const Step *st, int k) const {
     int64_t dist = 0, late = 0;
-    int t = 0, load = 0, routes = 0, prev = 0;
+    int t = 0, load = 0, routes = 0, prev = 0, len = 0, longest = 0;   // route lengths < 251 * 23171
     for (int p = 0; p < n; ++p) {
       const int c = cur[chain(st, k, p)] + 1;
       const int q = dem[c];
@@ -434,14 +444,17 @@ struct VrpK {
           dist += back;
           t += back;
           late += max(0, t - hor);
+          longest = max(longest, len + back);
         }
         ++routes;
         load = 0;
         t = 0;
         prev = 0;
+        len = 0;
       }
       const int dd = D[prev * dn + c];
       dist += dd;
+      len += dd;
       t = max(t + dd, rdy[c]);
       late += max(0, t - due[c]);
       t += svc;
@@ -453,8 +466,9 @@ struct VrpK {
       dist += back;
       t += back;
       late += max(0, t - hor);
+      longest = max(longest, len + back);
     }
-    return dist + 100 * late + 10000 * (int64_t)max(0, routes - veh);
+    return vrp_objective(I, dist, routes, longest, late);
   }
   __device__ __forceinline__ int64_t delta(const Step *st, int k, int64_t f) const {
     return eval(st, k) - f;
@@ -1951,7 +1965,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       stage16(rdy, I->rdy, 4u * dn);
       stage16(due, I->due, 4u * dn);
       __syncthreads();
-      VrpK kd{t0, t1, n, dn, I->capacity, I->vehicles, I->service, I->horizon, D, dem, rdy, due};
+      VrpK kd{t0, t1, n, dn, I->capacity, I->vehicles, I->service, I->horizon, D, dem, rdy, due, I};
       run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       perm_store(kd.cur, n, cur_g);
     }
@@ -2065,7 +2079,7 @@ __device__ int64_t full_objective(const DevInst *I, const int32_t *x) {
   if (I->kind == KVRP) {
     const int dn = I->dn;
     int64_t dist = 0, late = 0;
-    int t = 0, load = 0, routes = 0, prev = 0;
+    int t = 0, load = 0, routes = 0, prev = 0, len = 0, longest = 0;
     for (int p = 0; p < n; ++p) {
       const int c = x[p] + 1;
       if (routes == 0 || load + I->dem[c] > I->capacity) {
@@ -2074,14 +2088,17 @@ __device__ int64_t full_objective(const DevInst *I, const int32_t *x) {
           dist += back;
           t += back;
           late += max(0, t - I->horizon);
+          longest = max(longest, len + back);
         }
         ++routes;
         load = 0;
         t = 0;
         prev = 0;
+        len = 0;
       }
       const int dd = I->d16[prev * dn + c];
       dist += dd;
+      len += dd;
       t = max(t + dd, I->rdy[c]);
       late += max(0, t - I->due[c]);
       t += I->service;
@@ -2093,8 +2110,9 @@ __device__ int64_t full_objective(const DevInst *I, const int32_t *x) {
       dist += back;
       t += back;
       late += max(0, t - I->horizon);
+      longest = max(longest, len + back);
     }
-    return dist + 100 * late + 10000 * (int64_t)max(0, routes - I->vehicles);
+    return vrp_objective(I, dist, routes, longest, late);
   }
   int64_t f = 0;
   for (int e = 0; e < I->n_edges; ++e) f += x[I->edges[2 * e]] == x[I->edges[2 * e + 1]];

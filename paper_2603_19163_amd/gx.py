@@ -38,7 +38,8 @@ class gx_instance_desc(C.Structure):
                 ("a", C.c_void_p), ("b", C.c_void_p),
                 ("a_is_coords", C.c_int32), ("capacity", C.c_int32), ("vehicles", C.c_int32),
                 ("service_time", C.c_int32), ("horizon", C.c_int32), ("lb", C.c_int32),
-                ("ub", C.c_int32), ("n_edges", C.c_int32), ("instance_key", C.c_uint32)]
+                ("ub", C.c_int32), ("n_edges", C.c_int32), ("instance_key", C.c_uint32),
+                ("obj_weights", C.c_int32 * 3)]
 
 
 class gx_solve_params(C.Structure):
@@ -195,7 +196,8 @@ def _desc(inst, keep):
                             service_time=getattr(inst, "service_time", 0),
                             horizon=getattr(inst, "horizon", 0), lb=getattr(inst, "lb", 0),
                             ub=getattr(inst, "ub", 0), n_edges=getattr(inst, "n_edges", 0),
-                            instance_key=getattr(inst, "key", 0) & 0xFFFFFFFF)
+                            instance_key=getattr(inst, "key", 0) & 0xFFFFFFFF,
+                            obj_weights=(C.c_int32 * 3)(*getattr(inst, "obj_weights", (0, 0, 0))))
 
 
 def gx_instance_upload(ctx, inst):

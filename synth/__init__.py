@@ -58,6 +58,7 @@ class Instance:
     ub: int = 0
     n_edges: int = 0
     key: int = 0
+    obj_weights: tuple = (0, 0, 0)   # VRPTW: weights of distance, routes, longest route
 
     def __post_init__(self):
         self.a = np.ascontiguousarray(self.a, dtype=np.int32)

@@ -247,6 +247,16 @@ def test_c2_full_size_windowed(ctx):
     assert_same(b, a, "C2 window 1000..1020")
 
 
+@pytest.mark.parametrize("w", [(6, 2, 2), (0, 1000, 1)])
+def test_vrptw_weighted_objectives(ctx, w):
+    # distance, route count and longest route weighted; (0, 1000, 1): routes
+    # first, then the longest route
+    base = synth.vrptw_random(30, 4, key=41)
+    inst = synth.Instance(synth.VRPTW, base.n, base.a, base.b, capacity=base.capacity, vehicles=base.vehicles,
+                          service_time=base.service_time, horizon=base.horizon, key=41, obj_weights=w)
+    check(ctx, inst, P(seed=43, population=6, candidates=128, G=30), [10, 20], f"vrptw weights {w}")
+
+
 def test_invalid_arguments_are_rejected(ctx):
     inst = synth.tsp_uniform(10, 0)
     h = gx.gx_instance_upload(ctx, inst)
@@ -270,4 +280,13 @@ def test_invalid_arguments_are_rejected(ctx):
     with pytest.raises(gx.GxError) as e:
         gx.gx_instance_upload(ctx, synth.qap_random(70, 0))
     assert e.value.status == gx.GX_E_UNSUPPORTED
+    v = synth.vrptw_random(10, 0)
+    for kind_inst in (synth.Instance(synth.TSP, 10, synth.tsp_uniform(10, 0).a, a_is_coords=1, obj_weights=(1, 1, 0)),
+                      synth.Instance(synth.VRPTW, 10, v.a, v.b, capacity=v.capacity, vehicles=v.vehicles,
+                                     service_time=v.service_time, horizon=v.horizon, obj_weights=(1, -1, 0)),
+                      synth.Instance(synth.VRPTW, 10, v.a, v.b, capacity=v.capacity, vehicles=v.vehicles,
+                                     service_time=v.service_time, horizon=v.horizon, obj_weights=(1 << 21, 0, 0))):
+        with pytest.raises(gx.GxError) as e:
+            gx.gx_instance_upload(ctx, kind_inst)
+        assert e.value.status == gx.GX_E_INVALID
     gx.gx_instance_free(ctx, h)

@@ -289,6 +289,35 @@ def test_vrptw_worked_examples():
         assert o.objective(np.array(c["tour"])) == c["f"], c
 
 
+def test_vrptw_weighted_objectives_worked_examples():
+    g = gold("vrptw_small.json")
+    for c in g["weighted_cases"]:
+        b = np.array([g["demand"], g["ready"], [c["horizon"]] + g["due"][1:]], np.int32)
+        inst = synth.Instance(synth.VRPTW, 3, np.array(g["coords"]), b, capacity=g["capacity"],
+                              vehicles=g["vehicles"], service_time=g["service_time"],
+                              horizon=c["horizon"], obj_weights=tuple(c["weights"]))
+        assert oracle.OracleInstance(inst).objective(np.array(c["tour"])) == c["f"], c
+
+
+def test_vrptw_weighted_loose_reduces_to_tsp_through_depot():
+    # one route that never waits or runs late: distance = longest route = the
+    # closed tour through the depot, one route, so f = (wD + wM) tour + wR
+    inst = synth.vrptw_random(8, 3)
+    b = inst.b.copy()
+    b[1, :] = 0
+    b[2, :] = 10**6
+    t = oracle.OracleInstance(synth.Instance(synth.TSP, 9, inst.a, a_is_coords=1))
+    r = np.random.default_rng(5)
+    for w in [(6, 2, 2), (0, 1000, 1), (1, 0, 0), (3, 0, 7)]:
+        loose = synth.Instance(synth.VRPTW, 8, inst.a, b, capacity=10**6, vehicles=1, service_time=10,
+                               horizon=10**6, obj_weights=w)
+        o = oracle.OracleInstance(loose)
+        for _ in range(10):
+            x = r.permutation(8)
+            tour = t.objective(np.concatenate([[0], x + 1]))
+            assert o.objective(x) == (w[0] + w[2]) * tour + w[1], w
+
+
 def test_vrptw_loose_reduces_to_tsp_through_depot():
     # unlimited capacity, one vehicle, windows never binding: f = closed tour depot -> tour -> depot
     inst = synth.vrptw_random(8, 1)
