@@ -12,6 +12,7 @@ HBM before the timed region.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -373,6 +374,8 @@ def bench_kinds(args):
          tsp442(**isl, migrate_mode=2, migrate_n=4)),
         ("tsp50", "TSP n=50 uniform, P=64, 2-opt/swap/or-opt, 2000 generations", synth.c1_small_tsp(0)),
         ("vrptw100", "VRPTW 100 customers, giant tour + split, P=64, 5000 generations", synth.c3_vrptw()),
+        ("vrptw100_weighted", "same, weighted objectives 6 distance + 2 routes + 2 longest route",
+         (dataclasses.replace(synth.c3_vrptw()[0], obj_weights=(6, 2, 2)), synth.c3_vrptw()[1])),
         ("qap50", "QAP n=50, P=1024, 2000 generations", one(synth.qap_random(50, 7), 1024, 2000)),
     ]
     kp_inst, kp = one(synth.knapsack_random(1000, 7), 2048, 5000)
