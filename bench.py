@@ -125,6 +125,8 @@ def main():
                     help="tsp442: offered rate of the second served measurement (below capacity)")
     ap.add_argument("--mixed-duration", type=float, default=3.0,
                     help="tsp442: seconds of served arrivals measured for the line")
+    ap.add_argument("--kinds-rows", default="",
+                    help="kinds: comma-separated row names to run (default: all)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -376,7 +378,7 @@ def bench_kinds(args):
         ("vrptw100", "VRPTW 100 customers, giant tour + split, P=64, 5000 generations", synth.c3_vrptw()),
         ("vrptw100_weighted", "same, weighted objectives 6 distance + 2 routes + 2 longest route",
          (dataclasses.replace(synth.c3_vrptw()[0], obj_weights=(6, 2, 2)), synth.c3_vrptw()[1])),
-        ("qap50", "QAP n=50, P=1024, 2000 generations", one(synth.qap_random(50, 7), 1024, 2000)),
+        ("qap50", "QAP n=50, P autosized, 2000 generations", one(synth.qap_random(50, 7), 0, 2000)),
     ]
     kp_inst, kp = one(synth.knapsack_random(1000, 7), 2048, 5000)
     rows += [("knapsack1000_flip", "0/1 knapsack n=1000, P=2048, flip only, 5000 generations",
@@ -386,6 +388,9 @@ def bench_kinds(args):
     rows += [("color1000_reset", "planted 3-colouring n=1000 (integer encoding), P=2048, reset only, 5000 generations",
               (co_inst, co.with_(op_mask=1 << synth.OP_RESET))),
              ("color1000_reset_segreset", "same, reset + seg_reset", (co_inst, co.with_(op_mask=synth.INT_OPS)))]
+    if args.kinds_rows:
+        keep = set(args.kinds_rows.split(","))
+        rows = [r for r in rows if r[0] in keep]
     out = []
     for name, what, (inst, p) in rows:
         h = gx.gx_instance_upload(ctx, inst)
