@@ -15,8 +15,7 @@
  *     sum heuristics (Sec. "Population Management").
  * Where the paper leaves a choice open (random source, integer objectives,
  * tie-breaks, the meaning of "batch", constants of the AOS update) the code
- * follows the readings listed in the design doc's table of readings; each such
- * place is marked "reading:".
+ * makes one explicit choice, marked "reading:" where it is made.
  */
 #include "oracle.h"
 #include "exp_tables.h"
