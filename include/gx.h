@@ -197,6 +197,16 @@ gx_status gx_poll(gx_ctx *ctx, gx_job *job);
  * solution_out[capacity >= n]; synchronises the stream. */
 gx_status gx_fetch_best(gx_ctx *ctx, gx_job *job, int32_t *solution_out, int32_t capacity,
                         int64_t *objective_out);
+/* Portfolio selection (paper, Sec. "Multi-GPU" runs: independent solves of
+ * one instance with different seeds, the best kept; here the solves share one
+ * device, e.g. the jobs of one gx_solve_batch call): among count >= 1 jobs of
+ * the same instance, the one whose best objective is smallest (ties: the
+ * lowest position in jobs); its index into *index_out, its objective into
+ * *objective_out and its best solution into solution_out[capacity >= n].
+ * GX_E_INVALID for null arguments, count < 1 or jobs of different instances.
+ * Synchronises the stream. */
+gx_status gx_portfolio_best(gx_ctx *ctx, gx_job *const *jobs, int32_t count, int32_t *solution_out,
+                            int32_t capacity, int64_t *objective_out, int32_t *index_out);
 
 typedef struct {
   uint32_t population, candidates, generations_done, staging;

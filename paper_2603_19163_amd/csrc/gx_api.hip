@@ -869,6 +869,31 @@ gx_status gx_fetch_best(gx_ctx *c, gx_job *j, int32_t *sol, int32_t cap, int64_t
   return GX_OK;
 }
 
+gx_status gx_portfolio_best(gx_ctx *c, gx_job *const *jobs, int32_t count, int32_t *sol, int32_t cap, int64_t *obj,
+                            int32_t *index) {
+  if (!c || !jobs || count < 1 || !obj || !index) return fail(c, GX_E_INVALID, "bad portfolio arguments");
+  for (int i = 0; i < count; ++i)
+    if (!jobs[i] || jobs[i]->inst != jobs[0]->inst) return fail(c, GX_E_INVALID, "portfolio jobs must share one instance");
+  int best = 0;
+  int64_t fb = 0;
+  for (int i = 0; i < count; ++i) {
+    int64_t f = 0;
+    gx_status st = gx_fetch_best(c, jobs[i], nullptr, 0, &f);
+    if (st) return st;
+    if (i == 0 || f < fb) {
+      fb = f;
+      best = i;
+    }
+  }
+  if (sol) {
+    gx_status st = gx_fetch_best(c, jobs[best], sol, cap, &fb);
+    if (st) return st;
+  }
+  *obj = fb;
+  *index = best;
+  return GX_OK;
+}
+
 gx_status gx_job_info_get(gx_ctx *c, gx_job *j, gx_job_info *out) {
   if (!c || !j || !out) return fail(c, GX_E_INVALID, "null argument");
   gx_status st = gx_wait(c, j);

@@ -22,7 +22,7 @@ N_OPS = 8
 
 EXPORTED = ["gx_create", "gx_destroy", "gx_last_error", "gx_get_device_info", "gx_instance_upload",
             "gx_instance_free", "gx_autosize_population", "gx_job_create", "gx_job_advance", "gx_solve",
-            "gx_wait", "gx_poll", "gx_fetch_best", "gx_job_info_get", "gx_snapshot", "gx_job_free",
+            "gx_wait", "gx_poll", "gx_fetch_best", "gx_portfolio_best", "gx_job_info_get", "gx_snapshot", "gx_job_free",
             "gx_solve_batch", "gx_exp_tables", "gx_server_create", "gx_server_submit", "gx_server_poll",
             "gx_server_cancel", "gx_server_stats_get", "gx_server_destroy"]
 
@@ -110,6 +110,7 @@ def lib():
             "gx_wait": ([vp, vp], i32),
             "gx_poll": ([vp, vp], i32),
             "gx_fetch_best": ([vp, vp, vp, i32, C.POINTER(C.c_int64)], i32),
+            "gx_portfolio_best": ([vp, pp, i32, vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)], i32),
             "gx_job_info_get": ([vp, vp, C.POINTER(gx_job_info)], i32),
             "gx_snapshot": ([vp, vp, C.POINTER(gx_state_scalars), vp, vp, vp, vp], i32),
             "gx_job_free": ([vp, vp], i32),
@@ -266,6 +267,15 @@ def gx_fetch_best(ctx, job, n: int):
     f = C.c_int64()
     _check(ctx, lib().gx_fetch_best(ctx, job, sol.ctypes.data, n, C.byref(f)))
     return sol, int(f.value)
+
+
+def gx_portfolio_best(ctx, jobs, n: int):
+    arr = (C.c_void_p * len(jobs))(*[j.value if isinstance(j, C.c_void_p) else j for j in jobs])
+    sol = np.zeros(n, np.int32)
+    f, i = C.c_int64(), C.c_int32()
+    _check(ctx, lib().gx_portfolio_best(ctx, C.cast(arr, C.POINTER(C.c_void_p)), len(jobs), sol.ctypes.data, n,
+                                        C.byref(f), C.byref(i)))
+    return sol, int(f.value), int(i.value)
 
 
 def gx_job_info_get(ctx, job) -> dict:

@@ -140,3 +140,34 @@ def test_autotuner_choices_are_valid_and_result_neutral(ctx):
         assert f0 == f1 and np.array_equal(s0, s1)
     for h in hs:
         gx.gx_instance_free(ctx, h)
+
+
+def test_portfolio_best_of_seeds(ctx):
+    """Portfolio of independent solves of one instance (different seeds, one
+    batch): the selection returns the smallest best objective (ties: the first
+    job) and that job's solution, equal to the plain solves of the same seeds."""
+    inst = synth.tsp_uniform(40, 77, key=7)
+    G = 60
+    params = [synth.Params(seed=500 + s, generations=G, population=4, candidates=64,
+                           alpha_q32=synth.alpha_q32_for(G)) for s in range(6)]
+    h = gx.gx_instance_upload(ctx, inst)
+    jobs = gx.gx_solve_batch(ctx, [h] * len(params), params)
+    sol, f, idx = gx.gx_portfolio_best(ctx, jobs, inst.n)
+    plain = []
+    for p in params:
+        j = gx.gx_solve(ctx, h, p)
+        plain.append(gx.gx_fetch_best(ctx, j, inst.n))
+        gx.gx_job_free(ctx, j)
+    fs = [pf for _, pf in plain]
+    assert f == min(fs) and idx == fs.index(min(fs))
+    assert np.array_equal(sol, plain[idx][0])
+    other = gx.gx_instance_upload(ctx, synth.tsp_uniform(40, 78, key=8))
+    j2 = gx.gx_solve(ctx, other, params[0])
+    with pytest.raises(gx.GxError) as e:
+        gx.gx_portfolio_best(ctx, [jobs[0], j2], inst.n)
+    assert e.value.status == gx.GX_E_INVALID
+    gx.gx_job_free(ctx, j2)
+    gx.gx_instance_free(ctx, other)
+    for j in jobs:
+        gx.gx_job_free(ctx, j)
+    gx.gx_instance_free(ctx, h)
