@@ -656,6 +656,7 @@ void fan_free(Fan &f) {
 struct Group {
   int kind, stage;
   uint32_t off, count, lds, grid;
+  double cost;   // summed cost estimate of the group's items
 };
 struct ItemRec {
   int kind, stage;
@@ -679,9 +680,10 @@ gx_status make_groups(gx_ctx *c, std::vector<ItemRec> &recs, uint2 *items, std::
     if (gs.empty() || gs.back().kind != r.kind || gs.back().stage != r.stage ||
         lds_class(gs.back().lds) != lds_class(r.lds)) {
       if ((int)gs.size() == kMaxGroups) return fail(c, GX_E_UNSUPPORTED, "more than %d work-item groups", kMaxGroups);
-      gs.push_back(Group{r.kind, r.stage, (uint32_t)k, 0, std::max<uint32_t>(16, r.lds), 0});
+      gs.push_back(Group{r.kind, r.stage, (uint32_t)k, 0, std::max<uint32_t>(16, r.lds), 0, 0.0});
     }
     gs.back().count++;
+    gs.back().cost += r.cost;
     gs.back().lds = std::max(gs.back().lds, r.lds);
   }
   for (Group &g : gs) {
@@ -689,6 +691,9 @@ gx_status make_groups(gx_ctx *c, std::vector<ItemRec> &recs, uint2 *items, std::
     HIPCHK(c, gxk::occupancy_group(g.kind, g.stage, g.lds, &occ));
     g.grid = (uint32_t)std::min<size_t>(g.count, (size_t)c->info.cus * (size_t)std::max(1, occ));
   }
+  // the heaviest group is launched first, so that the epoch's critical path
+  // takes the CUs first and the lighter groups fill in beside it
+  std::stable_sort(gs.begin(), gs.end(), [](const Group &x, const Group &y) { return x.cost > y.cost; });
   return GX_OK;
 }
 
