@@ -73,6 +73,7 @@ def lib():
         L = C.CDLL(build())
         P32, P64 = C.POINTER(C.c_uint32), C.POINTER(C.c_int32)
         L.or_philox4x32_10.argtypes = [P32, P32, P32]
+        L.or_philox_many.argtypes = [C.c_void_p, C.c_int64, P32, C.c_void_p]
         L.or_nint_dist.argtypes = [C.c_int32] * 4
         L.or_nint_dist.restype = C.c_int32
         L.or_isqrt.argtypes = [C.c_uint64]
@@ -113,6 +114,15 @@ def philox(ctr, key) -> np.ndarray:
     o = (C.c_uint32 * 4)()
     lib().or_philox4x32_10(c, k, o)
     return np.array(list(o), dtype=np.uint32)
+
+
+def philox_many(ctr, key) -> np.ndarray:
+    """Philox4x32-10 blocks for an (m, 4) array of counters -> (m, 4) uint32."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
+    out = np.zeros_like(c)
+    lib().or_philox_many(c.ctypes.data, len(c), k, out.ctypes.data)
+    return out
 
 
 def nint_dist(x1, y1, x2, y2) -> int:

@@ -53,6 +53,11 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* the same block for `count` counters ctr[4i .. 4i+3] into out[4i .. 4i+3] */
+void or_philox_many(const uint32_t *ctr, int64_t count, const uint32_t key[2], uint32_t *out) {
+  for (int64_t i = 0; i < count; ++i) or_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
 static void draw(const or_params *p, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                  uint32_t r[4]) {
   uint32_t ctr[4] = {c0, c1, c2, c3};
@@ -336,11 +341,12 @@ void or_initial_weights(const or_inst *in, uint32_t op_mask, uint32_t w[OR_MAX_O
 /* ------------------------------------------------------------ acceptance
  * Alg. 1: accept if delta < 0 or rand() < e^{-delta/T}.  reading: delta = 0
  * always accepted (e^0 = 1); e^{-x} taken from two integer tables on
- * z = floor(delta * 2^24 / T_q16) = floor(256 * delta / T). */
+ * z = floor(delta * 2^24 / T_q16) = floor(256 * delta / T), the quotient
+ * taken exactly for every delta < 2^63 and T_q16 < 2^64 (128-bit numerator). */
 uint32_t or_accept_threshold(uint64_t delta, uint64_t t_q16, int *reject) {
   *reject = 0;
   if (t_q16 == 0) { *reject = 1; return 0; }
-  uint64_t z = (delta << 24) / t_q16;
+  unsigned __int128 z = ((unsigned __int128)delta << 24) / t_q16;
   if (z >= 4096) { *reject = 1; return 0; }
   return (uint32_t)(((uint64_t)OR_EXP_HI[z >> 8] * OR_EXP_LO[z & 255]) >> 31);
 }

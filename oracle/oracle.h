@@ -51,6 +51,7 @@ typedef struct {
 typedef struct or_inst or_inst;
 
 void    or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void    or_philox_many(const uint32_t *ctr, int64_t count, const uint32_t key[2], uint32_t *out);
 int32_t or_nint_dist(int32_t x1, int32_t y1, int32_t x2, int32_t y2);
 uint64_t or_isqrt(uint64_t v);
 uint32_t or_accept_threshold(uint64_t delta, uint64_t t_q16, int *reject_outright);

@@ -82,6 +82,32 @@ def test_exp_threshold_close_to_exp():
             assert abs(thr - want) <= 2 + want * 1e-8
 
 
+def test_exp_threshold_wide_deltas_exact():
+    # z = floor(2^24 delta / T) in Python big integers: the quotient must not
+    # wrap for delta >= 2^40 (Alg. 1, rand() < e^{-delta/T})
+    cases = [(2**40 + 5, 65536, None), (2**41, 2**62, 2081412522)]   # reject; z = 8
+    for delta, t_q16, p in cases:
+        thr, rej = oracle.accept_threshold(delta, t_q16)
+        assert rej if p is None else (not rej and thr == p)
+    deltas = [2**39, 2**39 + 3, 2**40 - 1, 2**40 + 5, 2**41, 2**44, 2**52 - 1, 2**52, 2**62 + 11]
+    temps = [2**16, 3 * 2**20 + 7, 2**40 + 17, 2**53 + 1, 2**62, 2**64 - 1]
+    r = np.random.default_rng(9)
+    for _ in range(400):
+        deltas.append(int(r.integers(1, 2**62)))
+        temps.append(int(r.integers(1, 2**63)) * 2 + 1)
+    for delta in deltas:
+        for t_q16 in temps + [delta << 12, (delta << 12) + 1, (delta << 12) - 1]:
+            if not 0 < t_q16 < 2**64:
+                continue
+            z = (delta << 24) // t_q16
+            thr, rej = oracle.accept_threshold(delta, t_q16)
+            if z >= 4096:
+                assert rej, (delta, t_q16)
+            else:
+                want = 2**31 * math.exp(-z / 256.0)
+                assert not rej and abs(thr - want) <= 2 + want * 1e-8, (delta, t_q16, z, thr)
+
+
 def test_cooling_exact_and_sequence():
     g = gold("worked_values.json")["cooling"]
     assert synth.alpha_q32_for(g["generations"]) == g["alpha_q32"]
