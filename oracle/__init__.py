@@ -96,6 +96,9 @@ def lib():
         L.or_heuristic_perms.argtypes = [C.c_void_p, P64, C.c_int]
         L.or_heuristic_perms.restype = C.c_int
         L.or_init.argtypes = [C.c_void_p, C.POINTER(_Params), C.POINTER(_State)]
+        L.or_random_solution.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_uint32, P64]
+        L.or_wpick.argtypes = [C.c_uint32, P32, C.c_int]
+        L.or_wpick.restype = C.c_int
         L.or_run.argtypes = [C.c_void_p, C.POINTER(_Params), C.POINTER(_State), C.c_uint32]
         L.or_effective_mask.argtypes = [C.c_void_p, C.c_uint32]
         L.or_effective_mask.restype = C.c_uint32
@@ -123,6 +126,12 @@ def philox_many(ctr, key) -> np.ndarray:
     out = np.zeros_like(c)
     lib().or_philox_many(c.ctypes.data, len(c), k, out.ctypes.data)
     return out
+
+
+def wpick(u16: int, w) -> int:
+    """Index the Q16 roulette picks for the 16-bit draw u16 over weights w."""
+    arr = (C.c_uint32 * len(w))(*[int(x) for x in w])
+    return int(lib().or_wpick(u16, arr, len(w)))
 
 
 def nint_dist(x1, y1, x2, y2) -> int:
@@ -203,6 +212,13 @@ class OracleInstance:
 
     def effective_mask(self, op_mask) -> int:
         return int(lib().or_effective_mask(self.h, op_mask))
+
+    def random_solution(self, params, pool_index: int) -> np.ndarray:
+        """The random member of the initial pool at `pool_index`."""
+        x = np.zeros(self.n, np.int32)
+        pp = _params(params)
+        lib().or_random_solution(self.h, C.byref(pp), pool_index, _i32p(x))
+        return x
 
     def heuristic_perms(self) -> np.ndarray:
         out = np.zeros((8, self.n), dtype=np.int32)

@@ -69,7 +69,7 @@ static void draw(const or_params *p, uint32_t c0, uint32_t c1, uint32_t c2, uint
 static uint32_t rmap(uint32_t w, uint32_t m) { return (uint32_t)(((uint64_t)w * m) >> 32); }
 
 /* Weighted choice from Q16 weights: u = floor(u16 * S / 2^16), smallest i with u < cumsum_i. */
-static int wpick(uint32_t u16, const uint32_t *w, int cnt) {
+int or_wpick(uint32_t u16, const uint32_t *w, int cnt) {
   uint64_t s = 0;
   for (int i = 0; i < cnt; ++i) s += w[i];
   uint64_t u = ((uint64_t)u16 * s) >> 16;
@@ -538,6 +538,30 @@ int or_heuristic_perms(const or_inst *in, int32_t *out, int cap) {
   return c;
 }
 
+/* A random member of the pool at index q: draw i is word (i mod 4) of the
+ * block with counter (0xFFFFFFFF, q, i / 4, instance key).  Permutations by
+ * Fisher-Yates from the identity (i = n-1 .. 1 swaps x[i] with x[j], j uniform
+ * in [0, i]); bits from the top bit of the draw; integers uniform in [lb, ub]. */
+void or_random_solution(const or_inst *in, const or_params *p, uint32_t q, int32_t *x) {
+  int n = in->d.n;
+  uint32_t key = in->d.key, r[4];
+  if (in->d.kind == K_KNAP || in->d.kind == K_COLOR) {
+    for (int i = 0; i < n; ++i) {
+      draw(p, 0xFFFFFFFFu, q, (uint32_t)(i >> 2), key, r);
+      uint32_t w = r[i & 3];
+      x[i] = in->d.kind == K_KNAP ? (int32_t)(w >> 31)
+                                  : in->d.lb + (int32_t)rmap(w, (uint32_t)(in->d.ub - in->d.lb + 1));
+    }
+  } else {
+    for (int i = 0; i < n; ++i) x[i] = i;
+    for (int i = n - 1; i >= 1; --i) {
+      draw(p, 0xFFFFFFFFu, q, (uint32_t)(i >> 2), key, r);
+      uint32_t j = rmap(r[i & 3], (uint32_t)(i + 1));
+      int32_t t = x[i]; x[i] = x[j]; x[j] = t;
+    }
+  }
+}
+
 typedef struct { int64_t f; int32_t q; } fq;
 static int fq_cmp(const void *a, const void *b) {
   const fq *x = (const fq *)a, *y = (const fq *)b;
@@ -555,26 +579,10 @@ int or_init(const or_inst *in, const or_params *p, or_state *st) {
   int32_t *heur = (int32_t *)malloc(sizeof(int32_t) * (size_t)8 * n);
   int H = or_heuristic_perms(in, heur, 8);
   if (H > Q) H = Q;
-  uint32_t key = in->d.key;
   for (int q = 0; q < Q; ++q) {
     int32_t *x = pool + (size_t)q * n;
-    if (q < H) { memcpy(x, heur + (size_t)q * n, sizeof(int32_t) * n); continue; }
-    uint32_t r[4];
-    if (in->d.kind == K_KNAP || in->d.kind == K_COLOR) {
-      for (int i = 0; i < n; ++i) {
-        draw(p, 0xFFFFFFFFu, (uint32_t)q, (uint32_t)(i >> 2), key, r);
-        uint32_t w = r[i & 3];
-        x[i] = in->d.kind == K_KNAP ? (int32_t)(w >> 31)
-                                    : in->d.lb + (int32_t)rmap(w, (uint32_t)(in->d.ub - in->d.lb + 1));
-      }
-    } else {  /* Fisher-Yates from the identity */
-      for (int i = 0; i < n; ++i) x[i] = i;
-      for (int i = n - 1; i >= 1; --i) {
-        draw(p, 0xFFFFFFFFu, (uint32_t)q, (uint32_t)(i >> 2), key, r);
-        uint32_t j = rmap(r[i & 3], (uint32_t)(i + 1));
-        int32_t t = x[i]; x[i] = x[j]; x[j] = t;
-      }
-    }
+    if (q < H) memcpy(x, heur + (size_t)q * n, sizeof(int32_t) * n);
+    else or_random_solution(in, p, (uint32_t)q, x);
   }
   fq *ord = (fq *)malloc(sizeof(fq) * Q);
   for (int q = 0; q < Q; ++q) { ord[q].f = or_objective(in, pool + (size_t)q * n); ord[q].q = q; }
@@ -630,11 +638,11 @@ int or_run(const or_inst *in, const or_params *p, or_state *st, uint32_t n_gens)
         memcpy(tmp, x, sizeof(int32_t) * n);           /* s_t <- copy(s) */
         uint32_t r[4];
         draw(p, g, (uint32_t)sol, (uint32_t)t << 2, key, r);
-        int k = 1 + wpick(r[0] >> 16, st->w_k, 3);      /* k_t from w_K */
+        int k = 1 + or_wpick(r[0] >> 16, st->w_k, 3);      /* k_t from w_K */
         int ops[3];
         for (int m = 0; m < k; ++m) {
           if (m > 0) draw(p, g, (uint32_t)sol, ((uint32_t)t << 2) | (uint32_t)m, key, r);
-          ops[m] = ids[wpick(r[0] & 0xFFFFu, wl, nids)];  /* sigma_i from R.w */
+          ops[m] = ids[or_wpick(r[0] & 0xFFFFu, wl, nids)];  /* sigma_i from R.w */
           or_apply_op(in, tmp, ops[m], r[1], r[2], r[3]);
         }
         int64_t d = or_objective(in, tmp) - st->cur_f[sol];

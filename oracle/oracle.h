@@ -67,6 +67,8 @@ void     or_aos_update(const or_params *, uint32_t op_mask, or_state *st, int64_
 void     or_migrate(const or_params *, int n, or_state *st, uint32_t epoch);  /* epoch: 1-based count */
 int      or_heuristic_perms(const or_inst *, int32_t *out, int cap); /* returns count */
 int      or_init(const or_inst *, const or_params *, or_state *st);
+void     or_random_solution(const or_inst *, const or_params *, uint32_t pool_index, int32_t *x);
+int      or_wpick(uint32_t u16, const uint32_t *w, int cnt);  /* Q16 roulette */
 int      or_run(const or_inst *, const or_params *, or_state *st, uint32_t n_gens);
 uint32_t or_effective_mask(const or_inst *, uint32_t op_mask);
 
