@@ -293,6 +293,28 @@ gx_status gx_server_destroy(gx_server *srv);
  * hi[i] = round(2^31 e^-i) for i < 16, lo[j] = round(2^31 e^-(j/256)) for j < 256. */
 gx_status gx_exp_tables(uint32_t hi[16], uint32_t lo[256]);
 
+/* Device arithmetic on caller-given inputs, so that the primitives the
+ * kernels use can be compared with an independent implementation.  `in` and
+ * `out` are host arrays of `count` elements (count <= 2^26); the call
+ * synchronises the context's stream.
+ *  GX_CHECK_PHILOX  Philox4x32-10 (Salmon et al., SC'11; the random source of
+ *                   Alg. 1's rand()): key = k0 | k1 << 32; in[2i], in[2i+1] =
+ *                   counter words c0 | c1 << 32, c2 | c3 << 32; out[4i..4i+1]
+ *                   the block from the per-lane form the candidate draws use,
+ *                   out[4i+2..4i+3] from the form of the single draws, each
+ *                   as r0 | r1 << 32, r2 | r3 << 32.
+ *  GX_CHECK_DIST    nearest-integer Euclidean distance (the TSP objective):
+ *                   in[i] = x1 | y1 << 16 | x2 << 32 | y2 << 48, coordinates in
+ *                   [0, 2^14) (GX_E_INVALID otherwise); out[2i] from the
+ *                   int16-pair path, out[2i+1] from the int32 path.
+ *  GX_CHECK_ACCEPT  acceptance threshold of Alg. 1 for a worse move:
+ *                   in[2i] = delta > 0, in[2i+1] = T_q16; out[i] = the value
+ *                   p a 31-bit draw must stay below, or UINT64_MAX when the
+ *                   move is rejected outright (T = 0 or delta / T >= 16). */
+enum { GX_CHECK_PHILOX = 1, GX_CHECK_DIST = 2, GX_CHECK_ACCEPT = 3 };
+gx_status gx_device_check(gx_ctx *ctx, int32_t what, uint64_t key, const uint64_t *in, uint64_t *out,
+                          int64_t count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -380,6 +380,36 @@ gx_status gx_exp_tables(uint32_t hi[16], uint32_t lo[256]) {
   return GX_OK;
 }
 
+gx_status gx_device_check(gx_ctx *c, int32_t what, uint64_t key, const uint64_t *in, uint64_t *out,
+                          int64_t count) {
+  if (!c || (count > 0 && (!in || !out))) return fail(c, GX_E_INVALID, "null argument");
+  if (what < GX_CHECK_PHILOX || what > GX_CHECK_ACCEPT) return fail(c, GX_E_INVALID, "unknown check %d", what);
+  if (count < 0 || count > (int64_t(1) << 26)) return fail(c, GX_E_INVALID, "count in [0, 2^26]");
+  if (count == 0) return GX_OK;
+  const size_t in_w = what == GX_CHECK_DIST ? 1 : 2, out_w = what == GX_CHECK_PHILOX ? 4 : (what == GX_CHECK_DIST ? 2 : 1);
+  if (what == GX_CHECK_DIST)
+    for (int64_t i = 0; i < count; ++i)
+      for (int s = 0; s < 64; s += 16)
+        if (((in[i] >> s) & 0xFFFF) >= (uint64_t)kMaxCoord)
+          return fail(c, GX_E_INVALID, "coordinates must lie in [0, 16384)");
+  HIPCHK(c, hipSetDevice(c->dev));
+  std::vector<void *> bufs;
+  uint64_t *din = nullptr, *dout = nullptr;
+  gx_status st;
+  if ((st = dalloc(c, bufs, &din, 8 * in_w * count)) || (st = dalloc(c, bufs, &dout, 8 * out_w * count))) {
+    free_bufs(bufs);
+    return st;
+  }
+  hipError_t e = hipMemcpyAsync(din, in, 8 * in_w * count, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = gxk::device_check(what, key, din, dout, count, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, dout, 8 * out_w * count, hipMemcpyDeviceToHost, c->stream);
+  const hipError_t es = hipStreamSynchronize(c->stream);   // before the buffers are freed
+  if (e == hipSuccess) e = es;
+  free_bufs(bufs);
+  if (e != hipSuccess) return fail(c, GX_E_DEVICE, "device check: %s", hipGetErrorString(e));
+  return GX_OK;
+}
+
 gx_status gx_create(int device_ordinal, void *hip_stream, gx_ctx **out) {
   if (!out) return GX_E_INVALID;
   *out = nullptr;

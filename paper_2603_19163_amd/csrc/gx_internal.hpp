@@ -127,4 +127,5 @@ hipError_t epoch(gx::DevJob *jobs, const uint32_t *idx, uint32_t count, uint32_t
 hipError_t prepare_kernel_attrs(uint32_t max_lds);
 hipError_t occupancy_plain(int kind, int stage, uint32_t lds, int *blocks_per_cu);
 hipError_t occupancy_group(int kind, int stage, uint32_t lds, int *blocks_per_cu);
+hipError_t device_check(int what, uint64_t key, const uint64_t *in, uint64_t *out, int64_t count, hipStream_t s);
 }  // namespace gxk

@@ -285,22 +285,30 @@ __device__ __forceinline__ unsigned long long wave_min_key(unsigned long long k)
 // Alg. 1: accept when delta < 0 or rand() < e^{-delta/T}; delta = 0 is
 // accepted.  e^{-delta/T} comes from the integer tables at z = floor(256
 // delta / T) (T in Q16), compared with a 31-bit draw.
+//
+// Threshold for a delta d > 0, or -1 when the move is rejected outright
+// (T = 0 or z >= 4096).  z = floor(2^24 d / T) is exact for every d < 2^63:
+// z >= 4096 exactly when 2^12 d >= T; otherwise a = 2^12 d < T and
+// z = floor(2^12 a / T) < 4096, whose double quotient is within 2^-38 of the
+// true one, so its floor is off by at most one and one comparison of the
+// 128-bit products each way makes it exact.
+__device__ __forceinline__ int64_t accept_threshold(uint64_t d, uint64_t T) {
+  if (T == 0 || d >= (1ull << 52)) return -1;
+  const uint64_t a = d << 12;
+  if (a >= T) return -1;
+  uint64_t z = (uint64_t)((double)a * 4096.0 / (double)T);
+  const unsigned __int128 num = (unsigned __int128)a << 12;
+  if ((unsigned __int128)z * T > num) --z;
+  else if (num - (unsigned __int128)z * T >= T) ++z;
+  return (int64_t)(((uint64_t)c_exp_hi[z >> 8] * c_exp_lo[z & 255]) >> 31);
+}
+
 __device__ __forceinline__ bool accept_worse(int64_t ds, uint64_t T, uint32_t g, uint32_t sol, const Uni &U) {
-  if (T == 0) return false;
-  // z = floor(num / T) without a 64-bit integer division: the double quotient
-  // is within 2^-37 of num / T whenever it is below 4097, so its floor is off
-  // by at most one, and one integer correction each way makes z exact.
-  const uint64_t num = (uint64_t)ds << 24;
-  const double qd = (double)num / (double)T;
-  if (qd >= 4097.0) return false;
-  uint64_t z = (uint64_t)qd;
-  if (__umul64hi(z, T) != 0 || z * T > num) --z;
-  if (num - z * T >= T) ++z;
-  if (z >= 4096) return false;
-  const uint32_t p = (uint32_t)(((uint64_t)c_exp_hi[z >> 8] * c_exp_lo[z & 255]) >> 31);
+  const int64_t p = accept_threshold((uint64_t)ds, T);
+  if (p < 0) return false;
   uint32_t r[4];
   philox(g, sol, 0xFFFFFFFFu, U.key, U.k0, U.k1, r);
-  return (r[0] >> 1) < p;
+  return (int64_t)(r[0] >> 1) < p;
 }
 
 // T <- floor(T * alpha / 2^32) in 64-bit pieces (Alg. 1, T <- alpha T)
@@ -2331,8 +2339,43 @@ __global__ void k_build_d32(const int32_t *xy, int n, int32_t *d32) {
   d32[idx] = nint_dist(p[i], p[j]);
 }
 
+// Device arithmetic on given inputs, for comparison with independent
+// implementations: what 1 = both Philox forms (the per-lane one with a
+// uniform key, and the general one), 2 = nearest-integer distance (int16 and
+// int32 coordinate paths), 3 = acceptance threshold.
+__global__ __launch_bounds__(64) void k_check(int what, uint64_t key, const uint64_t *in, uint64_t *out,
+                                              int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (i >= count) return;
+  if (what == 1) {
+    const uint64_t a = in[2 * i], b = in[2 * i + 1];
+    const uint32_t k0 = (uint32_t)key, k1 = (uint32_t)(key >> 32);
+    uint32_t r[4], s[4];
+    philox_lane((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32), k0, k1, r);
+    philox((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32), k0, k1, s);
+    out[4 * i] = r[0] | (uint64_t)r[1] << 32;
+    out[4 * i + 1] = r[2] | (uint64_t)r[3] << 32;
+    out[4 * i + 2] = s[0] | (uint64_t)s[1] << 32;
+    out[4 * i + 3] = s[2] | (uint64_t)s[3] << 32;
+  } else if (what == 2) {
+    const uint64_t v = in[i];
+    const int x1 = (int)(v & 0xFFFF), y1 = (int)((v >> 16) & 0xFFFF), x2 = (int)((v >> 32) & 0xFFFF),
+              y2 = (int)(v >> 48);
+    out[2 * i] = (uint64_t)nint_dist(make_short2((short)x1, (short)y1), make_short2((short)x2, (short)y2));
+    out[2 * i + 1] = (uint64_t)nint_dist(make_int2(x1, y1), make_int2(x2, y2));
+  } else {
+    out[i] = (uint64_t)accept_threshold(in[2 * i], in[2 * i + 1]);
+  }
+}
+
 // ------------------------------------------------------------ launch wrappers
 namespace gxk {
+
+hipError_t device_check(int what, uint64_t key, const uint64_t *in, uint64_t *out, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, s, what, key, in, out, count);
+  return hipGetLastError();
+}
 
 hipError_t set_exp_tables(const uint32_t *hi, const uint32_t *lo) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_exp_hi), hi, 16 * sizeof(uint32_t));

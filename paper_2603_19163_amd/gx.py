@@ -23,7 +23,7 @@ N_OPS = 8
 EXPORTED = ["gx_create", "gx_destroy", "gx_last_error", "gx_get_device_info", "gx_instance_upload",
             "gx_instance_free", "gx_autosize_population", "gx_job_create", "gx_job_advance", "gx_solve",
             "gx_wait", "gx_poll", "gx_fetch_best", "gx_portfolio_best", "gx_job_info_get", "gx_snapshot", "gx_job_free",
-            "gx_solve_batch", "gx_exp_tables", "gx_server_create", "gx_server_submit", "gx_server_poll",
+            "gx_solve_batch", "gx_exp_tables", "gx_device_check", "gx_server_create", "gx_server_submit", "gx_server_poll",
             "gx_server_cancel", "gx_server_stats_get", "gx_server_destroy"]
 
 
@@ -116,6 +116,7 @@ def lib():
             "gx_job_free": ([vp, vp], i32),
             "gx_solve_batch": ([vp, pp, C.POINTER(gx_solve_params), i32, pp], i32),
             "gx_exp_tables": ([C.POINTER(u32), C.POINTER(u32)], i32),
+            "gx_device_check": ([vp, i32, C.c_uint64, vp, vp, C.c_int64], i32),
             "gx_server_create": ([vp, C.POINTER(gx_server_cfg), pp], i32),
             "gx_server_submit": ([vp, C.POINTER(gx_instance_desc), C.POINTER(gx_solve_params),
                                   C.POINTER(C.c_uint64)], i32),
@@ -144,6 +145,20 @@ def gx_exp_tables():
     lo = (C.c_uint32 * 256)()
     _check(None, lib().gx_exp_tables(hi, lo))
     return np.array(list(hi), np.uint32), np.array(list(lo), np.uint32)
+
+
+GX_CHECK_PHILOX, GX_CHECK_DIST, GX_CHECK_ACCEPT = 1, 2, 3
+_CHECK_WIDTH = {GX_CHECK_PHILOX: (2, 4), GX_CHECK_DIST: (1, 2), GX_CHECK_ACCEPT: (2, 1)}
+
+
+def gx_device_check(ctx, what: int, inputs, key: int = 0) -> np.ndarray:
+    """Device arithmetic on `inputs` (uint64, `in` words per element as in
+    include/gx.h); returns the (count, out words) uint64 results."""
+    w_in, w_out = _CHECK_WIDTH[what]
+    x = np.ascontiguousarray(inputs, dtype=np.uint64).reshape(-1, w_in)
+    out = np.zeros((len(x), w_out), np.uint64)
+    _check(ctx, lib().gx_device_check(ctx, what, key & 0xFFFFFFFFFFFFFFFF, x.ctypes.data, out.ctypes.data, len(x)))
+    return out
 
 
 def gx_create(device: int = 0, stream=None):
