@@ -56,16 +56,22 @@ typedef enum {
   GX_INTCOLOR = 5   /* integer in [lb, ub]; graph colouring (monochromatic edges) */
 } gx_problem;
 
-/* Operator ids (bit i of op_mask enables operator i). */
+/* Operators (paper, Tab. "operators"); bit i of op_mask enables operator id
+ * i, and AOS keeps one weight per id.  Ids are contiguous per encoding:
+ * permutation 0-4 (5-7 are kept for the LNS operators of Sec. "Built-in
+ * Operator Hierarchy", which this library does not build), binary 8-9,
+ * integer 10-11. */
+#define GX_N_OPS 12
 enum {
-  GX_OP_2OPT = 1u << 0,    /* segment reversal */
-  GX_OP_SWAP = 1u << 1,
-  GX_OP_INSERT = 1u << 2,  /* move one element */
-  GX_OP_OROPT = 1u << 3,   /* move a block of 2 or 3 elements, orientation kept */
-  GX_OP_FLIP = 1u << 4,    /* binary: flip one bit */
-  GX_OP_SEGFLIP = 1u << 5, /* binary: flip L = 2..7 consecutive bits */
-  GX_OP_RESET = 1u << 6,   /* integer: draw a new value in [lb, ub] */
-  GX_OP_SEGRESET = 1u << 7 /* integer: set L = 2..7 consecutive elements to one new value */
+  GX_OP_2OPT = 1u << 0,    /* element level: segment reversal */
+  GX_OP_SWAP = 1u << 1,    /* element level */
+  GX_OP_INSERT = 1u << 2,  /* element level: move one element */
+  GX_OP_OROPT = 1u << 3,   /* segment level: move a block of 2 or 3 elements, orientation kept */
+  GX_OP_3OPT = 1u << 4,    /* segment level: three cuts a < b < c, blocks [a, b) and [b, c) exchanged */
+  GX_OP_FLIP = 1u << 8,    /* binary, element level: flip one bit */
+  GX_OP_SEGFLIP = 1u << 9, /* binary, segment level: flip L = 2..7 consecutive bits */
+  GX_OP_RESET = 1u << 10,  /* integer, element level: draw a new value in [lb, ub] */
+  GX_OP_SEGRESET = 1u << 11 /* integer, segment level: set L = 2..7 consecutive elements to one new value */
 };
 
 /* Where a TSP instance's distances live during the evolve kernel. */
@@ -136,7 +142,9 @@ typedef struct {
 gx_status gx_instance_upload(gx_ctx *ctx, const gx_instance_desc *desc, gx_instance **out);
 gx_status gx_instance_free(gx_ctx *ctx, gx_instance *inst);
 
-/* Solve parameters; integer only; 0 selects the default in brackets.
+/* Solve parameters (Alg. 1 and Alg. 2; Sec. "Adaptive Operator Selection";
+ * Sec. "Problem-Profile-Driven Prior Strategy"); integer only; 0 selects the
+ * default in brackets.
  *  seed            key of the counter-based generator
  *  generations     generations G to run (>= 1 for gx_solve)
  *  population      P solutions, one workgroup each [0: CUs x resident workgroups per CU]
@@ -152,6 +160,15 @@ gx_status gx_instance_free(gx_ctx *ctx, gx_instance *inst);
  *  aos_credit      0 every candidate credits its operators, 1 only the accepted move [0]
  *  oversample_k    pool of oversample_k * P starting solutions [4]
  *  staging         GX_STAGE_* for TSP [GX_STAGE_AUTO]
+ *  aos_scope       0 the weights of the instance, updated from the counts of
+ *                  all P solutions (Alg. 2); 1 each solution keeps its own
+ *                  weights, counts and stagnation count, updated the same way
+ *                  from its own candidates and its own best objective
+ *                  (aos_epoch * candidates <= 2^30) [0]
+ *  init_weight_q16 raw initial weight of operator id i, Q16 in [1, 2^24]; 0
+ *                  takes the Tab. weight_preset value (1.0; or-opt 0.8 / 0.7 /
+ *                  0.3 and 3-opt 0.5 / 0.3 / 0.05 for n <= 100, <= 250, > 250);
+ *                  the enabled operators' raw weights are then normalised
  * Island model and elite injection (paper, Sec. "Island Model and Elite
  * Injection"), applied at the end of an AOS epoch e, after the weight update:
  *  islands         I islands of P / I consecutive solutions (P a multiple of
@@ -175,26 +192,43 @@ typedef struct {
   uint32_t alpha_q32, aos_epoch, aos_alpha_q16, w_floor_q16;
   uint32_t stagnation_epochs, aos_credit, oversample_k, staging;
   uint32_t islands, migrate_epochs, migrate_mode, migrate_n;
-  uint32_t elite_epochs, reserved;
+  uint32_t elite_epochs, aos_scope;
+  uint32_t init_weight_q16[GX_N_OPS];
 } gx_solve_params;
 
-/* Population the library would use for P = 0 on this instance. */
+/* Population the library would use for P = 0 on this instance: the CUs times
+ * the workgroups one CU holds at the evolve kernel's registers and LDS (at
+ * most 32 per CU).  The paper sizes P from the L2 capacity (Eq. pop_sizing);
+ * this sizing is the gfx950 build's own. */
 gx_status gx_autosize_population(gx_ctx *ctx, const gx_instance *inst, const gx_solve_params *p,
                                  uint32_t *population_out);
 
-/* Allocate a job and run the initialisation (oversampled pool, heuristics,
- * selection of the best P, initial temperature and weights) on the stream. */
+/* Allocate a job and run the initialisation (Sec. "Population Management":
+ * oversampled pool of oversample_k * P starts, the row/column-sum heuristics
+ * of Sec. "Attribute-Agnostic Heuristic Initialization", selection of the
+ * best P; initial temperature and weights) on the stream.  Fails with
+ * GX_E_INVALID or GX_E_UNSUPPORTED as gx_solve does. */
 gx_status gx_job_create(gx_ctx *ctx, const gx_instance *inst, const gx_solve_params *p, gx_job **out);
-/* Enqueue `n_generations` more generations (asynchronous). */
+/* Enqueue `n_generations` more generations of Alg. 1, with the epoch update
+ * of Alg. 2 every aos_epoch generations (asynchronous).  GX_E_INVALID for a
+ * batched job or a total beyond 2^32 - 2 generations. */
 gx_status gx_job_advance(gx_ctx *ctx, gx_job *job, uint32_t n_generations);
-/* gx_job_create followed by gx_job_advance(generations). */
+/* gx_job_create followed by gx_job_advance(generations) (Alg. 1 run for a
+ * generation budget in place of the paper's time limit).  *out receives the
+ * job, which the caller frees with gx_job_free.  GX_E_INVALID for null
+ * arguments, generations = 0, alpha_q32 = 0, an op_mask with no operator of
+ * the encoding or a parameter out of its range above; GX_E_UNSUPPORTED when
+ * the instance needs more LDS than a workgroup has. */
 gx_status gx_solve(gx_ctx *ctx, const gx_instance *inst, const gx_solve_params *p, gx_job **out);
-/* Wait for everything enqueued on the context's stream. */
+/* Wait for everything enqueued on the context's stream (and record the
+ * job's evolve time, gx_job_info.evolve_ms). */
 gx_status gx_wait(gx_ctx *ctx, gx_job *job);
 /* GX_OK if the job's enqueued work has finished, GX_E_NOT_READY otherwise. */
 gx_status gx_poll(gx_ctx *ctx, gx_job *job);
-/* Best solution found (minimum of (best objective, solution index)) into
- * solution_out[capacity >= n]; synchronises the stream. */
+/* Best solution found (the paper returns the best of the population: the
+ * minimum of (best objective, solution index)) into solution_out[capacity >=
+ * n] (may be NULL) and its objective into *objective_out; synchronises the
+ * stream.  GX_E_INVALID when capacity < n. */
 gx_status gx_fetch_best(gx_ctx *ctx, gx_job *job, int32_t *solution_out, int32_t capacity,
                         int64_t *objective_out);
 /* Portfolio selection (paper, Sec. "Multi-GPU" runs: independent solves of
@@ -208,6 +242,8 @@ gx_status gx_fetch_best(gx_ctx *ctx, gx_job *job, int32_t *solution_out, int32_t
 gx_status gx_portfolio_best(gx_ctx *ctx, gx_job *const *jobs, int32_t count, int32_t *solution_out,
                             int32_t capacity, int64_t *objective_out, int32_t *index_out);
 
+/* Run facts of a job (synchronises the stream).  op_steps and k_count count
+ * every evaluated candidate's operators and k (zero with aos_credit = 1). */
 typedef struct {
   uint32_t population, candidates, generations_done, staging;
   uint64_t move_evals;        /* P * C * generations run */
@@ -215,24 +251,56 @@ typedef struct {
   uint32_t evolve_launches;   /* evolve-kernel launches so far */
   float evolve_ms;            /* device time between the first and last evolve launch of the
                                  last gx_job_advance (HIP events on the context stream) */
-  uint64_t op_steps[8];       /* operator steps evaluated over the run, per operator id */
+  uint64_t op_steps[GX_N_OPS]; /* operator steps evaluated over the run, per operator id */
   uint64_t k_count[3];        /* candidates with k = 1, 2, 3 operators over the run */
 } gx_job_info;
 gx_status gx_job_info_get(gx_ctx *ctx, gx_job *job, gx_job_info *out);
 
-/* Scalars of the job state at a generation boundary. */
+/* Run totals of the adaptive-operator-selection statistics (Sec. "Statistics
+ * Collection and Weight Update": per operator its uses u and improvements v,
+ * per k the same) as credited under aos_credit, summed over every generation
+ * and solution so far; synchronises the stream. */
+typedef struct {
+  uint64_t move_evals, accepted;
+  uint64_t u_op[GX_N_OPS], v_op[GX_N_OPS], u_k[3], v_k[3];
+  uint32_t generations_done, population;
+} gx_run_stats;
+gx_status gx_job_stats(gx_ctx *ctx, gx_job *job, gx_run_stats *out);
+/* Population P of a job (the autosized one when population was 0). */
+gx_status gx_job_population(gx_ctx *ctx, gx_job *job, uint32_t *population_out);
+
+/* Scalars of the job state at a generation boundary (Alg. 1 temperature,
+ * Alg. 2 weights, epoch statistics and stagnation count). */
 typedef struct {
   uint32_t g, stag;
   uint64_t T_q16;
   int64_t epoch_ref;          /* instance best at the start of the current epoch */
-  uint32_t w_op[8], w_k[3], pad_;
-  uint64_t u_op[8], v_op[8], u_k[3], v_k[3];   /* statistics of the current epoch */
+  uint32_t w_op[GX_N_OPS], w_k[3], pad_;
+  uint64_t u_op[GX_N_OPS], v_op[GX_N_OPS], u_k[3], v_k[3];   /* statistics of the current epoch */
   uint64_t accepted;
 } gx_state_scalars;
 /* Copy the job state to host buffers (any array may be NULL); synchronises.
  * cur and best are P x n int32, cur_f and best_f P int64. */
 gx_status gx_snapshot(gx_ctx *ctx, gx_job *job, gx_state_scalars *sc, int32_t *cur, int64_t *cur_f,
                       int32_t *best, int64_t *best_f);
+/* Per-solution AOS state (aos_scope = 1): weights, stagnation count, the
+ * solution's best at the start of the epoch, the epoch's counts. */
+typedef struct {
+  uint32_t w_op[GX_N_OPS], w_k[3], stag;
+  int64_t epoch_ref;
+  uint32_t u_op[GX_N_OPS], v_op[GX_N_OPS], u_k[3], v_k[3];
+} gx_sol_aos;
+/* The P per-solution records into out[P]; synchronises. */
+gx_status gx_snapshot_aos(gx_ctx *ctx, gx_job *job, gx_sol_aos *out);
+/* Resume from a snapshot: overwrite a non-batched job's state at a generation
+ * boundary with sc, cur, cur_f, best, best_f (all required, as gx_snapshot
+ * fills them) and, with aos_scope = 1, the P records of aos (else ignored).
+ * Continuing the job then gives the generations the snapshotted job would
+ * have run (same instance and parameters).  GX_E_INVALID for a batched job,
+ * a null array, sc->g beyond the job's generation budget, or a permutation
+ * or value that is not a solution of the instance; synchronises. */
+gx_status gx_job_restore(gx_ctx *ctx, gx_job *job, const gx_state_scalars *sc, const int32_t *cur,
+                         const int64_t *cur_f, const int32_t *best, const int64_t *best_f, const gx_sol_aos *aos);
 gx_status gx_job_free(gx_ctx *ctx, gx_job *job);
 
 /* Batched solve: `count` instances with their own parameters, run together
@@ -262,6 +330,9 @@ typedef struct {
   uint32_t max_lds_bytes;      /* LDS per workgroup a request may need [65536] */
   uint32_t max_items;          /* solutions (workgroups) resident at once; further
                                   requests wait in arrival order [40 x CUs] */
+  uint32_t quantum_epochs;     /* AOS epochs a lane advances per quantum [16 for TSP,
+                                  knapsack and colouring, 4 for QAP and VRPTW] */
+  uint32_t reserved;
 } gx_server_cfg;
 typedef struct {
   uint64_t submitted, admitted, completed, cancelled;

@@ -22,14 +22,14 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-N_OPS = 8
+N_OPS = 12
 
 
 def build(force: bool = False) -> str:
     src = os.path.join(_HERE, "oracle.c")
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < max(
             os.path.getmtime(src), os.path.getmtime(os.path.join(_HERE, "oracle.h"))):
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-Wall", "-shared", "-fPIC", "-pthread",
                                "-o", _SO + ".tmp", src])
         os.replace(_SO + ".tmp", _SO)
     return _SO
@@ -51,7 +51,14 @@ class _Params(C.Structure):
                 ("w_floor_q16", C.c_uint32), ("stagnation_epochs", C.c_uint32),
                 ("credit", C.c_uint32), ("oversample_k", C.c_uint32), ("islands", C.c_uint32),
                 ("migrate_epochs", C.c_uint32), ("migrate_mode", C.c_uint32), ("migrate_n", C.c_uint32),
-                ("elite_epochs", C.c_uint32)]
+                ("elite_epochs", C.c_uint32), ("aos_scope", C.c_uint32), ("init_w", C.c_uint32 * N_OPS)]
+
+
+# per-solution AOS state (or_sol_aos), as a numpy record
+SOL_AOS = np.dtype([("w_op", np.uint32, N_OPS), ("w_k", np.uint32, 3), ("stag", np.uint32),
+                    ("epoch_ref", np.int64), ("u_op", np.uint32, N_OPS), ("v_op", np.uint32, N_OPS),
+                    ("u_k", np.uint32, 3), ("v_k", np.uint32, 3)])
+assert SOL_AOS.itemsize == 192
 
 
 class _State(C.Structure):
@@ -60,8 +67,10 @@ class _State(C.Structure):
                 ("pad_", C.c_uint32),
                 ("u_op", C.c_uint64 * N_OPS), ("v_op", C.c_uint64 * N_OPS),
                 ("u_k", C.c_uint64 * 3), ("v_k", C.c_uint64 * 3), ("accepted", C.c_uint64),
+                ("tot_u_op", C.c_uint64 * N_OPS), ("tot_v_op", C.c_uint64 * N_OPS),
+                ("tot_u_k", C.c_uint64 * 3), ("tot_v_k", C.c_uint64 * 3),
                 ("cur", C.POINTER(C.c_int32)), ("cur_f", C.POINTER(C.c_int64)),
-                ("best", C.POINTER(C.c_int32)), ("best_f", C.POINTER(C.c_int64))]
+                ("best", C.POINTER(C.c_int32)), ("best_f", C.POINTER(C.c_int64)), ("saos", C.c_void_p)]
 
 
 _lib = None
@@ -90,7 +99,7 @@ def lib():
         L.or_dist.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
         L.or_dist.restype = C.c_int32
         L.or_apply_op.argtypes = [C.c_void_p, P64, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32]
-        L.or_initial_weights.argtypes = [C.c_void_p, C.c_uint32, P32]
+        L.or_initial_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, P32]
         L.or_aos_update.argtypes = [C.POINTER(_Params), C.c_uint32, C.POINTER(_State), C.c_int64]
         L.or_migrate.argtypes = [C.POINTER(_Params), C.c_int, C.POINTER(_State), C.c_uint32]
         L.or_heuristic_perms.argtypes = [C.c_void_p, P64, C.c_int]
@@ -100,6 +109,7 @@ def lib():
         L.or_wpick.argtypes = [C.c_uint32, P32, C.c_int]
         L.or_wpick.restype = C.c_int
         L.or_run.argtypes = [C.c_void_p, C.POINTER(_Params), C.POINTER(_State), C.c_uint32]
+        L.or_run_par.argtypes = [C.c_void_p, C.POINTER(_Params), C.POINTER(_State), C.c_uint32, C.c_int]
         L.or_effective_mask.argtypes = [C.c_void_p, C.c_uint32]
         L.or_effective_mask.restype = C.c_uint32
         _lib = L
@@ -162,7 +172,14 @@ def _params(p) -> _Params:
                    stagnation_epochs=p.stagnation_epochs or 5, credit=p.credit,
                    oversample_k=p.oversample_k or 4, islands=p.islands,
                    migrate_epochs=p.migrate_epochs, migrate_mode=p.migrate_mode,
-                   migrate_n=p.migrate_n, elite_epochs=p.elite_epochs)
+                   migrate_n=p.migrate_n, elite_epochs=p.elite_epochs,
+                   aos_scope=getattr(p, "aos_scope", 0),
+                   init_w=(C.c_uint32 * N_OPS)(*_init_w(p)))
+
+
+def _init_w(p):
+    w = list(getattr(p, "init_weight_q16", ()) or ())
+    return [int(x) for x in w] + [0] * (N_OPS - len(w))
 
 
 class OracleInstance:
@@ -205,9 +222,10 @@ class OracleInstance:
         lib().or_apply_op(self.h, _i32p(x), op, w1 & 0xFFFFFFFF, w2 & 0xFFFFFFFF, w3 & 0xFFFFFFFF)
         return x
 
-    def initial_weights(self, op_mask) -> np.ndarray:
+    def initial_weights(self, op_mask, init_w=None) -> np.ndarray:
         w = (C.c_uint32 * N_OPS)()
-        lib().or_initial_weights(self.h, op_mask, w)
+        iw = None if init_w is None else (C.c_uint32 * N_OPS)(*(list(init_w) + [0] * (N_OPS - len(init_w))))
+        lib().or_initial_weights(self.h, op_mask, iw, w)
         return np.array(list(w), dtype=np.uint32)
 
     def effective_mask(self, op_mask) -> int:
@@ -229,7 +247,7 @@ class OracleInstance:
     def _state_struct(self, st: dict) -> _State:
         s = _State(g=st["g"], stag=st["stag"], T_q16=st["T_q16"], epoch_ref=st["epoch_ref"],
                    accepted=st["accepted"])
-        for name in ("w_op", "w_k", "u_op", "v_op", "u_k", "v_k"):
+        for name in ("w_op", "w_k", "u_op", "v_op", "u_k", "v_k", "tot_u_op", "tot_v_op", "tot_u_k", "tot_v_k"):
             arr = getattr(s, name)
             for i, v in enumerate(st[name]):
                 arr[i] = int(v)
@@ -237,6 +255,7 @@ class OracleInstance:
         s.cur_f = st["cur_f"].ctypes.data_as(C.POINTER(C.c_int64))
         s.best = _i32p(st["best"])
         s.best_f = st["best_f"].ctypes.data_as(C.POINTER(C.c_int64))
+        s.saos = st["saos"].ctypes.data
         return s
 
     @staticmethod
@@ -244,7 +263,9 @@ class OracleInstance:
         st["g"], st["stag"], st["T_q16"] = int(s.g), int(s.stag), int(s.T_q16)
         st["epoch_ref"], st["accepted"] = int(s.epoch_ref), int(s.accepted)
         for name, dt in (("w_op", np.uint32), ("w_k", np.uint32), ("u_op", np.uint64),
-                         ("v_op", np.uint64), ("u_k", np.uint64), ("v_k", np.uint64)):
+                         ("v_op", np.uint64), ("u_k", np.uint64), ("v_k", np.uint64),
+                         ("tot_u_op", np.uint64), ("tot_v_op", np.uint64), ("tot_u_k", np.uint64),
+                         ("tot_v_k", np.uint64)):
             st[name] = np.array(list(getattr(s, name)), dtype=dt)
 
     def new_state(self, P: int) -> dict:
@@ -253,8 +274,11 @@ class OracleInstance:
                 "w_op": np.zeros(N_OPS, np.uint32), "w_k": np.zeros(3, np.uint32),
                 "u_op": np.zeros(N_OPS, np.uint64), "v_op": np.zeros(N_OPS, np.uint64),
                 "u_k": np.zeros(3, np.uint64), "v_k": np.zeros(3, np.uint64),
+                "tot_u_op": np.zeros(N_OPS, np.uint64), "tot_v_op": np.zeros(N_OPS, np.uint64),
+                "tot_u_k": np.zeros(3, np.uint64), "tot_v_k": np.zeros(3, np.uint64),
                 "cur": np.zeros((P, n), np.int32), "cur_f": np.zeros(P, np.int64),
-                "best": np.zeros((P, n), np.int32), "best_f": np.zeros(P, np.int64)}
+                "best": np.zeros((P, n), np.int32), "best_f": np.zeros(P, np.int64),
+                "saos": np.zeros(P, SOL_AOS)}
 
     def init(self, params) -> dict:
         st = self.new_state(params.population)
@@ -264,15 +288,24 @@ class OracleInstance:
         self._read_back(s, st)
         return st
 
-    def run(self, params, st: dict, n_gens: int) -> dict:
-        """Advance ``st`` (modified in place and returned) by ``n_gens`` generations."""
+    def run(self, params, st: dict, n_gens: int, threads: int = 1) -> dict:
+        """Advance ``st`` (modified in place and returned) by ``n_gens``
+        generations; ``threads`` > 1 takes the threaded runner (same result)."""
         for k in ("cur", "best"):
             st[k] = np.ascontiguousarray(st[k], dtype=np.int32)
         for k in ("cur_f", "best_f"):
             st[k] = np.ascontiguousarray(st[k], dtype=np.int64)
+        if "saos" not in st or len(st["saos"]) != len(st["cur_f"]):
+            st["saos"] = np.zeros(len(st["cur_f"]), SOL_AOS)
+        st["saos"] = np.ascontiguousarray(st["saos"], dtype=SOL_AOS)
+        for k in ("tot_u_op", "tot_v_op", "tot_u_k", "tot_v_k"):
+            st.setdefault(k, np.zeros(N_OPS if k.endswith("op") else 3, np.uint64))
         s = self._state_struct(st)
         pp = _params(params)
-        lib().or_run(self.h, C.byref(pp), C.byref(s), n_gens)
+        if threads > 1:
+            lib().or_run_par(self.h, C.byref(pp), C.byref(s), n_gens, threads)
+        else:
+            lib().or_run(self.h, C.byref(pp), C.byref(s), n_gens)
         self._read_back(s, st)
         return st
 
@@ -292,9 +325,9 @@ class OracleInstance:
         self._read_back(s, st)
         return st
 
-    def solve(self, params) -> dict:
+    def solve(self, params, threads: int = 1) -> dict:
         st = self.init(params)
-        return self.run(params, st, params.generations)
+        return self.run(params, st, params.generations, threads)
 
 
 def best_of(st: dict):

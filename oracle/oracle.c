@@ -20,12 +20,13 @@
 #include "oracle.h"
 #include "exp_tables.h"
 
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 
 enum { K_TSP = 1, K_QAP = 2, K_KNAP = 3, K_VRPTW = 4, K_COLOR = 5 };
-enum { OP_2OPT = 0, OP_SWAP = 1, OP_INSERT = 2, OP_OROPT = 3, OP_FLIP = 4, OP_SEGFLIP = 5, OP_RESET = 6,
-       OP_SEGRESET = 7 };
+enum { OP_2OPT = 0, OP_SWAP = 1, OP_INSERT = 2, OP_OROPT = 3, OP_3OPT = 4, OP_FLIP = 8, OP_SEGFLIP = 9,
+       OP_RESET = 10, OP_SEGRESET = 11 };
 
 struct or_inst {
   or_inst_desc d;
@@ -271,6 +272,30 @@ int or_apply_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2,
     return op;
   }
   if (n < 2) return op;                      /* every permutation move is the identity */
+  /* Tab. operators, segment level, 3-opt.  reading: the segment exchange, the
+   * 3-opt reconnection that keeps every segment's orientation: three distinct
+   * cut positions a < b < c of {0..n} (drawn as a uniform triple: w1 over n+1
+   * values, w2 over the other n, w3 over the remaining n-1, in increasing
+   * order of value), and s[a..b) and s[b..c) trade places. */
+  if (op == OP_3OPT) {
+    uint32_t c1 = rmap(w1, (uint32_t)n + 1), c2 = rmap(w2, (uint32_t)n), c3 = rmap(w3, (uint32_t)n - 1);
+    c2 += (c2 >= c1);
+    uint32_t lo = c1 < c2 ? c1 : c2, hi = c1 < c2 ? c2 : c1;
+    c3 += (c3 >= lo);
+    c3 += (c3 >= hi);
+    uint32_t a = lo, b = hi, c = c3;          /* sort the three cuts */
+    if (c < a) { uint32_t t = c; c = b; b = a; a = t; }
+    else if (c < b) { uint32_t t = c; c = b; b = t; }
+    int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * n);
+    int o = 0;
+    for (uint32_t p = 0; p < a; ++p) tmp[o++] = x[p];
+    for (uint32_t p = b; p < c; ++p) tmp[o++] = x[p];
+    for (uint32_t p = a; p < b; ++p) tmp[o++] = x[p];
+    for (uint32_t p = c; p < (uint32_t)n; ++p) tmp[o++] = x[p];
+    memcpy(x, tmp, sizeof(int32_t) * n);
+    free(tmp);
+    return op;
+  }
   if (op == OP_2OPT || op == OP_SWAP) {
     uint32_t i = rmap(w1, n), j = rmap(w2, n - 1);
     j += (j >= i);
@@ -304,7 +329,7 @@ int or_apply_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2,
 static uint32_t encoding_ops(int kind) {
   if (kind == K_KNAP) return (1u << OP_FLIP) | (1u << OP_SEGFLIP);
   if (kind == K_COLOR) return (1u << OP_RESET) | (1u << OP_SEGRESET);
-  return (1u << OP_2OPT) | (1u << OP_SWAP) | (1u << OP_INSERT) | (1u << OP_OROPT);
+  return (1u << OP_2OPT) | (1u << OP_SWAP) | (1u << OP_INSERT) | (1u << OP_OROPT) | (1u << OP_3OPT);
 }
 
 uint32_t or_effective_mask(const or_inst *in, uint32_t op_mask) {
@@ -319,9 +344,11 @@ static int enabled_list(uint32_t mask, int *ids) {
 }
 
 /* Sec. "Problem-Profile-Driven Prior Strategy", Tab. "weight_preset":
- * O(1) operators start at 1.0; or-opt at 0.8 / 0.7 / 0.3 for n <= 100,
- * <= 250, > 250; then the weights are normalised (Q16). */
-void or_initial_weights(const or_inst *in, uint32_t op_mask, uint32_t w[OR_MAX_OPS]) {
+ * O(1) operators start at 1.0; or-opt at 0.8 / 0.7 / 0.3 and 3-opt at
+ * 0.50 / 0.30 / 0.05 for n <= 100, <= 250, > 250 (Q16, rounded); a nonzero
+ * init_w[i] replaces the preset of operator i; then the weights are
+ * normalised (Q16). */
+void or_initial_weights(const or_inst *in, uint32_t op_mask, const uint32_t *init_w, uint32_t w[OR_MAX_OPS]) {
   uint32_t m = or_effective_mask(in, op_mask);
   int n = in->d.n;
   uint64_t raw[OR_MAX_OPS] = {0}, s = 0;
@@ -329,6 +356,8 @@ void or_initial_weights(const or_inst *in, uint32_t op_mask, uint32_t w[OR_MAX_O
     if (!(m & (1u << i))) continue;
     raw[i] = 65536;
     if (i == OP_OROPT) raw[i] = n <= 100 ? 52429 : (n <= 250 ? 45875 : 19661);
+    if (i == OP_3OPT) raw[i] = n <= 100 ? 32768 : (n <= 250 ? 19661 : 3277);
+    if (init_w && init_w[i]) raw[i] = init_w[i];
     s += raw[i];
   }
   for (int i = 0; i < OR_MAX_OPS; ++i) {
@@ -400,6 +429,34 @@ void or_aos_update(const or_params *p, uint32_t mask, or_state *st, int64_t inst
   memset(st->v_op, 0, sizeof(st->v_op));
   memset(st->u_k, 0, sizeof(st->u_k));
   memset(st->v_k, 0, sizeof(st->v_k));
+}
+
+/* Per-solution scope (aos_scope = 1).  reading: Alg. 2 pools the statistics
+ * of all blocks of the instance; the per-solution mode gives each solution
+ * (one workgroup) its own operator and K-step weights, updated from its own
+ * candidates' counts with the same Eq. ema arithmetic, and its own
+ * stagnation counter on its own best objective.  The instance-level weights
+ * and epoch counts are then not used and stay as initialised. */
+static void sol_aos_update(const or_params *p, uint32_t mask, or_sol_aos *a, int64_t best_now) {
+  int ids[OR_MAX_OPS];
+  int cnt = enabled_list(mask, ids);
+  uint64_t u[OR_MAX_OPS], v[OR_MAX_OPS], uk[3], vk[3];
+  for (int i = 0; i < OR_MAX_OPS; ++i) { u[i] = a->u_op[i]; v[i] = a->v_op[i]; }
+  for (int i = 0; i < 3; ++i) { uk[i] = a->u_k[i]; vk[i] = a->v_k[i]; }
+  ema_group(p, a->w_op, u, v, ids, cnt);
+  int kid[3] = {0, 1, 2};
+  ema_group(p, a->w_k, uk, vk, kid, 3);
+  if (best_now < a->epoch_ref) a->stag = 0;
+  else a->stag++;
+  a->epoch_ref = best_now;
+  if (a->stag >= p->stagnation_epochs) {
+    memcpy(a->w_k, WK_DEFAULT, sizeof(WK_DEFAULT));
+    a->stag = 0;
+  }
+  memset(a->u_op, 0, sizeof(a->u_op));
+  memset(a->v_op, 0, sizeof(a->v_op));
+  memset(a->u_k, 0, sizeof(a->u_k));
+  memset(a->v_k, 0, sizeof(a->v_k));
 }
 
 /* ------------------------------------------------------------ islands
@@ -600,13 +657,26 @@ int or_init(const or_inst *in, const or_params *p, or_state *st) {
     uint64_t a = (uint64_t)(ord[0].f < 0 ? -ord[0].f : ord[0].f);
     st->T_q16 = ((a << 16) / (uint64_t)n) >> 2;
   }
-  or_initial_weights(in, p->op_mask, st->w_op);
+  or_initial_weights(in, p->op_mask, p->init_w, st->w_op);
   memcpy(st->w_k, WK_DEFAULT, sizeof(WK_DEFAULT));
   memset(st->u_op, 0, sizeof(st->u_op));
   memset(st->v_op, 0, sizeof(st->v_op));
   memset(st->u_k, 0, sizeof(st->u_k));
   memset(st->v_k, 0, sizeof(st->v_k));
+  memset(st->tot_u_op, 0, sizeof(st->tot_u_op));
+  memset(st->tot_v_op, 0, sizeof(st->tot_v_op));
+  memset(st->tot_u_k, 0, sizeof(st->tot_u_k));
+  memset(st->tot_v_k, 0, sizeof(st->tot_v_k));
   st->accepted = 0;
+  if (p->aos_scope == 1) {   /* every solution starts from the same weights and its own objective */
+    for (int s = 0; s < P; ++s) {
+      or_sol_aos *a = &st->saos[s];
+      memset(a, 0, sizeof(*a));
+      memcpy(a->w_op, st->w_op, sizeof(a->w_op));
+      memcpy(a->w_k, WK_DEFAULT, sizeof(a->w_k));
+      a->epoch_ref = st->best_f[s];
+    }
+  }
   free(ord);
   free(heur);
   free(pool);
@@ -618,81 +688,235 @@ int or_init(const or_inst *in, const or_params *p, or_state *st) {
  * epoch of E generations the AOS update of Alg. 2.  reading: the RNG counter
  * of candidate t, operator slot m, is (g, solution, 4t + m, instance key);
  * the acceptance draw uses (g, solution, 0xFFFFFFFF, instance key). */
+
+/* AOS counts one generation of one solution adds (uses u and improvements v
+ * per operator and per k), and its accepted moves */
+typedef struct {
+  uint64_t u_op[OR_MAX_OPS], v_op[OR_MAX_OPS], u_k[3], v_k[3], acc;
+} or_counts;
+
+static void credit(or_counts *c, const int *ops, int k, int improved) {
+  for (int m = 0; m < k; ++m) { c->u_op[ops[m]]++; if (improved) c->v_op[ops[m]]++; }
+  c->u_k[k - 1]++;
+  if (improved) c->v_k[k - 1]++;
+}
+
+/* One generation of solution `sol` at generation g and temperature T (Alg. 1
+ * body); the credited counts are added to *c.  tmp and cand hold n entries. */
+static void generation(const or_inst *in, const or_params *p, or_state *st, int sol, uint32_t g, uint64_t T,
+                       const int *ids, int nids, int32_t *tmp, int32_t *cand, or_counts *c) {
+  int n = in->d.n, C = p->candidates;
+  uint32_t key = in->d.key;
+  int32_t *x = st->cur + (size_t)sol * n;
+  const uint32_t *w_op = p->aos_scope == 1 ? st->saos[sol].w_op : st->w_op;   /* R.w */
+  const uint32_t *w_k = p->aos_scope == 1 ? st->saos[sol].w_k : st->w_k;      /* w_K */
+  uint32_t wl[OR_MAX_OPS];
+  for (int i = 0; i < nids; ++i) wl[i] = w_op[ids[i]];
+  int64_t best_d = 0;
+  int best_t = -1, best_k = 0, best_ops[3] = {0, 0, 0};
+  for (int t = 0; t < C; ++t) {
+    memcpy(tmp, x, sizeof(int32_t) * n);           /* s_t <- copy(s) */
+    uint32_t r[4];
+    draw(p, g, (uint32_t)sol, (uint32_t)t << 2, key, r);
+    int k = 1 + or_wpick(r[0] >> 16, w_k, 3);      /* k_t from w_K */
+    int ops[3];
+    for (int m = 0; m < k; ++m) {
+      if (m > 0) draw(p, g, (uint32_t)sol, ((uint32_t)t << 2) | (uint32_t)m, key, r);
+      ops[m] = ids[or_wpick(r[0] & 0xFFFFu, wl, nids)];  /* sigma_i from R.w */
+      or_apply_op(in, tmp, ops[m], r[1], r[2], r[3]);
+    }
+    int64_t d = or_objective(in, tmp) - st->cur_f[sol];
+    if (p->credit == 0) credit(c, ops, k, d < 0);   /* reading: every candidate credits its operators */
+    if (best_t < 0 || d < best_d) {   /* argmin; ties keep the lowest t */
+      best_d = d; best_t = t; best_k = k;
+      memcpy(best_ops, ops, sizeof(ops));
+      memcpy(cand, tmp, sizeof(int32_t) * n);
+    }
+  }
+  int acc = 0;
+  if (best_d <= 0) acc = 1;
+  else {
+    int rej;
+    uint32_t thr = or_accept_threshold((uint64_t)best_d, T, &rej);
+    if (!rej) {
+      uint32_t r[4];
+      draw(p, g, (uint32_t)sol, 0xFFFFFFFFu, key, r);
+      acc = (r[0] >> 1) < thr;
+    }
+  }
+  if (acc) {
+    if (p->credit == 1) credit(c, best_ops, best_k, best_d < 0);   /* reading R2: only the accepted move */
+    memcpy(x, cand, sizeof(int32_t) * n);
+    st->cur_f[sol] += best_d;
+    c->acc++;
+    if (st->cur_f[sol] < st->best_f[sol]) {
+      st->best_f[sol] = st->cur_f[sol];
+      memcpy(st->best + (size_t)sol * n, x, sizeof(int32_t) * n);
+    }
+  }
+}
+
+/* The counts of one generation of one solution into the epoch statistics of
+ * its scope and the run totals. */
+static void add_counts(const or_params *p, or_state *st, int sol, const or_counts *c) {
+  for (int i = 0; i < OR_MAX_OPS; ++i) {
+    st->tot_u_op[i] += c->u_op[i];
+    st->tot_v_op[i] += c->v_op[i];
+    if (p->aos_scope == 1) {
+      st->saos[sol].u_op[i] += (uint32_t)c->u_op[i];
+      st->saos[sol].v_op[i] += (uint32_t)c->v_op[i];
+    } else {
+      st->u_op[i] += c->u_op[i];
+      st->v_op[i] += c->v_op[i];
+    }
+  }
+  for (int i = 0; i < 3; ++i) {
+    st->tot_u_k[i] += c->u_k[i];
+    st->tot_v_k[i] += c->v_k[i];
+    if (p->aos_scope == 1) {
+      st->saos[sol].u_k[i] += (uint32_t)c->u_k[i];
+      st->saos[sol].v_k[i] += (uint32_t)c->v_k[i];
+    } else {
+      st->u_k[i] += c->u_k[i];
+      st->v_k[i] += c->v_k[i];
+    }
+  }
+  st->accepted += c->acc;
+}
+
+/* At the end of an epoch (g_end a multiple of E): the weight update of the
+ * scope, then migration (Alg. 2; Sec. "Island Model and Elite Injection"). */
+static void epoch_end(const or_inst *in, const or_params *p, or_state *st, uint32_t g_end, uint32_t mask) {
+  int P = p->population;
+  if (p->aos_scope == 1) {
+    for (int s = 0; s < P; ++s) sol_aos_update(p, mask, &st->saos[s], st->best_f[s]);
+  } else {
+    int64_t ib = st->best_f[0];
+    for (int s = 1; s < P; ++s) if (st->best_f[s] < ib) ib = st->best_f[s];
+    or_aos_update(p, mask, st, ib);
+  }
+  or_migrate(p, in->d.n, st, g_end / p->epoch);
+}
+
+/* End of generation g: cooling, then the epoch end when one is reached. */
+static void end_generation(const or_inst *in, const or_params *p, or_state *st, uint32_t g, uint32_t mask) {
+  st->T_q16 = or_cool(st->T_q16, p->alpha_q32);
+  if ((g + 1) % p->epoch == 0) epoch_end(in, p, st, g + 1, mask);
+  st->g = g + 1;
+}
+
 int or_run(const or_inst *in, const or_params *p, or_state *st, uint32_t n_gens) {
-  int n = in->d.n, P = p->population, C = p->candidates;
+  int n = in->d.n, P = p->population;
   uint32_t mask = or_effective_mask(in, p->op_mask);
   int ids[OR_MAX_OPS];
   int nids = enabled_list(mask, ids);
-  uint32_t wl[OR_MAX_OPS];
   int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * n);
   int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * n);
-  uint32_t key = in->d.key;
   for (uint32_t it = 0; it < n_gens; ++it) {
     uint32_t g = st->g;
     for (int sol = 0; sol < P; ++sol) {
-      int32_t *x = st->cur + (size_t)sol * n;
-      for (int c = 0; c < nids; ++c) wl[c] = st->w_op[ids[c]];
-      int64_t best_d = 0;
-      int best_t = -1, best_k = 0, best_ops[3] = {0, 0, 0};
-      for (int t = 0; t < C; ++t) {
-        memcpy(tmp, x, sizeof(int32_t) * n);           /* s_t <- copy(s) */
-        uint32_t r[4];
-        draw(p, g, (uint32_t)sol, (uint32_t)t << 2, key, r);
-        int k = 1 + or_wpick(r[0] >> 16, st->w_k, 3);      /* k_t from w_K */
-        int ops[3];
-        for (int m = 0; m < k; ++m) {
-          if (m > 0) draw(p, g, (uint32_t)sol, ((uint32_t)t << 2) | (uint32_t)m, key, r);
-          ops[m] = ids[or_wpick(r[0] & 0xFFFFu, wl, nids)];  /* sigma_i from R.w */
-          or_apply_op(in, tmp, ops[m], r[1], r[2], r[3]);
-        }
-        int64_t d = or_objective(in, tmp) - st->cur_f[sol];
-        if (p->credit == 0) {  /* reading: every candidate credits its operators */
-          for (int m = 0; m < k; ++m) { st->u_op[ops[m]]++; if (d < 0) st->v_op[ops[m]]++; }
-          st->u_k[k - 1]++;
-          if (d < 0) st->v_k[k - 1]++;
-        }
-        if (best_t < 0 || d < best_d) {   /* argmin; ties keep the lowest t */
-          best_d = d; best_t = t; best_k = k;
-          memcpy(best_ops, ops, sizeof(ops));
-          memcpy(cand, tmp, sizeof(int32_t) * n);
-        }
-      }
-      int acc = 0;
-      if (best_d <= 0) acc = 1;
-      else {
-        int rej;
-        uint32_t thr = or_accept_threshold((uint64_t)best_d, st->T_q16, &rej);
-        if (!rej) {
-          uint32_t r[4];
-          draw(p, g, (uint32_t)sol, 0xFFFFFFFFu, key, r);
-          acc = (r[0] >> 1) < thr;
-        }
-      }
-      if (acc) {
-        if (p->credit == 1) {   /* reading R2: only the accepted move is credited */
-          for (int m = 0; m < best_k; ++m) { st->u_op[best_ops[m]]++; if (best_d < 0) st->v_op[best_ops[m]]++; }
-          st->u_k[best_k - 1]++;
-          if (best_d < 0) st->v_k[best_k - 1]++;
-        }
-        memcpy(x, cand, sizeof(int32_t) * n);
-        st->cur_f[sol] += best_d;
-        st->accepted++;
-        if (st->cur_f[sol] < st->best_f[sol]) {
-          st->best_f[sol] = st->cur_f[sol];
-          memcpy(st->best + (size_t)sol * n, x, sizeof(int32_t) * n);
-        }
-      }
+      or_counts c;
+      memset(&c, 0, sizeof c);
+      generation(in, p, st, sol, g, st->T_q16, ids, nids, tmp, cand, &c);
+      add_counts(p, st, sol, &c);
     }
-    st->T_q16 = or_cool(st->T_q16, p->alpha_q32);
-    if ((g + 1) % p->epoch == 0) {
-      int64_t ib = st->best_f[0];
-      for (int s = 1; s < P; ++s) if (st->best_f[s] < ib) ib = st->best_f[s];
-      or_aos_update(p, mask, st, ib);
-      or_migrate(p, n, st, (g + 1) / p->epoch);
-    }
-    st->g = g + 1;
+    end_generation(in, p, st, g, mask);
   }
   free(cand);
   free(tmp);
+  return 0;
+}
+
+/* ------------------------------------------------------------ parallel runner
+ * The same generations as or_run, spread over threads for speed (tests that
+ * check long windows).  Within an epoch the solutions do not interact: the
+ * weights are fixed and the temperature of generation g depends on g alone,
+ * so each thread runs its share of the solutions through the epoch's
+ * generations, and the counts are summed before the epoch end. */
+typedef struct {
+  const or_inst *in;
+  const or_params *p;
+  or_state *st;
+  const int *ids;
+  int nids, s0, s1;
+  uint32_t g0, L;
+  const uint64_t *T;
+  or_counts sum;
+} or_task;
+
+static void *run_task(void *arg) {
+  or_task *t = (or_task *)arg;
+  int n = t->in->d.n;
+  int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * n);
+  int32_t *cand = (int32_t *)malloc(sizeof(int32_t) * n);
+  memset(&t->sum, 0, sizeof t->sum);
+  for (int sol = t->s0; sol < t->s1; ++sol)
+    for (uint32_t i = 0; i < t->L; ++i) {
+      or_counts c;
+      memset(&c, 0, sizeof c);
+      generation(t->in, t->p, t->st, sol, t->g0 + i, t->T[i], t->ids, t->nids, tmp, cand, &c);
+      for (int o = 0; o < OR_MAX_OPS; ++o) { t->sum.u_op[o] += c.u_op[o]; t->sum.v_op[o] += c.v_op[o]; }
+      for (int q = 0; q < 3; ++q) { t->sum.u_k[q] += c.u_k[q]; t->sum.v_k[q] += c.v_k[q]; }
+      t->sum.acc += c.acc;
+      if (t->p->aos_scope == 1) {   /* the solution's own counts (owned by this thread) */
+        or_sol_aos *a = &t->st->saos[sol];
+        for (int o = 0; o < OR_MAX_OPS; ++o) { a->u_op[o] += (uint32_t)c.u_op[o]; a->v_op[o] += (uint32_t)c.v_op[o]; }
+        for (int q = 0; q < 3; ++q) { a->u_k[q] += (uint32_t)c.u_k[q]; a->v_k[q] += (uint32_t)c.v_k[q]; }
+      }
+    }
+  free(cand);
+  free(tmp);
+  return NULL;
+}
+
+int or_run_par(const or_inst *in, const or_params *p, or_state *st, uint32_t n_gens, int threads) {
+  int P = p->population;
+  if (threads < 1) threads = 1;
+  if (threads > P) threads = P;
+  uint32_t mask = or_effective_mask(in, p->op_mask);
+  int ids[OR_MAX_OPS];
+  int nids = enabled_list(mask, ids);
+  or_task *tasks = (or_task *)calloc((size_t)threads, sizeof(or_task));
+  pthread_t *th = (pthread_t *)calloc((size_t)threads, sizeof(pthread_t));
+  uint64_t *T = (uint64_t *)malloc(sizeof(uint64_t) * ((size_t)p->epoch + 1));
+  while (n_gens > 0) {
+    uint32_t g0 = st->g, E = p->epoch;
+    uint64_t nb = ((uint64_t)g0 / E + 1) * E;
+    uint32_t g1 = (uint64_t)g0 + n_gens < nb ? g0 + n_gens : (uint32_t)nb;
+    uint32_t L = g1 - g0;
+    T[0] = st->T_q16;
+    for (uint32_t i = 0; i < L; ++i) T[i + 1] = or_cool(T[i], p->alpha_q32);
+    for (int k = 0; k < threads; ++k) {
+      or_task *t = &tasks[k];
+      t->in = in; t->p = p; t->st = st; t->ids = ids; t->nids = nids;
+      t->s0 = (int)((int64_t)P * k / threads);
+      t->s1 = (int)((int64_t)P * (k + 1) / threads);
+      t->g0 = g0; t->L = L; t->T = T;
+      if (threads == 1) run_task(t);
+      else pthread_create(&th[k], NULL, run_task, t);
+    }
+    for (int k = 0; k < threads; ++k) {
+      if (threads > 1) pthread_join(th[k], NULL);
+      const or_counts *c = &tasks[k].sum;
+      for (int o = 0; o < OR_MAX_OPS; ++o) {
+        st->tot_u_op[o] += c->u_op[o];
+        st->tot_v_op[o] += c->v_op[o];
+        if (p->aos_scope != 1) { st->u_op[o] += c->u_op[o]; st->v_op[o] += c->v_op[o]; }
+      }
+      for (int q = 0; q < 3; ++q) {
+        st->tot_u_k[q] += c->u_k[q];
+        st->tot_v_k[q] += c->v_k[q];
+        if (p->aos_scope != 1) { st->u_k[q] += c->u_k[q]; st->v_k[q] += c->v_k[q]; }
+      }
+      st->accepted += c->acc;
+    }
+    st->T_q16 = T[L];
+    if (g1 % E == 0) epoch_end(in, p, st, g1, mask);
+    st->g = g1;
+    n_gens -= L;
+  }
+  free(T);
+  free(th);
+  free(tasks);
   return 0;
 }

@@ -12,7 +12,10 @@
 #define GX_ORACLE_H
 #include <stdint.h>
 
-#define OR_MAX_OPS 8
+/* Operator ids (Tab. "operators"): permutation 0 2-opt, 1 swap, 2 insert,
+ * 3 or-opt, 4 3-opt (ids 5-7 are kept for the LNS operators, which are not
+ * built); binary 8 flip, 9 seg_flip; integer 10 random_reset, 11 seg_reset. */
+#define OR_MAX_OPS 12
 
 typedef struct {
   int32_t kind, n;
@@ -31,7 +34,19 @@ typedef struct {
    * every migrate_epochs epochs (0: never) in mode 0 ring, 1 top-N, 2 hybrid,
    * N = migrate_n (0: 1), elite injection every elite_epochs epochs (0: never) */
   uint32_t islands, migrate_epochs, migrate_mode, migrate_n, elite_epochs;
+  /* Alg. 2 scope of the weight statistics: 0 the instance (counts of all
+   * solutions pooled), 1 each solution on its own (or_sol_aos below) */
+  uint32_t aos_scope;
+  /* initial raw operator weights, Q16; 0 selects the Tab. weight_preset value */
+  uint32_t init_w[OR_MAX_OPS];
 } or_params;
+
+/* Per-solution adaptive-operator-selection state (aos_scope = 1). */
+typedef struct {
+  uint32_t w_op[OR_MAX_OPS], w_k[3], stag;
+  int64_t epoch_ref;                  /* the solution's best at the start of the epoch */
+  uint32_t u_op[OR_MAX_OPS], v_op[OR_MAX_OPS], u_k[3], v_k[3];
+} or_sol_aos;
 
 /* Epoch-boundary state of one solve.  Arrays are caller-owned. */
 typedef struct {
@@ -42,10 +57,12 @@ typedef struct {
   uint32_t pad_;
   uint64_t u_op[OR_MAX_OPS], v_op[OR_MAX_OPS], u_k[3], v_k[3]; /* current-epoch counts */
   uint64_t accepted;                  /* accepted moves over the whole run */
+  uint64_t tot_u_op[OR_MAX_OPS], tot_v_op[OR_MAX_OPS], tot_u_k[3], tot_v_k[3]; /* run totals of the counts */
   int32_t *cur;                       /* P x n */
   int64_t *cur_f;                     /* P     */
   int32_t *best;                      /* P x n */
   int64_t *best_f;                    /* P     */
+  or_sol_aos *saos;                   /* P entries when aos_scope = 1, else NULL */
 } or_state;
 
 typedef struct or_inst or_inst;
@@ -62,7 +79,7 @@ void     or_inst_free(or_inst *);
 int64_t  or_objective(const or_inst *, const int32_t *x);
 int32_t  or_dist(const or_inst *, int32_t u, int32_t v);  /* TSP / VRPTW distances */
 int      or_apply_op(const or_inst *, int32_t *x, int op, uint32_t w1, uint32_t w2, uint32_t w3);
-void     or_initial_weights(const or_inst *, uint32_t op_mask, uint32_t w_op[OR_MAX_OPS]);
+void     or_initial_weights(const or_inst *, uint32_t op_mask, const uint32_t *init_w, uint32_t w_op[OR_MAX_OPS]);
 void     or_aos_update(const or_params *, uint32_t op_mask, or_state *st, int64_t inst_best_now);
 void     or_migrate(const or_params *, int n, or_state *st, uint32_t epoch);  /* epoch: 1-based count */
 int      or_heuristic_perms(const or_inst *, int32_t *out, int cap); /* returns count */
@@ -70,6 +87,9 @@ int      or_init(const or_inst *, const or_params *, or_state *st);
 void     or_random_solution(const or_inst *, const or_params *, uint32_t pool_index, int32_t *x);
 int      or_wpick(uint32_t u16, const uint32_t *w, int cnt);  /* Q16 roulette */
 int      or_run(const or_inst *, const or_params *, or_state *st, uint32_t n_gens);
+/* the same generations on `threads` threads (solutions split between them
+ * inside each epoch); equal to or_run */
+int      or_run_par(const or_inst *, const or_params *, or_state *st, uint32_t n_gens, int threads);
 uint32_t or_effective_mask(const or_inst *, uint32_t op_mask);
 
 #endif

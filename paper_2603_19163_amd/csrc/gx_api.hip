@@ -566,6 +566,11 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
       return fail(c, GX_E_UNSUPPORTED, "no int16 distance matrix for this instance");
     if (stage == SLDSXY && !ii.has_xy) return fail(c, GX_E_UNSUPPORTED, "coordinates-in-LDS needs coordinates");
   }
+  if (p->aos_scope > 1) return fail(c, GX_E_INVALID, "aos_scope is 0 (instance) or 1 (solution)");
+  if (p->aos_scope == 1 && (uint64_t)E * C > (1u << 30))
+    return fail(c, GX_E_INVALID, "per-solution weights need aos_epoch * candidates <= 2^30");
+  for (int i = 0; i < kOps; ++i)
+    if (p->init_weight_q16[i] > (1u << 24)) return fail(c, GX_E_INVALID, "init_weight_q16 entries <= 2^24");
   const uint32_t lds = job_lds(ii, stage);
   if (lds > lds_limit)
     return fail(c, GX_E_UNSUPPORTED, "instance needs %u bytes of LDS per workgroup (limit %u)", lds, lds_limit);
@@ -592,6 +597,8 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
   h.mig_mode = p->migrate_mode;
   h.mig_n = mig_n;
   h.elite_epochs = p->elite_epochs;
+  h.aos_scope = p->aos_scope;
+  for (int i = 0; i < kOps; ++i) h.init_w[i] = p->init_weight_q16[i];
   return GX_OK;
 }
 
@@ -604,7 +611,8 @@ int heur_mats_of(int kind) { return kind == KQAP ? 2 : ((kind == KTSP || kind ==
 // bytes of the per-job device arrays, laid out by carve_job
 size_t job_array_bytes(size_t n, size_t P, size_t Q) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  return 2 * al(4 * n * P) + 2 * al(8 * P) + al(4 * n * Q) + al(8 * Q) + al(32 * n) + al(4 * n) + al(8 * kShards * kEpochSlots);
+  return 2 * al(4 * n * P) + 2 * al(8 * P) + al(4 * n * Q) + al(8 * Q) + al(32 * n) + al(4 * n) +
+         al(8 * kShards * kEpochSlots) + al(sizeof(SolAos) * P);
 }
 
 void carve_job(DevJob &h, char *q, size_t n) {
@@ -623,6 +631,7 @@ void carve_job(DevJob &h, char *q, size_t n) {
   h.sums = (int64_t *)take(32 * n);
   h.best_out = (int32_t *)take(4 * n);
   h.shard = (unsigned long long *)take(8 * kShards * kEpochSlots);
+  h.saos = (SolAos *)take(sizeof(SolAos) * h.P);
 }
 
 gx_status ensure_d32(gx_ctx *c, gx_instance *in) {
@@ -818,6 +827,7 @@ gx_status gx_job_create(gx_ctx *c, const gx_instance *cin, const gx_solve_params
       (st = dalloc(c, j->bufs, &h.pool, 4 * n * h.Q)) || (st = dalloc(c, j->bufs, &h.pool_f, (size_t)8 * h.Q)) ||
       (st = dalloc(c, j->bufs, &h.sums, 32 * n)) || (st = dalloc(c, j->bufs, &h.best_out, 4 * n)) ||
       (st = dalloc(c, j->bufs, &h.shard, (size_t)8 * kShards * kEpochSlots)) ||
+      (st = dalloc(c, j->bufs, &h.saos, sizeof(SolAos) * h.P)) ||
       (st = dalloc(c, j->bufs, &j->d, sizeof(DevJob))))
     return bail(st);
   if (hipMemcpy(j->d, &h, sizeof(DevJob), hipMemcpyHostToDevice) != hipSuccess)
@@ -943,8 +953,44 @@ gx_status gx_job_info_get(gx_ctx *c, gx_job *j, gx_job_info *out) {
   out->accepted = h.accepted;
   out->evolve_launches = j->launches;
   out->evolve_ms = j->evolve_ms;
-  for (int i = 0; i < kOps; ++i) out->op_steps[i] = h.tot_u_op[i];
-  for (int i = 0; i < 3; ++i) out->k_count[i] = h.tot_u_k[i];
+  const bool every = j->h.credit == 0;   // the totals count evaluated steps only when every candidate credits
+  for (int i = 0; i < kOps; ++i) out->op_steps[i] = every ? h.tot_u_op[i] : 0;
+  for (int i = 0; i < 3; ++i) out->k_count[i] = every ? h.tot_u_k[i] : 0;
+  return GX_OK;
+}
+
+gx_status gx_job_stats(gx_ctx *c, gx_job *j, gx_run_stats *out) {
+  if (!c || !j || !out) return fail(c, GX_E_INVALID, "null argument");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  DevJob h;
+  HIPCHK(c, hipMemcpy(&h, j->d, sizeof h, hipMemcpyDeviceToHost));
+  memset(out, 0, sizeof *out);
+  out->move_evals = (uint64_t)j->h.P * j->h.C * h.g;
+  out->accepted = h.accepted;
+  for (int i = 0; i < kOps; ++i) {
+    out->u_op[i] = h.tot_u_op[i];
+    out->v_op[i] = h.tot_v_op[i];
+  }
+  for (int i = 0; i < 3; ++i) {
+    out->u_k[i] = h.tot_u_k[i];
+    out->v_k[i] = h.tot_v_k[i];
+  }
+  out->generations_done = h.g;
+  out->population = j->h.P;
+  return GX_OK;
+}
+
+gx_status gx_job_population(gx_ctx *c, gx_job *j, uint32_t *out) {
+  if (!c || !j || !out) return fail(c, GX_E_INVALID, "null argument");
+  *out = j->h.P;
+  return GX_OK;
+}
+
+gx_status gx_snapshot_aos(gx_ctx *c, gx_job *j, gx_sol_aos *out) {
+  if (!c || !j || !out) return fail(c, GX_E_INVALID, "null argument");
+  static_assert(sizeof(gx_sol_aos) == sizeof(SolAos), "per-solution record layout");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(out, j->h.saos, sizeof(SolAos) * j->h.P, hipMemcpyDeviceToHost));
   return GX_OK;
 }
 
@@ -977,6 +1023,69 @@ gx_status gx_snapshot(gx_ctx *c, gx_job *j, gx_state_scalars *sc, int32_t *cur, 
   if (best) HIPCHK(c, hipMemcpy(best, h.best, 4 * n * P, hipMemcpyDeviceToHost));
   if (cur_f) HIPCHK(c, hipMemcpy(cur_f, h.cur_f, 8 * P, hipMemcpyDeviceToHost));
   if (best_f) HIPCHK(c, hipMemcpy(best_f, h.best_f, 8 * P, hipMemcpyDeviceToHost));
+  return GX_OK;
+}
+
+// Whether x (n entries) is a solution of the instance: a permutation of
+// 0..n-1, bits, or values in [lb, ub].
+static bool valid_solution(const DevInst &ih, const int32_t *x, std::vector<char> &seen) {
+  const int n = ih.n;
+  if (ih.kind == KKNAP) {
+    for (int i = 0; i < n; ++i)
+      if (x[i] != 0 && x[i] != 1) return false;
+    return true;
+  }
+  if (ih.kind == KCOLOR) {
+    for (int i = 0; i < n; ++i)
+      if (x[i] < ih.lb || x[i] > ih.ub) return false;
+    return true;
+  }
+  seen.assign((size_t)n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (x[i] < 0 || x[i] >= n || seen[x[i]]) return false;
+    seen[x[i]] = 1;
+  }
+  return true;
+}
+
+gx_status gx_job_restore(gx_ctx *c, gx_job *j, const gx_state_scalars *sc, const int32_t *cur, const int64_t *cur_f,
+                         const int32_t *best, const int64_t *best_f, const gx_sol_aos *aos) {
+  if (!c || !j || !sc || !cur || !cur_f || !best || !best_f) return fail(c, GX_E_INVALID, "null argument");
+  if (j->batch) return fail(c, GX_E_INVALID, "batched jobs cannot be restored");
+  if (j->h.aos_scope == 1 && !aos) return fail(c, GX_E_INVALID, "per-solution weights need their records");
+  if (sc->g > 0xFFFFFFFEu) return fail(c, GX_E_INVALID, "generation beyond 2^32 - 2");
+  const size_t n = (size_t)j->inst->h.n, P = j->h.P;
+  std::vector<char> seen;
+  for (size_t s = 0; s < P; ++s)
+    if (!valid_solution(j->inst->h, cur + s * n, seen) || !valid_solution(j->inst->h, best + s * n, seen))
+      return fail(c, GX_E_INVALID, "solution %zu is not a solution of the instance", s);
+  HIPCHK(c, hipSetDevice(c->dev));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  DevJob h;
+  HIPCHK(c, hipMemcpy(&h, j->d, sizeof h, hipMemcpyDeviceToHost));
+  h.g = h.g_stop = sc->g;
+  h.stag = sc->stag;
+  h.T = sc->T_q16;
+  h.epoch_ref = sc->epoch_ref;
+  for (int i = 0; i < kOps; ++i) {
+    h.w_op[i] = sc->w_op[i];
+    h.u_op[i] = sc->u_op[i];
+    h.v_op[i] = sc->v_op[i];
+  }
+  for (int i = 0; i < 3; ++i) {
+    h.w_k[i] = sc->w_k[i];
+    h.u_k[i] = sc->u_k[i];
+    h.v_k[i] = sc->v_k[i];
+  }
+  h.accepted = sc->accepted;
+  h.inst_best = *std::min_element(best_f, best_f + P);
+  HIPCHK(c, hipMemcpy(h.cur, cur, 4 * n * P, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(h.best, best, 4 * n * P, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(h.cur_f, cur_f, 8 * P, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(h.best_f, best_f, 8 * P, hipMemcpyHostToDevice));
+  if (j->h.aos_scope == 1) HIPCHK(c, hipMemcpy(h.saos, aos, sizeof(SolAos) * P, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(j->d, &h, sizeof h, hipMemcpyHostToDevice));
+  j->g_host = sc->g;
   return GX_OK;
 }
 
@@ -1447,7 +1556,7 @@ void server_loop(gx_server *S) {
       const Group &g = groups[0];
       // requests that finish inside the quantum skip its remaining launches
       // (their generation window is empty)
-      const int qe = quantum_epochs(g.kind);
+      const int qe = S->cfg.quantum_epochs ? (int)S->cfg.quantum_epochs : quantum_epochs(g.kind);
       bool mig = false;
       for (SrvReq *r : act) mig |= migrates(r->hj);
       for (int q = 0; q < qe; ++q) {
@@ -1534,6 +1643,11 @@ gx_status gx_server_create(gx_ctx *c, const gx_server_cfg *cfg, gx_server **out)
   S->cfg.max_resident = cfg && cfg->max_resident ? cfg->max_resident : 1024;
   S->cfg.max_lds_bytes = cfg && cfg->max_lds_bytes ? std::min(cfg->max_lds_bytes, c->max_lds) : std::min(65536u, c->max_lds);
   S->cfg.max_items = cfg && cfg->max_items ? cfg->max_items : 40u * c->info.cus;
+  S->cfg.quantum_epochs = cfg ? cfg->quantum_epochs : 0;
+  if (S->cfg.quantum_epochs > 1024) {
+    delete S;
+    return fail(c, GX_E_INVALID, "quantum_epochs <= 1024");
+  }
   S->gctx.dev = c->dev;
   S->gctx.info = c->info;
   S->gctx.max_lds = c->max_lds;

@@ -7,7 +7,7 @@
 namespace gx {
 
 constexpr int kWave = 64;
-constexpr int kOps = 8;
+constexpr int kOps = 12;
 // Each evolve workgroup adds its per-launch counts (2 kOps + 7 of them) into
 // one of kShards rows of kEpochSlots 64-bit accumulators, picked by its
 // solution index, and lowers the row's smallest best objective (the last
@@ -21,8 +21,11 @@ constexpr int kMaxCoord = 1 << 14;
 constexpr int64_t kDeltaBias = int64_t(1) << 47;   // argmin key = ((delta + bias) << 16) | t
 
 enum Kind : int32_t { KTSP = 1, KQAP = 2, KKNAP = 3, KVRP = 4, KCOLOR = 5 };
-// operator ids: permutation 0-3, binary 4-5, integer 6-7 (contiguous per encoding)
-enum Op : int32_t { O2OPT = 0, OSWAP = 1, OINS = 2, OOROPT = 3, OFLIP = 4, OSFLIP = 5, ORESET = 6, OSRESET = 7 };
+// operator ids, contiguous per encoding: permutation 0-4 (5-7 are kept for
+// the LNS operators, which are not built), binary 8-9, integer 10-11
+enum Op : int32_t { O2OPT = 0, OSWAP = 1, OINS = 2, OOROPT = 3, O3OPT = 4, OFLIP = 8, OSFLIP = 9, ORESET = 10,
+                    OSRESET = 11 };
+constexpr int kPermOps = 5;
 enum Stage : int32_t { SAUTO = 0, SLDS16 = 1, SLDSXY = 2, SGLB16 = 3, SGLB32 = 4 };
 
 // One uploaded instance.  All pointers are device pointers owned by the instance.
@@ -44,6 +47,17 @@ struct DevInst {
   const int32_t *edges;            // colouring edge list
 };
 
+// Adaptive-operator-selection state of one solution when the weights are kept
+// per solution (aos_scope 1): its weights, stagnation count, its best at the
+// start of the epoch, and the counts of the current epoch.  Same layout as
+// gx_sol_aos in include/gx.h.
+struct SolAos {
+  uint32_t w_op[kOps], w_k[3], stag;
+  int64_t epoch_ref;
+  uint32_t u_op[kOps], v_op[kOps], u_k[3], v_k[3];
+};
+static_assert(sizeof(SolAos) == 192, "gx_sol_aos layout");
+
 // One solve.  Scalars below `g` change as the solve runs; the epoch kernel
 // after every evolve launch updates them.
 struct DevJob {
@@ -54,7 +68,8 @@ struct DevJob {
   uint32_t op_mask, credit, aos_A, w_floor;
   uint32_t stag_limit, key, alpha, Q;     // Q = oversample pool size
   uint32_t stage, lds_bytes, islands, mig_epochs;   // island model: see gx_solve_params
-  uint32_t mig_mode, mig_n, elite_epochs, pad1;
+  uint32_t mig_mode, mig_n, elite_epochs, aos_scope;   // aos_scope: 0 instance, 1 per solution
+  uint32_t init_w[kOps];      // caller's raw initial weights (0: Tab. weight_preset)
   // ---- mutable state
   uint32_t g, g_stop, stag, done;
   uint64_t T;
@@ -62,7 +77,8 @@ struct DevJob {
   uint32_t w_op[kOps], w_k[3], pad3;
   unsigned long long u_op[kOps], v_op[kOps], u_k[3], v_k[3];
   unsigned long long accepted;
-  unsigned long long tot_u_op[kOps], tot_u_k[3];   // whole-run usage counts
+  unsigned long long tot_u_op[kOps], tot_u_k[3];   // whole-run totals of the credited counts
+  unsigned long long tot_v_op[kOps], tot_v_k[3];
   // ---- arrays (device)
   int32_t *cur, *best;        // P x n
   int64_t *cur_f, *best_f;    // P
@@ -71,6 +87,7 @@ struct DevJob {
   int64_t *sums;              // 2 x n heuristic row/column sums
   int32_t *best_out;          // n
   unsigned long long *shard;  // kShards x kEpochSlots per-launch accumulators
+  SolAos *saos;               // P per-solution AOS records (used with aos_scope 1)
   int64_t best_out_f;
   int32_t best_idx, pad4;
 };
@@ -82,10 +99,11 @@ struct DevJob {
 constexpr int kOneBufferN = 1536;
 
 // LDS bytes one evolve workgroup needs for this instance and staging: the
-// candidate tables (3968 bytes) followed by the solution and instance data.
+// candidate tables (4736 bytes) followed by the solution and instance data.
+constexpr uint32_t kTables = 4736;
 inline uint32_t lds_bytes_for(int kind, int n, int stage) {
   auto al = [](uint32_t b) { return (b + 15u) & ~15u; };
-  const uint32_t un = (uint32_t)n, tables = 3968;
+  const uint32_t un = (uint32_t)n, tables = kTables;
   const uint32_t tours = (n <= kOneBufferN ? 1 : 2) * al(2 * un);
   switch (kind) {
     case KTSP: {

@@ -106,23 +106,30 @@ struct Step {
 };
 
 // weighted choice from Q16 weights: u = floor(u16 * S / 2^16); smallest i with
-// u < cumsum_i.  An encoding's operators are contiguous ids (permutations 0-3,
-// binary 4-5, integer 6-7) and the others have weight 0, so only the
+// u < cumsum_i.  An encoding's operators are contiguous ids (permutations 0-4,
+// binary 8-9, integer 10-11) and the others have weight 0, so only the
 // encoding's own cumulative sums matter.
 template <int ENC>
 __device__ __forceinline__ int pick_op(uint32_t u16, const Uni &U) {
+  const uint32_t u = (uint32_t)(((uint64_t)u16 * U.sw) >> 16);
   if (ENC != 0) {
     constexpr int lo = ENC == 1 ? OFLIP : ORESET;
-    const uint32_t u = (uint32_t)(((uint64_t)u16 * U.sw) >> 16);
     return lo + (U.w[lo] <= u);
   }
-  const uint32_t u = (uint32_t)(((uint64_t)u16 * U.sw) >> 16);
   uint32_t c = U.w[0];
   int r = (c <= u);
   c += U.w[1]; r += (c <= u);
   c += U.w[2]; r += (c <= u);
+  c += U.w[3]; r += (c <= u);
   return r;
 }
+
+// first operator id of an encoding
+template <int ENC>
+constexpr int enc_lo() { return ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET); }
+// last operator id of an encoding
+template <int ENC>
+constexpr int enc_hi() { return ENC == 0 ? O3OPT : enc_lo<ENC>() + 1; }
 
 // ENC: 0 permutation, 1 binary, 2 integer
 template <int ENC>
@@ -134,7 +141,9 @@ __device__ __forceinline__ Step make_step(int op, uint32_t r1, uint32_t r2, uint
   if (ENC == 0) {
     // 2-opt / swap: two distinct positions i, j of n, ordered; insert /
     // or-opt: block length L, start i of n - L + 1, target q != i of n - L + 1
-    // (one code path for both, selecting the ranges)
+    // (one code path for both, selecting the ranges); 3-opt: three distinct
+    // cuts a < b < c of 0..n, the blocks [a, b) and [b, c) exchanged, which is
+    // the block [a, b) moved to start at q = c - (b - a)
     const bool rv = op < OINS;
     const uint32_t L = rv ? 0u : min((op == OINS) ? 1u : 2u + rmap(r3, 2u), n - 1);
     const uint32_t i = rmap(r1, rv ? n : n - L + 1);
@@ -143,6 +152,19 @@ __device__ __forceinline__ Step make_step(int op, uint32_t r1, uint32_t r2, uint
     s.a = (int)(rv ? min(i, j) : i);
     s.b = (int)(rv ? max(i, j) : j);
     s.c = (int)L;
+    if (op == O3OPT) {
+      const uint32_t c1 = rmap(r1, n + 1);
+      uint32_t c2 = rmap(r2, n);
+      c2 += (c2 >= c1);
+      const uint32_t lo = min(c1, c2), hi = max(c1, c2);
+      uint32_t t = rmap(r3, n - 1);
+      t += (t >= lo);
+      t += (t >= hi);
+      const uint32_t ca = min(lo, t), cc = max(hi, t), cb = lo + hi + t - ca - cc;
+      s.a = (int)ca;
+      s.b = (int)(cc - (cb - ca));
+      s.c = (int)(cb - ca);
+    }
     if (n < 2) s.a = s.b = s.c = 0;
   } else {
     // flip / random reset: one element; seg_flip / seg_reset: L = 2..7
@@ -205,8 +227,7 @@ struct LStats {
 
 template <int ENC>
 __device__ __forceinline__ void credit(LStats &S, const Step *st, int k, bool imp) {
-  constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
-  constexpr int hi = ENC == 0 ? OOROPT : lo + 1;
+  constexpr int lo = enc_lo<ENC>(), hi = enc_hi<ENC>();
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     if (m < k) {
@@ -596,8 +617,8 @@ struct ColorK {
 // atomics.  Draws, moves and deltas are those of the per-candidate
 // formulation; only the order of evaluation differs.
 constexpr int kChunk = 128;
-constexpr uint32_t kTspScratch = kChunk * 3 * 4 + kChunk * 4 + kChunk * 6 * 2 + kChunk * 3;
-static_assert(kTspScratch == 3968, "lds_bytes_for() reserves 3968 bytes of candidate tables");
+constexpr uint32_t kTspScratch = kChunk * 3 * 4 + kChunk * 4 + kChunk * 6 * 2 + kChunk * 3 + kChunk * 3 * 2;
+static_assert(kTspScratch == kTables, "lds_bytes_for() reserves kTables bytes of candidate tables");
 // The pattern list holds at most 2 x 2 entries per candidate of a chunk
 // (steps 2 and 3, two patterns each): 1024 bytes from offset 2048; the rest of
 // its 1536 bytes, up to the operator table at 3584, is free on the TSP path
@@ -615,7 +636,9 @@ struct TspScratch {
   __device__ __forceinline__ uint16_t *lst() const { return (uint16_t *)(gx_lds + 2048); } // t | m << 8 | sub << 10
   // extra draws t | m << 8; used only before the pattern list is built
   __device__ __forceinline__ uint16_t *dl() const { return (uint16_t *)(gx_lds + 2048); }
-  __device__ __forceinline__ uint8_t *sop() const { return (uint8_t *)(gx_lds + 3584); }   // op | L << 3 at [3t + m], k << 6 at m = 0
+  // op - first op of the encoding | L << 3 at [3t + m], k << 6 at m = 0 (L of a 3-opt step in sl)
+  __device__ __forceinline__ uint8_t *sop() const { return (uint8_t *)(gx_lds + 3584); }
+  __device__ __forceinline__ uint16_t *sl() const { return (uint16_t *)(gx_lds + 3968); }   // block length of a 3-opt step
 };
 
 __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
@@ -664,7 +687,15 @@ __device__ __forceinline__ void unpack_step(const TspScratch &W, int t, int m, i
   a = (int)(ab & 0xFFFFu);
   b = (int)(ab >> 16);
   op = (int)(ol & 7u);
-  L = (int)((ol >> 3) & 7u);
+  L = op == O3OPT ? (int)W.sl()[3 * t + m] : (int)((ol >> 3) & 7u);
+}
+
+// a step into the tables (the operator relative to its encoding's first id)
+template <int ENC>
+__device__ __forceinline__ void store_step(const TspScratch &W, uint32_t idx, const Step &st, uint32_t kbits) {
+  W.sab()[idx] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
+  W.sop()[idx] = (uint8_t)((st.op - enc_lo<ENC>()) | ((st.c & 7) << 3) | kbits);
+  if (ENC == 0 && st.op == O3OPT) W.sl()[idx] = (uint16_t)st.c;
 }
 
 // Draw the composite moves of candidates [c0, c0 + cn): the first step of
@@ -689,8 +720,7 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
       const uint32_t u = (uint32_t)(((uint64_t)(w[0] >> 16) * U.swk) >> 16);
       kk[rr] = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
       const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
-      W.sab()[3 * tl] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
-      W.sop()[3 * tl] = (uint8_t)(st.op | (st.c << 3) | (kk[rr] << 6));
+      store_step<ENC>(W, 3 * tl, st, (uint32_t)kk[rr] << 6);
       if constexpr (RN == 2) W.del()[tl] = 0;
     }
   }
@@ -710,8 +740,7 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
     uint32_t w[4];
     philox_lane(g, sol, ((c0 + tl) << 2) | m, U.key, U.k0, U.k1, w);
     const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
-    W.sab()[3 * tl + m] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
-    W.sop()[3 * tl + m] = (uint8_t)(st.op | (st.c << 3));
+    store_step<ENC>(W, 3 * tl + m, st, 0u);
   }
   __syncthreads();
 }
@@ -724,8 +753,8 @@ __device__ __forceinline__ Step load_step(const TspScratch &W, int t, int m) {
   Step st;
   st.a = (int)(ab & 0xFFFFu);
   st.b = ENC == 2 ? (int)(int16_t)(ab >> 16) : (int)(ab >> 16);
-  st.op = (int)(ol & 7u);
-  st.c = (int)((ol >> 3) & 7u);
+  st.op = (int)(ol & 7u) + enc_lo<ENC>();
+  st.c = (ENC == 0 && st.op == O3OPT) ? (int)W.sl()[3 * t + m] : (int)((ol >> 3) & 7u);
   return st;
 }
 
@@ -858,16 +887,24 @@ __device__ __forceinline__ void fold_byte_counts(uint32_t *u, uint32_t *v, uint3
   }
 }
 
+// The same for 64-bit counters with up to 8 byte fields (operators 4-7 in
+// the high word).
+__device__ __forceinline__ void fold_op_counts(uint32_t *u, uint32_t *v, uint64_t cu, uint64_t cv, int fields) {
+  fold_byte_counts(u, v, (uint32_t)cu, (uint32_t)cv, fields < 4 ? fields : 4);
+  if (fields > 4) fold_byte_counts(u + 4, v + 4, (uint32_t)(cu >> 32), (uint32_t)(cv >> 32), fields - 4);
+}
+
 template <class DF>
 __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *el, int n, const DF &D, const TspScratch &W,
                                         const Uni &U, int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1,
                                         uint64_t &T, int64_t &f, int64_t &bf, LStats &S, uint32_t &nacc) {
   const uint32_t lane = lane_id();
-  // Per-lane use and improvement counts of the four operators and of k = 1..3
+  // Per-lane use and improvement counts of the operators and of k = 1..3
   // in byte fields (operator o at bits 8o, k at bits 8(k-1)); a chunk of
   // candidates adds at most 6 to a field of a lane, so the fields are folded
   // into the wave-wide counts of S every 42 chunks and at the end.
-  uint32_t cu_op = 0, cv_op = 0, cu_k = 0, cv_k = 0, since_fold = 0;
+  uint64_t cu_op = 0, cv_op = 0;
+  uint32_t cu_k = 0, cv_k = 0, since_fold = 0;
   // The wave-wide counts live in the unused tail of the pattern-list table
   // during the run (fewer scalar registers held across the generation loop)
   // and are added into S at the end.
@@ -935,9 +972,9 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
           const bool imp = d < 0;
 #pragma unroll
           for (int m = 0; m < 3; ++m) {
-            const uint32_t inc = kk[r] > m ? 1u << ((W.sop()[3 * tl + m] & 7u) << 3) : 0u;
+            const uint64_t inc = kk[r] > m ? 1ull << ((W.sop()[3 * tl + m] & 7u) << 3) : 0ull;
             cu_op += inc;
-            cv_op += imp ? inc : 0u;
+            cv_op += imp ? inc : 0ull;
           }
           const uint32_t inck = 1u << ((kk[r] - 1) << 3);
           cu_k += inck;
@@ -949,9 +986,10 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
         }
       }
       if (++since_fold == 42) {
-        fold_byte_counts(SL.u, SL.v, cu_op, cv_op, 4);
+        fold_op_counts(SL.u, SL.v, cu_op, cv_op, kPermOps);
         fold_byte_counts(SL.uk, SL.vk, cu_k, cv_k, 3);
-        cu_op = cv_op = cu_k = cv_k = 0;
+        cu_op = cv_op = 0;
+        cu_k = cv_k = 0;
         since_fold = 0;
       }
       __syncthreads();
@@ -979,7 +1017,7 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
-          for (int o = 0; o < 4; ++o) {
+          for (int o = 0; o < kPermOps; ++o) {
             const uint32_t hit = m < k && st[m].op == o;
             SL.u[o] += hit;
             SL.v[o] += hit & (uint32_t)(ds < 0);
@@ -1008,11 +1046,11 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
     }
     T = cool(T, U.alpha);
   }
-  fold_byte_counts(SL.u, SL.v, cu_op, cv_op, 4);
+  fold_op_counts(SL.u, SL.v, cu_op, cv_op, kPermOps);
   fold_byte_counts(SL.uk, SL.vk, cu_k, cv_k, 3);
   wave_sync();
 #pragma unroll
-  for (int o = 0; o < 4; ++o) {
+  for (int o = 0; o < kPermOps; ++o) {
     S.u[o] += SL.u[o];
     S.v[o] += SL.v[o];
   }
@@ -1323,14 +1361,14 @@ struct QapK {
 // Byte-field counts of one lane: operator o (relative to the encoding's first
 // operator) at bits 8o of cu/cv, k at bits 8(k-1) of cuk/cvk.
 template <int ENC>
-__device__ __forceinline__ void credit_bytes(uint32_t &cu, uint32_t &cv, uint32_t &cuk, uint32_t &cvk, const Step *st,
+__device__ __forceinline__ void credit_bytes(uint64_t &cu, uint64_t &cv, uint32_t &cuk, uint32_t &cvk, const Step *st,
                                              int k, bool imp) {
-  constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
+  constexpr int lo = enc_lo<ENC>();
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    const uint32_t inc = m < k ? 1u << ((st[m].op - lo) << 3) : 0u;
+    const uint64_t inc = m < k ? 1ull << ((st[m].op - lo) << 3) : 0ull;
     cu += inc;
-    cv += imp ? inc : 0u;
+    cv += imp ? inc : 0ull;
   }
   const uint32_t inck = 1u << ((k - 1) << 3);
   cuk += inck;
@@ -1342,12 +1380,13 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
                                          uint32_t g0, uint32_t g1, uint64_t &T, int64_t &f, int64_t &bf, LStats &S,
                                          uint32_t &nacc) {
   constexpr int ENC = KD::ENC;
-  constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
-  constexpr int nf = ENC == 0 ? 4 : 2;
+  constexpr int lo = enc_lo<ENC>();
+  constexpr int nf = enc_hi<ENC>() - lo + 1;
   const uint32_t lane = lane_id();
   // per-lane byte counts (a chunk adds at most 6 to a field of a lane),
   // folded into the wave-uniform counts of S every 42 chunks and at the end
-  uint32_t cu = 0, cv = 0, cuk = 0, cvk = 0, since_fold = 0;
+  uint64_t cu = 0, cv = 0;
+  uint32_t cuk = 0, cvk = 0, since_fold = 0;
   for (uint32_t g = g0; g < g1; ++g) {
     unsigned long long bk = ~0ull;
     for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
@@ -1370,9 +1409,10 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
         }
       }
       if (++since_fold == 42) {
-        fold_byte_counts(S.u + lo, S.v + lo, cu, cv, nf);
+        fold_op_counts(S.u + lo, S.v + lo, cu, cv, nf);
         fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
-        cu = cv = cuk = cvk = 0;
+        cu = cv = 0;
+        cuk = cvk = 0;
         since_fold = 0;
       }
       __syncthreads();
@@ -1396,7 +1436,7 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
     }
     T = cool(T, U.alpha);
   }
-  fold_byte_counts(S.u + lo, S.v + lo, cu, cv, nf);
+  fold_op_counts(S.u + lo, S.v + lo, cu, cv, nf);
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
 
@@ -1412,7 +1452,8 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
                                            uint32_t &nacc, unsigned long long *xk) {
   constexpr int ENC = KD::ENC;
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
-  uint32_t cu = 0, cv = 0, cuk = 0, cvk = 0, since_fold = 0;
+  uint64_t cu = 0, cv = 0;
+  uint32_t cuk = 0, cvk = 0, since_fold = 0;
   for (uint32_t g = g0; g < g1; ++g) {
     unsigned long long bk = ~0ull;
     for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
@@ -1436,9 +1477,10 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
         }
       }
       if (++since_fold == 84) {   // one candidate per lane per chunk: at most 3 per field
-        fold_byte_counts(S.u, S.v, cu, cv, 4);
+        fold_op_counts(S.u, S.v, cu, cv, kPermOps);
         fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
-        cu = cv = cuk = cvk = 0;
+        cu = cv = 0;
+        cuk = cvk = 0;
         since_fold = 0;
       }
       __syncthreads();
@@ -1464,7 +1506,7 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
     }
     T = cool(T, U.alpha);
   }
-  fold_byte_counts(S.u, S.v, cu, cv, 4);
+  fold_op_counts(S.u, S.v, cu, cv, kPermOps);
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
 
@@ -1513,8 +1555,7 @@ constexpr int kCountSlots = 2 * kOps + 7;   // uses, improvements per operator a
 
 template <int ENC, bool UNIFORM>
 __device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LStats &S, uint32_t nacc, int64_t bf) {
-  constexpr int lo = ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET);
-  constexpr int hi = ENC == 0 ? OOROPT : lo + 1;
+  constexpr int lo = enc_lo<ENC>(), hi = enc_hi<ENC>();
   const uint32_t lane = lane_id();
   uint32_t mine = 0;
 #pragma unroll
@@ -1752,13 +1793,14 @@ __device__ void migrate_block(DevJob *J, uint32_t e, MigLds &M) {
 static_assert(kShards == kWave, "one accumulator row per lane");
 __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, uint32_t g1) {
   // the job state in registers first (one batch of loads, no store between)
-  unsigned long long u_op[kOps], v_op[kOps], tu_op[kOps], u_k[3], v_k[3], tu_k[3];
+  unsigned long long u_op[kOps], v_op[kOps], tu_op[kOps], tv_op[kOps], u_k[3], v_k[3], tu_k[3], tv_k[3];
   uint32_t w_op[kOps], w_k[3];
 #pragma unroll
   for (int o = 0; o < kOps; ++o) {
     u_op[o] = J->u_op[o];
     v_op[o] = J->v_op[o];
     tu_op[o] = J->tot_u_op[o];
+    tv_op[o] = J->tot_v_op[o];
     w_op[o] = J->w_op[o];
   }
 #pragma unroll
@@ -1766,10 +1808,14 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
     u_k[q] = J->u_k[q];
     v_k[q] = J->v_k[q];
     tu_k[q] = J->tot_u_k[q];
+    tv_k[q] = J->tot_v_k[q];
     w_k[q] = J->w_k[q];
   }
-  const uint32_t credit = J->credit, alpha = J->alpha, op_mask = J->op_mask, aos_A = J->aos_A;
+  const uint32_t alpha = J->alpha, op_mask = J->op_mask, aos_A = J->aos_A;
   const uint32_t w_floor = J->w_floor, stag_limit = J->stag_limit;
+  // per-solution weights: the evolve workgroups update them; the instance
+  // statistics and weights stay as initialised
+  const bool inst_scope = J->aos_scope == 0;
   uint32_t stag = J->stag;
   uint64_t T = J->T;
   int64_t inst_best = J->inst_best, epoch_ref = J->epoch_ref;
@@ -1791,19 +1837,25 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
   if (tid != 0) return;
 #pragma unroll
   for (int o = 0; o < kOps; ++o) {
-    u_op[o] += t[o];
-    v_op[o] += t[kOps + o];
-    if (credit == 0) tu_op[o] += t[o];
+    if (inst_scope) {
+      u_op[o] += t[o];
+      v_op[o] += t[kOps + o];
+    }
+    tu_op[o] += t[o];
+    tv_op[o] += t[kOps + o];
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    u_k[q] += t[2 * kOps + q];
-    v_k[q] += t[2 * kOps + 3 + q];
-    if (credit == 0) tu_k[q] += t[2 * kOps + q];
+    if (inst_scope) {
+      u_k[q] += t[2 * kOps + q];
+      v_k[q] += t[2 * kOps + 3 + q];
+    }
+    tu_k[q] += t[2 * kOps + q];
+    tv_k[q] += t[2 * kOps + 3 + q];
   }
   if (mn < inst_best) inst_best = mn;
   for (uint32_t g = g0; g < g1; ++g) T = cool(T, alpha);
-  if (g1 % E == 0) {
+  if (g1 % E == 0 && inst_scope) {
     ema_group(w_op, u_op, v_op, op_mask, kOps, aos_A, w_floor);
     ema_group(w_k, u_k, v_k, 7u, 3, aos_A, w_floor);
     if (inst_best < epoch_ref) stag = 0;
@@ -1823,6 +1875,7 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
     J->u_op[o] = u_op[o];
     J->v_op[o] = v_op[o];
     J->tot_u_op[o] = tu_op[o];
+    J->tot_v_op[o] = tv_op[o];
     J->w_op[o] = w_op[o];
   }
 #pragma unroll
@@ -1830,6 +1883,7 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
     J->u_k[q] = u_k[q];
     J->v_k[q] = v_k[q];
     J->tot_u_k[q] = tu_k[q];
+    J->tot_v_k[q] = tv_k[q];
     J->w_k[q] = w_k[q];
   }
   J->accepted = accepted + t[2 * kOps + 6];
@@ -1867,6 +1921,77 @@ __global__ __launch_bounds__(kEpochWide) void k_epoch_mig(DevJob *jobs, const ui
 
 namespace {
 
+// Weights per solution (aos_scope 1): the workgroup adds its launch's counts
+// to its solution's record and, at an epoch end, applies the Eq. ema update,
+// clamp, normalisation and stagnation check of Alg. 2 to the solution's own
+// weights, with its own best objective in place of the instance best.  S
+// holds this wave's totals; two waves add theirs through LDS first.
+template <int NT>
+__device__ __forceinline__ void solution_aos_close(DevJob *J, uint32_t sol, LStats S, int64_t bf, uint32_t g1,
+                                                   uint32_t E) {
+  constexpr int NW = (int)(sizeof(LStats) / 4);
+  uint32_t *sw = (uint32_t *)&S;
+  if constexpr (NT > kWave) {
+    __syncthreads();   // the candidate tables are dead: wave 1's counts go there
+    uint32_t *X = (uint32_t *)gx_lds;
+    if (threadIdx.x == kWave)
+#pragma unroll
+      for (int i = 0; i < NW; ++i) X[i] = sw[i];
+    __syncthreads();
+    if (threadIdx.x < kWave)
+#pragma unroll
+      for (int i = 0; i < NW; ++i) sw[i] += X[i];
+    __syncthreads();
+  }
+  if (threadIdx.x >= kWave) return;
+  SolAos *A = J->saos + sol;
+  unsigned long long u[kOps], v[kOps], uk[3], vk[3];
+  uint32_t w[kOps], wk[3];
+#pragma unroll
+  for (int o = 0; o < kOps; ++o) {
+    u[o] = A->u_op[o] + S.u[o];
+    v[o] = A->v_op[o] + S.v[o];
+    w[o] = A->w_op[o];
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    uk[q] = A->u_k[q] + S.uk[q];
+    vk[q] = A->v_k[q] + S.vk[q];
+    wk[q] = A->w_k[q];
+  }
+  uint32_t stag = A->stag;
+  int64_t ref = A->epoch_ref;
+  if (g1 % E == 0) {
+    ema_group(w, u, v, J->op_mask, kOps, J->aos_A, J->w_floor);
+    ema_group(wk, uk, vk, 7u, 3, J->aos_A, J->w_floor);
+    stag = bf < ref ? 0u : stag + 1;
+    ref = bf;
+    if (stag >= J->stag_limit) {
+      wk[0] = 52429; wk[1] = 9830; wk[2] = 3277;
+      stag = 0;
+    }
+#pragma unroll
+    for (int o = 0; o < kOps; ++o) u[o] = v[o] = 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) uk[q] = vk[q] = 0;
+  }
+  if (lane_id() != 0) return;
+#pragma unroll
+  for (int o = 0; o < kOps; ++o) {
+    A->u_op[o] = (uint32_t)u[o];
+    A->v_op[o] = (uint32_t)v[o];
+    A->w_op[o] = w[o];
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    A->u_k[q] = (uint32_t)uk[q];
+    A->v_k[q] = (uint32_t)vk[q];
+    A->w_k[q] = wk[q];
+  }
+  A->stag = stag;
+  A->epoch_ref = ref;
+}
+
 // ------------------------------------------------------------ one workgroup
 template <int KIND, int STAGE>
 __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
@@ -1886,16 +2011,20 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
   U.alpha = J->alpha;
   U.lb = I->lb;
   U.ub = I->ub;
+  // the operator and K-step weights of the instance, or of this solution
+  const bool sol_scope = J->aos_scope != 0;
+  const uint32_t *wsrc = sol_scope ? J->saos[sol].w_op : J->w_op;
+  const uint32_t *wksrc = sol_scope ? J->saos[sol].w_k : J->w_k;
   U.sw = 0;
 #pragma unroll
   for (int i = 0; i < kOps; ++i) {
-    U.w[i] = J->w_op[i];
+    U.w[i] = wsrc[i];
     U.sw += U.w[i];
   }
   U.swk = 0;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    U.wk[i] = J->w_k[i];
+    U.wk[i] = wksrc[i];
     U.swk += U.wk[i];
   }
   uint64_t T = J->T;
@@ -2012,6 +2141,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     J->best_f[sol] = bf;
   }
   constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : 0);
+  if (sol_scope) solution_aos_close<kThreads<KIND>>(J, sol, S, bf, g1, E);
   write_counts<ENC, true>(J, sol, S, nacc, bf);   // every wave adds the counts of its own candidates
 }
 
@@ -2257,6 +2387,8 @@ __global__ void k_init_final(DevJob *jobs, int count) {
     if (!(J->op_mask & (1u << i))) continue;
     raw[i] = 65536;
     if (i == OOROPT) raw[i] = n <= 100 ? 52429 : (n <= 250 ? 45875 : 19661);
+    if (i == O3OPT) raw[i] = n <= 100 ? 32768 : (n <= 250 ? 19661 : 3277);
+    if (J->init_w[i]) raw[i] = J->init_w[i];
     s += raw[i];
   }
   for (int i = 0; i < kOps; ++i) {
@@ -2274,8 +2406,16 @@ __global__ void k_init_final(DevJob *jobs, int count) {
   }
   for (int i = 0; i < kOps; ++i) J->u_op[i] = J->v_op[i] = 0;
   for (int i = 0; i < 3; ++i) J->u_k[i] = J->v_k[i] = 0;
-  for (int i = 0; i < kOps; ++i) J->tot_u_op[i] = 0;
-  for (int i = 0; i < 3; ++i) J->tot_u_k[i] = 0;
+  for (int i = 0; i < kOps; ++i) J->tot_u_op[i] = J->tot_v_op[i] = 0;
+  for (int i = 0; i < 3; ++i) J->tot_u_k[i] = J->tot_v_k[i] = 0;
+  if (J->aos_scope)   // every solution starts from the instance's initial weights and its own objective
+    for (uint32_t sol = 0; sol < J->P; ++sol) {
+      SolAos *A = J->saos + sol;
+      for (int i = 0; i < kOps; ++i) A->w_op[i] = J->w_op[i], A->u_op[i] = A->v_op[i] = 0;
+      for (int i = 0; i < 3; ++i) A->w_k[i] = J->w_k[i], A->u_k[i] = A->v_k[i] = 0;
+      A->stag = 0;
+      A->epoch_ref = J->best_f[sol];
+    }
   J->g = 0;
   J->g_stop = 0;
   J->stag = 0;

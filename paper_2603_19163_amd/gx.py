@@ -18,11 +18,12 @@ GX_OK, GX_E_INVALID, GX_E_UNSUPPORTED, GX_E_NOMEM, GX_E_DEVICE, GX_E_NOT_READY, 
 STATUS_NAMES = {0: "GX_OK", -1: "GX_E_INVALID", -2: "GX_E_UNSUPPORTED", -3: "GX_E_NOMEM",
                 -4: "GX_E_DEVICE", -5: "GX_E_NOT_READY", -6: "GX_E_BUSY", -7: "GX_E_CANCELLED"}
 STAGE_AUTO, STAGE_LDS_D16, STAGE_LDS_XY, STAGE_GLB_D16, STAGE_GLB_D32 = 0, 1, 2, 3, 4
-N_OPS = 8
+N_OPS = 12
 
 EXPORTED = ["gx_create", "gx_destroy", "gx_last_error", "gx_get_device_info", "gx_instance_upload",
             "gx_instance_free", "gx_autosize_population", "gx_job_create", "gx_job_advance", "gx_solve",
-            "gx_wait", "gx_poll", "gx_fetch_best", "gx_portfolio_best", "gx_job_info_get", "gx_snapshot", "gx_job_free",
+            "gx_wait", "gx_poll", "gx_fetch_best", "gx_portfolio_best", "gx_job_info_get", "gx_job_stats",
+            "gx_job_population", "gx_snapshot", "gx_snapshot_aos", "gx_job_restore", "gx_job_free",
             "gx_solve_batch", "gx_exp_tables", "gx_device_check", "gx_server_create", "gx_server_submit", "gx_server_poll",
             "gx_server_cancel", "gx_server_stats_get", "gx_server_destroy"]
 
@@ -49,7 +50,8 @@ class gx_solve_params(C.Structure):
                 ("w_floor_q16", C.c_uint32), ("stagnation_epochs", C.c_uint32),
                 ("aos_credit", C.c_uint32), ("oversample_k", C.c_uint32), ("staging", C.c_uint32),
                 ("islands", C.c_uint32), ("migrate_epochs", C.c_uint32), ("migrate_mode", C.c_uint32),
-                ("migrate_n", C.c_uint32), ("elite_epochs", C.c_uint32), ("reserved", C.c_uint32)]
+                ("migrate_n", C.c_uint32), ("elite_epochs", C.c_uint32), ("aos_scope", C.c_uint32),
+                ("init_weight_q16", C.c_uint32 * N_OPS)]
 
 
 class gx_device_info(C.Structure):
@@ -65,9 +67,28 @@ class gx_job_info(C.Structure):
                 ("op_steps", C.c_uint64 * N_OPS), ("k_count", C.c_uint64 * 3)]
 
 
+class gx_run_stats(C.Structure):
+    _fields_ = [("move_evals", C.c_uint64), ("accepted", C.c_uint64),
+                ("u_op", C.c_uint64 * N_OPS), ("v_op", C.c_uint64 * N_OPS),
+                ("u_k", C.c_uint64 * 3), ("v_k", C.c_uint64 * 3),
+                ("generations_done", C.c_uint32), ("population", C.c_uint32)]
+
+
+class gx_sol_aos(C.Structure):
+    _fields_ = [("w_op", C.c_uint32 * N_OPS), ("w_k", C.c_uint32 * 3), ("stag", C.c_uint32),
+                ("epoch_ref", C.c_int64), ("u_op", C.c_uint32 * N_OPS), ("v_op", C.c_uint32 * N_OPS),
+                ("u_k", C.c_uint32 * 3), ("v_k", C.c_uint32 * 3)]
+
+
+# the same record as a numpy dtype (arrays of P records)
+SOL_AOS = np.dtype([("w_op", np.uint32, N_OPS), ("w_k", np.uint32, 3), ("stag", np.uint32),
+                    ("epoch_ref", np.int64), ("u_op", np.uint32, N_OPS), ("v_op", np.uint32, N_OPS),
+                    ("u_k", np.uint32, 3), ("v_k", np.uint32, 3)])
+
+
 class gx_server_cfg(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("max_resident", C.c_uint32), ("max_lds_bytes", C.c_uint32),
-                ("max_items", C.c_uint32)]
+                ("max_items", C.c_uint32), ("quantum_epochs", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class gx_server_stats(C.Structure):
@@ -112,7 +133,11 @@ def lib():
             "gx_fetch_best": ([vp, vp, vp, i32, C.POINTER(C.c_int64)], i32),
             "gx_portfolio_best": ([vp, pp, i32, vp, i32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)], i32),
             "gx_job_info_get": ([vp, vp, C.POINTER(gx_job_info)], i32),
+            "gx_job_stats": ([vp, vp, C.POINTER(gx_run_stats)], i32),
+            "gx_job_population": ([vp, vp, C.POINTER(u32)], i32),
             "gx_snapshot": ([vp, vp, C.POINTER(gx_state_scalars), vp, vp, vp, vp], i32),
+            "gx_snapshot_aos": ([vp, vp, vp], i32),
+            "gx_job_restore": ([vp, vp, C.POINTER(gx_state_scalars), vp, vp, vp, vp, vp], i32),
             "gx_job_free": ([vp, vp], i32),
             "gx_solve_batch": ([vp, pp, C.POINTER(gx_solve_params), i32, pp], i32),
             "gx_exp_tables": ([C.POINTER(u32), C.POINTER(u32)], i32),
@@ -237,7 +262,15 @@ def _params(p) -> gx_solve_params:
                            oversample_k=p.oversample_k, staging=getattr(p, "staging", 0),
                            islands=getattr(p, "islands", 0), migrate_epochs=getattr(p, "migrate_epochs", 0),
                            migrate_mode=getattr(p, "migrate_mode", 0), migrate_n=getattr(p, "migrate_n", 0),
-                           elite_epochs=getattr(p, "elite_epochs", 0))
+                           elite_epochs=getattr(p, "elite_epochs", 0), aos_scope=getattr(p, "aos_scope", 0),
+                           init_weight_q16=(C.c_uint32 * N_OPS)(*_init_w(p)))
+
+
+def _init_w(p):
+    w = [int(x) for x in (getattr(p, "init_weight_q16", ()) or ())]
+    if len(w) > N_OPS:
+        raise ValueError(f"at most {N_OPS} initial weights")
+    return w + [0] * (N_OPS - len(w))
 
 
 def gx_autosize_population(ctx, inst, params) -> int:
@@ -302,6 +335,47 @@ def gx_job_info_get(ctx, job) -> dict:
     return out
 
 
+def gx_job_stats(ctx, job) -> dict:
+    r = gx_run_stats()
+    _check(ctx, lib().gx_job_stats(ctx, job, C.byref(r)))
+    return {"move_evals": int(r.move_evals), "accepted": int(r.accepted),
+            "u_op": np.array(list(r.u_op), np.uint64), "v_op": np.array(list(r.v_op), np.uint64),
+            "u_k": np.array(list(r.u_k), np.uint64), "v_k": np.array(list(r.v_k), np.uint64),
+            "generations_done": int(r.generations_done), "population": int(r.population)}
+
+
+def gx_job_population(ctx, job) -> int:
+    out = C.c_uint32()
+    _check(ctx, lib().gx_job_population(ctx, job, C.byref(out)))
+    return int(out.value)
+
+
+def gx_snapshot_aos(ctx, job, P: int) -> np.ndarray:
+    """The P per-solution AOS records (numpy array of SOL_AOS)."""
+    out = np.zeros(P, SOL_AOS)
+    _check(ctx, lib().gx_snapshot_aos(ctx, job, out.ctypes.data))
+    return out
+
+
+def gx_job_restore(ctx, job, st: dict):
+    """Overwrite a job's state with ``st`` (the dict gx_snapshot returns, plus
+    "saos" records for per-solution weights)."""
+    sc = gx_state_scalars(g=st["g"], stag=st["stag"], T_q16=st["T_q16"], epoch_ref=st["epoch_ref"],
+                          accepted=st["accepted"])
+    for name in ("w_op", "w_k", "u_op", "v_op", "u_k", "v_k"):
+        arr = getattr(sc, name)
+        for i, v in enumerate(st[name]):
+            arr[i] = int(v)
+    cur = np.ascontiguousarray(st["cur"], np.int32)
+    best = np.ascontiguousarray(st["best"], np.int32)
+    cur_f = np.ascontiguousarray(st["cur_f"], np.int64)
+    best_f = np.ascontiguousarray(st["best_f"], np.int64)
+    aos = st.get("saos")
+    aos = None if aos is None else np.ascontiguousarray(aos, SOL_AOS)
+    _check(ctx, lib().gx_job_restore(ctx, job, C.byref(sc), cur.ctypes.data, cur_f.ctypes.data, best.ctypes.data,
+                                     best_f.ctypes.data, None if aos is None else aos.ctypes.data))
+
+
 def gx_snapshot(ctx, job, P: int, n: int) -> dict:
     """Job state in the oracle's state layout (dict of numpy arrays and ints)."""
     sc = gx_state_scalars()
@@ -334,9 +408,9 @@ def gx_solve_batch(ctx, insts, params_list):
 
 
 # ------------------------------------------------------------------ serving
-def gx_server_create(ctx, hbm_budget_bytes=0, max_resident=0, max_lds_bytes=0, max_items=0):
+def gx_server_create(ctx, hbm_budget_bytes=0, max_resident=0, max_lds_bytes=0, max_items=0, quantum_epochs=0):
     cfg = gx_server_cfg(hbm_budget_bytes=hbm_budget_bytes, max_resident=max_resident,
-                        max_lds_bytes=max_lds_bytes, max_items=max_items)
+                        max_lds_bytes=max_lds_bytes, max_items=max_items, quantum_epochs=quantum_epochs)
     out = C.c_void_p()
     _check(ctx, lib().gx_server_create(ctx, C.byref(cfg), C.byref(out)))
     return out

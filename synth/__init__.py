@@ -23,10 +23,14 @@ import numpy as np
 TSP, QAP, KNAPSACK, VRPTW, INTCOLOR = 1, 2, 3, 4, 5
 KIND_NAMES = {TSP: "tsp", QAP: "qap", KNAPSACK: "knapsack", VRPTW: "vrptw", INTCOLOR: "intcolor"}
 
-OP_2OPT, OP_SWAP, OP_INSERT, OP_OROPT, OP_FLIP, OP_SEGFLIP, OP_RESET, OP_SEGRESET = 0, 1, 2, 3, 4, 5, 6, 7
-OP_NAMES = ["2opt", "swap", "insert", "oropt", "flip", "segflip", "reset", "segreset"]
-N_OPS = 8
-PERM_OPS = (1 << OP_2OPT) | (1 << OP_SWAP) | (1 << OP_INSERT) | (1 << OP_OROPT)
+# permutation 0-4 (ids 5-7 are kept for the LNS operators, not built),
+# binary 8-9, integer 10-11
+OP_2OPT, OP_SWAP, OP_INSERT, OP_OROPT, OP_3OPT = 0, 1, 2, 3, 4
+OP_FLIP, OP_SEGFLIP, OP_RESET, OP_SEGRESET = 8, 9, 10, 11
+OP_NAMES = ["2opt", "swap", "insert", "oropt", "3opt", "lns5", "lns6", "lns7", "flip", "segflip", "reset", "segreset"]
+N_OPS = 12
+PERM4_OPS = (1 << OP_2OPT) | (1 << OP_SWAP) | (1 << OP_INSERT) | (1 << OP_OROPT)
+PERM_OPS = PERM4_OPS | (1 << OP_3OPT)
 BIN_OPS = (1 << OP_FLIP) | (1 << OP_SEGFLIP)
 INT_OPS = (1 << OP_RESET) | (1 << OP_SEGRESET)
 
@@ -92,6 +96,8 @@ class Params:
     migrate_mode: int = 0      # 0 ring, 1 global top-N, 2 hybrid
     migrate_n: int = 0         # N of top-N (0 = 1)
     elite_epochs: int = 0      # elite injection every this many epochs (0 = never)
+    aos_scope: int = 0         # 0 weights per instance, 1 per solution
+    init_weight_q16: tuple = ()  # raw initial operator weights by id (0 = preset)
 
     def with_(self, **kw) -> "Params":
         return replace(self, **kw)
@@ -229,10 +235,11 @@ def c1_small_tsp(inst_id: int = 0) -> tuple[Instance, Params]:
 
 
 def c2_tsp442(population: int, generations: int = 200_000, seed: int = 42) -> tuple[Instance, Params]:
-    """Clustered TSP n=442 (20 clusters, sigma 300), all four permutation ops."""
+    """Clustered TSP n=442 (20 clusters, sigma 300), the four element and
+    or-opt permutation ops (2-opt, swap, insert, or-opt)."""
     inst = tsp_clustered(442, 0)
     p = Params(seed=seed, generations=generations, population=population, candidates=128,
-               op_mask=PERM_OPS, alpha_q32=alpha_q32_for(generations))
+               op_mask=PERM4_OPS, alpha_q32=alpha_q32_for(generations))
     return inst, p
 
 

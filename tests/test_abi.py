@@ -85,12 +85,21 @@ def _py_layout(cls):
 def test_binding_structs_match_the_header():
     from paper_2603_19163_amd import gx
     classes = [gx.gx_instance_desc, gx.gx_solve_params, gx.gx_device_info, gx.gx_job_info,
-               gx.gx_server_cfg, gx.gx_server_stats, gx.gx_state_scalars]
+               gx.gx_server_cfg, gx.gx_server_stats, gx.gx_state_scalars, gx.gx_run_stats, gx.gx_sol_aos]
     c = _c_layout(os.path.join(ROOT, "include", "gx.h"),
                   {k.__name__: [f for f, _ in k._fields_] for k in classes})
     for k in classes:
         for key, val in _py_layout(k).items():
             assert c[key] == val, (key, c[key], val)
+
+
+def test_numpy_records_match_the_structs():
+    import oracle
+    from paper_2603_19163_amd import gx
+    assert gx.SOL_AOS.itemsize == ctypes.sizeof(gx.gx_sol_aos) == oracle.SOL_AOS.itemsize == 192
+    for name, _ in gx.gx_sol_aos._fields_:
+        assert gx.SOL_AOS.fields[name][1] == getattr(gx.gx_sol_aos, name).offset
+        assert oracle.SOL_AOS.fields[name][1] == getattr(gx.gx_sol_aos, name).offset
 
 
 def test_oracle_binding_structs_match_its_header():

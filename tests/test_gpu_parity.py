@@ -41,6 +41,7 @@ def gpu_states(ctx, inst, p, splits):
         gx.gx_job_advance(ctx, job, s)
         out.append(gx.gx_snapshot(ctx, job, p.population, inst.n))
     sol, f = gx.gx_fetch_best(ctx, job, inst.n)
+    out[-1]["stats"] = gx.gx_job_stats(ctx, job)
     gx.gx_job_free(ctx, job)
     gx.gx_instance_free(ctx, h)
     return out, (sol, f)
@@ -62,6 +63,9 @@ def check(ctx, inst, p, splits, what):
     os_ = oracle_states(inst, p, splits)
     for i, (g, o) in enumerate(zip(gs, os_)):
         assert_same(g, o, f"{what} snapshot {i}")
+    stats = gs[-1]["stats"]
+    for gk, ok in (("u_op", "tot_u_op"), ("v_op", "tot_v_op"), ("u_k", "tot_u_k"), ("v_k", "tot_v_k")):
+        assert np.array_equal(stats[gk], os_[-1][ok]), f"{what}: run total {gk}"
     fo, io = oracle.best_of(os_[-1])
     assert f == fo and np.array_equal(sol, os_[-1]["best"][io])
 

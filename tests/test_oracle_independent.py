@@ -48,8 +48,8 @@ def test_roulette_frequencies_in_a_run():
     p = synth.Params(seed=5, population=8, candidates=128, generations=60, epoch=1000,
                      alpha_q32=synth.alpha_q32_for(60))
     st = o.solve(p)
-    w_op = list(o.initial_weights(0)[:4])
-    for counts, w in ((st["u_op"][:4], w_op), (st["u_k"], [52429, 9830, 3277])):
+    w_op = list(o.initial_weights(0)[:5])
+    for counts, w in ((st["u_op"][:5], w_op), (st["u_k"], [52429, 9830, 3277])):
         n = int(sum(counts))
         prob = np.array(_roulette_counts(w)) / 65536
         chi2 = float((((np.asarray(counts, float) - n * prob) ** 2) / (n * prob)).sum())
@@ -73,7 +73,7 @@ def _hand_generation(o, D, x, f, p, w_op, w_k, T, key):
     lowest t; a worse move is accepted when word 0 of block
     (g, sol, 2^32 - 1, key), shifted right by one, is below the threshold."""
     seed = [p.seed & 0xFFFFFFFF, p.seed >> 32]
-    ids = [i for i in range(8) if w_op[i]]
+    ids = [i for i in range(len(w_op)) if w_op[i]]
     wl = [w_op[i] for i in ids]
     cands = []
     for t in range(p.candidates):
@@ -119,7 +119,7 @@ def test_one_generation_with_planted_tie():
         o.run(p, st, 1)
         assert list(st["cur"][0]) == list(cands[0][4])
         # every candidate credits its operators and its k (reading R1); none improves
-        want_u = np.zeros(8, np.int64)
+        want_u = np.zeros(len(st["u_op"]), np.int64)
         for c in cands:
             for op in c[3]:
                 want_u[op] += 1

@@ -172,7 +172,7 @@ def test_stagnation_resets_k_weights():
 def test_initial_weights_presets():
     for c in gold("worked_values.json")["initial_weights"]["cases"]:
         o = oracle.OracleInstance(synth.tsp_uniform(c["n"], 1))
-        assert list(o.initial_weights(c["mask"])) == c["w"]
+        assert list(o.initial_weights(c["mask"], c.get("init_w"))) == c["w"], c
 
 
 # ------------------------------------------------------------------ operators
