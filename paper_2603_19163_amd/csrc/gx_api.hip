@@ -1309,10 +1309,12 @@ class Arena {
 
 enum ReqState { RQ_PENDING, RQ_RESIDENT, RQ_FETCHING, RQ_DONE, RQ_CANCELLED };
 
+// state and cancel are read by the scheduler thread outside the server mutex
+// and written by it and by gx_server_cancel / gx_server_poll: both atomic.
 struct SrvReq {
   uint64_t ticket = 0, t_submit = 0, t_done = 0;
-  int state = RQ_PENDING;
-  bool cancel = false;
+  std::atomic<int> state{RQ_PENDING};
+  std::atomic<bool> cancel{false};
   Prepared pr;
   DevJob hj{};
   size_t inst_bytes = 0, bytes = 0, off = 0, pin_off = 0;
@@ -1446,7 +1448,8 @@ gx_status srv_stage(gx_server *S, SrvReq *r) {
   char *stage = S->pin + r->pin_off + pad16(4 * (size_t)r->n + 8);
   DevInst hh;
   DevInst *dd = nullptr;
-  gx_status st = place_instance(&S->vctx, r->pr, base, S->s, &hh, &dd, stage);
+  // the scheduler thread's own context for messages (vctx belongs to submitters)
+  gx_status st = place_instance(&S->gctx, r->pr, base, S->s, &hh, &dd, stage);
   if (st) return st;
   r->hj.inst = dd;
   carve_job(r->hj, base + r->inst_bytes, (size_t)r->n);
