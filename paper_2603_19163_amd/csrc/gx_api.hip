@@ -127,7 +127,7 @@ gx_status to_host(gx_ctx *c, const gx_instance_desc *d, const int32_t *src, size
 uint32_t encoding_ops(int kind) {
   if (kind == KKNAP) return (1u << OFLIP) | (1u << OSFLIP);
   if (kind == KCOLOR) return (1u << ORESET) | (1u << OSRESET);
-  return (1u << O2OPT) | (1u << OSWAP) | (1u << OINS) | (1u << OOROPT);
+  return (1u << O2OPT) | (1u << OSWAP) | (1u << OINS) | (1u << OOROPT) | (1u << O3OPT);
 }
 
 void free_bufs(std::vector<void *> &b) {
