@@ -220,6 +220,22 @@ gx_status gx_job_advance(gx_ctx *ctx, gx_job *job, uint32_t n_generations);
  * the encoding or a parameter out of its range above; GX_E_UNSUPPORTED when
  * the instance needs more LDS than a workgroup has. */
 gx_status gx_solve(gx_ctx *ctx, const gx_instance *inst, const gx_solve_params *p, gx_job **out);
+/* Solve without allocating: for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Runs the same solve as gx_solve (same result for the same
+ * instance and parameters) with all of its device state in a static
+ * workspace of 64 MiB that each device holds for the life of the process,
+ * and writes the best solution (n int32) to best_solution and its objective
+ * to best_objective, both caller-owned device memory.  Asynchronous on the
+ * context's stream (gx_wait(ctx, NULL) waits for it).  Every call on one
+ * device shares that device's workspace: calls must not overlap on a device
+ * (calls on one context's stream follow each other; calls from other
+ * contexts or streams of the same device race).  GX_E_UNSUPPORTED when the
+ * solve needs more than the workspace (about 4 (2 + oversample_k) P n bytes
+ * plus the instance-independent records) or int32 distances the instance
+ * does not already hold; other errors as gx_solve.  Calls no allocator. */
+gx_status gx_solve_static(gx_ctx *ctx, const gx_instance *inst, const gx_solve_params *p, int32_t *best_solution,
+                          int64_t *best_objective);
 /* Wait for everything enqueued on the context's stream (and record the
  * job's evolve time, gx_job_info.evolve_ms). */
 gx_status gx_wait(gx_ctx *ctx, gx_job *job);

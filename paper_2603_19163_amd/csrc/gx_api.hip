@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -372,6 +373,29 @@ gx_status place_instance(gx_ctx *c, Prepared &pr, char *base, hipStream_t s, Dev
 
 }  // namespace
 
+// ------------------------------------------------------------ static workspace
+// gx_solve_static keeps a whole solve's device state in this file-scope array
+// (each device holds its own copy for the life of the process).  Host code
+// never passes the array's name to a kernel or a copy: gx_create looks up the
+// array's device address once per device, with that device current, and the
+// entry point uses that address.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kMaxDevices];
+
+static hipError_t static_scratch_setup(int dev) {   // the device is current
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = (char *)ptr;
+  return hipSuccess;
+}
+
 extern "C" {
 
 gx_status gx_exp_tables(uint32_t hi[16], uint32_t lo[256]) {
@@ -442,7 +466,7 @@ gx_status gx_create(int device_ordinal, void *hip_stream, gx_ctx **out) {
   uint32_t hi[16], lo[256];
   make_exp_tables(hi, lo);
   if (gxk::set_exp_tables(hi, lo) != hipSuccess || gxk::prepare_kernel_attrs(c->max_lds) != hipSuccess ||
-      prop.warpSize != kWave) {
+      prop.warpSize != kWave || static_scratch_setup(device_ordinal) != hipSuccess) {
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return GX_E_DEVICE;
@@ -879,6 +903,45 @@ gx_status gx_solve(gx_ctx *c, const gx_instance *in, const gx_solve_params *p, g
     *out = nullptr;
   }
   return st;
+}
+
+gx_status gx_solve_static(gx_ctx *c, const gx_instance *in, const gx_solve_params *p, int32_t *best_solution,
+                          int64_t *best_objective) {
+  if (!c || !in || !p || !best_solution || !best_objective) return fail(c, GX_E_INVALID, "null argument");
+  if (p->generations == 0) return fail(c, GX_E_INVALID, "generations must be >= 1");
+  char *ws = (c->dev >= 0 && c->dev < kMaxDevices) ? g_scratch_ptr[c->dev] : nullptr;
+  if (!ws) return fail(c, GX_E_DEVICE, "static workspace address unknown on device %d", c->dev);
+  HIPCHK(c, hipSetDevice(c->dev));
+  uint32_t P_auto = 0;
+  gx_status st;
+  if (!p->population && (st = gx_autosize_population(c, in, p, &P_auto))) return st;
+  DevJob h;
+  if ((st = fill_job(c, info_of(in), p, h, P_auto, c->max_lds))) return st;
+  if (h.stage == SGLB32 && !in->h.d32)
+    return fail(c, GX_E_UNSUPPORTED, "int32 distances of coordinates would need an allocation: choose another staging");
+  const size_t n = (size_t)in->h.n;
+  const size_t rec = (sizeof(DevJob) + 255) & ~size_t(255);
+  const size_t need = rec + job_array_bytes(n, h.P, h.Q);
+  if (need > kStaticScratchBytes)
+    return fail(c, GX_E_UNSUPPORTED, "solve needs %zu bytes of workspace; the static workspace holds %zu", need,
+                kStaticScratchBytes);
+  DevJob *dj = (DevJob *)ws;
+  carve_job(h, ws + rec, n);
+  h.best_out = best_solution;
+  hipStream_t s = c->stream;
+  const bool mig = migrates(h);
+  const int kind = in->h.kind, stage = (int)h.stage;
+  HIPCHK(c, gxk::write_job(dj, h, s));
+  HIPCHK(c, gxk::init_jobs(dj, 1, h.Q, (int)n, heur_mats_of(kind), s));
+  HIPCHK(c, gxk::set_stop(dj, 1, 0, 1, s));
+  const uint32_t L = chunks_between(0, h.G, h.E);
+  for (uint32_t i = 0; i < L; ++i) {
+    HIPCHK(c, gxk::evolve_plain(dj, kind, stage, h.P, h.lds_bytes, s));
+    HIPCHK(c, gxk::epoch(dj, nullptr, 1, nullptr, 0, mig, s));
+  }
+  HIPCHK(c, gxk::fetch_best(dj, 1, s));
+  HIPCHK(c, gxk::copy_i64(best_objective, (const int64_t *)((char *)dj + offsetof(DevJob, best_out_f)), s));
+  return GX_OK;
 }
 
 gx_status gx_wait(gx_ctx *c, gx_job *j) {

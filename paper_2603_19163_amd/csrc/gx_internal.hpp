@@ -146,4 +146,6 @@ hipError_t prepare_kernel_attrs(uint32_t max_lds);
 hipError_t occupancy_plain(int kind, int stage, uint32_t lds, int *blocks_per_cu);
 hipError_t occupancy_group(int kind, int stage, uint32_t lds, int *blocks_per_cu);
 hipError_t device_check(int what, uint64_t key, const uint64_t *in, uint64_t *out, int64_t count, hipStream_t s);
+hipError_t write_job(gx::DevJob *dst, const gx::DevJob &src, hipStream_t s);
+hipError_t copy_i64(int64_t *dst, const int64_t *src, hipStream_t s);
 }  // namespace gxk

@@ -2508,8 +2508,22 @@ __global__ __launch_bounds__(64) void k_check(int what, uint64_t key, const uint
   }
 }
 
+// a job record written from the kernel argument (no host copy)
+__global__ void k_write_job(DevJob *dst, DevJob src) { *dst = src; }
+__global__ void k_copy_i64(int64_t *dst, const int64_t *src) { *dst = *src; }
+
 // ------------------------------------------------------------ launch wrappers
 namespace gxk {
+
+hipError_t write_job(DevJob *dst, const DevJob &src, hipStream_t s) {
+  hipLaunchKernelGGL(k_write_job, dim3(1), dim3(1), 0, s, dst, src);
+  return hipGetLastError();
+}
+
+hipError_t copy_i64(int64_t *dst, const int64_t *src, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_i64, dim3(1), dim3(1), 0, s, dst, src);
+  return hipGetLastError();
+}
 
 hipError_t device_check(int what, uint64_t key, const uint64_t *in, uint64_t *out, int64_t count, hipStream_t s) {
   if (count <= 0) return hipSuccess;

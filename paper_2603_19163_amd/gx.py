@@ -22,7 +22,7 @@ N_OPS = 12
 
 EXPORTED = ["gx_create", "gx_destroy", "gx_last_error", "gx_get_device_info", "gx_instance_upload",
             "gx_instance_free", "gx_autosize_population", "gx_job_create", "gx_job_advance", "gx_solve",
-            "gx_wait", "gx_poll", "gx_fetch_best", "gx_portfolio_best", "gx_job_info_get", "gx_job_stats",
+            "gx_solve_static", "gx_wait", "gx_poll", "gx_fetch_best", "gx_portfolio_best", "gx_job_info_get", "gx_job_stats",
             "gx_job_population", "gx_snapshot", "gx_snapshot_aos", "gx_job_restore", "gx_job_free",
             "gx_solve_batch", "gx_exp_tables", "gx_device_check", "gx_server_create", "gx_server_submit", "gx_server_poll",
             "gx_server_cancel", "gx_server_stats_get", "gx_server_destroy"]
@@ -128,6 +128,7 @@ def lib():
             "gx_job_create": ([vp, vp, C.POINTER(gx_solve_params), pp], i32),
             "gx_job_advance": ([vp, vp, u32], i32),
             "gx_solve": ([vp, vp, C.POINTER(gx_solve_params), pp], i32),
+            "gx_solve_static": ([vp, vp, C.POINTER(gx_solve_params), vp, vp], i32),
             "gx_wait": ([vp, vp], i32),
             "gx_poll": ([vp, vp], i32),
             "gx_fetch_best": ([vp, vp, vp, i32, C.POINTER(C.c_int64)], i32),
@@ -296,6 +297,17 @@ def gx_solve(ctx, inst, params):
     pp = _params(params)
     _check(ctx, lib().gx_solve(ctx, inst, C.byref(pp), C.byref(out)))
     return out
+
+
+def gx_solve_static(ctx, inst, params, best_solution, best_objective):
+    """Solve into caller-owned device buffers without allocating: best_solution
+    (n int32) and best_objective (one int64) are device pointers (ints) or
+    torch tensors on the context's device.  Asynchronous on the context's stream."""
+    def dptr(x):
+        return int(x.data_ptr()) if hasattr(x, "data_ptr") else int(x)
+    pp = _params(params)
+    _check(ctx, lib().gx_solve_static(ctx, inst, C.byref(pp), C.c_void_p(dptr(best_solution)),
+                                      C.c_void_p(dptr(best_objective))))
 
 
 def gx_wait(ctx, job=None):

@@ -1,0 +1,52 @@
+"""gx_solve_static (the entry point that allocates nothing: its device state
+lives in the library's static workspace) against gx_solve on the same
+requests: two calls in a row, the second smaller than the first, each equal
+to the plain solve in its best solution and objective; a solve larger than
+the workspace is refused on the host."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from paper_2603_19163_amd import gx
+
+pytestmark = pytest.mark.gpu
+
+
+def _plain(ctx, h, inst, p):
+    job = gx.gx_solve(ctx, h, p)
+    sol, f = gx.gx_fetch_best(ctx, job, inst.n)
+    gx.gx_job_free(ctx, job)
+    return sol, f
+
+
+def test_static_solves_equal_plain_solves():
+    ctx = gx.gx_create(0)
+    try:
+        reqs = [(synth.tsp_clustered(150, 3, key=61),
+                 synth.Params(seed=42, generations=120, population=48, alpha_q32=synth.alpha_q32_for(120))),
+                (synth.qap_random(18, 3, key=62),
+                 synth.Params(seed=7, generations=60, population=6, alpha_q32=synth.alpha_q32_for(60), aos_scope=1))]
+        for inst, p in reqs:                      # the second call is the smaller one
+            print(f"[static] kind {inst.kind} n={inst.n} P={p.population}", flush=True)
+            h = gx.gx_instance_upload(ctx, inst)
+            sol_d = torch.full((inst.n,), -1, dtype=torch.int32, device="cuda")
+            obj_d = torch.zeros(1, dtype=torch.int64, device="cuda")
+            torch.cuda.synchronize()
+            gx.gx_solve_static(ctx, h, p, sol_d, obj_d)
+            gx.gx_wait(ctx, None)
+            sol, f = _plain(ctx, h, inst, p)
+            assert int(obj_d.cpu()[0]) == f
+            assert np.array_equal(sol_d.cpu().numpy(), sol)
+            gx.gx_instance_free(ctx, h)
+        big = synth.tsp_uniform(2000, 1, key=63)
+        h = gx.gx_instance_upload(ctx, big)
+        sol_d = torch.zeros(big.n, dtype=torch.int32, device="cuda")
+        obj_d = torch.zeros(1, dtype=torch.int64, device="cuda")
+        with pytest.raises(gx.GxError) as e:
+            gx.gx_solve_static(ctx, h, synth.Params(seed=1, generations=10, population=2048,
+                                                    alpha_q32=synth.alpha_q32_for(10)), sol_d, obj_d)
+        assert e.value.status == gx.GX_E_UNSUPPORTED
+        gx.gx_instance_free(ctx, h)
+    finally:
+        gx.gx_destroy(ctx)
