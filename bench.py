@@ -76,25 +76,65 @@ def measured_traffic(path=os.path.join(ROOT, "profiles", "k_evolve_tsp442_traffi
         return None
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(inst, params, seconds: float):
-    """The oracle as it stands, single thread, on a bounded sample: the full
-    population of the same solve for as many generations as fit in about
-    `seconds` (after a 1-generation probe)."""
+    """The oracle as it stands on a bounded sample: the full population of
+    the same solve from its initial state for as many generations as fit in
+    about seconds / 2 on one thread, then the same generations from the same
+    state on all host threads (at most 16, the host share of one GPU), whose
+    result must equal the one-thread run's bit for bit.  `value` is the
+    all-thread rate, `single_core` the one-thread rate."""
+    import numpy as np
     import oracle
     o = oracle.OracleInstance(inst)
-    st = o.init(params)
+    st0 = o.init(params)
+
+    def copy(st):
+        return {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in st.items()}
+    probe = copy(st0)
     t = time.perf_counter()
-    o.run(params, st, 1)
+    o.run(params, probe, 1)
     t1 = time.perf_counter() - t
-    g = max(1, int(seconds / max(t1, 1e-6)) - 1)
+    g = max(1, int(seconds / 2 / max(t1, 1e-6)))
+    one = copy(st0)
     t = time.perf_counter()
-    o.run(params, st, g)
-    dt = time.perf_counter() - t
+    o.run(params, one, g)
+    dt1 = time.perf_counter() - t
+    threads = max(1, min(16, os.cpu_count() or 1))
+    many = copy(st0)
+    t = time.perf_counter()
+    o.run(params, many, g, threads=threads)
+    dtn = time.perf_counter() - t
+    same = all(np.array_equal(np.asarray(one[k]), np.asarray(many[k])) for k in one)
     evals = params.population * params.candidates * g
-    return {"value": evals / dt, "unit": "move evals/s", "cores": 1, "kind": "oracle",
+    return {"value": evals / dtn, "unit": "move evals/s", "cores": threads, "kind": "oracle",
+            "single_core": evals / dt1, "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+            "threads_equal_one_thread": bool(same),
             "sample": f"same instance and population P={params.population}, C={params.candidates}, "
-                      f"generations {1}..{1 + g} of the solve ({evals} move evals, {dt:.1f} s); "
+                      f"generations 0..{g} of the solve from its initial state ({evals} move evals), once on "
+                      f"one thread ({dt1:.1f} s) and once on {threads} threads ({dtn:.1f} s); "
                       f"full-recompute objective per candidate"}
+
+
+def bench_peaks(args):
+    """Measured device ceilings (gx_measure_peaks) beside the nominal ones."""
+    import torch
+    from paper_2603_19163_amd import gx
+    ctx = gx.gx_create(0, torch.cuda.Stream())
+    pk = gx.gx_measure_peaks(ctx)
+    gx.gx_destroy(ctx)
+    return {"metric": "device ceilings", "measured": pk,
+            "nominal": {"hbm_read_bytes_per_s": 8e12, "valu_lane_ops_per_s_1_per_clk": ALU_PEAK_GOPS * 1e9,
+                        "lds_bytes_per_s_128B_per_clk": LDS_PEAK_GBS * 1e9}}
 
 
 def main():
@@ -107,7 +147,7 @@ def main():
     ap.add_argument("--staging", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["tsp442", "batched", "served", "kinds"], default="tsp442",
+    ap.add_argument("--workload", choices=["tsp442", "batched", "served", "kinds", "peaks"], default="tsp442",
                     help="tsp442: the benchmark line; batched / served: the systems patterns; "
                          "kinds: one solve per encoding, operator set and island setting")
     ap.add_argument("--instances", type=int, default=4096, help="batched: number of instances")
@@ -154,6 +194,9 @@ def main():
         return
     if args.workload == "kinds":
         print(json.dumps(bench_kinds(args)), flush=True)
+        return
+    if args.workload == "peaks":
+        print(json.dumps(bench_peaks(args)), flush=True)
         return
 
     import torch

@@ -399,6 +399,20 @@ gx_status gx_exp_tables(uint32_t hi[16], uint32_t lo[256]);
  *                   p a 31-bit draw must stay below, or UINT64_MAX when the
  *                   move is rejected outright (T = 0 or delta / T >= 16). */
 enum { GX_CHECK_PHILOX = 1, GX_CHECK_DIST = 2, GX_CHECK_ACCEPT = 3 };
+
+/* Device ceilings the evolve kernels are measured against, each timed with
+ * HIP events on the context's stream (best of three launches after a
+ * warm-up, 8 workgroups of 256 threads per CU): random 4-byte LDS reads (64
+ * KiB per workgroup), Philox4x32-10 blocks of the per-lane form, full-rate
+ * 32-bit multiply-adds, random 4-byte reads from a 4 MiB buffer (fits the
+ * L2), and a 2 GiB read stream from HBM.  Allocates and frees its buffers;
+ * synchronises the stream. */
+typedef struct gx_peaks {
+  double lds_gather_bytes_per_s, philox_blocks_per_s, valu_lane_ops_per_s, valu_instr_per_s;
+  double l2_gather_bytes_per_s, hbm_read_bytes_per_s;
+  int32_t cus, pad_;
+} gx_peaks;
+gx_status gx_measure_peaks(gx_ctx *ctx, gx_peaks *out);
 gx_status gx_device_check(gx_ctx *ctx, int32_t what, uint64_t key, const uint64_t *in, uint64_t *out,
                           int64_t count);
 

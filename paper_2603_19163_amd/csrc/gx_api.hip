@@ -477,6 +477,14 @@ gx_status gx_create(int device_ordinal, void *hip_stream, gx_ctx **out) {
 
 const char *gx_last_error(const gx_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
+gx_status gx_measure_peaks(gx_ctx *c, gx_peaks *out) {
+  if (!c || !out) return fail(c, GX_E_INVALID, "null argument");
+  memset(out, 0, sizeof *out);
+  HIPCHK(c, hipSetDevice(c->dev));
+  HIPCHK(c, gxk::measure_peaks(c->info.cus, c->stream, out));
+  return GX_OK;
+}
+
 gx_status gx_get_device_info(gx_ctx *c, gx_device_info *out) {
   if (!c || !out) return GX_E_INVALID;
   *out = c->info;

@@ -126,8 +126,10 @@ inline uint32_t lds_bytes_for(int kind, int n, int stage) {
 
 }  // namespace gx
 
-// Launch wrappers implemented in gx_kernels.hip.
+// Launch wrappers implemented in gx_kernels.hip (measure_peaks: gx_peaks.hip).
+struct gx_peaks;
 namespace gxk {
+hipError_t measure_peaks(int cus, hipStream_t s, ::gx_peaks *out);
 hipError_t set_exp_tables(const uint32_t *hi, const uint32_t *lo);
 hipError_t build_tsp_d16_from_xy(const int32_t *xy, int n, int16_t *d16, hipStream_t s);
 hipError_t build_d32_from_xy(const int32_t *xy, int n, int32_t *d32, hipStream_t s);

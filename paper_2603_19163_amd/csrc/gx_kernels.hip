@@ -2148,8 +2148,12 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
 }  // namespace
 
 // ------------------------------------------------------------ evolve kernels
+// The TSP kernels are held to 96 VGPRs (5 waves per SIMD): their scalar state
+// exceeds the SGPR file and part of it lives in VGPR lanes; the compiler's
+// own choice (about 100 VGPRs, 4 waves) runs slower.
 template <int KIND, int STAGE>
-__global__ __launch_bounds__(kThreads<KIND>) void k_evolve(DevJob *job) {
+__global__ __launch_bounds__(kThreads<KIND>) __attribute__((amdgpu_waves_per_eu(KIND == KTSP ? 5 : 1))) void k_evolve(
+    DevJob *job) {
   evolve_wg<KIND, STAGE>(job, blockIdx.x, gx_lds);
 }
 

@@ -24,7 +24,7 @@ EXPORTED = ["gx_create", "gx_destroy", "gx_last_error", "gx_get_device_info", "g
             "gx_instance_free", "gx_autosize_population", "gx_job_create", "gx_job_advance", "gx_solve",
             "gx_solve_static", "gx_wait", "gx_poll", "gx_fetch_best", "gx_portfolio_best", "gx_job_info_get", "gx_job_stats",
             "gx_job_population", "gx_snapshot", "gx_snapshot_aos", "gx_job_restore", "gx_job_free",
-            "gx_solve_batch", "gx_exp_tables", "gx_device_check", "gx_server_create", "gx_server_submit", "gx_server_poll",
+            "gx_solve_batch", "gx_exp_tables", "gx_device_check", "gx_measure_peaks", "gx_server_create", "gx_server_submit", "gx_server_poll",
             "gx_server_cancel", "gx_server_stats_get", "gx_server_destroy"]
 
 
@@ -65,6 +65,13 @@ class gx_job_info(C.Structure):
                 ("move_evals", C.c_uint64), ("accepted", C.c_uint64),
                 ("evolve_launches", C.c_uint32), ("evolve_ms", C.c_float),
                 ("op_steps", C.c_uint64 * N_OPS), ("k_count", C.c_uint64 * 3)]
+
+
+class gx_peaks(C.Structure):
+    _fields_ = [("lds_gather_bytes_per_s", C.c_double), ("philox_blocks_per_s", C.c_double),
+                ("valu_lane_ops_per_s", C.c_double), ("valu_instr_per_s", C.c_double),
+                ("l2_gather_bytes_per_s", C.c_double), ("hbm_read_bytes_per_s", C.c_double),
+                ("cus", C.c_int32), ("pad_", C.c_int32)]
 
 
 class gx_run_stats(C.Structure):
@@ -143,6 +150,7 @@ def lib():
             "gx_solve_batch": ([vp, pp, C.POINTER(gx_solve_params), i32, pp], i32),
             "gx_exp_tables": ([C.POINTER(u32), C.POINTER(u32)], i32),
             "gx_device_check": ([vp, i32, C.c_uint64, vp, vp, C.c_int64], i32),
+            "gx_measure_peaks": ([vp, C.POINTER(gx_peaks)], i32),
             "gx_server_create": ([vp, C.POINTER(gx_server_cfg), pp], i32),
             "gx_server_submit": ([vp, C.POINTER(gx_instance_desc), C.POINTER(gx_solve_params),
                                   C.POINTER(C.c_uint64)], i32),
@@ -185,6 +193,13 @@ def gx_device_check(ctx, what: int, inputs, key: int = 0) -> np.ndarray:
     out = np.zeros((len(x), w_out), np.uint64)
     _check(ctx, lib().gx_device_check(ctx, what, key & 0xFFFFFFFFFFFFFFFF, x.ctypes.data, out.ctypes.data, len(x)))
     return out
+
+
+def gx_measure_peaks(ctx) -> dict:
+    """Measured device ceilings (include/gx.h, gx_measure_peaks)."""
+    r = gx_peaks()
+    _check(ctx, lib().gx_measure_peaks(ctx, C.byref(r)))
+    return {k: getattr(r, k) for k, _ in gx_peaks._fields_ if k != "pad_"}
 
 
 def gx_create(device: int = 0, stream=None):

@@ -85,7 +85,7 @@ def _py_layout(cls):
 def test_binding_structs_match_the_header():
     from paper_2603_19163_amd import gx
     classes = [gx.gx_instance_desc, gx.gx_solve_params, gx.gx_device_info, gx.gx_job_info,
-               gx.gx_server_cfg, gx.gx_server_stats, gx.gx_state_scalars, gx.gx_run_stats, gx.gx_sol_aos]
+               gx.gx_server_cfg, gx.gx_server_stats, gx.gx_state_scalars, gx.gx_run_stats, gx.gx_sol_aos, gx.gx_peaks]
     c = _c_layout(os.path.join(ROOT, "include", "gx.h"),
                   {k.__name__: [f for f, _ in k._fields_] for k in classes})
     for k in classes:

@@ -6,7 +6,9 @@ U[12,50], knapsack n U[100,1000], P = 4, 10 000 generations).  Every result is
 checked for properties that hold at any size (a valid solution whose
 objective, recomputed by the oracle, is the reported one); a sample is solved
 by the oracle in full and must match bit for bit."""
+import os
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -16,6 +18,20 @@ import synth
 from paper_2603_19163_amd import autotune, gx
 
 pytestmark = pytest.mark.gpu
+
+# oracle solves run side by side on the host's cores (the oracle call
+# releases the interpreter lock); at most 16, the host share of one GPU
+THREADS = max(1, min(16, os.cpu_count() or 1))
+
+
+def oracle_solves(cases):
+    """[(instance, params)] -> [(best objective, best solution)] by the oracle."""
+    def one(c):
+        o = oracle.OracleInstance(c[0]).solve(c[1])
+        fo, io = oracle.best_of(o)
+        return fo, o["best"][io].copy()
+    with ThreadPoolExecutor(THREADS) as ex:
+        return list(ex.map(one, cases))
 
 
 @pytest.fixture(scope="module")
@@ -51,14 +67,16 @@ def test_c4_full_batch(ctx):
         inst, (sol, f) = insts[k], res[k]
         assert valid(inst, sol), k
         assert oracle.OracleInstance(inst).objective(sol) == f, k
-    # sample: first, middle and last TSP instance, first and last QAP instance
-    for k in (0, 1535, 3071, 3072, 4095):
-        t = time.perf_counter()
-        o = oracle.OracleInstance(insts[k]).solve(params[k])
-        fo, io = oracle.best_of(o)
-        print(f"[fullsize] C4 instance {k} kind {insts[k].kind} n={insts[k].n}: oracle {time.perf_counter() - t:.1f} s",
-              flush=True)
-        assert res[k][1] == fo and np.array_equal(res[k][0], o["best"][io]), k
+    # a 1/16 subsample stratified by kind and size: instances ordered by
+    # (kind, n, index), every sixteenth, solved by the oracle in full
+    order = sorted(range(len(insts)), key=lambda k: (insts[k].kind, insts[k].n, k))
+    picks = order[::16]
+    t = time.perf_counter()
+    ref = oracle_solves([(insts[k], params[k]) for k in picks])
+    print(f"[fullsize] C4 {len(picks)} instances by the oracle in {time.perf_counter() - t:.1f} s "
+          f"({THREADS} threads)", flush=True)
+    for k, (fo, so) in zip(picks, ref):
+        assert res[k][1] == fo and np.array_equal(res[k][0], so), (k, insts[k].kind, insts[k].n)
 
 
 def test_c5_served_full_size(ctx):
@@ -80,17 +98,14 @@ def test_c5_served_full_size(ctx):
         sol, f = res[k][0], res[k][1]
         assert valid(inst, sol), k
         assert oracle.OracleInstance(inst).objective(sol) == f, k
-    # sample: the first request of each kind (QAP: the first with n <= 30, to
-    # bound the oracle's O(n^2) recomputation per candidate)
-    picks = {}
-    for k, (inst, _) in enumerate(reqs):
-        if inst.kind not in picks and (inst.kind != synth.QAP or inst.n <= 30):
-            picks[inst.kind] = k
-    assert len(picks) == 3
-    for kind, k in sorted(picks.items()):
-        inst, p = reqs[k]
-        t = time.perf_counter()
-        o = oracle.OracleInstance(inst).solve(p)
-        fo, io = oracle.best_of(o)
-        print(f"[fullsize] C5 request {k} kind {kind} n={inst.n}: oracle {time.perf_counter() - t:.1f} s", flush=True)
-        assert res[k][1] == fo and np.array_equal(res[k][0], o["best"][io]), k
+    # every request (TSP n up to 500, QAP n up to 50, knapsack n up to 1000)
+    # solved by the oracle in full
+    t = time.perf_counter()
+    ref = oracle_solves(reqs)
+    kinds = sorted({inst.kind for inst, _ in reqs})
+    print(f"[fullsize] C5 {len(reqs)} requests (kinds {kinds}, QAP n max "
+          f"{max(i.n for i, _ in reqs if i.kind == synth.QAP)}) by the oracle in {time.perf_counter() - t:.1f} s",
+          flush=True)
+    assert len(kinds) == 3
+    for k, (fo, so) in enumerate(ref):
+        assert res[k][1] == fo and np.array_equal(res[k][0], so), (k, reqs[k][0].kind, reqs[k][0].n)

@@ -216,7 +216,7 @@ def test_odd_epoch_and_stagnation(ctx):
     check(ctx, synth.color_planted(30, 3, key=6), p, [13, 27], "epoch 3")
 
 
-@pytest.mark.parametrize("seed", [42, 123])
+@pytest.mark.parametrize("seed", [42, 123, 456, 789, 2024])   # the paper's five seeds
 def test_c1_full_trajectory(ctx, seed):
     inst, p = synth.c1_small_tsp(0)
     p = p.with_(seed=seed)
