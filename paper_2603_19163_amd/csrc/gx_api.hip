@@ -559,8 +559,8 @@ uint32_t resolve_stage(const InstInfo &ii, uint32_t req) {
   return SGLB32;
 }
 
-uint32_t job_lds(const InstInfo &ii, uint32_t stage) {
-  uint32_t b = lds_bytes_for(ii.h.kind, ii.h.n, (int)stage);
+uint32_t job_lds(const InstInfo &ii, uint32_t stage, uint32_t op_mask) {
+  uint32_t b = lds_bytes_for(ii.h.kind, ii.h.n, evolve_variant(ii.h.kind, stage, op_mask));
   if (ii.h.kind == KCOLOR) b += (uint32_t)pad16((size_t)8 * ii.h.n_edges);
   return std::max<uint32_t>(b, 16);
 }
@@ -603,7 +603,7 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
     return fail(c, GX_E_INVALID, "per-solution weights need aos_epoch * candidates <= 2^30");
   for (int i = 0; i < kOps; ++i)
     if (p->init_weight_q16[i] > (1u << 24)) return fail(c, GX_E_INVALID, "init_weight_q16 entries <= 2^24");
-  const uint32_t lds = job_lds(ii, stage);
+  const uint32_t lds = job_lds(ii, stage, mask);
   if (lds > lds_limit)
     return fail(c, GX_E_UNSUPPORTED, "instance needs %u bytes of LDS per workgroup (limit %u)", lds, lds_limit);
   memset(&h, 0, sizeof h);
@@ -825,9 +825,10 @@ gx_status gx_autosize_population(gx_ctx *c, const gx_instance *in, const gx_solv
   if (!c || !in || !out) return fail(c, GX_E_INVALID, "null argument");
   const InstInfo ii = info_of(in);
   const uint32_t stage = resolve_stage(ii, p ? p->staging : 0);
-  const uint32_t lds = job_lds(ii, stage);
+  const uint32_t mask = p && p->op_mask ? (p->op_mask & encoding_ops(in->h.kind)) : encoding_ops(in->h.kind);
+  const uint32_t lds = job_lds(ii, stage, mask);
   int occ = 0;
-  HIPCHK(c, gxk::occupancy_plain(in->h.kind, (int)stage, lds, &occ));
+  HIPCHK(c, gxk::occupancy_plain(in->h.kind, evolve_variant(in->h.kind, stage, mask), lds, &occ));
   // every CU filled to the residency the kernel's registers and LDS allow
   occ = std::max(1, std::min(occ, 32));
   *out = (uint32_t)(c->info.cus * occ);
@@ -885,7 +886,7 @@ gx_status gx_job_advance(gx_ctx *c, gx_job *j, uint32_t ng) {
   HIPCHK(c, gxk::set_stop(j->d, 1, ng, 0, c->stream));
   HIPCHK(c, hipEventRecord(j->ev0, c->stream));
   DevJob *dj = j->d;
-  const int kind = j->inst->h.kind, stage = (int)j->h.stage;
+  const int kind = j->inst->h.kind, stage = evolve_variant(kind, j->h.stage, j->h.op_mask);
   const uint32_t P = j->h.P, lds = j->h.lds_bytes;
   const bool mig = migrates(j->h);
   hipStream_t s = c->stream;
@@ -938,7 +939,7 @@ gx_status gx_solve_static(gx_ctx *c, const gx_instance *in, const gx_solve_param
   h.best_out = best_solution;
   hipStream_t s = c->stream;
   const bool mig = migrates(h);
-  const int kind = in->h.kind, stage = (int)h.stage;
+  const int kind = in->h.kind, stage = evolve_variant(kind, h.stage, h.op_mask);
   HIPCHK(c, gxk::write_job(dj, h, s));
   HIPCHK(c, gxk::init_jobs(dj, 1, h.Q, (int)n, heur_mats_of(kind), s));
   HIPCHK(c, gxk::set_stop(dj, 1, 0, 1, s));
@@ -1252,7 +1253,8 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
     else if (ih.kind == KVRP) cost = 8.0 * n;
     cost *= (double)hj[i].C * (double)hj[i].G;
     for (uint32_t s2 = 0; s2 < hj[i].P; ++s2)
-      recs.push_back(ItemRec{ih.kind, (int)hj[i].stage, hj[i].lds_bytes, cost, make_uint2((uint32_t)i, s2)});
+      recs.push_back(ItemRec{ih.kind, evolve_variant(ih.kind, hj[i].stage, hj[i].op_mask), hj[i].lds_bytes, cost,
+                             make_uint2((uint32_t)i, s2)});
   }
   std::vector<uint2> items(n_items);
   std::vector<Group> groups;
@@ -1411,17 +1413,18 @@ struct SrvLane {
   bool wait_staged = false;
 };
 
-// lanes: (kind, staging) x LDS class
-constexpr int kLanes = 9 * kLdsClasses;
+// lanes: (kind, staging) x LDS class x 3-opt in the operator set
+constexpr int kLanes = 9 * kLdsClasses * 2;
 // epoch chunks a lane advances per quantum: the launches and the host's
 // turnaround are paid once per quantum, and a newly admitted request joins at
 // its lane's next quantum.  An epoch of TSP, knapsack or colouring takes tens
 // of microseconds, one of QAP or VRPTW several times more.
 inline int quantum_epochs(int kind) { return (kind == KQAP || kind == KVRP) ? 4 : 16; }
-int lane_of(int kind, int stage, uint32_t lds) {
+int lane_of(int kind, int var, uint32_t lds) {
+  const int stage = var & 7;
   const int ks = kind == KTSP ? std::min(std::max(stage, 1), 4) - 1
                               : (kind == KQAP ? 4 + (stage == 1) : (kind == KKNAP ? 6 : (kind == KVRP ? 7 : 8)));
-  return ks * kLdsClasses + lds_class(lds);
+  return ((var & kVarX3) ? 9 * kLdsClasses : 0) + ks * kLdsClasses + lds_class(lds);
 }
 
 }  // namespace
@@ -1618,7 +1621,8 @@ void server_loop(gx_server *S) {
       recs.clear();
       for (SrvReq *r : act)
         for (uint32_t sl = 0; sl < r->hj.P; ++sl)
-          recs.push_back(ItemRec{r->kind, (int)r->hj.stage, r->hj.lds_bytes, r->cost, make_uint2((uint32_t)r->slot, sl)});
+          recs.push_back(ItemRec{r->kind, evolve_variant(r->kind, r->hj.stage, r->hj.op_mask), r->hj.lds_bytes, r->cost,
+                                 make_uint2((uint32_t)r->slot, sl)});
       if (make_groups(&S->gctx, recs, L.items_h[b], groups) != GX_OK || groups.size() != 1) continue;
       for (size_t a = 0; a < act.size(); ++a) L.slots_h[b][a] = (uint32_t)act[a]->slot;
       if (L.wait_staged) {
@@ -1794,7 +1798,7 @@ gx_status gx_server_submit(gx_server *S, const gx_instance_desc *d, const gx_sol
   const double n = r->n;
   r->cost = (r->pr.h.kind == KQAP ? 4.0 * n * n / 3.0 : (r->pr.h.kind == KVRP ? 8.0 * n : n)) * r->hj.C;
   r->kind = r->pr.h.kind;
-  r->lane = lane_of(r->kind, (int)r->hj.stage, r->hj.lds_bytes);
+  r->lane = lane_of(r->kind, evolve_variant(r->kind, r->hj.stage, r->hj.op_mask), r->hj.lds_bytes);
   if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
     delete r;
     return GX_E_DEVICE;

@@ -27,6 +27,14 @@ enum Op : int32_t { O2OPT = 0, OSWAP = 1, OINS = 2, OOROPT = 3, O3OPT = 4, OFLIP
                     OSRESET = 11 };
 constexpr int kPermOps = 5;
 enum Stage : int32_t { SAUTO = 0, SLDS16 = 1, SLDSXY = 2, SGLB16 = 3, SGLB32 = 4 };
+// Evolve-kernel variant: the staging, plus kVarX3 when a permutation job's
+// operator set holds 3-opt (its loops are compiled apart from the others, so
+// that jobs without it carry none of its branches or wider counters).
+constexpr int kVarX3 = 8;
+inline int evolve_variant(int kind, uint32_t stage, uint32_t op_mask) {
+  const bool perm = kind == KTSP || kind == KQAP || kind == KVRP;
+  return (int)stage | ((perm && (op_mask & (1u << O3OPT))) ? kVarX3 : 0);
+}
 
 // One uploaded instance.  All pointers are device pointers owned by the instance.
 struct DevInst {
@@ -98,12 +106,14 @@ struct DevJob {
 // ones through a second tour buffer.
 constexpr int kOneBufferN = 1536;
 
-// LDS bytes one evolve workgroup needs for this instance and staging: the
-// candidate tables (4736 bytes) followed by the solution and instance data.
-constexpr uint32_t kTables = 4736;
-inline uint32_t lds_bytes_for(int kind, int n, int stage) {
+// LDS bytes one evolve workgroup needs for this instance and kernel variant:
+// the candidate tables (3968 bytes, or 4736 with the block lengths of 3-opt
+// steps) followed by the solution and instance data.
+constexpr uint32_t kTables = 3968, kTablesX3 = 4736;
+inline uint32_t lds_bytes_for(int kind, int n, int var) {
   auto al = [](uint32_t b) { return (b + 15u) & ~15u; };
-  const uint32_t un = (uint32_t)n, tables = kTables;
+  const int stage = var & 7;
+  const uint32_t un = (uint32_t)n, tables = (var & kVarX3) ? kTablesX3 : kTables;
   const uint32_t tours = (n <= kOneBufferN ? 1 : 2) * al(2 * un);
   switch (kind) {
     case KTSP: {

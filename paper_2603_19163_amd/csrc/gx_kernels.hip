@@ -94,11 +94,14 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
 }
 
 // Wave-uniform parameters of one job.
+// The roulettes use cumulative weights: cw[i] = sum of the first i + 1
+// weights of the encoding's operators, sw their total; ck[i] the same for
+// the K-step weights, swk their total.
 struct Uni {
   uint32_t n, C, key, k0, k1, credit, alpha;
   int32_t lb, ub;
-  uint32_t w[kOps], sw;
-  uint32_t wk[3], swk;
+  uint32_t cw[4], sw;
+  uint32_t ck[2], swk;
 };
 
 struct Step {
@@ -114,14 +117,15 @@ __device__ __forceinline__ int pick_op(uint32_t u16, const Uni &U) {
   const uint32_t u = (uint32_t)(((uint64_t)u16 * U.sw) >> 16);
   if (ENC != 0) {
     constexpr int lo = ENC == 1 ? OFLIP : ORESET;
-    return lo + (U.w[lo] <= u);
+    return lo + (U.cw[0] <= u);
   }
-  uint32_t c = U.w[0];
-  int r = (c <= u);
-  c += U.w[1]; r += (c <= u);
-  c += U.w[2]; r += (c <= u);
-  c += U.w[3]; r += (c <= u);
-  return r;
+  return (U.cw[0] <= u) + (U.cw[1] <= u) + (U.cw[2] <= u) + (U.cw[3] <= u);
+}
+
+// k in {1, 2, 3} from the high 16 bits of a draw
+__device__ __forceinline__ int pick_k(uint32_t w0, const Uni &U) {
+  const uint32_t u = (uint32_t)(((uint64_t)(w0 >> 16) * U.swk) >> 16);
+  return 1 + (U.ck[0] <= u) + (U.ck[1] <= u);
 }
 
 // first operator id of an encoding
@@ -131,8 +135,9 @@ constexpr int enc_lo() { return ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET); }
 template <int ENC>
 constexpr int enc_hi() { return ENC == 0 ? O3OPT : enc_lo<ENC>() + 1; }
 
-// ENC: 0 permutation, 1 binary, 2 integer
-template <int ENC>
+// ENC: 0 permutation, 1 binary, 2 integer; X3: the operator set holds 3-opt
+// (the loops without it are compiled without its branches)
+template <int ENC, bool X3>
 __device__ __forceinline__ Step make_step(int op, uint32_t r1, uint32_t r2, uint32_t r3, const Uni &U) {
   Step s;
   s.op = op;
@@ -152,7 +157,7 @@ __device__ __forceinline__ Step make_step(int op, uint32_t r1, uint32_t r2, uint
     s.a = (int)(rv ? min(i, j) : i);
     s.b = (int)(rv ? max(i, j) : j);
     s.c = (int)L;
-    if (op == O3OPT) {
+    if (X3 && op == O3OPT) {
       const uint32_t c1 = rmap(r1, n + 1);
       uint32_t c2 = rmap(r2, n);
       c2 += (c2 >= c1);
@@ -180,20 +185,19 @@ __device__ __forceinline__ Step make_step(int op, uint32_t r1, uint32_t r2, uint
 
 // Sample candidate t of generation g (Alg. 1: k from w_K, then k operators
 // from the operator weights).  Returns k.
-template <int ENC>
+template <int ENC, bool X3>
 __device__ __forceinline__ int sample(const Uni &U, uint32_t g, uint32_t sol, uint32_t t, Step st[3]) {
   uint32_t r[4];
   philox(g, sol, t << 2, U.key, U.k0, U.k1, r);
-  const uint32_t u = (uint32_t)(((uint64_t)(r[0] >> 16) * U.swk) >> 16);
-  const int k = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
-  st[0] = make_step<ENC>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+  const int k = pick_k(r[0], U);
+  st[0] = make_step<ENC, X3>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
   if (k > 1) {
     philox(g, sol, (t << 2) | 1u, U.key, U.k0, U.k1, r);
-    st[1] = make_step<ENC>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+    st[1] = make_step<ENC, X3>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
   }
   if (k > 2) {
     philox(g, sol, (t << 2) | 2u, U.key, U.k0, U.k1, r);
-    st[2] = make_step<ENC>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+    st[2] = make_step<ENC, X3>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
   }
   return k;
 }
@@ -617,8 +621,11 @@ struct ColorK {
 // atomics.  Draws, moves and deltas are those of the per-candidate
 // formulation; only the order of evaluation differs.
 constexpr int kChunk = 128;
-constexpr uint32_t kTspScratch = kChunk * 3 * 4 + kChunk * 4 + kChunk * 6 * 2 + kChunk * 3 + kChunk * 3 * 2;
-static_assert(kTspScratch == kTables, "lds_bytes_for() reserves kTables bytes of candidate tables");
+// tables (positions, deltas, pattern list, operator bytes), then for 3-opt
+// variants the block lengths of the steps
+constexpr uint32_t kTspScratch = kChunk * 3 * 4 + kChunk * 4 + kChunk * 6 * 2 + kChunk * 3;
+static_assert(kTspScratch == kTables && kTables + kChunk * 3 * 2 == kTablesX3,
+              "lds_bytes_for() reserves the candidate tables");
 // The pattern list holds at most 2 x 2 entries per candidate of a chunk
 // (steps 2 and 3, two patterns each): 1024 bytes from offset 2048; the rest of
 // its 1536 bytes, up to the operator table at 3584, is free on the TSP path
@@ -681,21 +688,22 @@ __device__ __forceinline__ int sapply(const SMap &M, int p) {
   return in ? t + off : p;
 }
 
+template <bool X3>
 __device__ __forceinline__ void unpack_step(const TspScratch &W, int t, int m, int &op, int &a, int &b, int &L) {
   const uint32_t ab = W.sab()[3 * t + m];
   const uint32_t ol = W.sop()[3 * t + m];
   a = (int)(ab & 0xFFFFu);
   b = (int)(ab >> 16);
   op = (int)(ol & 7u);
-  L = op == O3OPT ? (int)W.sl()[3 * t + m] : (int)((ol >> 3) & 7u);
+  L = (X3 && op == O3OPT) ? (int)W.sl()[3 * t + m] : (int)((ol >> 3) & 7u);
 }
 
 // a step into the tables (the operator relative to its encoding's first id)
-template <int ENC>
+template <int ENC, bool X3>
 __device__ __forceinline__ void store_step(const TspScratch &W, uint32_t idx, const Step &st, uint32_t kbits) {
   W.sab()[idx] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
   W.sop()[idx] = (uint8_t)((st.op - enc_lo<ENC>()) | ((st.c & 7) << 3) | kbits);
-  if (ENC == 0 && st.op == O3OPT) W.sl()[idx] = (uint16_t)st.c;
+  if (X3 && ENC == 0 && st.op == O3OPT) W.sl()[idx] = (uint16_t)st.c;
 }
 
 // Draw the composite moves of candidates [c0, c0 + cn): the first step of
@@ -703,7 +711,7 @@ __device__ __forceinline__ void store_step(const TspScratch &W, uint32_t idx, co
 // of the candidates with k >= 2 and k >= 3 compacted onto consecutive lanes,
 // so that the wave computes about as many Philox blocks as there are steps.
 // Steps land in the LDS tables; kk[r] receives k of the lane's candidates.
-template <int ENC, int RN = 2>
+template <int ENC, bool X3, int RN = 2>
 __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, uint32_t g, uint32_t sol, uint32_t c0,
                                            uint32_t cn, int kk[RN], uint32_t rb = 0) {
   // rounds rb .. rb + RN - 1 of the chunk (64 candidates each) on this wave;
@@ -717,10 +725,9 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
     if (tl < cn) {
       uint32_t w[4];
       philox_lane(g, sol, (c0 + tl) << 2, U.key, U.k0, U.k1, w);
-      const uint32_t u = (uint32_t)(((uint64_t)(w[0] >> 16) * U.swk) >> 16);
-      kk[rr] = 1 + (U.wk[0] <= u) + (U.wk[0] + U.wk[1] <= u);
-      const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
-      store_step<ENC>(W, 3 * tl, st, (uint32_t)kk[rr] << 6);
+      kk[rr] = pick_k(w[0], U);
+      const Step st = make_step<ENC, X3>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
+      store_step<ENC, X3>(W, 3 * tl, st, (uint32_t)kk[rr] << 6);
       if constexpr (RN == 2) W.del()[tl] = 0;
     }
   }
@@ -739,14 +746,14 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
     const uint32_t e = dl[j], tl = e & 0xFFu, m = e >> 8;
     uint32_t w[4];
     philox_lane(g, sol, ((c0 + tl) << 2) | m, U.key, U.k0, U.k1, w);
-    const Step st = make_step<ENC>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
-    store_step<ENC>(W, 3 * tl + m, st, 0u);
+    const Step st = make_step<ENC, X3>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
+    store_step<ENC, X3>(W, 3 * tl + m, st, 0u);
   }
   __syncthreads();
 }
 
 // step m of candidate t from the tables (integer values are stored as int16)
-template <int ENC>
+template <int ENC, bool X3>
 __device__ __forceinline__ Step load_step(const TspScratch &W, int t, int m) {
   const uint32_t ab = W.sab()[3 * t + m];
   const uint32_t ol = W.sop()[3 * t + m];
@@ -754,18 +761,18 @@ __device__ __forceinline__ Step load_step(const TspScratch &W, int t, int m) {
   st.a = (int)(ab & 0xFFFFu);
   st.b = ENC == 2 ? (int)(int16_t)(ab >> 16) : (int)(ab >> 16);
   st.op = (int)(ol & 7u) + enc_lo<ENC>();
-  st.c = (ENC == 0 && st.op == O3OPT) ? (int)W.sl()[3 * t + m] : (int)((ol >> 3) & 7u);
+  st.c = (X3 && ENC == 0 && st.op == O3OPT) ? (int)W.sl()[3 * t + m] : (int)((ol >> 3) & 7u);
   return st;
 }
 
 // delta of pattern step `sub` of operator m of candidate t, on the tour after
 // all earlier steps of that candidate (MAPPED: m >= 1, whose read positions
 // are mapped back through steps m-1 .. 0)
-template <bool MAPPED, class DF>
+template <bool MAPPED, bool X3, class DF>
 __device__ __forceinline__ int pattern_delta(const TspScratch &W, const uint16_t *tour, int n, const DF &D,
                                              int t, int m, int sub) {
   int op, a, b, L;
-  unpack_step(W, t, m, op, a, b, L);
+  unpack_step<X3>(W, t, m, op, a, b, L);
   // Every pattern reads the tour at (X-1, X, r2, r3, Z-1, Z): a block move
   // cuts before X = min(i, q), before B and before Z = max(i, q) + L, with
   // B = i (q < i) or i + L (q > i), so (r2, r3) = (B-1, B); a reversal of
@@ -789,7 +796,7 @@ __device__ __forceinline__ int pattern_delta(const TspScratch &W, const uint16_t
   if (MAPPED) {
     for (int mm = m - 1; mm >= 0; --mm) {
       int o2, a2, b2, L2;
-      unpack_step(W, t, mm, o2, a2, b2, L2);
+      unpack_step<X3>(W, t, mm, o2, a2, b2, L2);
       const SMap M = smap(o2, a2, b2, L2);
 #pragma unroll
       for (int i = 0; i < 6; ++i) r[i] = sapply(M, r[i]);
@@ -826,11 +833,11 @@ __device__ __forceinline__ void edges_fill(uint16_t *el, const uint16_t *tour, i
 //                  u = (X-1, B, B-1, Z-1, X, Z), pairs 0, 1 (as (u2,u5)) and 2,
 //                  removed edges X-1, B-1, Z-1.
 // Zero patterns as in pattern_delta.
-template <class DF>
+template <bool X3, class DF>
 __device__ __forceinline__ int first_step_delta(const TspScratch &W, const uint16_t *tour, const uint16_t *el, int n,
                                                 const DF &D, int t) {
   int op, a, b, L;
-  unpack_step(W, t, 0, op, a, b, L);
+  unpack_step<X3>(W, t, 0, op, a, b, L);
   const bool mv = op >= OINS;
   const bool adj = op == OSWAP && b - a == 1;
   const bool cyc = op == OSWAP && !adj && a == 0 && b == n - 1;
@@ -894,7 +901,17 @@ __device__ __forceinline__ void fold_op_counts(uint32_t *u, uint32_t *v, uint64_
   if (fields > 4) fold_byte_counts(u + 4, v + 4, (uint32_t)(cu >> 32), (uint32_t)(cv >> 32), fields - 4);
 }
 
-template <class DF>
+// Per-lane operator counters: four byte fields in 32 bits, or with 3-opt five
+// in 64 bits.
+template <bool X3>
+using OpCount = typename std::conditional<X3, uint64_t, uint32_t>::type;
+template <bool X3>
+__device__ __forceinline__ void fold_ops(uint32_t *u, uint32_t *v, OpCount<X3> cu, OpCount<X3> cv, int fields) {
+  if constexpr (X3) fold_op_counts(u, v, cu, cv, fields);
+  else fold_byte_counts(u, v, cu, cv, fields < 4 ? fields : 4);
+}
+
+template <bool X3, class DF>
 __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *el, int n, const DF &D, const TspScratch &W,
                                         const Uni &U, int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1,
                                         uint64_t &T, int64_t &f, int64_t &bf, LStats &S, uint32_t &nacc) {
@@ -903,7 +920,8 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
   // in byte fields (operator o at bits 8o, k at bits 8(k-1)); a chunk of
   // candidates adds at most 6 to a field of a lane, so the fields are folded
   // into the wave-wide counts of S every 42 chunks and at the end.
-  uint64_t cu_op = 0, cv_op = 0;
+  constexpr int kNops = X3 ? kPermOps : 4;
+  OpCount<X3> cu_op = 0, cv_op = 0;
   uint32_t cu_k = 0, cv_k = 0, since_fold = 0;
   // The wave-wide counts live in the unused tail of the pattern-list table
   // during the run (fewer scalar registers held across the generation loop)
@@ -923,13 +941,13 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
     for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
       const uint32_t cn = min((uint32_t)kChunk, U.C - c0);
       int kk[2];
-      draw_chunk<0>(W, U, g, sol, c0, cn, kk);
+      draw_chunk<0, X3>(W, U, g, sol, c0, cn, kk);
       // ---- first steps: one per candidate, on its own lane
       int d0[2];
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const uint32_t tl = r * kWave + lane;
-        d0[r] = (tl < cn && n >= 2) ? first_step_delta(W, cur, el, n, D, (int)tl) : 0;
+        d0[r] = (tl < cn && n >= 2) ? first_step_delta<X3>(W, cur, el, n, D, (int)tl) : 0;
       }
       // ---- later steps of k >= 2 candidates: (candidate, step, pattern)
       // entries, grouped by step, evaluated through the position maps
@@ -945,7 +963,7 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
             bool need = kk[r] > m;
             if (need && sub) {
               int op, a, b, L;
-              unpack_step(W, (int)tl, m, op, a, b, L);
+              unpack_step<X3>(W, (int)tl, m, op, a, b, L);
               need = n_patterns(op, a, b) == 2;
             }
             const unsigned long long mk = __ballot(need);
@@ -957,7 +975,7 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
       if (n >= 2) {
         for (uint32_t j = lane; j < nq; j += kWave) {
           const uint32_t e = W.lst()[j];
-          const int d = pattern_delta<true>(W, cur, n, D, (int)(e & 0xFFu), (int)((e >> 8) & 3u), (int)(e >> 10));
+          const int d = pattern_delta<true, X3>(W, cur, n, D, (int)(e & 0xFFu), (int)((e >> 8) & 3u), (int)(e >> 10));
           if (d) atomicAdd(&W.del()[e & 0xFFu], d);
         }
       }
@@ -972,9 +990,9 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
           const bool imp = d < 0;
 #pragma unroll
           for (int m = 0; m < 3; ++m) {
-            const uint64_t inc = kk[r] > m ? 1ull << ((W.sop()[3 * tl + m] & 7u) << 3) : 0ull;
+            const OpCount<X3> inc = kk[r] > m ? (OpCount<X3>)1 << ((W.sop()[3 * tl + m] & 7u) << 3) : (OpCount<X3>)0;
             cu_op += inc;
-            cv_op += imp ? inc : 0ull;
+            cv_op += imp ? inc : (OpCount<X3>)0;
           }
           const uint32_t inck = 1u << ((kk[r] - 1) << 3);
           cu_k += inck;
@@ -986,7 +1004,7 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
         }
       }
       if (++since_fold == 42) {
-        fold_op_counts(SL.u, SL.v, cu_op, cv_op, kPermOps);
+        fold_ops<X3>(SL.u, SL.v, cu_op, cv_op, kNops);
         fold_byte_counts(SL.uk, SL.vk, cu_k, cv_k, 3);
         cu_op = cv_op = 0;
         cu_k = cv_k = 0;
@@ -1007,17 +1025,17 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
       if (ts >= c_last) {
         const int tl = (int)(ts - c_last);
         k = (int)(W.sop()[3 * tl] >> 6);
-        st[0] = load_step<0>(W, tl, 0);
-        st[1] = load_step<0>(W, tl, 1);
-        st[2] = load_step<0>(W, tl, 2);
+        st[0] = load_step<0, X3>(W, tl, 0);
+        st[1] = load_step<0, X3>(W, tl, 1);
+        st[2] = load_step<0, X3>(W, tl, 2);
       } else {
-        k = sample<0>(U, g, sol, ts, st);
+        k = sample<0, X3>(U, g, sol, ts, st);
       }
       if (U.credit == 1) {   // wave-uniform counts on this path
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
-          for (int o = 0; o < kPermOps; ++o) {
+          for (int o = 0; o < kNops; ++o) {
             const uint32_t hit = m < k && st[m].op == o;
             SL.u[o] += hit;
             SL.v[o] += hit & (uint32_t)(ds < 0);
@@ -1046,11 +1064,11 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
     }
     T = cool(T, U.alpha);
   }
-  fold_op_counts(SL.u, SL.v, cu_op, cv_op, kPermOps);
+  fold_ops<X3>(SL.u, SL.v, cu_op, cv_op, kNops);
   fold_byte_counts(SL.uk, SL.vk, cu_k, cv_k, 3);
   wave_sync();
 #pragma unroll
-  for (int o = 0; o < kPermOps; ++o) {
+  for (int o = 0; o < kNops; ++o) {
     S.u[o] += SL.u[o];
     S.v[o] += SL.v[o];
   }
@@ -1228,6 +1246,7 @@ struct QapK {
   // entries processed together belong to candidates with similar pair
   // counts; a round with more entries than the list holds is processed in
   // windows of whole candidates.
+  template <bool X3>
   __device__ __forceinline__ int64_t delta_round(const TspScratch &W, int tl, int k) const {
     const uint32_t l = lane_id();
     uint32_t *tmp = (uint32_t *)dsum;
@@ -1236,7 +1255,7 @@ struct QapK {
     {
       Step st[3];
 #pragma unroll
-      for (int m = 0; m < 3; ++m) st[m] = load_step<ENC>(W, tl, m);
+      for (int m = 0; m < 3; ++m) st[m] = load_step<ENC, X3>(W, tl, m);
 #pragma unroll
       for (int m = 0; m < 3; ++m) {
         SMap M = smap(st[m].op, st[m].a, st[m].b, st[m].c);
@@ -1360,56 +1379,56 @@ struct QapK {
 
 // Byte-field counts of one lane: operator o (relative to the encoding's first
 // operator) at bits 8o of cu/cv, k at bits 8(k-1) of cuk/cvk.
-template <int ENC>
-__device__ __forceinline__ void credit_bytes(uint64_t &cu, uint64_t &cv, uint32_t &cuk, uint32_t &cvk, const Step *st,
-                                             int k, bool imp) {
+template <int ENC, bool X3>
+__device__ __forceinline__ void credit_bytes(OpCount<X3> &cu, OpCount<X3> &cv, uint32_t &cuk, uint32_t &cvk,
+                                             const Step *st, int k, bool imp) {
   constexpr int lo = enc_lo<ENC>();
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    const uint64_t inc = m < k ? 1ull << ((st[m].op - lo) << 3) : 0ull;
+    const OpCount<X3> inc = m < k ? (OpCount<X3>)1 << ((st[m].op - lo) << 3) : (OpCount<X3>)0;
     cu += inc;
-    cv += imp ? inc : 0ull;
+    cv += imp ? inc : (OpCount<X3>)0;
   }
   const uint32_t inck = 1u << ((k - 1) << 3);
   cuk += inck;
   cvk += imp ? inck : 0u;
 }
 
-template <class KD>
+template <bool X3, class KD>
 __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni &U, int32_t *best_row, uint32_t sol,
                                          uint32_t g0, uint32_t g1, uint64_t &T, int64_t &f, int64_t &bf, LStats &S,
                                          uint32_t &nacc) {
   constexpr int ENC = KD::ENC;
   constexpr int lo = enc_lo<ENC>();
-  constexpr int nf = enc_hi<ENC>() - lo + 1;
+  constexpr int nf = ENC == 0 ? (X3 ? kPermOps : 4) : 2;
   const uint32_t lane = lane_id();
   // per-lane byte counts (a chunk adds at most 6 to a field of a lane),
   // folded into the wave-uniform counts of S every 42 chunks and at the end
-  uint64_t cu = 0, cv = 0;
+  OpCount<X3> cu = 0, cv = 0;
   uint32_t cuk = 0, cvk = 0, since_fold = 0;
   for (uint32_t g = g0; g < g1; ++g) {
     unsigned long long bk = ~0ull;
     for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
       const uint32_t cn = min((uint32_t)kChunk, U.C - c0);
       int kk[2];
-      draw_chunk<ENC>(W, U, g, sol, c0, cn, kk);
+      draw_chunk<ENC, X3>(W, U, g, sol, c0, cn, kk);
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const uint32_t tl = r * kWave + lane;
         const bool valid = tl < cn;
         if (valid) {
           Step st[3];
-          st[0] = load_step<ENC>(W, (int)tl, 0);
-          st[1] = kk[r] > 1 ? load_step<ENC>(W, (int)tl, 1) : st[0];
-          st[2] = kk[r] > 2 ? load_step<ENC>(W, (int)tl, 2) : st[0];
+          st[0] = load_step<ENC, X3>(W, (int)tl, 0);
+          st[1] = kk[r] > 1 ? load_step<ENC, X3>(W, (int)tl, 1) : st[0];
+          st[2] = kk[r] > 2 ? load_step<ENC, X3>(W, (int)tl, 2) : st[0];
           const int64_t d = kd.delta(st, kk[r], f);
-          if (U.credit == 0) credit_bytes<ENC>(cu, cv, cuk, cvk, st, kk[r], d < 0);
+          if (U.credit == 0) credit_bytes<ENC, X3>(cu, cv, cuk, cvk, st, kk[r], d < 0);
           const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | (c0 + tl);
           bk = key < bk ? key : bk;
         }
       }
       if (++since_fold == 42) {
-        fold_op_counts(S.u + lo, S.v + lo, cu, cv, nf);
+        fold_ops<X3>(S.u + lo, S.v + lo, cu, cv, nf);
         fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
         cu = cv = 0;
         cuk = cvk = 0;
@@ -1424,7 +1443,7 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
     if (!acc) acc = accept_worse(ds, T, g, sol, U);
     if (acc) {
       Step st[3];
-      const int k = sample<ENC>(U, g, sol, ts, st);
+      const int k = sample<ENC, X3>(U, g, sol, ts, st);
       if (U.credit == 1) credit<ENC>(S, st, k, ds < 0);   // the same on every lane
       kd.apply(st, k);
       f += ds;
@@ -1436,7 +1455,7 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
     }
     T = cool(T, U.alpha);
   }
-  fold_op_counts(S.u + lo, S.v + lo, cu, cv, nf);
+  fold_ops<X3>(S.u + lo, S.v + lo, cu, cv, nf);
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
 
@@ -1446,38 +1465,39 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
 // the same on both (the move's shared state is written by wave 0 or
 // identically by both).  Each wave counts its own candidates; the accepted
 // count is wave 0's.
-template <class KD>
+template <bool X3, class KD>
 __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Uni &U, int32_t *best_row, uint32_t sol,
                                            uint32_t g0, uint32_t g1, uint64_t &T, int64_t &f, int64_t &bf, LStats &S,
                                            uint32_t &nacc, unsigned long long *xk) {
   constexpr int ENC = KD::ENC;
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
-  uint64_t cu = 0, cv = 0;
+  constexpr int nf = X3 ? kPermOps : 4;
+  OpCount<X3> cu = 0, cv = 0;
   uint32_t cuk = 0, cvk = 0, since_fold = 0;
   for (uint32_t g = g0; g < g1; ++g) {
     unsigned long long bk = ~0ull;
     for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
       const uint32_t cn = min((uint32_t)kChunk, U.C - c0);
       int kk[1];
-      draw_chunk<ENC, 1>(W, U, g, sol, c0, cn, kk, wv);
+      draw_chunk<ENC, X3, 1>(W, U, g, sol, c0, cn, kk, wv);
       const uint32_t tl = wv * kWave + lane;
       const bool valid = tl < cn;
       if (__ballot(valid)) {
         const int k = valid ? kk[0] : 0;
-        const int64_t d = kd.delta_round(W, (int)tl, k);
+        const int64_t d = kd.template delta_round<X3>(W, (int)tl, k);
         if (valid) {
           if (U.credit == 0) {   // the steps again from the tables: fewer registers live across the round
             Step st[3];
 #pragma unroll
             for (int m = 0; m < 3; ++m) st[m].op = (int)(W.sop()[3 * tl + m] & 7u);
-            credit_bytes<ENC>(cu, cv, cuk, cvk, st, k, d < 0);
+            credit_bytes<ENC, X3>(cu, cv, cuk, cvk, st, k, d < 0);
           }
           const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | (c0 + tl);
           bk = key < bk ? key : bk;
         }
       }
       if (++since_fold == 84) {   // one candidate per lane per chunk: at most 3 per field
-        fold_op_counts(S.u, S.v, cu, cv, kPermOps);
+        fold_ops<X3>(S.u, S.v, cu, cv, nf);
         fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
         cu = cv = 0;
         cuk = cvk = 0;
@@ -1494,7 +1514,7 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
     if (!acc) acc = accept_worse(ds, T, g, sol, U);
     if (acc) {
       Step st[3];
-      const int k = sample<ENC>(U, g, sol, ts, st);
+      const int k = sample<ENC, X3>(U, g, sol, ts, st);
       if (U.credit == 1 && wv == 0) credit<ENC>(S, st, k, ds < 0);   // the same on every lane of wave 0
       kd.apply(st, k);
       f += ds;
@@ -1506,7 +1526,7 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
     }
     T = cool(T, U.alpha);
   }
-  fold_op_counts(S.u, S.v, cu, cv, kPermOps);
+  fold_ops<X3>(S.u, S.v, cu, cv, nf);
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
 
@@ -1993,8 +2013,10 @@ __device__ __forceinline__ void solution_aos_close(DevJob *J, uint32_t sol, LSta
 }
 
 // ------------------------------------------------------------ one workgroup
-template <int KIND, int STAGE>
+template <int KIND, int VAR>
 __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
+  constexpr int STAGE = VAR & 7;
+  constexpr bool x3 = (VAR & kVarX3) != 0;   // 3-opt in the operator set
   const uint32_t g0 = uni(J->g), gstop = uni(J->g_stop);
   if (g0 >= gstop) return;
   const uint32_t E = J->E;
@@ -2015,18 +2037,20 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
   const bool sol_scope = J->aos_scope != 0;
   const uint32_t *wsrc = sol_scope ? J->saos[sol].w_op : J->w_op;
   const uint32_t *wksrc = sol_scope ? J->saos[sol].w_k : J->w_k;
-  U.sw = 0;
+  // cumulative weights of the encoding's operators (the others weigh 0)
+  constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : 0);
+  constexpr int lo = enc_lo<ENC>();
+  uint32_t c = 0;
 #pragma unroll
-  for (int i = 0; i < kOps; ++i) {
-    U.w[i] = wsrc[i];
-    U.sw += U.w[i];
+  for (int i = 0; i < 4; ++i) {
+    if (lo + i <= enc_hi<ENC>()) c += wsrc[lo + i];
+    U.cw[i] = c;
   }
-  U.swk = 0;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    U.wk[i] = wksrc[i];
-    U.swk += U.wk[i];
-  }
+  U.sw = c + (ENC == 0 ? wsrc[O3OPT] : 0u);
+  U.ck[0] = wksrc[0];
+  U.ck[1] = wksrc[0] + wksrc[1];
+  U.swk = U.ck[1] + wksrc[2];
+
   uint64_t T = J->T;
   int64_t f = J->cur_f[sol], bf = J->best_f[sol];
   LStats S = {};
@@ -2036,7 +2060,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
   int32_t *best_row = J->best + (size_t)sol * n;
   // LDS: candidate tables first, then the solution and the instance data
   const TspScratch W;
-  char *const base = lds + kTspScratch;
+  char *const base = lds + (x3 ? kTablesX3 : kTables);
 
   if constexpr (KIND == KTSP || KIND == KQAP || KIND == KVRP) {
     // one tour buffer; the move application writes through the candidate
@@ -2049,19 +2073,23 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       if constexpr (STAGE == SLDS16) {
         stage16(rest, I->d16, 2u * n * n);
         __syncthreads();
-        tsp_run(t0, t1, nullptr, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        if constexpr (x3) tsp_run<true>(t0, t1, nullptr, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        else tsp_run<false>(t0, t1, nullptr, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       } else if constexpr (STAGE == SLDSXY) {
         short2 *xy = (short2 *)rest;
         uint16_t *el = (uint16_t *)(rest + al16(4 * n));
         for (int p = lane; p < n; p += kWave) xy[p] = make_short2((short)I->xy[2 * p], (short)I->xy[2 * p + 1]);
         __syncthreads();
-        tsp_run(t0, t1, el, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        if constexpr (x3) tsp_run<true>(t0, t1, el, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        else tsp_run<false>(t0, t1, el, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       } else if constexpr (STAGE == SGLB16) {
         __syncthreads();
-        tsp_run(t0, t1, nullptr, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        if constexpr (x3) tsp_run<true>(t0, t1, nullptr, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        else tsp_run<false>(t0, t1, nullptr, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       } else {
         __syncthreads();
-        tsp_run(t0, t1, nullptr, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        if constexpr (x3) tsp_run<true>(t0, t1, nullptr, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        else tsp_run<false>(t0, t1, nullptr, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       }
       perm_store(t0, n, cur_g);
     } else if constexpr (KIND == KQAP) {
@@ -2089,7 +2117,8 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
                   I->qap_sums32 != 0};
       __syncthreads();
       kd.setup(I->qf);
-      round_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk);
+      if constexpr (x3) round_gens<true>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk);
+      else round_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk);
       if (wv == 0) perm_store(kd.cur, n, cur_g);
     } else {
       const int dn = n + 1;
@@ -2103,7 +2132,8 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       stage16(due, I->due, 4u * dn);
       __syncthreads();
       VrpK kd{t0, t1, n, dn, I->capacity, I->vehicles, I->service, I->horizon, D, dem, rdy, due, I};
-      run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+      if constexpr (x3) run_gens<true>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+      else run_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
       perm_store(kd.cur, n, cur_g);
     }
   } else if constexpr (KIND == KKNAP) {
@@ -2122,7 +2152,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     const int64_t Wsum = wave_sum64(pw), Vsum = wave_sum64(pv);
     __syncthreads();
     KnapK kd{bits, w, v, n, (int64_t)uni64((uint64_t)Wsum), (int64_t)uni64((uint64_t)Vsum), I->capacity, I->lambda};
-    run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+    run_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
     kd.store(cur_g);
   } else {
     int16_t *val = (int16_t *)base;
@@ -2133,14 +2163,13 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     stage16(adj, I->adj, 8u * I->n_edges);
     __syncthreads();
     ColorK kd{val, off, adj, n};
-    run_gens(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+    run_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
     kd.store(cur_g);
   }
   if (threadIdx.x == 0) {
     J->cur_f[sol] = f;
     J->best_f[sol] = bf;
   }
-  constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : 0);
   if (sol_scope) solution_aos_close<kThreads<KIND>>(J, sol, S, bf, g1, E);
   write_counts<ENC, true>(J, sol, S, nacc, bf);   // every wave adds the counts of its own candidates
 }
@@ -2151,17 +2180,17 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
 // The TSP kernels are held to 96 VGPRs (5 waves per SIMD): their scalar state
 // exceeds the SGPR file and part of it lives in VGPR lanes; the compiler's
 // own choice (about 100 VGPRs, 4 waves) runs slower.
-template <int KIND, int STAGE>
+template <int KIND, int VAR>
 __global__ __launch_bounds__(kThreads<KIND>) __attribute__((amdgpu_waves_per_eu(KIND == KTSP ? 5 : 1))) void k_evolve(
     DevJob *job) {
-  evolve_wg<KIND, STAGE>(job, blockIdx.x, gx_lds);
+  evolve_wg<KIND, VAR>(job, blockIdx.x, gx_lds);
 }
 
 // Persistent walk over the (job, solution) work items of one (kind, staging)
 // group of many jobs: each workgroup takes the next item from the group's
 // counter until the list is done, so workgroups that finish early take more.
 // The epoch kernel clears the counter after the launch.
-template <int KIND, int STAGE>
+template <int KIND, int VAR>
 __global__ __launch_bounds__(kThreads<KIND>) __attribute__((amdgpu_waves_per_eu(3))) void k_evolve_group(DevJob *jobs, const uint2 *items, uint32_t n_items,
                                                                  uint32_t *next) {
   for (;;) {
@@ -2176,7 +2205,7 @@ __global__ __launch_bounds__(kThreads<KIND>) __attribute__((amdgpu_waves_per_eu(
     it = uni(it);
     if (it >= n_items) break;
     const uint2 w = items[it];
-    evolve_wg<KIND, STAGE>(jobs + w.x, w.y, gx_lds);
+    evolve_wg<KIND, VAR>(jobs + w.x, w.y, gx_lds);
     __syncthreads();
   }
 }
@@ -2569,41 +2598,40 @@ hipError_t set_stop(DevJob *jobs, int count, uint32_t add, int use_total, hipStr
   return hipGetLastError();
 }
 
-static const void *plain_kernel(int kind, int stage) {
-  switch (kind) {
-    case KTSP:
-      switch (stage) {
-        case SLDS16: return (const void *)k_evolve<KTSP, SLDS16>;
-        case SLDSXY: return (const void *)k_evolve<KTSP, SLDSXY>;
-        case SGLB16: return (const void *)k_evolve<KTSP, SGLB16>;
-        default: return (const void *)k_evolve<KTSP, SGLB32>;
-      }
-    case KQAP: return stage == 1 ? (const void *)k_evolve<KQAP, 1> : (const void *)k_evolve<KQAP, 0>;
-    case KKNAP: return (const void *)k_evolve<KKNAP, 0>;
-    case KVRP: return (const void *)k_evolve<KVRP, 0>;
-    default: return (const void *)k_evolve<KCOLOR, 0>;
+// the kernel of a (kind, variant): variant = staging | kVarX3 (3-opt)
+#define GX_KERNEL_OF(KERNEL)                                                                 \
+  static const void *KERNEL##_of(int kind, int var) {                                      \
+    const bool x3 = (var & kVarX3) != 0;                                                     \
+    switch (kind) {                                                                          \
+      case KTSP:                                                                             \
+        switch (var & 7) {                                                                   \
+          case SLDS16: return x3 ? (const void *)KERNEL<KTSP, SLDS16 | kVarX3> : (const void *)KERNEL<KTSP, SLDS16>; \
+          case SLDSXY: return x3 ? (const void *)KERNEL<KTSP, SLDSXY | kVarX3> : (const void *)KERNEL<KTSP, SLDSXY>; \
+          case SGLB16: return x3 ? (const void *)KERNEL<KTSP, SGLB16 | kVarX3> : (const void *)KERNEL<KTSP, SGLB16>; \
+          default: return x3 ? (const void *)KERNEL<KTSP, SGLB32 | kVarX3> : (const void *)KERNEL<KTSP, SGLB32>;    \
+        }                                                                                    \
+      case KQAP:                                                                             \
+        if ((var & 7) == 1) return x3 ? (const void *)KERNEL<KQAP, 1 | kVarX3> : (const void *)KERNEL<KQAP, 1>;    \
+        return x3 ? (const void *)KERNEL<KQAP, kVarX3> : (const void *)KERNEL<KQAP, 0>;   \
+      case KKNAP: return (const void *)KERNEL<KKNAP, 0>;                                     \
+      case KVRP: return x3 ? (const void *)KERNEL<KVRP, kVarX3> : (const void *)KERNEL<KVRP, 0>; \
+      default: return (const void *)KERNEL<KCOLOR, 0>;                                      \
+    }                                                                                        \
   }
-}
+GX_KERNEL_OF(k_evolve)
+GX_KERNEL_OF(k_evolve_group)
+#undef GX_KERNEL_OF
 
-static const void *group_kernel(int kind, int stage) {
-  switch (kind) {
-    case KTSP:
-      switch (stage) {
-        case SLDS16: return (const void *)k_evolve_group<KTSP, SLDS16>;
-        case SLDSXY: return (const void *)k_evolve_group<KTSP, SLDSXY>;
-        case SGLB16: return (const void *)k_evolve_group<KTSP, SGLB16>;
-        default: return (const void *)k_evolve_group<KTSP, SGLB32>;
-      }
-    case KQAP: return stage == 1 ? (const void *)k_evolve_group<KQAP, 1> : (const void *)k_evolve_group<KQAP, 0>;
-    case KKNAP: return (const void *)k_evolve_group<KKNAP, 0>;
-    case KVRP: return (const void *)k_evolve_group<KVRP, 0>;
-    default: return (const void *)k_evolve_group<KCOLOR, 0>;
-  }
-}
+static const void *plain_kernel(int kind, int var) { return k_evolve_of(kind, var); }
+static const void *group_kernel(int kind, int var) { return k_evolve_group_of(kind, var); }
 
 hipError_t prepare_kernel_attrs(uint32_t max_lds) {
-  const int kinds[][2] = {{KTSP, SLDS16}, {KTSP, SLDSXY}, {KTSP, SGLB16}, {KTSP, SGLB32},
-                          {KQAP, 0},      {KQAP, 1},      {KKNAP, 0},     {KVRP, 0},      {KCOLOR, 0}};
+  const int kinds[][2] = {{KTSP, SLDS16},          {KTSP, SLDSXY},          {KTSP, SGLB16},
+                          {KTSP, SGLB32},          {KQAP, 0},               {KQAP, 1},
+                          {KKNAP, 0},              {KVRP, 0},               {KCOLOR, 0},
+                          {KTSP, SLDS16 | kVarX3}, {KTSP, SLDSXY | kVarX3}, {KTSP, SGLB16 | kVarX3},
+                          {KTSP, SGLB32 | kVarX3}, {KQAP, kVarX3},          {KQAP, 1 | kVarX3},
+                          {KVRP, kVarX3}};
   for (auto &k : kinds) {
     hipError_t e = hipFuncSetAttribute(plain_kernel(k[0], k[1]), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)max_lds);
