@@ -41,7 +41,7 @@ class _Desc(C.Structure):
                 ("a_is_coords", C.c_int32), ("capacity", C.c_int32), ("vehicles", C.c_int32),
                 ("service_time", C.c_int32), ("horizon", C.c_int32), ("lb", C.c_int32),
                 ("ub", C.c_int32), ("n_edges", C.c_int32), ("key", C.c_uint32),
-                ("obj_w", C.c_int32 * 3)]
+                ("obj_w", C.c_int32 * 3), ("lex_order", C.c_int32 * 3), ("lex_tol", C.c_int32 * 3)]
 
 
 class _Params(C.Structure):
@@ -70,7 +70,8 @@ class _State(C.Structure):
                 ("tot_u_op", C.c_uint64 * N_OPS), ("tot_v_op", C.c_uint64 * N_OPS),
                 ("tot_u_k", C.c_uint64 * 3), ("tot_v_k", C.c_uint64 * 3),
                 ("cur", C.POINTER(C.c_int32)), ("cur_f", C.POINTER(C.c_int64)),
-                ("best", C.POINTER(C.c_int32)), ("best_f", C.POINTER(C.c_int64)), ("saos", C.c_void_p)]
+                ("best", C.POINTER(C.c_int32)), ("best_f", C.POINTER(C.c_int64)), ("saos", C.c_void_p),
+                ("cur_v", C.c_void_p), ("best_v", C.c_void_p), ("ref_v", C.c_int64 * 4)]
 
 
 _lib = None
@@ -112,6 +113,13 @@ def lib():
         L.or_run_par.argtypes = [C.c_void_p, C.POINTER(_Params), C.POINTER(_State), C.c_uint32, C.c_int]
         L.or_effective_mask.argtypes = [C.c_void_p, C.c_uint32]
         L.or_effective_mask.restype = C.c_uint32
+        L.or_lex_mode.argtypes = [C.c_void_p]
+        L.or_lex_mode.restype = C.c_int
+        L.or_lex_vector.argtypes = [C.c_void_p, P64, C.c_void_p]
+        L.or_lex_better.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_lex_better.restype = C.c_int
+        L.or_lex_best.argtypes = [C.c_void_p, C.POINTER(_State), C.c_int]
+        L.or_lex_best.restype = C.c_int
         _lib = L
     return _lib
 
@@ -194,7 +202,9 @@ class OracleInstance:
                   a_is_coords=inst.a_is_coords, capacity=inst.capacity, vehicles=inst.vehicles,
                   service_time=inst.service_time, horizon=inst.horizon, lb=inst.lb, ub=inst.ub,
                   n_edges=inst.n_edges, key=inst.key & 0xFFFFFFFF,
-                  obj_w=(C.c_int32 * 3)(*getattr(inst, "obj_weights", (0, 0, 0))))
+                  obj_w=(C.c_int32 * 3)(*getattr(inst, "obj_weights", (0, 0, 0))),
+                  lex_order=(C.c_int32 * 3)(*getattr(inst, "lex_order", (0, 0, 0))),
+                  lex_tol=(C.c_int32 * 3)(*getattr(inst, "lex_tol", (0, 0, 0))))
         self._desc = d
         self.h = lib().or_inst_new(C.byref(d))
         if not self.h:
@@ -256,6 +266,10 @@ class OracleInstance:
         s.best = _i32p(st["best"])
         s.best_f = st["best_f"].ctypes.data_as(C.POINTER(C.c_int64))
         s.saos = st["saos"].ctypes.data
+        s.cur_v = st["cur_v"].ctypes.data
+        s.best_v = st["best_v"].ctypes.data
+        for i, v in enumerate(st["ref_v"]):
+            s.ref_v[i] = int(v)
         return s
 
     @staticmethod
@@ -267,6 +281,7 @@ class OracleInstance:
                          ("tot_u_op", np.uint64), ("tot_v_op", np.uint64), ("tot_u_k", np.uint64),
                          ("tot_v_k", np.uint64)):
             st[name] = np.array(list(getattr(s, name)), dtype=dt)
+        st["ref_v"] = np.array(list(s.ref_v), dtype=np.int64)
 
     def new_state(self, P: int) -> dict:
         n = self.n
@@ -278,7 +293,8 @@ class OracleInstance:
                 "tot_u_k": np.zeros(3, np.uint64), "tot_v_k": np.zeros(3, np.uint64),
                 "cur": np.zeros((P, n), np.int32), "cur_f": np.zeros(P, np.int64),
                 "best": np.zeros((P, n), np.int32), "best_f": np.zeros(P, np.int64),
-                "saos": np.zeros(P, SOL_AOS)}
+                "saos": np.zeros(P, SOL_AOS), "cur_v": np.zeros((P, 4), np.int64),
+                "best_v": np.zeros((P, 4), np.int64), "ref_v": np.zeros(4, np.int64)}
 
     def init(self, params) -> dict:
         st = self.new_state(params.population)
@@ -300,6 +316,10 @@ class OracleInstance:
         st["saos"] = np.ascontiguousarray(st["saos"], dtype=SOL_AOS)
         for k in ("tot_u_op", "tot_v_op", "tot_u_k", "tot_v_k"):
             st.setdefault(k, np.zeros(N_OPS if k.endswith("op") else 3, np.uint64))
+        P = len(st["cur_f"])
+        for k in ("cur_v", "best_v"):
+            st[k] = np.ascontiguousarray(st.get(k, np.zeros((P, 4), np.int64)), dtype=np.int64)
+        st.setdefault("ref_v", np.zeros(4, np.int64))
         s = self._state_struct(st)
         pp = _params(params)
         if threads > 1:
@@ -324,6 +344,32 @@ class OracleInstance:
         lib().or_migrate(C.byref(pp), self.n, C.byref(s), epoch)
         self._read_back(s, st)
         return st
+
+    @property
+    def lex(self) -> bool:
+        return bool(lib().or_lex_mode(self.h))
+
+    def lex_vector(self, x) -> np.ndarray:
+        """(penalty, level 1, level 2, level 3) of a solution in the lexicographic mode."""
+        x = np.ascontiguousarray(x, dtype=np.int32)
+        v = np.zeros(4, np.int64)
+        lib().or_lex_vector(self.h, _i32p(x), v.ctypes.data)
+        return v
+
+    def lex_better(self, a, b) -> bool:
+        a = np.ascontiguousarray(a, dtype=np.int64)
+        b = np.ascontiguousarray(b, dtype=np.int64)
+        return bool(lib().or_lex_better(self.h, a.ctypes.data, b.ctypes.data))
+
+    def best_of(self, st: dict):
+        """(reported objective, index) of the best solution: the minimum of
+        (best_f, index), or in the lexicographic mode the ordered scan of the
+        best vectors."""
+        if not self.lex:
+            return best_of(st)
+        s = self._state_struct(st)
+        i = int(lib().or_lex_best(self.h, C.byref(s), len(st["best_f"])))
+        return int(st["best_f"][i]), i
 
     def solve(self, params, threads: int = 1) -> dict:
         st = self.init(params)

@@ -188,7 +188,9 @@ static int64_t obj_knap(const or_inst *in, const int32_t *x) {
  * mode: the three objectives (total distance, number of routes, length of the
  * longest route) enter with the instance's integer weights; the default
  * (1, 0, 0) is the single distance objective. */
-static int64_t obj_vrptw(const or_inst *in, const int32_t *x) {
+/* parts[0..4]: total distance, routes, longest route, total lateness,
+ * routes beyond the fleet */
+static void vrptw_parts(const or_inst *in, const int32_t *x, int64_t parts[5]) {
   int n = in->d.n;
   const int32_t *dem = in->d.b, *ready = in->d.b + (n + 1), *due = in->d.b + 2 * (n + 1);
   int64_t dist = 0, late = 0, t = 0, load = 0, route_len = 0, longest = 0;
@@ -219,8 +221,54 @@ static int64_t obj_vrptw(const or_inst *in, const int32_t *x) {
     if (route_len > longest) longest = route_len;
   }
   int64_t extra = routes - in->d.vehicles;
-  return (int64_t)in->d.obj_w[0] * dist + (int64_t)in->d.obj_w[1] * routes + (int64_t)in->d.obj_w[2] * longest +
-         100 * late + 10000 * (extra > 0 ? extra : 0);
+  parts[0] = dist; parts[1] = routes; parts[2] = longest; parts[3] = late; parts[4] = extra > 0 ? extra : 0;
+}
+
+static int64_t obj_vrptw(const or_inst *in, const int32_t *x) {
+  int64_t q[5];
+  vrptw_parts(in, x, q);
+  return (int64_t)in->d.obj_w[0] * q[0] + (int64_t)in->d.obj_w[1] * q[1] + (int64_t)in->d.obj_w[2] * q[2] +
+         100 * q[3] + 10000 * q[4];
+}
+
+/* Sec. "Multi-Objective Optimization Modes", lexicographic mode.  reading:
+ * the penalty (lateness and fleet excess, as in the weighted mode) comes
+ * first and is compared exactly; then the objectives in the caller's
+ * priority order, where two values within the level's tolerance are equal
+ * and the next level decides.  v = (penalty, level 1, level 2, level 3),
+ * unused levels 0. */
+int or_lex_mode(const or_inst *in) { return in->d.kind == K_VRPTW && in->d.lex_order[0] != 0; }
+
+void or_lex_vector(const or_inst *in, const int32_t *x, int64_t v[4]) {
+  int64_t q[5];
+  vrptw_parts(in, x, q);
+  v[0] = 100 * q[3] + 10000 * q[4];
+  for (int i = 0; i < 3; ++i) {
+    int id = in->d.lex_order[i];
+    v[1 + i] = id ? q[id - 1] : 0;
+  }
+}
+
+/* a strictly better than b */
+int or_lex_better(const or_inst *in, const int64_t a[4], const int64_t b[4]) {
+  if (a[0] != b[0]) return a[0] < b[0];
+  for (int i = 0; i < 3 && in->d.lex_order[i]; ++i) {
+    int64_t tol = in->d.lex_tol[i];
+    if (a[1 + i] + tol < b[1 + i]) return 1;
+    if (b[1 + i] + tol < a[1 + i]) return 0;
+  }
+  return 0;
+}
+
+/* reading: where the paper compares two solutions' objectives over a set
+ * (the argmin over candidates, the best of a population), the lexicographic
+ * mode scans the set in index order and keeps the first element no later
+ * element is strictly better than the one kept so far. */
+int or_lex_best(const or_inst *in, const or_state *st, int population) {
+  int b = 0;
+  for (int s = 1; s < population; ++s)
+    if (or_lex_better(in, st->best_v + 4 * (size_t)s, st->best_v + 4 * (size_t)b)) b = s;
+  return b;
 }
 
 static int64_t obj_color(const or_inst *in, const int32_t *x) {
@@ -411,16 +459,16 @@ static void ema_group(const or_params *p, uint32_t *w, const uint64_t *u, const 
 
 static const uint32_t WK_DEFAULT[3] = {52429, 9830, 3277};
 
-void or_aos_update(const or_params *p, uint32_t mask, or_state *st, int64_t inst_best_now) {
+/* the update with the epoch's improvement of the instance best given */
+static void aos_update_flag(const or_params *p, uint32_t mask, or_state *st, int improved) {
   int ids[OR_MAX_OPS];
   int cnt = enabled_list(mask, ids);
   ema_group(p, st->w_op, st->u_op, st->v_op, ids, cnt);
   int kid[3] = {0, 1, 2};
   ema_group(p, st->w_k, st->u_k, st->v_k, kid, 3);
   /* reading: "consecutive no-improvement" counted in epochs of the instance best */
-  if (inst_best_now < st->epoch_ref) st->stag = 0;
+  if (improved) st->stag = 0;
   else st->stag++;
-  st->epoch_ref = inst_best_now;
   if (st->stag >= p->stagnation_epochs) {
     memcpy(st->w_k, WK_DEFAULT, sizeof(WK_DEFAULT));
     st->stag = 0;
@@ -429,6 +477,12 @@ void or_aos_update(const or_params *p, uint32_t mask, or_state *st, int64_t inst
   memset(st->v_op, 0, sizeof(st->v_op));
   memset(st->u_k, 0, sizeof(st->u_k));
   memset(st->v_k, 0, sizeof(st->v_k));
+}
+
+void or_aos_update(const or_params *p, uint32_t mask, or_state *st, int64_t inst_best_now) {
+  int improved = inst_best_now < st->epoch_ref;
+  st->epoch_ref = inst_best_now;
+  aos_update_flag(p, mask, st, improved);
 }
 
 /* Per-solution scope (aos_scope = 1).  reading: Alg. 2 pools the statistics
@@ -619,10 +673,17 @@ void or_random_solution(const or_inst *in, const or_params *p, uint32_t q, int32
   }
 }
 
-typedef struct { int64_t f; int32_t q; } fq;
+/* pool order: by f, or in the lexicographic mode by the objective vector
+ * level by level (no tolerances: a total order); ties by pool index */
+typedef struct { int64_t f, v[4]; int32_t q, lex; } fq;
 static int fq_cmp(const void *a, const void *b) {
   const fq *x = (const fq *)a, *y = (const fq *)b;
-  if (x->f != y->f) return x->f < y->f ? -1 : 1;
+  if (x->lex) {
+    for (int i = 0; i < 4; ++i)
+      if (x->v[i] != y->v[i]) return x->v[i] < y->v[i] ? -1 : 1;
+  } else if (x->f != y->f) {
+    return x->f < y->f ? -1 : 1;
+  }
   return x->q < y->q ? -1 : (x->q > y->q);
 }
 
@@ -642,13 +703,29 @@ int or_init(const or_inst *in, const or_params *p, or_state *st) {
     else or_random_solution(in, p, (uint32_t)q, x);
   }
   fq *ord = (fq *)malloc(sizeof(fq) * Q);
-  for (int q = 0; q < Q; ++q) { ord[q].f = or_objective(in, pool + (size_t)q * n); ord[q].q = q; }
+  const int lex = or_lex_mode(in);
+  for (int q = 0; q < Q; ++q) {
+    memset(&ord[q], 0, sizeof(fq));
+    ord[q].q = q;
+    ord[q].lex = lex;
+    if (lex) {   /* reading: the reported scalar of the lexicographic mode is penalty + level 1 */
+      or_lex_vector(in, pool + (size_t)q * n, ord[q].v);
+      ord[q].f = ord[q].v[0] + ord[q].v[1];
+    } else {
+      ord[q].f = or_objective(in, pool + (size_t)q * n);
+    }
+  }
   qsort(ord, Q, sizeof(fq), fq_cmp);
   for (int s = 0; s < P; ++s) {
     memcpy(st->cur + (size_t)s * n, pool + (size_t)ord[s].q * n, sizeof(int32_t) * n);
     memcpy(st->best + (size_t)s * n, pool + (size_t)ord[s].q * n, sizeof(int32_t) * n);
     st->cur_f[s] = st->best_f[s] = ord[s].f;
+    if (lex) {
+      memcpy(st->cur_v + 4 * (size_t)s, ord[s].v, 4 * sizeof(int64_t));
+      memcpy(st->best_v + 4 * (size_t)s, ord[s].v, 4 * sizeof(int64_t));
+    }
   }
+  if (lex) memcpy(st->ref_v, ord[0].v, 4 * sizeof(int64_t));
   st->g = 0;
   st->stag = 0;
   st->epoch_ref = ord[0].f;
@@ -701,10 +778,84 @@ static void credit(or_counts *c, const int *ops, int k, int improved) {
   if (improved) c->v_k[k - 1]++;
 }
 
+/* The difference a worse winner w makes against the current c in the
+ * lexicographic mode, for the acceptance test: the penalty difference when
+ * the penalties differ, else the difference at the first level where c is
+ * better than w by more than the tolerance. */
+static int64_t lex_delta(const or_inst *in, const int64_t w[4], const int64_t c[4]) {
+  if (w[0] != c[0]) return w[0] - c[0];
+  for (int i = 0; i < 3 && in->d.lex_order[i]; ++i)
+    if (c[1 + i] + in->d.lex_tol[i] < w[1 + i]) return w[1 + i] - c[1 + i];
+  return 0;
+}
+
+/* Alg. 1 body in the lexicographic mode: the candidates' objective vectors
+ * are compared with or_lex_better (argmin: ordered scan, ties to the lower
+ * t); a winner that the current solution does not beat is accepted, a worse
+ * one with the exponential test on lex_delta; a candidate improves when it is
+ * strictly better than the current solution. */
+static void generation_lex(const or_inst *in, const or_params *p, or_state *st, int sol, uint32_t g, uint64_t T,
+                           const int *ids, int nids, int32_t *tmp, int32_t *cand, or_counts *c) {
+  int n = in->d.n, C = p->candidates;
+  uint32_t key = in->d.key;
+  int32_t *x = st->cur + (size_t)sol * n;
+  int64_t *cv = st->cur_v + 4 * (size_t)sol, *bvs = st->best_v + 4 * (size_t)sol;
+  uint32_t wl[OR_MAX_OPS];
+  for (int i = 0; i < nids; ++i) wl[i] = st->w_op[ids[i]];
+  int64_t bv[4] = {0, 0, 0, 0}, v[4];
+  int best_t = -1, best_k = 0, best_ops[3] = {0, 0, 0};
+  for (int t = 0; t < C; ++t) {
+    memcpy(tmp, x, sizeof(int32_t) * n);
+    uint32_t r[4];
+    draw(p, g, (uint32_t)sol, (uint32_t)t << 2, key, r);
+    int k = 1 + or_wpick(r[0] >> 16, st->w_k, 3);
+    int ops[3];
+    for (int m = 0; m < k; ++m) {
+      if (m > 0) draw(p, g, (uint32_t)sol, ((uint32_t)t << 2) | (uint32_t)m, key, r);
+      ops[m] = ids[or_wpick(r[0] & 0xFFFFu, wl, nids)];
+      or_apply_op(in, tmp, ops[m], r[1], r[2], r[3]);
+    }
+    or_lex_vector(in, tmp, v);
+    if (p->credit == 0) credit(c, ops, k, or_lex_better(in, v, cv));
+    if (best_t < 0 || or_lex_better(in, v, bv)) {
+      memcpy(bv, v, sizeof(bv)); best_t = t; best_k = k;
+      memcpy(best_ops, ops, sizeof(ops));
+      memcpy(cand, tmp, sizeof(int32_t) * n);
+    }
+  }
+  int acc = 0;
+  if (!or_lex_better(in, cv, bv)) acc = 1;
+  else {
+    int rej;
+    uint32_t thr = or_accept_threshold((uint64_t)lex_delta(in, bv, cv), T, &rej);
+    if (!rej) {
+      uint32_t r[4];
+      draw(p, g, (uint32_t)sol, 0xFFFFFFFFu, key, r);
+      acc = (r[0] >> 1) < thr;
+    }
+  }
+  if (acc) {
+    if (p->credit == 1) credit(c, best_ops, best_k, or_lex_better(in, bv, cv));
+    memcpy(x, cand, sizeof(int32_t) * n);
+    memcpy(cv, bv, sizeof(bv));
+    st->cur_f[sol] = bv[0] + bv[1];
+    c->acc++;
+    if (or_lex_better(in, cv, bvs)) {
+      memcpy(bvs, cv, sizeof(bv));
+      st->best_f[sol] = st->cur_f[sol];
+      memcpy(st->best + (size_t)sol * n, x, sizeof(int32_t) * n);
+    }
+  }
+}
+
 /* One generation of solution `sol` at generation g and temperature T (Alg. 1
  * body); the credited counts are added to *c.  tmp and cand hold n entries. */
 static void generation(const or_inst *in, const or_params *p, or_state *st, int sol, uint32_t g, uint64_t T,
                        const int *ids, int nids, int32_t *tmp, int32_t *cand, or_counts *c) {
+  if (or_lex_mode(in)) {
+    generation_lex(in, p, st, sol, g, T, ids, nids, tmp, cand, c);
+    return;
+  }
   int n = in->d.n, C = p->candidates;
   uint32_t key = in->d.key;
   int32_t *x = st->cur + (size_t)sol * n;
@@ -788,7 +939,13 @@ static void add_counts(const or_params *p, or_state *st, int sol, const or_count
  * scope, then migration (Alg. 2; Sec. "Island Model and Elite Injection"). */
 static void epoch_end(const or_inst *in, const or_params *p, or_state *st, uint32_t g_end, uint32_t mask) {
   int P = p->population;
-  if (p->aos_scope == 1) {
+  if (or_lex_mode(in)) {   /* the instance best by the ordered scan; improved when strictly better */
+    int b = or_lex_best(in, st, P);
+    int improved = or_lex_better(in, st->best_v + 4 * (size_t)b, st->ref_v);
+    memcpy(st->ref_v, st->best_v + 4 * (size_t)b, sizeof(st->ref_v));
+    st->epoch_ref = st->best_f[b];
+    aos_update_flag(p, mask, st, improved);
+  } else if (p->aos_scope == 1) {
     for (int s = 0; s < P; ++s) sol_aos_update(p, mask, &st->saos[s], st->best_f[s]);
   } else {
     int64_t ib = st->best_f[0];

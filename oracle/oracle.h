@@ -23,6 +23,11 @@ typedef struct {
   int32_t a_is_coords, capacity, vehicles, service_time, horizon, lb, ub, n_edges;
   uint32_t key;
   int32_t obj_w[3];   /* VRPTW: weights of distance, routes, longest route; all 0 = (1, 0, 0) */
+  /* VRPTW lexicographic mode (Sec. "Multi-Objective Optimization Modes"):
+   * objectives in priority order (1 distance, 2 routes, 3 longest route; 0
+   * ends the list; lex_order[0] = 0 is the weighted mode) and the tolerance
+   * of each level */
+  int32_t lex_order[3], lex_tol[3];
 } or_inst_desc;
 
 typedef struct {
@@ -63,6 +68,11 @@ typedef struct {
   int32_t *best;                      /* P x n */
   int64_t *best_f;                    /* P     */
   or_sol_aos *saos;                   /* P entries when aos_scope = 1, else NULL */
+  /* lexicographic mode: objective vectors (penalty, then the priority levels)
+   * of the current and best solutions (P x 4) and of the instance best at the
+   * start of the epoch */
+  int64_t *cur_v, *best_v;
+  int64_t ref_v[4];
 } or_state;
 
 typedef struct or_inst or_inst;
@@ -86,6 +96,10 @@ int      or_heuristic_perms(const or_inst *, int32_t *out, int cap); /* returns 
 int      or_init(const or_inst *, const or_params *, or_state *st);
 void     or_random_solution(const or_inst *, const or_params *, uint32_t pool_index, int32_t *x);
 int      or_wpick(uint32_t u16, const uint32_t *w, int cnt);  /* Q16 roulette */
+int      or_lex_mode(const or_inst *);
+void     or_lex_vector(const or_inst *, const int32_t *x, int64_t v[4]);
+int      or_lex_better(const or_inst *, const int64_t a[4], const int64_t b[4]);
+int      or_lex_best(const or_inst *, const or_state *st, int population);   /* ordered scan of the bests */
 int      or_run(const or_inst *, const or_params *, or_state *st, uint32_t n_gens);
 /* the same generations on `threads` threads (solutions split between them
  * inside each epoch); equal to or_run */

@@ -63,6 +63,8 @@ class Instance:
     n_edges: int = 0
     key: int = 0
     obj_weights: tuple = (0, 0, 0)   # VRPTW: weights of distance, routes, longest route
+    lex_order: tuple = (0, 0, 0)     # VRPTW lexicographic mode: 1 distance, 2 routes, 3 longest; 0 ends
+    lex_tol: tuple = (0, 0, 0)       # tolerance of each lexicographic level
 
     def __post_init__(self):
         self.a = np.ascontiguousarray(self.a, dtype=np.int32)
