@@ -128,6 +128,23 @@ gx_status gx_get_device_info(gx_ctx *ctx, gx_device_info *out);
  *            route; each weight in [0, 2^20]; all zero means (1, 0, 0), the
  *            single objective).  n <= 250; coordinates in [0, 2^14), demand
  *            in [0, capacity], times in [0, 2^19].
+ *            Lexicographic mode (paper, Sec. "Multi-Objective Optimization
+ *            Modes"; Tab. lexicographic_mode) when lex_order[0] != 0: a
+ *            solution's objective is the vector (penalty, level 1, level 2,
+ *            level 3), penalty = 100 * lateness + 10000 * fleet excess, level
+ *            i the objective lex_order[i] (1 distance, 2 routes, 3 longest
+ *            route; a 0 ends the list; no repeats).  b is better than a when
+ *            its penalty is lower, or the penalties are equal and at the
+ *            first level where the two differ by more than lex_tol[i]
+ *            (in [0, 2^30]) b's value is the lower one; otherwise neither is
+ *            better.  Within a set (the candidates of a generation, the
+ *            population) the best is found by a scan in index order that
+ *            keeps the first element no later one is better than.  The
+ *            scalar reported for a solution (cur_f, best_f, the best
+ *            objective) is its penalty plus its level-1 value.  obj_weights
+ *            must be zero in this mode; solves on such an instance take one
+ *            island, no elite injection and aos_scope 0, and cannot be
+ *            restored (gx_job_restore).
  *   INTCOLOR a = edge list n_edges x 2 (no self loops); values in [lb, ub];
  *            f = number of edges whose ends share a value.
  * instance_key enters every random counter of solves on this instance: keep
@@ -138,6 +155,8 @@ typedef struct {
   int32_t a_is_coords, capacity, vehicles, service_time, horizon, lb, ub, n_edges;
   uint32_t instance_key;
   int32_t obj_weights[3];   /* VRPTW objective weights (above); zero for the other kinds */
+  int32_t lex_order[3];     /* VRPTW lexicographic mode (above); zero: the weighted mode */
+  int32_t lex_tol[3];
 } gx_instance_desc;
 gx_status gx_instance_upload(gx_ctx *ctx, const gx_instance_desc *desc, gx_instance **out);
 gx_status gx_instance_free(gx_ctx *ctx, gx_instance *inst);
@@ -308,13 +327,22 @@ typedef struct {
 } gx_sol_aos;
 /* The P per-solution records into out[P]; synchronises. */
 gx_status gx_snapshot_aos(gx_ctx *ctx, gx_job *job, gx_sol_aos *out);
+/* Objective vectors of a job on a VRPTW instance in the lexicographic mode
+ * (paper, Sec. "Multi-Objective Optimization Modes"): cur_v and best_v are
+ * P x 4 int64 (penalty, level 1, level 2, level 3; unused levels 0) of the
+ * current and best-so-far solutions, ref_v (4 int64) the instance best's
+ * vector at the last epoch end (the stagnation reference).  Any pointer may
+ * be NULL; host memory.  GX_E_INVALID for a job not in that mode;
+ * synchronises. */
+gx_status gx_snapshot_lex(gx_ctx *ctx, gx_job *job, int64_t *cur_v, int64_t *best_v, int64_t *ref_v);
 /* Resume from a snapshot: overwrite a non-batched job's state at a generation
  * boundary with sc, cur, cur_f, best, best_f (all required, as gx_snapshot
  * fills them) and, with aos_scope = 1, the P records of aos (else ignored).
  * Continuing the job then gives the generations the snapshotted job would
  * have run (same instance and parameters).  GX_E_INVALID for a batched job,
  * a null array, sc->g beyond the job's generation budget, or a permutation
- * or value that is not a solution of the instance; synchronises. */
+ * or value that is not a solution of the instance; GX_E_UNSUPPORTED for a
+ * job in the lexicographic mode; synchronises. */
 gx_status gx_job_restore(gx_ctx *ctx, gx_job *job, const gx_state_scalars *sc, const int32_t *cur,
                          const int64_t *cur_f, const int32_t *best, const int64_t *best_f, const gx_sol_aos *aos);
 gx_status gx_job_free(gx_ctx *ctx, gx_job *job);

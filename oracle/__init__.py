@@ -300,7 +300,8 @@ class OracleInstance:
         st = self.new_state(params.population)
         s = self._state_struct(st)
         pp = _params(params)
-        lib().or_init(self.h, C.byref(pp), C.byref(s))
+        if lib().or_init(self.h, C.byref(pp), C.byref(s)) != 0:
+            raise ValueError("the lexicographic mode takes one island, no elite injection and instance-level weights")
         self._read_back(s, st)
         return st
 

@@ -692,6 +692,10 @@ static int fq_cmp(const void *a, const void *b) {
  * random; ties in f keep the lower pool index. */
 int or_init(const or_inst *in, const or_params *p, or_state *st) {
   int n = in->d.n, P = p->population;
+  /* reading: the lexicographic mode runs one population under instance-level
+   * weights; islands, elite injection and per-solution weights compare by a
+   * scalar and are not combined with it */
+  if (or_lex_mode(in) && (p->islands > 1 || p->aos_scope == 1 || p->elite_epochs)) return -1;
   int Q = p->oversample_k * P;
   int32_t *pool = (int32_t *)malloc(sizeof(int32_t) * (size_t)Q * n);
   int32_t *heur = (int32_t *)malloc(sizeof(int32_t) * (size_t)8 * n);

@@ -189,6 +189,8 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
   pr.key = d->instance_key;
   if (d->kind != KVRP && (d->obj_weights[0] | d->obj_weights[1] | d->obj_weights[2]))
     return fail(c, GX_E_INVALID, "objective weights apply to VRPTW only");
+  if (d->kind != KVRP && (d->lex_order[0] | d->lex_order[1] | d->lex_order[2]))
+    return fail(c, GX_E_INVALID, "the lexicographic mode applies to VRPTW only");
   std::vector<int32_t> A, B;
   gx_status st = GX_OK;
   double fbound = 0;
@@ -272,6 +274,22 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
     h.vw_d = dflt ? 1 : w[0];
     h.vw_r = dflt ? 0 : w[1];
     h.vw_m = dflt ? 0 : w[2];
+    // lexicographic mode: levels up to the first 0, distinct objectives 1..3
+    int levels = 0;
+    while (levels < 3 && d->lex_order[levels] != 0) ++levels;
+    for (int i = 0; i < 3; ++i) {
+      const int id = d->lex_order[i], tol = d->lex_tol[i];
+      if (i >= levels ? (id != 0 || tol != 0) : (id < 1 || id > 3 || tol < 0 || tol > (1 << 30)))
+        return fail(c, GX_E_INVALID, "lex_order entries in 1..3 ended by 0 (tolerances in [0, 2^30], 0 past the end)");
+      for (int k = 0; k < i && i < levels; ++k)
+        if (d->lex_order[k] == id) return fail(c, GX_E_INVALID, "lex_order repeats an objective");
+    }
+    if (levels && !dflt) return fail(c, GX_E_INVALID, "obj_weights must be zero in the lexicographic mode");
+    h.lex_levels = levels;
+    for (int i = 0; i < 3; ++i) {
+      h.lex_id[i] = i < levels ? d->lex_order[i] : 0;
+      h.lex_tol[i] = i < levels ? d->lex_tol[i] : 0;
+    }
     h.dn = m;
     add_arr(pr, F_XY, A);
     h.has_xy = 1;
@@ -560,7 +578,7 @@ uint32_t resolve_stage(const InstInfo &ii, uint32_t req) {
 }
 
 uint32_t job_lds(const InstInfo &ii, uint32_t stage, uint32_t op_mask) {
-  uint32_t b = lds_bytes_for(ii.h.kind, ii.h.n, evolve_variant(ii.h.kind, stage, op_mask));
+  uint32_t b = lds_bytes_for(ii.h.kind, ii.h.n, evolve_variant(ii.h.kind, stage, op_mask, ii.h.lex_levels));
   if (ii.h.kind == KCOLOR) b += (uint32_t)pad16((size_t)8 * ii.h.n_edges);
   return std::max<uint32_t>(b, 16);
 }
@@ -603,6 +621,8 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
     return fail(c, GX_E_INVALID, "per-solution weights need aos_epoch * candidates <= 2^30");
   for (int i = 0; i < kOps; ++i)
     if (p->init_weight_q16[i] > (1u << 24)) return fail(c, GX_E_INVALID, "init_weight_q16 entries <= 2^24");
+  if (ii.h.lex_levels && (isl > 1 || p->elite_epochs || p->aos_scope))
+    return fail(c, GX_E_UNSUPPORTED, "the lexicographic mode takes one island, no elite injection and aos_scope 0");
   const uint32_t lds = job_lds(ii, stage, mask);
   if (lds > lds_limit)
     return fail(c, GX_E_UNSUPPORTED, "instance needs %u bytes of LDS per workgroup (limit %u)", lds, lds_limit);
@@ -631,6 +651,7 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
   h.elite_epochs = p->elite_epochs;
   h.aos_scope = p->aos_scope;
   for (int i = 0; i < kOps; ++i) h.init_w[i] = p->init_weight_q16[i];
+  h.lex_levels = (uint32_t)ii.h.lex_levels;
   return GX_OK;
 }
 
@@ -640,11 +661,12 @@ bool migrates(const DevJob &h) { return (h.mig_epochs && h.islands >= 2) || h.el
 
 int heur_mats_of(int kind) { return kind == KQAP ? 2 : ((kind == KTSP || kind == KVRP) ? 1 : 0); }
 
-// bytes of the per-job device arrays, laid out by carve_job
-size_t job_array_bytes(size_t n, size_t P, size_t Q) {
+// bytes of the per-job device arrays, laid out by carve_job (lex: the
+// objective vectors of the lexicographic mode)
+size_t job_array_bytes(size_t n, size_t P, size_t Q, bool lex) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   return 2 * al(4 * n * P) + 2 * al(8 * P) + al(4 * n * Q) + al(8 * Q) + al(32 * n) + al(4 * n) +
-         al(8 * kShards * kEpochSlots) + al(sizeof(SolAos) * P);
+         al(8 * kShards * kEpochSlots) + al(sizeof(SolAos) * P) + (lex ? 2 * al(32 * P) + al(32 * Q) : 0);
 }
 
 void carve_job(DevJob &h, char *q, size_t n) {
@@ -664,6 +686,18 @@ void carve_job(DevJob &h, char *q, size_t n) {
   h.best_out = (int32_t *)take(4 * n);
   h.shard = (unsigned long long *)take(8 * kShards * kEpochSlots);
   h.saos = (SolAos *)take(sizeof(SolAos) * h.P);
+  if (h.lex_levels) {
+    h.cur_v = (int64_t *)take(32 * (size_t)h.P);
+    h.best_v = (int64_t *)take(32 * (size_t)h.P);
+    h.pool_v = (int64_t *)take(32 * (size_t)h.Q);
+  }
+}
+
+// every device array the kernels dereference for this job is in place
+bool job_arrays_placed(const DevJob &h) {
+  const bool base = h.cur && h.best && h.cur_f && h.best_f && h.pool && h.pool_f && h.sums && h.best_out && h.shard &&
+                    h.saos;
+  return base && (!h.lex_levels || (h.cur_v && h.best_v && h.pool_v));
 }
 
 gx_status ensure_d32(gx_ctx *c, gx_instance *in) {
@@ -828,7 +862,7 @@ gx_status gx_autosize_population(gx_ctx *c, const gx_instance *in, const gx_solv
   const uint32_t mask = p && p->op_mask ? (p->op_mask & encoding_ops(in->h.kind)) : encoding_ops(in->h.kind);
   const uint32_t lds = job_lds(ii, stage, mask);
   int occ = 0;
-  HIPCHK(c, gxk::occupancy_plain(in->h.kind, evolve_variant(in->h.kind, stage, mask), lds, &occ));
+  HIPCHK(c, gxk::occupancy_plain(in->h.kind, evolve_variant(in->h.kind, stage, mask, in->h.lex_levels), lds, &occ));
   // every CU filled to the residency the kernel's registers and LDS allow
   occ = std::max(1, std::min(occ, 32));
   *out = (uint32_t)(c->info.cus * occ);
@@ -863,6 +897,11 @@ gx_status gx_job_create(gx_ctx *c, const gx_instance *cin, const gx_solve_params
       (st = dalloc(c, j->bufs, &h.saos, sizeof(SolAos) * h.P)) ||
       (st = dalloc(c, j->bufs, &j->d, sizeof(DevJob))))
     return bail(st);
+  if (h.lex_levels &&
+      ((st = dalloc(c, j->bufs, &h.cur_v, (size_t)32 * h.P)) || (st = dalloc(c, j->bufs, &h.best_v, (size_t)32 * h.P)) ||
+       (st = dalloc(c, j->bufs, &h.pool_v, (size_t)32 * h.Q))))
+    return bail(st);
+  if (!job_arrays_placed(h)) return bail(fail(c, GX_E_DEVICE, "job arrays incomplete"));
   if (hipMemcpy(j->d, &h, sizeof(DevJob), hipMemcpyHostToDevice) != hipSuccess)
     return bail(fail(c, GX_E_DEVICE, "job upload failed"));
   const int mats = heur_mats_of(in->h.kind);
@@ -886,7 +925,7 @@ gx_status gx_job_advance(gx_ctx *c, gx_job *j, uint32_t ng) {
   HIPCHK(c, gxk::set_stop(j->d, 1, ng, 0, c->stream));
   HIPCHK(c, hipEventRecord(j->ev0, c->stream));
   DevJob *dj = j->d;
-  const int kind = j->inst->h.kind, stage = evolve_variant(kind, j->h.stage, j->h.op_mask);
+  const int kind = j->inst->h.kind, stage = evolve_variant(kind, j->h.stage, j->h.op_mask, j->h.lex_levels);
   const uint32_t P = j->h.P, lds = j->h.lds_bytes;
   const bool mig = migrates(j->h);
   hipStream_t s = c->stream;
@@ -930,7 +969,7 @@ gx_status gx_solve_static(gx_ctx *c, const gx_instance *in, const gx_solve_param
     return fail(c, GX_E_UNSUPPORTED, "int32 distances of coordinates would need an allocation: choose another staging");
   const size_t n = (size_t)in->h.n;
   const size_t rec = (sizeof(DevJob) + 255) & ~size_t(255);
-  const size_t need = rec + job_array_bytes(n, h.P, h.Q);
+  const size_t need = rec + job_array_bytes(n, h.P, h.Q, h.lex_levels != 0);
   if (need > kStaticScratchBytes)
     return fail(c, GX_E_UNSUPPORTED, "solve needs %zu bytes of workspace; the static workspace holds %zu", need,
                 kStaticScratchBytes);
@@ -939,7 +978,7 @@ gx_status gx_solve_static(gx_ctx *c, const gx_instance *in, const gx_solve_param
   h.best_out = best_solution;
   hipStream_t s = c->stream;
   const bool mig = migrates(h);
-  const int kind = in->h.kind, stage = evolve_variant(kind, h.stage, h.op_mask);
+  const int kind = in->h.kind, stage = evolve_variant(kind, h.stage, h.op_mask, h.lex_levels);
   HIPCHK(c, gxk::write_job(dj, h, s));
   HIPCHK(c, gxk::init_jobs(dj, 1, h.Q, (int)n, heur_mats_of(kind), s));
   HIPCHK(c, gxk::set_stop(dj, 1, 0, 1, s));
@@ -1066,6 +1105,17 @@ gx_status gx_snapshot_aos(gx_ctx *c, gx_job *j, gx_sol_aos *out) {
   return GX_OK;
 }
 
+gx_status gx_snapshot_lex(gx_ctx *c, gx_job *j, int64_t *cur_v, int64_t *best_v, int64_t *ref_v) {
+  if (!c || !j) return fail(c, GX_E_INVALID, "null argument");
+  if (!j->h.lex_levels) return fail(c, GX_E_INVALID, "the job is not in the lexicographic mode");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const size_t P = j->h.P;
+  if (cur_v) HIPCHK(c, hipMemcpy(cur_v, j->h.cur_v, 32 * P, hipMemcpyDeviceToHost));
+  if (best_v) HIPCHK(c, hipMemcpy(best_v, j->h.best_v, 32 * P, hipMemcpyDeviceToHost));
+  if (ref_v) HIPCHK(c, hipMemcpy(ref_v, (char *)j->d + offsetof(DevJob, ref_v), 32, hipMemcpyDeviceToHost));
+  return GX_OK;
+}
+
 gx_status gx_snapshot(gx_ctx *c, gx_job *j, gx_state_scalars *sc, int32_t *cur, int64_t *cur_f, int32_t *best,
                       int64_t *best_f) {
   if (!c || !j) return fail(c, GX_E_INVALID, "null argument");
@@ -1124,6 +1174,7 @@ gx_status gx_job_restore(gx_ctx *c, gx_job *j, const gx_state_scalars *sc, const
                          const int32_t *best, const int64_t *best_f, const gx_sol_aos *aos) {
   if (!c || !j || !sc || !cur || !cur_f || !best || !best_f) return fail(c, GX_E_INVALID, "null argument");
   if (j->batch) return fail(c, GX_E_INVALID, "batched jobs cannot be restored");
+  if (j->h.lex_levels) return fail(c, GX_E_UNSUPPORTED, "jobs in the lexicographic mode cannot be restored");
   if (j->h.aos_scope == 1 && !aos) return fail(c, GX_E_INVALID, "per-solution weights need their records");
   if (sc->g > 0xFFFFFFFEu) return fail(c, GX_E_INVALID, "generation beyond 2^32 - 2");
   const size_t n = (size_t)j->inst->h.n, P = j->h.P;
@@ -1220,7 +1271,7 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
     if (hj[i].stage == SGLB32 && (st = ensure_d32(c, in))) return st;
     const size_t n = (size_t)in->h.n, P = hj[i].P, Q = hj[i].Q;
     off[i] = total;
-    total += job_array_bytes(n, P, Q);
+    total += job_array_bytes(n, P, Q, hj[i].lex_levels != 0);
     max_q = std::max(max_q, hj[i].Q);
     max_n = std::max(max_n, in->h.n);
     max_mats = std::max(max_mats, heur_mats_of(in->h.kind));
@@ -1253,7 +1304,7 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
     else if (ih.kind == KVRP) cost = 8.0 * n;
     cost *= (double)hj[i].C * (double)hj[i].G;
     for (uint32_t s2 = 0; s2 < hj[i].P; ++s2)
-      recs.push_back(ItemRec{ih.kind, evolve_variant(ih.kind, hj[i].stage, hj[i].op_mask), hj[i].lds_bytes, cost,
+      recs.push_back(ItemRec{ih.kind, evolve_variant(ih.kind, hj[i].stage, hj[i].op_mask, hj[i].lex_levels), hj[i].lds_bytes, cost,
                              make_uint2((uint32_t)i, s2)});
   }
   std::vector<uint2> items(n_items);
@@ -1413,8 +1464,9 @@ struct SrvLane {
   bool wait_staged = false;
 };
 
-// lanes: (kind, staging) x LDS class x 3-opt in the operator set
-constexpr int kLanes = 9 * kLdsClasses * 2;
+// lanes: (kind, staging) x LDS class x 3-opt in the operator set, and the
+// VRPTW lexicographic kernels (LDS class x 3-opt)
+constexpr int kLanes = 9 * kLdsClasses * 2 + 2 * kLdsClasses;
 // epoch chunks a lane advances per quantum: the launches and the host's
 // turnaround are paid once per quantum, and a newly admitted request joins at
 // its lane's next quantum.  An epoch of TSP, knapsack or colouring takes tens
@@ -1424,6 +1476,7 @@ int lane_of(int kind, int var, uint32_t lds) {
   const int stage = var & 7;
   const int ks = kind == KTSP ? std::min(std::max(stage, 1), 4) - 1
                               : (kind == KQAP ? 4 + (stage == 1) : (kind == KKNAP ? 6 : (kind == KVRP ? 7 : 8)));
+  if (var & kVarLex) return 18 * kLdsClasses + ((var & kVarX3) ? kLdsClasses : 0) + lds_class(lds);
   return ((var & kVarX3) ? 9 * kLdsClasses : 0) + ks * kLdsClasses + lds_class(lds);
 }
 
@@ -1621,7 +1674,7 @@ void server_loop(gx_server *S) {
       recs.clear();
       for (SrvReq *r : act)
         for (uint32_t sl = 0; sl < r->hj.P; ++sl)
-          recs.push_back(ItemRec{r->kind, evolve_variant(r->kind, r->hj.stage, r->hj.op_mask), r->hj.lds_bytes, r->cost,
+          recs.push_back(ItemRec{r->kind, evolve_variant(r->kind, r->hj.stage, r->hj.op_mask, r->hj.lex_levels), r->hj.lds_bytes, r->cost,
                                  make_uint2((uint32_t)r->slot, sl)});
       if (make_groups(&S->gctx, recs, L.items_h[b], groups) != GX_OK || groups.size() != 1) continue;
       for (size_t a = 0; a < act.size(); ++a) L.slots_h[b][a] = (uint32_t)act[a]->slot;
@@ -1788,7 +1841,7 @@ gx_status gx_server_submit(gx_server *S, const gx_instance_desc *d, const gx_sol
   }
   r->n = r->pr.h.n;
   r->inst_bytes = (r->pr.dev_bytes() + 255) & ~size_t(255);
-  r->bytes = r->inst_bytes + job_array_bytes((size_t)r->n, r->hj.P, r->hj.Q);
+  r->bytes = r->inst_bytes + job_array_bytes((size_t)r->n, r->hj.P, r->hj.Q, r->hj.lex_levels != 0);
   r->pin_bytes = pad16(4 * (size_t)r->n + 8) + staging_bytes(r->pr) + pad16(sizeof(DevJob));
   if (r->bytes > S->arena.cap() || r->pin_bytes > S->pin_arena.cap()) {
     S->err = "request larger than the server arena";
@@ -1798,7 +1851,7 @@ gx_status gx_server_submit(gx_server *S, const gx_instance_desc *d, const gx_sol
   const double n = r->n;
   r->cost = (r->pr.h.kind == KQAP ? 4.0 * n * n / 3.0 : (r->pr.h.kind == KVRP ? 8.0 * n : n)) * r->hj.C;
   r->kind = r->pr.h.kind;
-  r->lane = lane_of(r->kind, evolve_variant(r->kind, r->hj.stage, r->hj.op_mask), r->hj.lds_bytes);
+  r->lane = lane_of(r->kind, evolve_variant(r->kind, r->hj.stage, r->hj.op_mask, r->hj.lex_levels), r->hj.lds_bytes);
   if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
     delete r;
     return GX_E_DEVICE;

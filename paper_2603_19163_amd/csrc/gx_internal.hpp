@@ -29,11 +29,13 @@ constexpr int kPermOps = 5;
 enum Stage : int32_t { SAUTO = 0, SLDS16 = 1, SLDSXY = 2, SGLB16 = 3, SGLB32 = 4 };
 // Evolve-kernel variant: the staging, plus kVarX3 when a permutation job's
 // operator set holds 3-opt (its loops are compiled apart from the others, so
-// that jobs without it carry none of its branches or wider counters).
-constexpr int kVarX3 = 8;
-inline int evolve_variant(int kind, uint32_t stage, uint32_t op_mask) {
+// that jobs without it carry none of its branches or wider counters), plus
+// kVarLex for a VRPTW instance in the lexicographic mode.
+constexpr int kVarX3 = 8, kVarLex = 16;
+inline int evolve_variant(int kind, uint32_t stage, uint32_t op_mask, uint32_t lex_levels) {
   const bool perm = kind == KTSP || kind == KQAP || kind == KVRP;
-  return (int)stage | ((perm && (op_mask & (1u << O3OPT))) ? kVarX3 : 0);
+  return (int)stage | ((perm && (op_mask & (1u << O3OPT))) ? kVarX3 : 0) |
+         ((kind == KVRP && lex_levels) ? kVarLex : 0);
 }
 
 // One uploaded instance.  All pointers are device pointers owned by the instance.
@@ -44,6 +46,9 @@ struct DevInst {
   int32_t qap_sums32;         // QAP: 2 n * max F * max D < 2^31 (delta row and pair sums fit int32)
   int32_t qap_h16, pad_q;     // QAP: n * max F * max D < 2^16 (row sums H fit 16 bits: staging 1)
   int32_t vw_d, vw_r, vw_m, pad_v;   // VRPTW objective weights: distance, routes, longest route
+  // VRPTW lexicographic mode: number of levels (0: the weighted mode), each
+  // level's objective (1 distance, 2 routes, 3 longest route) and tolerance
+  int32_t lex_levels, lex_id[3], lex_tol[3], pad_l;
   int64_t lambda;             // knapsack penalty weight
   const int32_t *xy;          // TSP n x 2 / VRPTW (n+1) x 2 coordinates
   const int16_t *d16;         // TSP n x n / VRPTW dn x dn distances (int16)
@@ -78,10 +83,12 @@ struct DevJob {
   uint32_t stage, lds_bytes, islands, mig_epochs;   // island model: see gx_solve_params
   uint32_t mig_mode, mig_n, elite_epochs, aos_scope;   // aos_scope: 0 instance, 1 per solution
   uint32_t init_w[kOps];      // caller's raw initial weights (0: Tab. weight_preset)
+  uint32_t lex_levels, pad_lex;   // levels of the lexicographic mode (0: scalar objective)
   // ---- mutable state
   uint32_t g, g_stop, stag, done;
   uint64_t T;
   int64_t epoch_ref, inst_best;
+  int64_t ref_v[4];           // lexicographic mode: the instance best's vector at the last epoch end
   uint32_t w_op[kOps], w_k[3], pad3;
   unsigned long long u_op[kOps], v_op[kOps], u_k[3], v_k[3];
   unsigned long long accepted;
@@ -96,6 +103,8 @@ struct DevJob {
   int32_t *best_out;          // n
   unsigned long long *shard;  // kShards x kEpochSlots per-launch accumulators
   SolAos *saos;               // P per-solution AOS records (used with aos_scope 1)
+  int64_t *cur_v, *best_v;    // lexicographic mode: P x 4 objective vectors (else null)
+  int64_t *pool_v;            // lexicographic mode: Q x 4 vectors of the initial pool
   int64_t best_out_f;
   int32_t best_idx, pad4;
 };

@@ -458,6 +458,84 @@ __device__ __forceinline__ int64_t vrp_objective(const DevInst *I, int64_t dist,
          10000 * (int64_t)max(0, routes - I->vehicles);
 }
 
+// Parts of a split giant tour's objective
+struct VrpParts {
+  int64_t dist, late;
+  int routes, longest;
+};
+
+// ---- lexicographic mode (paper, Sec. "Multi-Objective Optimization Modes";
+// Tab. lexicographic_mode).  A solution's objective vector is (penalty,
+// level 1, level 2, level 3): the penalty (lateness and fleet excess, as in
+// the weighted mode) compared exactly, then the caller's objectives in
+// priority order, two values within a level's tolerance counting as equal so
+// that the next level decides.  Unused levels are 0.
+struct Vec4 {
+  int64_t v[4];
+};
+struct LexCfg {
+  int levels;
+  int id[3];        // 1 distance, 2 routes, 3 longest route
+  int64_t tol[3];
+};
+
+__device__ __forceinline__ LexCfg lex_cfg(const DevInst *I) {
+  LexCfg L;
+  L.levels = I->lex_levels;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    L.id[i] = I->lex_id[i];
+    L.tol[i] = I->lex_tol[i];
+  }
+  return L;
+}
+
+__device__ __forceinline__ Vec4 lex_vector(const VrpParts &q, int vehicles, const LexCfg &L) {
+  Vec4 x;
+  x.v[0] = 100 * q.late + 10000 * (int64_t)max(0, q.routes - vehicles);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int id = i < L.levels ? L.id[i] : 0;
+    x.v[1 + i] = id == 1 ? q.dist : (id == 2 ? (int64_t)q.routes : (id == 3 ? (int64_t)q.longest : 0));
+  }
+  return x;
+}
+
+// a strictly better than b
+__device__ __forceinline__ bool lex_better(const Vec4 &a, const Vec4 &b, const LexCfg &L) {
+  if (a.v[0] != b.v[0]) return a.v[0] < b.v[0];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (i >= L.levels) break;
+    if (a.v[1 + i] + L.tol[i] < b.v[1 + i]) return true;
+    if (b.v[1 + i] + L.tol[i] < a.v[1 + i]) return false;
+  }
+  return false;
+}
+
+// The worsening a winner w brings against the current c (c strictly better
+// than w), for the acceptance test: the penalty difference when the
+// penalties differ, else the difference at the first level where c is better
+// than w by more than the tolerance.
+__device__ __forceinline__ int64_t lex_delta(const Vec4 &w, const Vec4 &c, const LexCfg &L) {
+  if (w.v[0] != c.v[0]) return w.v[0] - c.v[0];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    if (i < L.levels && c.v[1 + i] + L.tol[i] < w.v[1 + i]) return w.v[1 + i] - c.v[1 + i];
+  return 0;
+}
+
+__device__ __forceinline__ Vec4 load_vec(const int64_t *p) {
+  Vec4 x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) x.v[i] = p[i];
+  return x;
+}
+__device__ __forceinline__ void store_vec(int64_t *p, const Vec4 &x) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) p[i] = x.v[i];
+}
+
 struct VrpK {
   static constexpr int ENC = 0;
   uint16_t *cur, *nxt;
@@ -466,6 +544,10 @@ struct VrpK {
   const int32_t *dem, *rdy, *due;
   const DevInst *I;
   __device__ __forceinline__ int64_t eval(const Step *st, int k) const {
+    const VrpParts q = parts(st, k);
+    return vrp_objective(I, q.dist, q.routes, q.longest, q.late);
+  }
+  __device__ __forceinline__ VrpParts parts(const Step *st, int k) const {
     int64_t dist = 0, late = 0;
     int t = 0, load = 0, routes = 0, prev = 0, len = 0, longest = 0;   // route lengths < 251 * 23171
     for (int p = 0; p < n; ++p) {
@@ -501,7 +583,7 @@ struct VrpK {
       late += max(0, t - hor);
       longest = max(longest, len + back);
     }
-    return vrp_objective(I, dist, routes, longest, late);
+    return VrpParts{dist, late, routes, longest};
   }
   __device__ __forceinline__ int64_t delta(const Step *st, int k, int64_t f) const {
     return eval(st, k) - f;
@@ -614,12 +696,15 @@ struct ColorK {
 // Every TSP operator is one or two "pattern" steps that share one delta
 // formula: 2-opt is a reversal, a swap of non-adjacent positions is the
 // reversal of [lo, hi] followed by that of [lo+1, hi-1], insert / or-opt is a
-// block move.  Per chunk of 128 candidates the wave draws all first steps,
-// then the extra steps of the candidates with k >= 2 compacted onto the lanes,
-// builds the list of pattern steps grouped by their position in the composite,
+// block move.  Per chunk of 128 candidates the wave draws all first steps
+// (evaluated on the candidates' own lanes from the drawn registers), then the
+// extra steps of the candidates with k >= 2 compacted onto the lanes, builds
+// the list of pattern steps grouped by their position in the composite,
 // evaluates it with all lanes busy, and sums each candidate's delta with LDS
 // atomics.  Draws, moves and deltas are those of the per-candidate
-// formulation; only the order of evaluation differs.
+// formulation; only the order of evaluation differs.  (Evaluating each extra
+// step's patterns on the lane that drew it, without the grouped list, ran
+// slower: swaps and third steps diverge within the wave.)
 constexpr int kChunk = 128;
 // tables (positions, deltas, pattern list, operator bytes), then for 3-opt
 // variants the block lengths of the steps
@@ -710,10 +795,12 @@ __device__ __forceinline__ void store_step(const TspScratch &W, uint32_t idx, co
 // every candidate on its own lane (t = c0 + r*64 + lane), then the extra steps
 // of the candidates with k >= 2 and k >= 3 compacted onto consecutive lanes,
 // so that the wave computes about as many Philox blocks as there are steps.
-// Steps land in the LDS tables; kk[r] receives k of the lane's candidates.
+// Steps land in the LDS tables; kk[r] receives k of the lane's candidates,
+// first[r] (when given) their first steps.  Returns the length of the list of
+// extra steps (candidate | step << 8 at dl + 128 rb).
 template <int ENC, bool X3, int RN = 2>
-__device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, uint32_t g, uint32_t sol, uint32_t c0,
-                                           uint32_t cn, int kk[RN], uint32_t rb = 0) {
+__device__ __forceinline__ uint32_t draw_chunk(const TspScratch &W, const Uni &U, uint32_t g, uint32_t sol, uint32_t c0,
+                                               uint32_t cn, int kk[RN], uint32_t rb = 0, Step *first = nullptr) {
   // rounds rb .. rb + RN - 1 of the chunk (64 candidates each) on this wave;
   // its extra-step list at dl + 128 rb
   const uint32_t lane = lane_id();
@@ -728,6 +815,7 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
       kk[rr] = pick_k(w[0], U);
       const Step st = make_step<ENC, X3>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
       store_step<ENC, X3>(W, 3 * tl, st, (uint32_t)kk[rr] << 6);
+      if (first) first[rr] = st;
       if constexpr (RN == 2) W.del()[tl] = 0;
     }
   }
@@ -750,6 +838,7 @@ __device__ __forceinline__ void draw_chunk(const TspScratch &W, const Uni &U, ui
     store_step<ENC, X3>(W, 3 * tl + m, st, 0u);
   }
   __syncthreads();
+  return nx;
 }
 
 // step m of candidate t from the tables (integer values are stored as int16)
@@ -833,11 +922,9 @@ __device__ __forceinline__ void edges_fill(uint16_t *el, const uint16_t *tour, i
 //                  u = (X-1, B, B-1, Z-1, X, Z), pairs 0, 1 (as (u2,u5)) and 2,
 //                  removed edges X-1, B-1, Z-1.
 // Zero patterns as in pattern_delta.
-template <bool X3, class DF>
-__device__ __forceinline__ int first_step_delta(const TspScratch &W, const uint16_t *tour, const uint16_t *el, int n,
-                                                const DF &D, int t) {
-  int op, a, b, L;
-  unpack_step<X3>(W, t, 0, op, a, b, L);
+template <class DF>
+__device__ __forceinline__ int first_step_delta(const uint16_t *tour, const uint16_t *el, int n, const DF &D, int op,
+                                                int a, int b, int L) {
   const bool mv = op >= OINS;
   const bool adj = op == OSWAP && b - a == 1;
   const bool cyc = op == OSWAP && !adj && a == 0 && b == n - 1;
@@ -941,13 +1028,14 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
     for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
       const uint32_t cn = min((uint32_t)kChunk, U.C - c0);
       int kk[2];
-      draw_chunk<0, X3>(W, U, g, sol, c0, cn, kk);
-      // ---- first steps: one per candidate, on its own lane
+      Step s0[2];
+      draw_chunk<0, X3>(W, U, g, sol, c0, cn, kk, 0, s0);
+      // ---- first steps: one per candidate, on its own lane, from the drawn step
       int d0[2];
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const uint32_t tl = r * kWave + lane;
-        d0[r] = (tl < cn && n >= 2) ? first_step_delta<X3>(W, cur, el, n, D, (int)tl) : 0;
+        d0[r] = (tl < cn && n >= 2) ? first_step_delta(cur, el, n, D, s0[r].op, s0[r].a, s0[r].b, s0[r].c) : 0;
       }
       // ---- later steps of k >= 2 candidates: (candidate, step, pattern)
       // entries, grouped by step, evaluated through the position maps
@@ -989,8 +1077,9 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
         if (U.credit == 0 && valid) {
           const bool imp = d < 0;
 #pragma unroll
-          for (int m = 0; m < 3; ++m) {
-            const OpCount<X3> inc = kk[r] > m ? (OpCount<X3>)1 << ((W.sop()[3 * tl + m] & 7u) << 3) : (OpCount<X3>)0;
+          for (int m = 0; m < 3; ++m) {   // the first step's operator is in registers
+            const uint32_t opm = m == 0 ? (uint32_t)s0[r].op : (W.sop()[3 * tl + m] & 7u);
+            const OpCount<X3> inc = kk[r] > m ? (OpCount<X3>)1 << (opm << 3) : (OpCount<X3>)0;
             cu_op += inc;
             cv_op += imp ? inc : (OpCount<X3>)0;
           }
@@ -1530,6 +1619,96 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
 
+__device__ __forceinline__ int64_t readlane64(int64_t x, uint32_t l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (int)l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), (int)l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Generations of a VRPTW solution in the lexicographic mode (Alg. 1 with the
+// comparisons of that mode).  Each lane evaluates its candidates' objective
+// vectors; the winner is the first candidate, in index order, that no later
+// candidate is strictly better than the one kept so far (the comparison has
+// tolerances and is not transitive, so the scan runs in order: after every
+// round of 64 candidates the wave walks its lanes one by one, reading each
+// vector into scalar registers).  A winner that the current solution does not
+// beat is accepted; a worse one passes the exponential test on lex_delta.  A
+// candidate improves when it is strictly better than the current solution.
+// The scalar f reported for a solution is its penalty plus its first level.
+template <bool X3>
+__device__ __forceinline__ void lex_gens(VrpK &kd, const TspScratch &W, const Uni &U, const LexCfg &L,
+                                         int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1, uint64_t &T,
+                                         int64_t &f, int64_t &bf, Vec4 &cv, Vec4 &bsv, LStats &S, uint32_t &nacc) {
+  constexpr int ENC = 0;
+  constexpr int nf = X3 ? kPermOps : 4;
+  const uint32_t lane = lane_id();
+  OpCount<X3> cu = 0, cvc = 0;
+  uint32_t cuk = 0, cvk = 0, since_fold = 0;
+  for (uint32_t g = g0; g < g1; ++g) {
+    Vec4 bv = {};
+    uint32_t bt = 0;
+    bool have = false;
+    for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
+      const uint32_t cn = min((uint32_t)kChunk, U.C - c0);
+      int kk[2];
+      draw_chunk<ENC, X3>(W, U, g, sol, c0, cn, kk);
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const uint32_t r0 = (uint32_t)r * kWave;
+        if (r0 >= cn) break;
+        const uint32_t tl = r0 + lane;
+        Vec4 v = {};
+        if (tl < cn) {
+          Step st[3];
+          st[0] = load_step<ENC, X3>(W, (int)tl, 0);
+          st[1] = kk[r] > 1 ? load_step<ENC, X3>(W, (int)tl, 1) : st[0];
+          st[2] = kk[r] > 2 ? load_step<ENC, X3>(W, (int)tl, 2) : st[0];
+          v = lex_vector(kd.parts(st, kk[r]), kd.veh, L);
+          if (U.credit == 0) credit_bytes<ENC, X3>(cu, cvc, cuk, cvk, st, kk[r], lex_better(v, cv, L));
+        }
+        const uint32_t cnt = min((uint32_t)kWave, cn - r0);
+        for (uint32_t j = 0; j < cnt; ++j) {
+          Vec4 x;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) x.v[i] = readlane64(v.v[i], j);
+          if (!have || lex_better(x, bv, L)) {
+            bv = x;
+            bt = c0 + r0 + j;
+            have = true;
+          }
+        }
+      }
+      if (++since_fold == 42) {
+        fold_ops<X3>(S.u, S.v, cu, cvc, nf);
+        fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
+        cu = cvc = 0;
+        cuk = cvk = 0;
+        since_fold = 0;
+      }
+      __syncthreads();
+    }
+    bool acc = !lex_better(cv, bv, L);
+    if (!acc) acc = accept_worse(lex_delta(bv, cv, L), T, g, sol, U);
+    if (acc) {
+      Step st[3];
+      const int k = sample<ENC, X3>(U, g, sol, bt, st);
+      if (U.credit == 1) credit<ENC>(S, st, k, lex_better(bv, cv, L));
+      kd.apply(st, k);
+      cv = bv;
+      f = bv.v[0] + bv.v[1];
+      ++nacc;
+      if (lex_better(cv, bsv, L)) {
+        bsv = cv;
+        bf = f;
+        kd.store(best_row);
+      }
+    }
+    T = cool(T, U.alpha);
+  }
+  fold_ops<X3>(S.u, S.v, cu, cvc, nf);
+  fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
+}
+
 // ------------------------------------------------------------ epoch close
 // floor(num / den) for den > 0, exact: a double quotient below 2^24 is within
 // 2^-27 of num / den, so its floor is off by at most one and one integer
@@ -1805,6 +1984,30 @@ __device__ void migrate_block(DevJob *J, uint32_t e, MigLds &M) {
   }
 }
 
+// Lexicographic mode: the population's best by the ordered scan over the
+// solutions' best vectors (index order; a later solution replaces the one
+// kept only when strictly better).  Every lane that calls it returns the same
+// index.  The vectors are read eight solutions at a time.
+__device__ __forceinline__ uint32_t lex_scan_best(const DevJob *J, const LexCfg &L) {
+  const uint32_t P = J->P;
+  const int64_t *bv = J->best_v;
+  Vec4 keep = load_vec(bv);
+  uint32_t b = 0;
+  constexpr uint32_t kB = 8;
+  for (uint32_t s0 = 1; s0 < P; s0 += kB) {
+    Vec4 x[kB];
+#pragma unroll
+    for (uint32_t u = 0; u < kB; ++u) x[u] = s0 + u < P ? load_vec(bv + 4 * (size_t)(s0 + u)) : keep;
+#pragma unroll
+    for (uint32_t u = 0; u < kB; ++u)
+      if (s0 + u < P && lex_better(x[u], keep, L)) {
+        keep = x[u];
+        b = s0 + u;
+      }
+  }
+  return b;
+}
+
 // After each evolve launch: fold the accumulator rows of every job into its
 // epoch statistics, the instance best and the temperature, and at an epoch
 // boundary apply the AOS update (the kernel boundary orders it after every
@@ -1836,6 +2039,9 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
   // per-solution weights: the evolve workgroups update them; the instance
   // statistics and weights stay as initialised
   const bool inst_scope = J->aos_scope == 0;
+  const bool lex = J->lex_levels != 0;
+  const LexCfg L = lex_cfg(J->inst);
+  Vec4 ref_v = load_vec(J->ref_v);
   uint32_t stag = J->stag;
   uint64_t T = J->T;
   int64_t inst_best = J->inst_best, epoch_ref = J->epoch_ref;
@@ -1878,9 +2084,18 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
   if (g1 % E == 0 && inst_scope) {
     ema_group(w_op, u_op, v_op, op_mask, kOps, aos_A, w_floor);
     ema_group(w_k, u_k, v_k, 7u, 3, aos_A, w_floor);
-    if (inst_best < epoch_ref) stag = 0;
+    bool improved = inst_best < epoch_ref;
+    int64_t ref_now = inst_best;
+    if (lex) {   // the instance best by the ordered scan; improved when strictly better than the last one
+      const uint32_t b = lex_scan_best(J, L);
+      const Vec4 now = load_vec(J->best_v + 4 * (size_t)b);
+      improved = lex_better(now, ref_v, L);
+      ref_v = now;
+      ref_now = J->best_f[b];
+    }
+    if (improved) stag = 0;
     else stag += 1;
-    epoch_ref = inst_best;
+    epoch_ref = ref_now;
     if (stag >= stag_limit) {
       w_k[0] = 52429; w_k[1] = 9830; w_k[2] = 3277;
       stag = 0;
@@ -1907,6 +2122,7 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
     J->w_k[q] = w_k[q];
   }
   J->accepted = accepted + t[2 * kOps + 6];
+  if (lex) store_vec(J->ref_v, ref_v);
   J->inst_best = inst_best;
   J->epoch_ref = epoch_ref;
   J->stag = stag;
@@ -2132,8 +2348,19 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       stage16(due, I->due, 4u * dn);
       __syncthreads();
       VrpK kd{t0, t1, n, dn, I->capacity, I->vehicles, I->service, I->horizon, D, dem, rdy, due, I};
-      if constexpr (x3) run_gens<true>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
-      else run_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+      if constexpr ((VAR & kVarLex) != 0) {
+        const LexCfg L = lex_cfg(I);
+        Vec4 cv = load_vec(J->cur_v + 4 * (size_t)sol), bsv = load_vec(J->best_v + 4 * (size_t)sol);
+        lex_gens<x3>(kd, W, U, L, best_row, sol, g0, g1, T, f, bf, cv, bsv, S, nacc);
+        if (threadIdx.x == 0) {
+          store_vec(J->cur_v + 4 * (size_t)sol, cv);
+          store_vec(J->best_v + 4 * (size_t)sol, bsv);
+        }
+      } else if constexpr (x3) {
+        run_gens<true>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+      } else {
+        run_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+      }
       perm_store(kd.cur, n, cur_g);
     }
   } else if constexpr (KIND == KKNAP) {
@@ -2221,6 +2448,8 @@ __device__ __forceinline__ int glb_tsp_dist(const DevInst *I, int a, int b) {
   return nint_dist(xy[a], xy[b]);
 }
 
+__device__ VrpParts vrp_parts_of(const DevInst *I, const int32_t *x);
+
 // full objective of one solution, by its definition (initial pool only)
 __device__ int64_t full_objective(const DevInst *I, const int32_t *x) {
   const int n = I->n;
@@ -2248,6 +2477,18 @@ __device__ int64_t full_objective(const DevInst *I, const int32_t *x) {
     return -V + I->lambda * (over > 0 ? over : 0);
   }
   if (I->kind == KVRP) {
+    const VrpParts q = vrp_parts_of(I, x);
+    return vrp_objective(I, q.dist, q.routes, q.longest, q.late);
+  }
+  int64_t f = 0;
+  for (int e = 0; e < I->n_edges; ++e) f += x[I->edges[2 * e]] == x[I->edges[2 * e + 1]];
+  return f;
+}
+
+// parts of a VRPTW giant tour's objective, from the instance's global arrays
+__device__ VrpParts vrp_parts_of(const DevInst *I, const int32_t *x) {
+  const int n = I->n;
+  {
     const int dn = I->dn;
     int64_t dist = 0, late = 0;
     int t = 0, load = 0, routes = 0, prev = 0, len = 0, longest = 0;
@@ -2283,11 +2524,8 @@ __device__ int64_t full_objective(const DevInst *I, const int32_t *x) {
       late += max(0, t - I->horizon);
       longest = max(longest, len + back);
     }
-    return vrp_objective(I, dist, routes, longest, late);
+    return VrpParts{dist, late, routes, longest};
   }
-  int64_t f = 0;
-  for (int e = 0; e < I->n_edges; ++e) f += x[I->edges[2 * e]] == x[I->edges[2 * e + 1]];
-  return f;
 }
 
 __device__ __forceinline__ int heur_mats(int kind) {
@@ -2376,21 +2614,50 @@ __global__ __launch_bounds__(64) void k_init_eval(DevJob *jobs) {
   DevJob *J = jobs + blockIdx.y;
   const uint32_t q = blockIdx.x * 64 + threadIdx.x;
   if (q >= J->Q) return;
-  J->pool_f[q] = full_objective(J->inst, J->pool + (size_t)q * J->inst->n);
+  const int32_t *x = J->pool + (size_t)q * J->inst->n;
+  if (J->lex_levels) {   // the vector, and as the scalar its penalty plus its first level
+    const Vec4 v = lex_vector(vrp_parts_of(J->inst, x), J->inst->vehicles, lex_cfg(J->inst));
+    store_vec(J->pool_v + 4 * (size_t)q, v);
+    J->pool_f[q] = v.v[0] + v.v[1];
+    return;
+  }
+  J->pool_f[q] = full_objective(J->inst, x);
 }
 
-// keep the P best of the pool, ordered by (f, pool index)
+// vector a before vector b, level by level without tolerances (a total order)
+__device__ __forceinline__ int vec_cmp(const Vec4 &a, const Vec4 &b) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    if (a.v[i] != b.v[i]) return a.v[i] < b.v[i] ? -1 : 1;
+  return 0;
+}
+
+// keep the P best of the pool, ordered by (f, pool index), or in the
+// lexicographic mode by (vector, pool index)
 __global__ __launch_bounds__(64) void k_init_select(DevJob *jobs) {
   DevJob *J = jobs + blockIdx.y;
   const uint32_t q = blockIdx.x * 64 + threadIdx.x;
   if (q >= J->Q) return;
   const int64_t fq = J->pool_f[q];
   uint32_t rank = 0;
-  for (uint32_t o = 0; o < J->Q; ++o) {
-    const int64_t fo = J->pool_f[o];
-    rank += (fo < fq) || (fo == fq && o < q);
+  if (J->lex_levels) {
+    const Vec4 vq = load_vec(J->pool_v + 4 * (size_t)q);
+    for (uint32_t o = 0; o < J->Q; ++o) {
+      const int c = vec_cmp(load_vec(J->pool_v + 4 * (size_t)o), vq);
+      rank += c < 0 || (c == 0 && o < q);
+    }
+  } else {
+    for (uint32_t o = 0; o < J->Q; ++o) {
+      const int64_t fo = J->pool_f[o];
+      rank += (fo < fq) || (fo == fq && o < q);
+    }
   }
   if (rank >= J->P) return;
+  if (J->lex_levels) {
+    const Vec4 vq = load_vec(J->pool_v + 4 * (size_t)q);
+    store_vec(J->cur_v + 4 * (size_t)rank, vq);
+    store_vec(J->best_v + 4 * (size_t)rank, vq);
+  }
   const int n = J->inst->n;
   const int32_t *src = J->pool + (size_t)q * n;
   int32_t *c = J->cur + (size_t)rank * n, *b = J->best + (size_t)rank * n;
@@ -2456,6 +2723,8 @@ __global__ void k_init_final(DevJob *jobs, int count) {
   J->accepted = 0;
   J->epoch_ref = f0;
   J->inst_best = f0;
+  if (J->lex_levels)
+    for (int i = 0; i < 4; ++i) J->ref_v[i] = J->cur_v[i];
 }
 
 __global__ void k_set_stop(DevJob *jobs, int count, uint32_t add, int use_total) {
@@ -2465,26 +2734,32 @@ __global__ void k_set_stop(DevJob *jobs, int count, uint32_t add, int use_total)
   J->g_stop = use_total ? J->G : J->g_stop + add;
 }
 
-// best solution of each job: min of (best_f, index)
+// best solution of each job: min of (best_f, index), or in the
+// lexicographic mode the ordered scan over the best vectors
 __global__ __launch_bounds__(64) void k_best(DevJob *jobs) {
   DevJob *J = jobs + blockIdx.x;
   const uint32_t lane = threadIdx.x;
   int64_t bf = INT64_MAX;
   uint32_t bi = 0xFFFFFFFFu;
-  for (uint32_t s = lane; s < J->P; s += 64) {
-    const int64_t f = J->best_f[s];
-    if (f < bf) {
-      bf = f;
-      bi = s;
+  if (J->lex_levels) {
+    bi = lex_scan_best(J, lex_cfg(J->inst));
+    bf = J->best_f[bi];
+  } else {
+    for (uint32_t s = lane; s < J->P; s += 64) {
+      const int64_t f = J->best_f[s];
+      if (f < bf) {
+        bf = f;
+        bi = s;
+      }
     }
-  }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const int64_t of = __shfl_xor(bf, o, 64);
-    const uint32_t oi = __shfl_xor(bi, o, 64);
-    if (of < bf || (of == bf && oi < bi)) {
-      bf = of;
-      bi = oi;
+    for (int o = 32; o > 0; o >>= 1) {
+      const int64_t of = __shfl_xor(bf, o, 64);
+      const uint32_t oi = __shfl_xor(bi, o, 64);
+      if (of < bf || (of == bf && oi < bi)) {
+        bf = of;
+        bi = oi;
+      }
     }
   }
   const int n = J->inst->n;
@@ -2598,7 +2873,7 @@ hipError_t set_stop(DevJob *jobs, int count, uint32_t add, int use_total, hipStr
   return hipGetLastError();
 }
 
-// the kernel of a (kind, variant): variant = staging | kVarX3 (3-opt)
+// the kernel of a (kind, variant): variant = staging | kVarX3 (3-opt) | kVarLex (VRPTW lexicographic)
 #define GX_KERNEL_OF(KERNEL)                                                                 \
   static const void *KERNEL##_of(int kind, int var) {                                      \
     const bool x3 = (var & kVarX3) != 0;                                                     \
@@ -2614,7 +2889,9 @@ hipError_t set_stop(DevJob *jobs, int count, uint32_t add, int use_total, hipStr
         if ((var & 7) == 1) return x3 ? (const void *)KERNEL<KQAP, 1 | kVarX3> : (const void *)KERNEL<KQAP, 1>;    \
         return x3 ? (const void *)KERNEL<KQAP, kVarX3> : (const void *)KERNEL<KQAP, 0>;   \
       case KKNAP: return (const void *)KERNEL<KKNAP, 0>;                                     \
-      case KVRP: return x3 ? (const void *)KERNEL<KVRP, kVarX3> : (const void *)KERNEL<KVRP, 0>; \
+      case KVRP:                                                                             \
+        if (var & kVarLex) return x3 ? (const void *)KERNEL<KVRP, kVarLex | kVarX3> : (const void *)KERNEL<KVRP, kVarLex>; \
+        return x3 ? (const void *)KERNEL<KVRP, kVarX3> : (const void *)KERNEL<KVRP, 0>;   \
       default: return (const void *)KERNEL<KCOLOR, 0>;                                      \
     }                                                                                        \
   }
@@ -2631,7 +2908,7 @@ hipError_t prepare_kernel_attrs(uint32_t max_lds) {
                           {KKNAP, 0},              {KVRP, 0},               {KCOLOR, 0},
                           {KTSP, SLDS16 | kVarX3}, {KTSP, SLDSXY | kVarX3}, {KTSP, SGLB16 | kVarX3},
                           {KTSP, SGLB32 | kVarX3}, {KQAP, kVarX3},          {KQAP, 1 | kVarX3},
-                          {KVRP, kVarX3}};
+                          {KVRP, kVarX3},          {KVRP, kVarLex},         {KVRP, kVarLex | kVarX3}};
   for (auto &k : kinds) {
     hipError_t e = hipFuncSetAttribute(plain_kernel(k[0], k[1]), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)max_lds);

@@ -23,7 +23,7 @@ N_OPS = 12
 EXPORTED = ["gx_create", "gx_destroy", "gx_last_error", "gx_get_device_info", "gx_instance_upload",
             "gx_instance_free", "gx_autosize_population", "gx_job_create", "gx_job_advance", "gx_solve",
             "gx_solve_static", "gx_wait", "gx_poll", "gx_fetch_best", "gx_portfolio_best", "gx_job_info_get", "gx_job_stats",
-            "gx_job_population", "gx_snapshot", "gx_snapshot_aos", "gx_job_restore", "gx_job_free",
+            "gx_job_population", "gx_snapshot", "gx_snapshot_aos", "gx_snapshot_lex", "gx_job_restore", "gx_job_free",
             "gx_solve_batch", "gx_exp_tables", "gx_device_check", "gx_measure_peaks", "gx_server_create", "gx_server_submit", "gx_server_poll",
             "gx_server_cancel", "gx_server_stats_get", "gx_server_destroy"]
 
@@ -40,7 +40,7 @@ class gx_instance_desc(C.Structure):
                 ("a_is_coords", C.c_int32), ("capacity", C.c_int32), ("vehicles", C.c_int32),
                 ("service_time", C.c_int32), ("horizon", C.c_int32), ("lb", C.c_int32),
                 ("ub", C.c_int32), ("n_edges", C.c_int32), ("instance_key", C.c_uint32),
-                ("obj_weights", C.c_int32 * 3)]
+                ("obj_weights", C.c_int32 * 3), ("lex_order", C.c_int32 * 3), ("lex_tol", C.c_int32 * 3)]
 
 
 class gx_solve_params(C.Structure):
@@ -145,6 +145,7 @@ def lib():
             "gx_job_population": ([vp, vp, C.POINTER(u32)], i32),
             "gx_snapshot": ([vp, vp, C.POINTER(gx_state_scalars), vp, vp, vp, vp], i32),
             "gx_snapshot_aos": ([vp, vp, vp], i32),
+            "gx_snapshot_lex": ([vp, vp, vp, vp, vp], i32),
             "gx_job_restore": ([vp, vp, C.POINTER(gx_state_scalars), vp, vp, vp, vp, vp], i32),
             "gx_job_free": ([vp, vp], i32),
             "gx_solve_batch": ([vp, pp, C.POINTER(gx_solve_params), i32, pp], i32),
@@ -254,7 +255,9 @@ def _desc(inst, keep):
                             horizon=getattr(inst, "horizon", 0), lb=getattr(inst, "lb", 0),
                             ub=getattr(inst, "ub", 0), n_edges=getattr(inst, "n_edges", 0),
                             instance_key=getattr(inst, "key", 0) & 0xFFFFFFFF,
-                            obj_weights=(C.c_int32 * 3)(*getattr(inst, "obj_weights", (0, 0, 0))))
+                            obj_weights=(C.c_int32 * 3)(*getattr(inst, "obj_weights", (0, 0, 0))),
+                            lex_order=(C.c_int32 * 3)(*getattr(inst, "lex_order", (0, 0, 0))),
+                            lex_tol=(C.c_int32 * 3)(*getattr(inst, "lex_tol", (0, 0, 0))))
 
 
 def gx_instance_upload(ctx, inst):
@@ -382,6 +385,16 @@ def gx_snapshot_aos(ctx, job, P: int) -> np.ndarray:
     out = np.zeros(P, SOL_AOS)
     _check(ctx, lib().gx_snapshot_aos(ctx, job, out.ctypes.data))
     return out
+
+
+def gx_snapshot_lex(ctx, job, P: int) -> dict:
+    """Objective vectors of a job in the VRPTW lexicographic mode: "cur_v" and
+    "best_v" (P x 4 int64), "ref_v" (4 int64)."""
+    cur_v = np.zeros((P, 4), np.int64)
+    best_v = np.zeros((P, 4), np.int64)
+    ref_v = np.zeros(4, np.int64)
+    _check(ctx, lib().gx_snapshot_lex(ctx, job, cur_v.ctypes.data, best_v.ctypes.data, ref_v.ctypes.data))
+    return {"cur_v": cur_v, "best_v": best_v, "ref_v": ref_v}
 
 
 def gx_job_restore(ctx, job, st: dict):

@@ -147,3 +147,10 @@ def test_run_invariants_and_threaded_runner():
     assert f == a["best_f"][i]
     for s in range(i + 1, p.population):      # nothing after the kept index beats it
         assert not o.lex_better(a["best_v"][s], a["best_v"][i])
+
+
+def test_islands_and_solution_scope_are_refused():
+    o = oracle.OracleInstance(vrptw(10, 2, lex_order=(DIST, 0, 0), lex_tol=(0, 0, 0)))
+    for kw in (dict(islands=2), dict(aos_scope=1), dict(elite_epochs=2)):
+        with pytest.raises(ValueError):
+            o.init(synth.Params(seed=1, population=4, candidates=64, generations=4, **kw))
