@@ -421,6 +421,8 @@ def bench_kinds(args):
         ("vrptw100", "VRPTW 100 customers, giant tour + split, P=64, 5000 generations", synth.c3_vrptw()),
         ("vrptw100_weighted", "same, weighted objectives 6 distance + 2 routes + 2 longest route",
          (dataclasses.replace(synth.c3_vrptw()[0], obj_weights=(6, 2, 2)), synth.c3_vrptw()[1])),
+        ("vrptw100_lex", "same, lexicographic: routes, then distance within 20, then longest route",
+         (dataclasses.replace(synth.c3_vrptw()[0], lex_order=(2, 1, 3), lex_tol=(0, 20, 0)), synth.c3_vrptw()[1])),
         ("qap50", "QAP n=50, P autosized, 2000 generations", one(synth.qap_random(50, 7), 0, 2000)),
     ]
     kp_inst, kp = one(synth.knapsack_random(1000, 7), 2048, 5000)

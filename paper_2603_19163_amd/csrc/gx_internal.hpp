@@ -138,7 +138,7 @@ inline uint32_t lds_bytes_for(int kind, int n, int var) {
              2 * (16 * kWave + al(lst) + al(2 * lst));
     }
     case KKNAP: return tables + al(un) + 2 * al(4 * un);
-    case KVRP: return tables + tours + al(2 * (un + 1) * (un + 1)) + 3 * al(4 * (un + 1));
+    case KVRP: return tables + tours + al(2 * (un + 1) * (un + 1)) + 16 * (un + 1) + 16;   // + chunk minima
     default: return tables + al(2 * un) + al(4 * (un + 1));   // + adjacency, added by the caller
   }
 }

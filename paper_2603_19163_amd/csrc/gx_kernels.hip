@@ -77,9 +77,10 @@ __device__ __forceinline__ uint32_t rmap(uint32_t w, uint32_t m) { return __umul
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 // threads of an evolve workgroup: two wavefronts for QAP (they share the
-// solution and split the delta entries), one for the other kinds
-template <int KIND>
-constexpr int kThreads = KIND == KQAP ? 128 : 64;
+// solution and split the delta entries) and for VRPTW in the weighted mode
+// (one candidate per lane), one for the other kinds
+template <int KIND, int VAR = 0>
+constexpr int kThreads = (KIND == KQAP || (KIND == KVRP && !(VAR & kVarLex))) ? 128 : 64;
 // LDS written by this wave visible to all of its lanes (a wave's LDS accesses
 // are performed in order; this only keeps the compiler from reordering them)
 __device__ __forceinline__ void wave_sync() {
@@ -458,6 +459,8 @@ __device__ __forceinline__ int64_t vrp_objective(const DevInst *I, int64_t dist,
          10000 * (int64_t)max(0, routes - I->vehicles);
 }
 
+struct TspScratch;
+
 // Parts of a split giant tour's objective
 struct VrpParts {
   int64_t dist, late;
@@ -536,58 +539,60 @@ __device__ __forceinline__ void store_vec(int64_t *p, const Vec4 &x) {
   for (int i = 0; i < 4; ++i) p[i] = x.v[i];
 }
 
+// The candidate's giant tour is read through its position maps and split in
+// one pass; each customer's demand, ready and due times come in one 16-byte
+// LDS read, and the three distances a position may need (previous customer
+// to this one, previous customer to the depot, depot to this one) are read
+// before the route-break test, which then only selects among them.  Two
+// waves per solution evaluate one candidate per lane (round by round).
 struct VrpK {
   static constexpr int ENC = 0;
   uint16_t *cur, *nxt;
   int n, dn, cap, veh, svc, hor;
   const int16_t *D;
-  const int32_t *dem, *rdy, *due;
+  const int4 *attr;   // (demand, ready, due, 0) per node
   const DevInst *I;
   __device__ __forceinline__ int64_t eval(const Step *st, int k) const {
     const VrpParts q = parts(st, k);
     return vrp_objective(I, q.dist, q.routes, q.longest, q.late);
   }
   __device__ __forceinline__ VrpParts parts(const Step *st, int k) const {
-    int64_t dist = 0, late = 0;
-    int t = 0, load = 0, routes = 0, prev = 0, len = 0, longest = 0;   // route lengths < 251 * 23171
+    int64_t late = 0;
+    // distances, times and route lengths stay below 2^31 (n <= 250, entries < 2^15, times <= 2^19)
+    int dist = 0, t = 0, load = 0, routes = n > 0 ? 1 : 0, prev = 0, len = 0, longest = 0;
     for (int p = 0; p < n; ++p) {
       const int c = cur[chain(st, k, p)] + 1;
-      const int q = dem[c];
-      if (routes == 0 || load + q > cap) {
-        if (routes > 0) {
-          const int back = D[prev * dn];
-          dist += back;
-          t += back;
-          late += max(0, t - hor);
-          longest = max(longest, len + back);
-        }
-        ++routes;
-        load = 0;
-        t = 0;
-        prev = 0;
-        len = 0;
-      }
-      const int dd = D[prev * dn + c];
+      const int4 a = attr[c];
+      const int dpc = D[prev * dn + c], dp0 = D[prev * dn], d0c = D[c];
+      // a demand never exceeds the capacity, so the first customer opens no second route
+      const bool brk = load + a.x > cap;
+      late += brk ? max(0, t + dp0 - hor) : 0;
+      longest = brk ? max(longest, len + dp0) : longest;
+      dist += brk ? dp0 : 0;
+      routes += brk ? 1 : 0;
+      t = brk ? 0 : t;
+      len = brk ? 0 : len;
+      load = brk ? 0 : load;
+      const int dd = brk ? d0c : dpc;
       dist += dd;
       len += dd;
-      t = max(t + dd, rdy[c]);
-      late += max(0, t - due[c]);
+      t = max(t + dd, a.y);
+      late += max(0, t - a.z);
       t += svc;
-      load += q;
+      load += a.x;
       prev = c;
     }
-    if (routes > 0) {
+    if (n > 0) {
       const int back = D[prev * dn];
       dist += back;
-      t += back;
-      late += max(0, t - hor);
+      late += max(0, t + back - hor);
       longest = max(longest, len + back);
     }
     return VrpParts{dist, late, routes, longest};
   }
-  __device__ __forceinline__ int64_t delta(const Step *st, int k, int64_t f) const {
-    return eval(st, k) - f;
-  }
+  // the delta of this lane's candidate of the wave's round (k = 0: no candidate)
+  template <bool X3>
+  __device__ __forceinline__ int64_t delta_round(const TspScratch &W, int tl, int k, int64_t f) const;
   __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, st, k); }
   __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
 };
@@ -857,6 +862,16 @@ __device__ __forceinline__ Step load_step(const TspScratch &W, int t, int m) {
 // delta of pattern step `sub` of operator m of candidate t, on the tour after
 // all earlier steps of that candidate (MAPPED: m >= 1, whose read positions
 // are mapped back through steps m-1 .. 0)
+template <bool X3>
+__device__ __forceinline__ int64_t VrpK::delta_round(const TspScratch &W, int tl, int k, int64_t f) const {
+  if (k == 0) return 0;
+  Step st[3];
+  st[0] = load_step<ENC, X3>(W, tl, 0);
+  st[1] = k > 1 ? load_step<ENC, X3>(W, tl, 1) : st[0];
+  st[2] = k > 2 ? load_step<ENC, X3>(W, tl, 2) : st[0];
+  return eval(st, k) - f;
+}
+
 template <bool MAPPED, bool X3, class DF>
 __device__ __forceinline__ int pattern_delta(const TspScratch &W, const uint16_t *tour, int n, const DF &D,
                                              int t, int m, int sub) {
@@ -1336,7 +1351,7 @@ struct QapK {
   // counts; a round with more entries than the list holds is processed in
   // windows of whole candidates.
   template <bool X3>
-  __device__ __forceinline__ int64_t delta_round(const TspScratch &W, int tl, int k) const {
+  __device__ __forceinline__ int64_t delta_round(const TspScratch &W, int tl, int k, int64_t) const {
     const uint32_t l = lane_id();
     uint32_t *tmp = (uint32_t *)dsum;
     const uint32_t cap = kQapListPerN * (uint32_t)n;
@@ -1548,7 +1563,7 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
 
-// Generations of a kind evaluated round by round (QAP): the workgroup's two
+// Generations of a kind evaluated round by round (QAP, VRPTW): the workgroup's two
 // waves each draw and evaluate one round of 64 candidates of every chunk,
 // then agree on the chunk minimum through LDS; acceptance and the move are
 // the same on both (the move's shared state is written by wave 0 or
@@ -1573,7 +1588,7 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
       const bool valid = tl < cn;
       if (__ballot(valid)) {
         const int k = valid ? kk[0] : 0;
-        const int64_t d = kd.template delta_round<X3>(W, (int)tl, k);
+        const int64_t d = kd.template delta_round<X3>(W, (int)tl, k, f);
         if (valid) {
           if (U.credit == 0) {   // the steps again from the tables: fewer registers live across the round
             Step st[3];
@@ -2337,17 +2352,17 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       else round_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk);
       if (wv == 0) perm_store(kd.cur, n, cur_g);
     } else {
+      // int16 distances, the per-node (demand, ready, due) records, the two
+      // waves' chunk minima
       const int dn = n + 1;
       int16_t *D = (int16_t *)rest;
-      int32_t *dem = (int32_t *)(rest + al16(2 * dn * dn));
-      int32_t *rdy = dem + al16(4 * dn) / 4;
-      int32_t *due = rdy + al16(4 * dn) / 4;
+      int4 *attr = (int4 *)(rest + al16(2 * dn * dn));
+      unsigned long long *xk = (unsigned long long *)(attr + dn);
       stage16(D, I->d16, 2u * dn * dn);
-      stage16(dem, I->dem, 4u * dn);
-      stage16(rdy, I->rdy, 4u * dn);
-      stage16(due, I->due, 4u * dn);
+      for (int c = (int)threadIdx.x; c < dn; c += kThreads<KIND, VAR>)
+        attr[c] = make_int4(I->dem[c], I->rdy[c], I->due[c], 0);
       __syncthreads();
-      VrpK kd{t0, t1, n, dn, I->capacity, I->vehicles, I->service, I->horizon, D, dem, rdy, due, I};
+      VrpK kd{t0, t1, n, dn, I->capacity, I->vehicles, I->service, I->horizon, D, attr, I};
       if constexpr ((VAR & kVarLex) != 0) {
         const LexCfg L = lex_cfg(I);
         Vec4 cv = load_vec(J->cur_v + 4 * (size_t)sol), bsv = load_vec(J->best_v + 4 * (size_t)sol);
@@ -2357,11 +2372,11 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
           store_vec(J->best_v + 4 * (size_t)sol, bsv);
         }
       } else if constexpr (x3) {
-        run_gens<true>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        round_gens<true>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk);
       } else {
-        run_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        round_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk);
       }
-      perm_store(kd.cur, n, cur_g);
+      if (threadIdx.x < kWave) perm_store(kd.cur, n, cur_g);
     }
   } else if constexpr (KIND == KKNAP) {
     uint8_t *bits = (uint8_t *)base;
@@ -2397,7 +2412,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     J->cur_f[sol] = f;
     J->best_f[sol] = bf;
   }
-  if (sol_scope) solution_aos_close<kThreads<KIND>>(J, sol, S, bf, g1, E);
+  if (sol_scope) solution_aos_close<kThreads<KIND, VAR>>(J, sol, S, bf, g1, E);
   write_counts<ENC, true>(J, sol, S, nacc, bf);   // every wave adds the counts of its own candidates
 }
 
@@ -2408,7 +2423,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
 // exceeds the SGPR file and part of it lives in VGPR lanes; the compiler's
 // own choice (about 100 VGPRs, 4 waves) runs slower.
 template <int KIND, int VAR>
-__global__ __launch_bounds__(kThreads<KIND>) __attribute__((amdgpu_waves_per_eu(KIND == KTSP ? 5 : 1))) void k_evolve(
+__global__ __launch_bounds__((kThreads<KIND, VAR>)) __attribute__((amdgpu_waves_per_eu(KIND == KTSP ? 5 : 1))) void k_evolve(
     DevJob *job) {
   evolve_wg<KIND, VAR>(job, blockIdx.x, gx_lds);
 }
@@ -2418,12 +2433,12 @@ __global__ __launch_bounds__(kThreads<KIND>) __attribute__((amdgpu_waves_per_eu(
 // counter until the list is done, so workgroups that finish early take more.
 // The epoch kernel clears the counter after the launch.
 template <int KIND, int VAR>
-__global__ __launch_bounds__(kThreads<KIND>) __attribute__((amdgpu_waves_per_eu(3))) void k_evolve_group(DevJob *jobs, const uint2 *items, uint32_t n_items,
+__global__ __launch_bounds__((kThreads<KIND, VAR>)) __attribute__((amdgpu_waves_per_eu(3))) void k_evolve_group(DevJob *jobs, const uint2 *items, uint32_t n_items,
                                                                  uint32_t *next) {
   for (;;) {
     uint32_t it = 0;
     if (threadIdx.x == 0) it = atomicAdd(next, 1u);
-    if constexpr (kThreads<KIND> > kWave) {   // to every wave of the workgroup (LDS is dead between items)
+    if constexpr (kThreads<KIND, VAR> > kWave) {   // to every wave of the workgroup (LDS is dead between items)
       if (threadIdx.x == 0) *(volatile uint32_t *)gx_lds = it;
       __syncthreads();
       it = *(volatile uint32_t *)gx_lds;
@@ -2922,17 +2937,19 @@ hipError_t prepare_kernel_attrs(uint32_t max_lds) {
   return hipSuccess;
 }
 
-static int threads_of(int kind) { return kind == KQAP ? kThreads<KQAP> : kWave; }
+static int threads_of(int kind, int var) {
+  return (kind == KQAP || (kind == KVRP && !(var & kVarLex))) ? 2 * kWave : kWave;
+}
 
 hipError_t evolve_plain(DevJob *job, int kind, int stage, uint32_t P, uint32_t lds, hipStream_t s) {
   void *args[] = {&job};
-  return hipLaunchKernel(plain_kernel(kind, stage), dim3(P), dim3(threads_of(kind)), args, lds, s);
+  return hipLaunchKernel(plain_kernel(kind, stage), dim3(P), dim3(threads_of(kind, stage)), args, lds, s);
 }
 
 hipError_t evolve_group(int kind, int stage, DevJob *jobs, const uint2 *items, uint32_t n_items, uint32_t *next,
                         uint32_t grid, uint32_t lds, hipStream_t s) {
   void *args[] = {&jobs, &items, &n_items, &next};
-  return hipLaunchKernel(group_kernel(kind, stage), dim3(grid), dim3(threads_of(kind)), args, lds, s);
+  return hipLaunchKernel(group_kernel(kind, stage), dim3(grid), dim3(threads_of(kind, stage)), args, lds, s);
 }
 
 hipError_t epoch(DevJob *jobs, const uint32_t *idx, uint32_t count, uint32_t *next, uint32_t n_next, bool mig,
@@ -2950,11 +2967,11 @@ hipError_t fetch_best(DevJob *jobs, int count, hipStream_t s) {
 }
 
 hipError_t occupancy_group(int kind, int stage, uint32_t lds, int *blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, group_kernel(kind, stage), threads_of(kind), lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, group_kernel(kind, stage), threads_of(kind, stage), lds);
 }
 
 hipError_t occupancy_plain(int kind, int stage, uint32_t lds, int *blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, plain_kernel(kind, stage), threads_of(kind), lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, plain_kernel(kind, stage), threads_of(kind, stage), lds);
 }
 
 }  // namespace gxk
