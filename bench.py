@@ -147,11 +147,16 @@ def main():
     ap.add_argument("--staging", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="tsp442: skip the device-ceiling microbenchmarks after the timed region")
     ap.add_argument("--workload", choices=["tsp442", "batched", "served", "kinds", "peaks"], default="tsp442",
                     help="tsp442: the benchmark line; batched / served: the systems patterns; "
                          "kinds: one solve per encoding, operator set and island setting")
     ap.add_argument("--instances", type=int, default=4096, help="batched: number of instances")
     ap.add_argument("--batch-generations", type=int, default=5000)
+    ap.add_argument("--population-rule", choices=["tuned", "fill"], default="tuned",
+                    help="batched: population per size bucket from measured costs (tuned) or the same "
+                         "device-filling population for every instance (fill)")
     ap.add_argument("--plain-sample", type=int, default=32, help="batched/served: requests solved alone")
     ap.add_argument("--rate", type=float, default=2000.0, help="served: offered requests/s")
     ap.add_argument("--duration", type=float, default=10.0, help="served: seconds of arrivals")
@@ -253,6 +258,9 @@ def main():
     achieved = ops_total / launches / avg_launch_s / 1e9
     tr = measured_traffic()
     traffic = tr[0] if tr and tr[1] == P else None
+    # device ceilings measured on this device after the timed region
+    # (gx_measure_peaks: random LDS gather, full-rate VALU issue, Philox, L2 gather, HBM read)
+    pk = None if args.no_peaks else gx.gx_measure_peaks(ctx)
     k_tot = [sum(i["k_count"][k] for i in infos) for k in range(3)]
     steps_per_eval = sum((k + 1) * k_tot[k] for k in range(3)) / max(1, sum(k_tot))
     line = {
@@ -288,11 +296,16 @@ def main():
             "avg_launch_ms": avg_launch_s * 1e3,
             "launches": launches,
             "algorithmic_ops_per_launch": ops_total / launches,
+            "peak_measured": pk["valu_instr_per_s"] / 1e9 if pk else None,
+            "frac_measured": achieved / (pk["valu_instr_per_s"] / 1e9) if pk else None,
         },
         "roofline_lds": {
             "achieved": lds_achieved, "peak": LDS_PEAK_GBS, "unit": "GB/s",
             "frac": lds_achieved / LDS_PEAK_GBS, "algorithmic_bytes_per_launch": bytes_total / launches,
+            "peak_measured": pk["lds_gather_bytes_per_s"] / 1e9 if pk else None,
+            "frac_measured": lds_achieved / (pk["lds_gather_bytes_per_s"] / 1e9) if pk else None,
         },
+        "peaks_measured": pk,
         "pcie_inclusive": {"upload_s": upload_s, "value": evals / (dt + args.steps * upload_s),
                            "note": "instance uploaded from host buffers once per solve"},
     }
@@ -336,21 +349,11 @@ def bench_batched(args):
     count, G = args.instances, args.batch_generations
     n_tsp = count * 3 // 4
     insts = synth.c4_batched_instances(count)
-    P = autotune.fill_population(ctx, count)
-    samples = {}
-    for inst in insts:
-        samples.setdefault(autotune.bucket_of(inst.kind, inst.n), inst)
-    alpha = synth.alpha_q32_for(G)
-    staging = autotune.tune_buckets(
-        ctx, samples, lambda i: synth.Params(seed=1, generations=50, population=P, alpha_q32=alpha))
-    params = [synth.Params(seed=10**6 + i, generations=G, population=P, candidates=128, alpha_q32=alpha,
-                           staging=staging[autotune.bucket_of(inst.kind, inst.n)])
-              for i, inst in enumerate(insts)]
+    params, plan = autotune.tune_batch(ctx, insts, synth.c4_params_for(G), rule=args.population_rule)
     handles = [gx.gx_instance_upload(ctx, i) for i in insts]
     # one untimed batch of the same shape first (first-call costs of the
     # runtime: code-object loading, graph instantiation, allocator growth)
-    warm = [synth.Params(seed=p.seed, generations=min(G, 100), population=P, candidates=128,
-                         alpha_q32=alpha, staging=p.staging) for p in params]
+    warm = [p.with_(generations=min(G, 100)) for p in params]
     for j in gx.gx_solve_batch(ctx, handles, warm):
         gx.gx_wait(ctx, j)
         gx.gx_job_free(ctx, j)
@@ -381,9 +384,11 @@ def bench_batched(args):
         "plain_solves_per_s": 1.0 / plain_dt, "speedup_vs_plain": plain_dt * count / dt,
         "plain_sample": int(len(idx)), "plain_identical": same,
         "config": {"workload": f"{count} instances: {n_tsp} TSP n U[20,200] + {count - n_tsp} QAP n "
-                               f"U[12,40]; P={P} each (sized to fill {cus} CUs), "
-                               f"C=128, {G} generations; staging per bucket {sorted(set(staging.values()))}",
-                   "population": P, "generations": G, "staging_per_bucket": staging},
+                               f"U[12,40]; population per size bucket by the '{args.population_rule}' rule "
+                               f"({sum(p.population for p in params)} solutions on {cus} CUs), C=128, "
+                               f"{G} generations; TSP staging per bucket tuned",
+                   "population_rule": args.population_rule, "generations": G, "plan": plan,
+                   "solutions": sum(p.population for p in params)},
     }
 
 
@@ -475,16 +480,23 @@ def bench_served(args):
     tickets = []
     t0 = time.perf_counter()
     t_next = t0
+    t_note = t0 + 10
     for (inst, p), gap in zip(reqs, gaps):
         t_next += gap
         while time.perf_counter() < t_next:
             pass
         tickets.append(gx.gx_server_submit(srv, inst, p))
+        if t_next >= t_note:   # a progress line every 10 s of a long stream
+            print(f"[served] {len(tickets)} of {n_req} submitted", file=sys.stderr, flush=True)
+            t_note += 10
     t_sub_end = time.perf_counter()
     lat, done, results = [], 0, {}
     deadline = time.perf_counter() + 600
     pending = set(range(n_req))
     while pending and time.perf_counter() < deadline:
+        if time.perf_counter() >= t_note:
+            print(f"[served] {n_req - len(pending)} of {n_req} done", file=sys.stderr, flush=True)
+            t_note += 10
         for k in list(pending):
             res = gx.gx_server_poll(srv, tickets[k], reqs[k][0].n)
             if res is not None:

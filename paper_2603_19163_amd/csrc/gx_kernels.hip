@@ -1027,11 +1027,15 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
   uint32_t cu_k = 0, cv_k = 0, since_fold = 0;
   // The wave-wide counts live in the unused tail of the pattern-list table
   // during the run (fewer scalar registers held across the generation loop)
-  // and are added into S at the end.
+  // and are added into S at the end.  The word after them says whether the
+  // current tour is the best-so-far one not yet written to HBM: the best tour
+  // is stored lazily, before a move that does not improve on it is applied,
+  // or at the end of the launch.
   LStats &SL = *(LStats *)(gx_lds + kTspStatsOff);
-  static_assert(sizeof(LStats) % 4 == 0 && sizeof(LStats) / 4 <= kWave, "one word per lane");
-  static_assert(kTspStatsOff + sizeof(LStats) <= 3584, "inside the free tail of the pattern list");
-  if (lane < sizeof(LStats) / 4) ((uint32_t *)&SL)[lane] = 0u;
+  volatile uint32_t *best_is_cur = (volatile uint32_t *)(gx_lds + kTspStatsOff + sizeof(LStats));
+  static_assert(sizeof(LStats) % 4 == 0 && sizeof(LStats) / 4 < kWave, "one word per lane");
+  static_assert(kTspStatsOff + sizeof(LStats) + 4 <= 3584, "inside the free tail of the pattern list");
+  if (lane <= sizeof(LStats) / 4) ((uint32_t *)&SL)[lane] = 0u;
   wave_sync();
   const uint32_t c_last = (U.C - 1) / kChunk * kChunk;
   if constexpr (DF::kEdges) {
@@ -1152,6 +1156,10 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
       }
       int lo, hi;
       move_range(st, k, lo, hi);
+      if (*best_is_cur && f + ds >= bf) {
+        perm_store(cur, n, best_row);
+        *best_is_cur = 0u;
+      }
       perm_apply(cur, nxt, st, k, lo, hi);
       if constexpr (DF::kEdges) {
         if (lo <= hi) {
@@ -1163,11 +1171,12 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
       ++nacc;
       if (f < bf) {
         bf = f;
-        perm_store(cur, n, best_row);
+        *best_is_cur = 1u;
       }
     }
     T = cool(T, U.alpha);
   }
+  if (*best_is_cur) perm_store(cur, n, best_row);
   fold_ops<X3>(SL.u, SL.v, cu_op, cv_op, kNops);
   fold_byte_counts(SL.uk, SL.vk, cu_k, cv_k, 3);
   wave_sync();
@@ -1510,6 +1519,7 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
   // folded into the wave-uniform counts of S every 42 chunks and at the end
   OpCount<X3> cu = 0, cv = 0;
   uint32_t cuk = 0, cvk = 0, since_fold = 0;
+  bool best_is_cur = false;   // the best-so-far solution is the current one, not yet written
   for (uint32_t g = g0; g < g1; ++g) {
     unsigned long long bk = ~0ull;
     for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
@@ -1549,16 +1559,21 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
       Step st[3];
       const int k = sample<ENC, X3>(U, g, sol, ts, st);
       if (U.credit == 1) credit<ENC>(S, st, k, ds < 0);   // the same on every lane
+      if (best_is_cur && f + ds >= bf) {
+        kd.store(best_row);
+        best_is_cur = false;
+      }
       kd.apply(st, k);
       f += ds;
       ++nacc;
       if (f < bf) {
         bf = f;
-        kd.store(best_row);
+        best_is_cur = true;
       }
     }
     T = cool(T, U.alpha);
   }
+  if (best_is_cur) kd.store(best_row);
   fold_ops<X3>(S.u + lo, S.v + lo, cu, cv, nf);
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
@@ -1578,6 +1593,7 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
   constexpr int nf = X3 ? kPermOps : 4;
   OpCount<X3> cu = 0, cv = 0;
   uint32_t cuk = 0, cvk = 0, since_fold = 0;
+  bool best_is_cur = false;   // the best-so-far solution is the current one, not yet written
   for (uint32_t g = g0; g < g1; ++g) {
     unsigned long long bk = ~0ull;
     for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
@@ -1620,16 +1636,21 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
       Step st[3];
       const int k = sample<ENC, X3>(U, g, sol, ts, st);
       if (U.credit == 1 && wv == 0) credit<ENC>(S, st, k, ds < 0);   // the same on every lane of wave 0
+      if (best_is_cur && f + ds >= bf) {   // wave 0 reads the solution before the move's first barrier
+        if (wv == 0) kd.store(best_row);
+        best_is_cur = false;
+      }
       kd.apply(st, k);
       f += ds;
       nacc += wv == 0;
       if (f < bf) {
         bf = f;
-        if (wv == 0) kd.store(best_row);
+        best_is_cur = true;
       }
     }
     T = cool(T, U.alpha);
   }
+  if (best_is_cur && wv == 0) kd.store(best_row);
   fold_ops<X3>(S.u, S.v, cu, cv, nf);
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
@@ -1659,6 +1680,7 @@ __device__ __forceinline__ void lex_gens(VrpK &kd, const TspScratch &W, const Un
   const uint32_t lane = lane_id();
   OpCount<X3> cu = 0, cvc = 0;
   uint32_t cuk = 0, cvk = 0, since_fold = 0;
+  bool best_is_cur = false;   // the best-so-far solution is the current one, not yet written
   for (uint32_t g = g0; g < g1; ++g) {
     Vec4 bv = {};
     uint32_t bt = 0;
@@ -1708,18 +1730,24 @@ __device__ __forceinline__ void lex_gens(VrpK &kd, const TspScratch &W, const Un
       Step st[3];
       const int k = sample<ENC, X3>(U, g, sol, bt, st);
       if (U.credit == 1) credit<ENC>(S, st, k, lex_better(bv, cv, L));
+      const bool new_best = lex_better(bv, bsv, L);
+      if (best_is_cur && !new_best) {
+        kd.store(best_row);
+        best_is_cur = false;
+      }
       kd.apply(st, k);
       cv = bv;
       f = bv.v[0] + bv.v[1];
       ++nacc;
-      if (lex_better(cv, bsv, L)) {
+      if (new_best) {
         bsv = cv;
         bf = f;
-        kd.store(best_row);
+        best_is_cur = true;
       }
     }
     T = cool(T, U.alpha);
   }
+  if (best_is_cur) kd.store(best_row);
   fold_ops<X3>(S.u, S.v, cu, cvc, nf);
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }

@@ -259,6 +259,17 @@ def c4_batched_instances(count: int = 4096) -> list[Instance]:
     return out
 
 
+def c4_params_for(generations: int = 5000):
+    """Parameters of batched instance `index` (seed 10^6 + index, C = 128,
+    cooling to 0.001 over the run) at a given population and staging."""
+    alpha = alpha_q32_for(generations)
+
+    def make(inst, index, population, staging):
+        return Params(seed=10**6 + index, generations=generations, population=population, candidates=128,
+                      alpha_q32=alpha, staging=staging)
+    return make
+
+
 def c5_requests(rate: float, duration: float, kinds=(0, 1, 2), generations: int = 10_000,
                 population: int = 4):
     """Served workload: int(rate * duration) requests with exponential gaps

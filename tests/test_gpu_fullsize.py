@@ -49,12 +49,10 @@ def valid(inst, sol):
 
 def test_c4_full_batch(ctx):
     insts = synth.c4_batched_instances(4096)
-    P = autotune.fill_population(ctx, len(insts))
     G = 5000
-    alpha = synth.alpha_q32_for(G)
-    params = [synth.Params(seed=10**6 + i, generations=G, population=P, candidates=128, alpha_q32=alpha)
-              for i in range(len(insts))]
-    print(f"[fullsize] C4 batch of {len(insts)} P={P}", flush=True)
+    params, plan = autotune.tune_batch(ctx, insts, synth.c4_params_for(G), rule="tuned")
+    print(f"[fullsize] C4 batch of {len(insts)}, populations per bucket "
+          f"{ {b: v['population'] for b, v in plan.items()} }", flush=True)
     handles = [gx.gx_instance_upload(ctx, i) for i in insts]
     jobs = gx.gx_solve_batch(ctx, handles, params)
     gx.gx_wait(ctx, jobs[0])
