@@ -1569,6 +1569,13 @@ void lane_free(SrvLane &L) {
 
 // Place an admitted request into its arena block and start its initialisation.
 gx_status srv_stage(gx_server *S, SrvReq *r) {
+  // the request's completion event belongs to the scheduler thread, which
+  // creates, records, queries and destroys it: the submitting and polling
+  // threads make no HIP calls
+  if (!r->ev && hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
+    r->ev = nullptr;
+    return GX_E_DEVICE;
+  }
   char *base = S->arena_d + r->off;
   // host-side copies go through the request's pinned block (after its result
   // area), so the scheduler thread never waits on a pageable copy
@@ -1727,14 +1734,17 @@ void server_loop(gx_server *S) {
           (void)hipEventRecord(S->drain[li], S->lanes[li].s);
           (void)hipStreamWaitEvent(S->s, S->drain[li], 0);
         }
-        (void)hipEventRecord(r->ev, S->s);
+        if (r->ev) (void)hipEventRecord(r->ev, S->s);
+        else (void)hipStreamSynchronize(S->s);   // no event (its creation failed): drain here
         r->state = RQ_FETCHING;
       }
     // completions
     bool done_any = false;
     for (SrvReq *r : S->slots) {
       if (!r || r->state != RQ_FETCHING) continue;
-      if (hipEventQuery(r->ev) != hipSuccess) continue;
+      if (r->ev && hipEventQuery(r->ev) != hipSuccess) continue;
+      if (r->ev) (void)hipEventDestroy(r->ev);   // complete: the scheduler's last use of it
+      r->ev = nullptr;
       std::lock_guard<std::mutex> lk(S->mu);
       if (!r->cancel) {
         const char *src = S->pin + r->pin_off;
@@ -1852,10 +1862,6 @@ gx_status gx_server_submit(gx_server *S, const gx_instance_desc *d, const gx_sol
   r->cost = (r->pr.h.kind == KQAP ? 4.0 * n * n / 3.0 : (r->pr.h.kind == KVRP ? 8.0 * n : n)) * r->hj.C;
   r->kind = r->pr.h.kind;
   r->lane = lane_of(r->kind, evolve_variant(r->kind, r->hj.stage, r->hj.op_mask, r->hj.lex_levels), r->hj.lds_bytes);
-  if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
-    delete r;
-    return GX_E_DEVICE;
-  }
   r->ticket = S->next_ticket++;
   r->t_submit = now_ns();
   S->reqs[r->ticket] = r;
@@ -1876,7 +1882,6 @@ gx_status gx_server_poll(gx_server *S, uint64_t ticket, int32_t *sol, int32_t ca
   SrvReq *r = it->second;
   if (r->state == RQ_CANCELLED) {
     S->reqs.erase(it);
-    (void)hipEventDestroy(r->ev);
     delete r;
     return GX_E_CANCELLED;
   }
@@ -1887,7 +1892,6 @@ gx_status gx_server_poll(gx_server *S, uint64_t ticket, int32_t *sol, int32_t ca
   if (t_sub) *t_sub = r->t_submit;
   if (t_done) *t_done = r->t_done;
   S->reqs.erase(it);
-  (void)hipEventDestroy(r->ev);
   delete r;
   return GX_OK;
 }
@@ -1927,8 +1931,8 @@ gx_status gx_server_destroy(gx_server *S) {
   S->cv.notify_all();
   if (S->th.joinable()) S->th.join();
   (void)hipStreamSynchronize(S->s);
-  for (auto &kv : S->reqs) {
-    (void)hipEventDestroy(kv.second->ev);
+  for (auto &kv : S->reqs) {   // the scheduler has stopped: its events are freed here
+    if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
     delete kv.second;
   }
   for (SrvLane &L : S->lanes) lane_free(L);

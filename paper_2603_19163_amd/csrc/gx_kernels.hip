@@ -2083,8 +2083,6 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
   // statistics and weights stay as initialised
   const bool inst_scope = J->aos_scope == 0;
   const bool lex = J->lex_levels != 0;
-  const LexCfg L = lex_cfg(J->inst);
-  Vec4 ref_v = load_vec(J->ref_v);
   uint32_t stag = J->stag;
   uint64_t T = J->T;
   int64_t inst_best = J->inst_best, epoch_ref = J->epoch_ref;
@@ -2130,10 +2128,11 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
     bool improved = inst_best < epoch_ref;
     int64_t ref_now = inst_best;
     if (lex) {   // the instance best by the ordered scan; improved when strictly better than the last one
+      const LexCfg L = lex_cfg(J->inst);
       const uint32_t b = lex_scan_best(J, L);
       const Vec4 now = load_vec(J->best_v + 4 * (size_t)b);
-      improved = lex_better(now, ref_v, L);
-      ref_v = now;
+      improved = lex_better(now, load_vec(J->ref_v), L);
+      store_vec(J->ref_v, now);
       ref_now = J->best_f[b];
     }
     if (improved) stag = 0;
@@ -2165,7 +2164,6 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
     J->w_k[q] = w_k[q];
   }
   J->accepted = accepted + t[2 * kOps + 6];
-  if (lex) store_vec(J->ref_v, ref_v);
   J->inst_best = inst_best;
   J->epoch_ref = epoch_ref;
   J->stag = stag;
