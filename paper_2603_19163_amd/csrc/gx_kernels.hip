@@ -2056,26 +2056,37 @@ __device__ __forceinline__ uint32_t lex_scan_best(const DevJob *J, const LexCfg 
 // boundary apply the AOS update (the kernel boundary orders it after every
 // evolve workgroup).  Wave 0 of the job's workgroup; lane l folds and clears
 // row l.  The launch covered generations [g0, g1).
-static_assert(kShards == kWave, "one accumulator row per lane");
+static_assert(kShards == kWave && kCountSlots < kWave, "one accumulator row and one slot per lane");
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t src) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, (int)src, kWave);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), (int)src, kWave);
+  return ((uint64_t)hi << 32) | lo;
+}
+// Lanes share the work: lane l sums slot l over the 64 rows (column l) and
+// clears it; lane o < kOps then owns operator o and lane 2 kOps + q owns
+// k = q + 1 (their statistics, run totals and weights: loads, the Eq. ema
+// update with its clamp, the normalisation through a wave sum, stores); the
+// scalars are uniform and lane 0 stores them.
 __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, uint32_t g1) {
-  // the job state in registers first (one batch of loads, no store between)
-  unsigned long long u_op[kOps], v_op[kOps], tu_op[kOps], tv_op[kOps], u_k[3], v_k[3], tu_k[3], tv_k[3];
-  uint32_t w_op[kOps], w_k[3];
-#pragma unroll
-  for (int o = 0; o < kOps; ++o) {
-    u_op[o] = J->u_op[o];
-    v_op[o] = J->v_op[o];
-    tu_op[o] = J->tot_u_op[o];
-    tv_op[o] = J->tot_v_op[o];
-    w_op[o] = J->w_op[o];
-  }
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    u_k[q] = J->u_k[q];
-    v_k[q] = J->v_k[q];
-    tu_k[q] = J->tot_u_k[q];
-    tv_k[q] = J->tot_v_k[q];
-    w_k[q] = J->w_k[q];
+  const uint32_t l = threadIdx.x;
+  constexpr uint32_t kMinSlot = kCountSlots, kAccSlot = 2 * kOps + 6;
+  const bool op_lane = l < (uint32_t)kOps, k_lane = l >= 2u * kOps && l < 2u * kOps + 3;
+  const uint32_t q = l - 2 * kOps;   // k lanes
+  // this lane's own state first (one batch of loads, no store between)
+  uint64_t u = 0, v = 0, tu = 0, tv = 0;
+  uint32_t w = 0;
+  if (op_lane) {
+    u = J->u_op[l];
+    v = J->v_op[l];
+    tu = J->tot_u_op[l];
+    tv = J->tot_v_op[l];
+    w = J->w_op[l];
+  } else if (k_lane) {
+    u = J->u_k[q];
+    v = J->v_k[q];
+    tu = J->tot_u_k[q];
+    tv = J->tot_v_k[q];
+    w = J->w_k[q];
   }
   const uint32_t alpha = J->alpha, op_mask = J->op_mask, aos_A = J->aos_A;
   const uint32_t w_floor = J->w_floor, stag_limit = J->stag_limit;
@@ -2087,44 +2098,53 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
   uint64_t T = J->T;
   int64_t inst_best = J->inst_best, epoch_ref = J->epoch_ref;
   const unsigned long long accepted = J->accepted;
-  const uint32_t tid = threadIdx.x;
-  unsigned long long *row = J->shard + (size_t)tid * kEpochSlots;
-  unsigned long long v[kEpochSlots];
+  // column l of the accumulator rows, then cleared for the next launch
+  unsigned long long *col = J->shard + l;
+  unsigned long long c = l == kMinSlot ? (unsigned long long)LLONG_MAX : 0ull;
+  if (l <= kMinSlot) {
+    constexpr int kB = kShards / 2;   // rows per batch of loads in flight
 #pragma unroll
-  for (int i = 0; i < kEpochSlots; ++i) v[i] = row[i];
+    for (int r0 = 0; r0 < kShards; r0 += kB) {
+      unsigned long long x[kB];
 #pragma unroll
-  for (int i = 0; i < kCountSlots; ++i) row[i] = 0;
-  row[kCountSlots] = (unsigned long long)LLONG_MAX;
-  unsigned long long t[kCountSlots];
+      for (int r = 0; r < kB; ++r) x[r] = col[(r0 + r) * kEpochSlots];
 #pragma unroll
-  for (int i = 0; i < kCountSlots; ++i) t[i] = wave_sum_u64(v[i]);
-  // signed minimum through the unsigned order of v ^ 2^63
-  constexpr unsigned long long kSign = 1ull << 63;
-  const long long mn = (long long)(wave_min_key(v[kCountSlots] ^ kSign) ^ kSign);
-  if (tid != 0) return;
+      for (int r = 0; r < kB; ++r)
+        col[(r0 + r) * kEpochSlots] = l == kMinSlot ? (unsigned long long)LLONG_MAX : 0ull;
 #pragma unroll
-  for (int o = 0; o < kOps; ++o) {
-    if (inst_scope) {
-      u_op[o] += t[o];
-      v_op[o] += t[kOps + o];
+      for (int r = 0; r < kB; ++r)
+        c = l == kMinSlot ? (unsigned long long)min((long long)c, (long long)x[r]) : c + x[r];
     }
-    tu_op[o] += t[o];
-    tv_op[o] += t[kOps + o];
   }
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  // the launch's counts where their owners need them
+  const uint64_t add_u = c;                                                 // slot l: uses of op l / of k (lane 2 kOps + q)
+  const uint64_t add_v = shfl64(c, op_lane ? l + kOps : (k_lane ? l + 3 : l));   // improvements
+  const unsigned long long add_acc = shfl64(c, kAccSlot);
+  const long long mn = (long long)shfl64(c, kMinSlot);
+  if (op_lane || k_lane) {
     if (inst_scope) {
-      u_k[q] += t[2 * kOps + q];
-      v_k[q] += t[2 * kOps + 3 + q];
+      u += add_u;
+      v += add_v;
     }
-    tu_k[q] += t[2 * kOps + q];
-    tv_k[q] += t[2 * kOps + 3 + q];
+    tu += add_u;
+    tv += add_v;
   }
   if (mn < inst_best) inst_best = mn;
   for (uint32_t g = g0; g < g1; ++g) T = cool(T, alpha);
   if (g1 % E == 0 && inst_scope) {
-    ema_group(w_op, u_op, v_op, op_mask, kOps, aos_A, w_floor);
-    ema_group(w_k, u_k, v_k, 7u, 3, aos_A, w_floor);
+    // Eq. ema on every enabled operator and on the k weights, clamp, then normalisation per group
+    const bool upd = (op_lane && ((op_mask >> l) & 1u)) || k_lane;
+    uint64_t nw = 0;
+    if (upd) {
+      const uint64_t r = udiv_q24(v << 16, u + 1);
+      nw = ((uint64_t)aos_A * w + (uint64_t)(65536 - aos_A) * (r + w_floor)) >> 16;
+      nw = nw < w_floor ? w_floor : (nw > 65536 ? 65536 : nw);
+    }
+    const uint32_t s_op = wave_sum(op_lane ? (uint32_t)nw : 0u), s_k = wave_sum(k_lane ? (uint32_t)nw : 0u);
+    if (upd) {
+      const uint64_t z = udiv_q24(nw << 16, op_lane ? s_op : s_k);
+      w = (uint32_t)(z < 1 ? 1 : z);
+    }
     bool improved = inst_best < epoch_ref;
     int64_t ref_now = inst_best;
     if (lex) {   // the instance best by the ordered scan; improved when strictly better than the last one
@@ -2132,43 +2152,39 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
       const uint32_t b = lex_scan_best(J, L);
       const Vec4 now = load_vec(J->best_v + 4 * (size_t)b);
       improved = lex_better(now, load_vec(J->ref_v), L);
-      store_vec(J->ref_v, now);
+      if (l == 0) store_vec(J->ref_v, now);
       ref_now = J->best_f[b];
     }
     if (improved) stag = 0;
     else stag += 1;
     epoch_ref = ref_now;
     if (stag >= stag_limit) {
-      w_k[0] = 52429; w_k[1] = 9830; w_k[2] = 3277;
+      if (k_lane) w = q == 0 ? 52429u : (q == 1 ? 9830u : 3277u);
       stag = 0;
     }
-#pragma unroll
-    for (int i = 0; i < kOps; ++i) u_op[i] = v_op[i] = 0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) u_k[i] = v_k[i] = 0;
+    u = v = 0;
   }
-#pragma unroll
-  for (int o = 0; o < kOps; ++o) {
-    J->u_op[o] = u_op[o];
-    J->v_op[o] = v_op[o];
-    J->tot_u_op[o] = tu_op[o];
-    J->tot_v_op[o] = tv_op[o];
-    J->w_op[o] = w_op[o];
+  if (op_lane) {
+    J->u_op[l] = u;
+    J->v_op[l] = v;
+    J->tot_u_op[l] = tu;
+    J->tot_v_op[l] = tv;
+    J->w_op[l] = w;
+  } else if (k_lane) {
+    J->u_k[q] = u;
+    J->v_k[q] = v;
+    J->tot_u_k[q] = tu;
+    J->tot_v_k[q] = tv;
+    J->w_k[q] = w;
   }
-#pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    J->u_k[q] = u_k[q];
-    J->v_k[q] = v_k[q];
-    J->tot_u_k[q] = tu_k[q];
-    J->tot_v_k[q] = tv_k[q];
-    J->w_k[q] = w_k[q];
+  if (l == 0) {
+    J->accepted = accepted + add_acc;
+    J->inst_best = inst_best;
+    J->epoch_ref = epoch_ref;
+    J->stag = stag;
+    J->T = T;
+    J->g = g1;
   }
-  J->accepted = accepted + t[2 * kOps + 6];
-  J->inst_best = inst_best;
-  J->epoch_ref = epoch_ref;
-  J->stag = stag;
-  J->T = T;
-  J->g = g1;
 }
 
 __global__ __launch_bounds__(64) void k_epoch(DevJob *jobs, const uint32_t *idx, uint32_t *next, uint32_t n_next) {
