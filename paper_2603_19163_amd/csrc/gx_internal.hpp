@@ -138,7 +138,8 @@ inline uint32_t lds_bytes_for(int kind, int n, int var) {
              2 * (16 * kWave + al(lst) + al(2 * lst));
     }
     case KKNAP: return tables + al(un) + 2 * al(4 * un);
-    case KVRP: return tables + tours + al(2 * (un + 1) * (un + 1)) + 16 * (un + 1) + 16;   // + chunk minima
+    case KVRP:   // + chunk minima, + the chunk's candidate vectors in the lexicographic mode
+      return tables + tours + al(2 * (un + 1) * (un + 1)) + 16 * (un + 1) + 16 + ((var & kVarLex) ? 128u * 32u : 0u);
     default: return tables + al(2 * un) + al(4 * (un + 1));   // + adjacency, added by the caller
   }
 }

@@ -77,10 +77,10 @@ __device__ __forceinline__ uint32_t rmap(uint32_t w, uint32_t m) { return __umul
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
 // threads of an evolve workgroup: two wavefronts for QAP (they share the
-// solution and split the delta entries) and for VRPTW in the weighted mode
-// (one candidate per lane), one for the other kinds
+// solution and split the delta entries) and for VRPTW (one candidate per
+// lane), one for the other kinds
 template <int KIND, int VAR = 0>
-constexpr int kThreads = (KIND == KQAP || (KIND == KVRP && !(VAR & kVarLex))) ? 128 : 64;
+constexpr int kThreads = (KIND == KQAP || KIND == KVRP) ? 128 : 64;
 // LDS written by this wave visible to all of its lanes (a wave's LDS accesses
 // are performed in order; this only keeps the compiler from reordering them)
 __device__ __forceinline__ void wave_sync() {
@@ -1655,29 +1655,26 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
 
-__device__ __forceinline__ int64_t readlane64(int64_t x, uint32_t l) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, (int)l);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)x >> 32), (int)l);
-  return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
 // Generations of a VRPTW solution in the lexicographic mode (Alg. 1 with the
-// comparisons of that mode).  Each lane evaluates its candidates' objective
-// vectors; the winner is the first candidate, in index order, that no later
-// candidate is strictly better than the one kept so far (the comparison has
-// tolerances and is not transitive, so the scan runs in order: after every
-// round of 64 candidates the wave walks its lanes one by one, reading each
-// vector into scalar registers).  A winner that the current solution does not
-// beat is accepted; a worse one passes the exponential test on lex_delta.  A
-// candidate improves when it is strictly better than the current solution.
-// The scalar f reported for a solution is its penalty plus its first level.
+// comparisons of that mode), two waves per solution: each wave draws and
+// evaluates one 64-candidate round of every chunk (one candidate per lane)
+// and writes the candidates' objective vectors to LDS; then both waves scan
+// the chunk's vectors in index order and keep the first candidate that no
+// later one is strictly better than (the comparison has tolerances and is not
+// transitive, so the scan runs in order; both waves reach the same winner).
+// A winner that the current solution does not beat is accepted; a worse one
+// passes the exponential test on lex_delta.  A candidate improves when it is
+// strictly better than the current solution.  The scalar f reported for a
+// solution is its penalty plus its first level.  Counts as in round_gens:
+// each wave its own candidates, accepted moves and credit R2 on wave 0.
 template <bool X3>
-__device__ __forceinline__ void lex_gens(VrpK &kd, const TspScratch &W, const Uni &U, const LexCfg &L,
-                                         int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1, uint64_t &T,
-                                         int64_t &f, int64_t &bf, Vec4 &cv, Vec4 &bsv, LStats &S, uint32_t &nacc) {
+__device__ __forceinline__ void lex_rounds(VrpK &kd, const TspScratch &W, const Uni &U, const LexCfg &L,
+                                           int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1, uint64_t &T,
+                                           int64_t &f, int64_t &bf, Vec4 &cv, Vec4 &bsv, LStats &S, uint32_t &nacc,
+                                           int64_t *vbuf) {
   constexpr int ENC = 0;
   constexpr int nf = X3 ? kPermOps : 4;
-  const uint32_t lane = lane_id();
+  const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
   OpCount<X3> cu = 0, cvc = 0;
   uint32_t cuk = 0, cvk = 0, since_fold = 0;
   bool best_is_cur = false;   // the best-so-far solution is the current one, not yet written
@@ -1687,35 +1684,28 @@ __device__ __forceinline__ void lex_gens(VrpK &kd, const TspScratch &W, const Un
     bool have = false;
     for (uint32_t c0 = 0; c0 < U.C; c0 += kChunk) {
       const uint32_t cn = min((uint32_t)kChunk, U.C - c0);
-      int kk[2];
-      draw_chunk<ENC, X3>(W, U, g, sol, c0, cn, kk);
-#pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const uint32_t r0 = (uint32_t)r * kWave;
-        if (r0 >= cn) break;
-        const uint32_t tl = r0 + lane;
-        Vec4 v = {};
-        if (tl < cn) {
-          Step st[3];
-          st[0] = load_step<ENC, X3>(W, (int)tl, 0);
-          st[1] = kk[r] > 1 ? load_step<ENC, X3>(W, (int)tl, 1) : st[0];
-          st[2] = kk[r] > 2 ? load_step<ENC, X3>(W, (int)tl, 2) : st[0];
-          v = lex_vector(kd.parts(st, kk[r]), kd.veh, L);
-          if (U.credit == 0) credit_bytes<ENC, X3>(cu, cvc, cuk, cvk, st, kk[r], lex_better(v, cv, L));
-        }
-        const uint32_t cnt = min((uint32_t)kWave, cn - r0);
-        for (uint32_t j = 0; j < cnt; ++j) {
-          Vec4 x;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) x.v[i] = readlane64(v.v[i], j);
-          if (!have || lex_better(x, bv, L)) {
-            bv = x;
-            bt = c0 + r0 + j;
-            have = true;
-          }
+      int kk[1];
+      draw_chunk<ENC, X3, 1>(W, U, g, sol, c0, cn, kk, wv);
+      const uint32_t tl = wv * kWave + lane;
+      if (tl < cn) {
+        Step st[3];
+        st[0] = load_step<ENC, X3>(W, (int)tl, 0);
+        st[1] = kk[0] > 1 ? load_step<ENC, X3>(W, (int)tl, 1) : st[0];
+        st[2] = kk[0] > 2 ? load_step<ENC, X3>(W, (int)tl, 2) : st[0];
+        const Vec4 v = lex_vector(kd.parts(st, kk[0]), kd.veh, L);
+        if (U.credit == 0) credit_bytes<ENC, X3>(cu, cvc, cuk, cvk, st, kk[0], lex_better(v, cv, L));
+        store_vec(vbuf + 4 * (size_t)tl, v);
+      }
+      __syncthreads();
+      for (uint32_t j = 0; j < cn; ++j) {
+        const Vec4 x = load_vec(vbuf + 4 * (size_t)j);
+        if (!have || lex_better(x, bv, L)) {
+          bv = x;
+          bt = c0 + j;
+          have = true;
         }
       }
-      if (++since_fold == 42) {
+      if (++since_fold == 84) {   // one candidate per lane per chunk: at most 3 per field
         fold_ops<X3>(S.u, S.v, cu, cvc, nf);
         fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
         cu = cvc = 0;
@@ -1729,16 +1719,16 @@ __device__ __forceinline__ void lex_gens(VrpK &kd, const TspScratch &W, const Un
     if (acc) {
       Step st[3];
       const int k = sample<ENC, X3>(U, g, sol, bt, st);
-      if (U.credit == 1) credit<ENC>(S, st, k, lex_better(bv, cv, L));
+      if (U.credit == 1 && wv == 0) credit<ENC>(S, st, k, lex_better(bv, cv, L));
       const bool new_best = lex_better(bv, bsv, L);
-      if (best_is_cur && !new_best) {
-        kd.store(best_row);
+      if (best_is_cur && !new_best) {   // wave 0 reads the solution before the move's first barrier
+        if (wv == 0) kd.store(best_row);
         best_is_cur = false;
       }
       kd.apply(st, k);
       cv = bv;
       f = bv.v[0] + bv.v[1];
-      ++nacc;
+      nacc += wv == 0;
       if (new_best) {
         bsv = cv;
         bf = f;
@@ -1747,7 +1737,7 @@ __device__ __forceinline__ void lex_gens(VrpK &kd, const TspScratch &W, const Un
     }
     T = cool(T, U.alpha);
   }
-  if (best_is_cur) kd.store(best_row);
+  if (best_is_cur && wv == 0) kd.store(best_row);
   fold_ops<X3>(S.u, S.v, cu, cvc, nf);
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
@@ -2395,7 +2385,8 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       if (wv == 0) perm_store(kd.cur, n, cur_g);
     } else {
       // int16 distances, the per-node (demand, ready, due) records, the two
-      // waves' chunk minima
+      // waves' chunk minima, and in the lexicographic mode the chunk's
+      // candidate vectors
       const int dn = n + 1;
       int16_t *D = (int16_t *)rest;
       int4 *attr = (int4 *)(rest + al16(2 * dn * dn));
@@ -2408,7 +2399,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       if constexpr ((VAR & kVarLex) != 0) {
         const LexCfg L = lex_cfg(I);
         Vec4 cv = load_vec(J->cur_v + 4 * (size_t)sol), bsv = load_vec(J->best_v + 4 * (size_t)sol);
-        lex_gens<x3>(kd, W, U, L, best_row, sol, g0, g1, T, f, bf, cv, bsv, S, nacc);
+        lex_rounds<x3>(kd, W, U, L, best_row, sol, g0, g1, T, f, bf, cv, bsv, S, nacc, (int64_t *)(xk + 2));
         if (threadIdx.x == 0) {
           store_vec(J->cur_v + 4 * (size_t)sol, cv);
           store_vec(J->best_v + 4 * (size_t)sol, bsv);
@@ -2979,9 +2970,7 @@ hipError_t prepare_kernel_attrs(uint32_t max_lds) {
   return hipSuccess;
 }
 
-static int threads_of(int kind, int var) {
-  return (kind == KQAP || (kind == KVRP && !(var & kVarLex))) ? 2 * kWave : kWave;
-}
+static int threads_of(int kind, int) { return (kind == KQAP || kind == KVRP) ? 2 * kWave : kWave; }
 
 hipError_t evolve_plain(DevJob *job, int kind, int stage, uint32_t P, uint32_t lds, hipStream_t s) {
   void *args[] = {&job};
