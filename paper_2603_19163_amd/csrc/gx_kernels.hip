@@ -459,6 +459,39 @@ __device__ __forceinline__ int64_t vrp_objective(const DevInst *I, int64_t dist,
          10000 * (int64_t)max(0, routes - I->vehicles);
 }
 
+// Position map of one step (the element at position p after the step was at
+// position map(p) before it), as up to three pieces inside [s1, s1 + len):
+// p < e1 -> o1, p < e1b -> o2, else -o1 added to p, or to -p for a reversal
+// (neg = -1); positions outside the range are fixed.  Only a swap reaches the
+// third piece.
+//   reversal of [a, b]:  p -> a + b - p;
+//   swap of a < b:        a -> b, b -> a;
+//   block [i, i+L) moved to start at q: [q, q+L) -> +(i-q) and [q+L, i+L)
+//   -> -L when q < i; [i, q) -> +L and [q, q+L) -> +(i-q) when q > i.
+struct SMap {
+  int s1, len, e1, e1b, neg, o1, o2;
+};
+
+__device__ __forceinline__ SMap smap(int op, int a, int b, int L) {
+  const bool mv = op >= OINS, sw = op == OSWAP, qlt = b < a;
+  SMap M;
+  M.s1 = mv ? min(a, b) : a;
+  M.len = (mv ? max(a, b) + L : b + 1) - M.s1;
+  M.e1 = mv ? (qlt ? b + L : b) : (sw ? a + 1 : b + 1);
+  M.e1b = mv ? max(a, b) + L : b;
+  M.neg = (mv || sw) ? 0 : -1;
+  M.o1 = mv ? (qlt ? a - b : L) : (sw ? b - a : a + b);
+  M.o2 = mv ? (qlt ? -L : a - b) : 0;
+  return M;
+}
+
+__device__ __forceinline__ int sapply(const SMap &M, int p) {
+  const int t = (p ^ M.neg) - M.neg;
+  const int off = p < M.e1 ? M.o1 : (p < M.e1b ? M.o2 : -M.o1);
+  const bool in = (uint32_t)(p - M.s1) < (uint32_t)M.len;
+  return in ? t + off : p;
+}
+
 struct TspScratch;
 
 // Parts of a split giant tour's objective
@@ -557,11 +590,18 @@ struct VrpK {
     return vrp_objective(I, q.dist, q.routes, q.longest, q.late);
   }
   __device__ __forceinline__ VrpParts parts(const Step *st, int k) const {
+    // the candidate's position maps, branch-free (identity past its k steps)
+    SMap M[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      M[m] = smap(st[m].op, st[m].a, st[m].b, st[m].c);
+      if (m >= k) M[m].len = 0;
+    }
     int64_t late = 0;
     // distances, times and route lengths stay below 2^31 (n <= 250, entries < 2^15, times <= 2^19)
     int dist = 0, t = 0, load = 0, routes = n > 0 ? 1 : 0, prev = 0, len = 0, longest = 0;
     for (int p = 0; p < n; ++p) {
-      const int c = cur[chain(st, k, p)] + 1;
+      const int c = cur[sapply(M[0], sapply(M[1], sapply(M[2], p)))] + 1;
       const int4 a = attr[c];
       const int dpc = D[prev * dn + c], dp0 = D[prev * dn], d0c = D[c];
       // a demand never exceeds the capacity, so the first customer opens no second route
@@ -745,38 +785,6 @@ __device__ __forceinline__ uint32_t lanes_below(unsigned long long mask) {
 // number of pattern steps of an operator
 __device__ __forceinline__ int n_patterns(int op, int a, int b) { return (op == OSWAP && b - a >= 2) ? 2 : 1; }
 
-// Position map of one step (the element at position p after the step was at
-// position map(p) before it), as up to three pieces inside [s1, s1 + len):
-// p < e1 -> o1, p < e1b -> o2, else -o1 added to p, or to -p for a reversal
-// (neg = -1); positions outside the range are fixed.  Only a swap reaches the
-// third piece.
-//   reversal of [a, b]:  p -> a + b - p;
-//   swap of a < b:        a -> b, b -> a;
-//   block [i, i+L) moved to start at q: [q, q+L) -> +(i-q) and [q+L, i+L)
-//   -> -L when q < i; [i, q) -> +L and [q, q+L) -> +(i-q) when q > i.
-struct SMap {
-  int s1, len, e1, e1b, neg, o1, o2;
-};
-
-__device__ __forceinline__ SMap smap(int op, int a, int b, int L) {
-  const bool mv = op >= OINS, sw = op == OSWAP, qlt = b < a;
-  SMap M;
-  M.s1 = mv ? min(a, b) : a;
-  M.len = (mv ? max(a, b) + L : b + 1) - M.s1;
-  M.e1 = mv ? (qlt ? b + L : b) : (sw ? a + 1 : b + 1);
-  M.e1b = mv ? max(a, b) + L : b;
-  M.neg = (mv || sw) ? 0 : -1;
-  M.o1 = mv ? (qlt ? a - b : L) : (sw ? b - a : a + b);
-  M.o2 = mv ? (qlt ? -L : a - b) : 0;
-  return M;
-}
-
-__device__ __forceinline__ int sapply(const SMap &M, int p) {
-  const int t = (p ^ M.neg) - M.neg;
-  const int off = p < M.e1 ? M.o1 : (p < M.e1b ? M.o2 : -M.o1);
-  const bool in = (uint32_t)(p - M.s1) < (uint32_t)M.len;
-  return in ? t + off : p;
-}
 
 template <bool X3>
 __device__ __forceinline__ void unpack_step(const TspScratch &W, int t, int m, int &op, int &a, int &b, int &L) {

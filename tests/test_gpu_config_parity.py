@@ -78,3 +78,32 @@ def test_c3_whole_run(ctx):
     assert f == fo and np.array_equal(sol, st["best"][io])
     gx.gx_job_free(ctx, job)
     gx.gx_instance_free(ctx, h)
+
+
+def test_c3_lexicographic_whole_run(ctx):
+    """The VRPTW configuration in the lexicographic mode as the per-kind bench
+    row runs it (routes, then distance within 20, then the longest route):
+    the whole 5000-generation run, state and objective vectors compared with
+    the oracle every 1000 generations."""
+    import dataclasses
+    base, p = synth.c3_vrptw(seed=42)
+    inst = dataclasses.replace(base, lex_order=(2, 1, 3), lex_tol=(0, 20, 0))
+    h = gx.gx_instance_upload(ctx, inst)
+    job = gx.gx_job_create(ctx, h, p)
+    o = oracle.OracleInstance(inst)
+    st = o.init(p)
+    for k in range(5):
+        gx.gx_job_advance(ctx, job, 1000)
+        t = time.perf_counter()
+        o.run(p, st, 1000, threads=THREADS)
+        print(f"[config parity] C3 lexicographic generations {1000 * k}..{1000 * (k + 1)}: "
+              f"oracle {time.perf_counter() - t:.1f} s", flush=True)
+        same(gx.gx_snapshot(ctx, job, p.population, inst.n), st, f"C3 lexicographic generation {1000 * (k + 1)}")
+        v = gx.gx_snapshot_lex(ctx, job, p.population)
+        for key in ("cur_v", "best_v", "ref_v"):
+            assert np.array_equal(v[key], st[key]), (key, 1000 * (k + 1))
+    sol, f = gx.gx_fetch_best(ctx, job, inst.n)
+    fo, io = o.best_of(st)
+    assert f == fo and np.array_equal(sol, st["best"][io])
+    gx.gx_job_free(ctx, job)
+    gx.gx_instance_free(ctx, h)
