@@ -415,7 +415,7 @@ def bench_kinds(args):
 
     isl = dict(islands=16, migrate_epochs=5, elite_epochs=10)
     rows = [
-        ("tsp442", "TSP n=442 clustered, all permutation ops, one population", tsp442()),
+        ("tsp442", "TSP n=442 clustered, 2-opt/swap/insert/or-opt, one population", tsp442()),
         ("tsp442_islands_ring", "same, 16 islands, ring migration every 5 epochs, elite every 10",
          tsp442(**isl, migrate_mode=0)),
         ("tsp442_islands_topn", "same, 16 islands, global top-4 migration every 5 epochs, elite every 10",
