@@ -102,7 +102,7 @@ def lib():
         L.or_apply_op.argtypes = [C.c_void_p, P64, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32]
         L.or_initial_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, P32]
         L.or_aos_update.argtypes = [C.POINTER(_Params), C.c_uint32, C.POINTER(_State), C.c_int64]
-        L.or_migrate.argtypes = [C.POINTER(_Params), C.c_int, C.POINTER(_State), C.c_uint32]
+        L.or_migrate.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_int, C.POINTER(_State), C.c_uint32]
         L.or_heuristic_perms.argtypes = [C.c_void_p, P64, C.c_int]
         L.or_heuristic_perms.restype = C.c_int
         L.or_init.argtypes = [C.c_void_p, C.POINTER(_Params), C.POINTER(_State)]
@@ -301,7 +301,7 @@ class OracleInstance:
         s = self._state_struct(st)
         pp = _params(params)
         if lib().or_init(self.h, C.byref(pp), C.byref(s)) != 0:
-            raise ValueError("the lexicographic mode takes one island, no elite injection and instance-level weights")
+            raise ValueError("the lexicographic mode takes instance-level weights")
         self._read_back(s, st)
         return st
 
@@ -342,7 +342,7 @@ class OracleInstance:
         """Migration and elite injection at the end of epoch `epoch` (1-based)."""
         s = self._state_struct(st)
         pp = _params(params)
-        lib().or_migrate(C.byref(pp), self.n, C.byref(s), epoch)
+        lib().or_migrate(self.h, C.byref(pp), self.n, C.byref(s), epoch)
         self._read_back(s, st)
         return st
 

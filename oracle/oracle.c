@@ -527,13 +527,26 @@ static void sol_aos_update(const or_params *p, uint32_t mask, or_sol_aos *a, int
  * Elite injection (e % elite_epochs == 0, after the migration): the best of
  * the population replaces its worst.  best = smallest (best_f, index); worst
  * = largest (cur_f, index).  A replaced solution takes the elite's vector and
- * objective as its current solution, and as its own best when it improves it. */
-static void mig_put(or_state *st, int n, int tgt, const int32_t *vec, int64_t f) {
+ * objective as its current solution, and as its own best when it improves it.
+ * reading, lexicographic mode: the same rules with "smaller" replaced by the
+ * mode's relation -- best: a later solution replaces the one kept when
+ * strictly better; worst: when the one kept is not strictly better than it
+ * (as ties go to the later index in the scalar rule); an elite improves a
+ * solution when strictly better than its best vector. */
+static int mig_better(const or_inst *in, const int64_t *fa, const int64_t *va, const int64_t *fb,
+                      const int64_t *vb) {
+  return or_lex_mode(in) ? or_lex_better(in, va, vb) : *fa < *fb;
+}
+
+static void mig_put(const or_inst *in, or_state *st, int n, int tgt, const int32_t *vec, int64_t f,
+                    const int64_t v[4]) {
   memcpy(st->cur + (size_t)tgt * n, vec, sizeof(int32_t) * n);
   st->cur_f[tgt] = f;
-  if (f < st->best_f[tgt]) {
+  if (or_lex_mode(in)) memcpy(st->cur_v + 4 * (size_t)tgt, v, 4 * sizeof(int64_t));
+  if (mig_better(in, &f, v, &st->best_f[tgt], st->best_v + 4 * (size_t)tgt)) {
     st->best_f[tgt] = f;
     memcpy(st->best + (size_t)tgt * n, vec, sizeof(int32_t) * n);
+    if (or_lex_mode(in)) memcpy(st->best_v + 4 * (size_t)tgt, v, 4 * sizeof(int64_t));
   }
 }
 
@@ -543,26 +556,32 @@ static int in_list(const int *l, int cnt, int v) {
 }
 
 /* the cnt best of [lo, hi) by (best_f, index), in that order */
-static void best_of_range(const or_state *st, int lo, int hi, int cnt, int *out) {
+static void best_of_range(const or_inst *in, const or_state *st, int lo, int hi, int cnt, int *out) {
   for (int k = 0; k < cnt; ++k) {
     int b = -1;
     for (int s = lo; s < hi; ++s)
-      if (!in_list(out, k, s) && (b < 0 || st->best_f[s] < st->best_f[b])) b = s;
+      if (!in_list(out, k, s) &&
+          (b < 0 || mig_better(in, &st->best_f[s], st->best_v + 4 * (size_t)s, &st->best_f[b],
+                               st->best_v + 4 * (size_t)b)))
+        b = s;
     out[k] = b;
   }
 }
 
 /* the cnt worst of [lo, hi) by (cur_f, index), worst first */
-static void worst_of_range(const or_state *st, int lo, int hi, int cnt, int *out) {
+static void worst_of_range(const or_inst *in, const or_state *st, int lo, int hi, int cnt, int *out) {
   for (int k = 0; k < cnt; ++k) {
     int w = -1;
     for (int s = lo; s < hi; ++s)
-      if (!in_list(out, k, s) && (w < 0 || st->cur_f[s] >= st->cur_f[w])) w = s;
+      if (!in_list(out, k, s) &&
+          (w < 0 || !mig_better(in, &st->cur_f[s], st->cur_v + 4 * (size_t)s, &st->cur_f[w],
+                                st->cur_v + 4 * (size_t)w)))
+        w = s;
     out[k] = w;
   }
 }
 
-void or_migrate(const or_params *p, int n, or_state *st, uint32_t e) {
+void or_migrate(const or_inst *in, const or_params *p, int n, or_state *st, uint32_t e) {
   const int P = (int)p->population;
   const int I = p->islands > 1 ? (int)p->islands : 1, S = P / I;
   if (p->migrate_epochs && e % p->migrate_epochs == 0 && I >= 2) {
@@ -573,32 +592,39 @@ void or_migrate(const or_params *p, int n, or_state *st, uint32_t e) {
     int *src = (int *)malloc(sizeof(int) * n_src), *tgt = (int *)malloc(sizeof(int) * I * N);
     int32_t *vec = (int32_t *)malloc(sizeof(int32_t) * (size_t)n_src * n);
     int64_t *f = (int64_t *)malloc(sizeof(int64_t) * n_src);
+    int64_t *v = (int64_t *)calloc((size_t)n_src * 4, sizeof(int64_t));
     if (mode == 0) {
       for (int i = 0; i < I; ++i) {
-        best_of_range(st, i * S, (i + 1) * S, 1, &src[i]);
+        best_of_range(in, st, i * S, (i + 1) * S, 1, &src[i]);
         const int j = (i + 1) % I;
-        worst_of_range(st, j * S, (j + 1) * S, 1, &tgt[i]);
+        worst_of_range(in, st, j * S, (j + 1) * S, 1, &tgt[i]);
       }
     } else {
-      best_of_range(st, 0, P, N, src);
-      for (int i = 0; i < I; ++i) worst_of_range(st, i * S, (i + 1) * S, N, &tgt[i * N]);
+      best_of_range(in, st, 0, P, N, src);
+      for (int i = 0; i < I; ++i) worst_of_range(in, st, i * S, (i + 1) * S, N, &tgt[i * N]);
     }
     for (int k = 0; k < n_src; ++k) {   /* sources read before any copy */
       memcpy(vec + (size_t)k * n, st->best + (size_t)src[k] * n, sizeof(int32_t) * n);
       f[k] = st->best_f[src[k]];
+      if (or_lex_mode(in)) memcpy(v + 4 * (size_t)k, st->best_v + 4 * (size_t)src[k], 4 * sizeof(int64_t));
     }
     if (mode == 0)
-      for (int i = 0; i < I; ++i) mig_put(st, n, tgt[i], vec + (size_t)i * n, f[i]);
+      for (int i = 0; i < I; ++i) mig_put(in, st, n, tgt[i], vec + (size_t)i * n, f[i], v + 4 * (size_t)i);
     else
       for (int i = 0; i < I; ++i)
-        for (int k = 0; k < N; ++k) mig_put(st, n, tgt[i * N + k], vec + (size_t)k * n, f[k]);
-    free(src); free(tgt); free(vec); free(f);
+        for (int k = 0; k < N; ++k)
+          mig_put(in, st, n, tgt[i * N + k], vec + (size_t)k * n, f[k], v + 4 * (size_t)k);
+    free(src); free(tgt); free(vec); free(f); free(v);
   }
   if (p->elite_epochs && e % p->elite_epochs == 0) {
     int b, w;
-    best_of_range(st, 0, P, 1, &b);
-    worst_of_range(st, 0, P, 1, &w);
-    if (w != b) mig_put(st, n, w, st->best + (size_t)b * n, st->best_f[b]);
+    best_of_range(in, st, 0, P, 1, &b);
+    worst_of_range(in, st, 0, P, 1, &w);
+    if (w != b) {
+      int64_t vb[4] = {0, 0, 0, 0};
+      if (or_lex_mode(in)) memcpy(vb, st->best_v + 4 * (size_t)b, sizeof vb);
+      mig_put(in, st, n, w, st->best + (size_t)b * n, st->best_f[b], vb);
+    }
   }
 }
 
@@ -692,10 +718,10 @@ static int fq_cmp(const void *a, const void *b) {
  * random; ties in f keep the lower pool index. */
 int or_init(const or_inst *in, const or_params *p, or_state *st) {
   int n = in->d.n, P = p->population;
-  /* reading: the lexicographic mode runs one population under instance-level
-   * weights; islands, elite injection and per-solution weights compare by a
-   * scalar and are not combined with it */
-  if (or_lex_mode(in) && (p->islands > 1 || p->aos_scope == 1 || p->elite_epochs)) return -1;
+  /* reading: the lexicographic mode runs under instance-level weights; the
+   * per-solution scope tracks each solution's improvement by a scalar and is
+   * not combined with it */
+  if (or_lex_mode(in) && p->aos_scope == 1) return -1;
   int Q = p->oversample_k * P;
   int32_t *pool = (int32_t *)malloc(sizeof(int32_t) * (size_t)Q * n);
   int32_t *heur = (int32_t *)malloc(sizeof(int32_t) * (size_t)8 * n);
@@ -956,7 +982,7 @@ static void epoch_end(const or_inst *in, const or_params *p, or_state *st, uint3
     for (int s = 1; s < P; ++s) if (st->best_f[s] < ib) ib = st->best_f[s];
     or_aos_update(p, mask, st, ib);
   }
-  or_migrate(p, in->d.n, st, g_end / p->epoch);
+  or_migrate(in, p, in->d.n, st, g_end / p->epoch);
 }
 
 /* End of generation g: cooling, then the epoch end when one is reached. */

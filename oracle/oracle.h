@@ -91,7 +91,7 @@ int32_t  or_dist(const or_inst *, int32_t u, int32_t v);  /* TSP / VRPTW distanc
 int      or_apply_op(const or_inst *, int32_t *x, int op, uint32_t w1, uint32_t w2, uint32_t w3);
 void     or_initial_weights(const or_inst *, uint32_t op_mask, const uint32_t *init_w, uint32_t w_op[OR_MAX_OPS]);
 void     or_aos_update(const or_params *, uint32_t op_mask, or_state *st, int64_t inst_best_now);
-void     or_migrate(const or_params *, int n, or_state *st, uint32_t epoch);  /* epoch: 1-based count */
+void     or_migrate(const or_inst *in, const or_params *, int n, or_state *st, uint32_t epoch);  /* epoch: 1-based count */
 int      or_heuristic_perms(const or_inst *, int32_t *out, int cap); /* returns count */
 int      or_init(const or_inst *, const or_params *, or_state *st);
 void     or_random_solution(const or_inst *, const or_params *, uint32_t pool_index, int32_t *x);

@@ -149,8 +149,78 @@ def test_run_invariants_and_threaded_runner():
         assert not o.lex_better(a["best_v"][s], a["best_v"][i])
 
 
-def test_islands_and_solution_scope_are_refused():
+def test_solution_scope_is_refused():
     o = oracle.OracleInstance(vrptw(10, 2, lex_order=(DIST, 0, 0), lex_tol=(0, 0, 0)))
-    for kw in (dict(islands=2), dict(aos_scope=1), dict(elite_epochs=2)):
-        with pytest.raises(ValueError):
-            o.init(synth.Params(seed=1, population=4, candidates=64, generations=4, **kw))
+    with pytest.raises(ValueError):
+        o.init(synth.Params(seed=1, population=4, candidates=64, generations=4, aos_scope=1))
+
+
+def _lex_state(o, cur_v, best_v):
+    """Six solutions of a small instance whose vectors are set by hand; the
+    solution rows name their index (every copy can be traced)."""
+    st = o.new_state(6)
+    n = o.n
+    base = np.arange(n, dtype=np.int32)
+    for s in range(6):
+        st["cur"][s] = np.roll(base, s)
+        st["best"][s] = np.roll(base, s)
+    st["cur_v"][:] = np.asarray(cur_v, np.int64)
+    st["best_v"][:] = np.asarray(best_v, np.int64)
+    st["cur_f"][:] = st["cur_v"][:, 0] + st["cur_v"][:, 1]
+    st["best_f"][:] = st["best_v"][:, 0] + st["best_v"][:, 1]
+    return st
+
+
+def test_lexicographic_migration_by_hand():
+    # distance first within 50, then routes; three islands of two
+    o = oracle.OracleInstance(vrptw(6, 1, lex_order=(DIST, VEH, 0), lex_tol=(50, 0, 0)))
+    best_v = [[0, 800, 5, 0], [0, 830, 4, 0],     # island 0: s1 is better (tie on distance, fewer routes)
+              [0, 700, 6, 0], [0, 760, 5, 0],     # island 1: s2 (more than 50 shorter)
+              [100, 500, 3, 0], [0, 900, 7, 0]]   # island 2: s5 (penalty first)
+    cur_v = [[0, 900, 6, 0], [0, 920, 6, 0],      # island 0: tie within 50 on distance and routes -> s1 worst (later)
+             [0, 850, 5, 0], [0, 820, 9, 0],      # island 1: s3 is not better than s2 (within 50, more routes) -> s3
+             [0, 800, 4, 0], [200, 100, 1, 0]]    # island 2: s5 (penalty)
+    st = o.migrate(synth.Params(population=6, islands=3, migrate_epochs=1, migrate_mode=0),
+                   _lex_state(o, cur_v, best_v), 1)
+    # ring: s1's best -> island 1's worst s3; s2's best -> island 2's worst s5; s5's best -> island 0's worst s1
+    assert st["cur"][3].tolist() == np.roll(np.arange(o.n), 1).tolist() and st["cur_v"][3].tolist() == best_v[1]
+    assert st["cur"][5].tolist() == np.roll(np.arange(o.n), 2).tolist() and st["cur_v"][5].tolist() == best_v[2]
+    assert st["cur"][1].tolist() == np.roll(np.arange(o.n), 5).tolist() and st["cur_v"][1].tolist() == best_v[5]
+    # a target's best changes only when the elite is strictly better than it
+    assert st["best_v"][3].tolist() == best_v[3]          # [0,830,4] vs [0,760,5]: 830 > 760 + 50, not better
+    assert st["best_v"][5].tolist() == best_v[2]          # [0,700,6] vs [0,900,7]: better
+    assert st["best_v"][1].tolist() == best_v[1]          # penalty 100 vs 0: not better
+    assert st["cur_f"][3] == 830 and st["best_f"][5] == 700
+    for s in (0, 2, 4):
+        assert st["cur_v"][s].tolist() == cur_v[s]
+
+
+def test_lexicographic_elite_injection_by_hand():
+    o = oracle.OracleInstance(vrptw(6, 1, lex_order=(VEH, DIST, 0), lex_tol=(0, 30, 0)))
+    best_v = [[0, 5, 700, 0], [0, 4, 900, 0], [0, 4, 880, 0], [0, 6, 500, 0], [0, 4, 860, 0], [0, 5, 100, 0]]
+    # best: s1 (4 routes), s2 ties s1 within 30, s4 beats s1 by more than 30? 860 + 30 < 900: yes -> s4
+    cur_v = [[0, 5, 100, 0]] * 6
+    st = o.migrate(synth.Params(population=6, elite_epochs=1), _lex_state(o, cur_v, best_v), 1)
+    # every current vector ties: the worst is the last one, s5, which takes s4's best
+    assert st["cur_v"][5].tolist() == best_v[4] and st["cur_f"][5] == 4
+    assert st["best_v"][5].tolist() == best_v[4]          # 4 routes beat 5
+    assert [s for s in range(6) if st["cur_v"][s].tolist() != cur_v[s]] == [5]
+
+
+def test_islands_run_invariants():
+    inst = vrptw(16, 12, lex_order=(DIST, VEH, 0), lex_tol=(25, 0, 0))
+    o = oracle.OracleInstance(inst)
+    for mode in (0, 1, 2):
+        p = synth.Params(seed=5, population=8, candidates=64, generations=30, epoch=3, islands=2,
+                         migrate_epochs=2, migrate_mode=mode, migrate_n=2, elite_epochs=3,
+                         alpha_q32=synth.alpha_q32_for(30))
+        a = o.init(p)
+        b = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in a.items()}
+        o.run(p, a, 30)
+        o.run(p, b, 30, threads=3)
+        for k in a:
+            assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (mode, k)
+        for s in range(p.population):
+            assert list(o.lex_vector(a["cur"][s])) == list(a["cur_v"][s])
+            assert list(o.lex_vector(a["best"][s])) == list(a["best_v"][s])
+            assert not o.lex_better(a["cur_v"][s], a["best_v"][s])
