@@ -141,9 +141,10 @@ gx_status gx_get_device_info(gx_ctx *ctx, gx_device_info *out);
  *            population) the best is found by a scan in index order that
  *            keeps the first element no later one is better than.  The
  *            scalar reported for a solution (cur_f, best_f, the best
- *            objective) is its penalty plus its level-1 value.  obj_weights
- *            must be zero in this mode; solves on such an instance take one
- *            island, no elite injection and aos_scope 0, and cannot be
+ *            objective) is its penalty plus its level-1 value; island
+ *            migration and elite injection pick best and worst solutions by
+ *            the same relation.  obj_weights must be zero in this mode;
+ *            solves on such an instance take aos_scope 0 and cannot be
  *            restored (gx_job_restore).
  *   INTCOLOR a = edge list n_edges x 2 (no self loops); values in [lb, ub];
  *            f = number of edges whose ends share a value.
@@ -270,7 +271,10 @@ gx_status gx_fetch_best(gx_ctx *ctx, gx_job *job, int32_t *solution_out, int32_t
  * one instance with different seeds, the best kept; here the solves share one
  * device, e.g. the jobs of one gx_solve_batch call): among count >= 1 jobs of
  * the same instance, the one whose best objective is smallest (ties: the
- * lowest position in jobs); its index into *index_out, its objective into
+ * lowest position in jobs; in the VRPTW lexicographic mode the jobs' best
+ * objective vectors are compared by that mode's relation, in job order, a
+ * later job replacing the one kept only when strictly better); its index
+ * into *index_out, its objective into
  * *objective_out and its best solution into solution_out[capacity >= n].
  * GX_E_INVALID for null arguments, count < 1 or jobs of different instances.
  * Synchronises the stream. */

@@ -621,8 +621,8 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
     return fail(c, GX_E_INVALID, "per-solution weights need aos_epoch * candidates <= 2^30");
   for (int i = 0; i < kOps; ++i)
     if (p->init_weight_q16[i] > (1u << 24)) return fail(c, GX_E_INVALID, "init_weight_q16 entries <= 2^24");
-  if (ii.h.lex_levels && (isl > 1 || p->elite_epochs || p->aos_scope))
-    return fail(c, GX_E_UNSUPPORTED, "the lexicographic mode takes one island, no elite injection and aos_scope 0");
+  if (ii.h.lex_levels && p->aos_scope)
+    return fail(c, GX_E_UNSUPPORTED, "the lexicographic mode takes aos_scope 0");
   const uint32_t lds = job_lds(ii, stage, mask);
   if (lds > lds_limit)
     return fail(c, GX_E_UNSUPPORTED, "instance needs %u bytes of LDS per workgroup (limit %u)", lds, lds_limit);
@@ -1025,18 +1025,39 @@ gx_status gx_fetch_best(gx_ctx *c, gx_job *j, int32_t *sol, int32_t cap, int64_t
   return GX_OK;
 }
 
+// a strictly better than b in the lexicographic mode of instance h (the
+// penalty exactly, then each level within its tolerance)
+static bool lex_better_host(const int64_t a[4], const int64_t b[4], const DevInst &h) {
+  if (a[0] != b[0]) return a[0] < b[0];
+  for (int i = 0; i < h.lex_levels; ++i) {
+    if (a[1 + i] + h.lex_tol[i] < b[1 + i]) return true;
+    if (b[1 + i] + h.lex_tol[i] < a[1 + i]) return false;
+  }
+  return false;
+}
+
 gx_status gx_portfolio_best(gx_ctx *c, gx_job *const *jobs, int32_t count, int32_t *sol, int32_t cap, int64_t *obj,
                             int32_t *index) {
   if (!c || !jobs || count < 1 || !obj || !index) return fail(c, GX_E_INVALID, "bad portfolio arguments");
   for (int i = 0; i < count; ++i)
     if (!jobs[i] || jobs[i]->inst != jobs[0]->inst) return fail(c, GX_E_INVALID, "portfolio jobs must share one instance");
+  const DevInst &ih = jobs[0]->inst->h;
   int best = 0;
-  int64_t fb = 0;
+  int64_t fb = 0, vb[4] = {0, 0, 0, 0};
   for (int i = 0; i < count; ++i) {
     int64_t f = 0;
     gx_status st = gx_fetch_best(c, jobs[i], nullptr, 0, &f);
     if (st) return st;
-    if (i == 0 || f < fb) {
+    bool take = i == 0 || f < fb;
+    if (ih.lex_levels) {   // the job's reported best vector, compared in job order
+      int32_t bi = 0;
+      int64_t v[4];
+      HIPCHK(c, hipMemcpy(&bi, (char *)jobs[i]->d + offsetof(DevJob, best_idx), 4, hipMemcpyDeviceToHost));
+      HIPCHK(c, hipMemcpy(v, jobs[i]->h.best_v + 4 * (size_t)bi, 32, hipMemcpyDeviceToHost));
+      take = i == 0 || lex_better_host(v, vb, ih);
+      if (take) memcpy(vb, v, sizeof vb);
+    }
+    if (take) {
       fb = f;
       best = i;
     }

@@ -1936,7 +1936,30 @@ struct MigLds {
   long long f[kMaxIslands * kMaxMigN];
   const int32_t *row[kMaxIslands * kMaxMigN];
   int src[kMaxIslands];
+  Vec4 v[kMaxIslands * kMaxMigN];   // the source's best vector (lexicographic mode)
 };
+
+// Lexicographic mode: the best (best vectors; a later solution replaces the
+// one kept when strictly better) or the worst (current vectors; a later one
+// replaces the one kept when the kept one is not strictly better than it) of
+// [lo, hi) outside ex[0..nex), by an ordered scan; the scalar rules with
+// "smaller" replaced by the mode's relation.  Uniform over the calling lanes.
+template <bool BEST>
+__device__ int lex_pick(const DevJob *J, const LexCfg &L, int lo, int hi, const int *ex, int nex) {
+  const int64_t *V = BEST ? J->best_v : J->cur_v;
+  int k = -1;
+  Vec4 kv = {};
+  for (int s = lo; s < hi; ++s) {
+    if (listed(ex, nex, s)) continue;
+    const Vec4 x = load_vec(V + 4 * (size_t)s);
+    const bool take = k < 0 || (BEST ? lex_better(x, kv, L) : !lex_better(x, kv, L));
+    if (take) {
+      k = s;
+      kv = x;
+    }
+  }
+  return k;
+}
 
 // Copies for `npairs` (target, source row) pairs in M: target t takes the
 // n-vector row as its current solution and objective f, and as its best when
@@ -1944,7 +1967,10 @@ struct MigLds {
 // Targets are distinct and no source row is a target's row.  All threads of
 // the workgroup take part.
 __device__ void mig_copy(DevJob *J, int n, int npairs, MigLds &M) {
-  for (int q = (int)threadIdx.x; q < npairs; q += (int)blockDim.x) M.better[q] = M.f[q] < J->best_f[M.tgt[q]];
+  const bool lex = J->lex_levels != 0;
+  for (int q = (int)threadIdx.x; q < npairs; q += (int)blockDim.x)
+    M.better[q] = lex ? lex_better(M.v[q], load_vec(J->best_v + 4 * (size_t)M.tgt[q]), lex_cfg(J->inst))
+                      : M.f[q] < J->best_f[M.tgt[q]];
   __syncthreads();
   group_copy(
       npairs * n, [&](int e) { return M.row[e / n][e % n]; },
@@ -1957,6 +1983,10 @@ __device__ void mig_copy(DevJob *J, int n, int npairs, MigLds &M) {
   for (int q = (int)threadIdx.x; q < npairs; q += (int)blockDim.x) {
     J->cur_f[M.tgt[q]] = M.f[q];
     if (M.better[q]) J->best_f[M.tgt[q]] = M.f[q];
+    if (lex) {
+      store_vec(J->cur_v + 4 * (size_t)M.tgt[q], M.v[q]);
+      if (M.better[q]) store_vec(J->best_v + 4 * (size_t)M.tgt[q], M.v[q]);
+    }
   }
   // vectors and objectives visible to the next choice: the workgroup's
   // waves share one CU, so the barrier's workgroup-scope ordering suffices (a
@@ -1967,6 +1997,8 @@ __device__ void mig_copy(DevJob *J, int n, int npairs, MigLds &M) {
 __device__ void migrate_block(DevJob *J, uint32_t e, MigLds &M) {
   const int P = (int)J->P, n = J->inst->n, I = (int)J->islands, S = P / I;
   const int nw = (int)(blockDim.x / kWave), w = (int)(threadIdx.x / kWave);
+  const bool lex = J->lex_levels != 0;
+  const LexCfg L = lex_cfg(J->inst);
   if (J->mig_epochs && e % J->mig_epochs == 0 && I >= 2) {
     int mode = (int)J->mig_mode;
     if (mode == 2) mode = ((e / J->mig_epochs) & 1) ? 0 : 1;
@@ -1975,8 +2007,10 @@ __device__ void migrate_block(DevJob *J, uint32_t e, MigLds &M) {
     if (mode == 0) {   // island i's best and island i+1's worst, islands spread over the waves
       for (int i = w; i < I; i += nw) {
         const int j = i + 1 == I ? 0 : i + 1;
-        const int src = wave_pick<true>(J->best_f, i * S, (i + 1) * S, chosen, 0);
-        const int tgt = wave_pick<false>(J->cur_f, j * S, (j + 1) * S, chosen, 0);
+        const int src = lex ? lex_pick<true>(J, L, i * S, (i + 1) * S, chosen, 0)
+                            : wave_pick<true>(J->best_f, i * S, (i + 1) * S, chosen, 0);
+        const int tgt = lex ? lex_pick<false>(J, L, j * S, (j + 1) * S, chosen, 0)
+                            : wave_pick<false>(J->cur_f, j * S, (j + 1) * S, chosen, 0);
         if (lane_id() == 0) {
           M.src[i] = src;
           M.tgt[i] = tgt;
@@ -1984,12 +2018,13 @@ __device__ void migrate_block(DevJob *J, uint32_t e, MigLds &M) {
       }
     } else {           // the population's N best, then each island's N worst
       for (int k = 0; k < N; ++k) {
-        chosen[k] = block_pick<true>(J->best_f, 0, P, chosen, k);
+        chosen[k] = lex ? lex_pick<true>(J, L, 0, P, chosen, k) : block_pick<true>(J->best_f, 0, P, chosen, k);
         if (threadIdx.x == 0) M.src[k] = chosen[k];
       }
       for (int i = w; i < I; i += nw)
         for (int k = 0; k < N; ++k) {
-          chosen[k] = wave_pick<false>(J->cur_f, i * S, (i + 1) * S, chosen, k);
+          chosen[k] = lex ? lex_pick<false>(J, L, i * S, (i + 1) * S, chosen, k)
+                          : wave_pick<false>(J->cur_f, i * S, (i + 1) * S, chosen, k);
           if (lane_id() == 0) M.tgt[i * N + k] = chosen[k];
         }
     }
@@ -2005,19 +2040,21 @@ __device__ void migrate_block(DevJob *J, uint32_t e, MigLds &M) {
       const int k = mode == 0 ? q : q % N;
       M.row[q] = J->pool + (size_t)k * n;
       M.f[q] = J->best_f[M.src[k]];
+      if (lex) M.v[q] = load_vec(J->best_v + 4 * (size_t)M.src[k]);
     }
     __syncthreads();
     mig_copy(J, n, npairs, M);
   }
   if (J->elite_epochs && e % J->elite_epochs == 0) {
     int none[1];
-    const int b = block_pick<true>(J->best_f, 0, P, none, 0);
-    const int wst = block_pick<false>(J->cur_f, 0, P, none, 0);
+    const int b = lex ? lex_pick<true>(J, L, 0, P, none, 0) : block_pick<true>(J->best_f, 0, P, none, 0);
+    const int wst = lex ? lex_pick<false>(J, L, 0, P, none, 0) : block_pick<false>(J->cur_f, 0, P, none, 0);
     if (wst != b) {
       if (threadIdx.x == 0) {
         M.tgt[0] = wst;
         M.row[0] = J->best + (size_t)b * n;
         M.f[0] = J->best_f[b];
+        if (lex) M.v[0] = load_vec(J->best_v + 4 * (size_t)b);
       }
       __syncthreads();
       mig_copy(J, n, 1, M);
@@ -2065,7 +2102,10 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t src) {
 // k = q + 1 (their statistics, run totals and weights: loads, the Eq. ema
 // update with its clamp, the normalisation through a wave sum, stores); the
 // scalars are uniform and lane 0 stores them.
-__device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, uint32_t g1) {
+// pre (lexicographic mode, launches that migrate): the instance best's vector
+// and objective taken before the exchange, which may change best vectors
+__device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, uint32_t g1,
+                                           const long long *pre = nullptr) {
   const uint32_t l = threadIdx.x;
   constexpr uint32_t kMinSlot = kCountSlots, kAccSlot = 2 * kOps + 6;
   const bool op_lane = l < (uint32_t)kOps, k_lane = l >= 2u * kOps && l < 2u * kOps + 3;
@@ -2147,11 +2187,17 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
     int64_t ref_now = inst_best;
     if (lex) {   // the instance best by the ordered scan; improved when strictly better than the last one
       const LexCfg L = lex_cfg(J->inst);
-      const uint32_t b = lex_scan_best(J, L);
-      const Vec4 now = load_vec(J->best_v + 4 * (size_t)b);
+      Vec4 now;
+      if (pre) {
+        now = load_vec((const int64_t *)pre);
+        ref_now = pre[4];
+      } else {
+        const uint32_t b = lex_scan_best(J, L);
+        now = load_vec(J->best_v + 4 * (size_t)b);
+        ref_now = J->best_f[b];
+      }
       improved = lex_better(now, load_vec(J->ref_v), L);
       if (l == 0) store_vec(J->ref_v, now);
-      ref_now = J->best_f[b];
     }
     if (improved) stag = 0;
     else stag += 1;
@@ -2205,9 +2251,20 @@ __global__ __launch_bounds__(kEpochWide) void k_epoch_mig(DevJob *jobs, const ui
   __syncthreads();   // every wave has read g before wave 0 advances it
   if (g0 >= gstop) return;
   const uint32_t g1 = min(gstop, (g0 / E + 1) * E);
+  // the lexicographic instance best is taken on the state before the exchange
+  __shared__ long long pre[5];
+  const bool lex_pre = J->lex_levels != 0 && J->aos_scope == 0 && g1 % E == 0;
+  if (lex_pre && threadIdx.x < kWave) {
+    const uint32_t b = lex_scan_best(J, lex_cfg(J->inst));
+    if (threadIdx.x == 0) {
+      store_vec((int64_t *)pre, load_vec(J->best_v + 4 * (size_t)b));
+      pre[4] = J->best_f[b];
+    }
+  }
+  __syncthreads();
   if (g1 % E == 0 && (J->mig_epochs | J->elite_epochs)) migrate_block(J, g1 / E, *(MigLds *)gx_lds);
   if (threadIdx.x >= kWave) return;
-  epoch_fold(J, g0, E, g1);
+  epoch_fold(J, g0, E, g1, lex_pre ? pre : nullptr);
 }
 
 namespace {

@@ -3,7 +3,8 @@ Optimization Modes"; Tab. lexicographic_mode), through the C interface,
 bit for bit against the oracle: every state field, the objective vectors of
 every solution, the stagnation reference and the run totals after each split
 of the run; the best solution a solve reports; a batch that mixes modes; a
-served request; and the combinations the interface refuses.
+served request; island migration and elite injection; the portfolio pick;
+and the combinations the interface refuses.
 
 The instances are VRPTW stand-ins (synth.vrptw_random) with a small fleet, so
 that the penalty level (lateness and fleet excess) takes part in the
@@ -97,6 +98,36 @@ def test_lex_parity(ctx, case):
     gx.gx_instance_free(ctx, h)
 
 
+ISLANDS = {
+    "ring": dict(islands=2, migrate_epochs=2, migrate_mode=0),
+    "top-n": dict(islands=4, migrate_epochs=1, migrate_mode=1, migrate_n=1),
+    "top-2": dict(islands=2, migrate_epochs=1, migrate_mode=1, migrate_n=2),
+    "hybrid-elite": dict(islands=2, migrate_epochs=2, migrate_mode=2, migrate_n=2, elite_epochs=3),
+    "elite-only": dict(elite_epochs=2),
+}
+
+
+@pytest.mark.parametrize("case", list(ISLANDS))
+def test_lex_islands_parity(ctx, case):
+    """Island migration and elite injection in the lexicographic mode: the
+    picks and the improvement test by the mode's relation, vectors copied
+    with the solutions, the stagnation reference taken before the exchange."""
+    inst = lex_inst(22, 71, (DIST, VEH, LONG), (35, 0, 10))
+    p = P(48, seed=13, population=8, candidates=128, epoch=3, stagnation_epochs=2, **ISLANDS[case])
+    print(f"[lex islands] {case}", flush=True)
+    h = gx.gx_instance_upload(ctx, inst)
+    job = gx.gx_job_create(ctx, h, p)
+    o = oracle.OracleInstance(inst)
+    st = o.init(p)
+    compare(ctx, job, p, inst.n, st, f"islands {case} init")
+    for i, s in enumerate([7, 11, 30]):
+        gx.gx_job_advance(ctx, job, s)
+        o.run(p, st, s)
+        compare(ctx, job, p, inst.n, st, f"islands {case} split {i}")
+    gx.gx_job_free(ctx, job)
+    gx.gx_instance_free(ctx, h)
+
+
 def test_one_level_without_penalty_matches_the_scalar_kernel(ctx):
     """Distance alone, tolerance 0, no penalty possible: the lexicographic
     kernel and the weighted kernel run the same generations."""
@@ -162,9 +193,8 @@ def test_served_lex_request(ctx):
 def test_refusals(ctx):
     inst = lex_inst(15, 95, (DIST, 0, 0), (0, 0, 0))
     h = gx.gx_instance_upload(ctx, inst)
-    for kw in (dict(islands=2), dict(aos_scope=1), dict(elite_epochs=2)):
-        with pytest.raises(gx.GxError):
-            gx.gx_job_create(ctx, h, P(10, seed=1, population=4, **kw))
+    with pytest.raises(gx.GxError):
+        gx.gx_job_create(ctx, h, P(10, seed=1, population=4, aos_scope=1))
     job = gx.gx_job_create(ctx, h, P(10, seed=1, population=4))
     snap = gx.gx_snapshot(ctx, job, 4, inst.n)
     with pytest.raises(gx.GxError):
@@ -187,3 +217,27 @@ def test_refusals(ctx):
             gx.gx_instance_upload(ctx, dataclasses.replace(s, **kw))
     with pytest.raises(gx.GxError):
         gx.gx_instance_upload(ctx, dataclasses.replace(synth.tsp_uniform(20, 1, key=97), lex_order=(DIST, 0, 0)))
+
+
+def test_portfolio_compares_vectors(ctx):
+    """Seeds of one lexicographic instance in one batch: the portfolio pick is
+    the ordered scan, in job order, over the oracle's reported best vectors."""
+    inst = lex_inst(24, 98, (VEH, DIST, LONG), (0, 40, 0))
+    params = [P(36, seed=s, population=4, candidates=128, epoch=4) for s in (42, 123, 456, 789, 2024)]
+    h = gx.gx_instance_upload(ctx, inst)
+    jobs = gx.gx_solve_batch(ctx, [h] * len(params), params)
+    gx.gx_wait(ctx)
+    sol, f, idx = gx.gx_portfolio_best(ctx, jobs, inst.n)
+    o = oracle.OracleInstance(inst)
+    keep, kv, kf = 0, None, None
+    for i, p in enumerate(params):
+        st = o.solve(p)
+        fo, io = o.best_of(st)
+        v = st["best_v"][io]
+        if i == 0 or o.lex_better(v, kv):
+            keep, kv, kf = i, v, fo
+    assert idx == keep and f == kf, (idx, keep, f, kf)
+    assert list(o.lex_vector(sol)) == list(kv)
+    for j in jobs:
+        gx.gx_job_free(ctx, j)
+    gx.gx_instance_free(ctx, h)

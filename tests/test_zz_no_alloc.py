@@ -1,8 +1,11 @@
 """gx_solve_static (the entry point that allocates nothing: its device state
 lives in the library's static workspace) against gx_solve on the same
-requests: two calls in a row, the second smaller than the first, each equal
-to the plain solve in its best solution and objective; a solve larger than
-the workspace is refused on the host."""
+requests: three calls in a row, each smaller than the one before (the last a
+VRPTW instance in the lexicographic mode, whose objective vectors live in the
+workspace too), each equal to the plain solve in its best solution and
+objective; a solve larger than the workspace is refused on the host."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -26,8 +29,12 @@ def test_static_solves_equal_plain_solves():
         reqs = [(synth.tsp_clustered(150, 3, key=61),
                  synth.Params(seed=42, generations=120, population=48, alpha_q32=synth.alpha_q32_for(120))),
                 (synth.qap_random(18, 3, key=62),
-                 synth.Params(seed=7, generations=60, population=6, alpha_q32=synth.alpha_q32_for(60), aos_scope=1))]
-        for inst, p in reqs:                      # the second call is the smaller one
+                 synth.Params(seed=7, generations=60, population=6, alpha_q32=synth.alpha_q32_for(60), aos_scope=1)),
+                # a VRPTW instance in the lexicographic mode: its objective vectors in the workspace too
+                (dataclasses.replace(synth.vrptw_random(16, 3, key=64), vehicles=2, lex_order=(2, 1, 0),
+                                     lex_tol=(0, 15, 0)),
+                 synth.Params(seed=9, generations=40, population=4, alpha_q32=synth.alpha_q32_for(40)))]
+        for inst, p in reqs:                      # each call smaller than the one before
             print(f"[static] kind {inst.kind} n={inst.n} P={p.population}", flush=True)
             h = gx.gx_instance_upload(ctx, inst)
             sol_d = torch.full((inst.n,), -1, dtype=torch.int32, device="cuda")
