@@ -279,27 +279,6 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Wave-wide sum of a 64-bit value with DPP moves only (the same pattern as
-// wave_min_u32; the row broadcasts add into rows 1, 3 and then 2, 3 only, the
-// other rows add zero); the sum is uniform.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, ROW_MASK, 0xF, false);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, ROW_MASK, 0xF, false);
-  return ((uint64_t)hi << 32) | lo;
-}
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-  v += dpp64<0xB1, 0xF>(v);
-  v += dpp64<0x4E, 0xF>(v);
-  v += dpp64<0x141, 0xF>(v);
-  v += dpp64<0x140, 0xF>(v);
-  v += dpp64<0x142, 0xA>(v);
-  v += dpp64<0x143, 0xC>(v);
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
-  return ((uint64_t)hi << 32) | lo;
-}
-
 // wave-wide minimum of a 64-bit key, high word first (result is uniform)
 __device__ __forceinline__ unsigned long long wave_min_key(unsigned long long k) {
   const uint32_t hi = wave_min_u32((uint32_t)(k >> 32));
