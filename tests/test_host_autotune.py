@@ -29,3 +29,17 @@ def test_plan_rounds_in_log_space_and_clamps():
 def test_buckets():
     assert autotune.bucket_of(1, 20) == "1:32" and autotune.bucket_of(1, 200) == "1:256"
     assert autotune.bucket_of(2, 40) == "2:64" and autotune.bucket_of(1, 5000) == "1:big"
+
+
+def test_cache_key_follows_the_kernel_sources(tmp_path, monkeypatch):
+    """The measurement cache is keyed on a hash of the HIP sources: a changed
+    source gives a different key, an unchanged tree the same one."""
+    src = tmp_path / "csrc"
+    src.mkdir()
+    (src / "a.hip").write_text("kernel one")
+    (src / "b.hpp").write_text("header")
+    monkeypatch.setattr(autotune, "_HERE", str(tmp_path))
+    h1 = autotune.kernel_source_hash()
+    assert autotune.kernel_source_hash() == h1
+    (src / "a.hip").write_text("kernel two")
+    assert autotune.kernel_source_hash() != h1
