@@ -217,7 +217,8 @@ class OracleInstance:
 
     @property
     def n(self):
-        return self.inst.n
+        """Entries of a solution: n, or n customers plus one marker per row in the multi-row VRPTW form."""
+        return self.inst.n + (self.inst.vehicles if self.inst.kind == 6 else 0)
 
     def objective(self, x) -> int:
         x = np.ascontiguousarray(x, dtype=np.int32)

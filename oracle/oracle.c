@@ -24,15 +24,16 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { K_TSP = 1, K_QAP = 2, K_KNAP = 3, K_VRPTW = 4, K_COLOR = 5 };
-enum { OP_2OPT = 0, OP_SWAP = 1, OP_INSERT = 2, OP_OROPT = 3, OP_3OPT = 4, OP_FLIP = 8, OP_SEGFLIP = 9,
-       OP_RESET = 10, OP_SEGRESET = 11 };
+enum { K_TSP = 1, K_QAP = 2, K_KNAP = 3, K_VRPTW = 4, K_COLOR = 5, K_VRPROWS = 6 };
+enum { OP_2OPT = 0, OP_SWAP = 1, OP_INSERT = 2, OP_OROPT = 3, OP_3OPT = 4, OP_ROWSWAP = 5, OP_ROWSPLIT = 6,
+       OP_ROWMERGE = 7, OP_FLIP = 8, OP_SEGFLIP = 9, OP_RESET = 10, OP_SEGRESET = 11 };
 
 struct or_inst {
   or_inst_desc d;
   int32_t *dist;   /* TSP: n x n; VRPTW: (n+1) x (n+1) */
   int32_t dn;      /* side of dist */
   int64_t lambda;  /* knapsack penalty weight */
+  int32_t nc;      /* multi-row VRPTW: customers (the solution holds nc + vehicles entries, d.n) */
 };
 
 /* ------------------------------------------------------------------ RNG
@@ -120,8 +121,8 @@ or_inst *or_inst_new(const or_inst_desc *d) {
         in->dist[(int64_t)i * n + j] =
             d->a_is_coords ? or_nint_dist(d->a[2 * i], d->a[2 * i + 1], d->a[2 * j], d->a[2 * j + 1])
                            : d->a[(int64_t)i * n + j];
-  } else if (d->kind == K_VRPTW) {
-    if (!d->b) { free(in); return NULL; }
+  } else if (d->kind == K_VRPTW || d->kind == K_VRPROWS) {
+    if (!d->b || (d->kind == K_VRPROWS && d->vehicles < 1)) { free(in); return NULL; }
     if (d->obj_w[0] == 0 && d->obj_w[1] == 0 && d->obj_w[2] == 0) in->d.obj_w[0] = 1;
     int m = n + 1;
     in->dn = m;
@@ -130,6 +131,10 @@ or_inst *or_inst_new(const or_inst_desc *d) {
       for (int j = 0; j < m; ++j)
         in->dist[(int64_t)i * m + j] =
             or_nint_dist(d->a[2 * i], d->a[2 * i + 1], d->a[2 * j], d->a[2 * j + 1]);
+    if (d->kind == K_VRPROWS) {   /* the solution: n customers and one marker per row */
+      in->nc = n;
+      in->d.n = n + d->vehicles;
+    }
   } else if (d->kind == K_QAP || d->kind == K_KNAP) {
     if (!d->b) { free(in); return NULL; }
     if (d->kind == K_KNAP) {
@@ -224,25 +229,74 @@ static void vrptw_parts(const or_inst *in, const int32_t *x, int64_t parts[5]) {
   parts[0] = dist; parts[1] = routes; parts[2] = longest; parts[3] = late; parts[4] = extra > 0 ? extra : 0;
 }
 
+/* Sec. "Solution Structure": a multi-row solution keeps one route per row
+ * (Tab. generality runs CVRP and VRPTW in this form).  Entries below nc are
+ * customers (entry c is node c + 1), the others row markers; a row is the run
+ * of customers before its marker and goes from the depot through them in
+ * order and back.  reading: an empty row is no route; lateness as for the
+ * giant tour; a row's load above the capacity costs 100 per unit (the row
+ * form's penalty, where the giant tour's split keeps every route within the
+ * capacity).  parts as vrptw_parts, plus parts[5] = load above capacity. */
+static void rows_parts(const or_inst *in, const int32_t *x, int64_t parts[6]) {
+  const int N = in->d.n, m = in->nc + 1;
+  const int32_t *dem = in->d.b, *ready = in->d.b + m, *due = in->d.b + 2 * m;
+  int64_t dist = 0, late = 0, longest = 0, over = 0;
+  int routes = 0, start = 0;
+  for (int p = 0; p < N; ++p) {
+    if (x[p] < in->nc) continue;            /* a customer */
+    if (p > start) {                        /* the row of entries start .. p-1 */
+      int64_t t = 0, load = 0, len = 0;
+      int prev = 0;
+      for (int i = start; i < p; ++i) {
+        int c = x[i] + 1;
+        int64_t dd = or_dist(in, prev, c);
+        dist += dd; len += dd; t += dd;
+        if (t < ready[c]) t = ready[c];
+        if (t > due[c]) late += t - due[c];
+        t += in->d.service_time;
+        load += dem[c];
+        prev = c;
+      }
+      int64_t back = or_dist(in, prev, 0);
+      dist += back; len += back; t += back;
+      if (t > in->d.horizon) late += t - in->d.horizon;
+      if (len > longest) longest = len;
+      if (load > in->d.capacity) over += load - in->d.capacity;
+      routes++;
+    }
+    start = p + 1;
+  }
+  parts[0] = dist; parts[1] = routes; parts[2] = longest; parts[3] = late; parts[4] = 0; parts[5] = over;
+}
+
+/* the parts of either VRPTW form (parts[5]: load above capacity, 0 for the giant tour) */
+static void vrp_parts(const or_inst *in, const int32_t *x, int64_t parts[6]) {
+  if (in->d.kind == K_VRPROWS) rows_parts(in, x, parts);
+  else { vrptw_parts(in, x, parts); parts[5] = 0; }
+}
+
 static int64_t obj_vrptw(const or_inst *in, const int32_t *x) {
-  int64_t q[5];
-  vrptw_parts(in, x, q);
+  int64_t q[6];
+  vrp_parts(in, x, q);
   return (int64_t)in->d.obj_w[0] * q[0] + (int64_t)in->d.obj_w[1] * q[1] + (int64_t)in->d.obj_w[2] * q[2] +
-         100 * q[3] + 10000 * q[4];
+         100 * q[3] + 10000 * q[4] + 100 * q[5];
 }
 
 /* Sec. "Multi-Objective Optimization Modes", lexicographic mode.  reading:
- * the penalty (lateness and fleet excess, as in the weighted mode) comes
+ * the penalty (lateness, fleet excess and, in the row form, load above capacity,
+ * as in the weighted mode) comes
  * first and is compared exactly; then the objectives in the caller's
  * priority order, where two values within the level's tolerance are equal
  * and the next level decides.  v = (penalty, level 1, level 2, level 3),
  * unused levels 0. */
-int or_lex_mode(const or_inst *in) { return in->d.kind == K_VRPTW && in->d.lex_order[0] != 0; }
+int or_lex_mode(const or_inst *in) {
+  return (in->d.kind == K_VRPTW || in->d.kind == K_VRPROWS) && in->d.lex_order[0] != 0;
+}
 
 void or_lex_vector(const or_inst *in, const int32_t *x, int64_t v[4]) {
-  int64_t q[5];
-  vrptw_parts(in, x, q);
-  v[0] = 100 * q[3] + 10000 * q[4];
+  int64_t q[6];
+  vrp_parts(in, x, q);
+  v[0] = 100 * q[3] + 10000 * q[4] + 100 * q[5];
   for (int i = 0; i < 3; ++i) {
     int id = in->d.lex_order[i];
     v[1 + i] = id ? q[id - 1] : 0;
@@ -283,7 +337,7 @@ int64_t or_objective(const or_inst *in, const int32_t *x) {
     case K_TSP: return obj_tsp(in, x);
     case K_QAP: return obj_qap(in, x);
     case K_KNAP: return obj_knap(in, x);
-    case K_VRPTW: return obj_vrptw(in, x);
+    case K_VRPTW: case K_VRPROWS: return obj_vrptw(in, x);
     default: return obj_color(in, x);
   }
 }
@@ -296,8 +350,18 @@ static void reverse_range(int32_t *x, int lo, int hi) {
   while (lo < hi) { int32_t t = x[lo]; x[lo] = x[hi]; x[hi] = t; ++lo; --hi; }
 }
 
+static void perm_op(int32_t *x, int n, int op, uint32_t w1, uint32_t w2, uint32_t w3);
+static void row_op(const or_inst *in, int32_t *x, int op, uint32_t w1);
+
 int or_apply_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2, uint32_t w3) {
   int n = in->d.n;
+  /* the row form: the permutation operators act on the entries before the
+   * final marker (which stays last), the row operators on whole rows */
+  if (in->d.kind == K_VRPROWS) {
+    if (op >= OP_ROWSWAP) row_op(in, x, op, w1);
+    else perm_op(x, n - 1, op, w1, w2, w3);
+    return op;
+  }
   if (op == OP_FLIP) { x[rmap(w1, n)] ^= 1; return op; }
   if (op == OP_RESET) {
     uint32_t i = rmap(w1, n);
@@ -319,7 +383,13 @@ int or_apply_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2,
     }
     return op;
   }
-  if (n < 2) return op;                      /* every permutation move is the identity */
+  perm_op(x, n, op, w1, w2, w3);
+  return op;
+}
+
+/* The permutation operators on x[0 .. n-1]. */
+static void perm_op(int32_t *x, int n, int op, uint32_t w1, uint32_t w2, uint32_t w3) {
+  if (n < 2) return;                         /* every permutation move is the identity */
   /* Tab. operators, segment level, 3-opt.  reading: the segment exchange, the
    * 3-opt reconnection that keeps every segment's orientation: three distinct
    * cut positions a < b < c of {0..n} (drawn as a uniform triple: w1 over n+1
@@ -342,14 +412,14 @@ int or_apply_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2,
     for (uint32_t p = c; p < (uint32_t)n; ++p) tmp[o++] = x[p];
     memcpy(x, tmp, sizeof(int32_t) * n);
     free(tmp);
-    return op;
+    return;
   }
   if (op == OP_2OPT || op == OP_SWAP) {
     uint32_t i = rmap(w1, n), j = rmap(w2, n - 1);
     j += (j >= i);
     if (op == OP_SWAP) { int32_t t = x[i]; x[i] = x[j]; x[j] = t; }
     else reverse_range(x, i < j ? i : j, i < j ? j : i);   /* reverse = 2-opt */
-    return op;
+    return;
   }
   /* insert (segment length 1) and or-opt (length 2 or 3, orientation kept):
    * remove s[i..i+L-1] and put it back so that it starts at index q */
@@ -370,13 +440,67 @@ int or_apply_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2,
     if (p < n - L) x[o++] = tmp[p];
   }
   free(tmp);
-  return op;
+  return;
+}
+
+/* Tab. "operators", row level: row_swap, row_split and row_merge act on whole
+ * rows of a multi-row solution (rows one after another, each closed by its
+ * marker; the final entry is a marker).  reading: w1 draws a position p
+ * uniformly among the N - 1 entries before the final marker, which names the
+ * row that holds it (the row p's entry belongs to, its marker included):
+ *   row_swap:  that row and the next one trade places, each with its marker;
+ *              nothing when it is the last row;
+ *   row_split: when the last row is empty, its marker (entry N - 2) is taken
+ *              out and put back at index p, so that the row ends before p's
+ *              entry and p's entry opens a new row with the rest of the row;
+ *              nothing when the last row holds customers or p = N - 2;
+ *   row_merge: the row's marker is taken out and put back just before the
+ *              final marker, so that the next row's customers join the row
+ *              and the rows after it move up, leaving the last row empty;
+ *              nothing when the row is the last one or the next one is the
+ *              empty last row.
+ * The operators only look at the solution they are applied to (the candidate
+ * as the earlier steps left it). */
+static void move_entry(int32_t *x, int from, int to) {   /* take x[from] out, put it back at index `to` */
+  int32_t v = x[from];
+  if (from < to) memmove(x + from, x + from + 1, sizeof(int32_t) * (size_t)(to - from));
+  else memmove(x + to + 1, x + to, sizeof(int32_t) * (size_t)(from - to));
+  x[to] = v;
+}
+
+static void row_op(const or_inst *in, int32_t *x, int op, uint32_t w1) {
+  const int N = in->d.n, nc = in->nc;
+  const int p = (int)rmap(w1, (uint32_t)(N - 1));
+  int e1 = p;                                   /* the marker that closes p's row */
+  while (x[e1] < nc) ++e1;
+  if (op == OP_ROWSPLIT) {
+    if (N >= 2 && x[N - 2] >= nc && p < N - 2) move_entry(x, N - 2, p);
+    return;
+  }
+  if (op == OP_ROWMERGE) {
+    if (e1 < N - 2) move_entry(x, e1, N - 2);
+    return;
+  }
+  if (e1 == N - 1) return;                      /* row_swap of the last row */
+  int s = p;                                    /* the first entry of p's row */
+  while (s > 0 && x[s - 1] < nc) --s;
+  int e2 = e1 + 1;                              /* the marker that closes the next row */
+  while (x[e2] < nc) ++e2;
+  int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(e2 - s + 1));
+  int o = 0;
+  for (int i = e1 + 1; i <= e2; ++i) tmp[o++] = x[i];
+  for (int i = s; i <= e1; ++i) tmp[o++] = x[i];
+  memcpy(x + s, tmp, sizeof(int32_t) * (size_t)o);
+  free(tmp);
 }
 
 /* ------------------------------------------------------------ encodings */
 static uint32_t encoding_ops(int kind) {
   if (kind == K_KNAP) return (1u << OP_FLIP) | (1u << OP_SEGFLIP);
   if (kind == K_COLOR) return (1u << OP_RESET) | (1u << OP_SEGRESET);
+  if (kind == K_VRPROWS)
+    return (1u << OP_2OPT) | (1u << OP_SWAP) | (1u << OP_INSERT) | (1u << OP_OROPT) | (1u << OP_3OPT) |
+           (1u << OP_ROWSWAP) | (1u << OP_ROWSPLIT) | (1u << OP_ROWMERGE);
   return (1u << OP_2OPT) | (1u << OP_SWAP) | (1u << OP_INSERT) | (1u << OP_OROPT) | (1u << OP_3OPT);
 }
 
@@ -393,7 +517,9 @@ static int enabled_list(uint32_t mask, int *ids) {
 
 /* Sec. "Problem-Profile-Driven Prior Strategy", Tab. "weight_preset":
  * O(1) operators start at 1.0; or-opt at 0.8 / 0.7 / 0.3 and 3-opt at
- * 0.50 / 0.30 / 0.05 for n <= 100, <= 250, > 250 (Q16, rounded); a nonzero
+ * 0.50 / 0.30 / 0.05 for n <= 100, <= 250, > 250 (Q16, rounded; n is the
+ * solution's length, customers and markers in the row form); reading: the
+ * row operators, which the table does not list, start at 1.0; a nonzero
  * init_w[i] replaces the preset of operator i; then the weights are
  * normalised (Q16). */
 void or_initial_weights(const or_inst *in, uint32_t op_mask, const uint32_t *init_w, uint32_t w[OR_MAX_OPS]) {
@@ -659,6 +785,73 @@ static int sum_perms(const int32_t *M, int n, int stride, int32_t *out) {
   return 4;
 }
 
+/* Sec. "Partition Encoding Heuristic Initialization": customers grouped by
+ * place, each route ordered by time window.  reading: a sweep around the
+ * depot.  Customers in order of polar angle about the depot, counter-clockwise
+ * from the positive x axis (compared exactly: the half-plane dy > 0 or
+ * (dy = 0, dx >= 0) first, then the sign of the cross product; ties by
+ * squared distance to the depot, then index), fill the rows in turn: a row is
+ * closed when the next customer's demand would take its load above the
+ * capacity, and the last row takes every customer left.  Each row is then
+ * ordered by due time, ties by ready time, then index; rows left over stay
+ * empty.  Row r is closed by marker nc + r. */
+static int sweep_half(int64_t dx, int64_t dy) { return (dy < 0 || (dy == 0 && dx < 0)) ? 1 : 0; }
+static int sweep_cmp(const or_inst *in, int a, int b) {   /* nodes 1..nc */
+  const int32_t *xy = in->d.a;
+  int64_t ax = xy[2 * a] - xy[0], ay = xy[2 * a + 1] - xy[1];
+  int64_t bx = xy[2 * b] - xy[0], by = xy[2 * b + 1] - xy[1];
+  int ha = sweep_half(ax, ay), hb = sweep_half(bx, by);
+  if (ha != hb) return ha - hb;
+  int64_t cr = ax * by - ay * bx;
+  if (cr != 0) return cr > 0 ? -1 : 1;
+  int64_t da = ax * ax + ay * ay, db = bx * bx + by * by;
+  if (da != db) return da < db ? -1 : 1;
+  return a < b ? -1 : (a > b);
+}
+static int window_cmp(const or_inst *in, int a, int b) {
+  const int m = in->nc + 1;
+  const int32_t *ready = in->d.b + m, *due = in->d.b + 2 * m;
+  if (due[a] != due[b]) return due[a] < due[b] ? -1 : 1;
+  if (ready[a] != ready[b]) return ready[a] < ready[b] ? -1 : 1;
+  return a < b ? -1 : (a > b);
+}
+/* insertion sort of v[0..cnt-1] by cmp */
+static void sort_nodes(const or_inst *in, int32_t *v, int cnt, int (*cmp)(const or_inst *, int, int)) {
+  for (int i = 1; i < cnt; ++i) {
+    int32_t x = v[i];
+    int j = i;
+    while (j > 0 && cmp(in, v[j - 1], x) > 0) { v[j] = v[j - 1]; --j; }
+    v[j] = x;
+  }
+}
+
+static int sweep_rows(const or_inst *in, int32_t *out) {
+  const int nc = in->nc, R = in->d.vehicles;
+  int32_t *ord = (int32_t *)malloc(sizeof(int32_t) * nc), *row = (int32_t *)malloc(sizeof(int32_t) * (nc + 1));
+  for (int i = 0; i < nc; ++i) ord[i] = i + 1;
+  sort_nodes(in, ord, nc, sweep_cmp);
+  int r = 0;
+  int64_t load = 0;
+  for (int i = 0; i < nc; ++i) {
+    int c = ord[i];
+    if (load + in->d.b[c] > in->d.capacity && r < R - 1) { ++r; load = 0; }
+    row[c] = r;
+    load += in->d.b[c];
+  }
+  int o = 0;
+  for (int rr = 0; rr < R; ++rr) {
+    int cnt = 0;
+    for (int i = 0; i < nc; ++i) if (row[ord[i]] == rr) out[o + cnt++] = ord[i];
+    sort_nodes(in, out + o, cnt, window_cmp);
+    for (int i = 0; i < cnt; ++i) out[o + i] -= 1;   /* node c is entry c - 1 */
+    o += cnt;
+    out[o++] = nc + rr;
+  }
+  free(ord);
+  free(row);
+  return 1;
+}
+
 int or_heuristic_perms(const or_inst *in, int32_t *out, int cap) {
   int n = in->d.n, c = 0;
   if (in->d.kind == K_TSP) {
@@ -671,6 +864,8 @@ int or_heuristic_perms(const or_inst *in, int32_t *out, int cap) {
   } else if (in->d.kind == K_VRPTW) {
     /* the customer block of the travel-time matrix */
     if (cap >= 4) c += sum_perms(in->dist + in->dn + 1, n, in->dn, out);
+  } else if (in->d.kind == K_VRPROWS) {
+    if (cap >= 1) c += sweep_rows(in, out);
   }
   return c;
 }
@@ -678,7 +873,7 @@ int or_heuristic_perms(const or_inst *in, int32_t *out, int cap) {
 /* A random member of the pool at index q: draw i is word (i mod 4) of the
  * block with counter (0xFFFFFFFF, q, i / 4, instance key).  Permutations by
  * Fisher-Yates from the identity (i = n-1 .. 1 swaps x[i] with x[j], j uniform
- * in [0, i]); bits from the top bit of the draw; integers uniform in [lb, ub]. */
+ * in [0, i]; in the row form over the first n-1 entries, i = n-2 .. 1); bits from the top bit of the draw; integers uniform in [lb, ub]. */
 void or_random_solution(const or_inst *in, const or_params *p, uint32_t q, int32_t *x) {
   int n = in->d.n;
   uint32_t key = in->d.key, r[4];
@@ -690,8 +885,10 @@ void or_random_solution(const or_inst *in, const or_params *p, uint32_t q, int32
                                   : in->d.lb + (int32_t)rmap(w, (uint32_t)(in->d.ub - in->d.lb + 1));
     }
   } else {
+    /* the row form shuffles the entries before the final marker, which stays last */
+    const int m = in->d.kind == K_VRPROWS ? n - 1 : n;
     for (int i = 0; i < n; ++i) x[i] = i;
-    for (int i = n - 1; i >= 1; --i) {
+    for (int i = m - 1; i >= 1; --i) {
       draw(p, 0xFFFFFFFFu, q, (uint32_t)(i >> 2), key, r);
       uint32_t j = rmap(r[i & 3], (uint32_t)(i + 1));
       int32_t t = x[i]; x[i] = x[j]; x[j] = t;

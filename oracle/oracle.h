@@ -13,10 +13,16 @@
 #include <stdint.h>
 
 /* Operator ids (Tab. "operators"): permutation 0 2-opt, 1 swap, 2 insert,
- * 3 or-opt, 4 3-opt (ids 5-7 are kept for the LNS operators, which are not
- * built); binary 8 flip, 9 seg_flip; integer 10 random_reset, 11 seg_reset. */
+ * 3 or-opt, 4 3-opt; row level (multi-row solutions) 5 row_swap, 6 row_split,
+ * 7 row_merge; binary 8 flip, 9 seg_flip; integer 10 random_reset,
+ * 11 seg_reset. */
 #define OR_MAX_OPS 12
 
+/* kind 1 TSP, 2 QAP, 3 knapsack, 4 VRPTW as a giant tour split by capacity,
+ * 5 colouring, 6 VRPTW in the multi-row form (Sec. "Solution Structure"): n
+ * customers and `vehicles` rows; a solution holds n + vehicles entries, the
+ * customers (entry c is node c + 1) and one marker per row (entries n ..
+ * n + vehicles - 1), each row's customers followed by its marker. */
 typedef struct {
   int32_t kind, n;
   const int32_t *a, *b;

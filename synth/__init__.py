@@ -6,7 +6,8 @@ distance rule, no move, no acceptance test); each side computes those itself.
 
 Problem kinds follow the paper's three encodings (Sec. "Encoding Types"):
 permutation (TSP, QAP, VRPTW giant tour), binary (0/1 knapsack) and bounded
-integer (graph colouring).  The benchmark datasets the paper evaluates on
+integer (graph colouring); VRPTW also in the multi-row form (Sec. "Solution
+Structure": one route per row).  The benchmark datasets the paper evaluates on
 (TSPLIB, QAPLIB, Solomon, Pisinger) are not available; the generators below
 stand in for them with the shapes, sizes and value ranges of the workloads
 this project measures.
@@ -20,21 +21,26 @@ from fractions import Fraction
 import numpy as np
 
 # ---- problem kinds and operator ids (shared vocabulary, no arithmetic) ----
-TSP, QAP, KNAPSACK, VRPTW, INTCOLOR = 1, 2, 3, 4, 5
-KIND_NAMES = {TSP: "tsp", QAP: "qap", KNAPSACK: "knapsack", VRPTW: "vrptw", INTCOLOR: "intcolor"}
+TSP, QAP, KNAPSACK, VRPTW, INTCOLOR, VRPTW_ROWS = 1, 2, 3, 4, 5, 6
+KIND_NAMES = {TSP: "tsp", QAP: "qap", KNAPSACK: "knapsack", VRPTW: "vrptw", INTCOLOR: "intcolor",
+              VRPTW_ROWS: "vrptw_rows"}
 
-# permutation 0-4 (ids 5-7 are kept for the LNS operators, not built),
-# binary 8-9, integer 10-11
+# permutation 0-4, row level 5-7 (multi-row solutions), binary 8-9, integer 10-11
 OP_2OPT, OP_SWAP, OP_INSERT, OP_OROPT, OP_3OPT = 0, 1, 2, 3, 4
+OP_ROWSWAP, OP_ROWSPLIT, OP_ROWMERGE = 5, 6, 7
 OP_FLIP, OP_SEGFLIP, OP_RESET, OP_SEGRESET = 8, 9, 10, 11
-OP_NAMES = ["2opt", "swap", "insert", "oropt", "3opt", "lns5", "lns6", "lns7", "flip", "segflip", "reset", "segreset"]
+OP_NAMES = ["2opt", "swap", "insert", "oropt", "3opt", "rowswap", "rowsplit", "rowmerge", "flip", "segflip",
+            "reset", "segreset"]
 N_OPS = 12
 PERM4_OPS = (1 << OP_2OPT) | (1 << OP_SWAP) | (1 << OP_INSERT) | (1 << OP_OROPT)
 PERM_OPS = PERM4_OPS | (1 << OP_3OPT)
+ROW_OPS = (1 << OP_ROWSWAP) | (1 << OP_ROWSPLIT) | (1 << OP_ROWMERGE)
+ROWS_ALL_OPS = PERM_OPS | ROW_OPS
 BIN_OPS = (1 << OP_FLIP) | (1 << OP_SEGFLIP)
 INT_OPS = (1 << OP_RESET) | (1 << OP_SEGRESET)
 
-ENCODING_OF = {TSP: "perm", QAP: "perm", VRPTW: "perm", KNAPSACK: "binary", INTCOLOR: "integer"}
+ENCODING_OF = {TSP: "perm", QAP: "perm", VRPTW: "perm", KNAPSACK: "binary", INTCOLOR: "integer",
+               VRPTW_ROWS: "perm_rows"}
 
 
 @dataclass
@@ -47,6 +53,8 @@ class Instance:
     VRPTW    n = customers; a = coords (n+1,2) with the depot at row 0;
              b = (3, n+1): demand, ready time, due time; capacity, vehicles,
              service_time, horizon
+    VRPTW_ROWS  the VRPTW data, solved in the multi-row form with `vehicles`
+             rows (a solution holds n + vehicles entries)
     INTCOLOR a = edge list (n_edges, 2); values in [lb, ub]
     """
     kind: int
@@ -202,6 +210,16 @@ def vrptw_random(n: int = 100, inst_id: int = 0, key: int | None = None,
                     key=inst_id if key is None else key)
 
 
+def vrptw_rows(n: int = 100, inst_id: int = 0, key: int | None = None, vehicles: int = 25, **kw) -> Instance:
+    """The VRPTW data of `vrptw_random`, for the multi-row form with `vehicles` rows."""
+    return replace(vrptw_random(n, inst_id, key, vehicles=vehicles, **kw), kind=VRPTW_ROWS)
+
+
+def solution_len(inst: Instance) -> int:
+    """Entries of one solution of `inst` (customers plus one marker per row in the multi-row form)."""
+    return inst.n + (inst.vehicles if inst.kind == VRPTW_ROWS else 0)
+
+
 def color_planted(n: int, k: int = 3, m: int | None = None, inst_id: int = 0,
                   key: int | None = None) -> Instance:
     """Integer-encoding test problem: a random k-partite graph (so a proper
@@ -298,4 +316,12 @@ def c3_vrptw(seed: int = 42, generations: int = 5000, population: int = 64) -> t
     inst = vrptw_random(100, 0)
     p = Params(seed=seed, generations=generations, population=population, candidates=128,
                op_mask=PERM_OPS, alpha_q32=alpha_q32_for(generations))
+    return inst, p
+
+
+def c3_vrptw_rows(seed: int = 42, generations: int = 5000, population: int = 64) -> tuple[Instance, Params]:
+    """The C3 customers in the multi-row form (25 rows), every operator of the form."""
+    inst = vrptw_rows(100, 0)
+    p = Params(seed=seed, generations=generations, population=population, candidates=128,
+               op_mask=ROWS_ALL_OPS, alpha_q32=alpha_q32_for(generations))
     return inst, p
