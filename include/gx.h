@@ -53,14 +53,15 @@ typedef enum {
   GX_QAP = 2,       /* permutation; quadratic assignment, p[i] = location of facility i */
   GX_KNAPSACK = 3,  /* binary; 0/1 knapsack, penalised overweight */
   GX_VRPTW = 4,     /* permutation of customers (giant tour) split into routes */
-  GX_INTCOLOR = 5   /* integer in [lb, ub]; graph colouring (monochromatic edges) */
+  GX_INTCOLOR = 5,  /* integer in [lb, ub]; graph colouring (monochromatic edges) */
+  GX_VRPTW_ROWS = 6 /* multi-row permutation: one route per row (Sec. "Solution Structure") */
 } gx_problem;
 
 /* Operators (paper, Tab. "operators"); bit i of op_mask enables operator id
  * i, and AOS keeps one weight per id.  Ids are contiguous per encoding:
- * permutation 0-4 (5-7 are kept for the LNS operators of Sec. "Built-in
- * Operator Hierarchy", which this library does not build), binary 8-9,
- * integer 10-11. */
+ * permutation 0-4, the multi-row permutation 0-7 (the permutation operators
+ * and the row level), binary 8-9, integer 10-11.  (The LNS operators of Sec.
+ * "Built-in Operator Hierarchy" are not built.) */
 #define GX_N_OPS 12
 enum {
   GX_OP_2OPT = 1u << 0,    /* element level: segment reversal */
@@ -68,6 +69,14 @@ enum {
   GX_OP_INSERT = 1u << 2,  /* element level: move one element */
   GX_OP_OROPT = 1u << 3,   /* segment level: move a block of 2 or 3 elements, orientation kept */
   GX_OP_3OPT = 1u << 4,    /* segment level: three cuts a < b < c, blocks [a, b) and [b, c) exchanged */
+  /* row level (GX_VRPTW_ROWS); p is drawn uniformly among the entries before
+   * the final marker and names the row holding it (its marker included) */
+  GX_OP_ROWSWAP = 1u << 5,  /* that row and the next trade places (nothing for the last row) */
+  GX_OP_ROWSPLIT = 1u << 6, /* when the last row is empty, its marker moves to p: the row ends
+                               before p's entry and the rest opens a row (else nothing) */
+  GX_OP_ROWMERGE = 1u << 7, /* the row's marker moves before the final one: the next row's
+                               customers join it and the last row is left empty (nothing when
+                               the next row is the empty last row, or there is none) */
   GX_OP_FLIP = 1u << 8,    /* binary, element level: flip one bit */
   GX_OP_SEGFLIP = 1u << 9, /* binary, segment level: flip L = 2..7 consecutive bits */
   GX_OP_RESET = 1u << 10,  /* integer, element level: draw a new value in [lb, ub] */
@@ -131,21 +140,40 @@ gx_status gx_get_device_info(gx_ctx *ctx, gx_device_info *out);
  *            Lexicographic mode (paper, Sec. "Multi-Objective Optimization
  *            Modes"; Tab. lexicographic_mode) when lex_order[0] != 0: a
  *            solution's objective is the vector (penalty, level 1, level 2,
- *            level 3), penalty = 100 * lateness + 10000 * fleet excess, level
+ *            level 3), penalty = 100 * lateness + 10000 * fleet excess (+ 100 *
+ *            load above capacity in the multi-row form), level
  *            i the objective lex_order[i] (1 distance, 2 routes, 3 longest
  *            route; a 0 ends the list; no repeats).  b is better than a when
  *            its penalty is lower, or the penalties are equal and at the
  *            first level where the two differ by more than lex_tol[i]
  *            (in [0, 2^30]) b's value is the lower one; otherwise neither is
  *            better.  Within a set (the candidates of a generation, the
- *            population) the best is found by a scan in index order that
- *            keeps the first element no later one is better than.  The
+ *            population) the best is found by a scan in index order in
+ *            which a later element replaces the one kept when better.  The
  *            scalar reported for a solution (cur_f, best_f, the best
  *            objective) is its penalty plus its level-1 value; island
  *            migration and elite injection pick best and worst solutions by
  *            the same relation.  obj_weights must be zero in this mode;
  *            solves on such an instance take aos_scope 0 and cannot be
  *            restored (gx_job_restore).
+ *   VRPTW_ROWS  the VRPTW data and modes (above) in the multi-row form of
+ *            Sec. "Solution Structure" (Tab. generality runs CVRP and VRPTW
+ *            so): `vehicles` rows (>= 1, <= 250), one route each.  A
+ *            solution holds n + vehicles entries: entry e < n is customer
+ *            e + 1, entries n .. n + vehicles - 1 are row markers; the rows
+ *            come one after another, each followed by its marker, and the
+ *            final entry is a marker (the paper's rows of per-row length,
+ *            stored back to back).  A row is a route from the depot through
+ *            its customers in order and back; an empty row is no route.  f as
+ *            for VRPTW with routes = non-empty rows (the fleet term is then
+ *            0) plus 100 * (load above capacity, summed over rows).
+ *            capacity <= 2^22.  Operators: the permutation ones act on the
+ *            entries before the final marker, the row ones on whole rows.
+ *            Initial pool slot 0 is the sweep solution of Sec. "Partition
+ *            Encoding Heuristic Initialization" (customers by polar angle
+ *            about the depot fill the rows in turn up to the capacity, each
+ *            row then ordered by due time, ready time, index); the others
+ *            shuffle the entries before the final marker.
  *   INTCOLOR a = edge list n_edges x 2 (no self loops); values in [lb, ub];
  *            f = number of edges whose ends share a value.
  * instance_key enters every random counter of solves on this instance: keep

@@ -125,10 +125,12 @@ gx_status to_host(gx_ctx *c, const gx_instance_desc *d, const int32_t *src, size
   return GX_OK;
 }
 
-uint32_t encoding_ops(int kind) {
-  if (kind == KKNAP) return (1u << OFLIP) | (1u << OSFLIP);
-  if (kind == KCOLOR) return (1u << ORESET) | (1u << OSRESET);
-  return (1u << O2OPT) | (1u << OSWAP) | (1u << OINS) | (1u << OOROPT) | (1u << O3OPT);
+uint32_t encoding_ops(const DevInst &h) {
+  if (h.kind == KKNAP) return (1u << OFLIP) | (1u << OSFLIP);
+  if (h.kind == KCOLOR) return (1u << ORESET) | (1u << OSRESET);
+  const uint32_t perm = (1u << O2OPT) | (1u << OSWAP) | (1u << OINS) | (1u << OOROPT) | (1u << O3OPT);
+  if (h.rows) return perm | (1u << OROWSWAP) | (1u << OROWSPLIT) | (1u << OROWMERGE);
+  return perm;
 }
 
 void free_bufs(std::vector<void *> &b) {
@@ -177,7 +179,9 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
   const int n = d->n;
   if (n < 1) return fail(c, GX_E_INVALID, "n must be >= 1 (got %d)", n);
   DevInst &h = pr.h;
-  h.kind = d->kind;
+  // the multi-row VRPTW runs the VRPTW kernels with its rows (and markers) in the solution
+  const bool rows = d->kind == GX_VRPTW_ROWS;
+  h.kind = rows ? KVRP : d->kind;
   h.n = n;
   h.lb = d->lb;
   h.ub = d->ub;
@@ -187,9 +191,9 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
   h.horizon = d->horizon;
   h.n_edges = d->n_edges;
   pr.key = d->instance_key;
-  if (d->kind != KVRP && (d->obj_weights[0] | d->obj_weights[1] | d->obj_weights[2]))
+  if (h.kind != KVRP && (d->obj_weights[0] | d->obj_weights[1] | d->obj_weights[2]))
     return fail(c, GX_E_INVALID, "objective weights apply to VRPTW only");
-  if (d->kind != KVRP && (d->lex_order[0] | d->lex_order[1] | d->lex_order[2]))
+  if (h.kind != KVRP && (d->lex_order[0] | d->lex_order[1] | d->lex_order[2]))
     return fail(c, GX_E_INVALID, "the lexicographic mode applies to VRPTW only");
   std::vector<int32_t> A, B;
   gx_status st = GX_OK;
@@ -253,8 +257,11 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
     add_arr(pr, F_KW, A);
     add_arr(pr, F_KV, B);
     fbound = 4.0 * ((double)sv + (double)h.lambda * (double)sw);
-  } else if (d->kind == KVRP) {
+  } else if (h.kind == KVRP) {
     if (n > kMaxVrpN) return fail(c, GX_E_UNSUPPORTED, "VRPTW n <= %d", kMaxVrpN);
+    if (rows && (d->vehicles < 1 || d->vehicles > kMaxVrpN))
+      return fail(c, GX_E_UNSUPPORTED, "multi-row VRPTW takes 1 to %d rows (vehicles)", kMaxVrpN);
+    if (rows && d->capacity > (1 << 22)) return fail(c, GX_E_UNSUPPORTED, "multi-row VRPTW capacity <= 2^22");
     const int m = n + 1;
     if ((st = to_host(c, d, d->a, (size_t)2 * m, A)) || (st = to_host(c, d, d->b, (size_t)3 * m, B))) return st;
     for (int32_t v : A)
@@ -300,6 +307,11 @@ gx_status prepare_instance(gx_ctx *c, const gx_instance_desc *d, Prepared &pr, b
     add_arr(pr, F_DUE, std::vector<int32_t>(B.begin() + 2 * m, B.end()));
     fbound = 4.0 * ((h.vw_d + h.vw_m) * m * 23171.0 + (double)h.vw_r * m +
                     100.0 * m * (m * 23171.0 + (1 << 19) + (double)m * (1 << 16)) + 10000.0 * m);
+    if (rows) {   // the solution's entries: customers and one marker per row; loads above capacity
+      h.rows = d->vehicles;
+      h.n = n + d->vehicles;
+      fbound += 4.0 * 100.0 * m * (double)d->capacity;
+    }
   } else if (d->kind == KCOLOR) {
     if (n > 32767) return fail(c, GX_E_UNSUPPORTED, "colouring n <= 32767");
     if (d->lb > d->ub || d->lb < -32768 || d->ub > 32767)
@@ -578,7 +590,8 @@ uint32_t resolve_stage(const InstInfo &ii, uint32_t req) {
 }
 
 uint32_t job_lds(const InstInfo &ii, uint32_t stage, uint32_t op_mask) {
-  uint32_t b = lds_bytes_for(ii.h.kind, ii.h.n, evolve_variant(ii.h.kind, stage, op_mask, ii.h.lex_levels));
+  uint32_t b = lds_bytes_for(ii.h.kind, ii.h.n, evolve_variant(ii.h.kind, stage, op_mask, ii.h.lex_levels, ii.h.rows),
+                             ii.h.rows);
   if (ii.h.kind == KCOLOR) b += (uint32_t)pad16((size_t)8 * ii.h.n_edges);
   return std::max<uint32_t>(b, 16);
 }
@@ -587,7 +600,7 @@ uint32_t job_lds(const InstInfo &ii, uint32_t stage, uint32_t op_mask) {
 gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJob &h, uint32_t P_auto,
                    uint32_t lds_limit) {
   if (!p) return fail(c, GX_E_INVALID, "null parameters");
-  const uint32_t mask = p->op_mask ? (p->op_mask & encoding_ops(ii.h.kind)) : encoding_ops(ii.h.kind);
+  const uint32_t mask = p->op_mask ? (p->op_mask & encoding_ops(ii.h)) : encoding_ops(ii.h);
   if (!mask) return fail(c, GX_E_INVALID, "op_mask enables no operator of this encoding");
   if (p->alpha_q32 == 0) return fail(c, GX_E_INVALID, "alpha_q32 is required");
   const uint32_t C = p->candidates ? p->candidates : 128;
@@ -652,6 +665,7 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
   h.aos_scope = p->aos_scope;
   for (int i = 0; i < kOps; ++i) h.init_w[i] = p->init_weight_q16[i];
   h.lex_levels = (uint32_t)ii.h.lex_levels;
+  h.rows = (uint32_t)ii.h.rows;
   return GX_OK;
 }
 
@@ -859,10 +873,10 @@ gx_status gx_autosize_population(gx_ctx *c, const gx_instance *in, const gx_solv
   if (!c || !in || !out) return fail(c, GX_E_INVALID, "null argument");
   const InstInfo ii = info_of(in);
   const uint32_t stage = resolve_stage(ii, p ? p->staging : 0);
-  const uint32_t mask = p && p->op_mask ? (p->op_mask & encoding_ops(in->h.kind)) : encoding_ops(in->h.kind);
+  const uint32_t mask = p && p->op_mask ? (p->op_mask & encoding_ops(in->h)) : encoding_ops(in->h);
   const uint32_t lds = job_lds(ii, stage, mask);
   int occ = 0;
-  HIPCHK(c, gxk::occupancy_plain(in->h.kind, evolve_variant(in->h.kind, stage, mask, in->h.lex_levels), lds, &occ));
+  HIPCHK(c, gxk::occupancy_plain(in->h.kind, evolve_variant(in->h.kind, stage, mask, in->h.lex_levels, in->h.rows), lds, &occ));
   // every CU filled to the residency the kernel's registers and LDS allow
   occ = std::max(1, std::min(occ, 32));
   *out = (uint32_t)(c->info.cus * occ);
@@ -925,7 +939,7 @@ gx_status gx_job_advance(gx_ctx *c, gx_job *j, uint32_t ng) {
   HIPCHK(c, gxk::set_stop(j->d, 1, ng, 0, c->stream));
   HIPCHK(c, hipEventRecord(j->ev0, c->stream));
   DevJob *dj = j->d;
-  const int kind = j->inst->h.kind, stage = evolve_variant(kind, j->h.stage, j->h.op_mask, j->h.lex_levels);
+  const int kind = j->inst->h.kind, stage = evolve_variant(kind, j->h.stage, j->h.op_mask, j->h.lex_levels, j->h.rows);
   const uint32_t P = j->h.P, lds = j->h.lds_bytes;
   const bool mig = migrates(j->h);
   hipStream_t s = c->stream;
@@ -978,7 +992,7 @@ gx_status gx_solve_static(gx_ctx *c, const gx_instance *in, const gx_solve_param
   h.best_out = best_solution;
   hipStream_t s = c->stream;
   const bool mig = migrates(h);
-  const int kind = in->h.kind, stage = evolve_variant(kind, h.stage, h.op_mask, h.lex_levels);
+  const int kind = in->h.kind, stage = evolve_variant(kind, h.stage, h.op_mask, h.lex_levels, h.rows);
   HIPCHK(c, gxk::write_job(dj, h, s));
   HIPCHK(c, gxk::init_jobs(dj, 1, h.Q, (int)n, heur_mats_of(kind), s));
   HIPCHK(c, gxk::set_stop(dj, 1, 0, 1, s));
@@ -1188,7 +1202,8 @@ static bool valid_solution(const DevInst &ih, const int32_t *x, std::vector<char
     if (x[i] < 0 || x[i] >= n || seen[x[i]]) return false;
     seen[x[i]] = 1;
   }
-  return true;
+  // the multi-row form ends with a row marker
+  return !ih.rows || x[n - 1] >= ih.dn - 1;
 }
 
 gx_status gx_job_restore(gx_ctx *c, gx_job *j, const gx_state_scalars *sc, const int32_t *cur, const int64_t *cur_f,
@@ -1325,7 +1340,7 @@ gx_status gx_solve_batch(gx_ctx *c, const gx_instance *const *insts, const gx_so
     else if (ih.kind == KVRP) cost = 8.0 * n;
     cost *= (double)hj[i].C * (double)hj[i].G;
     for (uint32_t s2 = 0; s2 < hj[i].P; ++s2)
-      recs.push_back(ItemRec{ih.kind, evolve_variant(ih.kind, hj[i].stage, hj[i].op_mask, hj[i].lex_levels), hj[i].lds_bytes, cost,
+      recs.push_back(ItemRec{ih.kind, evolve_variant(ih.kind, hj[i].stage, hj[i].op_mask, hj[i].lex_levels, hj[i].rows), hj[i].lds_bytes, cost,
                              make_uint2((uint32_t)i, s2)});
   }
   std::vector<uint2> items(n_items);
@@ -1702,7 +1717,7 @@ void server_loop(gx_server *S) {
       recs.clear();
       for (SrvReq *r : act)
         for (uint32_t sl = 0; sl < r->hj.P; ++sl)
-          recs.push_back(ItemRec{r->kind, evolve_variant(r->kind, r->hj.stage, r->hj.op_mask, r->hj.lex_levels), r->hj.lds_bytes, r->cost,
+          recs.push_back(ItemRec{r->kind, evolve_variant(r->kind, r->hj.stage, r->hj.op_mask, r->hj.lex_levels, r->hj.rows), r->hj.lds_bytes, r->cost,
                                  make_uint2((uint32_t)r->slot, sl)});
       if (make_groups(&S->gctx, recs, L.items_h[b], groups) != GX_OK || groups.size() != 1) continue;
       for (size_t a = 0; a < act.size(); ++a) L.slots_h[b][a] = (uint32_t)act[a]->slot;
@@ -1882,7 +1897,7 @@ gx_status gx_server_submit(gx_server *S, const gx_instance_desc *d, const gx_sol
   const double n = r->n;
   r->cost = (r->pr.h.kind == KQAP ? 4.0 * n * n / 3.0 : (r->pr.h.kind == KVRP ? 8.0 * n : n)) * r->hj.C;
   r->kind = r->pr.h.kind;
-  r->lane = lane_of(r->kind, evolve_variant(r->kind, r->hj.stage, r->hj.op_mask, r->hj.lex_levels), r->hj.lds_bytes);
+  r->lane = lane_of(r->kind, evolve_variant(r->kind, r->hj.stage, r->hj.op_mask, r->hj.lex_levels, r->hj.rows), r->hj.lds_bytes);
   r->ticket = S->next_ticket++;
   r->t_submit = now_ns();
   S->reqs[r->ticket] = r;

@@ -21,21 +21,22 @@ constexpr int kMaxCoord = 1 << 14;
 constexpr int64_t kDeltaBias = int64_t(1) << 47;   // argmin key = ((delta + bias) << 16) | t
 
 enum Kind : int32_t { KTSP = 1, KQAP = 2, KKNAP = 3, KVRP = 4, KCOLOR = 5 };
-// operator ids, contiguous per encoding: permutation 0-4 (5-7 are kept for
-// the LNS operators, which are not built), binary 8-9, integer 10-11
-enum Op : int32_t { O2OPT = 0, OSWAP = 1, OINS = 2, OOROPT = 3, O3OPT = 4, OFLIP = 8, OSFLIP = 9, ORESET = 10,
-                    OSRESET = 11 };
+// operator ids, contiguous per encoding: permutation 0-4, the row operators
+// of multi-row solutions 5-7, binary 8-9, integer 10-11
+enum Op : int32_t { O2OPT = 0, OSWAP = 1, OINS = 2, OOROPT = 3, O3OPT = 4, OROWSWAP = 5, OROWSPLIT = 6,
+                    OROWMERGE = 7, OFLIP = 8, OSFLIP = 9, ORESET = 10, OSRESET = 11 };
 constexpr int kPermOps = 5;
 enum Stage : int32_t { SAUTO = 0, SLDS16 = 1, SLDSXY = 2, SGLB16 = 3, SGLB32 = 4 };
 // Evolve-kernel variant: the staging, plus kVarX3 when a permutation job's
 // operator set holds 3-opt (its loops are compiled apart from the others, so
 // that jobs without it carry none of its branches or wider counters), plus
-// kVarLex for a VRPTW instance in the lexicographic mode.
-constexpr int kVarX3 = 8, kVarLex = 16;
-inline int evolve_variant(int kind, uint32_t stage, uint32_t op_mask, uint32_t lex_levels) {
+// kVarLex for a VRPTW instance in the lexicographic mode, plus kVarRows for a
+// VRPTW instance in the multi-row form.
+constexpr int kVarX3 = 8, kVarLex = 16, kVarRows = 32;
+inline int evolve_variant(int kind, uint32_t stage, uint32_t op_mask, uint32_t lex_levels, uint32_t rows) {
   const bool perm = kind == KTSP || kind == KQAP || kind == KVRP;
   return (int)stage | ((perm && (op_mask & (1u << O3OPT))) ? kVarX3 : 0) |
-         ((kind == KVRP && lex_levels) ? kVarLex : 0);
+         ((kind == KVRP && lex_levels) ? kVarLex : 0) | ((kind == KVRP && rows) ? kVarRows : 0);
 }
 
 // One uploaded instance.  All pointers are device pointers owned by the instance.
@@ -45,7 +46,11 @@ struct DevInst {
   int32_t lb, ub, has_xy;
   int32_t qap_sums32;         // QAP: 2 n * max F * max D < 2^31 (delta row and pair sums fit int32)
   int32_t qap_h16, pad_q;     // QAP: n * max F * max D < 2^16 (row sums H fit 16 bits: staging 1)
-  int32_t vw_d, vw_r, vw_m, pad_v;   // VRPTW objective weights: distance, routes, longest route
+  int32_t vw_d, vw_r, vw_m;   // VRPTW objective weights: distance, routes, longest route
+  // VRPTW in the multi-row form: the number of rows (0: a giant tour split by
+  // capacity).  A solution then holds n = customers + rows entries: entry
+  // e < dn - 1 is customer node e + 1, the others are row markers.
+  int32_t rows;
   // VRPTW lexicographic mode: number of levels (0: the weighted mode), each
   // level's objective (1 distance, 2 routes, 3 longest route) and tolerance
   int32_t lex_levels, lex_id[3], lex_tol[3], pad_l;
@@ -83,7 +88,8 @@ struct DevJob {
   uint32_t stage, lds_bytes, islands, mig_epochs;   // island model: see gx_solve_params
   uint32_t mig_mode, mig_n, elite_epochs, aos_scope;   // aos_scope: 0 instance, 1 per solution
   uint32_t init_w[kOps];      // caller's raw initial weights (0: Tab. weight_preset)
-  uint32_t lex_levels, pad_lex;   // levels of the lexicographic mode (0: scalar objective)
+  uint32_t lex_levels;        // levels of the lexicographic mode (0: scalar objective)
+  uint32_t rows;              // rows of a multi-row VRPTW solution (0: other kinds)
   // ---- mutable state
   uint32_t g, g_stop, stag, done;
   uint64_t T;
@@ -117,9 +123,10 @@ constexpr int kOneBufferN = 1536;
 
 // LDS bytes one evolve workgroup needs for this instance and kernel variant:
 // the candidate tables (3968 bytes, or 4736 with the block lengths of 3-opt
-// steps) followed by the solution and instance data.
+// steps) followed by the solution and instance data (rows: the rows of a
+// multi-row VRPTW solution, whose n entries include one marker per row).
 constexpr uint32_t kTables = 3968, kTablesX3 = 4736;
-inline uint32_t lds_bytes_for(int kind, int n, int var) {
+inline uint32_t lds_bytes_for(int kind, int n, int var, int rows) {
   auto al = [](uint32_t b) { return (b + 15u) & ~15u; };
   const int stage = var & 7;
   const uint32_t un = (uint32_t)n, tables = (var & kVarX3) ? kTablesX3 : kTables;
@@ -138,8 +145,11 @@ inline uint32_t lds_bytes_for(int kind, int n, int var) {
              2 * (16 * kWave + al(lst) + al(2 * lst));
     }
     case KKNAP: return tables + al(un) + 2 * al(4 * un);
-    case KVRP:   // + chunk minima, + the chunk's candidate vectors in the lexicographic mode
-      return tables + tours + al(2 * (un + 1) * (un + 1)) + 16 * (un + 1) + 16 + ((var & kVarLex) ? 128u * 32u : 0u);
+    case KVRP: {   // distances and node records over the depot and the customers, chunk minima, and
+                   // the chunk's candidate vectors in the lexicographic mode
+      const uint32_t dn = un - (uint32_t)rows + 1u;
+      return tables + tours + al(2 * dn * dn) + 16 * dn + 16 + ((var & kVarLex) ? 128u * 32u : 0u);
+    }
     default: return tables + al(2 * un) + al(4 * (un + 1));   // + adjacency, added by the caller
   }
 }

@@ -101,7 +101,7 @@ __device__ __forceinline__ uint64_t uni64(uint64_t v) {
 struct Uni {
   uint32_t n, C, key, k0, k1, credit, alpha;
   int32_t lb, ub;
-  uint32_t cw[4], sw;
+  uint32_t cw[7], sw;
   uint32_t ck[2], swk;
 };
 
@@ -111,16 +111,18 @@ struct Step {
 
 // weighted choice from Q16 weights: u = floor(u16 * S / 2^16); smallest i with
 // u < cumsum_i.  An encoding's operators are contiguous ids (permutations 0-4,
-// binary 8-9, integer 10-11) and the others have weight 0, so only the
-// encoding's own cumulative sums matter.
+// multi-row permutations 0-7, binary 8-9, integer 10-11) and the others have
+// weight 0, so only the encoding's own cumulative sums matter.
 template <int ENC>
 __device__ __forceinline__ int pick_op(uint32_t u16, const Uni &U) {
   const uint32_t u = (uint32_t)(((uint64_t)u16 * U.sw) >> 16);
-  if (ENC != 0) {
+  if (ENC == 1 || ENC == 2) {
     constexpr int lo = ENC == 1 ? OFLIP : ORESET;
     return lo + (U.cw[0] <= u);
   }
-  return (U.cw[0] <= u) + (U.cw[1] <= u) + (U.cw[2] <= u) + (U.cw[3] <= u);
+  int op = (U.cw[0] <= u) + (U.cw[1] <= u) + (U.cw[2] <= u) + (U.cw[3] <= u);
+  if (ENC == 3) op += (U.cw[4] <= u) + (U.cw[5] <= u) + (U.cw[6] <= u);
+  return op;
 }
 
 // k in {1, 2, 3} from the high 16 bits of a draw
@@ -129,22 +131,29 @@ __device__ __forceinline__ int pick_k(uint32_t w0, const Uni &U) {
   return 1 + (U.ck[0] <= u) + (U.ck[1] <= u);
 }
 
+// Encodings: 0 permutation, 1 binary, 2 integer, 3 multi-row permutation
+// (the permutation operators on the entries before the final row marker, and
+// the row operators).
 // first operator id of an encoding
 template <int ENC>
-constexpr int enc_lo() { return ENC == 0 ? 0 : (ENC == 1 ? OFLIP : ORESET); }
+constexpr int enc_lo() { return (ENC == 0 || ENC == 3) ? 0 : (ENC == 1 ? OFLIP : ORESET); }
 // last operator id of an encoding
 template <int ENC>
-constexpr int enc_hi() { return ENC == 0 ? O3OPT : enc_lo<ENC>() + 1; }
+constexpr int enc_hi() { return ENC == 0 ? O3OPT : (ENC == 3 ? OROWMERGE : enc_lo<ENC>() + 1); }
+template <int ENC>
+constexpr bool enc_perm() { return ENC == 0 || ENC == 3; }
 
-// ENC: 0 permutation, 1 binary, 2 integer; X3: the operator set holds 3-opt
-// (the loops without it are compiled without its branches)
+// X3: the operator set holds 3-opt (the loops without it are compiled
+// without its branches).  A row operator's step keeps only its drawn position
+// (a, uniform over the entries before the final marker): what it moves
+// depends on the rows of the candidate it is applied to and is resolved there.
 template <int ENC, bool X3>
 __device__ __forceinline__ Step make_step(int op, uint32_t r1, uint32_t r2, uint32_t r3, const Uni &U) {
   Step s;
   s.op = op;
   s.c = 0;
   const uint32_t n = U.n;
-  if (ENC == 0) {
+  if (enc_perm<ENC>()) {
     // 2-opt / swap: two distinct positions i, j of n, ordered; insert /
     // or-opt: block length L, start i of n - L + 1, target q != i of n - L + 1
     // (one code path for both, selecting the ranges); 3-opt: three distinct
@@ -172,6 +181,10 @@ __device__ __forceinline__ Step make_step(int op, uint32_t r1, uint32_t r2, uint
       s.c = (int)(cb - ca);
     }
     if (n < 2) s.a = s.b = s.c = 0;
+    if (ENC == 3 && op >= OROWSWAP) {
+      s.a = (int)rmap(r1, n);
+      s.b = s.c = 0;
+    }
   } else {
     // flip / random reset: one element; seg_flip / seg_reset: L = 2..7
     // consecutive elements (at most n) from a; a step covers [a, a + c)
@@ -429,13 +442,21 @@ __device__ __forceinline__ void perm_store(const uint16_t *cur, int n, int32_t *
 // delta = sum_{a in X} sum_b m_b F[a][b] (D[y_a][y_b] - D[x_a][x_b]), X the
 // changed positions, y the candidate, m_b = 1 inside X and 2 outside (F, D symmetric)
 // ------------------------------------------------------------ VRPTW (giant tour)
-// Objective of a split giant tour: weighted distance, route count and
-// longest route (the weighted multi-objective mode; default weights (1, 0, 0))
-// plus the lateness and fleet penalties.
-__device__ __forceinline__ int64_t vrp_objective(const DevInst *I, int64_t dist, int routes, int64_t longest,
-                                                 int64_t late) {
-  return (int64_t)I->vw_d * dist + (int64_t)I->vw_r * routes + (int64_t)I->vw_m * longest + 100 * late +
-         10000 * (int64_t)max(0, routes - I->vehicles);
+// Parts of a VRPTW solution's objective (over: load above the capacity, which
+// only the multi-row form can carry; the giant tour's split avoids it)
+struct VrpParts {
+  int64_t dist, late;
+  int routes, longest;
+  int64_t over;
+};
+
+// Objective of a VRPTW solution: weighted distance, route count and longest
+// route (the weighted multi-objective mode; default weights (1, 0, 0)) plus
+// the lateness and fleet penalties, and in the multi-row form 100 per unit of
+// a row's load above the capacity.
+__device__ __forceinline__ int64_t vrp_objective(const DevInst *I, const VrpParts &q) {
+  return (int64_t)I->vw_d * q.dist + (int64_t)I->vw_r * q.routes + (int64_t)I->vw_m * q.longest + 100 * q.late +
+         10000 * (int64_t)max(0, q.routes - I->vehicles) + 100 * q.over;
 }
 
 // Position map of one step (the element at position p after the step was at
@@ -473,12 +494,6 @@ __device__ __forceinline__ int sapply(const SMap &M, int p) {
 
 struct TspScratch;
 
-// Parts of a split giant tour's objective
-struct VrpParts {
-  int64_t dist, late;
-  int routes, longest;
-};
-
 // ---- lexicographic mode (paper, Sec. "Multi-Objective Optimization Modes";
 // Tab. lexicographic_mode).  A solution's objective vector is (penalty,
 // level 1, level 2, level 3): the penalty (lateness and fleet excess, as in
@@ -507,7 +522,7 @@ __device__ __forceinline__ LexCfg lex_cfg(const DevInst *I) {
 
 __device__ __forceinline__ Vec4 lex_vector(const VrpParts &q, int vehicles, const LexCfg &L) {
   Vec4 x;
-  x.v[0] = 100 * q.late + 10000 * (int64_t)max(0, q.routes - vehicles);
+  x.v[0] = 100 * q.late + 10000 * (int64_t)max(0, q.routes - vehicles) + 100 * q.over;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
     const int id = i < L.levels ? L.id[i] : 0;
@@ -557,18 +572,67 @@ __device__ __forceinline__ void store_vec(int64_t *p, const Vec4 &x) {
 // to this one, previous customer to the depot, depot to this one) are read
 // before the route-break test, which then only selects among them.  Two
 // waves per solution evaluate one candidate per lane (round by round).
+//
+// ROWS: the multi-row form (paper, Sec. "Solution Structure"; Tab. operators,
+// row level).  The solution's n entries are the rows one after another, each
+// closed by a marker (entries >= nc), the final entry a marker; a candidate
+// is read through its maps in the same way and each row is a route from the
+// depot and back.  Row operator steps are resolved on the candidate as the
+// earlier steps left it (resolve_rows) before their maps are built.
+template <bool ROWS>
 struct VrpK {
-  static constexpr int ENC = 0;
+  static constexpr int ENC = ROWS ? 3 : 0;
   uint16_t *cur, *nxt;
   int n, dn, cap, veh, svc, hor;
   const int16_t *D;
   const int4 *attr;   // (demand, ready, due, 0) per node
   const DevInst *I;
-  __device__ __forceinline__ int64_t eval(const Step *st, int k) const {
-    const VrpParts q = parts(st, k);
-    return vrp_objective(I, q.dist, q.routes, q.longest, q.late);
+  int nc;             // customers (dn - 1)
+  __device__ __forceinline__ int64_t eval(const Step *st, int k) const { return vrp_objective(I, parts(st, k)); }
+  // Row operator steps of a candidate replaced by the block moves they make
+  // on the candidate after its earlier steps (the solution's entry at
+  // position p after steps 0..m-1 is cur[chain(st, m, p)]); a step that does
+  // nothing becomes an empty block move.  Position n-1 always holds a marker
+  // (the permutation steps act on the first n-1 entries, and no row step moves
+  // anything past a marker at n-1), which ends every scan below.
+  __device__ __forceinline__ void resolve_rows(Step *st, int k) const {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      if (m >= k || st[m].op < OROWSWAP) continue;
+      const int op = st[m].op, p = st[m].a;
+      int a = 0, b = 0, L = 0;
+      if (op == OROWSPLIT) {   // the empty last row's marker moves to p
+        if (n >= 2 && p < n - 2 && (int)cur[chain(st, m, n - 2)] >= nc) {
+          a = n - 2;
+          b = p;
+          L = 1;
+        }
+      } else {
+        int e1 = p;            // the marker that closes p's row
+        while (e1 < n - 1 && (int)cur[chain(st, m, e1)] < nc) ++e1;
+        if (op == OROWMERGE) {   // that marker moves to just before the final one
+          if (e1 < n - 2) {
+            a = e1;
+            b = n - 2;
+            L = 1;
+          }
+        } else if (e1 < n - 1) {   // row swap: the row [s, e1] and the next one [e1 + 1, e2]
+          int s0 = p, e2 = e1 + 1;
+          while (s0 > 0 && (int)cur[chain(st, m, s0 - 1)] < nc) --s0;
+          while (e2 < n - 1 && (int)cur[chain(st, m, e2)] < nc) ++e2;
+          a = s0;
+          b = s0 + e2 - e1;
+          L = e1 - s0 + 1;
+        }
+      }
+      st[m].a = a;
+      st[m].b = b;
+      st[m].c = L;
+    }
   }
-  __device__ __forceinline__ VrpParts parts(const Step *st, int k) const {
+  __device__ __forceinline__ VrpParts parts(const Step *st_in, int k) const {
+    Step st[3] = {st_in[0], st_in[1], st_in[2]};
+    if constexpr (ROWS) resolve_rows(st, k);
     // the candidate's position maps, branch-free (identity past its k steps)
     SMap M[3];
 #pragma unroll
@@ -578,41 +642,72 @@ struct VrpK {
     }
     int64_t late = 0;
     // distances, times and route lengths stay below 2^31 (n <= 250, entries < 2^15, times <= 2^19)
-    int dist = 0, t = 0, load = 0, routes = n > 0 ? 1 : 0, prev = 0, len = 0, longest = 0;
-    for (int p = 0; p < n; ++p) {
-      const int c = cur[sapply(M[0], sapply(M[1], sapply(M[2], p)))] + 1;
-      const int4 a = attr[c];
-      const int dpc = D[prev * dn + c], dp0 = D[prev * dn], d0c = D[c];
-      // a demand never exceeds the capacity, so the first customer opens no second route
-      const bool brk = load + a.x > cap;
-      late += brk ? max(0, t + dp0 - hor) : 0;
-      longest = brk ? max(longest, len + dp0) : longest;
-      dist += brk ? dp0 : 0;
-      routes += brk ? 1 : 0;
-      t = brk ? 0 : t;
-      len = brk ? 0 : len;
-      load = brk ? 0 : load;
-      const int dd = brk ? d0c : dpc;
-      dist += dd;
-      len += dd;
-      t = max(t + dd, a.y);
-      late += max(0, t - a.z);
-      t += svc;
-      load += a.x;
-      prev = c;
+    if constexpr (ROWS) {
+      int64_t over = 0;
+      int dist = 0, t = 0, load = 0, routes = 0, prev = 0, len = 0, longest = 0;
+      for (int p = 0; p < n; ++p) {
+        const int e = cur[sapply(M[0], sapply(M[1], sapply(M[2], p)))];
+        const bool mk = e >= nc;
+        const int c = mk ? 0 : e + 1;
+        const int4 a = attr[c];
+        const int dd = D[prev * dn + c];
+        // a marker closes its row: back to the depot when the row has customers
+        const bool open = prev != 0, close = mk && open;
+        const int step = (mk && !open) ? 0 : dd;
+        dist += step;
+        len += step;
+        const int ta = t + step, tw = max(ta, a.y);
+        late += mk ? (close ? max(0, ta - hor) : 0) : max(0, tw - a.z);
+        longest = close ? max(longest, len) : longest;
+        over += mk ? max(0, load - cap) : 0;
+        routes += close ? 1 : 0;
+        t = mk ? 0 : tw + svc;
+        len = mk ? 0 : len;
+        load = mk ? 0 : load + a.x;
+        prev = c;
+      }
+      return VrpParts{dist, late, routes, longest, over};
+    } else {
+      int dist = 0, t = 0, load = 0, routes = n > 0 ? 1 : 0, prev = 0, len = 0, longest = 0;
+      for (int p = 0; p < n; ++p) {
+        const int c = cur[sapply(M[0], sapply(M[1], sapply(M[2], p)))] + 1;
+        const int4 a = attr[c];
+        const int dpc = D[prev * dn + c], dp0 = D[prev * dn], d0c = D[c];
+        // a demand never exceeds the capacity, so the first customer opens no second route
+        const bool brk = load + a.x > cap;
+        late += brk ? max(0, t + dp0 - hor) : 0;
+        longest = brk ? max(longest, len + dp0) : longest;
+        dist += brk ? dp0 : 0;
+        routes += brk ? 1 : 0;
+        t = brk ? 0 : t;
+        len = brk ? 0 : len;
+        load = brk ? 0 : load;
+        const int dd = brk ? d0c : dpc;
+        dist += dd;
+        len += dd;
+        t = max(t + dd, a.y);
+        late += max(0, t - a.z);
+        t += svc;
+        load += a.x;
+        prev = c;
+      }
+      if (n > 0) {
+        const int back = D[prev * dn];
+        dist += back;
+        late += max(0, t + back - hor);
+        longest = max(longest, len + back);
+      }
+      return VrpParts{dist, late, routes, longest, 0};
     }
-    if (n > 0) {
-      const int back = D[prev * dn];
-      dist += back;
-      late += max(0, t + back - hor);
-      longest = max(longest, len + back);
-    }
-    return VrpParts{dist, late, routes, longest};
   }
   // the delta of this lane's candidate of the wave's round (k = 0: no candidate)
   template <bool X3>
   __device__ __forceinline__ int64_t delta_round(const TspScratch &W, int tl, int k, int64_t f) const;
-  __device__ __forceinline__ void apply(const Step *st, int k) { perm_apply(cur, nxt, st, k); }
+  __device__ __forceinline__ void apply(const Step *st_in, int k) {
+    Step st[3] = {st_in[0], st_in[1], st_in[2]};
+    if constexpr (ROWS) resolve_rows(st, k);   // every lane reads the same solution: the same steps
+    perm_apply(cur, nxt, st, k);
+  }
   __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
 };
 
@@ -780,7 +875,7 @@ template <int ENC, bool X3>
 __device__ __forceinline__ void store_step(const TspScratch &W, uint32_t idx, const Step &st, uint32_t kbits) {
   W.sab()[idx] = (uint32_t)(uint16_t)st.a | ((uint32_t)(uint16_t)st.b << 16);
   W.sop()[idx] = (uint8_t)((st.op - enc_lo<ENC>()) | ((st.c & 7) << 3) | kbits);
-  if (X3 && ENC == 0 && st.op == O3OPT) W.sl()[idx] = (uint16_t)st.c;
+  if (X3 && enc_perm<ENC>() && st.op == O3OPT) W.sl()[idx] = (uint16_t)st.c;
 }
 
 // Draw the composite moves of candidates [c0, c0 + cn): the first step of
@@ -842,15 +937,16 @@ __device__ __forceinline__ Step load_step(const TspScratch &W, int t, int m) {
   st.a = (int)(ab & 0xFFFFu);
   st.b = ENC == 2 ? (int)(int16_t)(ab >> 16) : (int)(ab >> 16);
   st.op = (int)(ol & 7u) + enc_lo<ENC>();
-  st.c = (X3 && ENC == 0 && st.op == O3OPT) ? (int)W.sl()[3 * t + m] : (int)((ol >> 3) & 7u);
+  st.c = (X3 && enc_perm<ENC>() && st.op == O3OPT) ? (int)W.sl()[3 * t + m] : (int)((ol >> 3) & 7u);
   return st;
 }
 
 // delta of pattern step `sub` of operator m of candidate t, on the tour after
 // all earlier steps of that candidate (MAPPED: m >= 1, whose read positions
 // are mapped back through steps m-1 .. 0)
+template <bool ROWS>
 template <bool X3>
-__device__ __forceinline__ int64_t VrpK::delta_round(const TspScratch &W, int tl, int k, int64_t f) const {
+__device__ __forceinline__ int64_t VrpK<ROWS>::delta_round(const TspScratch &W, int tl, int k, int64_t f) const {
   if (k == 0) return 0;
   Step st[3];
   st[0] = load_step<ENC, X3>(W, tl, 0);
@@ -990,13 +1086,13 @@ __device__ __forceinline__ void fold_op_counts(uint32_t *u, uint32_t *v, uint64_
   if (fields > 4) fold_byte_counts(u + 4, v + 4, (uint32_t)(cu >> 32), (uint32_t)(cv >> 32), fields - 4);
 }
 
-// Per-lane operator counters: four byte fields in 32 bits, or with 3-opt five
-// in 64 bits.
-template <bool X3>
-using OpCount = typename std::conditional<X3, uint64_t, uint32_t>::type;
-template <bool X3>
-__device__ __forceinline__ void fold_ops(uint32_t *u, uint32_t *v, OpCount<X3> cu, OpCount<X3> cv, int fields) {
-  if constexpr (X3) fold_op_counts(u, v, cu, cv, fields);
+// Per-lane operator counters: four byte fields in 32 bits, or with 3-opt (five
+// fields) and for the multi-row encoding (eight) in 64 bits.
+template <bool W64>
+using OpCount = typename std::conditional<W64, uint64_t, uint32_t>::type;
+template <bool W64>
+__device__ __forceinline__ void fold_ops(uint32_t *u, uint32_t *v, OpCount<W64> cu, OpCount<W64> cv, int fields) {
+  if constexpr (W64) fold_op_counts(u, v, cu, cv, fields);
   else fold_byte_counts(u, v, cu, cv, fields < 4 ? fields : 4);
 }
 
@@ -1479,15 +1575,15 @@ struct QapK {
 
 // Byte-field counts of one lane: operator o (relative to the encoding's first
 // operator) at bits 8o of cu/cv, k at bits 8(k-1) of cuk/cvk.
-template <int ENC, bool X3>
-__device__ __forceinline__ void credit_bytes(OpCount<X3> &cu, OpCount<X3> &cv, uint32_t &cuk, uint32_t &cvk,
+template <int ENC, bool W64>
+__device__ __forceinline__ void credit_bytes(OpCount<W64> &cu, OpCount<W64> &cv, uint32_t &cuk, uint32_t &cvk,
                                              const Step *st, int k, bool imp) {
   constexpr int lo = enc_lo<ENC>();
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
-    const OpCount<X3> inc = m < k ? (OpCount<X3>)1 << ((st[m].op - lo) << 3) : (OpCount<X3>)0;
+    const OpCount<W64> inc = m < k ? (OpCount<W64>)1 << ((st[m].op - lo) << 3) : (OpCount<W64>)0;
     cu += inc;
-    cv += imp ? inc : (OpCount<X3>)0;
+    cv += imp ? inc : (OpCount<W64>)0;
   }
   const uint32_t inck = 1u << ((k - 1) << 3);
   cuk += inck;
@@ -1577,8 +1673,10 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
                                            uint32_t &nacc, unsigned long long *xk) {
   constexpr int ENC = KD::ENC;
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
-  constexpr int nf = X3 ? kPermOps : 4;
-  OpCount<X3> cu = 0, cv = 0;
+  // the multi-row encoding's eight operators take the 64-bit counters of 3-opt
+  constexpr bool W64 = X3 || ENC == 3;
+  constexpr int nf = ENC == 3 ? 8 : (X3 ? kPermOps : 4);
+  OpCount<W64> cu = 0, cv = 0;
   uint32_t cuk = 0, cvk = 0, since_fold = 0;
   bool best_is_cur = false;   // the best-so-far solution is the current one, not yet written
   for (uint32_t g = g0; g < g1; ++g) {
@@ -1597,14 +1695,14 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
             Step st[3];
 #pragma unroll
             for (int m = 0; m < 3; ++m) st[m].op = (int)(W.sop()[3 * tl + m] & 7u);
-            credit_bytes<ENC, X3>(cu, cv, cuk, cvk, st, k, d < 0);
+            credit_bytes<ENC, W64>(cu, cv, cuk, cvk, st, k, d < 0);
           }
           const unsigned long long key = ((unsigned long long)(d + kDeltaBias) << 16) | (c0 + tl);
           bk = key < bk ? key : bk;
         }
       }
       if (++since_fold == 84) {   // one candidate per lane per chunk: at most 3 per field
-        fold_ops<X3>(S.u, S.v, cu, cv, nf);
+        fold_ops<W64>(S.u, S.v, cu, cv, nf);
         fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
         cu = cv = 0;
         cuk = cvk = 0;
@@ -1638,7 +1736,7 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
     T = cool(T, U.alpha);
   }
   if (best_is_cur && wv == 0) kd.store(best_row);
-  fold_ops<X3>(S.u, S.v, cu, cv, nf);
+  fold_ops<W64>(S.u, S.v, cu, cv, nf);
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
 
@@ -1654,15 +1752,16 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
 // strictly better than the current solution.  The scalar f reported for a
 // solution is its penalty plus its first level.  Counts as in round_gens:
 // each wave its own candidates, accepted moves and credit R2 on wave 0.
-template <bool X3>
-__device__ __forceinline__ void lex_rounds(VrpK &kd, const TspScratch &W, const Uni &U, const LexCfg &L,
+template <bool X3, class KD>
+__device__ __forceinline__ void lex_rounds(KD &kd, const TspScratch &W, const Uni &U, const LexCfg &L,
                                            int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1, uint64_t &T,
                                            int64_t &f, int64_t &bf, Vec4 &cv, Vec4 &bsv, LStats &S, uint32_t &nacc,
                                            int64_t *vbuf) {
-  constexpr int ENC = 0;
-  constexpr int nf = X3 ? kPermOps : 4;
+  constexpr int ENC = KD::ENC;
+  constexpr bool W64 = X3 || ENC == 3;
+  constexpr int nf = ENC == 3 ? 8 : (X3 ? kPermOps : 4);
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
-  OpCount<X3> cu = 0, cvc = 0;
+  OpCount<W64> cu = 0, cvc = 0;
   uint32_t cuk = 0, cvk = 0, since_fold = 0;
   bool best_is_cur = false;   // the best-so-far solution is the current one, not yet written
   for (uint32_t g = g0; g < g1; ++g) {
@@ -1680,7 +1779,7 @@ __device__ __forceinline__ void lex_rounds(VrpK &kd, const TspScratch &W, const 
         st[1] = kk[0] > 1 ? load_step<ENC, X3>(W, (int)tl, 1) : st[0];
         st[2] = kk[0] > 2 ? load_step<ENC, X3>(W, (int)tl, 2) : st[0];
         const Vec4 v = lex_vector(kd.parts(st, kk[0]), kd.veh, L);
-        if (U.credit == 0) credit_bytes<ENC, X3>(cu, cvc, cuk, cvk, st, kk[0], lex_better(v, cv, L));
+        if (U.credit == 0) credit_bytes<ENC, W64>(cu, cvc, cuk, cvk, st, kk[0], lex_better(v, cv, L));
         store_vec(vbuf + 4 * (size_t)tl, v);
       }
       __syncthreads();
@@ -1693,7 +1792,7 @@ __device__ __forceinline__ void lex_rounds(VrpK &kd, const TspScratch &W, const 
         }
       }
       if (++since_fold == 84) {   // one candidate per lane per chunk: at most 3 per field
-        fold_ops<X3>(S.u, S.v, cu, cvc, nf);
+        fold_ops<W64>(S.u, S.v, cu, cvc, nf);
         fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
         cu = cvc = 0;
         cuk = cvk = 0;
@@ -1725,7 +1824,7 @@ __device__ __forceinline__ void lex_rounds(VrpK &kd, const TspScratch &W, const 
     T = cool(T, U.alpha);
   }
   if (best_is_cur && wv == 0) kd.store(best_row);
-  fold_ops<X3>(S.u, S.v, cu, cvc, nf);
+  fold_ops<W64>(S.u, S.v, cu, cvc, nf);
   fold_byte_counts(S.uk, S.vk, cuk, cvk, 3);
 }
 
@@ -2330,8 +2429,9 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
   const uint32_t g1 = min(gstop, (g0 / E + 1) * E);
   const DevInst *I = J->inst;
   const int n = I->n;
+  constexpr bool rows = (VAR & kVarRows) != 0;   // multi-row VRPTW
   Uni U;
-  U.n = (uint32_t)n;
+  U.n = (uint32_t)(rows ? n - 1 : n);   // the multi-row form keeps its final marker in place
   U.C = J->C;
   U.key = J->key;
   U.k0 = (uint32_t)J->seed;
@@ -2344,16 +2444,17 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
   const bool sol_scope = J->aos_scope != 0;
   const uint32_t *wsrc = sol_scope ? J->saos[sol].w_op : J->w_op;
   const uint32_t *wksrc = sol_scope ? J->saos[sol].w_k : J->w_k;
-  // cumulative weights of the encoding's operators (the others weigh 0)
-  constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : 0);
-  constexpr int lo = enc_lo<ENC>();
+  // cumulative weights of the encoding's operators (the others weigh 0): one
+  // bound per operator but the last, which only adds to the total
+  constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : (rows ? 3 : 0));
+  constexpr int lo = enc_lo<ENC>(), span = enc_hi<ENC>() - lo;
   uint32_t c = 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    if (lo + i <= enc_hi<ENC>()) c += wsrc[lo + i];
+  for (int i = 0; i < span; ++i) {
+    c += wsrc[lo + i];
     U.cw[i] = c;
   }
-  U.sw = c + (ENC == 0 ? wsrc[O3OPT] : 0u);
+  U.sw = c + wsrc[enc_hi<ENC>()];
   U.ck[0] = wksrc[0];
   U.ck[1] = wksrc[0] + wksrc[1];
   U.swk = U.ck[1] + wksrc[2];
@@ -2431,7 +2532,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       // int16 distances, the per-node (demand, ready, due) records, the two
       // waves' chunk minima, and in the lexicographic mode the chunk's
       // candidate vectors
-      const int dn = n + 1;
+      const int dn = I->dn;   // depot and customers
       int16_t *D = (int16_t *)rest;
       int4 *attr = (int4 *)(rest + al16(2 * dn * dn));
       unsigned long long *xk = (unsigned long long *)(attr + dn);
@@ -2439,7 +2540,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       for (int c = (int)threadIdx.x; c < dn; c += kThreads<KIND, VAR>)
         attr[c] = make_int4(I->dem[c], I->rdy[c], I->due[c], 0);
       __syncthreads();
-      VrpK kd{t0, t1, n, dn, I->capacity, I->vehicles, I->service, I->horizon, D, attr, I};
+      VrpK<rows> kd{t0, t1, n, dn, I->capacity, I->vehicles, I->service, I->horizon, D, attr, I, dn - 1};
       if constexpr ((VAR & kVarLex) != 0) {
         const LexCfg L = lex_cfg(I);
         Vec4 cv = load_vec(J->cur_v + 4 * (size_t)sol), bsv = load_vec(J->best_v + 4 * (size_t)sol);
@@ -2568,18 +2669,44 @@ __device__ int64_t full_objective(const DevInst *I, const int32_t *x) {
     const int64_t over = W - I->capacity;
     return -V + I->lambda * (over > 0 ? over : 0);
   }
-  if (I->kind == KVRP) {
-    const VrpParts q = vrp_parts_of(I, x);
-    return vrp_objective(I, q.dist, q.routes, q.longest, q.late);
-  }
+  if (I->kind == KVRP) return vrp_objective(I, vrp_parts_of(I, x));
   int64_t f = 0;
   for (int e = 0; e < I->n_edges; ++e) f += x[I->edges[2 * e]] == x[I->edges[2 * e + 1]];
   return f;
 }
 
-// parts of a VRPTW giant tour's objective, from the instance's global arrays
+// parts of a VRPTW solution's objective, from the instance's global arrays
 __device__ VrpParts vrp_parts_of(const DevInst *I, const int32_t *x) {
   const int n = I->n;
+  if (I->rows) {   // rows closed by markers, each a route from the depot and back
+    const int dn = I->dn, nc = dn - 1;
+    int64_t dist = 0, late = 0, over = 0;
+    int t = 0, load = 0, routes = 0, prev = 0, len = 0, longest = 0;
+    for (int p = 0; p < n; ++p) {
+      const int e = x[p];
+      if (e < nc) {
+        const int c = e + 1, dd = I->d16[prev * dn + c];
+        dist += dd;
+        len += dd;
+        t = max(t + dd, I->rdy[c]);
+        late += max(0, t - I->due[c]);
+        t += I->service;
+        load += I->dem[c];
+        prev = c;
+        continue;
+      }
+      if (prev != 0) {
+        const int back = I->d16[prev * dn];
+        dist += back;
+        late += max(0, t + back - I->horizon);
+        longest = max(longest, len + back);
+        over += max(0, load - I->capacity);
+        ++routes;
+      }
+      t = load = len = prev = 0;
+    }
+    return VrpParts{dist, late, routes, longest, over};
+  }
   {
     const int dn = I->dn;
     int64_t dist = 0, late = 0;
@@ -2616,12 +2743,88 @@ __device__ VrpParts vrp_parts_of(const DevInst *I, const int32_t *x) {
       late += max(0, t - I->horizon);
       longest = max(longest, len + back);
     }
-    return VrpParts{dist, late, routes, longest};
+    return VrpParts{dist, late, routes, longest, 0};
   }
 }
 
 __device__ __forceinline__ int heur_mats(int kind) {
   return kind == KQAP ? 2 : ((kind == KTSP || kind == KVRP) ? 1 : 0);
+}
+// pool slots the heuristic solutions take: four per data matrix, or the one
+// sweep solution of the multi-row form
+__device__ __forceinline__ uint32_t heur_slots(const DevInst *I) {
+  return I->rows ? 1u : 4u * (uint32_t)heur_mats(I->kind);
+}
+
+// sweep order of customer nodes a and b about the depot: polar angle
+// counter-clockwise from the positive x axis (the half-plane dy > 0 or
+// (dy = 0, dx >= 0) first, then the sign of the cross product), then squared
+// distance, then index -- all exact in integers
+__device__ __forceinline__ bool sweep_before(const int2 *xy, int a, int b) {
+  const int64_t ax = xy[a].x - xy[0].x, ay = xy[a].y - xy[0].y, bx = xy[b].x - xy[0].x, by = xy[b].y - xy[0].y;
+  const int ha = (ay < 0 || (ay == 0 && ax < 0)), hb = (by < 0 || (by == 0 && bx < 0));
+  if (ha != hb) return ha < hb;
+  const int64_t cr = ax * by - ay * bx;
+  if (cr != 0) return cr > 0;
+  const int64_t da = ax * ax + ay * ay, db = bx * bx + by * by;
+  if (da != db) return da < db;
+  return a < b;
+}
+// window order within a row: due time, then ready time, then index
+__device__ __forceinline__ bool window_before(const DevInst *I, int a, int b) {
+  if (I->due[a] != I->due[b]) return I->due[a] < I->due[b];
+  if (I->rdy[a] != I->rdy[b]) return I->rdy[a] < I->rdy[b];
+  return a < b;
+}
+
+// Initial solution of the multi-row form (Sec. "Partition Encoding Heuristic
+// Initialization": customers grouped by place, routes ordered by time
+// window), read as a sweep: customers in sweep order fill the rows in turn, a
+// row closing when the next demand would take its load above the capacity
+// (the last row takes the rest); each row is ordered by window_before and
+// closed by its marker nc + r.  One workgroup per job; the job's heuristic-sum
+// scratch holds the sweep order, each customer's row and the row offsets.
+__device__ void sweep_rows(DevJob *J, const DevInst *I, int32_t *out) {
+  const int nc = I->dn - 1, R = I->rows;
+  const int2 *xy = (const int2 *)I->xy;
+  int32_t *ord = (int32_t *)J->sums, *row = ord + nc, *off = row + nc + 1;
+  for (int c = 1 + (int)threadIdx.x; c <= nc; c += blockDim.x) {
+    int rank = 0;
+    for (int b = 1; b <= nc; ++b) rank += sweep_before(xy, b, c);
+    ord[rank] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int r = 0, load = 0, cnt = 0;
+    for (int i = 0; i < nc; ++i) {
+      const int c = ord[i];
+      if (load + I->dem[c] > I->capacity && r < R - 1) {
+        off[r++] = cnt;
+        cnt = 0;
+        load = 0;
+      }
+      row[c] = r;
+      load += I->dem[c];
+      ++cnt;
+    }
+    off[r] = cnt;
+    for (int q = r + 1; q < R; ++q) off[q] = 0;
+    // counts -> first entry of each row (customers of the earlier rows plus their markers)
+    int at = 0;
+    for (int q = 0; q < R; ++q) {
+      const int k = off[q];
+      off[q] = at;
+      at += k + 1;
+      out[at - 1] = nc + q;
+    }
+  }
+  __syncthreads();
+  for (int c = 1 + (int)threadIdx.x; c <= nc; c += blockDim.x) {
+    const int r = row[c];
+    int rank = 0;
+    for (int b = 1; b <= nc; ++b) rank += (row[b] == r) && window_before(I, b, c);
+    out[off[r] + rank] = c - 1;
+  }
 }
 
 // entry (i, j) of heuristic data matrix `mat` (Sec. heuristic init: any n x n data matrix)
@@ -2639,6 +2842,10 @@ __global__ __launch_bounds__(256) void k_init_heur(DevJob *jobs) {
   DevJob *J = jobs + blockIdx.x;
   const DevInst *I = J->inst;
   const int mat = blockIdx.y;
+  if (I->rows) {
+    if (mat == 0 && J->Q > 0) sweep_rows(J, I, J->pool);
+    return;
+  }
   if (mat >= heur_mats(I->kind)) return;
   const int base = 4 * mat;
   if ((uint32_t)base >= J->Q) return;
@@ -2671,14 +2878,15 @@ __global__ __launch_bounds__(256) void k_init_heur(DevJob *jobs) {
   }
 }
 
-// random members of the pool: Fisher-Yates from the identity, random bits, or
-// uniform integers; draw i comes from word (i mod 4) of the block with counter
+// random members of the pool: Fisher-Yates from the identity (multi-row
+// form: over the entries before the final marker), random bits, or uniform
+// integers; draw i comes from word (i mod 4) of the block with counter
 // (0xFFFFFFFF, pool index, i / 4, instance key)
 __global__ __launch_bounds__(64) void k_init_random(DevJob *jobs) {
   DevJob *J = jobs + blockIdx.y;
   const DevInst *I = J->inst;
   const uint32_t q = blockIdx.x * 64 + threadIdx.x;
-  const uint32_t H = min((uint32_t)(4 * heur_mats(I->kind)), J->Q);
+  const uint32_t H = min(heur_slots(I), J->Q);
   if (q < H || q >= J->Q) return;
   const int n = I->n;
   int32_t *x = J->pool + (size_t)q * n;
@@ -2691,9 +2899,11 @@ __global__ __launch_bounds__(64) void k_init_random(DevJob *jobs) {
       x[i] = I->kind == KKNAP ? (int32_t)(w >> 31) : I->lb + (int32_t)rmap(w, (uint32_t)(I->ub - I->lb + 1));
     }
   } else {
+    // the multi-row form shuffles the entries before its final marker
+    const int m = I->rows ? n - 1 : n;
     for (int i = 0; i < n; ++i) x[i] = i;
-    for (int i = n - 1; i >= 1; --i) {
-      if (i == n - 1 || (i & 3) == 3) philox(0xFFFFFFFFu, q, (uint32_t)(i >> 2), J->key, k0, k1, r);
+    for (int i = m - 1; i >= 1; --i) {
+      if (i == m - 1 || (i & 3) == 3) philox(0xFFFFFFFFu, q, (uint32_t)(i >> 2), J->key, k0, k1, r);
       const uint32_t j = rmap(r[i & 3], (uint32_t)(i + 1));
       const int32_t t = x[i];
       x[i] = x[j];
@@ -2966,6 +3176,7 @@ hipError_t set_stop(DevJob *jobs, int count, uint32_t add, int use_total, hipStr
 }
 
 // the kernel of a (kind, variant): variant = staging | kVarX3 (3-opt) | kVarLex (VRPTW lexicographic)
+// | kVarRows (VRPTW multi-row)
 #define GX_KERNEL_OF(KERNEL)                                                                 \
   static const void *KERNEL##_of(int kind, int var) {                                      \
     const bool x3 = (var & kVarX3) != 0;                                                     \
@@ -2982,6 +3193,12 @@ hipError_t set_stop(DevJob *jobs, int count, uint32_t add, int use_total, hipStr
         return x3 ? (const void *)KERNEL<KQAP, kVarX3> : (const void *)KERNEL<KQAP, 0>;   \
       case KKNAP: return (const void *)KERNEL<KKNAP, 0>;                                     \
       case KVRP:                                                                             \
+        if (var & kVarRows) {                                                                \
+          if (var & kVarLex)                                                                 \
+            return x3 ? (const void *)KERNEL<KVRP, kVarRows | kVarLex | kVarX3>              \
+                      : (const void *)KERNEL<KVRP, kVarRows | kVarLex>;                      \
+          return x3 ? (const void *)KERNEL<KVRP, kVarRows | kVarX3> : (const void *)KERNEL<KVRP, kVarRows>; \
+        }                                                                                    \
         if (var & kVarLex) return x3 ? (const void *)KERNEL<KVRP, kVarLex | kVarX3> : (const void *)KERNEL<KVRP, kVarLex>; \
         return x3 ? (const void *)KERNEL<KVRP, kVarX3> : (const void *)KERNEL<KVRP, 0>;   \
       default: return (const void *)KERNEL<KCOLOR, 0>;                                      \
@@ -3000,7 +3217,9 @@ hipError_t prepare_kernel_attrs(uint32_t max_lds) {
                           {KKNAP, 0},              {KVRP, 0},               {KCOLOR, 0},
                           {KTSP, SLDS16 | kVarX3}, {KTSP, SLDSXY | kVarX3}, {KTSP, SGLB16 | kVarX3},
                           {KTSP, SGLB32 | kVarX3}, {KQAP, kVarX3},          {KQAP, 1 | kVarX3},
-                          {KVRP, kVarX3},          {KVRP, kVarLex},         {KVRP, kVarLex | kVarX3}};
+                          {KVRP, kVarX3},          {KVRP, kVarLex},         {KVRP, kVarLex | kVarX3},
+                          {KVRP, kVarRows},        {KVRP, kVarRows | kVarX3},
+                          {KVRP, kVarRows | kVarLex}, {KVRP, kVarRows | kVarLex | kVarX3}};
   for (auto &k : kinds) {
     hipError_t e = hipFuncSetAttribute(plain_kernel(k[0], k[1]), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)max_lds);
