@@ -428,6 +428,11 @@ def bench_kinds(args):
          (dataclasses.replace(synth.c3_vrptw()[0], obj_weights=(6, 2, 2)), synth.c3_vrptw()[1])),
         ("vrptw100_lex", "same, lexicographic: routes, then distance within 20, then longest route",
          (dataclasses.replace(synth.c3_vrptw()[0], lex_order=(2, 1, 3), lex_tol=(0, 20, 0)), synth.c3_vrptw()[1])),
+        ("vrptw100_rows", "same customers in the multi-row form: 25 rows, every permutation and row operator",
+         synth.c3_vrptw_rows()),
+        ("vrptw100_rows_lex", "same, multi-row, lexicographic: routes, then distance within 20, then longest route",
+         (dataclasses.replace(synth.c3_vrptw_rows()[0], lex_order=(2, 1, 3), lex_tol=(0, 20, 0)),
+          synth.c3_vrptw_rows()[1])),
         ("qap50", "QAP n=50, P autosized, 2000 generations", one(synth.qap_random(50, 7), 0, 2000)),
     ]
     kp_inst, kp = one(synth.knapsack_random(1000, 7), 2048, 5000)
@@ -448,7 +453,7 @@ def bench_kinds(args):
             p = p.with_(population=gx.gx_autosize_population(ctx, h, p))
         for rep in range(2):
             job = gx.gx_solve(ctx, h, p)
-            _, f = gx.gx_fetch_best(ctx, job, inst.n)
+            _, f = gx.gx_fetch_best(ctx, job, synth.solution_len(inst))
             info = gx.gx_job_info_get(ctx, job)
             gx.gx_job_free(ctx, job)
         gx.gx_instance_free(ctx, h)

@@ -641,55 +641,90 @@ struct VrpK {
       if (m >= k) M[m].len = 0;
     }
     int64_t late = 0;
-    // distances, times and route lengths stay below 2^31 (n <= 250, entries < 2^15, times <= 2^19)
+    // distances, times and route lengths stay below 2^31 (n <= 250, entries < 2^15, times <= 2^19).
+    // The entries are taken kB at a time: the LDS reads of a batch (entries,
+    // node records, the distances from each entry's predecessor) depend on
+    // the sequence alone and are issued together; only the time, load and
+    // route arithmetic runs entry after entry.
+    constexpr int kB = 8;
     if constexpr (ROWS) {
       int64_t over = 0;
       int dist = 0, t = 0, load = 0, routes = 0, prev = 0, len = 0, longest = 0;
-      for (int p = 0; p < n; ++p) {
-        const int e = cur[sapply(M[0], sapply(M[1], sapply(M[2], p)))];
-        const bool mk = e >= nc;
-        const int c = mk ? 0 : e + 1;
-        const int4 a = attr[c];
-        const int dd = D[prev * dn + c];
-        // a marker closes its row: back to the depot when the row has customers
-        const bool open = prev != 0, close = mk && open;
-        const int step = (mk && !open) ? 0 : dd;
-        dist += step;
-        len += step;
-        const int ta = t + step, tw = max(ta, a.y);
-        late += mk ? (close ? max(0, ta - hor) : 0) : max(0, tw - a.z);
-        longest = close ? max(longest, len) : longest;
-        over += mk ? max(0, load - cap) : 0;
-        routes += close ? 1 : 0;
-        t = mk ? 0 : tw + svc;
-        len = mk ? 0 : len;
-        load = mk ? 0 : load + a.x;
-        prev = c;
+      for (int p0 = 0; p0 < n; p0 += kB) {
+        int cc[kB], dd[kB];
+        bool mk[kB];
+        int4 aa[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int p = min(p0 + u, n - 1);
+          const int e = cur[sapply(M[0], sapply(M[1], sapply(M[2], p)))];
+          mk[u] = e >= nc;
+          cc[u] = mk[u] ? 0 : e + 1;
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          aa[u] = attr[cc[u]];
+          dd[u] = D[(u == 0 ? prev : cc[u - 1]) * dn + cc[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          if (p0 + u < n) {
+            // a marker closes its row: back to the depot when the row has customers
+            const bool open = prev != 0, close = mk[u] && open;
+            const int step = (mk[u] && !open) ? 0 : dd[u];
+            dist += step;
+            len += step;
+            const int ta = t + step, tw = max(ta, aa[u].y);
+            late += mk[u] ? (close ? max(0, ta - hor) : 0) : max(0, tw - aa[u].z);
+            longest = close ? max(longest, len) : longest;
+            over += mk[u] ? max(0, load - cap) : 0;
+            routes += close ? 1 : 0;
+            t = mk[u] ? 0 : tw + svc;
+            len = mk[u] ? 0 : len;
+            load = mk[u] ? 0 : load + aa[u].x;
+            prev = cc[u];
+          }
+        }
       }
       return VrpParts{dist, late, routes, longest, over};
     } else {
       int dist = 0, t = 0, load = 0, routes = n > 0 ? 1 : 0, prev = 0, len = 0, longest = 0;
-      for (int p = 0; p < n; ++p) {
-        const int c = cur[sapply(M[0], sapply(M[1], sapply(M[2], p)))] + 1;
-        const int4 a = attr[c];
-        const int dpc = D[prev * dn + c], dp0 = D[prev * dn], d0c = D[c];
-        // a demand never exceeds the capacity, so the first customer opens no second route
-        const bool brk = load + a.x > cap;
-        late += brk ? max(0, t + dp0 - hor) : 0;
-        longest = brk ? max(longest, len + dp0) : longest;
-        dist += brk ? dp0 : 0;
-        routes += brk ? 1 : 0;
-        t = brk ? 0 : t;
-        len = brk ? 0 : len;
-        load = brk ? 0 : load;
-        const int dd = brk ? d0c : dpc;
-        dist += dd;
-        len += dd;
-        t = max(t + dd, a.y);
-        late += max(0, t - a.z);
-        t += svc;
-        load += a.x;
-        prev = c;
+      for (int p0 = 0; p0 < n; p0 += kB) {
+        int cc[kB], dpc[kB], dp0[kB], d0c[kB];
+        int4 aa[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u)
+          cc[u] = cur[sapply(M[0], sapply(M[1], sapply(M[2], min(p0 + u, n - 1))))] + 1;
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          const int pv = u == 0 ? prev : cc[u - 1];
+          aa[u] = attr[cc[u]];
+          dpc[u] = D[pv * dn + cc[u]];
+          dp0[u] = D[pv * dn];
+          d0c[u] = D[cc[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+          if (p0 + u < n) {
+            // a demand never exceeds the capacity, so the first customer opens no second route
+            const bool brk = load + aa[u].x > cap;
+            late += brk ? max(0, t + dp0[u] - hor) : 0;
+            longest = brk ? max(longest, len + dp0[u]) : longest;
+            dist += brk ? dp0[u] : 0;
+            routes += brk ? 1 : 0;
+            t = brk ? 0 : t;
+            len = brk ? 0 : len;
+            load = brk ? 0 : load;
+            const int d = brk ? d0c[u] : dpc[u];
+            dist += d;
+            len += d;
+            t = max(t + d, aa[u].y);
+            late += max(0, t - aa[u].z);
+            t += svc;
+            load += aa[u].x;
+            prev = cc[u];
+          }
+        }
       }
       if (n > 0) {
         const int back = D[prev * dn];
