@@ -101,7 +101,11 @@ def lib():
         L.or_dist.restype = C.c_int32
         L.or_apply_op.argtypes = [C.c_void_p, P64, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32]
         L.or_initial_weights.argtypes = [C.c_void_p, C.c_uint32, C.c_void_p, P32]
-        L.or_aos_update.argtypes = [C.POINTER(_Params), C.c_uint32, C.POINTER(_State), C.c_int64]
+        L.or_aos_update.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_uint32, C.POINTER(_State), C.c_int64]
+        L.or_lns_len.argtypes = [C.c_int]
+        L.or_lns_len.restype = C.c_int
+        L.or_lns_cap.argtypes = [C.c_void_p]
+        L.or_lns_cap.restype = C.c_uint32
         L.or_migrate.argtypes = [C.c_void_p, C.POINTER(_Params), C.c_int, C.POINTER(_State), C.c_uint32]
         L.or_heuristic_perms.argtypes = [C.c_void_p, P64, C.c_int]
         L.or_heuristic_perms.restype = C.c_int
@@ -129,6 +133,10 @@ def _i32p(a):
 
 
 # ------------------------------------------------------------------ helpers
+def lns_len(n: int) -> int:
+    return int(lib().or_lns_len(n))
+
+
 def philox(ctr, key) -> np.ndarray:
     c = (C.c_uint32 * 4)(*[int(x) & 0xFFFFFFFF for x in ctr])
     k = (C.c_uint32 * 2)(*[int(x) & 0xFFFFFFFF for x in key])
@@ -239,6 +247,9 @@ class OracleInstance:
         lib().or_initial_weights(self.h, op_mask, iw, w)
         return np.array(list(w), dtype=np.uint32)
 
+    def lns_cap(self) -> int:
+        return int(lib().or_lns_cap(self.h))
+
     def effective_mask(self, op_mask) -> int:
         return int(lib().or_effective_mask(self.h, op_mask))
 
@@ -335,7 +346,7 @@ class OracleInstance:
         s = self._state_struct(st)
         pp = _params(params)
         m = self.effective_mask(params.op_mask if op_mask is None else op_mask)
-        lib().or_aos_update(C.byref(pp), m, C.byref(s), inst_best_now)
+        lib().or_aos_update(self.h, C.byref(pp), m, C.byref(s), inst_best_now)
         self._read_back(s, st)
         return st
 

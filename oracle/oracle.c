@@ -27,6 +27,8 @@
 enum { K_TSP = 1, K_QAP = 2, K_KNAP = 3, K_VRPTW = 4, K_COLOR = 5, K_VRPROWS = 6 };
 enum { OP_2OPT = 0, OP_SWAP = 1, OP_INSERT = 2, OP_OROPT = 3, OP_3OPT = 4, OP_ROWSWAP = 5, OP_ROWSPLIT = 6,
        OP_ROWMERGE = 7, OP_FLIP = 8, OP_SEGFLIP = 9, OP_RESET = 10, OP_SEGRESET = 11 };
+/* on single-row permutations ids 5-7 are the LNS operators */
+enum { OP_LNS_SEG = 5, OP_LNS_SCATTER = 6, OP_LNS_GUIDED = 7 };
 
 struct or_inst {
   or_inst_desc d;
@@ -34,6 +36,7 @@ struct or_inst {
   int32_t dn;      /* side of dist */
   int64_t lambda;  /* knapsack penalty weight */
   int32_t nc;      /* multi-row VRPTW: customers (the solution holds nc + vehicles entries, d.n) */
+  int64_t *hkey;   /* permutations: heuristic key of each entry (row sums of the first data matrix) */
 };
 
 /* ------------------------------------------------------------------ RNG
@@ -150,11 +153,22 @@ or_inst *or_inst_new(const or_inst_desc *d) {
     free(in);
     return NULL;
   }
+  if (d->kind == K_TSP || d->kind == K_QAP || d->kind == K_VRPTW) {
+    /* the row sums of the heuristic initialisation: TSP distances, QAP flows,
+     * VRPTW travel times among the customers */
+    in->hkey = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        in->hkey[i] += d->kind == K_TSP ? in->dist[(int64_t)i * n + j]
+                       : d->kind == K_QAP ? d->a[(int64_t)i * n + j]
+                                          : in->dist[(int64_t)(i + 1) * in->dn + (j + 1)];
+  }
   return in;
 }
 
 void or_inst_free(or_inst *in) {
   if (!in) return;
+  free(in->hkey);
   free(in->dist);
   free(in);
 }
@@ -352,6 +366,7 @@ static void reverse_range(int32_t *x, int lo, int hi) {
 
 static void perm_op(int32_t *x, int n, int op, uint32_t w1, uint32_t w2, uint32_t w3);
 static void row_op(const or_inst *in, int32_t *x, int op, uint32_t w1);
+static void lns_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2, uint32_t w3);
 
 int or_apply_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2, uint32_t w3) {
   int n = in->d.n;
@@ -360,6 +375,10 @@ int or_apply_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2,
   if (in->d.kind == K_VRPROWS) {
     if (op >= OP_ROWSWAP) row_op(in, x, op, w1);
     else perm_op(x, n - 1, op, w1, w2, w3);
+    return op;
+  }
+  if (op >= OP_LNS_SEG && op <= OP_LNS_GUIDED) {
+    lns_op(in, x, op, w1, w2, w3);
     return op;
   }
   if (op == OP_FLIP) { x[rmap(w1, n)] ^= 1; return op; }
@@ -494,6 +513,83 @@ static void row_op(const or_inst *in, int32_t *x, int op, uint32_t w1) {
   free(tmp);
 }
 
+/* Sec. "Built-in Operator Hierarchy": the LNS operators -- segment shuffle,
+ * scatter shuffle, guided rebuild -- destroy a part of the solution whose
+ * size follows the problem size and rebuild it.  On single-row permutations
+ * (ids 5-7).  readings:
+ *  - destroyed part L(n) = min(n, 2 + floor(n / 16), 64) entries;
+ *  - draws beyond the step's three words: x_i is word i mod 4 of the
+ *    Philox4x32-10 block with counter (w1, w2, w3, floor(i / 4)) and key
+ *    (0x4C4E5331, 0x4C4E5332), so that a step stays a function of its words;
+ *  - segment shuffle: the L entries from a = floor(w1 (n - L + 1) / 2^32)
+ *    shuffled by Fisher-Yates: for i = L-1 down to 1 entry i and entry
+ *    floor(x_{L-1-i} (i + 1) / 2^32) of the segment trade places;
+ *  - scatter shuffle: L distinct positions by Floyd's sampling (for
+ *    j = n-L .. n-1 in turn, r = floor(x_{j-n+L} (j + 1) / 2^32) joins the
+ *    set, or j when r is already in it), in increasing order; their entries
+ *    shuffled as above with the words x_{L + L-1-i};
+ *  - guided rebuild: the L entries from a (drawn as for the segment shuffle)
+ *    put back in order of their heuristic key (the row sums of the heuristic
+ *    initialisation), ascending when the top bit of w2 is 0 and descending
+ *    otherwise, ties by entry value ascending. */
+int or_lns_len(int n) {
+  int L = 2 + n / 16;
+  if (L > 64) L = 64;
+  return L < n ? L : n;
+}
+
+static uint32_t lns_word(uint32_t w1, uint32_t w2, uint32_t w3, int i) {
+  const uint32_t ctr[4] = {w1, w2, w3, (uint32_t)(i >> 2)}, key[2] = {0x4C4E5331u, 0x4C4E5332u};
+  uint32_t r[4];
+  or_philox4x32_10(ctr, key, r);
+  return r[i & 3];
+}
+
+static void lns_op(const or_inst *in, int32_t *x, int op, uint32_t w1, uint32_t w2, uint32_t w3) {
+  const int n = in->d.n, L = or_lns_len(n);
+  if (L < 2) return;
+  int pos[64];
+  if (op == OP_LNS_SCATTER) {
+    int cnt = 0;
+    for (int j = n - L; j < n; ++j) {
+      int r = (int)rmap(lns_word(w1, w2, w3, j - n + L), (uint32_t)(j + 1)), have = 0;
+      for (int q = 0; q < cnt; ++q) have |= pos[q] == r;
+      pos[cnt++] = have ? j : r;
+    }
+    for (int i = 1; i < L; ++i) {             /* increasing order */
+      int v = pos[i], q = i;
+      while (q > 0 && pos[q - 1] > v) { pos[q] = pos[q - 1]; --q; }
+      pos[q] = v;
+    }
+  } else {
+    const int a = (int)rmap(w1, (uint32_t)(n - L + 1));
+    for (int i = 0; i < L; ++i) pos[i] = a + i;
+  }
+  if (op == OP_LNS_GUIDED) {
+    const int desc = (int)(w2 >> 31);
+    int32_t v[64];
+    for (int i = 0; i < L; ++i) v[i] = x[pos[i]];
+    for (int i = 1; i < L; ++i) {             /* insertion sort by (key, value) */
+      int32_t e = v[i];
+      int q = i;
+      while (q > 0) {
+        int64_t kp = in->hkey[v[q - 1]], ke = in->hkey[e];
+        if (desc) { kp = -kp; ke = -ke; }
+        if (kp > ke || (kp == ke && v[q - 1] > e)) { v[q] = v[q - 1]; --q; }
+        else break;
+      }
+      v[q] = e;
+    }
+    for (int i = 0; i < L; ++i) x[pos[i]] = v[i];
+    return;
+  }
+  const int base = op == OP_LNS_SCATTER ? L : 0;
+  for (int i = L - 1; i >= 1; --i) {
+    int j = (int)rmap(lns_word(w1, w2, w3, base + L - 1 - i), (uint32_t)(i + 1));
+    int32_t t = x[pos[i]]; x[pos[i]] = x[pos[j]]; x[pos[j]] = t;
+  }
+}
+
 /* ------------------------------------------------------------ encodings */
 static uint32_t encoding_ops(int kind) {
   if (kind == K_KNAP) return (1u << OP_FLIP) | (1u << OP_SEGFLIP);
@@ -504,9 +600,23 @@ static uint32_t encoding_ops(int kind) {
   return (1u << OP_2OPT) | (1u << OP_SWAP) | (1u << OP_INSERT) | (1u << OP_OROPT) | (1u << OP_3OPT);
 }
 
+/* reading: the LNS operators are taken when op_mask names them; the default
+ * set of a single-row permutation is its element and segment operators */
+static int lns_kind(int kind) { return kind == K_TSP || kind == K_QAP || kind == K_VRPTW; }
+
 uint32_t or_effective_mask(const or_inst *in, uint32_t op_mask) {
   uint32_t e = encoding_ops(in->d.kind);
+  if (lns_kind(in->d.kind) && op_mask) e |= (1u << OP_LNS_SEG) | (1u << OP_LNS_SCATTER) | (1u << OP_LNS_GUIDED);
   return op_mask ? (op_mask & e) : e;
+}
+
+/* Tab. "weight_preset", LNS cap: the largest weight the EMA update gives an
+ * LNS operator, 0.02 / 0.01 / 0.005 (Q16, rounded) by scale; the lower bound
+ * of its clamp is the smaller of the floor and the cap.  0: no LNS. */
+uint32_t or_lns_cap(const or_inst *in) {
+  if (!lns_kind(in->d.kind)) return 0;
+  const int n = in->d.n;
+  return n <= 100 ? 1311u : (n <= 250 ? 655u : 328u);
 }
 
 static int enabled_list(uint32_t mask, int *ids) {
@@ -518,8 +628,9 @@ static int enabled_list(uint32_t mask, int *ids) {
 /* Sec. "Problem-Profile-Driven Prior Strategy", Tab. "weight_preset":
  * O(1) operators start at 1.0; or-opt at 0.8 / 0.7 / 0.3 and 3-opt at
  * 0.50 / 0.30 / 0.05 for n <= 100, <= 250, > 250 (Q16, rounded; n is the
- * solution's length, customers and markers in the row form); reading: the
- * row operators, which the table does not list, start at 1.0; a nonzero
+ * solution's length, customers and markers in the row form); LNS at
+ * 0.006 / 0.004 / 0.001; reading: the row operators, which the table does
+ * not list, start at 1.0; a nonzero
  * init_w[i] replaces the preset of operator i; then the weights are
  * normalised (Q16). */
 void or_initial_weights(const or_inst *in, uint32_t op_mask, const uint32_t *init_w, uint32_t w[OR_MAX_OPS]) {
@@ -531,6 +642,8 @@ void or_initial_weights(const or_inst *in, uint32_t op_mask, const uint32_t *ini
     raw[i] = 65536;
     if (i == OP_OROPT) raw[i] = n <= 100 ? 52429 : (n <= 250 ? 45875 : 19661);
     if (i == OP_3OPT) raw[i] = n <= 100 ? 32768 : (n <= 250 ? 19661 : 3277);
+    if (lns_kind(in->d.kind) && i >= OP_LNS_SEG && i <= OP_LNS_GUIDED)
+      raw[i] = n <= 100 ? 393 : (n <= 250 ? 262 : 66);
     if (init_w && init_w[i]) raw[i] = init_w[i];
     s += raw[i];
   }
@@ -564,15 +677,19 @@ uint64_t or_cool(uint64_t t, uint32_t alpha) {
  * Eq. ema: w <- a w + (1-a)(v/(u+eps) + w_floor); clamp to [w_floor, 1];
  * normalise; Alg. 2 also updates the K-step weights the same way and resets
  * them to (0.8, 0.15, 0.05) after stagnation. */
+/* cap: the LNS cap (Q16) of ids 5-7, 0 when they are not LNS operators (and
+ * for the K-step group) */
 static void ema_group(const or_params *p, uint32_t *w, const uint64_t *u, const uint64_t *v,
-                      const int *ids, int cnt) {
+                      const int *ids, int cnt, uint32_t cap) {
   uint64_t A = p->aos_alpha_q16, FL = p->w_floor_q16, s = 0;
   for (int c = 0; c < cnt; ++c) {
     int i = ids[c];
     uint64_t r = (v[i] << 16) / (u[i] + 1);
     uint64_t nw = (A * w[i] + (65536 - A) * (r + FL)) >> 16;
-    if (nw < FL) nw = FL;
-    if (nw > 65536) nw = 65536;
+    const int lns = cap && i >= OP_LNS_SEG && i <= OP_LNS_GUIDED;
+    const uint64_t lo = lns ? (cap < FL ? cap : FL) : FL, hi = lns ? cap : 65536;
+    if (nw < lo) nw = lo;
+    if (nw > hi) nw = hi;
     w[i] = (uint32_t)nw;
     s += nw;
   }
@@ -586,12 +703,12 @@ static void ema_group(const or_params *p, uint32_t *w, const uint64_t *u, const 
 static const uint32_t WK_DEFAULT[3] = {52429, 9830, 3277};
 
 /* the update with the epoch's improvement of the instance best given */
-static void aos_update_flag(const or_params *p, uint32_t mask, or_state *st, int improved) {
+static void aos_update_flag(const or_params *p, uint32_t mask, uint32_t cap, or_state *st, int improved) {
   int ids[OR_MAX_OPS];
   int cnt = enabled_list(mask, ids);
-  ema_group(p, st->w_op, st->u_op, st->v_op, ids, cnt);
+  ema_group(p, st->w_op, st->u_op, st->v_op, ids, cnt, cap);
   int kid[3] = {0, 1, 2};
-  ema_group(p, st->w_k, st->u_k, st->v_k, kid, 3);
+  ema_group(p, st->w_k, st->u_k, st->v_k, kid, 3, 0);
   /* reading: "consecutive no-improvement" counted in epochs of the instance best */
   if (improved) st->stag = 0;
   else st->stag++;
@@ -605,10 +722,10 @@ static void aos_update_flag(const or_params *p, uint32_t mask, or_state *st, int
   memset(st->v_k, 0, sizeof(st->v_k));
 }
 
-void or_aos_update(const or_params *p, uint32_t mask, or_state *st, int64_t inst_best_now) {
+void or_aos_update(const or_inst *in, const or_params *p, uint32_t mask, or_state *st, int64_t inst_best_now) {
   int improved = inst_best_now < st->epoch_ref;
   st->epoch_ref = inst_best_now;
-  aos_update_flag(p, mask, st, improved);
+  aos_update_flag(p, mask, or_lns_cap(in), st, improved);
 }
 
 /* Per-solution scope (aos_scope = 1).  reading: Alg. 2 pools the statistics
@@ -617,15 +734,15 @@ void or_aos_update(const or_params *p, uint32_t mask, or_state *st, int64_t inst
  * candidates' counts with the same Eq. ema arithmetic, and its own
  * stagnation counter on its own best objective.  The instance-level weights
  * and epoch counts are then not used and stay as initialised. */
-static void sol_aos_update(const or_params *p, uint32_t mask, or_sol_aos *a, int64_t best_now) {
+static void sol_aos_update(const or_params *p, uint32_t mask, uint32_t cap, or_sol_aos *a, int64_t best_now) {
   int ids[OR_MAX_OPS];
   int cnt = enabled_list(mask, ids);
   uint64_t u[OR_MAX_OPS], v[OR_MAX_OPS], uk[3], vk[3];
   for (int i = 0; i < OR_MAX_OPS; ++i) { u[i] = a->u_op[i]; v[i] = a->v_op[i]; }
   for (int i = 0; i < 3; ++i) { uk[i] = a->u_k[i]; vk[i] = a->v_k[i]; }
-  ema_group(p, a->w_op, u, v, ids, cnt);
+  ema_group(p, a->w_op, u, v, ids, cnt, cap);
   int kid[3] = {0, 1, 2};
-  ema_group(p, a->w_k, uk, vk, kid, 3);
+  ema_group(p, a->w_k, uk, vk, kid, 3, 0);
   if (best_now < a->epoch_ref) a->stag = 0;
   else a->stag++;
   a->epoch_ref = best_now;
@@ -1171,13 +1288,13 @@ static void epoch_end(const or_inst *in, const or_params *p, or_state *st, uint3
     int improved = or_lex_better(in, st->best_v + 4 * (size_t)b, st->ref_v);
     memcpy(st->ref_v, st->best_v + 4 * (size_t)b, sizeof(st->ref_v));
     st->epoch_ref = st->best_f[b];
-    aos_update_flag(p, mask, st, improved);
+    aos_update_flag(p, mask, or_lns_cap(in), st, improved);
   } else if (p->aos_scope == 1) {
-    for (int s = 0; s < P; ++s) sol_aos_update(p, mask, &st->saos[s], st->best_f[s]);
+    for (int s = 0; s < P; ++s) sol_aos_update(p, mask, or_lns_cap(in), &st->saos[s], st->best_f[s]);
   } else {
     int64_t ib = st->best_f[0];
     for (int s = 1; s < P; ++s) if (st->best_f[s] < ib) ib = st->best_f[s];
-    or_aos_update(p, mask, st, ib);
+    or_aos_update(in, p, mask, st, ib);
   }
   or_migrate(in, p, in->d.n, st, g_end / p->epoch);
 }

@@ -13,9 +13,11 @@
 #include <stdint.h>
 
 /* Operator ids (Tab. "operators"): permutation 0 2-opt, 1 swap, 2 insert,
- * 3 or-opt, 4 3-opt; row level (multi-row solutions) 5 row_swap, 6 row_split,
- * 7 row_merge; binary 8 flip, 9 seg_flip; integer 10 random_reset,
- * 11 seg_reset. */
+ * 3 or-opt, 4 3-opt; ids 5-7 are the LNS operators on single-row
+ * permutations (5 segment shuffle, 6 scatter shuffle, 7 guided rebuild; Sec.
+ * "Built-in Operator Hierarchy") and the row operators on multi-row solutions
+ * (5 row_swap, 6 row_split, 7 row_merge); binary 8 flip, 9 seg_flip; integer
+ * 10 random_reset, 11 seg_reset. */
 #define OR_MAX_OPS 12
 
 /* kind 1 TSP, 2 QAP, 3 knapsack, 4 VRPTW as a giant tour split by capacity,
@@ -96,7 +98,9 @@ int64_t  or_objective(const or_inst *, const int32_t *x);
 int32_t  or_dist(const or_inst *, int32_t u, int32_t v);  /* TSP / VRPTW distances */
 int      or_apply_op(const or_inst *, int32_t *x, int op, uint32_t w1, uint32_t w2, uint32_t w3);
 void     or_initial_weights(const or_inst *, uint32_t op_mask, const uint32_t *init_w, uint32_t w_op[OR_MAX_OPS]);
-void     or_aos_update(const or_params *, uint32_t op_mask, or_state *st, int64_t inst_best_now);
+void     or_aos_update(const or_inst *, const or_params *, uint32_t op_mask, or_state *st, int64_t inst_best_now);
+int      or_lns_len(int n);                     /* entries an LNS step destroys */
+uint32_t or_lns_cap(const or_inst *);           /* Q16 weight cap of the LNS operators (0: none) */
 void     or_migrate(const or_inst *in, const or_params *, int n, or_state *st, uint32_t epoch);  /* epoch: 1-based count */
 int      or_heuristic_perms(const or_inst *, int32_t *out, int cap); /* returns count */
 int      or_init(const or_inst *, const or_params *, or_state *st);

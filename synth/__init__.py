@@ -25,9 +25,11 @@ TSP, QAP, KNAPSACK, VRPTW, INTCOLOR, VRPTW_ROWS = 1, 2, 3, 4, 5, 6
 KIND_NAMES = {TSP: "tsp", QAP: "qap", KNAPSACK: "knapsack", VRPTW: "vrptw", INTCOLOR: "intcolor",
               VRPTW_ROWS: "vrptw_rows"}
 
-# permutation 0-4, row level 5-7 (multi-row solutions), binary 8-9, integer 10-11
+# permutation 0-4; ids 5-7: the LNS operators on single-row permutations, the
+# row operators on multi-row solutions; binary 8-9, integer 10-11
 OP_2OPT, OP_SWAP, OP_INSERT, OP_OROPT, OP_3OPT = 0, 1, 2, 3, 4
 OP_ROWSWAP, OP_ROWSPLIT, OP_ROWMERGE = 5, 6, 7
+OP_LNS_SEG, OP_LNS_SCATTER, OP_LNS_GUIDED = 5, 6, 7
 OP_FLIP, OP_SEGFLIP, OP_RESET, OP_SEGRESET = 8, 9, 10, 11
 OP_NAMES = ["2opt", "swap", "insert", "oropt", "3opt", "rowswap", "rowsplit", "rowmerge", "flip", "segflip",
             "reset", "segreset"]
@@ -36,6 +38,8 @@ PERM4_OPS = (1 << OP_2OPT) | (1 << OP_SWAP) | (1 << OP_INSERT) | (1 << OP_OROPT)
 PERM_OPS = PERM4_OPS | (1 << OP_3OPT)
 ROW_OPS = (1 << OP_ROWSWAP) | (1 << OP_ROWSPLIT) | (1 << OP_ROWMERGE)
 ROWS_ALL_OPS = PERM_OPS | ROW_OPS
+LNS_OPS = (1 << OP_LNS_SEG) | (1 << OP_LNS_SCATTER) | (1 << OP_LNS_GUIDED)
+PERM_LNS_OPS = PERM_OPS | LNS_OPS
 BIN_OPS = (1 << OP_FLIP) | (1 << OP_SEGFLIP)
 INT_OPS = (1 << OP_RESET) | (1 << OP_SEGRESET)
 
