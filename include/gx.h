@@ -59,9 +59,10 @@ typedef enum {
 
 /* Operators (paper, Tab. "operators"); bit i of op_mask enables operator id
  * i, and AOS keeps one weight per id.  Ids are contiguous per encoding:
- * permutation 0-4, the multi-row permutation 0-7 (the permutation operators
- * and the row level), binary 8-9, integer 10-11.  (The LNS operators of Sec.
- * "Built-in Operator Hierarchy" are not built.) */
+ * permutation 0-4, plus 5-7 the LNS operators on single-row permutations
+ * (TSP, QAP, VRPTW giant tour) and the row operators on multi-row ones;
+ * binary 8-9, integer 10-11.  op_mask 0 takes every operator of the encoding
+ * but the LNS ones, which run only when named. */
 #define GX_N_OPS 12
 enum {
   GX_OP_2OPT = 1u << 0,    /* element level: segment reversal */
@@ -69,6 +70,18 @@ enum {
   GX_OP_INSERT = 1u << 2,  /* element level: move one element */
   GX_OP_OROPT = 1u << 3,   /* segment level: move a block of 2 or 3 elements, orientation kept */
   GX_OP_3OPT = 1u << 4,    /* segment level: three cuts a < b < c, blocks [a, b) and [b, c) exchanged */
+  /* LNS (single-row permutations; Sec. "Built-in Operator Hierarchy"): a step
+   * destroys L = min(n, 2 + n/16, 64) entries and rebuilds them; its draws
+   * beyond the step's words w1..w3 are word i mod 4 of the Philox4x32-10
+   * block with counter (w1, w2, w3, i/4) and key (0x4C4E5331, 0x4C4E5332).
+   * Initial weights 0.006 / 0.004 / 0.001 and a weight cap of 0.02 / 0.01 /
+   * 0.005 (Tab. weight_preset, n <= 100 / <= 250 / > 250): the EMA update
+   * clamps an LNS weight to [min(w_floor, cap), cap]. */
+  GX_OP_LNS_SEGMENT = 1u << 5, /* shuffle the L entries from a uniform start (Fisher-Yates) */
+  GX_OP_LNS_SCATTER = 1u << 6, /* shuffle the entries at L distinct uniform positions (Floyd's sampling) */
+  GX_OP_LNS_GUIDED = 1u << 7,  /* the L entries from a uniform start in order of their heuristic key
+                                  (row sums of the first data matrix), ascending, or descending when
+                                  the top bit of w2 is set; ties by entry */
   /* row level (GX_VRPTW_ROWS); p is drawn uniformly among the entries before
    * the final marker and names the row holding it (its marker included) */
   GX_OP_ROWSWAP = 1u << 5,  /* that row and the next trade places (nothing for the last row) */

@@ -125,12 +125,24 @@ gx_status to_host(gx_ctx *c, const gx_instance_desc *d, const int32_t *src, size
   return GX_OK;
 }
 
+// the operators a job on this instance takes when op_mask is 0
 uint32_t encoding_ops(const DevInst &h) {
   if (h.kind == KKNAP) return (1u << OFLIP) | (1u << OSFLIP);
   if (h.kind == KCOLOR) return (1u << ORESET) | (1u << OSRESET);
   const uint32_t perm = (1u << O2OPT) | (1u << OSWAP) | (1u << OINS) | (1u << OOROPT) | (1u << O3OPT);
   if (h.rows) return perm | (1u << OROWSWAP) | (1u << OROWSPLIT) | (1u << OROWMERGE);
   return perm;
+}
+// the operators op_mask may name: single-row permutations add the LNS
+// operators, which are taken only when named
+uint32_t allowed_ops(const DevInst &h) {
+  const bool single = !h.rows && (h.kind == KTSP || h.kind == KQAP || h.kind == KVRP);
+  return encoding_ops(h) | (single ? kLnsMask : 0u);
+}
+// Tab. weight_preset, LNS cap (Q16) by scale; 0 where ids 5-7 are not LNS operators
+uint32_t lns_cap_of(const DevInst &h) {
+  if (h.rows || !(h.kind == KTSP || h.kind == KQAP || h.kind == KVRP)) return 0;
+  return h.n <= 100 ? 1311u : (h.n <= 250 ? 655u : 328u);
 }
 
 void free_bufs(std::vector<void *> &b) {
@@ -600,7 +612,7 @@ uint32_t job_lds(const InstInfo &ii, uint32_t stage, uint32_t op_mask) {
 gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJob &h, uint32_t P_auto,
                    uint32_t lds_limit) {
   if (!p) return fail(c, GX_E_INVALID, "null parameters");
-  const uint32_t mask = p->op_mask ? (p->op_mask & encoding_ops(ii.h)) : encoding_ops(ii.h);
+  const uint32_t mask = p->op_mask ? (p->op_mask & allowed_ops(ii.h)) : encoding_ops(ii.h);
   if (!mask) return fail(c, GX_E_INVALID, "op_mask enables no operator of this encoding");
   if (p->alpha_q32 == 0) return fail(c, GX_E_INVALID, "alpha_q32 is required");
   const uint32_t C = p->candidates ? p->candidates : 128;
@@ -666,6 +678,7 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
   for (int i = 0; i < kOps; ++i) h.init_w[i] = p->init_weight_q16[i];
   h.lex_levels = (uint32_t)ii.h.lex_levels;
   h.rows = (uint32_t)ii.h.rows;
+  h.lns_cap = lns_cap_of(ii.h);
   return GX_OK;
 }
 
@@ -873,7 +886,7 @@ gx_status gx_autosize_population(gx_ctx *c, const gx_instance *in, const gx_solv
   if (!c || !in || !out) return fail(c, GX_E_INVALID, "null argument");
   const InstInfo ii = info_of(in);
   const uint32_t stage = resolve_stage(ii, p ? p->staging : 0);
-  const uint32_t mask = p && p->op_mask ? (p->op_mask & encoding_ops(in->h)) : encoding_ops(in->h);
+  const uint32_t mask = p && p->op_mask ? (p->op_mask & allowed_ops(in->h)) : encoding_ops(in->h);
   const uint32_t lds = job_lds(ii, stage, mask);
   int occ = 0;
   HIPCHK(c, gxk::occupancy_plain(in->h.kind, evolve_variant(in->h.kind, stage, mask, in->h.lex_levels, in->h.rows), lds, &occ));

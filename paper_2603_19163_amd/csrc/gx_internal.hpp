@@ -21,21 +21,27 @@ constexpr int kMaxCoord = 1 << 14;
 constexpr int64_t kDeltaBias = int64_t(1) << 47;   // argmin key = ((delta + bias) << 16) | t
 
 enum Kind : int32_t { KTSP = 1, KQAP = 2, KKNAP = 3, KVRP = 4, KCOLOR = 5 };
-// operator ids, contiguous per encoding: permutation 0-4, the row operators
-// of multi-row solutions 5-7, binary 8-9, integer 10-11
+// operator ids, contiguous per encoding: permutation 0-4; ids 5-7 are the
+// LNS operators of single-row permutations and the row operators of
+// multi-row solutions; binary 8-9, integer 10-11
 enum Op : int32_t { O2OPT = 0, OSWAP = 1, OINS = 2, OOROPT = 3, O3OPT = 4, OROWSWAP = 5, OROWSPLIT = 6,
                     OROWMERGE = 7, OFLIP = 8, OSFLIP = 9, ORESET = 10, OSRESET = 11 };
+enum LnsOp : int32_t { OLNSSEG = 5, OLNSSCAT = 6, OLNSGUIDE = 7 };
+constexpr uint32_t kLnsMask = (1u << OLNSSEG) | (1u << OLNSSCAT) | (1u << OLNSGUIDE);
+constexpr int kLnsMax = 64;   // most entries an LNS step destroys
 constexpr int kPermOps = 5;
 enum Stage : int32_t { SAUTO = 0, SLDS16 = 1, SLDSXY = 2, SGLB16 = 3, SGLB32 = 4 };
 // Evolve-kernel variant: the staging, plus kVarX3 when a permutation job's
-// operator set holds 3-opt (its loops are compiled apart from the others, so
-// that jobs without it carry none of its branches or wider counters), plus
+// operator set holds 3-opt or, on single-row permutations, an LNS operator
+// (their loops are compiled apart from the others, so that jobs without them
+// carry none of their branches or wider counters), plus
 // kVarLex for a VRPTW instance in the lexicographic mode, plus kVarRows for a
 // VRPTW instance in the multi-row form.
 constexpr int kVarX3 = 8, kVarLex = 16, kVarRows = 32;
 inline int evolve_variant(int kind, uint32_t stage, uint32_t op_mask, uint32_t lex_levels, uint32_t rows) {
   const bool perm = kind == KTSP || kind == KQAP || kind == KVRP;
-  return (int)stage | ((perm && (op_mask & (1u << O3OPT))) ? kVarX3 : 0) |
+  const bool wide = (op_mask & (1u << O3OPT)) || (!rows && (op_mask & kLnsMask));
+  return (int)stage | ((perm && wide) ? kVarX3 : 0) |
          ((kind == KVRP && lex_levels) ? kVarLex : 0) | ((kind == KVRP && rows) ? kVarRows : 0);
 }
 
@@ -112,7 +118,8 @@ struct DevJob {
   int64_t *cur_v, *best_v;    // lexicographic mode: P x 4 objective vectors (else null)
   int64_t *pool_v;            // lexicographic mode: Q x 4 vectors of the initial pool
   int64_t best_out_f;
-  int32_t best_idx, pad4;
+  int32_t best_idx;
+  uint32_t lns_cap;           // Q16 weight cap of the LNS operators (0: ids 5-7 are not LNS here)
 };
 
 // Permutations of up to kOneBufferN elements are rewritten through the first
@@ -126,7 +133,20 @@ constexpr int kOneBufferN = 1536;
 // steps) followed by the solution and instance data (rows: the rows of a
 // multi-row VRPTW solution, whose n entries include one marker per row).
 constexpr uint32_t kTables = 3968, kTablesX3 = 4736;
-inline uint32_t lds_bytes_for(int kind, int n, int var, int rows) {
+// LNS scratch per wave, at the end of the workgroup's LDS in the variants
+// that may draw LNS steps: three step tables (positions, sources, length)
+// and the candidate's entries
+struct LnsTab {
+  uint16_t pos[kLnsMax];
+  uint8_t src[kLnsMax];
+  int32_t L;
+  int32_t pad[3];
+};
+__host__ __device__ inline uint32_t lns_wave_bytes(int n) { return 3u * (uint32_t)sizeof(LnsTab) + ((2u * n + 15u) & ~15u); }
+__host__ __device__ inline bool lns_variant(int kind, int var) {
+  return (var & kVarX3) && !(var & kVarRows) && (kind == KTSP || kind == KQAP || kind == KVRP);
+}
+__host__ __device__ inline uint32_t lds_core_bytes(int kind, int n, int var, int rows) {
   auto al = [](uint32_t b) { return (b + 15u) & ~15u; };
   const int stage = var & 7;
   const uint32_t un = (uint32_t)n, tables = (var & kVarX3) ? kTablesX3 : kTables;
@@ -152,6 +172,10 @@ inline uint32_t lds_bytes_for(int kind, int n, int var, int rows) {
     }
     default: return tables + al(2 * un) + al(4 * (un + 1));   // + adjacency, added by the caller
   }
+}
+__host__ __device__ inline uint32_t lds_bytes_for(int kind, int n, int var, int rows) {
+  const uint32_t lns = lns_variant(kind, var) ? 2u * lns_wave_bytes(n) : 0u;
+  return lds_core_bytes(kind, n, var, rows) + lns;
 }
 
 }  // namespace gx

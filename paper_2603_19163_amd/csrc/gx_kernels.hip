@@ -113,7 +113,9 @@ struct Step {
 // u < cumsum_i.  An encoding's operators are contiguous ids (permutations 0-4,
 // multi-row permutations 0-7, binary 8-9, integer 10-11) and the others have
 // weight 0, so only the encoding's own cumulative sums matter.
-template <int ENC>
+// (X3: the wide variant of a single-row permutation, whose ids 5-7 are the
+// LNS operators)
+template <int ENC, bool X3>
 __device__ __forceinline__ int pick_op(uint32_t u16, const Uni &U) {
   const uint32_t u = (uint32_t)(((uint64_t)u16 * U.sw) >> 16);
   if (ENC == 1 || ENC == 2) {
@@ -121,7 +123,7 @@ __device__ __forceinline__ int pick_op(uint32_t u16, const Uni &U) {
     return lo + (U.cw[0] <= u);
   }
   int op = (U.cw[0] <= u) + (U.cw[1] <= u) + (U.cw[2] <= u) + (U.cw[3] <= u);
-  if (ENC == 3) op += (U.cw[4] <= u) + (U.cw[5] <= u) + (U.cw[6] <= u);
+  if (ENC == 3 || X3) op += (U.cw[4] <= u) + (U.cw[5] <= u) + (U.cw[6] <= u);
   return op;
 }
 
@@ -142,6 +144,10 @@ template <int ENC>
 constexpr int enc_hi() { return ENC == 0 ? O3OPT : (ENC == 3 ? OROWMERGE : enc_lo<ENC>() + 1); }
 template <int ENC>
 constexpr bool enc_perm() { return ENC == 0 || ENC == 3; }
+// last operator id a kernel variant may draw: the wide variant of a
+// single-row permutation adds the LNS operators (ids 5-7)
+template <int ENC, bool X3>
+constexpr int enc_top() { return (ENC == 0 && X3) ? OLNSGUIDE : enc_hi<ENC>(); }
 
 // X3: the operator set holds 3-opt (the loops without it are compiled
 // without its branches).  A row operator's step keeps only its drawn position
@@ -204,14 +210,14 @@ __device__ __forceinline__ int sample(const Uni &U, uint32_t g, uint32_t sol, ui
   uint32_t r[4];
   philox(g, sol, t << 2, U.key, U.k0, U.k1, r);
   const int k = pick_k(r[0], U);
-  st[0] = make_step<ENC, X3>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+  st[0] = make_step<ENC, X3>(pick_op<ENC, X3>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
   if (k > 1) {
     philox(g, sol, (t << 2) | 1u, U.key, U.k0, U.k1, r);
-    st[1] = make_step<ENC, X3>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+    st[1] = make_step<ENC, X3>(pick_op<ENC, X3>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
   }
   if (k > 2) {
     philox(g, sol, (t << 2) | 2u, U.key, U.k0, U.k1, r);
-    st[2] = make_step<ENC, X3>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+    st[2] = make_step<ENC, X3>(pick_op<ENC, X3>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
   }
   return k;
 }
@@ -238,14 +244,194 @@ __device__ __forceinline__ int chain(const Step *st, int m, int p) {
   return p;
 }
 
+// ------------------------------------------------------------ LNS steps
+// The LNS operators (paper, Sec. "Built-in Operator Hierarchy"; ids 5-7 of a
+// single-row permutation) destroy L(n) = min(n, 2 + n / 16, 64) entries and
+// rebuild them: the segment shuffle permutes the entries from a uniform
+// start, the scatter shuffle the entries at L distinct uniform positions
+// (Floyd's sampling), the guided rebuild puts the segment's entries in order
+// of their heuristic key (the row sums of the heuristic initialisation),
+// ascending or, when the top bit of the step's second word is set,
+// descending, ties by entry.  Draws beyond the step's three words are word
+// i mod 4 of the Philox4x32-10 block with counter (w1, w2, w3, i / 4) and a
+// fixed key.  A drawn step becomes a table in LDS: the L positions it touches
+// in increasing order and, for each, the index of the position its new entry
+// comes from.  Candidates with such a step are rare (their weights stay
+// below 2 %); the whole wave computes their objectives from their entries,
+// in place of the per-lane delta, and applies them when they win.
+__device__ __forceinline__ bool is_lns(int op) { return op >= OLNSSEG && op <= OLNSGUIDE; }
+__device__ __forceinline__ int lns_len(int n) { return min(min(2 + n / 16, kLnsMax), n); }
+__device__ __forceinline__ uint32_t lns_word(const uint32_t *w, int i) {
+  uint32_t r[4];
+  philox(w[0], w[1], w[2], (uint32_t)(i >> 2), 0x4C4E5331u, 0x4C4E5332u, r);
+  return r[i & 3];
+}
+// the position the entry at p after an LNS step comes from
+__device__ __forceinline__ int lns_psi(const LnsTab &T, bool scat, int p) {
+  int i;
+  if (!scat) {
+    i = p - (int)T.pos[0];
+    if ((uint32_t)i >= (uint32_t)T.L) return p;
+  } else {
+    int lo = 0, hi = T.L;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if ((int)T.pos[mid] < p) lo = mid + 1;
+      else hi = mid;
+    }
+    if (lo >= T.L || (int)T.pos[lo] != p) return p;
+    i = lo;
+  }
+  return T.pos[T.src[i]];
+}
+// chain() with LNS steps read from their tables
+__device__ __forceinline__ int lchain(const Step *st, int m, int p, const LnsTab *tabs) {
+#pragma unroll
+  for (int j = 2; j >= 0; --j)
+    if (j < m) p = is_lns(st[j].op) ? lns_psi(tabs[j], st[j].op == OLNSSCAT, p) : psi(st[j], p);
+  return p;
+}
+// the table of LNS step m (op, words w) of a candidate whose earlier steps
+// are st[0..m-1] (their tables built); one lane.  tmp: L entries of scratch.
+__device__ void lns_make(LnsTab &T, int op, const uint32_t *w, int n, const uint16_t *cur, const Step *st,
+                         const LnsTab *tabs, int m, const int64_t *hkey, uint16_t *tmp) {
+  const int L = n >= 2 ? lns_len(n) : 0;
+  T.L = L < 2 ? 0 : L;
+  if (L < 2) return;
+  if (op == OLNSSCAT) {
+    for (int j = n - L; j < n; ++j) {
+      const int r = (int)rmap(lns_word(w, j - n + L), (uint32_t)(j + 1));
+      bool have = false;
+      for (int q = 0; q < j - n + L; ++q) have |= (int)T.pos[q] == r;
+      T.pos[j - n + L] = (uint16_t)(have ? j : r);
+    }
+    for (int i = 1; i < L; ++i) {   // increasing order
+      const uint16_t v = T.pos[i];
+      int q = i;
+      for (; q > 0 && T.pos[q - 1] > v; --q) T.pos[q] = T.pos[q - 1];
+      T.pos[q] = v;
+    }
+  } else {
+    const int a = (int)rmap(w[0], (uint32_t)(n - L + 1));
+    for (int i = 0; i < L; ++i) T.pos[i] = (uint16_t)(a + i);
+  }
+  for (int i = 0; i < L; ++i) T.src[i] = (uint8_t)i;
+  if (op == OLNSGUIDE) {   // sources ordered by (key, entry) of the entries before the step
+    const bool desc = (w[1] >> 31) != 0;
+    for (int i = 0; i < L; ++i) tmp[i] = cur[lchain(st, m, T.pos[i], tabs)];
+    for (int i = 1; i < L; ++i) {
+      const uint8_t x = T.src[i];
+      const int ex = tmp[x];
+      const int64_t kx = desc ? -hkey[ex] : hkey[ex];
+      int q = i;
+      for (; q > 0; --q) {
+        const int ep = tmp[T.src[q - 1]];
+        const int64_t kp = desc ? -hkey[ep] : hkey[ep];
+        if (kp > kx || (kp == kx && ep > ex)) T.src[q] = T.src[q - 1];
+        else break;
+      }
+      T.src[q] = x;
+    }
+    return;
+  }
+  const int base = op == OLNSSCAT ? L : 0;
+  for (int i = L - 1; i >= 1; --i) {   // Fisher-Yates on the sources
+    const int j = (int)rmap(lns_word(w, base + L - 1 - i), (uint32_t)(i + 1));
+    const uint8_t t = T.src[i];
+    T.src[i] = T.src[j];
+    T.src[j] = t;
+  }
+}
+
+// One wave's LNS scratch: the step tables, the candidate's entries, and the
+// heuristic keys of the entries (in HBM)
+struct LnsCtx {
+  LnsTab *tabs;
+  uint16_t *y;
+  const int64_t *hkey;
+};
+
+__device__ __forceinline__ bool lns_in(const Step *st, int k) {
+  bool h = false;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) h |= m < k && is_lns(st[m].op);
+  return h;
+}
+// candidate tl of the chunk has an LNS step among its k (op bytes of the tables)
+__device__ __forceinline__ bool lns_drawn(const uint8_t *sop, uint32_t tl, int k) {
+  bool h = false;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) h |= m < k && is_lns((int)(sop[3 * tl + m] & 7u));
+  return h;
+}
+// the tables of the LNS steps of candidate t (steps st, k of them) of
+// generation g, built by lane 0 of the calling wave
+template <bool X3>
+__device__ __forceinline__ void lns_tables(const Uni &U, uint32_t g, uint32_t sol, uint32_t t, const Step *st, int k,
+                                           int n, const uint16_t *cur, const LnsCtx &lx) {
+  if (lane_id() == 0) {
+    for (int m = 0; m < k; ++m) {
+      if (!is_lns(st[m].op)) continue;
+      uint32_t r[4];
+      philox(g, sol, (t << 2) | (uint32_t)m, U.key, U.k0, U.k1, r);
+      lns_make(lx.tabs[m], st[m].op, r + 1, n, cur, st, lx.tabs, m, lx.hkey, lx.y);
+    }
+  }
+  wave_sync();
+}
+// the hull of the positions a candidate with LNS steps changes
+__device__ __forceinline__ void lns_range(const Step *st, int k, const LnsTab *tabs, int &lo, int &hi) {
+  lo = 0x7FFFFFFF;
+  hi = -1;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    if (m >= k) continue;
+    if (is_lns(st[m].op)) {
+      if (tabs[m].L) {
+        lo = min(lo, (int)tabs[m].pos[0]);
+        hi = max(hi, (int)tabs[m].pos[tabs[m].L - 1]);
+      }
+    } else {
+      const bool mv = st[m].op >= OINS;
+      lo = min(lo, mv ? min(st[m].a, st[m].b) : st[m].a);
+      hi = max(hi, mv ? max(st[m].a, st[m].b) + st[m].c - 1 : st[m].b);
+    }
+  }
+}
+// objective of candidate t of generation g (which holds an LNS step) by the
+// whole wave: its entries into lx.y, then obj(y), the same on every lane
+template <bool X3, class OBJ>
+__device__ __forceinline__ auto lns_eval(const Uni &U, uint32_t g, uint32_t sol, uint32_t t, int n,
+                                         const uint16_t *cur, const LnsCtx &lx, const OBJ &obj) {
+  Step st[3];
+  const int k = sample<0, X3>(U, g, sol, t, st);
+  lns_tables<X3>(U, g, sol, t, st, k, n, cur, lx);
+  for (int p = (int)lane_id(); p < n; p += kWave) lx.y[p] = cur[lchain(st, k, p, lx.tabs)];
+  wave_sync();
+  return obj(lx.y);
+}
+// apply the winning candidate t (steps st, with an LNS step) to cur through
+// tmp; returns the changed range.  Every wave of the workgroup calls it.
+template <bool X3>
+__device__ __forceinline__ void lns_apply(const Uni &U, uint32_t g, uint32_t sol, uint32_t t, const Step *st, int k,
+                                          int n, uint16_t *cur, uint16_t *tmp, const LnsCtx &lx, int &lo, int &hi) {
+  lns_tables<X3>(U, g, sol, t, st, k, n, cur, lx);
+  lns_range(st, k, lx.tabs, lo, hi);
+  for (int p = lo + (int)lane_id(); p <= hi; p += kWave) tmp[p] = cur[lchain(st, k, p, lx.tabs)];
+  __syncthreads();
+  for (int p = lo + (int)lane_id(); p <= hi; p += kWave) cur[p] = tmp[p];
+  __syncthreads();
+}
+
+
 // ------------------------------------------------------------ statistics
 struct LStats {
   uint32_t u[kOps], v[kOps], uk[3], vk[3];
 };
 
-template <int ENC>
+template <int ENC, bool X3>
 __device__ __forceinline__ void credit(LStats &S, const Step *st, int k, bool imp) {
-  constexpr int lo = enc_lo<ENC>(), hi = enc_hi<ENC>();
+  constexpr int lo = enc_lo<ENC>(), hi = enc_top<ENC, X3>();
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     if (m < k) {
@@ -743,6 +929,15 @@ struct VrpK {
     if constexpr (ROWS) resolve_rows(st, k);   // every lane reads the same solution: the same steps
     perm_apply(cur, nxt, st, k);
   }
+  __device__ __forceinline__ void refresh(int, int) {}
+  // parts of the solution with entries y (LNS candidates; every lane the same)
+  __device__ __forceinline__ VrpParts parts_of(const uint16_t *y) const {
+    VrpK k2 = *this;
+    k2.cur = (uint16_t *)y;
+    const Step none[3] = {};
+    return k2.parts(none, 0);
+  }
+  __device__ __forceinline__ int64_t objective_of(const uint16_t *y) const { return vrp_objective(I, parts_of(y)); }
   __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
 };
 
@@ -935,7 +1130,7 @@ __device__ __forceinline__ uint32_t draw_chunk(const TspScratch &W, const Uni &U
       uint32_t w[4];
       philox_lane(g, sol, (c0 + tl) << 2, U.key, U.k0, U.k1, w);
       kk[rr] = pick_k(w[0], U);
-      const Step st = make_step<ENC, X3>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
+      const Step st = make_step<ENC, X3>(pick_op<ENC, X3>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
       store_step<ENC, X3>(W, 3 * tl, st, (uint32_t)kk[rr] << 6);
       if (first) first[rr] = st;
       if constexpr (RN == 2) W.del()[tl] = 0;
@@ -956,7 +1151,7 @@ __device__ __forceinline__ uint32_t draw_chunk(const TspScratch &W, const Uni &U
     const uint32_t e = dl[j], tl = e & 0xFFu, m = e >> 8;
     uint32_t w[4];
     philox_lane(g, sol, ((c0 + tl) << 2) | m, U.key, U.k0, U.k1, w);
-    const Step st = make_step<ENC, X3>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
+    const Step st = make_step<ENC, X3>(pick_op<ENC, X3>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
     store_step<ENC, X3>(W, 3 * tl + m, st, 0u);
   }
   __syncthreads();
@@ -1134,13 +1329,14 @@ __device__ __forceinline__ void fold_ops(uint32_t *u, uint32_t *v, OpCount<W64> 
 template <bool X3, class DF>
 __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *el, int n, const DF &D, const TspScratch &W,
                                         const Uni &U, int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1,
-                                        uint64_t &T, int64_t &f, int64_t &bf, LStats &S, uint32_t &nacc) {
+                                        uint64_t &T, int64_t &f, int64_t &bf, LStats &S, uint32_t &nacc,
+                                        const LnsCtx &lx) {
   const uint32_t lane = lane_id();
   // Per-lane use and improvement counts of the operators and of k = 1..3
   // in byte fields (operator o at bits 8o, k at bits 8(k-1)); a chunk of
   // candidates adds at most 6 to a field of a lane, so the fields are folded
   // into the wave-wide counts of S every 42 chunks and at the end.
-  constexpr int kNops = X3 ? kPermOps : 4;
+  constexpr int kNops = X3 ? 8 : 4;   // the wide variant: 3-opt and the LNS operators
   OpCount<X3> cu_op = 0, cv_op = 0;
   uint32_t cu_k = 0, cv_k = 0, since_fold = 0;
   // The wave-wide counts live in the unused tail of the pattern-list table
@@ -1205,12 +1401,36 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
         }
       }
       __syncthreads();
+      // ---- candidates with an LNS step (wide variant): their objectives by
+      // the whole wave, in place of the per-lane delta
+      int64_t lns_d[2] = {0, 0};
+      uint32_t lns_c = 0;   // bit r: lane's candidate of round r holds an LNS step
+      if constexpr (X3) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const uint32_t tl = r * kWave + lane;
+          const bool has = tl < cn && (is_lns(s0[r].op) || (kk[r] > 1 && lns_drawn(W.sop(), tl, kk[r])));
+          for (unsigned long long mk = __ballot(has); mk; mk &= mk - 1) {
+            const uint32_t t = (uint32_t)__builtin_ctzll(mk);
+            const int64_t fn = lns_eval<X3>(U, g, sol, c0 + r * kWave + t, n, cur, lx, [&](const uint16_t *y) {
+              int64_t acc = 0;
+              for (int p = (int)lane; p < n; p += kWave) acc += D(y[p], y[p + 1 == n ? 0 : p + 1]);
+              return wave_sum64(acc);
+            });
+            if (lane == t) {
+              lns_d[r] = fn - f;
+              lns_c |= 1u << r;
+            }
+          }
+        }
+      }
       // ---- keys and per-lane statistics (byte counters, folded into S below)
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const uint32_t tl = r * kWave + lane;
         const bool valid = tl < cn;
-        const int64_t d = valid ? (int64_t)(d0[r] + W.del()[tl]) : 0;
+        int64_t d = valid ? (int64_t)(d0[r] + W.del()[tl]) : 0;
+        if constexpr (X3) d = ((lns_c >> r) & 1u) ? lns_d[r] : d;
         if (U.credit == 0 && valid) {
           const bool imp = d < 0;
 #pragma unroll
@@ -1273,12 +1493,25 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
         }
       }
       int lo, hi;
-      move_range(st, k, lo, hi);
-      if (*best_is_cur && f + ds >= bf) {
-        perm_store(cur, n, best_row);
-        *best_is_cur = 0u;
+      if constexpr (X3) {
+        if (*best_is_cur && f + ds >= bf) {
+          perm_store(cur, n, best_row);
+          *best_is_cur = 0u;
+        }
+        if (lns_in(st, k)) {
+          lns_apply<X3>(U, g, sol, ts, st, k, n, cur, nxt, lx, lo, hi);
+        } else {
+          move_range(st, k, lo, hi);
+          perm_apply(cur, nxt, st, k, lo, hi);
+        }
+      } else {
+        move_range(st, k, lo, hi);
+        if (*best_is_cur && f + ds >= bf) {
+          perm_store(cur, n, best_row);
+          *best_is_cur = 0u;
+        }
+        perm_apply(cur, nxt, st, k, lo, hi);
       }
-      perm_apply(cur, nxt, st, k, lo, hi);
       if constexpr (DF::kEdges) {
         if (lo <= hi) {
           edges_fill(el, cur, n, D, lo - 1, hi);
@@ -1557,6 +1790,10 @@ struct QapK {
     int lo, hi;
     move_range(st, k, lo, hi);
     perm_apply(cur, nxt, st, k, lo, hi);
+    refresh(lo, hi);
+  }
+  // DX and H after the solution changed on [lo, hi]
+  __device__ __forceinline__ void refresh(int lo, int hi) {
     if (lo > hi) return;
     const int v = (int)lane_id();
     const bool w0 = threadIdx.x < (uint32_t)kWave;
@@ -1604,6 +1841,15 @@ struct QapK {
       __syncthreads();
       build_sums();
     }
+  }
+  // objective of the solution with entries y (LNS candidates): the wave's sum
+  __device__ __forceinline__ int64_t objective_of(const uint16_t *y) const {
+    int64_t acc = 0;
+    for (int a = (int)lane_id(); a < n; a += kWave) {
+      const int16_t *Fa = F + a * np, *Dr = Dg + (int)y[a] * n;
+      for (int b = 0; b < n; ++b) acc += (int64_t)Fa[b] * Dr[y[b]];
+    }
+    return wave_sum64(acc);
   }
   __device__ __forceinline__ void store(int32_t *dst) const { perm_store(cur, n, dst); }
 };
@@ -1676,7 +1922,7 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
     if (acc) {
       Step st[3];
       const int k = sample<ENC, X3>(U, g, sol, ts, st);
-      if (U.credit == 1) credit<ENC>(S, st, k, ds < 0);   // the same on every lane
+      if (U.credit == 1) credit<ENC, X3>(S, st, k, ds < 0);   // the same on every lane
       if (best_is_cur && f + ds >= bf) {
         kd.store(best_row);
         best_is_cur = false;
@@ -1705,12 +1951,12 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
 template <bool X3, class KD>
 __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Uni &U, int32_t *best_row, uint32_t sol,
                                            uint32_t g0, uint32_t g1, uint64_t &T, int64_t &f, int64_t &bf, LStats &S,
-                                           uint32_t &nacc, unsigned long long *xk) {
+                                           uint32_t &nacc, unsigned long long *xk, const LnsCtx &lx) {
   constexpr int ENC = KD::ENC;
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
-  // the multi-row encoding's eight operators take the 64-bit counters of 3-opt
+  // the wide variant and the multi-row encoding count eight operators in 64 bits
   constexpr bool W64 = X3 || ENC == 3;
-  constexpr int nf = ENC == 3 ? 8 : (X3 ? kPermOps : 4);
+  constexpr int nf = W64 ? 8 : 4;
   OpCount<W64> cu = 0, cv = 0;
   uint32_t cuk = 0, cvk = 0, since_fold = 0;
   bool best_is_cur = false;   // the best-so-far solution is the current one, not yet written
@@ -1724,7 +1970,15 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
       const bool valid = tl < cn;
       if (__ballot(valid)) {
         const int k = valid ? kk[0] : 0;
-        const int64_t d = kd.template delta_round<X3>(W, (int)tl, k, f);
+        int64_t d = kd.template delta_round<X3>(W, (int)tl, k, f);
+        if constexpr (X3 && ENC == 0) {   // candidates with an LNS step: by the whole wave
+          for (unsigned long long mk = __ballot(valid && lns_drawn(W.sop(), tl, k)); mk; mk &= mk - 1) {
+            const uint32_t t = (uint32_t)__builtin_ctzll(mk);
+            const int64_t fn = lns_eval<X3>(U, g, sol, c0 + wv * kWave + t, kd.n, kd.cur, lx,
+                                            [&](const uint16_t *y) { return kd.objective_of(y); });
+            if (lane == t) d = fn - f;
+          }
+        }
         if (valid) {
           if (U.credit == 0) {   // the steps again from the tables: fewer registers live across the round
             Step st[3];
@@ -1755,12 +2009,22 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
     if (acc) {
       Step st[3];
       const int k = sample<ENC, X3>(U, g, sol, ts, st);
-      if (U.credit == 1 && wv == 0) credit<ENC>(S, st, k, ds < 0);   // the same on every lane of wave 0
+      if (U.credit == 1 && wv == 0) credit<ENC, X3>(S, st, k, ds < 0);   // the same on every lane of wave 0
       if (best_is_cur && f + ds >= bf) {   // wave 0 reads the solution before the move's first barrier
         if (wv == 0) kd.store(best_row);
         best_is_cur = false;
       }
-      kd.apply(st, k);
+      if constexpr (X3 && ENC == 0) {
+        if (lns_in(st, k)) {
+          int lo, hi;
+          lns_apply<X3>(U, g, sol, ts, st, k, kd.n, kd.cur, kd.nxt, lx, lo, hi);
+          kd.refresh(lo, hi);
+        } else {
+          kd.apply(st, k);
+        }
+      } else {
+        kd.apply(st, k);
+      }
       f += ds;
       nacc += wv == 0;
       if (f < bf) {
@@ -1791,10 +2055,10 @@ template <bool X3, class KD>
 __device__ __forceinline__ void lex_rounds(KD &kd, const TspScratch &W, const Uni &U, const LexCfg &L,
                                            int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1, uint64_t &T,
                                            int64_t &f, int64_t &bf, Vec4 &cv, Vec4 &bsv, LStats &S, uint32_t &nacc,
-                                           int64_t *vbuf) {
+                                           int64_t *vbuf, const LnsCtx &lx) {
   constexpr int ENC = KD::ENC;
   constexpr bool W64 = X3 || ENC == 3;
-  constexpr int nf = ENC == 3 ? 8 : (X3 ? kPermOps : 4);
+  constexpr int nf = W64 ? 8 : 4;
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
   OpCount<W64> cu = 0, cvc = 0;
   uint32_t cuk = 0, cvk = 0, since_fold = 0;
@@ -1808,12 +2072,23 @@ __device__ __forceinline__ void lex_rounds(KD &kd, const TspScratch &W, const Un
       int kk[1];
       draw_chunk<ENC, X3, 1>(W, U, g, sol, c0, cn, kk, wv);
       const uint32_t tl = wv * kWave + lane;
+      Step st[3];
+      Vec4 v = {};
       if (tl < cn) {
-        Step st[3];
         st[0] = load_step<ENC, X3>(W, (int)tl, 0);
         st[1] = kk[0] > 1 ? load_step<ENC, X3>(W, (int)tl, 1) : st[0];
         st[2] = kk[0] > 2 ? load_step<ENC, X3>(W, (int)tl, 2) : st[0];
-        const Vec4 v = lex_vector(kd.parts(st, kk[0]), kd.veh, L);
+        v = lex_vector(kd.parts(st, kk[0]), kd.veh, L);
+      }
+      if constexpr (X3 && ENC == 0) {   // candidates with an LNS step: by the whole wave
+        for (unsigned long long mk = __ballot(tl < cn && lns_drawn(W.sop(), tl, kk[0])); mk; mk &= mk - 1) {
+          const uint32_t t = (uint32_t)__builtin_ctzll(mk);
+          const Vec4 vn = lns_eval<X3>(U, g, sol, c0 + wv * kWave + t, kd.n, kd.cur, lx,
+                                       [&](const uint16_t *y) { return lex_vector(kd.parts_of(y), kd.veh, L); });
+          if (lane == t) v = vn;
+        }
+      }
+      if (tl < cn) {
         if (U.credit == 0) credit_bytes<ENC, W64>(cu, cvc, cuk, cvk, st, kk[0], lex_better(v, cv, L));
         store_vec(vbuf + 4 * (size_t)tl, v);
       }
@@ -1840,13 +2115,22 @@ __device__ __forceinline__ void lex_rounds(KD &kd, const TspScratch &W, const Un
     if (acc) {
       Step st[3];
       const int k = sample<ENC, X3>(U, g, sol, bt, st);
-      if (U.credit == 1 && wv == 0) credit<ENC>(S, st, k, lex_better(bv, cv, L));
+      if (U.credit == 1 && wv == 0) credit<ENC, X3>(S, st, k, lex_better(bv, cv, L));
       const bool new_best = lex_better(bv, bsv, L);
       if (best_is_cur && !new_best) {   // wave 0 reads the solution before the move's first barrier
         if (wv == 0) kd.store(best_row);
         best_is_cur = false;
       }
-      kd.apply(st, k);
+      if constexpr (X3 && ENC == 0) {
+        if (lns_in(st, k)) {
+          int lo, hi;
+          lns_apply<X3>(U, g, sol, bt, st, k, kd.n, kd.cur, kd.nxt, lx, lo, hi);
+        } else {
+          kd.apply(st, k);
+        }
+      } else {
+        kd.apply(st, k);
+      }
       cv = bv;
       f = bv.v[0] + bv.v[1];
       nacc += wv == 0;
@@ -1878,14 +2162,18 @@ __device__ __forceinline__ uint64_t udiv_q24(uint64_t num, uint64_t den) {
 
 // Eq. ema per enabled operator and per K-step, clamp to [floor, 1], normalise;
 // stagnation of the instance best resets the K-step weights (Alg. 2).
+// cap: the LNS weight cap (Tab. weight_preset) of ids 5-7, 0 when they are not
+// LNS operators; an LNS weight is clamped to [min(floor, cap), cap]
 __device__ __forceinline__ void ema_group(uint32_t *w, const unsigned long long *u, const unsigned long long *v, uint32_t mask,
-                          int cnt, uint32_t A, uint32_t FL) {
+                          int cnt, uint32_t A, uint32_t FL, uint32_t cap) {
   uint64_t s = 0;
   for (int i = 0; i < cnt; ++i) {
     if (!(mask & (1u << i))) continue;
     const uint64_t r = udiv_q24((uint64_t)v[i] << 16, u[i] + 1);
     uint64_t nw = ((uint64_t)A * w[i] + (uint64_t)(65536 - A) * (r + FL)) >> 16;
     nw = nw < FL ? FL : (nw > 65536 ? 65536 : nw);
+    // an LNS weight: [min(floor, cap), cap], i.e. the clamp above, then at most cap
+    if (cap && ((kLnsMask >> i) & 1u)) nw = nw > cap ? cap : nw;
     w[i] = (uint32_t)nw;
     s += nw;
   }
@@ -1906,9 +2194,9 @@ __device__ __forceinline__ void ema_group(uint32_t *w, const unsigned long long 
 // the rows after the kernel boundary.
 constexpr int kCountSlots = 2 * kOps + 7;   // uses, improvements per operator and per k, accepted
 
-template <int ENC, bool UNIFORM>
+template <int ENC, bool UNIFORM, bool X3>
 __device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LStats &S, uint32_t nacc, int64_t bf) {
-  constexpr int lo = enc_lo<ENC>(), hi = enc_hi<ENC>();
+  constexpr int lo = enc_lo<ENC>(), hi = enc_top<ENC, X3>();
   const uint32_t lane = lane_id();
   uint32_t mine = 0;
 #pragma unroll
@@ -2240,7 +2528,7 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
     w = J->w_k[q];
   }
   const uint32_t alpha = J->alpha, op_mask = J->op_mask, aos_A = J->aos_A;
-  const uint32_t w_floor = J->w_floor, stag_limit = J->stag_limit;
+  const uint32_t w_floor = J->w_floor, stag_limit = J->stag_limit, lns_cap = J->lns_cap;
   // per-solution weights: the evolve workgroups update them; the instance
   // statistics and weights stay as initialised
   const bool inst_scope = J->aos_scope == 0;
@@ -2286,10 +2574,12 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
     // Eq. ema on every enabled operator and on the k weights, clamp, then normalisation per group
     const bool upd = (op_lane && ((op_mask >> l) & 1u)) || k_lane;
     uint64_t nw = 0;
-    if (upd) {
+    if (upd) {   // an LNS weight is clamped to [min(floor, cap), cap]
       const uint64_t r = udiv_q24(v << 16, u + 1);
       nw = ((uint64_t)aos_A * w + (uint64_t)(65536 - aos_A) * (r + w_floor)) >> 16;
-      nw = nw < w_floor ? w_floor : (nw > 65536 ? 65536 : nw);
+      const bool lns = op_lane && lns_cap && ((kLnsMask >> l) & 1u);
+      const uint64_t lo = lns ? min(w_floor, lns_cap) : w_floor, hi = lns ? lns_cap : 65536u;
+      nw = nw < lo ? lo : (nw > hi ? hi : nw);
     }
     const uint32_t s_op = wave_sum(op_lane ? (uint32_t)nw : 0u), s_k = wave_sum(k_lane ? (uint32_t)nw : 0u);
     if (upd) {
@@ -2423,8 +2713,8 @@ __device__ __forceinline__ void solution_aos_close(DevJob *J, uint32_t sol, LSta
   uint32_t stag = A->stag;
   int64_t ref = A->epoch_ref;
   if (g1 % E == 0) {
-    ema_group(w, u, v, J->op_mask, kOps, J->aos_A, J->w_floor);
-    ema_group(wk, uk, vk, 7u, 3, J->aos_A, J->w_floor);
+    ema_group(w, u, v, J->op_mask, kOps, J->aos_A, J->w_floor, J->lns_cap);
+    ema_group(wk, uk, vk, 7u, 3, J->aos_A, J->w_floor, 0u);
     stag = bf < ref ? 0u : stag + 1;
     ref = bf;
     if (stag >= J->stag_limit) {
@@ -2482,18 +2772,26 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
   // cumulative weights of the encoding's operators (the others weigh 0): one
   // bound per operator but the last, which only adds to the total
   constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : (rows ? 3 : 0));
-  constexpr int lo = enc_lo<ENC>(), span = enc_hi<ENC>() - lo;
+  constexpr int lo = enc_lo<ENC>(), span = enc_top<ENC, x3>() - lo;
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < span; ++i) {
     c += wsrc[lo + i];
     U.cw[i] = c;
   }
-  U.sw = c + wsrc[enc_hi<ENC>()];
+  U.sw = c + wsrc[enc_top<ENC, x3>()];
   U.ck[0] = wksrc[0];
   U.ck[1] = wksrc[0] + wksrc[1];
   U.swk = U.ck[1] + wksrc[2];
 
+  // LNS scratch of this wave (wide variants of single-row permutations)
+  LnsCtx lx{nullptr, nullptr, nullptr};
+  if constexpr (x3 && !rows && (KIND == KTSP || KIND == KQAP || KIND == KVRP)) {
+    char *lb = lds + lds_core_bytes(KIND, n, VAR, I->rows) + (threadIdx.x >> 6) * lns_wave_bytes(n);
+    lx.hkey = J->sums;
+    lx.tabs = (LnsTab *)lb;
+    lx.y = (uint16_t *)(lb + 3 * sizeof(LnsTab));
+  }
   uint64_t T = J->T;
   int64_t f = J->cur_f[sol], bf = J->best_f[sol];
   LStats S = {};
@@ -2516,23 +2814,23 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       if constexpr (STAGE == SLDS16) {
         stage16(rest, I->d16, 2u * n * n);
         __syncthreads();
-        if constexpr (x3) tsp_run<true>(t0, t1, nullptr, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
-        else tsp_run<false>(t0, t1, nullptr, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        if constexpr (x3) tsp_run<true>(t0, t1, nullptr, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
+        else tsp_run<false>(t0, t1, nullptr, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
       } else if constexpr (STAGE == SLDSXY) {
         short2 *xy = (short2 *)rest;
         uint16_t *el = (uint16_t *)(rest + al16(4 * n));
         for (int p = lane; p < n; p += kWave) xy[p] = make_short2((short)I->xy[2 * p], (short)I->xy[2 * p + 1]);
         __syncthreads();
-        if constexpr (x3) tsp_run<true>(t0, t1, el, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
-        else tsp_run<false>(t0, t1, el, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        if constexpr (x3) tsp_run<true>(t0, t1, el, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
+        else tsp_run<false>(t0, t1, el, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
       } else if constexpr (STAGE == SGLB16) {
         __syncthreads();
-        if constexpr (x3) tsp_run<true>(t0, t1, nullptr, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
-        else tsp_run<false>(t0, t1, nullptr, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        if constexpr (x3) tsp_run<true>(t0, t1, nullptr, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
+        else tsp_run<false>(t0, t1, nullptr, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
       } else {
         __syncthreads();
-        if constexpr (x3) tsp_run<true>(t0, t1, nullptr, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
-        else tsp_run<false>(t0, t1, nullptr, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc);
+        if constexpr (x3) tsp_run<true>(t0, t1, nullptr, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
+        else tsp_run<false>(t0, t1, nullptr, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
       }
       perm_store(t0, n, cur_g);
     } else if constexpr (KIND == KQAP) {
@@ -2560,8 +2858,8 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
                   I->qap_sums32 != 0};
       __syncthreads();
       kd.setup(I->qf);
-      if constexpr (x3) round_gens<true>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk);
-      else round_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk);
+      if constexpr (x3) round_gens<true>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk, lx);
+      else round_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk, lx);
       if (wv == 0) perm_store(kd.cur, n, cur_g);
     } else {
       // int16 distances, the per-node (demand, ready, due) records, the two
@@ -2579,15 +2877,15 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       if constexpr ((VAR & kVarLex) != 0) {
         const LexCfg L = lex_cfg(I);
         Vec4 cv = load_vec(J->cur_v + 4 * (size_t)sol), bsv = load_vec(J->best_v + 4 * (size_t)sol);
-        lex_rounds<x3>(kd, W, U, L, best_row, sol, g0, g1, T, f, bf, cv, bsv, S, nacc, (int64_t *)(xk + 2));
+        lex_rounds<x3>(kd, W, U, L, best_row, sol, g0, g1, T, f, bf, cv, bsv, S, nacc, (int64_t *)(xk + 2), lx);
         if (threadIdx.x == 0) {
           store_vec(J->cur_v + 4 * (size_t)sol, cv);
           store_vec(J->best_v + 4 * (size_t)sol, bsv);
         }
       } else if constexpr (x3) {
-        round_gens<true>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk);
+        round_gens<true>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk, lx);
       } else {
-        round_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk);
+        round_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk, lx);
       }
       if (threadIdx.x < kWave) perm_store(kd.cur, n, cur_g);
     }
@@ -2626,7 +2924,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     J->best_f[sol] = bf;
   }
   if (sol_scope) solution_aos_close<kThreads<KIND, VAR>>(J, sol, S, bf, g1, E);
-  write_counts<ENC, true>(J, sol, S, nacc, bf);   // every wave adds the counts of its own candidates
+  write_counts<ENC, true, x3>(J, sol, S, nacc, bf);   // every wave adds the counts of its own candidates
 }
 
 }  // namespace
@@ -3025,6 +3323,7 @@ __global__ void k_init_final(DevJob *jobs, int count) {
     raw[i] = 65536;
     if (i == OOROPT) raw[i] = n <= 100 ? 52429 : (n <= 250 ? 45875 : 19661);
     if (i == O3OPT) raw[i] = n <= 100 ? 32768 : (n <= 250 ? 19661 : 3277);
+    if (J->lns_cap && ((kLnsMask >> i) & 1u)) raw[i] = n <= 100 ? 393 : (n <= 250 ? 262 : 66);
     if (J->init_w[i]) raw[i] = J->init_w[i];
     s += raw[i];
   }

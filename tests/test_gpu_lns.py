@@ -1,0 +1,168 @@
+"""GPU parity of the LNS operators (paper, Sec. "Built-in Operator Hierarchy":
+segment shuffle, scatter shuffle, guided rebuild; Tab. weight_preset: LNS
+weights and caps), through the C interface, bit for bit against the oracle:
+every state field and the run totals after each split of a run and the best
+a solve reports, on TSP (every staging), QAP, the VRPTW giant tour (weighted
+and lexicographic), with the LNS operators alone and beside the others, with
+their initial weights raised so that many candidates hold LNS steps (the
+epoch is long, so the cap applies late), per-solution weights, tiny sizes,
+the 442-city instance (the largest destroyed part), and a batch."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2603_19163_amd import gx
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ["g", "stag", "T_q16", "epoch_ref", "accepted", "w_op", "w_k", "u_op", "v_op", "u_k", "v_k",
+        "cur", "cur_f", "best", "best_f"]
+TOT = [("u_op", "tot_u_op"), ("v_op", "tot_v_op"), ("u_k", "tot_u_k"), ("v_k", "tot_v_k")]
+LNS, ALL = synth.LNS_OPS, synth.PERM_LNS_OPS
+RAISED = [0, 0, 0, 0, 0, 30000, 30000, 30000]      # LNS weights raised for the first epoch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gx.gx_create(0)
+    yield c
+    gx.gx_destroy(c)
+
+
+def P(G, **kw):
+    kw.setdefault("alpha_q32", synth.alpha_q32_for(G))
+    return synth.Params(generations=G, **kw)
+
+
+def compare(ctx, job, p, inst, st, what, lex=False):
+    g = gx.gx_snapshot(ctx, job, p.population, inst.n)
+    for k in KEYS:
+        a, b = np.asarray(g[k]), np.asarray(st[k])
+        assert np.array_equal(a, b), f"{what}: {k} gpu {a.ravel()[:10]} oracle {b.ravel()[:10]}"
+    if lex:
+        v = gx.gx_snapshot_lex(ctx, job, p.population)
+        for k in ("cur_v", "best_v", "ref_v"):
+            assert np.array_equal(v[k], st[k]), f"{what}: {k}"
+    s = gx.gx_job_stats(ctx, job)
+    for gk, ok in TOT:
+        assert np.array_equal(s[gk], st[ok]), f"{what}: run total {gk} gpu {s[gk]} oracle {st[ok]}"
+    assert s["accepted"] == st["accepted"]
+
+
+def run_parity(ctx, inst, p, splits, what, lex=False, threads=1):
+    print(f"[lns] {what} kind={inst.kind} n={inst.n} P={p.population} C={p.candidates} mask={p.op_mask:#x}",
+          flush=True)
+    h = gx.gx_instance_upload(ctx, inst)
+    job = gx.gx_job_create(ctx, h, p)
+    o = oracle.OracleInstance(inst)
+    st = o.init(p)
+    compare(ctx, job, p, inst, st, f"{what} init", lex)
+    for i, s in enumerate(splits):
+        gx.gx_job_advance(ctx, job, s)
+        o.run(p, st, s, threads=threads)
+        compare(ctx, job, p, inst, st, f"{what} split {i}", lex)
+    gx.gx_job_free(ctx, job)
+    job = gx.gx_solve(ctx, h, p)
+    gx.gx_wait(ctx, job)
+    sol, f = gx.gx_fetch_best(ctx, job, inst.n)
+    fo, io = o.best_of(st)
+    assert f == fo and np.array_equal(sol, st["best"][io]), (what, f, fo)
+    gx.gx_job_free(ctx, job)
+    gx.gx_instance_free(ctx, h)
+    return st
+
+
+@pytest.mark.parametrize("staging", [1, 2, 3, 4])
+def test_tsp_lns(ctx, staging):
+    inst = synth.tsp_clustered(70, 2, key=21)
+    p = P(36, seed=5, population=5, candidates=128, op_mask=ALL, epoch=30, staging=staging, init_weight_q16=RAISED)
+    st = run_parity(ctx, inst, p, [7, 29], f"tsp staging {staging}")
+    assert int(st["tot_u_op"][5:8].min()) > 0
+
+
+@pytest.mark.parametrize("case", ["lns-only", "credit1", "sol-scope"])
+def test_tsp_lns_modes(ctx, case):
+    inst = synth.tsp_uniform(45, 3, key=22)
+    kw = {"lns-only": dict(op_mask=LNS), "credit1": dict(op_mask=ALL, credit=1, init_weight_q16=RAISED),
+          "sol-scope": dict(op_mask=ALL, aos_scope=1, epoch=4, init_weight_q16=RAISED)}[case]
+    kw.setdefault("epoch", 25)
+    p = P(30, seed=9, population=4, candidates=100, **kw)
+    run_parity(ctx, inst, p, [11, 19], f"tsp {case}")
+
+
+def test_qap_lns(ctx):
+    inst = synth.qap_random(26, 3, key=23)
+    p = P(30, seed=4, population=4, candidates=128, op_mask=ALL, epoch=25, init_weight_q16=RAISED)
+    st = run_parity(ctx, inst, p, [9, 21], "qap")
+    assert int(st["tot_u_op"][5:8].min()) > 0
+
+
+def test_qap_lns_only_wide_sums(ctx):
+    base = synth.qap_random(20, 4, key=24)
+    inst = dataclasses.replace(base, a=base.a * 1000, b=base.b * 160)   # the 64-bit row sums
+    run_parity(ctx, inst, P(20, seed=2, population=3, candidates=96, op_mask=LNS), [20], "qap wide")
+
+
+@pytest.mark.parametrize("mode", ["weighted", "lex"])
+def test_vrptw_lns(ctx, mode):
+    base = synth.vrptw_random(30, 5, key=25)
+    inst = dataclasses.replace(base, vehicles=4, obj_weights=(6, 2, 2)) if mode == "weighted" else \
+        dataclasses.replace(base, vehicles=4, lex_order=(2, 1, 0), lex_tol=(0, 25, 0))
+    p = P(30, seed=6, population=4, candidates=128, op_mask=ALL, epoch=25, init_weight_q16=RAISED)
+    run_parity(ctx, inst, p, [13, 17], f"vrptw {mode}", lex=mode == "lex")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17])
+def test_lns_tiny(ctx, n):
+    for inst in (synth.tsp_uniform(n, 1, key=30 + n), synth.qap_random(n, 1, key=40 + n)):
+        run_parity(ctx, inst, P(12, seed=7, population=3, candidates=65, op_mask=ALL, init_weight_q16=RAISED),
+                   [12], f"tiny {n}")
+
+
+def test_tsp442_lns(ctx):
+    """The 442-city instance: 29 entries destroyed per LNS step."""
+    inst, _ = synth.c2_tsp442(population=64, generations=24)
+    p = P(24, seed=42, population=64, candidates=128, op_mask=ALL, epoch=20, init_weight_q16=RAISED)
+    run_parity(ctx, inst, p, [10, 14], "tsp442", threads=16)
+
+
+def test_lns_batch(ctx):
+    insts = [synth.tsp_uniform(40, 6, key=50), synth.qap_random(18, 6, key=51), synth.vrptw_random(20, 6, key=52),
+             synth.tsp_uniform(33, 7, key=53)]
+    masks = [ALL, ALL, ALL, synth.PERM_OPS]
+    params = [P(25, seed=1 + i, population=3 + i, candidates=128, op_mask=m, epoch=20, init_weight_q16=RAISED)
+              for i, m in enumerate(masks)]
+    hs = [gx.gx_instance_upload(ctx, i) for i in insts]
+    jobs = gx.gx_solve_batch(ctx, hs, params)
+    gx.gx_wait(ctx)
+    for inst, p, job in zip(insts, params, jobs):
+        o = oracle.OracleInstance(inst)
+        st = o.solve(p)
+        fo, io = o.best_of(st)
+        sol, f = gx.gx_fetch_best(ctx, job, inst.n)
+        assert f == fo and np.array_equal(sol, st["best"][io]), (inst.kind, f, fo)
+    for j in jobs:
+        gx.gx_job_free(ctx, j)
+    for h in hs:
+        gx.gx_instance_free(ctx, h)
+
+
+def test_lns_masks(ctx):
+    """LNS bits are taken only where they are LNS operators."""
+    h = gx.gx_instance_upload(ctx, synth.knapsack_random(20, 1, key=60))
+    with pytest.raises(gx.GxError):
+        gx.gx_job_create(ctx, h, P(5, seed=1, population=2, op_mask=LNS))
+    gx.gx_instance_free(ctx, h)
+    h = gx.gx_instance_upload(ctx, synth.tsp_uniform(20, 1, key=61))
+    job = gx.gx_job_create(ctx, h, P(5, seed=1, population=2, op_mask=LNS))
+    st = gx.gx_snapshot(ctx, job, 2, 20)
+    assert (st["w_op"][5:8] > 0).all() and not st["w_op"][:5].any()
+    gx.gx_job_free(ctx, job)
+    job = gx.gx_job_create(ctx, h, P(5, seed=1, population=2))
+    st = gx.gx_snapshot(ctx, job, 2, 20)
+    assert not st["w_op"][5:8].any()                 # op_mask 0: no LNS
+    gx.gx_job_free(ctx, job)
+    gx.gx_instance_free(ctx, h)
