@@ -422,6 +422,8 @@ def bench_kinds(args):
          tsp442(**isl, migrate_mode=1, migrate_n=4)),
         ("tsp442_islands_hybrid", "same, 16 islands, hybrid migration every 5 epochs, elite every 10",
          tsp442(**isl, migrate_mode=2, migrate_n=4)),
+        ("tsp442_lns", "same, one population, with the three LNS operators at their preset weights",
+         tsp442(op_mask=synth.PERM4_OPS | synth.LNS_OPS)),
         ("tsp50", "TSP n=50 uniform, P=64, 2-opt/swap/or-opt, 2000 generations", synth.c1_small_tsp(0)),
         ("vrptw100", "VRPTW 100 customers, giant tour + split, P=64, 5000 generations", synth.c3_vrptw()),
         ("vrptw100_weighted", "same, weighted objectives 6 distance + 2 routes + 2 longest route",
@@ -434,6 +436,8 @@ def bench_kinds(args):
          (dataclasses.replace(synth.c3_vrptw_rows()[0], lex_order=(2, 1, 3), lex_tol=(0, 20, 0)),
           synth.c3_vrptw_rows()[1])),
         ("qap50", "QAP n=50, P autosized, 2000 generations", one(synth.qap_random(50, 7), 0, 2000)),
+        ("vrptw100_lns", "VRPTW 100 customers, giant tour, every permutation operator and the LNS operators",
+         (synth.c3_vrptw()[0], synth.c3_vrptw()[1].with_(op_mask=synth.PERM_LNS_OPS))),
     ]
     kp_inst, kp = one(synth.knapsack_random(1000, 7), 2048, 5000)
     rows += [("knapsack1000_flip", "0/1 knapsack n=1000, P=2048, flip only, 5000 generations",
@@ -458,10 +462,13 @@ def bench_kinds(args):
             gx.gx_job_free(ctx, job)
         gx.gx_instance_free(ctx, h)
         s = info["evolve_ms"] / 1e3
+        names = list(synth.OP_NAMES)
+        if inst.kind != synth.VRPTW_ROWS:   # ids 5-7 are the LNS operators on single-row permutations
+            names[5:8] = ["lns_segment", "lns_scatter", "lns_guided"]
         out.append({"row": name, "workload": what, "population": p.population,
                     "move_evals_per_s": info["move_evals"] / s, "avg_launch_us": s * 1e6 / info["evolve_launches"],
-                    "best": int(f), "op_steps": {synth.OP_NAMES[o]: int(info["op_steps"][o])
-                                                 for o in range(len(synth.OP_NAMES)) if info["op_steps"][o]}})
+                    "best": int(f), "op_steps": {names[o]: int(info["op_steps"][o])
+                                                 for o in range(len(names)) if info["op_steps"][o]}})
     gx.gx_destroy(ctx)
     return {"metric": "move evals/s per problem kind", "unit": "move evals/s", "rows": out}
 

@@ -1515,7 +1515,11 @@ struct SrvLane {
 
 // lanes: (kind, staging) x LDS class x 3-opt in the operator set, and the
 // VRPTW lexicographic kernels (LDS class x 3-opt)
-constexpr int kLanes = 9 * kLdsClasses * 2 + 2 * kLdsClasses;
+// one lane per kernel and LDS class: 9 kind-stagings with or without the wide
+// variant, VRPTW lexicographic (2), VRPTW multi-row (4: wide, lexicographic),
+// and the LNS variants (TSP stagings 4, QAP 2, VRPTW 2)
+constexpr int kLaneKernels = 32;
+constexpr int kLanes = kLaneKernels * kLdsClasses;
 // epoch chunks a lane advances per quantum: the launches and the host's
 // turnaround are paid once per quantum, and a newly admitted request joins at
 // its lane's next quantum.  An epoch of TSP, knapsack or colouring takes tens
@@ -1525,8 +1529,13 @@ int lane_of(int kind, int var, uint32_t lds) {
   const int stage = var & 7;
   const int ks = kind == KTSP ? std::min(std::max(stage, 1), 4) - 1
                               : (kind == KQAP ? 4 + (stage == 1) : (kind == KKNAP ? 6 : (kind == KVRP ? 7 : 8)));
-  if (var & kVarLex) return 18 * kLdsClasses + ((var & kVarX3) ? kLdsClasses : 0) + lds_class(lds);
-  return ((var & kVarX3) ? 9 * kLdsClasses : 0) + ks * kLdsClasses + lds_class(lds);
+  const int x3 = (var & kVarX3) ? 1 : 0, lex = (var & kVarLex) ? 1 : 0;
+  int k;
+  if (var & kVarLns) k = 24 + (kind == KVRP ? 6 + lex : ks);   // TSP 0-3, QAP 4-5, VRPTW 6-7
+  else if (var & kVarRows) k = 20 + x3 + 2 * lex;
+  else if (lex) k = 18 + x3;
+  else k = 9 * x3 + ks;
+  return k * kLdsClasses + lds_class(lds);
 }
 
 }  // namespace

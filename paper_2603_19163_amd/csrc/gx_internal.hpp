@@ -36,12 +36,14 @@ enum Stage : int32_t { SAUTO = 0, SLDS16 = 1, SLDSXY = 2, SGLB16 = 3, SGLB32 = 4
 // (their loops are compiled apart from the others, so that jobs without them
 // carry none of their branches or wider counters), plus
 // kVarLex for a VRPTW instance in the lexicographic mode, plus kVarRows for a
-// VRPTW instance in the multi-row form.
-constexpr int kVarX3 = 8, kVarLex = 16, kVarRows = 32;
+// VRPTW instance in the multi-row form, plus kVarLns (with kVarX3) when a
+// single-row permutation job's operator set holds an LNS operator.
+constexpr int kVarX3 = 8, kVarLex = 16, kVarRows = 32, kVarLns = 64;
 inline int evolve_variant(int kind, uint32_t stage, uint32_t op_mask, uint32_t lex_levels, uint32_t rows) {
   const bool perm = kind == KTSP || kind == KQAP || kind == KVRP;
-  const bool wide = (op_mask & (1u << O3OPT)) || (!rows && (op_mask & kLnsMask));
-  return (int)stage | ((perm && wide) ? kVarX3 : 0) |
+  const bool lns = perm && !rows && (op_mask & kLnsMask);
+  const bool wide = (op_mask & (1u << O3OPT)) || lns;
+  return (int)stage | ((perm && wide) ? kVarX3 : 0) | (lns ? kVarLns : 0) |
          ((kind == KVRP && lex_levels) ? kVarLex : 0) | ((kind == KVRP && rows) ? kVarRows : 0);
 }
 
@@ -144,7 +146,7 @@ struct LnsTab {
 };
 __host__ __device__ inline uint32_t lns_wave_bytes(int n) { return 3u * (uint32_t)sizeof(LnsTab) + ((2u * n + 15u) & ~15u); }
 __host__ __device__ inline bool lns_variant(int kind, int var) {
-  return (var & kVarX3) && !(var & kVarRows) && (kind == KTSP || kind == KQAP || kind == KVRP);
+  return (var & kVarLns) && (kind == KTSP || kind == KQAP || kind == KVRP);
 }
 __host__ __device__ inline uint32_t lds_core_bytes(int kind, int n, int var, int rows) {
   auto al = [](uint32_t b) { return (b + 15u) & ~15u; };

@@ -113,9 +113,7 @@ struct Step {
 // u < cumsum_i.  An encoding's operators are contiguous ids (permutations 0-4,
 // multi-row permutations 0-7, binary 8-9, integer 10-11) and the others have
 // weight 0, so only the encoding's own cumulative sums matter.
-// (X3: the wide variant of a single-row permutation, whose ids 5-7 are the
-// LNS operators)
-template <int ENC, bool X3>
+template <int ENC>
 __device__ __forceinline__ int pick_op(uint32_t u16, const Uni &U) {
   const uint32_t u = (uint32_t)(((uint64_t)u16 * U.sw) >> 16);
   if (ENC == 1 || ENC == 2) {
@@ -123,7 +121,7 @@ __device__ __forceinline__ int pick_op(uint32_t u16, const Uni &U) {
     return lo + (U.cw[0] <= u);
   }
   int op = (U.cw[0] <= u) + (U.cw[1] <= u) + (U.cw[2] <= u) + (U.cw[3] <= u);
-  if (ENC == 3 || X3) op += (U.cw[4] <= u) + (U.cw[5] <= u) + (U.cw[6] <= u);
+  if (ENC >= 3) op += (U.cw[4] <= u) + (U.cw[5] <= u) + (U.cw[6] <= u);
   return op;
 }
 
@@ -135,19 +133,16 @@ __device__ __forceinline__ int pick_k(uint32_t w0, const Uni &U) {
 
 // Encodings: 0 permutation, 1 binary, 2 integer, 3 multi-row permutation
 // (the permutation operators on the entries before the final row marker, and
-// the row operators).
+// the row operators), 4 permutation with the LNS operators (ids 5-7; the
+// kernel variants whose operator set holds them).
 // first operator id of an encoding
 template <int ENC>
-constexpr int enc_lo() { return (ENC == 0 || ENC == 3) ? 0 : (ENC == 1 ? OFLIP : ORESET); }
+constexpr int enc_lo() { return (ENC == 1 || ENC == 2) ? (ENC == 1 ? OFLIP : ORESET) : 0; }
 // last operator id of an encoding
 template <int ENC>
-constexpr int enc_hi() { return ENC == 0 ? O3OPT : (ENC == 3 ? OROWMERGE : enc_lo<ENC>() + 1); }
+constexpr int enc_hi() { return ENC == 0 ? O3OPT : (ENC >= 3 ? OROWMERGE : enc_lo<ENC>() + 1); }
 template <int ENC>
-constexpr bool enc_perm() { return ENC == 0 || ENC == 3; }
-// last operator id a kernel variant may draw: the wide variant of a
-// single-row permutation adds the LNS operators (ids 5-7)
-template <int ENC, bool X3>
-constexpr int enc_top() { return (ENC == 0 && X3) ? OLNSGUIDE : enc_hi<ENC>(); }
+constexpr bool enc_perm() { return ENC == 0 || ENC >= 3; }
 
 // X3: the operator set holds 3-opt (the loops without it are compiled
 // without its branches).  A row operator's step keeps only its drawn position
@@ -210,14 +205,14 @@ __device__ __forceinline__ int sample(const Uni &U, uint32_t g, uint32_t sol, ui
   uint32_t r[4];
   philox(g, sol, t << 2, U.key, U.k0, U.k1, r);
   const int k = pick_k(r[0], U);
-  st[0] = make_step<ENC, X3>(pick_op<ENC, X3>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+  st[0] = make_step<ENC, X3>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
   if (k > 1) {
     philox(g, sol, (t << 2) | 1u, U.key, U.k0, U.k1, r);
-    st[1] = make_step<ENC, X3>(pick_op<ENC, X3>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+    st[1] = make_step<ENC, X3>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
   }
   if (k > 2) {
     philox(g, sol, (t << 2) | 2u, U.key, U.k0, U.k1, r);
-    st[2] = make_step<ENC, X3>(pick_op<ENC, X3>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
+    st[2] = make_step<ENC, X3>(pick_op<ENC>(r[0] & 0xFFFFu, U), r[1], r[2], r[3], U);
   }
   return k;
 }
@@ -259,6 +254,12 @@ __device__ __forceinline__ int chain(const Step *st, int m, int p) {
 // comes from.  Candidates with such a step are rare (their weights stay
 // below 2 %); the whole wave computes their objectives from their entries,
 // in place of the per-lane delta, and applies them when they win.
+// (shfl64: a 64-bit value from lane src)
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t src) {
+  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, (int)src, kWave);
+  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), (int)src, kWave);
+  return ((uint64_t)hi << 32) | lo;
+}
 __device__ __forceinline__ bool is_lns(int op) { return op >= OLNSSEG && op <= OLNSGUIDE; }
 __device__ __forceinline__ int lns_len(int n) { return min(min(2 + n / 16, kLnsMax), n); }
 __device__ __forceinline__ uint32_t lns_word(const uint32_t *w, int i) {
@@ -292,55 +293,59 @@ __device__ __forceinline__ int lchain(const Step *st, int m, int p, const LnsTab
   return p;
 }
 // the table of LNS step m (op, words w) of a candidate whose earlier steps
-// are st[0..m-1] (their tables built); one lane.  tmp: L entries of scratch.
-__device__ void lns_make(LnsTab &T, int op, const uint32_t *w, int n, const uint16_t *cur, const Step *st,
-                         const LnsTab *tabs, int m, const int64_t *hkey, uint16_t *tmp) {
+// are st[0..m-1] (their tables built), by the whole wave: lane q draws the
+// q-th position and holds the q-th words; the shuffles run over the lanes.
+__device__ __forceinline__ void lns_make(LnsTab &T, int op, const uint32_t *w, int n, const uint16_t *cur,
+                                         const Step *st, const LnsTab *tabs, int m, const int64_t *hkey) {
+  const int lane = (int)lane_id();
   const int L = n >= 2 ? lns_len(n) : 0;
-  T.L = L < 2 ? 0 : L;
-  if (L < 2) return;
-  if (op == OLNSSCAT) {
-    for (int j = n - L; j < n; ++j) {
-      const int r = (int)rmap(lns_word(w, j - n + L), (uint32_t)(j + 1));
-      bool have = false;
-      for (int q = 0; q < j - n + L; ++q) have |= (int)T.pos[q] == r;
-      T.pos[j - n + L] = (uint16_t)(have ? j : r);
-    }
-    for (int i = 1; i < L; ++i) {   // increasing order
-      const uint16_t v = T.pos[i];
-      int q = i;
-      for (; q > 0 && T.pos[q - 1] > v; --q) T.pos[q] = T.pos[q - 1];
-      T.pos[q] = v;
-    }
-  } else {
-    const int a = (int)rmap(w[0], (uint32_t)(n - L + 1));
-    for (int i = 0; i < L; ++i) T.pos[i] = (uint16_t)(a + i);
-  }
-  for (int i = 0; i < L; ++i) T.src[i] = (uint8_t)i;
-  if (op == OLNSGUIDE) {   // sources ordered by (key, entry) of the entries before the step
-    const bool desc = (w[1] >> 31) != 0;
-    for (int i = 0; i < L; ++i) tmp[i] = cur[lchain(st, m, T.pos[i], tabs)];
-    for (int i = 1; i < L; ++i) {
-      const uint8_t x = T.src[i];
-      const int ex = tmp[x];
-      const int64_t kx = desc ? -hkey[ex] : hkey[ex];
-      int q = i;
-      for (; q > 0; --q) {
-        const int ep = tmp[T.src[q - 1]];
-        const int64_t kp = desc ? -hkey[ep] : hkey[ep];
-        if (kp > kx || (kp == kx && ep > ex)) T.src[q] = T.src[q - 1];
-        else break;
-      }
-      T.src[q] = x;
-    }
+  if (L < 2) {
+    if (lane == 0) T.L = 0;
+    wave_sync();
     return;
   }
-  const int base = op == OLNSSCAT ? L : 0;
-  for (int i = L - 1; i >= 1; --i) {   // Fisher-Yates on the sources
-    const int j = (int)rmap(lns_word(w, base + L - 1 - i), (uint32_t)(i + 1));
-    const uint8_t t = T.src[i];
-    T.src[i] = T.src[j];
-    T.src[j] = t;
+  // words q and L + q of the step on lane q (Floyd's draws or the segment's
+  // shuffle, and the scattered entries' shuffle)
+  const uint32_t wa = lns_word(w, lane), wb = op == OLNSSCAT ? lns_word(w, L + lane) : 0u;
+  const int a = (int)rmap(w[0], (uint32_t)(n - L + 1));
+  if (op == OLNSSCAT) {
+    int pos = 0;
+    for (int q = 0; q < L; ++q) {   // Floyd's sampling: position q is r, or j when r is taken
+      const int j = n - L + q;
+      const int r = (int)rmap((uint32_t)__shfl((int)wa, q, kWave), (uint32_t)(j + 1));
+      const bool have = __ballot(lane < q && pos == r) != 0ull;
+      if (lane == q) pos = have ? j : r;
+    }
+    int rank = 0;   // increasing order
+    for (int q = 0; q < L; ++q) rank += __shfl(pos, q, kWave) < pos;
+    if (lane < L) T.pos[rank] = (uint16_t)pos;
+  } else if (lane < L) {
+    T.pos[lane] = (uint16_t)(a + lane);
   }
+  wave_sync();
+  if (op == OLNSGUIDE) {   // sources ordered by (key, entry) of the entries before the step
+    const bool desc = (w[1] >> 31) != 0;
+    const int e = lane < L ? (int)cur[lchain(st, m, a + lane, tabs)] : 0;
+    const int64_t ky = lane < L ? (desc ? -hkey[e] : hkey[e]) : 0;
+    int rank = 0;
+    for (int q = 0; q < L; ++q) {
+      const int eq = __shfl(e, q, kWave);
+      const int64_t kq = (int64_t)shfl64((uint64_t)ky, (uint32_t)q);
+      rank += kq < ky || (kq == ky && eq < e);
+    }
+    if (lane < L) T.src[rank] = (uint8_t)lane;
+  } else {   // Fisher-Yates on the sources, entry i of the step on lane i
+    const uint32_t wf = op == OLNSSCAT ? wb : wa;
+    int src = lane;
+    for (int i = L - 1; i >= 1; --i) {
+      const int j = (int)rmap((uint32_t)__shfl((int)wf, L - 1 - i, kWave), (uint32_t)(i + 1));
+      const int si = __shfl(src, i, kWave), sj = __shfl(src, j, kWave);
+      src = lane == i ? sj : (lane == j ? si : src);
+    }
+    if (lane < L) T.src[lane] = (uint8_t)src;
+  }
+  if (lane == 0) T.L = L;
+  wave_sync();
 }
 
 // One wave's LNS scratch: the step tables, the candidate's entries, and the
@@ -365,19 +370,16 @@ __device__ __forceinline__ bool lns_drawn(const uint8_t *sop, uint32_t tl, int k
   return h;
 }
 // the tables of the LNS steps of candidate t (steps st, k of them) of
-// generation g, built by lane 0 of the calling wave
+// generation g, built by the calling wave
 template <bool X3>
 __device__ __forceinline__ void lns_tables(const Uni &U, uint32_t g, uint32_t sol, uint32_t t, const Step *st, int k,
                                            int n, const uint16_t *cur, const LnsCtx &lx) {
-  if (lane_id() == 0) {
-    for (int m = 0; m < k; ++m) {
-      if (!is_lns(st[m].op)) continue;
-      uint32_t r[4];
-      philox(g, sol, (t << 2) | (uint32_t)m, U.key, U.k0, U.k1, r);
-      lns_make(lx.tabs[m], st[m].op, r + 1, n, cur, st, lx.tabs, m, lx.hkey, lx.y);
-    }
+  for (int m = 0; m < k; ++m) {   // k and the steps are the same on every lane
+    if (!is_lns(st[m].op)) continue;
+    uint32_t r[4];
+    philox(g, sol, (t << 2) | (uint32_t)m, U.key, U.k0, U.k1, r);
+    lns_make(lx.tabs[m], st[m].op, r + 1, n, cur, st, lx.tabs, m, lx.hkey);
   }
-  wave_sync();
 }
 // the hull of the positions a candidate with LNS steps changes
 __device__ __forceinline__ void lns_range(const Step *st, int k, const LnsTab *tabs, int &lo, int &hi) {
@@ -404,7 +406,7 @@ template <bool X3, class OBJ>
 __device__ __forceinline__ auto lns_eval(const Uni &U, uint32_t g, uint32_t sol, uint32_t t, int n,
                                          const uint16_t *cur, const LnsCtx &lx, const OBJ &obj) {
   Step st[3];
-  const int k = sample<0, X3>(U, g, sol, t, st);
+  const int k = sample<4, X3>(U, g, sol, t, st);
   lns_tables<X3>(U, g, sol, t, st, k, n, cur, lx);
   for (int p = (int)lane_id(); p < n; p += kWave) lx.y[p] = cur[lchain(st, k, p, lx.tabs)];
   wave_sync();
@@ -429,9 +431,9 @@ struct LStats {
   uint32_t u[kOps], v[kOps], uk[3], vk[3];
 };
 
-template <int ENC, bool X3>
+template <int ENC>
 __device__ __forceinline__ void credit(LStats &S, const Step *st, int k, bool imp) {
-  constexpr int lo = enc_lo<ENC>(), hi = enc_top<ENC, X3>();
+  constexpr int lo = enc_lo<ENC>(), hi = enc_hi<ENC>();
 #pragma unroll
   for (int m = 0; m < 3; ++m) {
     if (m < k) {
@@ -1130,7 +1132,7 @@ __device__ __forceinline__ uint32_t draw_chunk(const TspScratch &W, const Uni &U
       uint32_t w[4];
       philox_lane(g, sol, (c0 + tl) << 2, U.key, U.k0, U.k1, w);
       kk[rr] = pick_k(w[0], U);
-      const Step st = make_step<ENC, X3>(pick_op<ENC, X3>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
+      const Step st = make_step<ENC, X3>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
       store_step<ENC, X3>(W, 3 * tl, st, (uint32_t)kk[rr] << 6);
       if (first) first[rr] = st;
       if constexpr (RN == 2) W.del()[tl] = 0;
@@ -1151,7 +1153,7 @@ __device__ __forceinline__ uint32_t draw_chunk(const TspScratch &W, const Uni &U
     const uint32_t e = dl[j], tl = e & 0xFFu, m = e >> 8;
     uint32_t w[4];
     philox_lane(g, sol, ((c0 + tl) << 2) | m, U.key, U.k0, U.k1, w);
-    const Step st = make_step<ENC, X3>(pick_op<ENC, X3>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
+    const Step st = make_step<ENC, X3>(pick_op<ENC>(w[0] & 0xFFFFu, U), w[1], w[2], w[3], U);
     store_step<ENC, X3>(W, 3 * tl + m, st, 0u);
   }
   __syncthreads();
@@ -1326,7 +1328,7 @@ __device__ __forceinline__ void fold_ops(uint32_t *u, uint32_t *v, OpCount<W64> 
   else fold_byte_counts(u, v, cu, cv, fields < 4 ? fields : 4);
 }
 
-template <bool X3, class DF>
+template <bool X3, bool LNS, class DF>
 __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *el, int n, const DF &D, const TspScratch &W,
                                         const Uni &U, int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1,
                                         uint64_t &T, int64_t &f, int64_t &bf, LStats &S, uint32_t &nacc,
@@ -1336,7 +1338,8 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
   // in byte fields (operator o at bits 8o, k at bits 8(k-1)); a chunk of
   // candidates adds at most 6 to a field of a lane, so the fields are folded
   // into the wave-wide counts of S every 42 chunks and at the end.
-  constexpr int kNops = X3 ? 8 : 4;   // the wide variant: 3-opt and the LNS operators
+  constexpr int kNops = LNS ? 8 : (X3 ? kPermOps : 4);   // the LNS variant: ids 5-7 too
+  constexpr int ENC = LNS ? 4 : 0;
   OpCount<X3> cu_op = 0, cv_op = 0;
   uint32_t cu_k = 0, cv_k = 0, since_fold = 0;
   // The wave-wide counts live in the unused tail of the pattern-list table
@@ -1362,7 +1365,7 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
       const uint32_t cn = min((uint32_t)kChunk, U.C - c0);
       int kk[2];
       Step s0[2];
-      draw_chunk<0, X3>(W, U, g, sol, c0, cn, kk, 0, s0);
+      draw_chunk<ENC, X3>(W, U, g, sol, c0, cn, kk, 0, s0);
       // ---- first steps: one per candidate, on its own lane, from the drawn step
       int d0[2];
 #pragma unroll
@@ -1405,7 +1408,7 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
       // the whole wave, in place of the per-lane delta
       int64_t lns_d[2] = {0, 0};
       uint32_t lns_c = 0;   // bit r: lane's candidate of round r holds an LNS step
-      if constexpr (X3) {
+      if constexpr (LNS) {
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
           const uint32_t tl = r * kWave + lane;
@@ -1430,7 +1433,7 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
         const uint32_t tl = r * kWave + lane;
         const bool valid = tl < cn;
         int64_t d = valid ? (int64_t)(d0[r] + W.del()[tl]) : 0;
-        if constexpr (X3) d = ((lns_c >> r) & 1u) ? lns_d[r] : d;
+        if constexpr (LNS) d = ((lns_c >> r) & 1u) ? lns_d[r] : d;
         if (U.credit == 0 && valid) {
           const bool imp = d < 0;
 #pragma unroll
@@ -1471,11 +1474,11 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
       if (ts >= c_last) {
         const int tl = (int)(ts - c_last);
         k = (int)(W.sop()[3 * tl] >> 6);
-        st[0] = load_step<0, X3>(W, tl, 0);
-        st[1] = load_step<0, X3>(W, tl, 1);
-        st[2] = load_step<0, X3>(W, tl, 2);
+        st[0] = load_step<ENC, X3>(W, tl, 0);
+        st[1] = load_step<ENC, X3>(W, tl, 1);
+        st[2] = load_step<ENC, X3>(W, tl, 2);
       } else {
-        k = sample<0, X3>(U, g, sol, ts, st);
+        k = sample<ENC, X3>(U, g, sol, ts, st);
       }
       if (U.credit == 1) {   // wave-uniform counts on this path
 #pragma unroll
@@ -1493,7 +1496,7 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
         }
       }
       int lo, hi;
-      if constexpr (X3) {
+      if constexpr (LNS) {
         if (*best_is_cur && f + ds >= bf) {
           perm_store(cur, n, best_row);
           *best_is_cur = 0u;
@@ -1922,7 +1925,7 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
     if (acc) {
       Step st[3];
       const int k = sample<ENC, X3>(U, g, sol, ts, st);
-      if (U.credit == 1) credit<ENC, X3>(S, st, k, ds < 0);   // the same on every lane
+      if (U.credit == 1) credit<ENC>(S, st, k, ds < 0);   // the same on every lane
       if (best_is_cur && f + ds >= bf) {
         kd.store(best_row);
         best_is_cur = false;
@@ -1948,15 +1951,15 @@ __device__ __forceinline__ void run_gens(KD &kd, const TspScratch &W, const Uni 
 // the same on both (the move's shared state is written by wave 0 or
 // identically by both).  Each wave counts its own candidates; the accepted
 // count is wave 0's.
-template <bool X3, class KD>
+template <bool X3, bool LNS, class KD>
 __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Uni &U, int32_t *best_row, uint32_t sol,
                                            uint32_t g0, uint32_t g1, uint64_t &T, int64_t &f, int64_t &bf, LStats &S,
                                            uint32_t &nacc, unsigned long long *xk, const LnsCtx &lx) {
-  constexpr int ENC = KD::ENC;
+  constexpr int ENC = (KD::ENC == 0 && LNS) ? 4 : KD::ENC;
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
-  // the wide variant and the multi-row encoding count eight operators in 64 bits
-  constexpr bool W64 = X3 || ENC == 3;
-  constexpr int nf = W64 ? 8 : 4;
+  // 3-opt and the eight operators of the multi-row and LNS encodings count in 64 bits
+  constexpr bool W64 = X3 || ENC >= 3;
+  constexpr int nf = ENC >= 3 ? 8 : (X3 ? kPermOps : 4);
   OpCount<W64> cu = 0, cv = 0;
   uint32_t cuk = 0, cvk = 0, since_fold = 0;
   bool best_is_cur = false;   // the best-so-far solution is the current one, not yet written
@@ -1971,7 +1974,7 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
       if (__ballot(valid)) {
         const int k = valid ? kk[0] : 0;
         int64_t d = kd.template delta_round<X3>(W, (int)tl, k, f);
-        if constexpr (X3 && ENC == 0) {   // candidates with an LNS step: by the whole wave
+        if constexpr (LNS) {   // candidates with an LNS step: by the whole wave
           for (unsigned long long mk = __ballot(valid && lns_drawn(W.sop(), tl, k)); mk; mk &= mk - 1) {
             const uint32_t t = (uint32_t)__builtin_ctzll(mk);
             const int64_t fn = lns_eval<X3>(U, g, sol, c0 + wv * kWave + t, kd.n, kd.cur, lx,
@@ -2009,12 +2012,12 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
     if (acc) {
       Step st[3];
       const int k = sample<ENC, X3>(U, g, sol, ts, st);
-      if (U.credit == 1 && wv == 0) credit<ENC, X3>(S, st, k, ds < 0);   // the same on every lane of wave 0
+      if (U.credit == 1 && wv == 0) credit<ENC>(S, st, k, ds < 0);   // the same on every lane of wave 0
       if (best_is_cur && f + ds >= bf) {   // wave 0 reads the solution before the move's first barrier
         if (wv == 0) kd.store(best_row);
         best_is_cur = false;
       }
-      if constexpr (X3 && ENC == 0) {
+      if constexpr (LNS) {
         if (lns_in(st, k)) {
           int lo, hi;
           lns_apply<X3>(U, g, sol, ts, st, k, kd.n, kd.cur, kd.nxt, lx, lo, hi);
@@ -2051,14 +2054,14 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
 // strictly better than the current solution.  The scalar f reported for a
 // solution is its penalty plus its first level.  Counts as in round_gens:
 // each wave its own candidates, accepted moves and credit R2 on wave 0.
-template <bool X3, class KD>
+template <bool X3, bool LNS, class KD>
 __device__ __forceinline__ void lex_rounds(KD &kd, const TspScratch &W, const Uni &U, const LexCfg &L,
                                            int32_t *best_row, uint32_t sol, uint32_t g0, uint32_t g1, uint64_t &T,
                                            int64_t &f, int64_t &bf, Vec4 &cv, Vec4 &bsv, LStats &S, uint32_t &nacc,
                                            int64_t *vbuf, const LnsCtx &lx) {
-  constexpr int ENC = KD::ENC;
-  constexpr bool W64 = X3 || ENC == 3;
-  constexpr int nf = W64 ? 8 : 4;
+  constexpr int ENC = (KD::ENC == 0 && LNS) ? 4 : KD::ENC;
+  constexpr bool W64 = X3 || ENC >= 3;
+  constexpr int nf = ENC >= 3 ? 8 : (X3 ? kPermOps : 4);
   const uint32_t lane = lane_id(), wv = threadIdx.x >> 6;
   OpCount<W64> cu = 0, cvc = 0;
   uint32_t cuk = 0, cvk = 0, since_fold = 0;
@@ -2080,7 +2083,7 @@ __device__ __forceinline__ void lex_rounds(KD &kd, const TspScratch &W, const Un
         st[2] = kk[0] > 2 ? load_step<ENC, X3>(W, (int)tl, 2) : st[0];
         v = lex_vector(kd.parts(st, kk[0]), kd.veh, L);
       }
-      if constexpr (X3 && ENC == 0) {   // candidates with an LNS step: by the whole wave
+      if constexpr (LNS) {   // candidates with an LNS step: by the whole wave
         for (unsigned long long mk = __ballot(tl < cn && lns_drawn(W.sop(), tl, kk[0])); mk; mk &= mk - 1) {
           const uint32_t t = (uint32_t)__builtin_ctzll(mk);
           const Vec4 vn = lns_eval<X3>(U, g, sol, c0 + wv * kWave + t, kd.n, kd.cur, lx,
@@ -2115,13 +2118,13 @@ __device__ __forceinline__ void lex_rounds(KD &kd, const TspScratch &W, const Un
     if (acc) {
       Step st[3];
       const int k = sample<ENC, X3>(U, g, sol, bt, st);
-      if (U.credit == 1 && wv == 0) credit<ENC, X3>(S, st, k, lex_better(bv, cv, L));
+      if (U.credit == 1 && wv == 0) credit<ENC>(S, st, k, lex_better(bv, cv, L));
       const bool new_best = lex_better(bv, bsv, L);
       if (best_is_cur && !new_best) {   // wave 0 reads the solution before the move's first barrier
         if (wv == 0) kd.store(best_row);
         best_is_cur = false;
       }
-      if constexpr (X3 && ENC == 0) {
+      if constexpr (LNS) {
         if (lns_in(st, k)) {
           int lo, hi;
           lns_apply<X3>(U, g, sol, bt, st, k, kd.n, kd.cur, kd.nxt, lx, lo, hi);
@@ -2194,9 +2197,9 @@ __device__ __forceinline__ void ema_group(uint32_t *w, const unsigned long long 
 // the rows after the kernel boundary.
 constexpr int kCountSlots = 2 * kOps + 7;   // uses, improvements per operator and per k, accepted
 
-template <int ENC, bool UNIFORM, bool X3>
+template <int ENC, bool UNIFORM>
 __device__ __forceinline__ void write_counts(DevJob *J, uint32_t sol, const LStats &S, uint32_t nacc, int64_t bf) {
-  constexpr int lo = enc_lo<ENC>(), hi = enc_top<ENC, X3>();
+  constexpr int lo = enc_lo<ENC>(), hi = enc_hi<ENC>();
   const uint32_t lane = lane_id();
   uint32_t mine = 0;
 #pragma unroll
@@ -2490,14 +2493,9 @@ __device__ __forceinline__ uint32_t lex_scan_best(const DevJob *J, const LexCfg 
 // After each evolve launch: fold the accumulator rows of every job into its
 // epoch statistics, the instance best and the temperature, and at an epoch
 // boundary apply the AOS update (the kernel boundary orders it after every
-// evolve workgroup).  Wave 0 of the job's workgroup; lane l folds and clears
-// row l.  The launch covered generations [g0, g1).
+// evolve workgroup).  Wave 0 of the job's workgroup, its lanes sharing the
+// work as described at epoch_fold.  The launch covered generations [g0, g1).
 static_assert(kShards == kWave && kCountSlots < kWave, "one accumulator row and one slot per lane");
-__device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t src) {
-  const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, (int)src, kWave);
-  const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), (int)src, kWave);
-  return ((uint64_t)hi << 32) | lo;
-}
 // Lanes share the work: lane l sums slot l over the 64 rows (column l) and
 // clears it; lane o < kOps then owns operator o and lane 2 kOps + q owns
 // k = q + 1 (their statistics, run totals and weights: loads, the Eq. ema
@@ -2677,9 +2675,10 @@ namespace {
 // clamp, normalisation and stagnation check of Alg. 2 to the solution's own
 // weights, with its own best objective in place of the instance best.  S
 // holds this wave's totals; two waves add theirs through LDS first.
+// (cap: the LNS weight cap, 0 in the variants without LNS operators)
 template <int NT>
 __device__ __forceinline__ void solution_aos_close(DevJob *J, uint32_t sol, LStats S, int64_t bf, uint32_t g1,
-                                                   uint32_t E) {
+                                                   uint32_t E, uint32_t cap) {
   constexpr int NW = (int)(sizeof(LStats) / 4);
   uint32_t *sw = (uint32_t *)&S;
   if constexpr (NT > kWave) {
@@ -2713,7 +2712,7 @@ __device__ __forceinline__ void solution_aos_close(DevJob *J, uint32_t sol, LSta
   uint32_t stag = A->stag;
   int64_t ref = A->epoch_ref;
   if (g1 % E == 0) {
-    ema_group(w, u, v, J->op_mask, kOps, J->aos_A, J->w_floor, J->lns_cap);
+    ema_group(w, u, v, J->op_mask, kOps, J->aos_A, J->w_floor, cap);
     ema_group(wk, uk, vk, 7u, 3, J->aos_A, J->w_floor, 0u);
     stag = bf < ref ? 0u : stag + 1;
     ref = bf;
@@ -2771,22 +2770,23 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
   const uint32_t *wksrc = sol_scope ? J->saos[sol].w_k : J->w_k;
   // cumulative weights of the encoding's operators (the others weigh 0): one
   // bound per operator but the last, which only adds to the total
-  constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : (rows ? 3 : 0));
-  constexpr int lo = enc_lo<ENC>(), span = enc_top<ENC, x3>() - lo;
+  constexpr bool lnsv = (VAR & kVarLns) != 0;   // LNS operators in the operator set
+  constexpr int ENC = KIND == KKNAP ? 1 : (KIND == KCOLOR ? 2 : (rows ? 3 : (lnsv ? 4 : 0)));
+  constexpr int lo = enc_lo<ENC>(), span = enc_hi<ENC>() - lo;
   uint32_t c = 0;
 #pragma unroll
   for (int i = 0; i < span; ++i) {
     c += wsrc[lo + i];
     U.cw[i] = c;
   }
-  U.sw = c + wsrc[enc_top<ENC, x3>()];
+  U.sw = c + wsrc[enc_hi<ENC>()];
   U.ck[0] = wksrc[0];
   U.ck[1] = wksrc[0] + wksrc[1];
   U.swk = U.ck[1] + wksrc[2];
 
   // LNS scratch of this wave (wide variants of single-row permutations)
   LnsCtx lx{nullptr, nullptr, nullptr};
-  if constexpr (x3 && !rows && (KIND == KTSP || KIND == KQAP || KIND == KVRP)) {
+  if constexpr (lnsv) {
     char *lb = lds + lds_core_bytes(KIND, n, VAR, I->rows) + (threadIdx.x >> 6) * lns_wave_bytes(n);
     lx.hkey = J->sums;
     lx.tabs = (LnsTab *)lb;
@@ -2814,23 +2814,23 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       if constexpr (STAGE == SLDS16) {
         stage16(rest, I->d16, 2u * n * n);
         __syncthreads();
-        if constexpr (x3) tsp_run<true>(t0, t1, nullptr, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
-        else tsp_run<false>(t0, t1, nullptr, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
+        if constexpr (x3) tsp_run<true, lnsv>(t0, t1, nullptr, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
+        else tsp_run<false, false>(t0, t1, nullptr, n, DistL16{(const int16_t *)rest, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
       } else if constexpr (STAGE == SLDSXY) {
         short2 *xy = (short2 *)rest;
         uint16_t *el = (uint16_t *)(rest + al16(4 * n));
         for (int p = lane; p < n; p += kWave) xy[p] = make_short2((short)I->xy[2 * p], (short)I->xy[2 * p + 1]);
         __syncthreads();
-        if constexpr (x3) tsp_run<true>(t0, t1, el, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
-        else tsp_run<false>(t0, t1, el, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
+        if constexpr (x3) tsp_run<true, lnsv>(t0, t1, el, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
+        else tsp_run<false, false>(t0, t1, el, n, DistXY{xy}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
       } else if constexpr (STAGE == SGLB16) {
         __syncthreads();
-        if constexpr (x3) tsp_run<true>(t0, t1, nullptr, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
-        else tsp_run<false>(t0, t1, nullptr, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
+        if constexpr (x3) tsp_run<true, lnsv>(t0, t1, nullptr, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
+        else tsp_run<false, false>(t0, t1, nullptr, n, DistG16{I->d16, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
       } else {
         __syncthreads();
-        if constexpr (x3) tsp_run<true>(t0, t1, nullptr, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
-        else tsp_run<false>(t0, t1, nullptr, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
+        if constexpr (x3) tsp_run<true, lnsv>(t0, t1, nullptr, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
+        else tsp_run<false, false>(t0, t1, nullptr, n, DistG32{I->d32, n}, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, lx);
       }
       perm_store(t0, n, cur_g);
     } else if constexpr (KIND == KQAP) {
@@ -2858,8 +2858,8 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
                   I->qap_sums32 != 0};
       __syncthreads();
       kd.setup(I->qf);
-      if constexpr (x3) round_gens<true>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk, lx);
-      else round_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk, lx);
+      if constexpr (x3) round_gens<true, lnsv>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk, lx);
+      else round_gens<false, false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk, lx);
       if (wv == 0) perm_store(kd.cur, n, cur_g);
     } else {
       // int16 distances, the per-node (demand, ready, due) records, the two
@@ -2877,15 +2877,15 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
       if constexpr ((VAR & kVarLex) != 0) {
         const LexCfg L = lex_cfg(I);
         Vec4 cv = load_vec(J->cur_v + 4 * (size_t)sol), bsv = load_vec(J->best_v + 4 * (size_t)sol);
-        lex_rounds<x3>(kd, W, U, L, best_row, sol, g0, g1, T, f, bf, cv, bsv, S, nacc, (int64_t *)(xk + 2), lx);
+        lex_rounds<x3, lnsv>(kd, W, U, L, best_row, sol, g0, g1, T, f, bf, cv, bsv, S, nacc, (int64_t *)(xk + 2), lx);
         if (threadIdx.x == 0) {
           store_vec(J->cur_v + 4 * (size_t)sol, cv);
           store_vec(J->best_v + 4 * (size_t)sol, bsv);
         }
       } else if constexpr (x3) {
-        round_gens<true>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk, lx);
+        round_gens<true, lnsv>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk, lx);
       } else {
-        round_gens<false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk, lx);
+        round_gens<false, false>(kd, W, U, best_row, sol, g0, g1, T, f, bf, S, nacc, xk, lx);
       }
       if (threadIdx.x < kWave) perm_store(kd.cur, n, cur_g);
     }
@@ -2923,8 +2923,8 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     J->cur_f[sol] = f;
     J->best_f[sol] = bf;
   }
-  if (sol_scope) solution_aos_close<kThreads<KIND, VAR>>(J, sol, S, bf, g1, E);
-  write_counts<ENC, true, x3>(J, sol, S, nacc, bf);   // every wave adds the counts of its own candidates
+  if (sol_scope) solution_aos_close<kThreads<KIND, VAR>>(J, sol, S, bf, g1, E, lnsv ? J->lns_cap : 0u);
+  write_counts<ENC, true>(J, sol, S, nacc, bf);   // every wave adds the counts of its own candidates
 }
 
 }  // namespace
@@ -3510,10 +3510,25 @@ hipError_t set_stop(DevJob *jobs, int count, uint32_t add, int use_total, hipStr
 }
 
 // the kernel of a (kind, variant): variant = staging | kVarX3 (3-opt) | kVarLex (VRPTW lexicographic)
-// | kVarRows (VRPTW multi-row)
+// | kVarRows (VRPTW multi-row) | kVarLns (LNS operators; always with kVarX3)
 #define GX_KERNEL_OF(KERNEL)                                                                 \
   static const void *KERNEL##_of(int kind, int var) {                                      \
     const bool x3 = (var & kVarX3) != 0;                                                     \
+    if (var & kVarLns) switch (kind) {                                                       \
+        case KTSP:                                                                           \
+          switch (var & 7) {                                                                 \
+            case SLDS16: return (const void *)KERNEL<KTSP, SLDS16 | kVarX3 | kVarLns>;       \
+            case SLDSXY: return (const void *)KERNEL<KTSP, SLDSXY | kVarX3 | kVarLns>;       \
+            case SGLB16: return (const void *)KERNEL<KTSP, SGLB16 | kVarX3 | kVarLns>;       \
+            default: return (const void *)KERNEL<KTSP, SGLB32 | kVarX3 | kVarLns>;           \
+          }                                                                                  \
+        case KQAP:                                                                           \
+          if ((var & 7) == 1) return (const void *)KERNEL<KQAP, 1 | kVarX3 | kVarLns>;       \
+          return (const void *)KERNEL<KQAP, kVarX3 | kVarLns>;                               \
+        default:                                                                             \
+          if (var & kVarLex) return (const void *)KERNEL<KVRP, kVarLex | kVarX3 | kVarLns>;  \
+          return (const void *)KERNEL<KVRP, kVarX3 | kVarLns>;                               \
+      }                                                                                      \
     switch (kind) {                                                                          \
       case KTSP:                                                                             \
         switch (var & 7) {                                                                   \
@@ -3553,7 +3568,11 @@ hipError_t prepare_kernel_attrs(uint32_t max_lds) {
                           {KTSP, SGLB32 | kVarX3}, {KQAP, kVarX3},          {KQAP, 1 | kVarX3},
                           {KVRP, kVarX3},          {KVRP, kVarLex},         {KVRP, kVarLex | kVarX3},
                           {KVRP, kVarRows},        {KVRP, kVarRows | kVarX3},
-                          {KVRP, kVarRows | kVarLex}, {KVRP, kVarRows | kVarLex | kVarX3}};
+                          {KVRP, kVarRows | kVarLex}, {KVRP, kVarRows | kVarLex | kVarX3},
+                          {KTSP, SLDS16 | kVarX3 | kVarLns}, {KTSP, SLDSXY | kVarX3 | kVarLns},
+                          {KTSP, SGLB16 | kVarX3 | kVarLns}, {KTSP, SGLB32 | kVarX3 | kVarLns},
+                          {KQAP, kVarX3 | kVarLns}, {KQAP, 1 | kVarX3 | kVarLns},
+                          {KVRP, kVarX3 | kVarLns}, {KVRP, kVarLex | kVarX3 | kVarLns}};
   for (auto &k : kinds) {
     hipError_t e = hipFuncSetAttribute(plain_kernel(k[0], k[1]), hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)max_lds);

@@ -166,3 +166,34 @@ def test_lns_masks(ctx):
     assert not st["w_op"][5:8].any()                 # op_mask 0: no LNS
     gx.gx_job_free(ctx, job)
     gx.gx_instance_free(ctx, h)
+
+
+def test_served_lanes_keep_variants_apart(ctx):
+    """Requests of one kind that need different kernels (LNS or not, giant
+    tour or rows) are served together, each equal to the oracle."""
+    import time
+    reqs = [(synth.tsp_uniform(40, 8, key=70), P(30, seed=1, population=4, op_mask=ALL, epoch=20,
+                                                  init_weight_q16=RAISED)),
+            (synth.tsp_uniform(40, 9, key=71), P(30, seed=2, population=4, op_mask=synth.PERM_OPS)),
+            (synth.vrptw_random(20, 3, key=72), P(30, seed=3, population=4)),
+            (synth.vrptw_rows(20, 3, key=73, vehicles=4), P(30, seed=4, population=4)),
+            (synth.vrptw_random(20, 4, key=74), P(30, seed=5, population=4, op_mask=ALL, init_weight_q16=RAISED)),
+            (synth.qap_random(16, 5, key=75), P(30, seed=6, population=4, op_mask=ALL, init_weight_q16=RAISED))]
+    srv = gx.gx_server_create(ctx, quantum_epochs=1)
+    tickets = [gx.gx_server_submit(srv, i, p) for i, p in reqs]
+    got = {}
+    t_end = time.time() + 60
+    while len(got) < len(reqs) and time.time() < t_end:
+        for k, t in enumerate(tickets):
+            if k not in got:
+                r = gx.gx_server_poll(srv, t, synth.solution_len(reqs[k][0]))
+                if r is not None:
+                    got[k] = r
+        time.sleep(0.002)
+    gx.gx_server_destroy(srv)
+    assert len(got) == len(reqs), f"served {sorted(got)} of {len(reqs)}"
+    for k, (inst, p) in enumerate(reqs):
+        o = oracle.OracleInstance(inst)
+        st = o.solve(p)
+        fo, io = o.best_of(st)
+        assert got[k][1] == fo and np.array_equal(got[k][0], st["best"][io]), (k, got[k][1], fo)

@@ -230,10 +230,14 @@ def test_rows_refusals(ctx):
     # operators of other encodings enable nothing here
     with pytest.raises(gx.GxError):
         gx.gx_job_create(ctx, h, P(5, seed=1, population=2, op_mask=1 << synth.OP_FLIP))
-    # the giant tour takes no row operators: only its own bits count
-    g = gx.gx_instance_upload(ctx, synth.vrptw_random(12, 2, key=67))
-    with pytest.raises(gx.GxError):
-        gx.gx_job_create(ctx, g, P(5, seed=1, population=2, op_mask=R_OPS))
+    # on the giant tour the same bits name the LNS operators, not the row ones
+    gi = synth.vrptw_random(12, 2, key=67)
+    g = gx.gx_instance_upload(ctx, gi)
+    job = gx.gx_job_create(ctx, g, P(5, seed=1, population=2, op_mask=R_OPS))
+    w = gx.gx_snapshot(ctx, job, 2, gi.n)["w_op"]
+    o = oracle.OracleInstance(gi)
+    assert list(w) == list(o.initial_weights(R_OPS)) and o.lns_cap() > 0
+    gx.gx_job_free(ctx, job)
     gx.gx_instance_free(ctx, g)
     gx.gx_instance_free(ctx, h)
 
