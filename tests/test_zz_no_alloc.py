@@ -1,9 +1,10 @@
 """gx_solve_static (the entry point that allocates nothing: its device state
 lives in the library's static workspace) against gx_solve on the same
-requests: three calls in a row, each smaller than the one before (the last a
-VRPTW instance in the lexicographic mode, whose objective vectors live in the
-workspace too), each equal to the plain solve in its best solution and
-objective; a solve larger than the workspace is refused on the host."""
+requests: five calls in a row, each smaller than the one before (a VRPTW
+instance in the lexicographic mode, whose objective vectors live in the
+workspace too, a multi-row VRPTW and a TSP with the LNS operators among
+them), each equal to the plain solve in its best solution and objective; a
+solve larger than the workspace is refused on the host."""
 import dataclasses
 
 import numpy as np
@@ -18,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 def _plain(ctx, h, inst, p):
     job = gx.gx_solve(ctx, h, p)
-    sol, f = gx.gx_fetch_best(ctx, job, inst.n)
+    sol, f = gx.gx_fetch_best(ctx, job, synth.solution_len(inst))
     gx.gx_job_free(ctx, job)
     return sol, f
 
@@ -33,11 +34,17 @@ def test_static_solves_equal_plain_solves():
                 # a VRPTW instance in the lexicographic mode: its objective vectors in the workspace too
                 (dataclasses.replace(synth.vrptw_random(16, 3, key=64), vehicles=2, lex_order=(2, 1, 0),
                                      lex_tol=(0, 15, 0)),
-                 synth.Params(seed=9, generations=40, population=4, alpha_q32=synth.alpha_q32_for(40)))]
+                 synth.Params(seed=9, generations=40, population=4, alpha_q32=synth.alpha_q32_for(40))),
+                # the multi-row form (rows closed by markers) and the LNS operators' kernels
+                (synth.vrptw_rows(12, 3, key=65, vehicles=3),
+                 synth.Params(seed=11, generations=30, population=3, alpha_q32=synth.alpha_q32_for(30))),
+                (synth.tsp_uniform(20, 3, key=66),
+                 synth.Params(seed=13, generations=30, population=2, alpha_q32=synth.alpha_q32_for(30),
+                              op_mask=synth.PERM_LNS_OPS, init_weight_q16=[0, 0, 0, 0, 0, 20000, 20000, 20000]))]
         for inst, p in reqs:                      # each call smaller than the one before
             print(f"[static] kind {inst.kind} n={inst.n} P={p.population}", flush=True)
             h = gx.gx_instance_upload(ctx, inst)
-            sol_d = torch.full((inst.n,), -1, dtype=torch.int32, device="cuda")
+            sol_d = torch.full((synth.solution_len(inst),), -1, dtype=torch.int32, device="cuda")
             obj_d = torch.zeros(1, dtype=torch.int64, device="cuda")
             torch.cuda.synchronize()
             gx.gx_solve_static(ctx, h, p, sol_d, obj_d)
