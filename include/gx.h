@@ -230,6 +230,12 @@ gx_status gx_instance_free(gx_ctx *ctx, gx_instance *inst);
  *                  takes the Tab. weight_preset value (1.0; or-opt 0.8 / 0.7 /
  *                  0.3 and 3-opt 0.5 / 0.3 / 0.05 for n <= 100, <= 250, > 250);
  *                  the enabled operators' raw weights are then normalised
+ *  weight_cap_q16  per-sequence weight cap of operator id i, Q16 in [1, 2^16]
+ *                  (Sec. "Two-Level Weight Structure": the Eq. ema update
+ *                  clamps weight i to [w_floor, min(1, cap_i)], to [cap_i,
+ *                  cap_i] when cap_i is below the floor); 0 takes the default:
+ *                  the LNS cap of Tab. weight_preset for the LNS operators,
+ *                  1.0 for the others
  * Island model and elite injection (paper, Sec. "Island Model and Elite
  * Injection"), applied at the end of an AOS epoch e, after the weight update:
  *  islands         I islands of P / I consecutive solutions (P a multiple of
@@ -255,6 +261,7 @@ typedef struct {
   uint32_t islands, migrate_epochs, migrate_mode, migrate_n;
   uint32_t elite_epochs, aos_scope;
   uint32_t init_weight_q16[GX_N_OPS];
+  uint32_t weight_cap_q16[GX_N_OPS];
 } gx_solve_params;
 
 /* Population the library would use for P = 0 on this instance: the CUs times

@@ -51,7 +51,8 @@ class _Params(C.Structure):
                 ("w_floor_q16", C.c_uint32), ("stagnation_epochs", C.c_uint32),
                 ("credit", C.c_uint32), ("oversample_k", C.c_uint32), ("islands", C.c_uint32),
                 ("migrate_epochs", C.c_uint32), ("migrate_mode", C.c_uint32), ("migrate_n", C.c_uint32),
-                ("elite_epochs", C.c_uint32), ("aos_scope", C.c_uint32), ("init_w", C.c_uint32 * N_OPS)]
+                ("elite_epochs", C.c_uint32), ("aos_scope", C.c_uint32), ("init_w", C.c_uint32 * N_OPS),
+                ("cap_w", C.c_uint32 * N_OPS)]
 
 
 # per-solution AOS state (or_sol_aos), as a numpy record
@@ -190,12 +191,17 @@ def _params(p) -> _Params:
                    migrate_epochs=p.migrate_epochs, migrate_mode=p.migrate_mode,
                    migrate_n=p.migrate_n, elite_epochs=p.elite_epochs,
                    aos_scope=getattr(p, "aos_scope", 0),
-                   init_w=(C.c_uint32 * N_OPS)(*_init_w(p)))
+                   init_w=(C.c_uint32 * N_OPS)(*_init_w(p)),
+                   cap_w=(C.c_uint32 * N_OPS)(*_per_op(p, "weight_cap_q16")))
+
+
+def _per_op(p, name):
+    w = list(getattr(p, name, ()) or ())
+    return [int(x) for x in w] + [0] * (N_OPS - len(w))
 
 
 def _init_w(p):
-    w = list(getattr(p, "init_weight_q16", ()) or ())
-    return [int(x) for x in w] + [0] * (N_OPS - len(w))
+    return _per_op(p, "init_weight_q16")
 
 
 class OracleInstance:

@@ -619,6 +619,14 @@ uint32_t or_lns_cap(const or_inst *in) {
   return n <= 100 ? 1311u : (n <= 250 ? 655u : 328u);
 }
 
+/* the per-sequence caps of a solve: the caller's, else the LNS cap for the
+ * LNS operators and 1.0 for the others */
+static void op_caps(const or_inst *in, const or_params *p, uint32_t caps[OR_MAX_OPS]) {
+  const uint32_t lc = or_lns_cap(in);
+  for (int i = 0; i < OR_MAX_OPS; ++i)
+    caps[i] = p->cap_w[i] ? p->cap_w[i] : ((lc && i >= OP_LNS_SEG && i <= OP_LNS_GUIDED) ? lc : 65536u);
+}
+
 static int enabled_list(uint32_t mask, int *ids) {
   int c = 0;
   for (int i = 0; i < OR_MAX_OPS; ++i) if (mask & (1u << i)) ids[c++] = i;
@@ -677,17 +685,18 @@ uint64_t or_cool(uint64_t t, uint32_t alpha) {
  * Eq. ema: w <- a w + (1-a)(v/(u+eps) + w_floor); clamp to [w_floor, 1];
  * normalise; Alg. 2 also updates the K-step weights the same way and resets
  * them to (0.8, 0.15, 0.05) after stagnation. */
-/* cap: the LNS cap (Q16) of ids 5-7, 0 when they are not LNS operators (and
- * for the K-step group) */
+/* Eq. ema, then the clamp to [w_floor, min(w_cap, cap_i)] with w_cap = 1.0
+ * and cap_i the per-sequence cap of operator i (Sec. "Two-Level Weight
+ * Structure"); reading: when cap_i is below the floor the clamp is [cap_i,
+ * cap_i].  caps: per operator id, NULL for the K-step group. */
 static void ema_group(const or_params *p, uint32_t *w, const uint64_t *u, const uint64_t *v,
-                      const int *ids, int cnt, uint32_t cap) {
+                      const int *ids, int cnt, const uint32_t *caps) {
   uint64_t A = p->aos_alpha_q16, FL = p->w_floor_q16, s = 0;
   for (int c = 0; c < cnt; ++c) {
     int i = ids[c];
     uint64_t r = (v[i] << 16) / (u[i] + 1);
     uint64_t nw = (A * w[i] + (65536 - A) * (r + FL)) >> 16;
-    const int lns = cap && i >= OP_LNS_SEG && i <= OP_LNS_GUIDED;
-    const uint64_t lo = lns ? (cap < FL ? cap : FL) : FL, hi = lns ? cap : 65536;
+    const uint64_t hi = caps ? caps[i] : 65536, lo = hi < FL ? hi : FL;
     if (nw < lo) nw = lo;
     if (nw > hi) nw = hi;
     w[i] = (uint32_t)nw;
@@ -703,12 +712,12 @@ static void ema_group(const or_params *p, uint32_t *w, const uint64_t *u, const 
 static const uint32_t WK_DEFAULT[3] = {52429, 9830, 3277};
 
 /* the update with the epoch's improvement of the instance best given */
-static void aos_update_flag(const or_params *p, uint32_t mask, uint32_t cap, or_state *st, int improved) {
+static void aos_update_flag(const or_params *p, uint32_t mask, const uint32_t *caps, or_state *st, int improved) {
   int ids[OR_MAX_OPS];
   int cnt = enabled_list(mask, ids);
-  ema_group(p, st->w_op, st->u_op, st->v_op, ids, cnt, cap);
+  ema_group(p, st->w_op, st->u_op, st->v_op, ids, cnt, caps);
   int kid[3] = {0, 1, 2};
-  ema_group(p, st->w_k, st->u_k, st->v_k, kid, 3, 0);
+  ema_group(p, st->w_k, st->u_k, st->v_k, kid, 3, NULL);
   /* reading: "consecutive no-improvement" counted in epochs of the instance best */
   if (improved) st->stag = 0;
   else st->stag++;
@@ -725,7 +734,9 @@ static void aos_update_flag(const or_params *p, uint32_t mask, uint32_t cap, or_
 void or_aos_update(const or_inst *in, const or_params *p, uint32_t mask, or_state *st, int64_t inst_best_now) {
   int improved = inst_best_now < st->epoch_ref;
   st->epoch_ref = inst_best_now;
-  aos_update_flag(p, mask, or_lns_cap(in), st, improved);
+  uint32_t caps[OR_MAX_OPS];
+  op_caps(in, p, caps);
+  aos_update_flag(p, mask, caps, st, improved);
 }
 
 /* Per-solution scope (aos_scope = 1).  reading: Alg. 2 pools the statistics
@@ -734,15 +745,15 @@ void or_aos_update(const or_inst *in, const or_params *p, uint32_t mask, or_stat
  * candidates' counts with the same Eq. ema arithmetic, and its own
  * stagnation counter on its own best objective.  The instance-level weights
  * and epoch counts are then not used and stay as initialised. */
-static void sol_aos_update(const or_params *p, uint32_t mask, uint32_t cap, or_sol_aos *a, int64_t best_now) {
+static void sol_aos_update(const or_params *p, uint32_t mask, const uint32_t *caps, or_sol_aos *a, int64_t best_now) {
   int ids[OR_MAX_OPS];
   int cnt = enabled_list(mask, ids);
   uint64_t u[OR_MAX_OPS], v[OR_MAX_OPS], uk[3], vk[3];
   for (int i = 0; i < OR_MAX_OPS; ++i) { u[i] = a->u_op[i]; v[i] = a->v_op[i]; }
   for (int i = 0; i < 3; ++i) { uk[i] = a->u_k[i]; vk[i] = a->v_k[i]; }
-  ema_group(p, a->w_op, u, v, ids, cnt, cap);
+  ema_group(p, a->w_op, u, v, ids, cnt, caps);
   int kid[3] = {0, 1, 2};
-  ema_group(p, a->w_k, uk, vk, kid, 3, 0);
+  ema_group(p, a->w_k, uk, vk, kid, 3, NULL);
   if (best_now < a->epoch_ref) a->stag = 0;
   else a->stag++;
   a->epoch_ref = best_now;
@@ -1283,14 +1294,16 @@ static void add_counts(const or_params *p, or_state *st, int sol, const or_count
  * scope, then migration (Alg. 2; Sec. "Island Model and Elite Injection"). */
 static void epoch_end(const or_inst *in, const or_params *p, or_state *st, uint32_t g_end, uint32_t mask) {
   int P = p->population;
+  uint32_t caps[OR_MAX_OPS];
+  op_caps(in, p, caps);
   if (or_lex_mode(in)) {   /* the instance best by the ordered scan; improved when strictly better */
     int b = or_lex_best(in, st, P);
     int improved = or_lex_better(in, st->best_v + 4 * (size_t)b, st->ref_v);
     memcpy(st->ref_v, st->best_v + 4 * (size_t)b, sizeof(st->ref_v));
     st->epoch_ref = st->best_f[b];
-    aos_update_flag(p, mask, or_lns_cap(in), st, improved);
+    aos_update_flag(p, mask, caps, st, improved);
   } else if (p->aos_scope == 1) {
-    for (int s = 0; s < P; ++s) sol_aos_update(p, mask, or_lns_cap(in), &st->saos[s], st->best_f[s]);
+    for (int s = 0; s < P; ++s) sol_aos_update(p, mask, caps, &st->saos[s], st->best_f[s]);
   } else {
     int64_t ib = st->best_f[0];
     for (int s = 1; s < P; ++s) if (st->best_f[s] < ib) ib = st->best_f[s];

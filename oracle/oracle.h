@@ -52,6 +52,9 @@ typedef struct {
   uint32_t aos_scope;
   /* initial raw operator weights, Q16; 0 selects the Tab. weight_preset value */
   uint32_t init_w[OR_MAX_OPS];
+  /* per-operator weight caps (Q16, <= 65536); 0 selects the default: the LNS
+   * cap of Tab. weight_preset for the LNS operators, 1.0 for the others */
+  uint32_t cap_w[OR_MAX_OPS];
 } or_params;
 
 /* Per-solution adaptive-operator-selection state (aos_scope = 1). */

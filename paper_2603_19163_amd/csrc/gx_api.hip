@@ -646,6 +646,8 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
     return fail(c, GX_E_INVALID, "per-solution weights need aos_epoch * candidates <= 2^30");
   for (int i = 0; i < kOps; ++i)
     if (p->init_weight_q16[i] > (1u << 24)) return fail(c, GX_E_INVALID, "init_weight_q16 entries <= 2^24");
+  for (int i = 0; i < kOps; ++i)
+    if (p->weight_cap_q16[i] > 65536u) return fail(c, GX_E_INVALID, "weight_cap_q16 entries <= 2^16");
   if (ii.h.lex_levels && p->aos_scope)
     return fail(c, GX_E_UNSUPPORTED, "the lexicographic mode takes aos_scope 0");
   const uint32_t lds = job_lds(ii, stage, mask);
@@ -679,6 +681,9 @@ gx_status fill_job(gx_ctx *c, const InstInfo &ii, const gx_solve_params *p, DevJ
   h.lex_levels = (uint32_t)ii.h.lex_levels;
   h.rows = (uint32_t)ii.h.rows;
   h.lns_cap = lns_cap_of(ii.h);
+  for (int i = 0; i < kOps; ++i)   // the caller's caps, else the LNS cap or 1.0
+    h.w_cap[i] = p->weight_cap_q16[i] ? p->weight_cap_q16[i]
+                                      : ((h.lns_cap && ((kLnsMask >> i) & 1u)) ? h.lns_cap : 65536u);
   return GX_OK;
 }
 

@@ -96,6 +96,7 @@ struct DevJob {
   uint32_t stage, lds_bytes, islands, mig_epochs;   // island model: see gx_solve_params
   uint32_t mig_mode, mig_n, elite_epochs, aos_scope;   // aos_scope: 0 instance, 1 per solution
   uint32_t init_w[kOps];      // caller's raw initial weights (0: Tab. weight_preset)
+  uint32_t w_cap[kOps];       // per-sequence weight caps (Q16; the caller's or the defaults)
   uint32_t lex_levels;        // levels of the lexicographic mode (0: scalar objective)
   uint32_t rows;              // rows of a multi-row VRPTW solution (0: other kinds)
   // ---- mutable state

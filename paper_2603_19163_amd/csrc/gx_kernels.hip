@@ -2165,18 +2165,18 @@ __device__ __forceinline__ uint64_t udiv_q24(uint64_t num, uint64_t den) {
 
 // Eq. ema per enabled operator and per K-step, clamp to [floor, 1], normalise;
 // stagnation of the instance best resets the K-step weights (Alg. 2).
-// cap: the LNS weight cap (Tab. weight_preset) of ids 5-7, 0 when they are not
-// LNS operators; an LNS weight is clamped to [min(floor, cap), cap]
+// caps: the per-sequence weight caps (null for the K-step group); weight i is
+// clamped to [min(floor, cap_i), cap_i]
 __device__ __forceinline__ void ema_group(uint32_t *w, const unsigned long long *u, const unsigned long long *v, uint32_t mask,
-                          int cnt, uint32_t A, uint32_t FL, uint32_t cap) {
+                          int cnt, uint32_t A, uint32_t FL, const uint32_t *caps) {
   uint64_t s = 0;
   for (int i = 0; i < cnt; ++i) {
     if (!(mask & (1u << i))) continue;
     const uint64_t r = udiv_q24((uint64_t)v[i] << 16, u[i] + 1);
     uint64_t nw = ((uint64_t)A * w[i] + (uint64_t)(65536 - A) * (r + FL)) >> 16;
     nw = nw < FL ? FL : (nw > 65536 ? 65536 : nw);
-    // an LNS weight: [min(floor, cap), cap], i.e. the clamp above, then at most cap
-    if (cap && ((kLnsMask >> i) & 1u)) nw = nw > cap ? cap : nw;
+    // [min(floor, cap), cap]: the clamp above, then at most the cap
+    if (caps && nw > caps[i]) nw = caps[i];
     w[i] = (uint32_t)nw;
     s += nw;
   }
@@ -2511,13 +2511,14 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
   const uint32_t q = l - 2 * kOps;   // k lanes
   // this lane's own state first (one batch of loads, no store between)
   uint64_t u = 0, v = 0, tu = 0, tv = 0;
-  uint32_t w = 0;
+  uint32_t w = 0, cap = 65536;
   if (op_lane) {
     u = J->u_op[l];
     v = J->v_op[l];
     tu = J->tot_u_op[l];
     tv = J->tot_v_op[l];
     w = J->w_op[l];
+    cap = J->w_cap[l];
   } else if (k_lane) {
     u = J->u_k[q];
     v = J->v_k[q];
@@ -2526,7 +2527,7 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
     w = J->w_k[q];
   }
   const uint32_t alpha = J->alpha, op_mask = J->op_mask, aos_A = J->aos_A;
-  const uint32_t w_floor = J->w_floor, stag_limit = J->stag_limit, lns_cap = J->lns_cap;
+  const uint32_t w_floor = J->w_floor, stag_limit = J->stag_limit;
   // per-solution weights: the evolve workgroups update them; the instance
   // statistics and weights stay as initialised
   const bool inst_scope = J->aos_scope == 0;
@@ -2572,12 +2573,11 @@ __device__ __forceinline__ void epoch_fold(DevJob *J, uint32_t g0, uint32_t E, u
     // Eq. ema on every enabled operator and on the k weights, clamp, then normalisation per group
     const bool upd = (op_lane && ((op_mask >> l) & 1u)) || k_lane;
     uint64_t nw = 0;
-    if (upd) {   // an LNS weight is clamped to [min(floor, cap), cap]
+    if (upd) {   // clamped to [min(floor, cap), cap] (an operator's cap; 1.0 for the k weights)
       const uint64_t r = udiv_q24(v << 16, u + 1);
       nw = ((uint64_t)aos_A * w + (uint64_t)(65536 - aos_A) * (r + w_floor)) >> 16;
-      const bool lns = op_lane && lns_cap && ((kLnsMask >> l) & 1u);
-      const uint64_t lo = lns ? min(w_floor, lns_cap) : w_floor, hi = lns ? lns_cap : 65536u;
-      nw = nw < lo ? lo : (nw > hi ? hi : nw);
+      const uint64_t lo = min(w_floor, cap);
+      nw = nw < lo ? lo : (nw > cap ? cap : nw);
     }
     const uint32_t s_op = wave_sum(op_lane ? (uint32_t)nw : 0u), s_k = wave_sum(k_lane ? (uint32_t)nw : 0u);
     if (upd) {
@@ -2675,10 +2675,9 @@ namespace {
 // clamp, normalisation and stagnation check of Alg. 2 to the solution's own
 // weights, with its own best objective in place of the instance best.  S
 // holds this wave's totals; two waves add theirs through LDS first.
-// (cap: the LNS weight cap, 0 in the variants without LNS operators)
 template <int NT>
 __device__ __forceinline__ void solution_aos_close(DevJob *J, uint32_t sol, LStats S, int64_t bf, uint32_t g1,
-                                                   uint32_t E, uint32_t cap) {
+                                                   uint32_t E) {
   constexpr int NW = (int)(sizeof(LStats) / 4);
   uint32_t *sw = (uint32_t *)&S;
   if constexpr (NT > kWave) {
@@ -2712,8 +2711,8 @@ __device__ __forceinline__ void solution_aos_close(DevJob *J, uint32_t sol, LSta
   uint32_t stag = A->stag;
   int64_t ref = A->epoch_ref;
   if (g1 % E == 0) {
-    ema_group(w, u, v, J->op_mask, kOps, J->aos_A, J->w_floor, cap);
-    ema_group(wk, uk, vk, 7u, 3, J->aos_A, J->w_floor, 0u);
+    ema_group(w, u, v, J->op_mask, kOps, J->aos_A, J->w_floor, J->w_cap);
+    ema_group(wk, uk, vk, 7u, 3, J->aos_A, J->w_floor, nullptr);
     stag = bf < ref ? 0u : stag + 1;
     ref = bf;
     if (stag >= J->stag_limit) {
@@ -2923,7 +2922,7 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
     J->cur_f[sol] = f;
     J->best_f[sol] = bf;
   }
-  if (sol_scope) solution_aos_close<kThreads<KIND, VAR>>(J, sol, S, bf, g1, E, lnsv ? J->lns_cap : 0u);
+  if (sol_scope) solution_aos_close<kThreads<KIND, VAR>>(J, sol, S, bf, g1, E);
   write_counts<ENC, true>(J, sol, S, nacc, bf);   // every wave adds the counts of its own candidates
 }
 

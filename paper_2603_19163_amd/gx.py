@@ -51,7 +51,7 @@ class gx_solve_params(C.Structure):
                 ("aos_credit", C.c_uint32), ("oversample_k", C.c_uint32), ("staging", C.c_uint32),
                 ("islands", C.c_uint32), ("migrate_epochs", C.c_uint32), ("migrate_mode", C.c_uint32),
                 ("migrate_n", C.c_uint32), ("elite_epochs", C.c_uint32), ("aos_scope", C.c_uint32),
-                ("init_weight_q16", C.c_uint32 * N_OPS)]
+                ("init_weight_q16", C.c_uint32 * N_OPS), ("weight_cap_q16", C.c_uint32 * N_OPS)]
 
 
 class gx_device_info(C.Structure):
@@ -282,14 +282,19 @@ def _params(p) -> gx_solve_params:
                            islands=getattr(p, "islands", 0), migrate_epochs=getattr(p, "migrate_epochs", 0),
                            migrate_mode=getattr(p, "migrate_mode", 0), migrate_n=getattr(p, "migrate_n", 0),
                            elite_epochs=getattr(p, "elite_epochs", 0), aos_scope=getattr(p, "aos_scope", 0),
-                           init_weight_q16=(C.c_uint32 * N_OPS)(*_init_w(p)))
+                           init_weight_q16=(C.c_uint32 * N_OPS)(*_init_w(p)),
+                           weight_cap_q16=(C.c_uint32 * N_OPS)(*_per_op(p, "weight_cap_q16")))
+
+
+def _per_op(p, name):
+    w = [int(x) for x in (getattr(p, name, ()) or ())]
+    if len(w) > N_OPS:
+        raise ValueError(f"at most {N_OPS} entries in {name}")
+    return w + [0] * (N_OPS - len(w))
 
 
 def _init_w(p):
-    w = [int(x) for x in (getattr(p, "init_weight_q16", ()) or ())]
-    if len(w) > N_OPS:
-        raise ValueError(f"at most {N_OPS} initial weights")
-    return w + [0] * (N_OPS - len(w))
+    return _per_op(p, "init_weight_q16")
 
 
 def gx_autosize_population(ctx, inst, params) -> int:

@@ -112,6 +112,7 @@ class Params:
     elite_epochs: int = 0      # elite injection every this many epochs (0 = never)
     aos_scope: int = 0         # 0 weights per instance, 1 per solution
     init_weight_q16: tuple = ()  # raw initial operator weights by id (0 = preset)
+    weight_cap_q16: tuple = ()   # per-operator weight caps by id (0 = default)
 
     def with_(self, **kw) -> "Params":
         return replace(self, **kw)

@@ -38,7 +38,7 @@ def P(G, **kw):
 
 
 def compare(ctx, job, p, inst, st, what, lex=False):
-    g = gx.gx_snapshot(ctx, job, p.population, inst.n)
+    g = gx.gx_snapshot(ctx, job, p.population, synth.solution_len(inst))
     for k in KEYS:
         a, b = np.asarray(g[k]), np.asarray(st[k])
         assert np.array_equal(a, b), f"{what}: {k} gpu {a.ravel()[:10]} oracle {b.ravel()[:10]}"
@@ -67,7 +67,7 @@ def run_parity(ctx, inst, p, splits, what, lex=False, threads=1):
     gx.gx_job_free(ctx, job)
     job = gx.gx_solve(ctx, h, p)
     gx.gx_wait(ctx, job)
-    sol, f = gx.gx_fetch_best(ctx, job, inst.n)
+    sol, f = gx.gx_fetch_best(ctx, job, synth.solution_len(inst))
     fo, io = o.best_of(st)
     assert f == fo and np.array_equal(sol, st["best"][io]), (what, f, fo)
     gx.gx_job_free(ctx, job)
@@ -197,3 +197,17 @@ def test_served_lanes_keep_variants_apart(ctx):
         st = o.solve(p)
         fo, io = o.best_of(st)
         assert got[k][1] == fo and np.array_equal(got[k][0], st["best"][io]), (k, got[k][1], fo)
+
+
+@pytest.mark.parametrize("scope", [0, 1])
+def test_per_sequence_caps(ctx, scope):
+    """Caller weight caps (one above the floor, one below it, defaults for the
+    rest), under both AOS scopes, and on the multi-row VRPTW's row operators."""
+    caps = [20000, 500, 0, 0, 0, 0, 900, 0]
+    inst = synth.tsp_uniform(50, 4, key=80)
+    p = P(40, seed=3, population=4, candidates=128, op_mask=ALL, epoch=4, aos_scope=scope, weight_cap_q16=caps)
+    run_parity(ctx, inst, p, [13, 27], f"caps scope {scope}")
+    rows = dataclasses.replace(synth.vrptw_rows(18, 5, key=81, vehicles=4), capacity=70)
+    pr = P(30, seed=4, population=4, candidates=128, epoch=3, aos_scope=scope,
+           weight_cap_q16=[0, 0, 3000, 0, 0, 600, 0, 40000])
+    run_parity(ctx, rows, pr, [30], f"rows caps scope {scope}")

@@ -219,3 +219,33 @@ def test_runs_with_lns_stay_valid(which):
         assert sorted(a["cur"][s]) == list(range(inst.n))
         assert a["cur_f"][s] == o.objective(a["cur"][s]) and a["best_f"][s] == o.objective(a["best"][s])
     assert int(a["tot_u_op"][5:8].sum()) > 0
+
+
+def test_per_sequence_caps_by_hand():
+    """Caller caps (Sec. "Two-Level Weight Structure": the clamp is [w_floor,
+    min(w_cap, cap_i)]): a cap above the floor bounds the weight, a cap below
+    it pins the weight to the cap, 0 keeps the default (1.0, or the LNS cap)."""
+    inst = synth.tsp_uniform(90, 5)
+    o = oracle.OracleInstance(inst)
+    caps = [20000, 500, 0, 0, 0, 0, 900, 0]
+    p = synth.Params(seed=1, generations=10, population=2, candidates=8, op_mask=synth.PERM_LNS_OPS,
+                     alpha_q32=synth.alpha_q32_for(10), weight_cap_q16=caps)
+    st = o.init(p)
+    st["w_op"][:] = 0
+    st["w_op"][:8] = [30000, 20000, 10000, 5000, 5000, 393, 393, 393]
+    st["u_op"][:] = 0
+    st["v_op"][:] = 0
+    st["u_op"][:8] = [100, 100, 100, 100, 100, 10, 10, 10]
+    st["v_op"][:8] = [90, 30, 50, 0, 0, 9, 5, 1]
+    w0, u0, v0 = st["w_op"].copy(), st["u_op"].copy(), st["v_op"].copy()
+    out = o.aos_update(p, st, st["epoch_ref"], op_mask=synth.PERM_LNS_OPS)
+    A, FL = 49152, 1024
+    raw = []
+    for i in range(8):
+        r = (int(v0[i]) << 16) // (int(u0[i]) + 1)
+        nw = (A * int(w0[i]) + (65536 - A) * (r + FL)) >> 16
+        hi = caps[i] or (1311 if i >= 5 else 65536)
+        raw.append(min(max(nw, min(FL, hi)), hi))
+    s = sum(raw)
+    assert list(out["w_op"][:8]) == [max(1, (r << 16) // s) for r in raw]
+    assert raw[0] == 20000 and raw[1] == 500 and raw[6] == 900 and raw[5] == 1311
