@@ -39,7 +39,7 @@ typedef int32_t gx_status;
 enum {
   GX_OK = 0,
   GX_E_INVALID = -1,      /* an argument is out of its documented domain */
-  GX_E_UNSUPPORTED = -2,  /* valid, but beyond this build's kernel limits */
+  GX_E_UNSUPPORTED = -2,  /* valid, but beyond the library's kernel limits */
   GX_E_NOMEM = -3,        /* device or host allocation failed */
   GX_E_DEVICE = -4,       /* a HIP runtime error (message in gx_last_error) */
   GX_E_NOT_READY = -5,    /* gx_poll: work still running */
