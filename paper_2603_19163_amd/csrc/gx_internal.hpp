@@ -138,14 +138,18 @@ constexpr int kOneBufferN = 1536;
 constexpr uint32_t kTables = 3968, kTablesX3 = 4736;
 // LNS scratch per wave, at the end of the workgroup's LDS in the variants
 // that may draw LNS steps: three step tables (positions, sources, length)
-// and the candidate's entries
+// and the candidate's entries (VRPTW: the entries of up to kLnsBatch
+// candidates, whose splits the lanes then run side by side)
 struct LnsTab {
   uint16_t pos[kLnsMax];
   uint8_t src[kLnsMax];
   int32_t L;
   int32_t pad[3];
 };
-__host__ __device__ inline uint32_t lns_wave_bytes(int n) { return 3u * (uint32_t)sizeof(LnsTab) + ((2u * n + 15u) & ~15u); }
+constexpr int kLnsBatch = 16;
+__host__ __device__ inline uint32_t lns_wave_bytes(int kind, int n) {
+  return 3u * (uint32_t)sizeof(LnsTab) + (kind == KVRP ? (uint32_t)kLnsBatch : 1u) * ((2u * n + 15u) & ~15u);
+}
 __host__ __device__ inline bool lns_variant(int kind, int var) {
   return (var & kVarLns) && (kind == KTSP || kind == KQAP || kind == KVRP);
 }
@@ -177,7 +181,7 @@ __host__ __device__ inline uint32_t lds_core_bytes(int kind, int n, int var, int
   }
 }
 __host__ __device__ inline uint32_t lds_bytes_for(int kind, int n, int var, int rows) {
-  const uint32_t lns = lns_variant(kind, var) ? 2u * lns_wave_bytes(n) : 0u;
+  const uint32_t lns = lns_variant(kind, var) ? 2u * lns_wave_bytes(kind, n) : 0u;
   return lds_core_bytes(kind, n, var, rows) + lns;
 }
 

@@ -352,8 +352,9 @@ __device__ __forceinline__ void lns_make(LnsTab &T, int op, const uint32_t *w, i
 // heuristic keys of the entries (in HBM)
 struct LnsCtx {
   LnsTab *tabs;
-  uint16_t *y;
+  uint16_t *y;            // the candidate's entries (VRPTW: buffer b at y + b stride)
   const int64_t *hkey;
+  int stride;
 };
 
 __device__ __forceinline__ bool lns_in(const Step *st, int k) {
@@ -400,17 +401,52 @@ __device__ __forceinline__ void lns_range(const Step *st, int k, const LnsTab *t
     }
   }
 }
-// objective of candidate t of generation g (which holds an LNS step) by the
-// whole wave: its entries into lx.y, then obj(y), the same on every lane
-template <bool X3, class OBJ>
-__device__ __forceinline__ auto lns_eval(const Uni &U, uint32_t g, uint32_t sol, uint32_t t, int n,
-                                         const uint16_t *cur, const LnsCtx &lx, const OBJ &obj) {
+// the entries of candidate t of generation g (which holds an LNS step) into
+// dst, by the whole wave
+template <bool X3>
+__device__ __forceinline__ void lns_entries(const Uni &U, uint32_t g, uint32_t sol, uint32_t t, int n,
+                                            const uint16_t *cur, const LnsCtx &lx, uint16_t *dst) {
   Step st[3];
   const int k = sample<4, X3>(U, g, sol, t, st);
   lns_tables<X3>(U, g, sol, t, st, k, n, cur, lx);
-  for (int p = (int)lane_id(); p < n; p += kWave) lx.y[p] = cur[lchain(st, k, p, lx.tabs)];
+  for (int p = (int)lane_id(); p < n; p += kWave) dst[p] = cur[lchain(st, k, p, lx.tabs)];
   wave_sync();
+}
+// its objective: obj of its entries, the same on every lane
+template <bool X3, class OBJ>
+__device__ __forceinline__ auto lns_eval(const Uni &U, uint32_t g, uint32_t sol, uint32_t t, int n,
+                                         const uint16_t *cur, const LnsCtx &lx, const OBJ &obj) {
+  lns_entries<X3>(U, g, sol, t, n, cur, lx, lx.y);
   return obj(lx.y);
+}
+// The LNS candidates of a round (mask mk, candidate index base + lane) of a
+// kind whose objective one lane computes alone (VRPTW): the wave writes the
+// entries of up to kLnsBatch of them, then lane b computes batch member b's
+// value, which moves to the candidate's own lane.  obj(y) runs on one lane.
+template <bool X3, class T, class OBJ>
+__device__ __forceinline__ void lns_batched(const Uni &U, uint32_t g, uint32_t sol, uint32_t base, unsigned long long mk,
+                                            int n, const uint16_t *cur, const LnsCtx &lx, T &mine, const OBJ &obj) {
+  const uint32_t lane = lane_id();
+  while (mk) {
+    unsigned long long bm = 0ull;
+    int cnt = 0;
+    for (; mk && cnt < kLnsBatch; ++cnt) {
+      const uint32_t t = (uint32_t)__builtin_ctzll(mk);
+      mk &= mk - 1;
+      bm |= 1ull << t;
+      lns_entries<X3>(U, g, sol, base + t, n, cur, lx, lx.y + cnt * lx.stride);
+    }
+    T v{};
+    if ((int)lane < cnt) v = obj(lx.y + lane * lx.stride);
+    const uint32_t src = (uint32_t)__popcll(bm & ((1ull << lane) - 1ull));   // this lane's member index
+    T got;
+    const uint64_t *pv = (const uint64_t *)&v;
+    uint64_t *pg = (uint64_t *)&got;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 8); ++i) pg[i] = shfl64(pv[i], src);
+    if ((bm >> lane) & 1ull) mine = got;
+    wave_sync();   // the buffers are rewritten by the next batch
+  }
 }
 // apply the winning candidate t (steps st, with an LNS step) to cur through
 // tmp; returns the changed range.  Every wave of the workgroup calls it.
@@ -770,6 +806,7 @@ __device__ __forceinline__ void store_vec(int64_t *p, const Vec4 &x) {
 template <bool ROWS>
 struct VrpK {
   static constexpr int ENC = ROWS ? 3 : 0;
+  static constexpr bool kOneLaneObjective = true;   // one lane computes a solution's objective
   uint16_t *cur, *nxt;
   int n, dn, cap, veh, svc, hor;
   const int16_t *D;
@@ -1599,6 +1636,7 @@ __device__ __forceinline__ SMap smap_unpack(uint2 v) {
 template <class HT>
 struct QapK {
   static constexpr int ENC = 0;
+  static constexpr bool kOneLaneObjective = false;   // the wave computes a solution's objective
   uint16_t *cur, *nxt;
   int n, np;             // np: n rounded up to 8 (row stride of F and DX)
   const int16_t *F;      // F[a][b] at a * np + b, zero for b >= n
@@ -1974,12 +2012,20 @@ __device__ __forceinline__ void round_gens(KD &kd, const TspScratch &W, const Un
       if (__ballot(valid)) {
         const int k = valid ? kk[0] : 0;
         int64_t d = kd.template delta_round<X3>(W, (int)tl, k, f);
-        if constexpr (LNS) {   // candidates with an LNS step: by the whole wave
-          for (unsigned long long mk = __ballot(valid && lns_drawn(W.sop(), tl, k)); mk; mk &= mk - 1) {
-            const uint32_t t = (uint32_t)__builtin_ctzll(mk);
-            const int64_t fn = lns_eval<X3>(U, g, sol, c0 + wv * kWave + t, kd.n, kd.cur, lx,
-                                            [&](const uint16_t *y) { return kd.objective_of(y); });
-            if (lane == t) d = fn - f;
+        if constexpr (LNS) {   // candidates with an LNS step: their entries by the whole wave
+          const unsigned long long mk = __ballot(valid && lns_drawn(W.sop(), tl, k));
+          if constexpr (KD::kOneLaneObjective) {   // the splits of a batch side by side
+            int64_t fn = f + d;
+            lns_batched<X3>(U, g, sol, c0 + wv * kWave, mk, kd.n, kd.cur, lx, fn,
+                            [&](const uint16_t *y) { return kd.objective_of(y); });
+            d = fn - f;
+          } else {
+            for (unsigned long long m = mk; m; m &= m - 1) {
+              const uint32_t t = (uint32_t)__builtin_ctzll(m);
+              const int64_t fn = lns_eval<X3>(U, g, sol, c0 + wv * kWave + t, kd.n, kd.cur, lx,
+                                              [&](const uint16_t *y) { return kd.objective_of(y); });
+              if (lane == t) d = fn - f;
+            }
           }
         }
         if (valid) {
@@ -2083,13 +2129,10 @@ __device__ __forceinline__ void lex_rounds(KD &kd, const TspScratch &W, const Un
         st[2] = kk[0] > 2 ? load_step<ENC, X3>(W, (int)tl, 2) : st[0];
         v = lex_vector(kd.parts(st, kk[0]), kd.veh, L);
       }
-      if constexpr (LNS) {   // candidates with an LNS step: by the whole wave
-        for (unsigned long long mk = __ballot(tl < cn && lns_drawn(W.sop(), tl, kk[0])); mk; mk &= mk - 1) {
-          const uint32_t t = (uint32_t)__builtin_ctzll(mk);
-          const Vec4 vn = lns_eval<X3>(U, g, sol, c0 + wv * kWave + t, kd.n, kd.cur, lx,
-                                       [&](const uint16_t *y) { return lex_vector(kd.parts_of(y), kd.veh, L); });
-          if (lane == t) v = vn;
-        }
+      if constexpr (LNS) {   // candidates with an LNS step: their splits side by side, by batches
+        const unsigned long long mk = __ballot(tl < cn && lns_drawn(W.sop(), tl, kk[0]));
+        lns_batched<X3>(U, g, sol, c0 + wv * kWave, mk, kd.n, kd.cur, lx, v,
+                        [&](const uint16_t *y) { return lex_vector(kd.parts_of(y), kd.veh, L); });
       }
       if (tl < cn) {
         if (U.credit == 0) credit_bytes<ENC, W64>(cu, cvc, cuk, cvk, st, kk[0], lex_better(v, cv, L));
@@ -2784,12 +2827,13 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
   U.swk = U.ck[1] + wksrc[2];
 
   // LNS scratch of this wave (wide variants of single-row permutations)
-  LnsCtx lx{nullptr, nullptr, nullptr};
+  LnsCtx lx{nullptr, nullptr, nullptr, 0};
   if constexpr (lnsv) {
-    char *lb = lds + lds_core_bytes(KIND, n, VAR, I->rows) + (threadIdx.x >> 6) * lns_wave_bytes(n);
+    char *lb = lds + lds_core_bytes(KIND, n, VAR, I->rows) + (threadIdx.x >> 6) * lns_wave_bytes(KIND, n);
     lx.hkey = J->sums;
     lx.tabs = (LnsTab *)lb;
     lx.y = (uint16_t *)(lb + 3 * sizeof(LnsTab));
+    lx.stride = (int)(((2u * n + 15u) & ~15u) / 2u);
   }
   uint64_t T = J->T;
   int64_t f = J->cur_f[sol], bf = J->best_f[sol];
