@@ -2975,9 +2975,10 @@ __device__ __forceinline__ void evolve_wg(DevJob *J, uint32_t sol, char *lds) {
 // ------------------------------------------------------------ evolve kernels
 // The TSP kernels are held to 96 VGPRs (5 waves per SIMD): their scalar state
 // exceeds the SGPR file and part of it lives in VGPR lanes; the compiler's
-// own choice (about 100 VGPRs, 4 waves) runs slower.
+// own choice (about 100 VGPRs, 4 waves) runs slower.  The LNS variant takes
+// 128 (4 waves): at 96 it spills most of its wave-wide evaluation path.
 template <int KIND, int VAR>
-__global__ __launch_bounds__((kThreads<KIND, VAR>)) __attribute__((amdgpu_waves_per_eu(KIND == KTSP ? 5 : 1))) void k_evolve(
+__global__ __launch_bounds__((kThreads<KIND, VAR>)) __attribute__((amdgpu_waves_per_eu(KIND == KTSP ? ((VAR & kVarLns) ? 4 : 5) : 1))) void k_evolve(
     DevJob *job) {
   evolve_wg<KIND, VAR>(job, blockIdx.x, gx_lds);
 }
