@@ -211,3 +211,15 @@ def test_per_sequence_caps(ctx, scope):
     pr = P(30, seed=4, population=4, candidates=128, epoch=3, aos_scope=scope,
            weight_cap_q16=[0, 0, 3000, 0, 0, 600, 0, 40000])
     run_parity(ctx, rows, pr, [30], f"rows caps scope {scope}")
+
+
+@pytest.mark.parametrize("mode", [dict(islands=2, migrate_epochs=2, migrate_mode=0, elite_epochs=3),
+                                  dict(islands=4, migrate_epochs=1, migrate_mode=2, migrate_n=1)])
+def test_lns_with_islands(ctx, mode):
+    """The LNS kernels with island migration and elite injection at the epoch ends."""
+    inst = synth.tsp_clustered(60, 5, key=90)
+    p = P(36, seed=8, population=8, candidates=128, op_mask=ALL, epoch=3, init_weight_q16=RAISED, **mode)
+    run_parity(ctx, inst, p, [7, 29], f"lns islands {mode['migrate_mode']}")
+    vr = dataclasses.replace(synth.vrptw_random(24, 6, key=91), vehicles=4)
+    run_parity(ctx, vr, P(24, seed=9, population=8, candidates=128, op_mask=ALL, epoch=3,
+                          init_weight_q16=RAISED, **mode), [24], f"vrptw lns islands {mode['migrate_mode']}")
