@@ -8,6 +8,8 @@ their initial weights raised so that many candidates hold LNS steps (the
 epoch is long, so the cap applies late), per-solution weights, tiny sizes,
 the 442-city instance (the largest destroyed part), and a batch."""
 import dataclasses
+import os
+import time
 
 import numpy as np
 import pytest
@@ -23,6 +25,7 @@ KEYS = ["g", "stag", "T_q16", "epoch_ref", "accepted", "w_op", "w_k", "u_op", "v
 TOT = [("u_op", "tot_u_op"), ("v_op", "tot_v_op"), ("u_k", "tot_u_k"), ("v_k", "tot_v_k")]
 LNS, ALL = synth.LNS_OPS, synth.PERM_LNS_OPS
 RAISED = [0, 0, 0, 0, 0, 30000, 30000, 30000]      # LNS weights raised for the first epoch
+THREADS = max(1, min(16, os.cpu_count() or 1))
 
 
 @pytest.fixture(scope="module")
@@ -171,7 +174,6 @@ def test_lns_masks(ctx):
 def test_served_lanes_keep_variants_apart(ctx):
     """Requests of one kind that need different kernels (LNS or not, giant
     tour or rows) are served together, each equal to the oracle."""
-    import time
     reqs = [(synth.tsp_uniform(40, 8, key=70), P(30, seed=1, population=4, op_mask=ALL, epoch=20,
                                                   init_weight_q16=RAISED)),
             (synth.tsp_uniform(40, 9, key=71), P(30, seed=2, population=4, op_mask=synth.PERM_OPS)),
@@ -223,3 +225,59 @@ def test_lns_with_islands(ctx, mode):
     vr = dataclasses.replace(synth.vrptw_random(24, 6, key=91), vehicles=4)
     run_parity(ctx, vr, P(24, seed=9, population=8, candidates=128, op_mask=ALL, epoch=3,
                           init_weight_q16=RAISED, **mode), [24], f"vrptw lns islands {mode['migrate_mode']}")
+
+
+
+def test_c3_lns_whole_run(ctx):
+    """The 100-customer giant-tour configuration with the LNS operators as the
+    per-kind bench row runs it (P = 64, 5000 generations, presets): state and
+    run totals compared with the oracle every 1000 generations."""
+    base, p0 = synth.c3_vrptw(seed=42)
+    p = p0.with_(op_mask=ALL)
+    h = gx.gx_instance_upload(ctx, base)
+    job = gx.gx_job_create(ctx, h, p)
+    o = oracle.OracleInstance(base)
+    st = o.init(p)
+    compare(ctx, job, p, base, st, "C3 LNS init")
+    for k in range(5):
+        gx.gx_job_advance(ctx, job, 1000)
+        t = time.perf_counter()
+        o.run(p, st, 1000, threads=THREADS)
+        print(f"[lns] C3 LNS generations {1000 * k}..{1000 * (k + 1)}: oracle {time.perf_counter() - t:.1f} s",
+              flush=True)
+        compare(ctx, job, p, base, st, f"C3 LNS generation {1000 * (k + 1)}")
+    assert st["tot_v_op"][5:8].sum() > 0   # LNS steps were drawn
+    sol, f = gx.gx_fetch_best(ctx, job, base.n)
+    fo, io = o.best_of(st)
+    assert f == fo and np.array_equal(sol, st["best"][io])
+    gx.gx_job_free(ctx, job)
+    gx.gx_instance_free(ctx, h)
+
+
+def test_c2_lns_windows(ctx):
+    """The 442-city LNS row of the per-kind bench (autosized population, the
+    default staging, 20 000 generations): 20-generation windows at generations
+    1000, 5000, 10 000 and 19 980 of one job, each resumed by the oracle from the GPU's state."""
+    inst, p = synth.c2_tsp442(population=0, generations=20_000)
+    p = p.with_(op_mask=synth.PERM4_OPS | LNS)
+    h = gx.gx_instance_upload(ctx, inst)
+    p = p.with_(population=gx.gx_autosize_population(ctx, h, p))
+    job = gx.gx_job_create(ctx, h, p)
+    o = oracle.OracleInstance(inst)
+    g = 0
+    for start in (1000, 5000, 10_000, 19_980):
+        gx.gx_job_advance(ctx, job, start - g)
+        a = gx.gx_snapshot(ctx, job, p.population, inst.n)
+        gx.gx_job_advance(ctx, job, 20)
+        b = gx.gx_snapshot(ctx, job, p.population, inst.n)
+        g = start + 20
+        assert a["g"] == start and b["g"] == g
+        t = time.perf_counter()
+        o.run(p, a, 20, threads=THREADS)
+        print(f"[lns] C2 LNS P={p.population} window {start}..{g}: best {int(b['best_f'].min())}, "
+              f"oracle {time.perf_counter() - t:.1f} s", flush=True)
+        for k in KEYS:
+            x, y = np.asarray(b[k]), np.asarray(a[k])
+            assert np.array_equal(x, y), f"C2 LNS window {start}: {k} gpu {x.ravel()[:6]} oracle {y.ravel()[:6]}"
+    gx.gx_job_free(ctx, job)
+    gx.gx_instance_free(ctx, h)
