@@ -2,8 +2,10 @@
 the 442-city configuration (autosized population, benchmark staging) in
 20-generation windows at generations 10 000, 50 000, 100 000 and 199 980 of
 one job advanced in this process, each window resumed by the oracle from the
-GPU's own state; and the VRPTW configuration (100 customers, P = 64) over its
-whole 5000-generation run with a snapshot every 1000 generations.  The oracle
+GPU's own state; the island rows of the 442-city configuration (three
+migration modes) in 100-generation windows that hold migrations and an elite
+injection; and the VRPTW configuration (100 customers, P = 64) over its whole
+5000-generation run with a snapshot every 1000 generations.  The oracle
 runs threaded (pinned equal to its plain runner on the CPU)."""
 import os
 import time
@@ -105,5 +107,36 @@ def test_c3_lexicographic_whole_run(ctx):
     sol, f = gx.gx_fetch_best(ctx, job, inst.n)
     fo, io = o.best_of(st)
     assert f == fo and np.array_equal(sol, st["best"][io])
+    gx.gx_job_free(ctx, job)
+    gx.gx_instance_free(ctx, h)
+
+
+@pytest.mark.parametrize("mode,mig_n", [(0, 0), (1, 4), (2, 4)])
+def test_c2_islands_windows(ctx, mode, mig_n):
+    """The 442-city island rows of the per-kind bench (autosized population,
+    16 islands, migration every 5 epochs, elite injection every 10, 20 000
+    generations): 100-generation windows, each holding two migrations and an
+    elite injection, at generations 9900 and 19 900 of one job, each resumed by
+    the oracle from the GPU's state."""
+    inst, p = synth.c2_tsp442(population=0, generations=20_000)
+    p = p.with_(islands=16, migrate_epochs=5, elite_epochs=10, migrate_mode=mode, migrate_n=mig_n)
+    h = gx.gx_instance_upload(ctx, inst)
+    P = gx.gx_autosize_population(ctx, h, p)
+    p = p.with_(population=P)
+    job = gx.gx_job_create(ctx, h, p)
+    o = oracle.OracleInstance(inst)
+    g = 0
+    for start in (9_900, 19_900):
+        gx.gx_job_advance(ctx, job, start - g)
+        a = gx.gx_snapshot(ctx, job, P, inst.n)
+        gx.gx_job_advance(ctx, job, 100)
+        b = gx.gx_snapshot(ctx, job, P, inst.n)
+        g = start + 100
+        assert a["g"] == start and b["g"] == g
+        t = time.perf_counter()
+        o.run(p, a, 100, threads=THREADS)
+        print(f"[config parity] C2 islands mode {mode} P={P} window {start}..{g}: best {int(b['best_f'].min())}, "
+              f"oracle {time.perf_counter() - t:.1f} s", flush=True)
+        same(b, a, f"C2 islands mode {mode} window {start}..{g}")
     gx.gx_job_free(ctx, job)
     gx.gx_instance_free(ctx, h)
