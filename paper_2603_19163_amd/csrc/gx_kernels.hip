@@ -260,6 +260,15 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, uint32_t src) {
   const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), (int)src, kWave);
   return ((uint64_t)hi << 32) | lo;
 }
+// the value of v on lane q, for a q that is the same on every lane: a register
+// read (v_readlane), with none of a shuffle's round trip through the LDS
+// crossbar, for the serial loops below whose every pass waits on the last
+__device__ __forceinline__ int lane_val(int v, int q) { return __builtin_amdgcn_readlane(v, q); }
+__device__ __forceinline__ int64_t lane_val64(int64_t v, int q) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, q);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), q);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 __device__ __forceinline__ bool is_lns(int op) { return op >= OLNSSEG && op <= OLNSGUIDE; }
 __device__ __forceinline__ int lns_len(int n) { return min(min(2 + n / 16, kLnsMax), n); }
 __device__ __forceinline__ uint32_t lns_word(const uint32_t *w, int i) {
@@ -294,7 +303,8 @@ __device__ __forceinline__ int lchain(const Step *st, int m, int p, const LnsTab
 }
 // the table of LNS step m (op, words w) of a candidate whose earlier steps
 // are st[0..m-1] (their tables built), by the whole wave: lane q draws the
-// q-th position and holds the q-th words; the shuffles run over the lanes.
+// q-th position and holds the q-th words; the serial loops read the
+// other lanes' registers.
 __device__ __forceinline__ void lns_make(LnsTab &T, int op, const uint32_t *w, int n, const uint16_t *cur,
                                          const Step *st, const LnsTab *tabs, int m, const int64_t *hkey) {
   const int lane = (int)lane_id();
@@ -312,12 +322,12 @@ __device__ __forceinline__ void lns_make(LnsTab &T, int op, const uint32_t *w, i
     int pos = 0;
     for (int q = 0; q < L; ++q) {   // Floyd's sampling: position q is r, or j when r is taken
       const int j = n - L + q;
-      const int r = (int)rmap((uint32_t)__shfl((int)wa, q, kWave), (uint32_t)(j + 1));
+      const int r = (int)rmap((uint32_t)lane_val((int)wa, q), (uint32_t)(j + 1));
       const bool have = __ballot(lane < q && pos == r) != 0ull;
       if (lane == q) pos = have ? j : r;
     }
     int rank = 0;   // increasing order
-    for (int q = 0; q < L; ++q) rank += __shfl(pos, q, kWave) < pos;
+    for (int q = 0; q < L; ++q) rank += lane_val(pos, q) < pos;
     if (lane < L) T.pos[rank] = (uint16_t)pos;
   } else if (lane < L) {
     T.pos[lane] = (uint16_t)(a + lane);
@@ -329,8 +339,8 @@ __device__ __forceinline__ void lns_make(LnsTab &T, int op, const uint32_t *w, i
     const int64_t ky = lane < L ? (desc ? -hkey[e] : hkey[e]) : 0;
     int rank = 0;
     for (int q = 0; q < L; ++q) {
-      const int eq = __shfl(e, q, kWave);
-      const int64_t kq = (int64_t)shfl64((uint64_t)ky, (uint32_t)q);
+      const int eq = lane_val(e, q);
+      const int64_t kq = lane_val64(ky, q);
       rank += kq < ky || (kq == ky && eq < e);
     }
     if (lane < L) T.src[rank] = (uint8_t)lane;
@@ -338,8 +348,8 @@ __device__ __forceinline__ void lns_make(LnsTab &T, int op, const uint32_t *w, i
     const uint32_t wf = op == OLNSSCAT ? wb : wa;
     int src = lane;
     for (int i = L - 1; i >= 1; --i) {
-      const int j = (int)rmap((uint32_t)__shfl((int)wf, L - 1 - i, kWave), (uint32_t)(i + 1));
-      const int si = __shfl(src, i, kWave), sj = __shfl(src, j, kWave);
+      const int j = (int)rmap((uint32_t)lane_val((int)wf, L - 1 - i), (uint32_t)(i + 1));
+      const int si = lane_val(src, i), sj = lane_val(src, j);
       src = lane == i ? sj : (lane == j ? si : src);
     }
     if (lane < L) T.src[lane] = (uint8_t)src;
@@ -499,6 +509,45 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
+}
+// The delta of a tour candidate t with an LNS step, by the whole wave: its
+// entries over the hull [lo, hi] of the positions its steps change and the
+// edges that touch the hull, new against old (el: the current edge lengths,
+// or null); when the hull leaves fewer than two positions out, the whole new
+// tour against f.  Entries outside the hull are the current ones, so the
+// value is the full recomputation's.
+template <bool X3, class DF>
+__device__ __forceinline__ int64_t lns_tour_delta(const Uni &U, uint32_t g, uint32_t sol, uint32_t t, int n,
+                                                  const uint16_t *cur, const uint16_t *el, const LnsCtx &lx,
+                                                  const DF &D, int64_t f) {
+  Step st[3];
+  const int k = sample<4, X3>(U, g, sol, t, st);
+  lns_tables<X3>(U, g, sol, t, st, k, n, cur, lx);
+  int lo, hi;
+  lns_range(st, k, lx.tabs, lo, hi);
+  if (hi < lo) return 0;   // no step changes a position
+  const int lane = (int)lane_id();
+  const bool whole = hi - lo + 2 > n;
+  if (whole) {
+    lo = 0;
+    hi = n - 1;
+  }
+  uint16_t *y = lx.y;
+  for (int p = lo + lane; p <= hi; p += kWave) y[p] = cur[lchain(st, k, p, lx.tabs)];
+  wave_sync();
+  int64_t acc = 0;
+  if (whole) {
+    for (int p = lane; p < n; p += kWave) acc += D(y[p], y[p + 1 == n ? 0 : p + 1]);
+  } else {   // edges (u, u + 1 mod n) for u = lo - 1 .. hi, all distinct
+    for (int j = lane; j <= hi - lo + 1; j += kWave) {
+      const int u = lo - 1 + j < 0 ? n - 1 : lo - 1 + j, v = u + 1 == n ? 0 : u + 1;
+      const int yu = u >= lo && u <= hi ? y[u] : cur[u], yv = v >= lo && v <= hi ? y[v] : cur[v];
+      acc += (int64_t)D(yu, yv) - (el ? (int64_t)el[u] : (int64_t)D(cur[u], cur[v]));
+    }
+  }
+  const int64_t s = wave_sum64(acc);
+  wave_sync();   // y is rewritten by the next candidate
+  return whole ? s - f : s;
 }
 
 // Wave-wide minimum of a 32-bit value with DPP moves only (no LDS path):
@@ -1452,13 +1501,9 @@ __device__ __forceinline__ void tsp_run(uint16_t *cur, uint16_t *nxt, uint16_t *
           const bool has = tl < cn && (is_lns(s0[r].op) || (kk[r] > 1 && lns_drawn(W.sop(), tl, kk[r])));
           for (unsigned long long mk = __ballot(has); mk; mk &= mk - 1) {
             const uint32_t t = (uint32_t)__builtin_ctzll(mk);
-            const int64_t fn = lns_eval<X3>(U, g, sol, c0 + r * kWave + t, n, cur, lx, [&](const uint16_t *y) {
-              int64_t acc = 0;
-              for (int p = (int)lane; p < n; p += kWave) acc += D(y[p], y[p + 1 == n ? 0 : p + 1]);
-              return wave_sum64(acc);
-            });
+            const int64_t dl = lns_tour_delta<X3>(U, g, sol, c0 + r * kWave + t, n, cur, el, lx, D, f);
             if (lane == t) {
-              lns_d[r] = fn - f;
+              lns_d[r] = dl;
               lns_c |= 1u << r;
             }
           }
