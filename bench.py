@@ -424,6 +424,10 @@ def bench_kinds(args):
          tsp442(**isl, migrate_mode=2, migrate_n=4)),
         ("tsp442_lns", "same, one population, with the three LNS operators at their preset weights",
          tsp442(op_mask=synth.PERM4_OPS | synth.LNS_OPS)),
+        ("tsp442_lns_capped", "same, the LNS operators' weights capped at 1/65536 (the LNS kernel, almost no LNS step)",
+         tsp442(op_mask=synth.PERM4_OPS | synth.LNS_OPS, weight_cap_q16=(0, 0, 0, 0, 0, 1, 1, 1))),
+        ("tsp442_3opt", "same, 2-opt/swap/insert/or-opt and 3-opt (the kernel the LNS one extends)",
+         tsp442(op_mask=synth.PERM4_OPS | (1 << synth.OP_3OPT))),
         ("tsp50", "TSP n=50 uniform, P=64, 2-opt/swap/or-opt, 2000 generations", synth.c1_small_tsp(0)),
         ("vrptw100", "VRPTW 100 customers, giant tour + split, P=64, 5000 generations", synth.c3_vrptw()),
         ("vrptw100_weighted", "same, weighted objectives 6 distance + 2 routes + 2 longest route",
